@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of the TSL sign function + all-links derivative on one MI355X.
+
+One step = one source: S = Re <eta|TSL_k(H(U), psi)>, sgn(H)psi by two-sided
+Lanczos, and dS/dU over all 4V links (tslov_sign_grad), on the 8^4 workload
+(V = 4096, n = 49152, Wilson mass -2, mu = 0.2, k = 200, FP64) with seeded
+synthetic SU(3) links (spread 0.4) and Z2-complex sources resident in HBM.
+
+The JSON line carries:
+* value: sources/s of the FP64 path over the timed steps;
+* roofline: the dominant kernel's algorithmic bytes per launch over its mean
+  duration, timed with HIP events on the library stream during the timed steps;
+* cpu_baseline: the CPU oracle (torch/NumPy float64; forward TSL + autograd
+  gradient) on one source of the same workload, on the host cores;
+* mixed: the float32-stencil path on the same workload (sources/s, error vs FP64);
+* stencil_large: the FP64 Wilson stencil alone on a 32^4 lattice (1.15 GB per
+  application, above the 256 MB last-level cache) for the HBM-bound figure.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sgn(H)ψ+dU-derivative sources/s, mixed vs FP64 @≤1e-6 rel; stencil HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+KERNEL_NAMES = {0: "k_fwd_pair<double> (fused Lanczos stencil pair)",
+                1: "k_bwd_rb<double> (reverse-mode stencil pair)"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_pair_8x8x8x8.txt")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("common.h", "fields.hip"):
+        with open(os.path.join(ROOT, "paper_1604_08057_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch of the forward pair kernel from the committed counter summary,
+    or None if absent or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(ctx, eta, psi, k, steps, warmup, dU, timing=False):
+    import torch
+    for _ in range(warmup):
+        ctx.sign_grad(eta, psi, k, dU=dU)
+    torch.cuda.synchronize()
+    if timing:
+        ctx.timing_enable(True)
+        ctx.timing_read(0)
+        ctx.timing_read(1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S, _, _, info = ctx.sign_grad(eta, psi, k, dU=dU)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if timing:
+        ctx.timing_enable(False)
+    return (t1 - t0), S, info
+
+
+def cpu_baseline(wl):
+    import torch
+    from oracle import grad as GR
+    from oracle.wilson import WilsonOperator
+    op = WilsonOperator(wl.dims, wl.mass, wl.mu)
+    U, psi, eta = wl.links(), wl.psi(), wl.eta()
+    t0 = time.perf_counter()
+    GR.grad_autograd(op, U, psi, eta, wl.k)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "sources/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"1 source of the same workload ({wl.dims[0]}^4, k={wl.k}): forward TSL + torch-CPU "
+                      f"autograd dS/dU, {dt:.1f} s"}
+
+
+def stencil_large():
+    import torch
+    from paper_1604_08057_amd import Context
+    from paper_1604_08057_amd.tslov import KERNEL_APPLY
+    dims = (32, 32, 32, 32)
+    V = 32 ** 4
+    g = torch.Generator(device="cuda").manual_seed(1604)
+    U = torch.randn((4, V, 3, 3), dtype=torch.complex128, device="cuda", generator=g)
+    x = torch.randn((V, 4, 3), dtype=torch.complex128, device="cuda", generator=g)
+    ctx = Context(dims, -2.0, 0.3)
+    ctx.set_links(U)
+    for _ in range(3):
+        ctx.apply_h(x)
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    ctx.timing_read(KERNEL_APPLY)
+    for _ in range(20):
+        ctx.apply_h(x)
+    n, ms = ctx.timing_read(KERNEL_APPLY)
+    b = ctx.kernel_bytes(KERNEL_APPLY)
+    ctx.close()
+    gbs = b / (ms / n * 1e-3) / 1e9
+    return {"lattice": "32^4", "kernel": "k_apply<double>", "bytes_per_launch": b, "mean_ms": ms / n,
+            "achieved_GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the mixed and 32^4 legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the single-GPU path is what this "
+              f"library implements", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1604_08057_amd import Context
+    from synthetic import workload
+
+    wl = workload(2)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")  # noqa: E731
+    U, psi, eta = dev(wl.links()), dev(wl.psi()), dev(wl.eta())
+    ctx = Context(wl.dims, wl.mass, wl.mu, precision="fp64")
+    ctx.set_links(U)
+    dU = torch.empty((4, wl.volume, 3, 3), dtype=torch.complex128, device="cuda")
+    log(f"bench: workload {wl.dims} k={wl.k} fp64, warmup {args.warmup}, steps {args.steps}")
+    dt, S, info = time_steps(ctx, eta, psi, wl.k, args.steps, args.warmup, dU, timing=True)
+    n0, ms0 = ctx.timing_read(0)
+    n1, ms1 = ctx.timing_read(1)
+    log(f"bench: {args.steps / dt:.2f} sources/s; fwd pair {n0} x {ms0 / max(n0, 1) * 1e3:.2f} us, "
+        f"bwd pair {n1} x {ms1 / max(n1, 1) * 1e3:.2f} us")
+    which = 0 if ms0 >= ms1 else 1
+    n, ms = (n0, ms0) if which == 0 else (n1, ms1)
+    per_launch = ctx.kernel_bytes(which)
+    achieved = per_launch / (ms / n * 1e-3) / 1e9
+    traffic = read_traffic() if which == 0 else None
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": KERNEL_NAMES[which],
+                "bytes_per_launch": per_launch, "launches": n, "mean_us": ms / n * 1e3}
+    y64, _ = ctx.sign(psi, wl.k)
+    dU64 = dU.clone()
+    ctx.close()
+
+    out = {"metric": METRIC, "value": args.steps / dt, "unit": "sources/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "sgn(H)psi + all-links dS/dU, 8^4 lattice (V=4096, n=49152), "
+                                  "Wilson mass -2, mu=0.2, SU(3) link spread 0.4, k=200, one Z2 source",
+                      "lattice": "8x8x8x8", "k": wl.k, "precision": "fp64", "k_used": info.k_used,
+                      "newton_iters": info.newton_iters},
+           "roofline": roofline}
+
+    if not args.no_extras:
+        ctxm = Context(wl.dims, wl.mass, wl.mu, precision="mixed")
+        ctxm.set_links(U)
+        dUm = torch.empty_like(dU)
+        dtm, Sm, _ = time_steps(ctxm, eta, psi, wl.k, max(args.steps // 2, 1), 1, dUm)
+        ym, _ = ctxm.sign(psi, wl.k)
+        ctxm.close()
+        rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))  # noqa: E731
+        out["mixed"] = {"sources_per_s": max(args.steps // 2, 1) / dtm, "precision": "float32 stencil and "
+                        "vectors, float64 dots/coefficients/sign step/accumulation",
+                        "rel_err_y_vs_fp64": rel(ym, y64), "rel_err_dU_vs_fp64": rel(dUm, dU64),
+                        "rel_err_S_vs_fp64": abs(Sm - S) / abs(S)}
+        log(f"bench: mixed {out['mixed']['sources_per_s']:.2f} sources/s")
+        out["stencil_large"] = stencil_large()
+        log(f"bench: 32^4 stencil {out['stencil_large']['achieved_GBs']:.0f} GB/s")
+
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle on one source (~15-30 s)")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

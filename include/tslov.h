@@ -1,0 +1,155 @@
+/*
+ * tslov -- two-sided Lanczos sign function of the Wilson-Dirac operator at
+ * finite chemical potential and its derivative with respect to the gauge links,
+ * on one AMD MI355X (gfx950).
+ *
+ * Paper: M. Puhr and P. Buividovich, "A numerical method to compute derivatives
+ * of functions of large complex matrices and its application to the overlap
+ * Dirac operator at finite chemical potential" (arXiv:1604.08057).
+ *
+ * Canonical layouts (all device pointers unless stated otherwise):
+ *   site       s = x + Nx*(y + Ny*(z + Nz*t))           dims = {Nx, Ny, Nz, Nt}
+ *   links      U[mu][s][a][b]     complex128, 4*V*9      mu = x, y, z, t; U_mu(s) leaves s
+ *   spinors    psi[s][spin][c]    complex128, V*12
+ *   complex128 = two doubles (re, im), C99 "double complex" / torch.complex128.
+ * Dirac matrices: chiral basis g_k = [[0, -i s_k], [i s_k, 0]], g_4 = [[0, 1], [1, 0]],
+ * g_5 = g_1 g_2 g_3 g_4 = diag(1, 1, -1, -1).
+ *
+ * Ownership: the caller allocates every input and output buffer; the library
+ * never frees nor retains them after a call returns.  The library owns its
+ * workspace (device memory allocated on demand and kept until tslov_destroy).
+ * All device work is enqueued on the stream given to tslov_create.
+ *
+ * Errors: every call returns a tslov_status; tslov_last_error() gives a
+ * human-readable message for the calling thread.  Argument errors are detected
+ * before any work is enqueued.  HIP errors surface on the failing call.
+ */
+#ifndef TSLOV_H
+#define TSLOV_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tslov_status {
+    TSLOV_OK = 0,
+    TSLOV_ERR_ARG = 1,            /* invalid argument; nothing was enqueued            */
+    TSLOV_ERR_HIP = 2,            /* a HIP runtime call or kernel launch failed        */
+    TSLOV_ERR_OOM = 3,            /* workspace allocation failed                       */
+    TSLOV_ERR_BREAKDOWN = 4,      /* serious Lanczos breakdown: s^H r = 0, r != 0      */
+    TSLOV_ERR_SIGN_UNDEFINED = 5, /* sign of the projected matrix undefined (Re = 0)   */
+    TSLOV_ERR_NOT_CONVERGED = 6   /* an iterative inner step did not converge          */
+} tslov_status;
+
+typedef enum tslov_precision {
+    TSLOV_FP64 = 0,   /* links, Krylov vectors and stencil in float64                     */
+    TSLOV_MIXED = 1   /* links, Krylov vectors and stencil in float32 with float32
+                         accumulation; inner products, Lanczos coefficients, the
+                         projected-matrix sign / Frechet step and the output
+                         accumulation in float64                                          */
+} tslov_precision;
+
+/* Lattice and operator description (App. A, eq. WD_op / WD_G). */
+typedef struct tslov_lattice_desc {
+    int dims[4];         /* Nx, Ny, Nz, Nt (each >= 2)                                   */
+    double mass;         /* signed Wilson mass m; hopping parameter kappa = 1/(2m + 8)   */
+    double mu;           /* quark chemical potential: e^{+mu} on forward temporal hops   */
+    int antiperiodic_t;  /* 1: antiperiodic in t (factor -1 across t = Nt-1 -> 0)        */
+    int precision;       /* tslov_precision                                              */
+} tslov_lattice_desc;
+
+/* Per-call diagnostics (host struct, valid after the call returns). */
+typedef struct tslov_info {
+    int k_used;          /* Krylov size reached (< k after a lucky breakdown)           */
+    int breakdown;       /* 0 none, 1 lucky (invariant Krylov space), 2 serious           */
+    int newton_iters;    /* iterations of the projected-matrix sign step                 */
+    int reserved;
+    double norm_x;       /* |psi|                                                        */
+    double biorth_err;   /* |w_1^H v_k| + |w_k^H v_1| (loss of biorthogonality probe)    */
+    double ms[6];        /* phase times in ms: forward, dense, output, backward, force, total */
+} tslov_info;
+
+typedef struct tslov_ctx tslov_ctx;
+
+/* Create a context on the current HIP device.  `stream` is a hipStream_t (may be
+ * NULL for the default stream).  Fails with ERR_ARG for dims < 2 or unknown
+ * precision, ERR_HIP if no device is usable. */
+tslov_status tslov_create(const tslov_lattice_desc* desc, void* stream, tslov_ctx** out);
+void tslov_destroy(tslov_ctx* ctx);
+const char* tslov_last_error(void);
+
+/* Copy the gauge field (canonical complex128 [4][V][3][3], device) into the
+ * library's structure-of-arrays layout; the antiperiodic sign is folded into
+ * the temporal links on the last time slice.  No caller pointer is kept. */
+tslov_status tslov_set_links(tslov_ctx* ctx, const void* U);
+
+/* out = D_w(mu) in (dagger = 0) or D_w(mu)^dagger in = g5 D_w(-mu) g5 in
+ * (dagger = 1), eq. WD_op.  `in` and `out` are canonical spinors and must not
+ * overlap.  Runs in the context precision. */
+tslov_status tslov_apply_dw(tslov_ctx* ctx, const void* in, void* out, int dagger);
+
+/* out = H(mu) in = g5 D_w(mu) in (dagger = 0) or H(mu)^dagger in = H(-mu) in (dagger = 1),
+ * Sec. 1 (definition after eq. overlap). */
+tslov_status tslov_apply_h(tslov_ctx* ctx, const void* in, void* out, int dagger);
+
+/* Optional deflation by known eigenpairs of H (Sec. 3 eq. final_res, App. E);
+ * R, L: l canonical spinors each (device), biorthonormal L_i^H R_j = delta_ij;
+ * lambda: host array of 2*l doubles (re, im).  Not supported yet: pass NULL. */
+typedef struct tslov_deflation {
+    int l;
+    const void* R;
+    const void* L;
+    const double* lambda;
+} tslov_deflation;
+
+/* Two-sided Lanczos approximation out = |psi| V_k sgn(T_k) e_1 ~ sgn(H(mu)) psi
+ * (Sec. 2: Krylov spaces of H and H^dagger from the same source; v_1 = w_1 = psi/|psi|),
+ * k >= 1 basis vectors (k <= 1024).  A lucky breakdown returns OK with
+ * info->k_used < k and the exact result on the invariant space; a serious
+ * breakdown returns ERR_BREAKDOWN (out undefined).  info may be NULL. */
+tslov_status tslov_sign(tslov_ctx* ctx, const void* psi, void* out, int k,
+                        const tslov_deflation* defl, tslov_info* info);
+
+/* out = D_ov psi = psi + g5 sgn(H(mu)) psi with lattice spacing a = 1 (eq. overlap),
+ * sgn by two-sided Lanczos as in tslov_sign. */
+tslov_status tslov_overlap(tslov_ctx* ctx, const void* psi, void* out, int k,
+                           const tslov_deflation* defl, tslov_info* info);
+
+/* S = Re <eta | TSL_k(H(U), psi)> and its exact derivative with respect to every
+ * link (eq. derivative_def taken through the k-step approximation, with the
+ * Frechet derivative of sgn on T_k from Theorem 1):
+ *   dU_out[mu][s] = dS/dRe U_mu(s) + i dS/dIm U_mu(s)  (canonical complex128, device),
+ *   so dS = Re tr(dU_out^H dU);  the U(1) link-phase derivative is -Im tr(dU_out^H U).
+ * dpsi_out (nullable, canonical spinor) receives dS/dRe psi + i dS/dIm psi.
+ * S_out is a host pointer.  recompute_stride must be 0 (all Krylov vectors are
+ * stored; 2*k*12*V complex values of workspace).  For D_ov the caller passes
+ * g5 eta and adds Re <eta|psi>. */
+tslov_status tslov_sign_grad(tslov_ctx* ctx, const void* eta, const void* psi, int k,
+                             const tslov_deflation* defl, int recompute_stride,
+                             double* S_out, void* dU_out, void* dpsi_out, tslov_info* info);
+
+/* Projected-matrix step on its own (for tests): S = sgn(T) for a dense complex128
+ * k x k row-major device matrix T by the scaled Newton iteration, and, if E is
+ * not NULL, L = L_sgn(T, E), the upper-right block of sgn([[T, E], [0, T]])
+ * (Theorem 1).  S_out, L_out: device k x k; iters (host, nullable). */
+tslov_status tslov_dense_sign(tslov_ctx* ctx, const void* T, int k, const void* E,
+                              void* S_out, void* L_out, int* iters);
+
+/* Kernel timing for roofline measurement.  When enabled, the library records a
+ * HIP event pair around every launch of the given kernel class on its stream.
+ *   which = 0: forward Lanczos stencil pair (the dominant kernel)
+ *   which = 1: backward stencil pair
+ *   which = 2: plain operator application (tslov_apply_dw / tslov_apply_h)
+ * tslov_timing_read synchronises the stream and returns the number of recorded
+ * launches and their summed duration, then clears the record. */
+tslov_status tslov_timing_enable(tslov_ctx* ctx, int enable);
+tslov_status tslov_timing_read(tslov_ctx* ctx, int which, int* count, double* total_ms);
+
+/* Algorithmic bytes moved by one launch of kernel class `which` (see above) for
+ * this context's lattice and precision (minimal traffic, each field once). */
+double tslov_kernel_bytes(const tslov_ctx* ctx, int which);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSLOV_H */

@@ -1,0 +1,316 @@
+// Internal device helpers shared by the tslov HIP kernels: complex arithmetic,
+// lattice geometry, structure-of-arrays field access, deterministic block
+// reductions and the spin-projected Wilson hopping term (App. A, eq. WD_op/WD_G).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tslov {
+
+constexpr int kWave = 64;      // CDNA wavefront
+constexpr int kBlock = 128;    // threads per block of the lattice-field kernels
+
+// ------------------------------------------------------------------ complex
+template <typename R>
+struct __align__(2 * sizeof(R)) Z {
+    R re, im;
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ Z<R> mk(R a, R b) { Z<R> z; z.re = a; z.im = b; return z; }
+template <typename R>
+__host__ __device__ __forceinline__ Z<R> operator+(Z<R> a, Z<R> b) { return mk<R>(a.re + b.re, a.im + b.im); }
+template <typename R>
+__host__ __device__ __forceinline__ Z<R> operator-(Z<R> a, Z<R> b) { return mk<R>(a.re - b.re, a.im - b.im); }
+template <typename R>
+__host__ __device__ __forceinline__ Z<R> operator-(Z<R> a) { return mk<R>(-a.re, -a.im); }
+template <typename R>
+__host__ __device__ __forceinline__ Z<R> operator*(Z<R> a, Z<R> b) {
+    return mk<R>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename R>
+__host__ __device__ __forceinline__ Z<R> operator*(R s, Z<R> a) { return mk<R>(s * a.re, s * a.im); }
+template <typename R>
+__host__ __device__ __forceinline__ Z<R> cj(Z<R> a) { return mk<R>(a.re, -a.im); }
+// conj(a) * b
+template <typename R>
+__host__ __device__ __forceinline__ Z<R> cjmul(Z<R> a, Z<R> b) {
+    return mk<R>(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+// a * conj(b)
+template <typename R>
+__host__ __device__ __forceinline__ Z<R> mulcj(Z<R> a, Z<R> b) {
+    return mk<R>(a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im);
+}
+template <typename R>
+__host__ __device__ __forceinline__ Z<R> timesI(Z<R> a) { return mk<R>(-a.im, a.re); }
+template <typename R>
+__host__ __device__ __forceinline__ Z<R> timesMinusI(Z<R> a) { return mk<R>(a.im, -a.re); }
+template <typename R>
+__host__ __device__ __forceinline__ R norm2(Z<R> a) { return a.re * a.re + a.im * a.im; }
+
+template <typename To, typename From>
+__host__ __device__ __forceinline__ Z<To> zcast(Z<From> a) { return mk<To>((To)a.re, (To)a.im); }
+
+__host__ __device__ __forceinline__ Z<double> zdiv(Z<double> a, Z<double> b) {
+    double d = b.re * b.re + b.im * b.im;
+    return mk<double>((a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d);
+}
+
+using ZD = Z<double>;
+
+// ------------------------------------------------------------------ geometry
+struct Geom {
+    int nx, ny, nz, nt;
+    int V;      // sites
+    int ldv;    // plane stride (V rounded up to 64)
+};
+
+struct Nbr {
+    int fwd[4];
+    int bwd[4];
+};
+
+__device__ __forceinline__ Nbr neighbours(const Geom& g, int s) {
+    const int x = s % g.nx;
+    const int r1 = s / g.nx;
+    const int y = r1 % g.ny;
+    const int r2 = r1 / g.ny;
+    const int z = r2 % g.nz;
+    const int t = r2 / g.nz;
+    const int sy = g.nx, sz = g.nx * g.ny, st = g.nx * g.ny * g.nz;
+    Nbr n;
+    n.fwd[0] = (x + 1 == g.nx) ? s - (g.nx - 1) : s + 1;
+    n.bwd[0] = (x == 0) ? s + (g.nx - 1) : s - 1;
+    n.fwd[1] = (y + 1 == g.ny) ? s - (g.ny - 1) * sy : s + sy;
+    n.bwd[1] = (y == 0) ? s + (g.ny - 1) * sy : s - sy;
+    n.fwd[2] = (z + 1 == g.nz) ? s - (g.nz - 1) * sz : s + sz;
+    n.bwd[2] = (z == 0) ? s + (g.nz - 1) * sz : s - sz;
+    n.fwd[3] = (t + 1 == g.nt) ? s - (g.nt - 1) * st : s + st;
+    n.bwd[3] = (t == 0) ? s + (g.nt - 1) * st : s - st;
+    return n;
+}
+
+// ------------------------------------------------------------------ fields
+// Spinor field: 12 complex planes (index spin*3 + colour) of stride ldv.
+// Gauge field: 4 directions x 9 complex planes (index a*3 + b) of stride ldv.
+template <typename R>
+struct Spinor {
+    Z<R> c[4][3];
+};
+
+template <typename R>
+__device__ __forceinline__ void load_spinor(Spinor<R>& p, const Z<R>* __restrict__ f, int ldv, int s) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p.c[sp][c] = f[(sp * 3 + c) * ldv + s];
+}
+
+template <typename R>
+__device__ __forceinline__ void store_spinor(Z<R>* __restrict__ f, int ldv, int s, const Spinor<R>& p) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f[(sp * 3 + c) * ldv + s] = p.c[sp][c];
+}
+
+template <typename R>
+__device__ __forceinline__ void zero_spinor(Spinor<R>& p) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p.c[sp][c] = mk<R>(0, 0);
+}
+
+template <typename R>
+__device__ __forceinline__ void load_link(Z<R> (&u)[3][3], const Z<R>* __restrict__ U, int ldv, int nu, int s) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) u[a][b] = U[(nu * 9 + a * 3 + b) * ldv + s];
+}
+
+// ------------------------------------------------------------------ spin projection
+// Chiral basis: g_k = [[0, -i s_k], [i s_k, 0]], g_4 = [[0, 1], [1, 0]].
+// (1 + S g_nu) psi has rank 2: it equals [h; L h] with the half spinor
+// h = psi_up + S * (-i s_k or 1) psi_dn and L the lower-block map.  PROJ<NU, S>
+// gives h from psi and the two lower spin components from h.
+template <int NU, int S, typename R>
+__device__ __forceinline__ void project(const Spinor<R>& p, Z<R> (&h)[2][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const Z<R> p0 = p.c[0][c], p1 = p.c[1][c], p2 = p.c[2][c], p3 = p.c[3][c];
+        if (NU == 0) {          // -i s_1 psi_dn = (-i p3, -i p2)
+            h[0][c] = (S > 0) ? p0 + timesMinusI(p3) : p0 + timesI(p3);
+            h[1][c] = (S > 0) ? p1 + timesMinusI(p2) : p1 + timesI(p2);
+        } else if (NU == 1) {   // -i s_2 psi_dn = (-p3, p2)
+            h[0][c] = (S > 0) ? p0 - p3 : p0 + p3;
+            h[1][c] = (S > 0) ? p1 + p2 : p1 - p2;
+        } else if (NU == 2) {   // -i s_3 psi_dn = (-i p2, i p3)
+            h[0][c] = (S > 0) ? p0 + timesMinusI(p2) : p0 + timesI(p2);
+            h[1][c] = (S > 0) ? p1 + timesI(p3) : p1 + timesMinusI(p3);
+        } else {                // g_4: psi_dn
+            h[0][c] = (S > 0) ? p0 + p2 : p0 - p2;
+            h[1][c] = (S > 0) ? p1 + p3 : p1 - p3;
+        }
+    }
+}
+
+// acc += coef * [h; L h]
+template <int NU, int S, typename R>
+__device__ __forceinline__ void reconstruct_add(Spinor<R>& acc, const Z<R> (&h)[2][3], R coef) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const Z<R> h0 = coef * h[0][c], h1 = coef * h[1][c];
+        acc.c[0][c] = acc.c[0][c] + h0;
+        acc.c[1][c] = acc.c[1][c] + h1;
+        Z<R> l2, l3;
+        if (NU == 0) {          // lower = S * i s_1 h = S (i h1, i h0)
+            l2 = timesI(h1); l3 = timesI(h0);
+        } else if (NU == 1) {   // S * i s_2 h = S (h1, -h0)
+            l2 = h1; l3 = -h0;
+        } else if (NU == 2) {   // S * i s_3 h = S (i h0, -i h1)
+            l2 = timesI(h0); l3 = timesMinusI(h1);
+        } else {                // S * h
+            l2 = h0; l3 = h1;
+        }
+        if (S > 0) {
+            acc.c[2][c] = acc.c[2][c] + l2;
+            acc.c[3][c] = acc.c[3][c] + l3;
+        } else {
+            acc.c[2][c] = acc.c[2][c] - l2;
+            acc.c[3][c] = acc.c[3][c] - l3;
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void mat_vec(const Z<R> (&u)[3][3], const Z<R> (&h)[2][3], Z<R> (&o)[2][3]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) o[s][a] = u[a][0] * h[s][0] + u[a][1] * h[s][1] + u[a][2] * h[s][2];
+}
+
+template <typename R>
+__device__ __forceinline__ void adj_mat_vec(const Z<R> (&u)[3][3], const Z<R> (&h)[2][3], Z<R> (&o)[2][3]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) o[s][a] = cjmul(u[0][a], h[s][0]) + cjmul(u[1][a], h[s][1]) + cjmul(u[2][a], h[s][2]);
+}
+
+// Forward hop of direction NU into acc:  acc += coef * (1 + g_NU) u psi
+template <int NU, typename R>
+__device__ __forceinline__ void hop_fwd(Spinor<R>& acc, const Z<R> (&u)[3][3], const Spinor<R>& psi, R coef) {
+    Z<R> h[2][3], o[2][3];
+    project<NU, +1>(psi, h);
+    mat_vec(u, h, o);
+    reconstruct_add<NU, +1>(acc, o, coef);
+}
+
+// Backward hop of direction NU into acc:  acc += coef * (1 - g_NU) u^dag psi
+template <int NU, typename R>
+__device__ __forceinline__ void hop_bwd(Spinor<R>& acc, const Z<R> (&u)[3][3], const Spinor<R>& psi, R coef) {
+    Z<R> h[2][3], o[2][3];
+    project<NU, -1>(psi, h);
+    adj_mat_vec(u, h, o);
+    reconstruct_add<NU, -1>(acc, o, coef);
+}
+
+// ------------------------------------------------------------------ reductions
+// Deterministic: fixed shuffle tree inside a wave, then waves in index order.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+    return v;
+}
+
+// Block sum of NV values per thread; result valid in every thread.
+template <int NV, int BLK>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+    __shared__ double red[BLK / kWave][NV];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[wave][i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < BLK / kWave; ++w) s += red[w][i];
+        v[i] = s;
+    }
+    __syncthreads();
+}
+
+// Sum of per-block partials part[b*NV + i], b < nparts, in a fixed order; every
+// block that calls this gets bit-identical results.
+template <int NV, int BLK>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nparts, double (&out)[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += BLK)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) out[i] += part[b * NV + i];
+    block_sum<NV, BLK>(out);
+}
+
+template <int NV, int BLK>
+__device__ __forceinline__ void write_partials(double* __restrict__ part, double (&v)[NV]) {
+    block_sum<NV, BLK>(v);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) part[blockIdx.x * NV + i] = v[i];
+}
+
+// Accumulate conj(a) . b over a spinor into (re, im) in double.
+template <typename R>
+__device__ __forceinline__ void acc_dot(double& re, double& im, const Spinor<R>& a, const Spinor<R>& b) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double ar = a.c[sp][c].re, ai = a.c[sp][c].im, br = b.c[sp][c].re, bi = b.c[sp][c].im;
+            re += ar * br + ai * bi;
+            im += ar * bi - ai * br;
+        }
+}
+
+template <typename R>
+__device__ __forceinline__ double spinor_norm2(const Spinor<R>& a) {
+    double n = 0.0;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) n += (double)a.c[sp][c].re * a.c[sp][c].re + (double)a.c[sp][c].im * a.c[sp][c].im;
+    return n;
+}
+
+// ------------------------------------------------------------------ scalars
+// Device-resident Lanczos coefficients (1-based step index j).
+struct Coef {
+    ZD* alpha;      // alpha_j = w_j^H H v_j
+    double* beta;   // beta_j (beta_1 = |x|)
+    ZD* gamma;      // gamma_j (gamma_1 = |x|)
+    double* anorm2; // |H v_j|^2
+    ZD* h;          // eta^H v_j (derivative mode)
+    ZD* c;          // sgn(T) e_1
+    ZD* abar_T;     // adjoints seeded by the Frechet step
+    double* bbar_T;
+    ZD* gbar_T;
+    double* bbar_tot;  // beta/gamma adjoints including the recursion's contributions
+    ZD* gbar_tot;
+    int* status;    // [0] stop flag, [1] k_used, [2] breakdown code, [3] breakdown step
+    double* misc;   // [0] |x|, [1] S, [2] mu (Newton scaling), [3] scratch
+};
+
+constexpr double kTauLucky = 1e-11;
+constexpr double kTauSerious = 1e-14;
+
+}  // namespace tslov

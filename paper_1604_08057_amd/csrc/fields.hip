@@ -1,0 +1,753 @@
+// Lattice-field kernels of the TSL hot path: layout conversion, the Wilson
+// stencil (App. A, eq. WD_op/WD_G), the fused two-sided Lanczos step (Sec. 2),
+// output assembly (eq. overlap), the reverse-mode recursion and the per-link
+// force contraction for dS/dU.
+#include "kernels.h"
+
+#include <cmath>
+
+namespace tslov {
+
+namespace {
+
+// Block-uniform read of a device flag written by other blocks or launches.
+__device__ __forceinline__ int block_flag(const int* p) {
+    __shared__ int f;
+    if (threadIdx.x == 0) f = *(volatile const int*)p;
+    __syncthreads();
+    const int r = f;
+    __syncthreads();
+    return r;
+}
+
+template <typename R>
+__device__ __forceinline__ void g5_inplace(Spinor<R>& p) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        p.c[2][c] = -p.c[2][c];
+        p.c[3][c] = -p.c[3][c];
+    }
+}
+
+// One direction of the hopping sum for a single field.
+template <int NU, typename R>
+__device__ __forceinline__ void hop_dir(Spinor<R>& acc, const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+                                        const Geom& g, int s, const Nbr& n, R cf, R cb, int g5_in) {
+    Z<R> u[3][3];
+    Spinor<R> p;
+    load_link(u, U, g.ldv, NU, s);
+    load_spinor(p, in, g.ldv, n.fwd[NU]);
+    if (g5_in) g5_inplace(p);
+    hop_fwd<NU>(acc, u, p, cf);
+    load_link(u, U, g.ldv, NU, n.bwd[NU]);
+    load_spinor(p, in, g.ldv, n.bwd[NU]);
+    if (g5_in) g5_inplace(p);
+    hop_bwd<NU>(acc, u, p, cb);
+}
+
+// One direction of the hopping sums of two fields sharing the link loads:
+// field A with chemical potential +mu, field B with -mu.
+template <int NU, typename R>
+__device__ __forceinline__ void hop_dir_pair(Spinor<R>& acca, Spinor<R>& accb, const Z<R>* __restrict__ U,
+                                             const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
+                                             const Geom& g, int s, const Nbr& n, R ep, R em) {
+    const R fa_f = (NU == 3) ? ep : R(1), fa_b = (NU == 3) ? em : R(1);
+    Z<R> u[3][3];
+    Spinor<R> p;
+    load_link(u, U, g.ldv, NU, s);
+    load_spinor(p, fa, g.ldv, n.fwd[NU]);
+    hop_fwd<NU>(acca, u, p, fa_f);
+    load_spinor(p, fb, g.ldv, n.fwd[NU]);
+    hop_fwd<NU>(accb, u, p, fa_b);
+    load_link(u, U, g.ldv, NU, n.bwd[NU]);
+    load_spinor(p, fa, g.ldv, n.bwd[NU]);
+    hop_bwd<NU>(acca, u, p, fa_b);
+    load_spinor(p, fb, g.ldv, n.bwd[NU]);
+    hop_bwd<NU>(accb, u, p, fa_f);
+}
+
+// Pair variant where field A is formed on the fly as fa0 + ca * fa1 (fa0 nullable).
+template <int NU, typename R>
+__device__ __forceinline__ void load_combo(Spinor<R>& p, const Z<R>* __restrict__ f0, const Z<R>* __restrict__ f1,
+                                           Z<R> c1, int ldv, int s) {
+    Spinor<R> q;
+    load_spinor(q, f1, ldv, s);
+    if (f0) {
+        load_spinor(p, f0, ldv, s);
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) p.c[sp][c] = p.c[sp][c] + c1 * q.c[sp][c];
+    } else {
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) p.c[sp][c] = c1 * q.c[sp][c];
+    }
+}
+
+// Backward pair: A = H(-mu) abar with abar = r0 + ca w (on the fly), B = H(+mu) sbar.
+template <int NU, typename R>
+__device__ __forceinline__ void hop_dir_bwd_pair(Spinor<R>& acca, Spinor<R>& accb, const Z<R>* __restrict__ U,
+                                                 const Z<R>* __restrict__ r0, const Z<R>* __restrict__ w,
+                                                 Z<R> ca, const Z<R>* __restrict__ sb, const Geom& g, int s,
+                                                 const Nbr& n, R ep, R em) {
+    // field A runs at -mu: forward temporal factor e^{-mu}, backward e^{+mu}
+    const R a_f = (NU == 3) ? em : R(1), a_b = (NU == 3) ? ep : R(1);
+    Z<R> u[3][3];
+    Spinor<R> p;
+    load_link(u, U, g.ldv, NU, s);
+    load_combo<NU>(p, r0, w, ca, g.ldv, n.fwd[NU]);
+    hop_fwd<NU>(acca, u, p, a_f);
+    if (sb) {
+        load_spinor(p, sb, g.ldv, n.fwd[NU]);
+        hop_fwd<NU>(accb, u, p, a_b);
+    }
+    load_link(u, U, g.ldv, NU, n.bwd[NU]);
+    load_combo<NU>(p, r0, w, ca, g.ldv, n.bwd[NU]);
+    hop_bwd<NU>(acca, u, p, a_b);
+    if (sb) {
+        load_spinor(p, sb, g.ldv, n.bwd[NU]);
+        hop_bwd<NU>(accb, u, p, a_f);
+    }
+}
+
+}  // namespace
+
+// =============================================================== layout
+__global__ __launch_bounds__(kBlock) void k_links_to_soa(const ZD* __restrict__ Uc, ZD* __restrict__ U64,
+                                                         Z<float>* __restrict__ U32, Geom g, int antiperiodic) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const int nu = blockIdx.y;
+    if (s >= g.V) return;
+    double sign = 1.0;
+    if (nu == 3 && antiperiodic && s / (g.nx * g.ny * g.nz) == g.nt - 1) sign = -1.0;
+#pragma unroll
+    for (int ab = 0; ab < 9; ++ab) {
+        const ZD u = sign * Uc[((size_t)nu * g.V + s) * 9 + ab];
+        U64[(size_t)(nu * 9 + ab) * g.ldv + s] = u;
+        if (U32) U32[(size_t)(nu * 9 + ab) * g.ldv + s] = zcast<float>(u);
+    }
+}
+
+void launch_links_to_soa(const ZD* Ucanon, ZD* U64, Z<float>* U32, const Geom& g, int antiperiodic,
+                         hipStream_t st) {
+    dim3 grid(grid_for(g.V), 4);
+    hipLaunchKernelGGL(k_links_to_soa, grid, dim3(kBlock), 0, st, Ucanon, U64, U32, g, antiperiodic);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_spinor_to_soa(const ZD* __restrict__ in, Z<R>* __restrict__ out, Geom g,
+                                                          double* __restrict__ part) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double v[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
+    if (s < g.V) {
+        double n2 = 0.0;
+#pragma unroll
+        for (int p = 0; p < 12; ++p) {
+            const ZD z = in[(size_t)s * 12 + p];
+            const Z<R> zr = zcast<R>(z);
+            out[(size_t)p * g.ldv + s] = zr;
+            n2 += (double)zr.re * zr.re + (double)zr.im * zr.im;
+        }
+        // |x|^2 laid out as (omega re, omega im, |r|^2, |s|^2) so that the first
+        // Lanczos step normalises with beta_1 = gamma_1 = |x|.
+        v[0] = n2;
+        v[2] = n2;
+        v[3] = n2;
+    }
+    if (part) write_partials<kNvRecur, kBlock>(part, v);
+}
+
+template <typename R>
+void launch_spinor_to_soa(const ZD* in, Z<R>* out, const Geom& g, double* part_norm, hipStream_t st) {
+    hipLaunchKernelGGL(k_spinor_to_soa<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, in, out, g, part_norm);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_spinor_from_soa(const Z<R>* __restrict__ in, ZD* __restrict__ out, Geom g) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+#pragma unroll
+    for (int p = 0; p < 12; ++p) out[(size_t)s * 12 + p] = zcast<double>(in[(size_t)p * g.ldv + s]);
+}
+
+template <typename R>
+void launch_spinor_from_soa(const Z<R>* in, ZD* out, const Geom& g, hipStream_t st) {
+    hipLaunchKernelGGL(k_spinor_from_soa<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, in, out, g);
+}
+
+// =============================================================== operator
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_apply(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+                                                  Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em, int g5_in,
+                                                  int g5_out) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const Nbr n = neighbours(g, s);
+    Spinor<R> acc;
+    zero_spinor(acc);
+    hop_dir<0>(acc, U, in, g, s, n, R(1), R(1), g5_in);
+    hop_dir<1>(acc, U, in, g, s, n, R(1), R(1), g5_in);
+    hop_dir<2>(acc, U, in, g, s, n, R(1), R(1), g5_in);
+    hop_dir<3>(acc, U, in, g, s, n, ep, em, g5_in);
+    Spinor<R> x;
+    load_spinor(x, in, g.ldv, s);
+    if (g5_in) g5_inplace(x);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) x.c[sp][c] = x.c[sp][c] - kappa * acc.c[sp][c];
+    if (g5_out) g5_inplace(x);
+    store_spinor(out, g.ldv, s, x);
+}
+
+template <typename R>
+void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu, int g5_in,
+                  int g5_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_apply<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, U, in, out, g, (R)kappa,
+                       (R)std::exp(mu), (R)std::exp(-mu), g5_in, g5_out);
+}
+
+// =============================================================== forward Lanczos
+// Step j: normalise the previous residuals (v_j = r/beta_j, w_j = s/conj(gamma_j)),
+// apply a = H(mu) v_j and b = H(-mu) w_j = H^dag w_j with shared link loads, and
+// emit per-block partial sums of alpha_j = w_j^H a, |a|^2 and eta^H v_j.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
+                                                     const Z<R>* __restrict__ rin, const Z<R>* __restrict__ sin,
+                                                     const double* __restrict__ part_in, int npart_in, int first,
+                                                     Coef coef, int j, Z<R>* __restrict__ vout,
+                                                     Z<R>* __restrict__ wout, Z<R>* __restrict__ aout,
+                                                     Z<R>* __restrict__ bout, const Z<R>* __restrict__ eta,
+                                                     double* __restrict__ part_out) {
+    if (block_flag(coef.status)) return;
+    double red[kNvRecur];
+    reduce_partials<kNvRecur, kBlock>(part_in, npart_in, red);
+    const ZD om = mk<double>(red[0], red[1]);
+    const double rn2 = red[2], sn2 = red[3];
+    const double aom = std::sqrt(norm2(om));
+    if (!first) {
+        const double an2 = coef.anorm2[j - 1];
+        const bool lucky = rn2 <= kTauLucky * kTauLucky * an2;
+        const bool finite = std::isfinite(om.re) && std::isfinite(om.im);
+        const bool serious = !lucky && (!finite || aom <= kTauSerious * std::sqrt(rn2 * sn2));
+        if (lucky || serious) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                coef.status[1] = j - 1;
+                coef.status[2] = lucky ? 1 : 2;
+                coef.status[3] = j;
+                *(volatile int*)coef.status = 1;
+            }
+            return;
+        }
+    }
+    const double beta = std::sqrt(aom);
+    const ZD gam = (1.0 / beta) * om;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        coef.beta[j] = beta;
+        coef.gamma[j] = gam;
+        if (first) coef.misc[0] = beta;
+    }
+    const R ib = (R)(1.0 / beta);
+    const Z<R> icg = zcast<R>(zdiv(mk<double>(1.0, 0.0), cj(gam)));
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double pv[kNvPair] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (s < g.V) {
+        const Nbr n = neighbours(g, s);
+        Spinor<R> acca, accb;
+        zero_spinor(acca);
+        zero_spinor(accb);
+        const R ep = (R)emu, em = (R)(1.0 / emu);
+        hop_dir_pair<0>(acca, accb, U, rin, sin, g, s, n, ep, em);
+        hop_dir_pair<1>(acca, accb, U, rin, sin, g, s, n, ep, em);
+        hop_dir_pair<2>(acca, accb, U, rin, sin, g, s, n, ep, em);
+        hop_dir_pair<3>(acca, accb, U, rin, sin, g, s, n, ep, em);
+        Spinor<R> r0, s0, v, w, a, b;
+        load_spinor(r0, rin, g.ldv, s);
+        load_spinor(s0, sin, g.ldv, s);
+        const R kap = (R)kappa;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            const R sg = sp < 2 ? R(1) : R(-1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                v.c[sp][c] = ib * r0.c[sp][c];
+                w.c[sp][c] = icg * s0.c[sp][c];
+                a.c[sp][c] = (sg * ib) * (r0.c[sp][c] - kap * acca.c[sp][c]);
+                b.c[sp][c] = icg * ((sg) * (s0.c[sp][c] - kap * accb.c[sp][c]));
+            }
+        }
+        store_spinor(vout, g.ldv, s, v);
+        store_spinor(wout, g.ldv, s, w);
+        store_spinor(aout, g.ldv, s, a);
+        store_spinor(bout, g.ldv, s, b);
+        acc_dot(pv[0], pv[1], w, a);
+        pv[2] = spinor_norm2(a);
+        if (eta) {
+            Spinor<R> e;
+            load_spinor(e, eta, g.ldv, s);
+            acc_dot(pv[3], pv[4], e, v);
+        }
+    }
+    write_partials<kNvPair, kBlock>(part_out, pv);
+}
+
+template <typename R>
+void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Z<R>* rin, const Z<R>* sin,
+                     const double* part_in, int npart_in, int first, Coef coef, int j, Z<R>* vout, Z<R>* wout,
+                     Z<R>* aout, Z<R>* bout, const Z<R>* eta, double* part_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_fwd_pair<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, U, g, kappa, std::exp(mu), rin, sin,
+                       part_in, npart_in, first, coef, j, vout, wout, aout, bout, eta, part_out);
+}
+
+// r = a - alpha_j v_j - gamma_j v_{j-1},  s = b - conj(alpha_j) w_j - beta_j w_{j-1},
+// with per-block partials of omega = s^H r, |r|^2, |s|^2.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_recur(Geom g, const Z<R>* __restrict__ a, const Z<R>* __restrict__ b,
+                                                  const Z<R>* __restrict__ v, const Z<R>* __restrict__ w,
+                                                  const Z<R>* __restrict__ vp, const Z<R>* __restrict__ wp,
+                                                  const double* __restrict__ part_in, int npart_in, Coef coef, int j,
+                                                  int last, Z<R>* __restrict__ rout, Z<R>* __restrict__ sout,
+                                                  double* __restrict__ part_out) {
+    if (block_flag(coef.status)) return;
+    double red[kNvPair];
+    reduce_partials<kNvPair, kBlock>(part_in, npart_in, red);
+    const ZD alpha = mk<double>(red[0], red[1]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        coef.alpha[j] = alpha;
+        coef.anorm2[j] = red[2];
+        coef.h[j] = mk<double>(red[3], red[4]);
+    }
+    if (last) return;
+    const Z<R> al = zcast<R>(alpha), alc = zcast<R>(cj(alpha));
+    const bool has_prev = j > 1;
+    const Z<R> gj = has_prev ? zcast<R>(coef.gamma[j]) : mk<R>(0, 0);
+    const R bj = has_prev ? (R)coef.beta[j] : R(0);
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double pv[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
+    if (s < g.V) {
+#pragma unroll
+        for (int p = 0; p < 12; ++p) {
+            const size_t i = (size_t)p * g.ldv + s;
+            Z<R> r = a[i] - al * v[i];
+            Z<R> q = b[i] - alc * w[i];
+            if (has_prev) {
+                r = r - gj * vp[i];
+                q = q - bj * wp[i];
+            }
+            rout[i] = r;
+            sout[i] = q;
+            const double rr = r.re, ri = r.im, qr = q.re, qi = q.im;
+            pv[0] += qr * rr + qi * ri;
+            pv[1] += qr * ri - qi * rr;
+            pv[2] += rr * rr + ri * ri;
+            pv[3] += qr * qr + qi * qi;
+        }
+    }
+    write_partials<kNvRecur, kBlock>(part_out, pv);
+}
+
+template <typename R>
+void launch_recur(const Geom& g, const Z<R>* a, const Z<R>* b, const Z<R>* v, const Z<R>* w, const Z<R>* vp,
+                  const Z<R>* wp, const double* part_in, int npart_in, Coef coef, int j, int last, Z<R>* rout,
+                  Z<R>* sout, double* part_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_recur<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, g, a, b, v, w, vp, wp, part_in,
+                       npart_in, coef, j, last, rout, sout, part_out);
+}
+
+// out(s) = [psi(s) +] g5^{overlap} |x| sum_{j <= k_used} c_j v_j(s), canonical layout.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_assemble(Geom g, const Z<R>* __restrict__ basis, size_t fstride,
+                                                     Coef coef, const ZD* __restrict__ psi, int overlap,
+                                                     ZD* __restrict__ out) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const int k = coef.status[1];
+    const double nx = coef.misc[0];
+    ZD acc[12];
+#pragma unroll
+    for (int p = 0; p < 12; ++p) acc[p] = mk<double>(0, 0);
+    for (int j = 1; j <= k; ++j) {
+        const ZD c = coef.c[j];
+        const Z<R>* f = basis + (size_t)(j - 1) * fstride;
+#pragma unroll
+        for (int p = 0; p < 12; ++p) acc[p] = acc[p] + c * zcast<double>(f[(size_t)p * g.ldv + s]);
+    }
+#pragma unroll
+    for (int p = 0; p < 12; ++p) {
+        const double sg = (overlap && p >= 6) ? -nx : nx;
+        ZD o = sg * acc[p];
+        if (overlap) o = o + psi[(size_t)s * 12 + p];
+        out[(size_t)s * 12 + p] = o;
+    }
+}
+
+template <typename R>
+void launch_assemble(const Geom& g, const Z<R>* basis, size_t field_stride, Coef coef, const ZD* psi_canon,
+                     int overlap, ZD* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_assemble<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, g, basis, field_stride, coef,
+                       psi_canon, overlap, out);
+}
+
+// =============================================================== backward (reverse mode)
+// Reverse of the normalisation and of omega = s^H r for step j < k_used:
+// from vbar_{j+1}, wbar_{j+1} and the beta/gamma adjoints form
+//   omegabar = gbar/beta + [bbar - Re(conj(gbar) omega)/beta^2] omega / (2 beta^3),
+//   rbar_j = vbar_{j+1}/beta + omegabar conj(gamma) w_{j+1},
+//   sbar_j = wbar_{j+1}/gamma + conj(omegabar) beta v_{j+1},
+// and partials P1 = v_j^H rbar, P2 = sbar^H w_j, P3 = v_{j-1}^H rbar, P4 = w_{j-1}^H sbar.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_bwd_ra(Geom g, const Z<R>* __restrict__ vbar, const Z<R>* __restrict__ wbar,
+                                                   const Z<R>* __restrict__ vn, const Z<R>* __restrict__ wn,
+                                                   const Z<R>* __restrict__ vj, const Z<R>* __restrict__ wj,
+                                                   const Z<R>* __restrict__ vp, const Z<R>* __restrict__ wp,
+                                                   const double* __restrict__ part_in, int npart_in, Coef coef,
+                                                   int j, Z<R>* __restrict__ rbar, Z<R>* __restrict__ sbar,
+                                                   double* __restrict__ part_out) {
+    double red[kNvRB];
+    reduce_partials<kNvRB, kBlock>(part_in, npart_in, red);
+    const double D1 = red[0];
+    const ZD D2 = mk<double>(red[1], red[2]);
+    const double beta = coef.beta[j + 1];
+    const ZD gam = coef.gamma[j + 1];
+    const ZD om = beta * gam;
+    const double bbarR = coef.bbar_tot[j + 1] - D1 / beta;
+    const ZD gbar = coef.gbar_tot[j + 1] - zdiv(D2, cj(gam));
+    const ZD cgo = cjmul(gbar, om);   // conj(gbar) * omega
+    const double K = (bbarR - cgo.re / (beta * beta)) / (2.0 * beta * beta * beta);
+    const ZD ombar = (1.0 / beta) * gbar + K * om;
+    const R c1 = (R)(1.0 / beta);
+    const Z<R> c2 = zcast<R>(mulcj(ombar, gam));                 // omegabar conj(gamma)
+    const Z<R> c3 = zcast<R>(zdiv(mk<double>(1.0, 0.0), gam));   // 1/gamma
+    const Z<R> c4 = zcast<R>(beta * cj(ombar));                  // conj(omegabar) beta
+    const bool has_prev = vp != nullptr;
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double pv[kNvRA] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (s < g.V) {
+#pragma unroll
+        for (int p = 0; p < 12; ++p) {
+            const size_t i = (size_t)p * g.ldv + s;
+            const Z<R> r = c1 * vbar[i] + c2 * wn[i];
+            const Z<R> q = c3 * wbar[i] + c4 * vn[i];
+            rbar[i] = r;
+            sbar[i] = q;
+            const ZD rd = zcast<double>(r), qd = zcast<double>(q);
+            const ZD p1 = cjmul(zcast<double>(vj[i]), rd);
+            const ZD p2 = cjmul(qd, zcast<double>(wj[i]));
+            pv[0] += p1.re; pv[1] += p1.im;
+            pv[2] += p2.re; pv[3] += p2.im;
+            if (has_prev) {
+                const ZD p3 = cjmul(zcast<double>(vp[i]), rd);
+                const ZD p4 = cjmul(zcast<double>(wp[i]), qd);
+                pv[4] += p3.re; pv[5] += p3.im;
+                pv[6] += p4.re; pv[7] += p4.im;
+            }
+        }
+    }
+    write_partials<kNvRA, kBlock>(part_out, pv);
+}
+
+template <typename R>
+void launch_bwd_ra(const Geom& g, const Z<R>* vbar, const Z<R>* wbar, const Z<R>* v_next, const Z<R>* w_next,
+                   const Z<R>* v_j, const Z<R>* w_j, const Z<R>* v_prev, const Z<R>* w_prev, const double* part_in,
+                   int npart_in, Coef coef, int j, Z<R>* rbar_out, Z<R>* sbar_out, double* part_out,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_bwd_ra<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, g, vbar, wbar, v_next, w_next, v_j,
+                       w_j, v_prev, w_prev, part_in, npart_in, coef, j, rbar_out, sbar_out, part_out);
+}
+
+// Reverse of a_j = H v_j, b_j = H^dag w_j, alpha_j = w_j^H a_j and of the recurrence:
+//   alphabar_j = conj(Gamma_jj) - v_j^H rbar_j - sbar_j^H w_j,   abar_j = rbar_j + alphabar_j w_j,
+//   vbar_j = |x| conj(c_j) eta + H^dag abar_j - conj(alpha_j) rbar_j - conj(gamma_{j+1}) rbar_{j+1},
+//   wbar_j = H sbar_j + conj(alphabar_j) a_j - alpha_j sbar_j - beta_{j+1} sbar_{j+1},
+// storing abar_j for the force and emitting partials of Re vbar_j^H v_j, wbar_j^H w_j.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
+                                                   const double* __restrict__ part_in, int npart_in, Coef coef,
+                                                   int j, int k_used, const Z<R>* __restrict__ rbar_j,
+                                                   const Z<R>* __restrict__ rbar_n, const Z<R>* __restrict__ sbar_j,
+                                                   const Z<R>* __restrict__ sbar_n, const Z<R>* __restrict__ vp,
+                                                   const Z<R>* __restrict__ vj, const Z<R>* __restrict__ vn,
+                                                   const Z<R>* __restrict__ wj, const Z<R>* __restrict__ a_last,
+                                                   const Z<R>* __restrict__ eta, Z<R>* __restrict__ vbar_out,
+                                                   Z<R>* __restrict__ wbar_out, Z<R>* __restrict__ abar_out,
+                                                   double* __restrict__ part_out) {
+    const bool last = (j == k_used);
+    ZD abar = coef.abar_T[j];
+    if (!last) {
+        double red[kNvRA];
+        reduce_partials<kNvRA, kBlock>(part_in, npart_in, red);
+        abar = abar - mk<double>(red[0], red[1]) - mk<double>(red[2], red[3]);
+        if (blockIdx.x == 0 && threadIdx.x == 0 && j >= 2) {
+            coef.gbar_tot[j] = coef.gbar_T[j] - mk<double>(red[4], red[5]);
+            coef.bbar_tot[j] = coef.bbar_T[j] - red[6];
+        }
+    }
+    const bool carry = j + 1 < k_used;
+    const Z<R> ca = zcast<R>(abar);
+    const ZD alpha = coef.alpha[j];
+    const Z<R> alr = zcast<R>(alpha), alc = zcast<R>(cj(alpha)), abc = zcast<R>(cj(abar));
+    const Z<R> etac = zcast<R>(coef.misc[0] * cj(coef.c[j]));
+    const Z<R> gnc = carry ? zcast<R>(cj(coef.gamma[j + 1])) : mk<R>(0, 0);
+    const R bn = last ? R(0) : (R)coef.beta[j + 1];
+    const Z<R> gj = (j >= 2) ? zcast<R>(coef.gamma[j]) : mk<R>(0, 0);
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double pv[kNvRB] = {0.0, 0.0, 0.0};
+    if (s < g.V) {
+        const Nbr n = neighbours(g, s);
+        Spinor<R> acca, accb;
+        zero_spinor(acca);
+        zero_spinor(accb);
+        const R ep = (R)emu, em = (R)(1.0 / emu);
+        const Z<R>* r0 = last ? nullptr : rbar_j;
+        const Z<R>* sb = last ? nullptr : sbar_j;
+        hop_dir_bwd_pair<0>(acca, accb, U, r0, wj, ca, sb, g, s, n, ep, em);
+        hop_dir_bwd_pair<1>(acca, accb, U, r0, wj, ca, sb, g, s, n, ep, em);
+        hop_dir_bwd_pair<2>(acca, accb, U, r0, wj, ca, sb, g, s, n, ep, em);
+        hop_dir_bwd_pair<3>(acca, accb, U, r0, wj, ca, sb, g, s, n, ep, em);
+        const R kap = (R)kappa;
+        double d1 = 0.0, d2r = 0.0, d2i = 0.0;
+#pragma unroll
+        for (int p = 0; p < 12; ++p) {
+            const size_t i = (size_t)p * g.ldv + s;
+            const R sg = p < 6 ? R(1) : R(-1);
+            const Z<R> w_s = wj[i];
+            const Z<R> r_s = last ? mk<R>(0, 0) : rbar_j[i];
+            const Z<R> ab_s = r_s + ca * w_s;
+            const Z<R> sb_s = last ? mk<R>(0, 0) : sbar_j[i];
+            const Z<R> HA = sg * (ab_s - kap * acca.c[p / 3][p % 3]);
+            const Z<R> HB = sg * (sb_s - kap * accb.c[p / 3][p % 3]);
+            const Z<R> v_s = vj[i];
+            Z<R> vb = etac * eta[i] + HA;
+            Z<R> a_s;
+            Z<R> wb;
+            if (last) {
+                a_s = a_last[i];
+                wb = abc * a_s;
+            } else {
+                a_s = bn * vn[i] + alr * v_s;
+                if (j >= 2) a_s = a_s + gj * vp[i];
+                vb = vb - alc * r_s;
+                wb = HB + abc * a_s - alr * sb_s;
+                if (carry) {
+                    vb = vb - gnc * rbar_n[i];
+                    wb = wb - bn * sbar_n[i];
+                }
+            }
+            vbar_out[i] = vb;
+            wbar_out[i] = wb;
+            abar_out[i] = ab_s;
+            const ZD x1 = cjmul(zcast<double>(vb), zcast<double>(v_s));
+            const ZD x2 = cjmul(zcast<double>(wb), zcast<double>(w_s));
+            d1 += x1.re;
+            d2r += x2.re;
+            d2i += x2.im;
+        }
+        pv[0] = d1;
+        pv[1] = d2r;
+        pv[2] = d2i;
+    }
+    write_partials<kNvRB, kBlock>(part_out, pv);
+}
+
+template <typename R>
+void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const double* part_in, int npart_in,
+                   Coef coef, int j, int k_used, const Z<R>* rbar_j, const Z<R>* rbar_next, const Z<R>* sbar_j,
+                   const Z<R>* sbar_next, const Z<R>* v_prev, const Z<R>* v_j, const Z<R>* v_next, const Z<R>* w_j,
+                   const Z<R>* a_last, const Z<R>* eta, Z<R>* vbar_out, Z<R>* wbar_out, Z<R>* abar_out,
+                   double* part_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_bwd_rb<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, U, g, kappa, std::exp(mu), part_in,
+                       npart_in, coef, j, k_used, rbar_j, rbar_next, sbar_j, sbar_next, v_prev, v_j, v_next, w_j,
+                       a_last, eta, vbar_out, wbar_out, abar_out, part_out);
+}
+
+// =============================================================== force contraction
+// dS = sum_j Re(abar_j^H dH v_j) + Re(w_j^H dH sbar_j) with H = g5 D_w(mu).
+// For the link U_nu(x) and a pair (p, q) the coefficient of dU is
+//   G_ab += -kappa sum_{s=0,1} [ e_f hP[s][a] conj(hQ[s][b]) + e_b hQ2[s][a] conj(hP2[s][b]) ]
+// with hP = P+(g5 p(x)), hQ = P+(q(x+nu)), hP2 = P-(g5 p(x+nu)), hQ2 = P-(q(x)) the
+// half spinors of the (1 +- g_nu) projectors, e_f = e^{+mu}, e_b = e^{-mu} for nu = t.
+template <int NU, typename R>
+__device__ __forceinline__ void force_pair(ZD (&G)[3][3], const Spinor<R>& p_x, const Spinor<R>& q_x,
+                                           const Spinor<R>& p_y, const Spinor<R>& q_y, double ef, double eb) {
+    Spinor<R> gp_x = p_x, gp_y = p_y;
+    g5_inplace(gp_x);
+    g5_inplace(gp_y);
+    Z<R> hP[2][3], hQ[2][3], hP2[2][3], hQ2[2][3];
+    project<NU, +1>(gp_x, hP);
+    project<NU, +1>(q_y, hQ);
+    project<NU, -1>(gp_y, hP2);
+    project<NU, -1>(q_x, hQ2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            ZD t = mk<double>(0, 0);
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp) {
+                t = t + ef * mulcj(zcast<double>(hP[sp][a]), zcast<double>(hQ[sp][b]));
+                t = t + eb * mulcj(zcast<double>(hQ2[sp][a]), zcast<double>(hP2[sp][b]));
+            }
+            G[a][b] = G[a][b] + t;
+        }
+}
+
+template <int NU, typename R>
+__device__ void force_body(const Geom& g, double kappa, double emu, const Z<R>* __restrict__ abar,
+                           const Z<R>* __restrict__ sbar, const Z<R>* __restrict__ vb, const Z<R>* __restrict__ wb,
+                           size_t fs, int k, int j0, int j1, int s, ZD* __restrict__ gout) {
+    const Nbr n = neighbours(g, s);
+    const int y = n.fwd[NU];
+    const double ef = (NU == 3) ? emu : 1.0, eb = (NU == 3) ? 1.0 / emu : 1.0;
+    ZD G[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) G[a][b] = mk<double>(0, 0);
+    for (int j = j0; j < j1; ++j) {
+        const size_t o = (size_t)(j - 1) * fs;
+        Spinor<R> px, qx, py, qy;
+        load_spinor(px, abar + o, g.ldv, s);
+        load_spinor(qx, vb + o, g.ldv, s);
+        load_spinor(py, abar + o, g.ldv, y);
+        load_spinor(qy, vb + o, g.ldv, y);
+        force_pair<NU>(G, px, qx, py, qy, ef, eb);
+        if (j < k) {
+            load_spinor(px, wb + o, g.ldv, s);
+            load_spinor(qx, sbar + o, g.ldv, s);
+            load_spinor(py, wb + o, g.ldv, y);
+            load_spinor(qy, sbar + o, g.ldv, y);
+            force_pair<NU>(G, px, qx, py, qy, ef, eb);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) gout[(size_t)(NU * 9 + a * 3 + b) * g.ldv + s] = (-kappa) * G[a][b];
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_force(Geom g, double kappa, double emu, const Z<R>* __restrict__ abar,
+                                                  const Z<R>* __restrict__ sbar, const Z<R>* __restrict__ vb,
+                                                  const Z<R>* __restrict__ wb, size_t fs, const int* __restrict__ status,
+                                                  int nchunk, ZD* __restrict__ gpart) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const int k = status[1];
+    const int chunk = blockIdx.y;
+    const int j0 = 1 + (int)((long long)k * chunk / nchunk);
+    const int j1 = 1 + (int)((long long)k * (chunk + 1) / nchunk);
+    ZD* out = gpart + (size_t)chunk * 36 * g.ldv;
+    switch (blockIdx.z) {
+        case 0: force_body<0>(g, kappa, emu, abar, sbar, vb, wb, fs, k, j0, j1, s, out); break;
+        case 1: force_body<1>(g, kappa, emu, abar, sbar, vb, wb, fs, k, j0, j1, s, out); break;
+        case 2: force_body<2>(g, kappa, emu, abar, sbar, vb, wb, fs, k, j0, j1, s, out); break;
+        default: force_body<3>(g, kappa, emu, abar, sbar, vb, wb, fs, k, j0, j1, s, out); break;
+    }
+}
+
+template <typename R>
+void launch_force(const Geom& g, double kappa, double mu, const Z<R>* abar, const Z<R>* sbar, const Z<R>* vb,
+                  const Z<R>* wb, size_t field_stride, const int* status, int nchunk, ZD* gpart, hipStream_t st) {
+    dim3 grid(grid_for(g.V), nchunk, 4);
+    hipLaunchKernelGGL(k_force<R>, grid, dim3(kBlock), 0, st, g, kappa, std::exp(mu), abar, sbar, vb, wb,
+                       field_stride, status, nchunk, gpart);
+}
+
+__global__ __launch_bounds__(kBlock) void k_force_reduce(Geom g, const ZD* __restrict__ gpart, int nchunk,
+                                                         int antiperiodic, ZD* __restrict__ out) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const int nu = blockIdx.y;
+    if (s >= g.V) return;
+    // gradient with respect to the caller's link: undo the folded boundary sign
+    double sign = 1.0;
+    if (nu == 3 && antiperiodic && s / (g.nx * g.ny * g.nz) == g.nt - 1) sign = -1.0;
+#pragma unroll
+    for (int ab = 0; ab < 9; ++ab) {
+        ZD acc = mk<double>(0, 0);
+        for (int c = 0; c < nchunk; ++c) acc = acc + gpart[(size_t)c * 36 * g.ldv + (size_t)(nu * 9 + ab) * g.ldv + s];
+        out[((size_t)nu * g.V + s) * 9 + ab] = sign * acc;
+    }
+}
+
+void launch_force_reduce(const Geom& g, const ZD* gpart, int nchunk, int antiperiodic, ZD* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_force_reduce, dim3(grid_for(g.V), 4), dim3(kBlock), 0, st, g, gpart, nchunk, antiperiodic,
+                       out);
+}
+
+// =============================================================== source gradient
+// x = |x| v_1 with v_1 = w_1 = x/|x|:  xbar = u/|x| + [S/|x| - Re(u^H x)/|x|^2] x/|x|, u = vbar_1 + wbar_1.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_sgrad_dot(Geom g, const Z<R>* __restrict__ vbar,
+                                                      const Z<R>* __restrict__ wbar, const Z<R>* __restrict__ x,
+                                                      double* __restrict__ part) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {0.0};
+    if (s < g.V) {
+#pragma unroll
+        for (int p = 0; p < 12; ++p) {
+            const size_t i = (size_t)p * g.ldv + s;
+            const ZD u = zcast<double>(vbar[i]) + zcast<double>(wbar[i]);
+            v[0] += cjmul(u, zcast<double>(x[i])).re;
+        }
+    }
+    write_partials<1, kBlock>(part, v);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_sgrad_out(Geom g, const Z<R>* __restrict__ vbar,
+                                                      const Z<R>* __restrict__ wbar, const Z<R>* __restrict__ x,
+                                                      const double* __restrict__ part, int npart, Coef coef,
+                                                      ZD* __restrict__ out) {
+    double red[1];
+    reduce_partials<1, kBlock>(part, npart, red);
+    const double nx = coef.misc[0], S = coef.misc[1];
+    const double c2 = (S / nx - red[0] / (nx * nx)) / nx;
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+#pragma unroll
+    for (int p = 0; p < 12; ++p) {
+        const size_t i = (size_t)p * g.ldv + s;
+        const ZD u = zcast<double>(vbar[i]) + zcast<double>(wbar[i]);
+        out[(size_t)s * 12 + p] = (1.0 / nx) * u + c2 * zcast<double>(x[i]);
+    }
+}
+
+template <typename R>
+void launch_source_grad(const Geom& g, const Z<R>* vbar, const Z<R>* wbar, const Z<R>* x, Coef coef, double* part,
+                        ZD* out, hipStream_t st) {
+    const int nb = grid_for(g.V);
+    hipLaunchKernelGGL(k_sgrad_dot<R>, dim3(nb), dim3(kBlock), 0, st, g, vbar, wbar, x, part);
+    hipLaunchKernelGGL(k_sgrad_out<R>, dim3(nb), dim3(kBlock), 0, st, g, vbar, wbar, x, part, nb, coef, out);
+}
+
+// =============================================================== instantiations
+#define TSLOV_INST(R)                                                                                           \
+    template void launch_spinor_to_soa<R>(const ZD*, Z<R>*, const Geom&, double*, hipStream_t);                 \
+    template void launch_spinor_from_soa<R>(const Z<R>*, ZD*, const Geom&, hipStream_t);                        \
+    template void launch_apply<R>(const Z<R>*, const Z<R>*, Z<R>*, const Geom&, double, double, int, int,       \
+                                  hipStream_t);                                                                 \
+    template void launch_fwd_pair<R>(const Z<R>*, const Geom&, double, double, const Z<R>*, const Z<R>*,        \
+                                     const double*, int, int, Coef, int, Z<R>*, Z<R>*, Z<R>*, Z<R>*,            \
+                                     const Z<R>*, double*, hipStream_t);                                        \
+    template void launch_recur<R>(const Geom&, const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, \
+                                  const Z<R>*, const double*, int, Coef, int, int, Z<R>*, Z<R>*, double*,       \
+                                  hipStream_t);                                                                 \
+    template void launch_assemble<R>(const Geom&, const Z<R>*, size_t, Coef, const ZD*, int, ZD*, hipStream_t); \
+    template void launch_bwd_ra<R>(const Geom&, const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*,             \
+                                   const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, const double*, int, Coef, \
+                                   int, Z<R>*, Z<R>*, double*, hipStream_t);                                    \
+    template void launch_bwd_rb<R>(const Z<R>*, const Geom&, double, double, const double*, int, Coef, int, int, \
+                                   const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, \
+                                   const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, Z<R>*, Z<R>*, Z<R>*,     \
+                                   double*, hipStream_t);                                                       \
+    template void launch_force<R>(const Geom&, double, double, const Z<R>*, const Z<R>*, const Z<R>*,           \
+                                  const Z<R>*, size_t, const int*, int, ZD*, hipStream_t);                      \
+    template void launch_source_grad<R>(const Geom&, const Z<R>*, const Z<R>*, const Z<R>*, Coef, double*, ZD*, \
+                                        hipStream_t);
+
+TSLOV_INST(double)
+TSLOV_INST(float)
+
+}  // namespace tslov
