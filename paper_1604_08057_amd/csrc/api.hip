@@ -85,7 +85,7 @@ struct tslov_ctx {
     int links_set = 0;
     Buf U64, U32;
     Buf fields;      // psi, eta, r, s, a, b in the working precision
-    Buf basisV, basisW;
+    Buf basisV, basisW, basisA, basisB;   // v_j, w_j, a_j = H v_j, b_j = H^dag w_j
     Buf abarS, sbarS;
     Buf bwork;       // vbar, wbar, rbar ring
     Buf part;        // partial sums (4 arrays)
@@ -177,9 +177,11 @@ tslov_status ensure_host_part(tslov_ctx* c, int n) {
 }
 
 // Partial-sum arrays: [0] forward pair / RB, [1] recurrence / RA, [2] misc, [3] dense.
-double* part_array(tslov_ctx* c, int i) { return c->part.as<double>() + (size_t)i * 8 * c->nblk(); }
+double* part_array(tslov_ctx* c, int i) { return c->part.as<double>() + (size_t)i * 8 * tslov::np_max(c->g.V); }
 
-tslov_status ensure_part(tslov_ctx* c) { return ensure(c->part, (size_t)4 * 8 * c->nblk() * sizeof(double)); }
+tslov_status ensure_part(tslov_ctx* c) {
+    return ensure(c->part, (size_t)4 * 8 * tslov::np_max(c->g.V) * sizeof(double));
+}
 
 template <typename R>
 Z<R>* fld(const Buf& b, const tslov_ctx* c, int i) { return b.as<Z<R>>() + (size_t)i * c->field_elems(); }
@@ -195,18 +197,18 @@ const Z<R>* links(const tslov_ctx* c) {
 template <typename R>
 tslov_status forward(tslov_ctx* c, const ZD* psi, const ZD* eta, int k, int* k_used, int* breakdown) {
     const Geom& g = c->g;
-    const int nb = c->nblk();
+    const int np_norm = c->nblk(), np_st = tslov::np_stencil(g.V), np_pt = tslov::np_point(g.V);
     CHK(ensure(c->fields, 6 * c->field_elems() * sizeof(Z<R>)));
     CHK(ensure(c->basisV, (size_t)k * c->field_elems() * sizeof(Z<R>)));
     CHK(ensure(c->basisW, (size_t)k * c->field_elems() * sizeof(Z<R>)));
+    CHK(ensure(c->basisA, (size_t)k * c->field_elems() * sizeof(Z<R>)));
+    CHK(ensure(c->basisB, (size_t)k * c->field_elems() * sizeof(Z<R>)));
     CHK(ensure_part(c));
     CHK(ensure_coef(c, k));
     Z<R>* X = fld<R>(c->fields, c, 0);
     Z<R>* E = fld<R>(c->fields, c, 1);
     Z<R>* Rf = fld<R>(c->fields, c, 2);
     Z<R>* Sf = fld<R>(c->fields, c, 3);
-    Z<R>* Af = fld<R>(c->fields, c, 4);
-    Z<R>* Bf = fld<R>(c->fields, c, 5);
     double* p_pair = part_array(c, 0);
     double* p_rec = part_array(c, 1);
     c->status_init[0] = 0;
@@ -220,14 +222,17 @@ tslov_status forward(tslov_ctx* c, const ZD* psi, const ZD* eta, int k, int* k_u
     for (int j = 1; j <= k; ++j) {
         Z<R>* vj = fld<R>(c->basisV, c, j - 1);
         Z<R>* wj = fld<R>(c->basisW, c, j - 1);
+        Z<R>* Af = fld<R>(c->basisA, c, j - 1);
+        Z<R>* Bf = fld<R>(c->basisB, c, j - 1);
         {
             TimedLaunch tl(c, 0);
-            tslov::launch_fwd_pair<R>(U, g, c->kappa, c->mu, j == 1 ? X : Rf, j == 1 ? X : Sf, p_rec, nb, j == 1,
-                                      c->coef, j, vj, wj, Af, Bf, eta ? E : nullptr, p_pair, c->st);
+            tslov::launch_fwd_pair<R>(U, g, c->kappa, c->mu, j == 1 ? X : Rf, j == 1 ? X : Sf, p_rec,
+                                      j == 1 ? np_norm : np_pt, j == 1, c->coef, j, vj, wj, Af, Bf, eta ? E : nullptr,
+                                      p_pair, c->st);
         }
         tslov::launch_recur<R>(g, Af, Bf, vj, wj, j > 1 ? fld<R>(c->basisV, c, j - 2) : nullptr,
-                               j > 1 ? fld<R>(c->basisW, c, j - 2) : nullptr, p_pair, nb, c->coef, j, j == k, Rf, Sf,
-                               p_rec, c->st);
+                               j > 1 ? fld<R>(c->basisW, c, j - 2) : nullptr, p_pair, np_st, c->coef, j, j == k, Rf,
+                               Sf, p_rec, c->st);
     }
     HIPCHK(hipGetLastError());
     int st[4];
@@ -247,7 +252,7 @@ tslov_status ensure_dense(tslov_ctx* c, int k, DenseWork& w) {
     CHK(ensure(c->denseInt, (size_t)2 * k * sizeof(int)));
     CHK(ensure(c->denseLog, (size_t)k * sizeof(double)));
     const int np = tslov::grid_for((int)kk, 256);
-    CHK(ensure(c->densePart, (size_t)(2 * np + 8) * sizeof(double)));
+    CHK(ensure(c->densePart, (size_t)(4 * np + 8) * sizeof(double)));
     CHK(ensure_host_part(c, 2 * np + 8));
     ZD* d = c->dense.as<ZD>();
     w.X = d;
@@ -264,7 +269,7 @@ tslov_status ensure_dense(tslov_ctx* c, int k, DenseWork& w) {
 
 int choose_nb(const tslov_ctx* c, int k) {
     for (int nb : {16, 8, 4, 2, 1})
-        if ((size_t)(k * nb + k) * sizeof(ZD) + 2048 <= c->lds_max) return nb;
+        if ((size_t)(k * (nb + 1)) * sizeof(ZD) + (size_t)k * sizeof(int) + 2048 <= c->lds_max) return nb;
     return 1;
 }
 
@@ -288,7 +293,9 @@ tslov_status newton(tslov_ctx* c, int k, int grad, DenseWork& w, int* iters_out)
         if (!std::isfinite(delta))
             return fail(TSLOV_ERR_SIGN_UNDEFINED, "projected matrix is singular or its sign is undefined");
         if (delta < 1e-2) scaling = 0;
-        const bool conv = delta <= 1e-13 || (delta < 1e-10 && delta > 0.5 * prev);
+        // quadratic convergence: once the step is below 1e-8 the new iterate's error
+        // is at rounding level; stagnation above that also ends the iteration
+        const bool conv = delta <= 1e-8 || (delta < 1e-6 && delta > 0.5 * prev);
         if (conv) {
             if (extra) extra = 0;
             else done = true;
@@ -307,7 +314,7 @@ tslov_status newton(tslov_ctx* c, int k, int grad, DenseWork& w, int* iters_out)
 template <typename R>
 tslov_status backward(tslov_ctx* c, int k, ZD* dU, ZD* dpsi) {
     const Geom& g = c->g;
-    const int nb = c->nblk();
+    const int np_st = tslov::np_stencil(g.V), np_pt = tslov::np_point(g.V);
     CHK(ensure(c->abarS, (size_t)k * c->field_elems() * sizeof(Z<R>)));
     CHK(ensure(c->sbarS, (size_t)k * c->field_elems() * sizeof(Z<R>)));
     CHK(ensure(c->bwork, 4 * c->field_elems() * sizeof(Z<R>)));
@@ -315,23 +322,23 @@ tslov_status backward(tslov_ctx* c, int k, ZD* dU, ZD* dpsi) {
     Z<R>* WB = fld<R>(c->bwork, c, 1);
     Z<R>* X = fld<R>(c->fields, c, 0);
     Z<R>* E = fld<R>(c->fields, c, 1);
-    Z<R>* Af = fld<R>(c->fields, c, 4);
     double* p_rb = part_array(c, 0);
     double* p_ra = part_array(c, 1);
     const Z<R>* U = links<R>(c);
     auto V = [&](int j) { return fld<R>(c->basisV, c, j - 1); };   // v_j, 1-based
     auto W = [&](int j) { return fld<R>(c->basisW, c, j - 1); };
+    auto A = [&](int j) { return fld<R>(c->basisA, c, j - 1); };
+    auto B = [&](int j) { return fld<R>(c->basisB, c, j - 1); };
     auto RB = [&](int j) { return fld<R>(c->bwork, c, 2 + (j & 1)); };
     auto SB = [&](int j) { return fld<R>(c->sbarS, c, j - 1); };
     auto AB = [&](int j) { return fld<R>(c->abarS, c, j - 1); };
     for (int j = k; j >= 1; --j) {
         if (j < k)
             tslov::launch_bwd_ra<R>(g, VB, WB, V(j + 1), W(j + 1), V(j), W(j), j > 1 ? V(j - 1) : nullptr,
-                                    j > 1 ? W(j - 1) : nullptr, p_rb, nb, c->coef, j, RB(j), SB(j), p_ra, c->st);
+                                    j > 1 ? W(j - 1) : nullptr, p_rb, np_st, c->coef, j, RB(j), SB(j), p_ra, c->st);
         TimedLaunch tl(c, 1);
-        tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, p_ra, nb, c->coef, j, k, RB(j), RB(j + 1), SB(j),
-                                j < k ? SB(j + 1) : SB(j), j > 1 ? V(j - 1) : nullptr, V(j), j < k ? V(j + 1) : nullptr,
-                                W(j), Af, E, VB, WB, AB(j), p_rb, c->st);
+        tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, p_ra, np_pt, c->coef, j, k, RB(j), RB(j + 1), SB(j),
+                                j < k ? SB(j + 1) : SB(j), V(j), W(j), A(j), B(j), E, VB, WB, AB(j), p_rb, c->st);
     }
     // force contraction over all steps, split in chunks of j for parallelism
     int nchunk = (1 << 18) / (4 * g.V);
@@ -470,7 +477,8 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
 void tslov_destroy(tslov_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
-    for (Buf* b : {&c->U64, &c->U32, &c->fields, &c->basisV, &c->basisW, &c->abarS, &c->sbarS, &c->bwork, &c->part,
+    for (Buf* b : {&c->U64, &c->U32, &c->fields, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
+                   &c->bwork, &c->part,
                    &c->coefmem, &c->dense, &c->denseInt, &c->denseLog, &c->densePart, &c->gpart})
         release(*b);
     if (c->host_part) (void)hipHostFree(c->host_part);

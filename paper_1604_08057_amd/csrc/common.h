@@ -9,7 +9,15 @@
 namespace tslov {
 
 constexpr int kWave = 64;      // CDNA wavefront
-constexpr int kBlock = 128;    // threads per block of the lattice-field kernels
+constexpr int kBlock = 128;    // threads per block of the simple per-site kernels
+constexpr int kSites = 64;     // sites per block of the colour-split stencil kernels
+constexpr int kCBlock = 3 * kSites;   // one wavefront per colour
+constexpr int kPBlock = 256;   // pointwise kernels: sites per block, grid.y = 12 planes
+
+// Number of per-block partial sums written by each kernel family.
+__host__ __device__ inline int np_stencil(int V) { return (V + kSites - 1) / kSites; }
+__host__ __device__ inline int np_point(int V) { return 12 * ((V + kPBlock - 1) / kPBlock); }
+__host__ __device__ inline int np_max(int V) { return np_stencil(V) > np_point(V) ? np_stencil(V) : np_point(V); }
 
 // ------------------------------------------------------------------ complex
 template <typename R>
@@ -100,20 +108,57 @@ struct Spinor {
     Z<R> c[4][3];
 };
 
+// Field access through raw buffer instructions: the field base and the plane
+// offset are wavefront-uniform (scalar registers), the site offset is one
+// 32-bit vector register shared by every load of a thread, and the hardware
+// range check turns an out-of-range site into a zero load / dropped store.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;   // raw (untyped) buffer, gfx9-family dword 3
+
+template <typename R>
+__device__ __forceinline__ rsrc_t make_rsrc(const Z<R>* base, int nplanes, int ldv) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<Z<R>*>(base), (short)0,
+                                             (int)((unsigned)nplanes * (unsigned)ldv * (unsigned)sizeof(Z<R>)),
+                                             kRsrcWord3);
+}
+
+template <typename R>
+__device__ __forceinline__ Z<R> bload(rsrc_t r, int ldv, int pl, unsigned s) {
+    const unsigned soff = (unsigned)pl * (unsigned)ldv * (unsigned)sizeof(Z<R>);
+    if constexpr (sizeof(R) == 8)
+        return __builtin_bit_cast(Z<R>, __builtin_amdgcn_raw_buffer_load_b128(r, s * 16u, soff, 0));
+    else
+        return __builtin_bit_cast(Z<R>, __builtin_amdgcn_raw_buffer_load_b64(r, s * 8u, soff, 0));
+}
+
+template <typename R>
+__device__ __forceinline__ void bstore(rsrc_t r, int ldv, int pl, unsigned s, Z<R> v) {
+    const unsigned soff = (unsigned)pl * (unsigned)ldv * (unsigned)sizeof(Z<R>);
+    if constexpr (sizeof(R) == 8) {
+        using V4 = __attribute__((ext_vector_type(4))) unsigned;
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, s * 16u, soff, 0);
+    } else {
+        using V2 = __attribute__((ext_vector_type(2))) unsigned;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, s * 8u, soff, 0);
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ void load_spinor(Spinor<R>& p, const Z<R>* __restrict__ f, int ldv, int s) {
+    const rsrc_t r = make_rsrc(f, 12, ldv);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) p.c[sp][c] = f[(sp * 3 + c) * ldv + s];
+        for (int c = 0; c < 3; ++c) p.c[sp][c] = bload<R>(r, ldv, sp * 3 + c, (unsigned)s);
 }
 
 template <typename R>
 __device__ __forceinline__ void store_spinor(Z<R>* __restrict__ f, int ldv, int s, const Spinor<R>& p) {
+    const rsrc_t r = make_rsrc(f, 12, ldv);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) f[(sp * 3 + c) * ldv + s] = p.c[sp][c];
+        for (int c = 0; c < 3; ++c) bstore<R>(r, ldv, sp * 3 + c, (unsigned)s, p.c[sp][c]);
 }
 
 template <typename R>
@@ -129,7 +174,7 @@ __device__ __forceinline__ void load_link(Z<R> (&u)[3][3], const Z<R>* __restric
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) u[a][b] = U[(nu * 9 + a * 3 + b) * ldv + s];
+        for (int b = 0; b < 3; ++b) u[a][b] = bload<R>(make_rsrc(U, 36, ldv), ldv, nu * 9 + a * 3 + b, (unsigned)s);
 }
 
 // ------------------------------------------------------------------ spin projection
@@ -220,6 +265,51 @@ __device__ __forceinline__ void hop_bwd(Spinor<R>& acc, const Z<R> (&u)[3][3], c
     reconstruct_add<NU, -1>(acc, o, coef);
 }
 
+// ------------------------------------------------------------------ one colour
+// Colour-split stencil: a thread owns colour a of a site.  For a hop it needs
+// the neighbour's full half spinor h[2][3] and one row of the (adjoint) link.
+template <int NU, int S, typename R>
+__device__ __forceinline__ void recon1_add(Z<R> (&acc)[4], const Z<R> (&o)[2], R coef) {
+    const Z<R> h0 = coef * o[0], h1 = coef * o[1];
+    acc[0] = acc[0] + h0;
+    acc[1] = acc[1] + h1;
+    Z<R> l2, l3;
+    if (NU == 0) { l2 = timesI(h1); l3 = timesI(h0); }
+    else if (NU == 1) { l2 = h1; l3 = -h0; }
+    else if (NU == 2) { l2 = timesI(h0); l3 = timesMinusI(h1); }
+    else { l2 = h0; l3 = h1; }
+    if (S > 0) { acc[2] = acc[2] + l2; acc[3] = acc[3] + l3; }
+    else { acc[2] = acc[2] - l2; acc[3] = acc[3] - l3; }
+}
+
+// acc += coef * [(1 + S g_NU) u psi]_a with u given by its row a (forward hop,
+// u = U_nu(x)) or by conj of its column a (backward hop, u = U_nu(x-nu)^dag).
+template <int NU, int S, typename R>
+__device__ __forceinline__ void hop1(Z<R> (&acc)[4], const Z<R> (&urow)[3], const Spinor<R>& psi, R coef) {
+    Z<R> h[2][3], o[2];
+    project<NU, S>(psi, h);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) o[s] = urow[0] * h[s][0] + urow[1] * h[s][1] + urow[2] * h[s][2];
+    recon1_add<NU, S>(acc, o, coef);
+}
+
+template <typename R>
+__device__ __forceinline__ void load_row(Z<R> (&u)[3], const Z<R>* __restrict__ U, int ldv, int nu, int a, int s) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) u[b] = bload<R>(make_rsrc(U, 36, ldv), ldv, nu * 9 + a * 3 + b, (unsigned)s);
+}
+
+template <typename R>
+__device__ __forceinline__ void load_col_conj(Z<R> (&u)[3], const Z<R>* __restrict__ U, int ldv, int nu, int a,
+                                              int s) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) u[b] = cj(bload<R>(make_rsrc(U, 36, ldv), ldv, nu * 9 + b * 3 + a, (unsigned)s));
+}
+
+// Colour handled by this thread in the colour-split kernels: one wavefront per
+// colour, made explicit as a scalar so plane addresses stay uniform.
+__device__ __forceinline__ int wave_colour() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kSites); }
+
 // ------------------------------------------------------------------ reductions
 // Deterministic: fixed shuffle tree inside a wave, then waves in index order.
 __device__ __forceinline__ double wave_sum(double v) {
@@ -267,6 +357,15 @@ __device__ __forceinline__ void write_partials(double* __restrict__ part, double
     if (threadIdx.x == 0)
 #pragma unroll
         for (int i = 0; i < NV; ++i) part[blockIdx.x * NV + i] = v[i];
+}
+
+// Same with the partial slot given explicitly (2-D grids).
+template <int NV, int BLK>
+__device__ __forceinline__ void write_partials_at(double* __restrict__ part, int slot, double (&v)[NV]) {
+    block_sum<NV, BLK>(v);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) part[slot * NV + i] = v[i];
 }
 
 // Accumulate conj(a) . b over a spinor into (re, im) in double.

@@ -52,202 +52,219 @@ __global__ __launch_bounds__(kDB) void k_rowperm_init(int* rowperm, int k) {
     if (i < k) rowperm[i] = i;
 }
 
-// Panel K: columns [c0, c0 + nbK) of Wk, all k rows, held in LDS.  For each
-// pivot p = c0 + q: choose the largest |P[i][q]| over rows i >= p (smallest
-// index on ties), swap rows, scale the pivot row, eliminate the column from
-// every other row; column q then holds the transform's column (in-place GJ).
-__global__ __launch_bounds__(kDB) void k_gj_panel(ZD* __restrict__ Wk, int k, int c0, int nb, int* __restrict__ rowperm,
-                                                  int* __restrict__ ipiv, double* __restrict__ logpiv) {
-    extern __shared__ ZD smem[];
-    ZD* P = smem;               // k * nb
-    ZD* fcol = smem + k * nb;   // k
+// Panel K: columns [c0, c0 + nbK) of Wk, all k rows, held in LDS and factored by
+// one block of four wavefronts; thread t owns rows t, t + 256, ...  For each pivot
+// p = c0 + q: the largest |P[i][q]| over rows i >= p (smallest index on ties) is
+// the pivot row imax; with inv = 1/P[imax][q] and prow = P[imax] * inv,
+//   new row p    = prow with column q set to inv,
+//   new row imax = old row p - f prow,  f = old P[p][q]   (the row swap),
+//   new row i    = row i - f prow,       f = P[i][q]   (other rows),
+// and in every eliminated row column q becomes -f inv (in-place Gauss-Jordan: the
+// column then holds the transform's column).  All reads of a pivot step precede
+// its writes, so two block barriers per pivot suffice; no global memory traffic
+// happens inside the loop (a barrier would wait for it).
+template <int NB>
+__global__ __launch_bounds__(kDB) void k_gj_panel(ZD* __restrict__ Wk, int k, int c0, int* __restrict__ rowperm,
+                                                  int* __restrict__ ipiv) {
+    extern __shared__ ZD P[];   // k rows of stride NB + 1 (odd: spreads rows over the LDS banks)
+    constexpr int LD = NB + 1;
+    int* perm = reinterpret_cast<int*>(P + (size_t)k * LD);
+    __shared__ int piv_s[NB];
     __shared__ double wbest[kDB / kWave];
     __shared__ int wi[kDB / kWave];
-    __shared__ int s_imax;
     const int tid = threadIdx.x;
-    const int nbK = min(nb, k - c0);
-    for (int e = tid; e < k * nbK; e += kDB) {
-        const int i = e / nbK, q = e % nbK;
-        P[i * nb + q] = Wk[(size_t)i * k + c0 + q];
+    const int nbK = min(NB, k - c0);
+    for (int i = tid; i < k; i += kDB) perm[i] = rowperm[i];
+#pragma unroll 8
+    for (int e = tid; e < k * NB; e += kDB) {
+        const int i = e / NB, q = e % NB;
+        P[i * LD + q] = Wk[(size_t)i * k + c0 + (q < nbK ? q : nbK - 1)];
     }
     __syncthreads();
     for (int q = 0; q < nbK; ++q) {
         const int p = c0 + q;
         double best = -1.0;
         int bi = k;
-        for (int i = p + tid; i < k; i += kDB) {
-            const double m = norm2(P[i * nb + q]);
+        for (int i = tid; i < k; i += kDB) {
+            const double m = (i >= p) ? norm2(P[i * LD + q]) : -1.0;
             if (m > best) { best = m; bi = i; }
         }
 #pragma unroll
         for (int off = kWave / 2; off > 0; off >>= 1) {
-            const double ob = __shfl_down(best, off, kWave);
-            const int oi = __shfl_down(bi, off, kWave);
+            const double ob = __shfl_xor(best, off, kWave);
+            const int oi = __shfl_xor(bi, off, kWave);
             if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
         }
         if (tid % kWave == 0) { wbest[tid / kWave] = best; wi[tid / kWave] = bi; }
         __syncthreads();
+        double b = wbest[0];
+        int imax = wi[0];
+#pragma unroll
+        for (int w = 1; w < kDB / kWave; ++w)
+            if (wbest[w] > b || (wbest[w] == b && wi[w] < imax)) { b = wbest[w]; imax = wi[w]; }
+        if (imax < p || imax >= k) imax = p;   // non-finite column: keep the order, the NaN propagates
+        // reads: pivot row (all threads), old row p (owner of row imax), own rows' factors
+        const ZD inv = zdiv(mk<double>(1.0, 0.0), P[imax * LD + q]);
+        ZD prow[NB];
+#pragma unroll
+        for (int qq = 0; qq < NB; ++qq) prow[qq] = P[imax * LD + qq] * inv;
+        ZD rowp[NB];
+        ZD fp = mk<double>(0, 0);
+        const bool own_imax = (imax != p) && (imax % kDB == tid);
+        if (own_imax) {   // old row p is overwritten after the barrier: read it now
+#pragma unroll
+            for (int qq = 0; qq < NB; ++qq) rowp[qq] = P[p * LD + qq];
+            fp = P[p * LD + q];
+        }
         if (tid == 0) {
-            double b = wbest[0];
-            int ii = wi[0];
-            for (int w = 1; w < kDB / kWave; ++w)
-                if (wbest[w] > b || (wbest[w] == b && wi[w] < ii)) { b = wbest[w]; ii = wi[w]; }
-            if (ii < p || ii >= k) ii = p;   // non-finite column: keep the row order, the NaN propagates
-            s_imax = ii;
-            ipiv[p] = ii;
-            if (ii != p) {
-                const int t = rowperm[p];
-                rowperm[p] = rowperm[ii];
-                rowperm[ii] = t;
+            piv_s[q] = imax;
+            if (imax != p) {
+                const int t = perm[p];
+                perm[p] = perm[imax];
+                perm[imax] = t;
             }
         }
         __syncthreads();
-        const int imax = s_imax;
-        if (imax != p) {
-            for (int qq = tid; qq < nbK; qq += kDB) {
-                const ZD t = P[p * nb + qq];
-                P[p * nb + qq] = P[imax * nb + qq];
-                P[imax * nb + qq] = t;
+        for (int i = tid; i < k; i += kDB) {
+            if (i == p) {
+#pragma unroll
+                for (int qq = 0; qq < NB; ++qq) P[i * LD + qq] = prow[qq];
+                P[i * LD + q] = inv;
+            } else {
+                ZD row[NB];
+                if (i == imax) {
+#pragma unroll
+                    for (int qq = 0; qq < NB; ++qq) row[qq] = rowp[qq];
+                } else {
+#pragma unroll
+                    for (int qq = 0; qq < NB; ++qq) row[qq] = P[i * LD + qq];
+                }
+                const ZD f = (i == imax) ? fp : P[i * LD + q];
+#pragma unroll
+                for (int qq = 0; qq < NB; ++qq) P[i * LD + qq] = row[qq] - f * prow[qq];
+                P[i * LD + q] = -(f * inv);
             }
-        }
-        __syncthreads();
-        const ZD piv = P[p * nb + q];
-        const ZD inv = zdiv(mk<double>(1.0, 0.0), piv);
-        if (tid == 0) logpiv[p] = 0.5 * std::log(norm2(piv));
-        __syncthreads();
-        for (int qq = tid; qq < nbK; qq += kDB) {
-            const ZD val = (qq == q) ? mk<double>(1.0, 0.0) : P[p * nb + qq];
-            P[p * nb + qq] = val * inv;
-        }
-        for (int i = tid; i < k; i += kDB) fcol[i] = (i == p) ? mk<double>(0, 0) : P[i * nb + q];
-        __syncthreads();
-        for (int e = tid; e < k * nbK; e += kDB) {
-            const int i = e / nbK, qq = e % nbK;
-            if (i == p) continue;
-            const ZD base = (qq == q) ? mk<double>(0, 0) : P[i * nb + qq];
-            P[i * nb + qq] = base - fcol[i] * P[p * nb + qq];
         }
         __syncthreads();
     }
-    for (int e = tid; e < k * nbK; e += kDB) {
-        const int i = e / nbK, q = e % nbK;
-        Wk[(size_t)i * k + c0 + q] = P[i * nb + q];
+    if (tid < nbK) ipiv[c0 + tid] = piv_s[tid];
+    for (int i = tid; i < k; i += kDB) rowperm[i] = perm[i];
+#pragma unroll 8
+    for (int e = tid; e < k * NB; e += kDB) {
+        const int i = e / NB, q = e % NB;
+        if (q < nbK) Wk[(size_t)i * k + c0 + q] = P[i * LD + q];
     }
 }
 
 // Apply panel K's row swaps and transform to TC columns outside the panel:
 // x <- swaps(x);  x_new[i] = [i outside panel] x[i] + sum_q P[i][q] x[c0 + q].
-__global__ __launch_bounds__(kDB) void k_gj_trailing(ZD* __restrict__ Wk, int k, int c0, int nb, int TC,
+// Thread t owns rows i = t, t + 256, ... of the block's TC columns.
+template <int NB>
+__global__ __launch_bounds__(kDB) void k_gj_trailing(ZD* __restrict__ Wk, int k, int c0, int TC,
                                                      const int* __restrict__ ipiv) {
     extern __shared__ ZD smem[];
-    const int nbK = min(nb, k - c0);
-    ZD* xs = smem;              // k * TC
-    ZD* xp = smem + k * TC;     // nbK * TC
+    const int nbK = min(NB, k - c0);
+    const int LT = TC + 1;      // odd row stride: rows spread over the LDS banks
+    ZD* xs = smem;              // k rows of stride LT
+    ZD* xp = smem + k * LT;     // nbK * TC
     const int tid = threadIdx.x;
     const int nother = k - nbK;
     const int cid0 = blockIdx.x * TC;
     const int tcv = min(TC, nother - cid0);
     if (tcv <= 0) return;
-    for (int e = tid; e < k * tcv; e += kDB) {
-        const int i = e / tcv, t = e % tcv;
-        const int cid = cid0 + t;
+    // flat, unrolled staging (TC is a power of two): columns past the last valid
+    // one are clamped instead of branched around, so loads stay in flight
+    const int sh = __builtin_ctz(TC);
+#pragma unroll 8
+    for (int e = tid; e < k * TC; e += kDB) {
+        const int i = e >> sh, t = e & (TC - 1);
+        const int cid = cid0 + (t < tcv ? t : tcv - 1);
         const int c = cid < c0 ? cid : cid + nbK;
-        xs[i * TC + t] = Wk[(size_t)i * k + c];
+        xs[i * LT + t] = Wk[(size_t)i * k + c];
     }
     __syncthreads();
     if (tid < tcv) {
         for (int q = 0; q < nbK; ++q) {
             const int p = c0 + q, im = ipiv[p];
             if (im != p) {
-                const ZD t = xs[p * TC + tid];
-                xs[p * TC + tid] = xs[im * TC + tid];
-                xs[im * TC + tid] = t;
+                const ZD t = xs[p * LT + tid];
+                xs[p * LT + tid] = xs[im * LT + tid];
+                xs[im * LT + tid] = t;
             }
         }
     }
     __syncthreads();
-    for (int e = tid; e < nbK * tcv; e += kDB) {
-        const int q = e / tcv, t = e % tcv;
-        xp[q * TC + t] = xs[(c0 + q) * TC + t];
-    }
+    if (tid < tcv)
+        for (int q = 0; q < nbK; ++q) xp[q * TC + tid] = xs[(c0 + q) * LT + tid];
     __syncthreads();
-    for (int e = tid; e < k * tcv; e += kDB) {
-        const int i = e / tcv, t = e % tcv;
-        const int cid = cid0 + t;
-        const int c = cid < c0 ? cid : cid + nbK;
+    for (int i = tid; i < k; i += kDB) {
         const bool inblk = i >= c0 && i < c0 + nbK;
-        ZD acc = inblk ? mk<double>(0, 0) : xs[i * TC + t];
         const ZD* prow = Wk + (size_t)i * k + c0;
-        for (int q = 0; q < nbK; ++q) acc = acc + prow[q] * xp[q * TC + t];
-        Wk[(size_t)i * k + c] = acc;
+        ZD pr[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) pr[q] = (q < nbK) ? prow[q] : mk<double>(0, 0);
+        for (int t = 0; t < tcv; ++t) {
+            ZD acc = inblk ? mk<double>(0, 0) : xs[i * LT + t];
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (q < nbK) acc = acc + pr[q] * xp[q * TC + t];
+            const int cid = cid0 + t;
+            const int c = cid < c0 ? cid : cid + nbK;
+            Wk[(size_t)i * k + c] = acc;
+        }
     }
 }
 
-// X^{-1}[:, rowperm[i]] = Wk[:, i]; block 0 also forms the scaling mu = |det X|^{-1/k}.
+// X^{-1}[:, rowperm[i]] = Wk[:, i], with per-block partials of |X^{-1}|_F^2 and |X|_F^2.
 __global__ __launch_bounds__(kDB) void k_dense_scatter(const ZD* __restrict__ Wk, const int* __restrict__ rowperm,
-                                                       int k, ZD* __restrict__ Xinv, const double* __restrict__ logpiv,
-                                                       int scaling, double* __restrict__ mu_out) {
+                                                       int k, ZD* __restrict__ Xinv, const ZD* __restrict__ X,
+                                                       double* __restrict__ part) {
     const int idx = blockIdx.x * kDB + threadIdx.x;
-    if (blockIdx.x == 0) {
-        double v[1] = {0.0};
-        for (int i = threadIdx.x; i < k; i += kDB) v[0] += logpiv[i];
-        block_sum<1, kDB>(v);
-        if (threadIdx.x == 0) *mu_out = scaling ? std::exp(-v[0] / k) : 1.0;
+    double v[2] = {0.0, 0.0};
+    if (idx < k * k) {
+        const int r = idx / k, i = idx % k;
+        const ZD w = Wk[idx];
+        Xinv[(size_t)r * k + rowperm[i]] = w;
+        v[0] = norm2(w);
+        v[1] = norm2(X[idx]);
     }
-    if (idx >= k * k) return;
-    const int r = idx / k, i = idx % k;
-    Xinv[(size_t)r * k + rowperm[i]] = Wk[idx];
+    write_partials<2, kDB>(part, v);
+}
+
+// Newton scaling: mu = sqrt(|X^{-1}|_F / |X|_F) while scaling is on, else 1.
+__global__ __launch_bounds__(kDB) void k_dense_mu(const double* __restrict__ part, int npart, int scaling,
+                                                  double* __restrict__ mu_out) {
+    double red[2];
+    reduce_partials<2, kDB>(part, npart, red);
+    if (threadIdx.x == 0) *mu_out = scaling ? std::sqrt(std::sqrt(red[0] / red[1])) : 1.0;
 }
 
 // ------------------------------------------------------------------ complex GEMM
 // mode 0: C = A B;  mode 1: C <- (mu C - (A B)/mu)/2  (mu read from device).
+// 16 x 16 output tiles, one output per thread, 16-deep LDS tiles of A and B.
 __global__ __launch_bounds__(kDB) void k_zgemm(const ZD* __restrict__ A, const ZD* __restrict__ B, ZD* __restrict__ C,
                                                int k, int mode, const double* __restrict__ mu_p) {
-    __shared__ ZD As[32][17];
-    __shared__ ZD Bs[16][33];
-    const int tid = threadIdx.x;
-    const int tx = tid % 16, ty = tid / 16;
-    const int row0 = blockIdx.y * 32, col0 = blockIdx.x * 32;
-    ZD acc[2][2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) acc[u][v] = mk<double>(0, 0);
+    __shared__ ZD As[16][17];
+    __shared__ ZD Bs[16][17];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int r = blockIdx.y * 16 + ty, c = blockIdx.x * 16 + tx;
+    ZD acc = mk<double>(0, 0);
     for (int kk = 0; kk < k; kk += 16) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int e = tid + kDB * u;
-            const int r = e / 16, cc = e % 16;
-            const int gr = row0 + r, gc = kk + cc;
-            As[r][cc] = (gr < k && gc < k) ? A[(size_t)gr * k + gc] : mk<double>(0, 0);
-            const int r2 = e / 32, c2 = e % 32;
-            const int br = kk + r2, bc = col0 + c2;
-            Bs[r2][c2] = (br < k && bc < k) ? B[(size_t)br * k + bc] : mk<double>(0, 0);
-        }
+        As[ty][tx] = (r < k && kk + tx < k) ? A[(size_t)r * k + kk + tx] : mk<double>(0, 0);
+        Bs[ty][tx] = (kk + ty < k && c < k) ? B[(size_t)(kk + ty) * k + c] : mk<double>(0, 0);
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const ZD a0 = As[ty * 2][q], a1 = As[ty * 2 + 1][q];
-            const ZD b0 = Bs[q][tx * 2], b1 = Bs[q][tx * 2 + 1];
-            acc[0][0] = acc[0][0] + a0 * b0;
-            acc[0][1] = acc[0][1] + a0 * b1;
-            acc[1][0] = acc[1][0] + a1 * b0;
-            acc[1][1] = acc[1][1] + a1 * b1;
-        }
+        for (int q = 0; q < 16; ++q) acc = acc + As[ty][q] * Bs[q][tx];
         __syncthreads();
     }
-    const double mu = mode ? *mu_p : 1.0;
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            const int r = row0 + ty * 2 + u, c = col0 + tx * 2 + v;
-            if (r < k && c < k) {
-                const size_t o = (size_t)r * k + c;
-                if (mode == 0) C[o] = acc[u][v];
-                else C[o] = 0.5 * (mu * C[o] - (1.0 / mu) * acc[u][v]);
-            }
+    if (r < k && c < k) {
+        const size_t o = (size_t)r * k + c;
+        if (mode == 0) C[o] = acc;
+        else {
+            const double mu = *mu_p;
+            C[o] = 0.5 * (mu * C[o] - (1.0 / mu) * acc);
         }
+    }
 }
 
 // X <- (mu X + X^{-1}/mu)/2, copy into Wk for the next inversion, partials of
@@ -272,29 +289,46 @@ __global__ __launch_bounds__(kDB) void k_dense_update(ZD* __restrict__ X, ZD* __
 int dense_newton_step(int k, int grad, int scaling, int nb, size_t lds_bytes, DenseWork w, hipStream_t st) {
     hipLaunchKernelGGL(k_rowperm_init, dim3(grid_for(k, kDB)), dim3(kDB), 0, st, w.rowperm, k);
     int* ipiv = w.rowperm + k;
-    const size_t panel_lds = (size_t)(k * nb + k) * sizeof(ZD);
+    const size_t panel_lds = (size_t)(k * (nb + 1)) * sizeof(ZD) + (size_t)k * sizeof(int);
     // trailing tile: TC columns of k + nb complex values each, within the LDS budget
-    int TC = (int)((lds_bytes - 2048) / ((size_t)(k + nb) * sizeof(ZD)));
-    if (TC < 1) TC = 1;
-    if (TC > 16) TC = 16;
+    // trailing tile: TC columns per block; small enough to spread over many CUs,
+    // large enough to amortise each row's panel load, and within the LDS budget
+    const int tc_want = (k - nb) / 96;
+    const int tc_lds = (int)((lds_bytes - 2048) / ((size_t)(k + nb) * sizeof(ZD))) - 1;
+    int TC = 1;   // largest power of two <= min(tc_want, tc_lds, 16)
+    while (TC * 2 <= tc_want && TC * 2 <= tc_lds && TC * 2 <= 16) TC *= 2;
     for (int c0 = 0; c0 < k; c0 += nb) {
-        hipLaunchKernelGGL(k_gj_panel, dim3(1), dim3(kDB), panel_lds, st, w.Wk, k, c0, nb, w.rowperm, ipiv, w.logpiv);
+        switch (nb) {
+            case 16: hipLaunchKernelGGL(k_gj_panel<16>, dim3(1), dim3(kDB), panel_lds, st, w.Wk, k, c0, w.rowperm, ipiv); break;
+            case 8: hipLaunchKernelGGL(k_gj_panel<8>, dim3(1), dim3(kDB), panel_lds, st, w.Wk, k, c0, w.rowperm, ipiv); break;
+            case 4: hipLaunchKernelGGL(k_gj_panel<4>, dim3(1), dim3(kDB), panel_lds, st, w.Wk, k, c0, w.rowperm, ipiv); break;
+            case 2: hipLaunchKernelGGL(k_gj_panel<2>, dim3(1), dim3(kDB), panel_lds, st, w.Wk, k, c0, w.rowperm, ipiv); break;
+            default: hipLaunchKernelGGL(k_gj_panel<1>, dim3(1), dim3(kDB), panel_lds, st, w.Wk, k, c0, w.rowperm, ipiv); break;
+        }
         const int nbK = (k - c0) < nb ? (k - c0) : nb;
         const int nother = k - nbK;
         if (nother > 0) {
-            const size_t tl = (size_t)(k * TC + nbK * TC) * sizeof(ZD);
-            hipLaunchKernelGGL(k_gj_trailing, dim3(grid_for(nother, TC)), dim3(kDB), tl, st, w.Wk, k, c0, nb, TC, ipiv);
+            const size_t tl = (size_t)(k * (TC + 1) + nbK * TC) * sizeof(ZD);
+            const dim3 gt(grid_for(nother, TC));
+            switch (nb) {
+                case 16: hipLaunchKernelGGL(k_gj_trailing<16>, gt, dim3(kDB), tl, st, w.Wk, k, c0, TC, ipiv); break;
+                case 8: hipLaunchKernelGGL(k_gj_trailing<8>, gt, dim3(kDB), tl, st, w.Wk, k, c0, TC, ipiv); break;
+                case 4: hipLaunchKernelGGL(k_gj_trailing<4>, gt, dim3(kDB), tl, st, w.Wk, k, c0, TC, ipiv); break;
+                case 2: hipLaunchKernelGGL(k_gj_trailing<2>, gt, dim3(kDB), tl, st, w.Wk, k, c0, TC, ipiv); break;
+                default: hipLaunchKernelGGL(k_gj_trailing<1>, gt, dim3(kDB), tl, st, w.Wk, k, c0, TC, ipiv); break;
+            }
         }
     }
-    double* mu = w.part + 2 * w.npart_max;   // device scalar after the partials
-    hipLaunchKernelGGL(k_dense_scatter, dim3(grid_for(k * k, kDB)), dim3(kDB), 0, st, w.Wk, w.rowperm, k, w.Xinv,
-                       w.logpiv, scaling, mu);
+    const int nblk = grid_for(k * k, kDB);
+    double* mu = w.part + 4 * w.npart_max;    // device scalar after the partials
+    double* spart = w.part + 2 * w.npart_max;  // norm partials of the scatter
+    hipLaunchKernelGGL(k_dense_scatter, dim3(nblk), dim3(kDB), 0, st, w.Wk, w.rowperm, k, w.Xinv, w.X, spart);
+    hipLaunchKernelGGL(k_dense_mu, dim3(1), dim3(kDB), 0, st, spart, nblk, scaling, mu);
     if (grad) {
-        dim3 g2(grid_for(k, 32), grid_for(k, 32));
+        dim3 g2(grid_for(k, 16), grid_for(k, 16));
         hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w.Xinv, w.Y, w.Zt, k, 0, mu);
         hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w.Zt, w.Xinv, w.Y, k, 1, mu);
     }
-    const int nblk = grid_for(k * k, kDB);
     hipLaunchKernelGGL(k_dense_update, dim3(nblk), dim3(kDB), 0, st, w.X, w.Wk, w.Xinv, k, mu, w.part);
     return nblk;
 }

@@ -29,6 +29,10 @@ __device__ __forceinline__ void g5_inplace(Spinor<R>& p) {
     }
 }
 
+// Compiler barrier for memory operations: keeps the epilogue's own-site loads from
+// being hoisted above the hopping loop, where they would stay live (and spill).
+__device__ __forceinline__ void mem_fence_compiler() { asm volatile("" ::: "memory"); }
+
 // One direction of the hopping sum for a single field.
 template <int NU, typename R>
 __device__ __forceinline__ void hop_dir(Spinor<R>& acc, const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
@@ -64,52 +68,6 @@ __device__ __forceinline__ void hop_dir_pair(Spinor<R>& acca, Spinor<R>& accb, c
     hop_bwd<NU>(acca, u, p, fa_b);
     load_spinor(p, fb, g.ldv, n.bwd[NU]);
     hop_bwd<NU>(accb, u, p, fa_f);
-}
-
-// Pair variant where field A is formed on the fly as fa0 + ca * fa1 (fa0 nullable).
-template <int NU, typename R>
-__device__ __forceinline__ void load_combo(Spinor<R>& p, const Z<R>* __restrict__ f0, const Z<R>* __restrict__ f1,
-                                           Z<R> c1, int ldv, int s) {
-    Spinor<R> q;
-    load_spinor(q, f1, ldv, s);
-    if (f0) {
-        load_spinor(p, f0, ldv, s);
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) p.c[sp][c] = p.c[sp][c] + c1 * q.c[sp][c];
-    } else {
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) p.c[sp][c] = c1 * q.c[sp][c];
-    }
-}
-
-// Backward pair: A = H(-mu) abar with abar = r0 + ca w (on the fly), B = H(+mu) sbar.
-template <int NU, typename R>
-__device__ __forceinline__ void hop_dir_bwd_pair(Spinor<R>& acca, Spinor<R>& accb, const Z<R>* __restrict__ U,
-                                                 const Z<R>* __restrict__ r0, const Z<R>* __restrict__ w,
-                                                 Z<R> ca, const Z<R>* __restrict__ sb, const Geom& g, int s,
-                                                 const Nbr& n, R ep, R em) {
-    // field A runs at -mu: forward temporal factor e^{-mu}, backward e^{+mu}
-    const R a_f = (NU == 3) ? em : R(1), a_b = (NU == 3) ? ep : R(1);
-    Z<R> u[3][3];
-    Spinor<R> p;
-    load_link(u, U, g.ldv, NU, s);
-    load_combo<NU>(p, r0, w, ca, g.ldv, n.fwd[NU]);
-    hop_fwd<NU>(acca, u, p, a_f);
-    if (sb) {
-        load_spinor(p, sb, g.ldv, n.fwd[NU]);
-        hop_fwd<NU>(accb, u, p, a_b);
-    }
-    load_link(u, U, g.ldv, NU, n.bwd[NU]);
-    load_combo<NU>(p, r0, w, ca, g.ldv, n.bwd[NU]);
-    hop_bwd<NU>(acca, u, p, a_b);
-    if (sb) {
-        load_spinor(p, sb, g.ldv, n.bwd[NU]);
-        hop_bwd<NU>(accb, u, p, a_f);
-    }
 }
 
 }  // namespace
@@ -177,53 +135,127 @@ void launch_spinor_from_soa(const Z<R>* in, ZD* out, const Geom& g, hipStream_t 
     hipLaunchKernelGGL(k_spinor_from_soa<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, in, out, g);
 }
 
+// =============================================================== colour-split stencil
+// Blocks of 3 wavefronts: wavefront a handles colour a of 64 consecutive sites, so
+// every load instruction of a wavefront touches 64 consecutive sites of one plane.
+template <typename R>
+struct Spin1 {
+    Z<R> c[4];   // the four spin components of one colour
+};
+
+template <typename R>
+__device__ __forceinline__ void load1(Z<R> (&p)[4], const Z<R>* __restrict__ f, int ldv, int a, int s) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) p[sp] = bload<R>(make_rsrc(f, 12, ldv), ldv, sp * 3 + a, (unsigned)s);
+}
+
+template <typename R>
+__device__ __forceinline__ void store1(Z<R>* __restrict__ f, int ldv, int a, int s, const Z<R> (&p)[4]) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) bstore<R>(make_rsrc(f, 12, ldv), ldv, sp * 3 + a, (unsigned)s, p[sp]);
+}
+
+template <typename R>
+__device__ __forceinline__ void zero1(Z<R> (&p)[4]) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) p[sp] = mk<R>(0, 0);
+}
+
+// Both hops of direction NU for one field (colour a):
+// acc += cf (1+g) U(x) f(x+nu) + cb (1-g) U(x-nu)^dag f(x-nu); f optionally g5-multiplied.
+template <int NU, typename R>
+__device__ __forceinline__ void hop_dir1(Z<R> (&acc)[4], const Z<R>* __restrict__ U, const Z<R>* __restrict__ f,
+                                         const Geom& g, int s, int a, const Nbr& n, R cf, R cb, int g5_in) {
+    Z<R> u[3];
+    Spinor<R> p;
+    load_row(u, U, g.ldv, NU, a, s);
+    load_spinor(p, f, g.ldv, n.fwd[NU]);
+    if (g5_in) g5_inplace(p);
+    hop1<NU, +1>(acc, u, p, cf);
+    load_col_conj(u, U, g.ldv, NU, a, n.bwd[NU]);
+    load_spinor(p, f, g.ldv, n.bwd[NU]);
+    if (g5_in) g5_inplace(p);
+    hop1<NU, -1>(acc, u, p, cb);
+}
+
+// Both hops of direction NU for two fields sharing the link rows: field A at +mu,
+// field B at -mu (the temporal factors swap).
+template <int NU, typename R>
+__device__ __forceinline__ void hop_dir_pair1(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
+                                              const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
+                                              const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
+    const R up = (NU == 3) ? ep : R(1), dn = (NU == 3) ? em : R(1);
+    Z<R> u[3];
+    Spinor<R> p;
+    load_row(u, U, g.ldv, NU, a, s);
+    load_spinor(p, fa, g.ldv, n.fwd[NU]);
+    hop1<NU, +1>(acca, u, p, up);
+    load_spinor(p, fb, g.ldv, n.fwd[NU]);
+    hop1<NU, +1>(accb, u, p, dn);
+    load_col_conj(u, U, g.ldv, NU, a, n.bwd[NU]);
+    load_spinor(p, fa, g.ldv, n.bwd[NU]);
+    hop1<NU, -1>(acca, u, p, dn);
+    load_spinor(p, fb, g.ldv, n.bwd[NU]);
+    hop1<NU, -1>(accb, u, p, up);
+}
+
 // =============================================================== operator
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_apply(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
-                                                  Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em, int g5_in,
-                                                  int g5_out) {
-    const int s = blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kCBlock) void k_apply(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+                                                   Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em, int g5_in,
+                                                   int g5_out) {
+    const int a = wave_colour();
+    const int s = blockIdx.x * kSites + threadIdx.x % kSites;
     if (s >= g.V) return;
     const Nbr n = neighbours(g, s);
-    Spinor<R> acc;
-    zero_spinor(acc);
-    hop_dir<0>(acc, U, in, g, s, n, R(1), R(1), g5_in);
-    hop_dir<1>(acc, U, in, g, s, n, R(1), R(1), g5_in);
-    hop_dir<2>(acc, U, in, g, s, n, R(1), R(1), g5_in);
-    hop_dir<3>(acc, U, in, g, s, n, ep, em, g5_in);
-    Spinor<R> x;
-    load_spinor(x, in, g.ldv, s);
-    if (g5_in) g5_inplace(x);
+    Z<R> acc[4];
+    zero1(acc);
+    // A rolled loop over a wavefront-uniform switch keeps one direction's loads
+    // in flight at a time instead of all eight hops' worth of registers.
+#pragma unroll 1
+    for (int nu = 0; nu < 4; ++nu) {
+        switch (nu) {
+            case 0: hop_dir1<0>(acc, U, in, g, s, a, n, R(1), R(1), g5_in); break;
+            case 1: hop_dir1<1>(acc, U, in, g, s, a, n, R(1), R(1), g5_in); break;
+            case 2: hop_dir1<2>(acc, U, in, g, s, a, n, R(1), R(1), g5_in); break;
+            default: hop_dir1<3>(acc, U, in, g, s, a, n, ep, em, g5_in); break;
+        }
+    }
+    mem_fence_compiler();
+    Z<R> x[4];
+    load1(x, in, g.ldv, a, s);
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) x.c[sp][c] = x.c[sp][c] - kappa * acc.c[sp][c];
-    if (g5_out) g5_inplace(x);
-    store_spinor(out, g.ldv, s, x);
+    for (int sp = 0; sp < 4; ++sp) {
+        const R s_in = (g5_in && sp >= 2) ? R(-1) : R(1);
+        const R s_out = (g5_out && sp >= 2) ? R(-1) : R(1);
+        x[sp] = s_out * (s_in * x[sp] - kappa * acc[sp]);
+    }
+    store1(out, g.ldv, a, s, x);
 }
 
 template <typename R>
 void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu, int g5_in,
                   int g5_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_apply<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, U, in, out, g, (R)kappa,
+    hipLaunchKernelGGL(k_apply<R>, dim3(np_stencil(g.V)), dim3(kCBlock), 0, st, U, in, out, g, (R)kappa,
                        (R)std::exp(mu), (R)std::exp(-mu), g5_in, g5_out);
 }
 
 // =============================================================== forward Lanczos
 // Step j: normalise the previous residuals (v_j = r/beta_j, w_j = s/conj(gamma_j)),
 // apply a = H(mu) v_j and b = H(-mu) w_j = H^dag w_j with shared link loads, and
-// emit per-block partial sums of alpha_j = w_j^H a, |a|^2 and eta^H v_j.
+// emit per-block partial sums of alpha_j = w_j^H a, |a|^2 and eta^H v_j.  At
+// j >= 2 the step first decides breakdown from the previous omega and norms.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
-                                                     const Z<R>* __restrict__ rin, const Z<R>* __restrict__ sin,
-                                                     const double* __restrict__ part_in, int npart_in, int first,
-                                                     Coef coef, int j, Z<R>* __restrict__ vout,
-                                                     Z<R>* __restrict__ wout, Z<R>* __restrict__ aout,
-                                                     Z<R>* __restrict__ bout, const Z<R>* __restrict__ eta,
-                                                     double* __restrict__ part_out) {
+__global__ __launch_bounds__(kCBlock) void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
+                                                      const Z<R>* __restrict__ rin, const Z<R>* __restrict__ sin,
+                                                      const double* __restrict__ part_in, int npart_in, int first,
+                                                      Coef coef, int j, Z<R>* __restrict__ vout,
+                                                      Z<R>* __restrict__ wout, Z<R>* __restrict__ aout,
+                                                      Z<R>* __restrict__ bout, const Z<R>* __restrict__ eta,
+                                                      double* __restrict__ part_out) {
     if (block_flag(coef.status)) return;
     double red[kNvRecur];
-    reduce_partials<kNvRecur, kBlock>(part_in, npart_in, red);
+    reduce_partials<kNvRecur, kCBlock>(part_in, npart_in, red);
     const ZD om = mk<double>(red[0], red[1]);
     const double rn2 = red[2], sn2 = red[3];
     const double aom = std::sqrt(norm2(om));
@@ -251,70 +283,83 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pair(const Z<R>* __restrict__ U,
     }
     const R ib = (R)(1.0 / beta);
     const Z<R> icg = zcast<R>(zdiv(mk<double>(1.0, 0.0), cj(gam)));
-    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const int a = wave_colour();
+    const int s = blockIdx.x * kSites + threadIdx.x % kSites;
     double pv[kNvPair] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (s < g.V) {
         const Nbr n = neighbours(g, s);
-        Spinor<R> acca, accb;
-        zero_spinor(acca);
-        zero_spinor(accb);
+        Z<R> acca[4], accb[4];
+        zero1(acca);
+        zero1(accb);
         const R ep = (R)emu, em = (R)(1.0 / emu);
-        hop_dir_pair<0>(acca, accb, U, rin, sin, g, s, n, ep, em);
-        hop_dir_pair<1>(acca, accb, U, rin, sin, g, s, n, ep, em);
-        hop_dir_pair<2>(acca, accb, U, rin, sin, g, s, n, ep, em);
-        hop_dir_pair<3>(acca, accb, U, rin, sin, g, s, n, ep, em);
-        Spinor<R> r0, s0, v, w, a, b;
-        load_spinor(r0, rin, g.ldv, s);
-        load_spinor(s0, sin, g.ldv, s);
+#pragma unroll 1
+        for (int nu = 0; nu < 4; ++nu) {
+            switch (nu) {
+                case 0: hop_dir_pair1<0>(acca, accb, U, rin, sin, g, s, a, n, ep, em); break;
+                case 1: hop_dir_pair1<1>(acca, accb, U, rin, sin, g, s, a, n, ep, em); break;
+                case 2: hop_dir_pair1<2>(acca, accb, U, rin, sin, g, s, a, n, ep, em); break;
+                default: hop_dir_pair1<3>(acca, accb, U, rin, sin, g, s, a, n, ep, em); break;
+            }
+        }
+        mem_fence_compiler();
+        Z<R> r0[4], s0[4], v[4], w[4], av[4], bv[4];
+        load1(r0, rin, g.ldv, a, s);
+        load1(s0, sin, g.ldv, a, s);
         const R kap = (R)kappa;
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp) {
             const R sg = sp < 2 ? R(1) : R(-1);
+            v[sp] = ib * r0[sp];
+            w[sp] = icg * s0[sp];
+            av[sp] = (sg * ib) * (r0[sp] - kap * acca[sp]);
+            bv[sp] = icg * (sg * (s0[sp] - kap * accb[sp]));
+            const ZD wd = zcast<double>(w[sp]), ad = zcast<double>(av[sp]);
+            const ZD wa = cjmul(wd, ad);
+            pv[0] += wa.re;
+            pv[1] += wa.im;
+            pv[2] += norm2(ad);
+        }
+        store1(vout, g.ldv, a, s, v);
+        store1(wout, g.ldv, a, s, w);
+        store1(aout, g.ldv, a, s, av);
+        store1(bout, g.ldv, a, s, bv);
+        if (eta) {
+            Z<R> e[4];
+            load1(e, eta, g.ldv, a, s);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                v.c[sp][c] = ib * r0.c[sp][c];
-                w.c[sp][c] = icg * s0.c[sp][c];
-                a.c[sp][c] = (sg * ib) * (r0.c[sp][c] - kap * acca.c[sp][c]);
-                b.c[sp][c] = icg * ((sg) * (s0.c[sp][c] - kap * accb.c[sp][c]));
+            for (int sp = 0; sp < 4; ++sp) {
+                const ZD ev = cjmul(zcast<double>(e[sp]), zcast<double>(v[sp]));
+                pv[3] += ev.re;
+                pv[4] += ev.im;
             }
         }
-        store_spinor(vout, g.ldv, s, v);
-        store_spinor(wout, g.ldv, s, w);
-        store_spinor(aout, g.ldv, s, a);
-        store_spinor(bout, g.ldv, s, b);
-        acc_dot(pv[0], pv[1], w, a);
-        pv[2] = spinor_norm2(a);
-        if (eta) {
-            Spinor<R> e;
-            load_spinor(e, eta, g.ldv, s);
-            acc_dot(pv[3], pv[4], e, v);
-        }
     }
-    write_partials<kNvPair, kBlock>(part_out, pv);
+    write_partials<kNvPair, kCBlock>(part_out, pv);
 }
 
 template <typename R>
 void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Z<R>* rin, const Z<R>* sin,
                      const double* part_in, int npart_in, int first, Coef coef, int j, Z<R>* vout, Z<R>* wout,
                      Z<R>* aout, Z<R>* bout, const Z<R>* eta, double* part_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_fwd_pair<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, U, g, kappa, std::exp(mu), rin, sin,
-                       part_in, npart_in, first, coef, j, vout, wout, aout, bout, eta, part_out);
+    hipLaunchKernelGGL(k_fwd_pair<R>, dim3(np_stencil(g.V)), dim3(kCBlock), 0, st, U, g, kappa, std::exp(mu), rin,
+                       sin, part_in, npart_in, first, coef, j, vout, wout, aout, bout, eta, part_out);
 }
 
 // r = a - alpha_j v_j - gamma_j v_{j-1},  s = b - conj(alpha_j) w_j - beta_j w_{j-1},
-// with per-block partials of omega = s^H r, |r|^2, |s|^2.
+// with per-block partials of omega = s^H r, |r|^2, |s|^2.  One thread per
+// (plane, site): grid.y runs over the 12 spin-colour planes.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_recur(Geom g, const Z<R>* __restrict__ a, const Z<R>* __restrict__ b,
-                                                  const Z<R>* __restrict__ v, const Z<R>* __restrict__ w,
-                                                  const Z<R>* __restrict__ vp, const Z<R>* __restrict__ wp,
-                                                  const double* __restrict__ part_in, int npart_in, Coef coef, int j,
-                                                  int last, Z<R>* __restrict__ rout, Z<R>* __restrict__ sout,
-                                                  double* __restrict__ part_out) {
+__global__ __launch_bounds__(kPBlock) void k_recur(Geom g, const Z<R>* __restrict__ a, const Z<R>* __restrict__ b,
+                                                   const Z<R>* __restrict__ v, const Z<R>* __restrict__ w,
+                                                   const Z<R>* __restrict__ vp, const Z<R>* __restrict__ wp,
+                                                   const double* __restrict__ part_in, int npart_in, Coef coef, int j,
+                                                   int last, Z<R>* __restrict__ rout, Z<R>* __restrict__ sout,
+                                                   double* __restrict__ part_out) {
     if (block_flag(coef.status)) return;
     double red[kNvPair];
-    reduce_partials<kNvPair, kBlock>(part_in, npart_in, red);
+    reduce_partials<kNvPair, kPBlock>(part_in, npart_in, red);
     const ZD alpha = mk<double>(red[0], red[1]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         coef.alpha[j] = alpha;
         coef.anorm2[j] = red[2];
         coef.h[j] = mk<double>(red[3], red[4]);
@@ -324,36 +369,34 @@ __global__ __launch_bounds__(kBlock) void k_recur(Geom g, const Z<R>* __restrict
     const bool has_prev = j > 1;
     const Z<R> gj = has_prev ? zcast<R>(coef.gamma[j]) : mk<R>(0, 0);
     const R bj = has_prev ? (R)coef.beta[j] : R(0);
-    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const int s = blockIdx.x * kPBlock + threadIdx.x;
     double pv[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
     if (s < g.V) {
-#pragma unroll
-        for (int p = 0; p < 12; ++p) {
-            const size_t i = (size_t)p * g.ldv + s;
-            Z<R> r = a[i] - al * v[i];
-            Z<R> q = b[i] - alc * w[i];
-            if (has_prev) {
-                r = r - gj * vp[i];
-                q = q - bj * wp[i];
-            }
-            rout[i] = r;
-            sout[i] = q;
-            const double rr = r.re, ri = r.im, qr = q.re, qi = q.im;
-            pv[0] += qr * rr + qi * ri;
-            pv[1] += qr * ri - qi * rr;
-            pv[2] += rr * rr + ri * ri;
-            pv[3] += qr * qr + qi * qi;
+        const size_t i = (size_t)blockIdx.y * g.ldv + s;
+        Z<R> r = a[i] - al * v[i];
+        Z<R> q = b[i] - alc * w[i];
+        if (has_prev) {
+            r = r - gj * vp[i];
+            q = q - bj * wp[i];
         }
+        rout[i] = r;
+        sout[i] = q;
+        const double rr = r.re, ri = r.im, qr = q.re, qi = q.im;
+        pv[0] = qr * rr + qi * ri;
+        pv[1] = qr * ri - qi * rr;
+        pv[2] = rr * rr + ri * ri;
+        pv[3] = qr * qr + qi * qi;
     }
-    write_partials<kNvRecur, kBlock>(part_out, pv);
+    write_partials_at<kNvRecur, kPBlock>(part_out, blockIdx.y * gridDim.x + blockIdx.x, pv);
 }
 
 template <typename R>
 void launch_recur(const Geom& g, const Z<R>* a, const Z<R>* b, const Z<R>* v, const Z<R>* w, const Z<R>* vp,
                   const Z<R>* wp, const double* part_in, int npart_in, Coef coef, int j, int last, Z<R>* rout,
                   Z<R>* sout, double* part_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_recur<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, g, a, b, v, w, vp, wp, part_in,
-                       npart_in, coef, j, last, rout, sout, part_out);
+    dim3 grid((g.V + kPBlock - 1) / kPBlock, 12);
+    hipLaunchKernelGGL(k_recur<R>, grid, dim3(kPBlock), 0, st, g, a, b, v, w, vp, wp, part_in, npart_in, coef, j,
+                       last, rout, sout, part_out);
 }
 
 // out(s) = [psi(s) +] g5^{overlap} |x| sum_{j <= k_used} c_j v_j(s), canonical layout.
@@ -398,15 +441,15 @@ void launch_assemble(const Geom& g, const Z<R>* basis, size_t field_stride, Coef
 //   sbar_j = wbar_{j+1}/gamma + conj(omegabar) beta v_{j+1},
 // and partials P1 = v_j^H rbar, P2 = sbar^H w_j, P3 = v_{j-1}^H rbar, P4 = w_{j-1}^H sbar.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_bwd_ra(Geom g, const Z<R>* __restrict__ vbar, const Z<R>* __restrict__ wbar,
-                                                   const Z<R>* __restrict__ vn, const Z<R>* __restrict__ wn,
-                                                   const Z<R>* __restrict__ vj, const Z<R>* __restrict__ wj,
-                                                   const Z<R>* __restrict__ vp, const Z<R>* __restrict__ wp,
-                                                   const double* __restrict__ part_in, int npart_in, Coef coef,
-                                                   int j, Z<R>* __restrict__ rbar, Z<R>* __restrict__ sbar,
-                                                   double* __restrict__ part_out) {
+__global__ __launch_bounds__(kPBlock) void k_bwd_ra(Geom g, const Z<R>* __restrict__ vbar,
+                                                    const Z<R>* __restrict__ wbar, const Z<R>* __restrict__ vn,
+                                                    const Z<R>* __restrict__ wn, const Z<R>* __restrict__ vj,
+                                                    const Z<R>* __restrict__ wj, const Z<R>* __restrict__ vp,
+                                                    const Z<R>* __restrict__ wp, const double* __restrict__ part_in,
+                                                    int npart_in, Coef coef, int j, Z<R>* __restrict__ rbar,
+                                                    Z<R>* __restrict__ sbar, double* __restrict__ part_out) {
     double red[kNvRB];
-    reduce_partials<kNvRB, kBlock>(part_in, npart_in, red);
+    reduce_partials<kNvRB, kPBlock>(part_in, npart_in, red);
     const double D1 = red[0];
     const ZD D2 = mk<double>(red[1], red[2]);
     const double beta = coef.beta[j + 1];
@@ -422,30 +465,27 @@ __global__ __launch_bounds__(kBlock) void k_bwd_ra(Geom g, const Z<R>* __restric
     const Z<R> c3 = zcast<R>(zdiv(mk<double>(1.0, 0.0), gam));   // 1/gamma
     const Z<R> c4 = zcast<R>(beta * cj(ombar));                  // conj(omegabar) beta
     const bool has_prev = vp != nullptr;
-    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const int s = blockIdx.x * kPBlock + threadIdx.x;
     double pv[kNvRA] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (s < g.V) {
-#pragma unroll
-        for (int p = 0; p < 12; ++p) {
-            const size_t i = (size_t)p * g.ldv + s;
-            const Z<R> r = c1 * vbar[i] + c2 * wn[i];
-            const Z<R> q = c3 * wbar[i] + c4 * vn[i];
-            rbar[i] = r;
-            sbar[i] = q;
-            const ZD rd = zcast<double>(r), qd = zcast<double>(q);
-            const ZD p1 = cjmul(zcast<double>(vj[i]), rd);
-            const ZD p2 = cjmul(qd, zcast<double>(wj[i]));
-            pv[0] += p1.re; pv[1] += p1.im;
-            pv[2] += p2.re; pv[3] += p2.im;
-            if (has_prev) {
-                const ZD p3 = cjmul(zcast<double>(vp[i]), rd);
-                const ZD p4 = cjmul(zcast<double>(wp[i]), qd);
-                pv[4] += p3.re; pv[5] += p3.im;
-                pv[6] += p4.re; pv[7] += p4.im;
-            }
+        const size_t i = (size_t)blockIdx.y * g.ldv + s;
+        const Z<R> r = c1 * vbar[i] + c2 * wn[i];
+        const Z<R> q = c3 * wbar[i] + c4 * vn[i];
+        rbar[i] = r;
+        sbar[i] = q;
+        const ZD rd = zcast<double>(r), qd = zcast<double>(q);
+        const ZD p1 = cjmul(zcast<double>(vj[i]), rd);
+        const ZD p2 = cjmul(qd, zcast<double>(wj[i]));
+        pv[0] = p1.re; pv[1] = p1.im;
+        pv[2] = p2.re; pv[3] = p2.im;
+        if (has_prev) {
+            const ZD p3 = cjmul(zcast<double>(vp[i]), rd);
+            const ZD p4 = cjmul(zcast<double>(wp[i]), qd);
+            pv[4] = p3.re; pv[5] = p3.im;
+            pv[6] = p4.re; pv[7] = p4.im;
         }
     }
-    write_partials<kNvRA, kBlock>(part_out, pv);
+    write_partials_at<kNvRA, kPBlock>(part_out, blockIdx.y * gridDim.x + blockIdx.x, pv);
 }
 
 template <typename R>
@@ -453,31 +493,34 @@ void launch_bwd_ra(const Geom& g, const Z<R>* vbar, const Z<R>* wbar, const Z<R>
                    const Z<R>* v_j, const Z<R>* w_j, const Z<R>* v_prev, const Z<R>* w_prev, const double* part_in,
                    int npart_in, Coef coef, int j, Z<R>* rbar_out, Z<R>* sbar_out, double* part_out,
                    hipStream_t st) {
-    hipLaunchKernelGGL(k_bwd_ra<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, g, vbar, wbar, v_next, w_next, v_j,
-                       w_j, v_prev, w_prev, part_in, npart_in, coef, j, rbar_out, sbar_out, part_out);
+    dim3 grid((g.V + kPBlock - 1) / kPBlock, 12);
+    hipLaunchKernelGGL(k_bwd_ra<R>, grid, dim3(kPBlock), 0, st, g, vbar, wbar, v_next, w_next, v_j, w_j, v_prev,
+                       w_prev, part_in, npart_in, coef, j, rbar_out, sbar_out, part_out);
 }
 
 // Reverse of a_j = H v_j, b_j = H^dag w_j, alpha_j = w_j^H a_j and of the recurrence:
 //   alphabar_j = conj(Gamma_jj) - v_j^H rbar_j - sbar_j^H w_j,   abar_j = rbar_j + alphabar_j w_j,
-//   vbar_j = |x| conj(c_j) eta + H^dag abar_j - conj(alpha_j) rbar_j - conj(gamma_{j+1}) rbar_{j+1},
+//   vbar_j = |x| conj(c_j) eta + H^dag rbar_j + alphabar_j b_j - conj(alpha_j) rbar_j - conj(gamma_{j+1}) rbar_{j+1},
 //   wbar_j = H sbar_j + conj(alphabar_j) a_j - alpha_j sbar_j - beta_{j+1} sbar_{j+1},
-// storing abar_j for the force and emitting partials of Re vbar_j^H v_j, wbar_j^H w_j.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
-                                                   const double* __restrict__ part_in, int npart_in, Coef coef,
-                                                   int j, int k_used, const Z<R>* __restrict__ rbar_j,
-                                                   const Z<R>* __restrict__ rbar_n, const Z<R>* __restrict__ sbar_j,
-                                                   const Z<R>* __restrict__ sbar_n, const Z<R>* __restrict__ vp,
-                                                   const Z<R>* __restrict__ vj, const Z<R>* __restrict__ vn,
-                                                   const Z<R>* __restrict__ wj, const Z<R>* __restrict__ a_last,
-                                                   const Z<R>* __restrict__ eta, Z<R>* __restrict__ vbar_out,
-                                                   Z<R>* __restrict__ wbar_out, Z<R>* __restrict__ abar_out,
-                                                   double* __restrict__ part_out) {
-    const bool last = (j == k_used);
+// using the forward pass's a_j and b_j = H^dag w_j, so the stencil acts on rbar_j
+// (at -mu) and sbar_j (at +mu) only.  Stores abar_j for the force and emits
+// partials of Re vbar_j^H v_j and wbar_j^H w_j.  The last step (j = k_used) has
+// no residual adjoints: abar = alphabar w, vbar = |x| conj(c) eta + alphabar b,
+// wbar = conj(alphabar) a.
+template <typename R, bool LAST>
+__global__ __launch_bounds__(kCBlock) void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
+                                                    const double* __restrict__ part_in, int npart_in, Coef coef,
+                                                    int j, int k_used, const Z<R>* __restrict__ rbar_j,
+                                                    const Z<R>* __restrict__ rbar_n, const Z<R>* __restrict__ sbar_j,
+                                                    const Z<R>* __restrict__ sbar_n, const Z<R>* __restrict__ vj,
+                                                    const Z<R>* __restrict__ wj, const Z<R>* __restrict__ aj,
+                                                    const Z<R>* __restrict__ bj, const Z<R>* __restrict__ eta,
+                                                    Z<R>* __restrict__ vbar_out, Z<R>* __restrict__ wbar_out,
+                                                    Z<R>* __restrict__ abar_out, double* __restrict__ part_out) {
     ZD abar = coef.abar_T[j];
-    if (!last) {
+    if (!LAST) {
         double red[kNvRA];
-        reduce_partials<kNvRA, kBlock>(part_in, npart_in, red);
+        reduce_partials<kNvRA, kCBlock>(part_in, npart_in, red);
         abar = abar - mk<double>(red[0], red[1]) - mk<double>(red[2], red[3]);
         if (blockIdx.x == 0 && threadIdx.x == 0 && j >= 2) {
             coef.gbar_tot[j] = coef.gbar_T[j] - mk<double>(red[4], red[5]);
@@ -490,76 +533,90 @@ __global__ __launch_bounds__(kBlock) void k_bwd_rb(const Z<R>* __restrict__ U, G
     const Z<R> alr = zcast<R>(alpha), alc = zcast<R>(cj(alpha)), abc = zcast<R>(cj(abar));
     const Z<R> etac = zcast<R>(coef.misc[0] * cj(coef.c[j]));
     const Z<R> gnc = carry ? zcast<R>(cj(coef.gamma[j + 1])) : mk<R>(0, 0);
-    const R bn = last ? R(0) : (R)coef.beta[j + 1];
-    const Z<R> gj = (j >= 2) ? zcast<R>(coef.gamma[j]) : mk<R>(0, 0);
-    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const R bn = carry ? (R)coef.beta[j + 1] : R(0);
+    const int a = wave_colour();
+    const int s = blockIdx.x * kSites + threadIdx.x % kSites;
     double pv[kNvRB] = {0.0, 0.0, 0.0};
     if (s < g.V) {
-        const Nbr n = neighbours(g, s);
-        Spinor<R> acca, accb;
-        zero_spinor(acca);
-        zero_spinor(accb);
-        const R ep = (R)emu, em = (R)(1.0 / emu);
-        const Z<R>* r0 = last ? nullptr : rbar_j;
-        const Z<R>* sb = last ? nullptr : sbar_j;
-        hop_dir_bwd_pair<0>(acca, accb, U, r0, wj, ca, sb, g, s, n, ep, em);
-        hop_dir_bwd_pair<1>(acca, accb, U, r0, wj, ca, sb, g, s, n, ep, em);
-        hop_dir_bwd_pair<2>(acca, accb, U, r0, wj, ca, sb, g, s, n, ep, em);
-        hop_dir_bwd_pair<3>(acca, accb, U, r0, wj, ca, sb, g, s, n, ep, em);
-        const R kap = (R)kappa;
-        double d1 = 0.0, d2r = 0.0, d2i = 0.0;
-#pragma unroll
-        for (int p = 0; p < 12; ++p) {
-            const size_t i = (size_t)p * g.ldv + s;
-            const R sg = p < 6 ? R(1) : R(-1);
-            const Z<R> w_s = wj[i];
-            const Z<R> r_s = last ? mk<R>(0, 0) : rbar_j[i];
-            const Z<R> ab_s = r_s + ca * w_s;
-            const Z<R> sb_s = last ? mk<R>(0, 0) : sbar_j[i];
-            const Z<R> HA = sg * (ab_s - kap * acca.c[p / 3][p % 3]);
-            const Z<R> HB = sg * (sb_s - kap * accb.c[p / 3][p % 3]);
-            const Z<R> v_s = vj[i];
-            Z<R> vb = etac * eta[i] + HA;
-            Z<R> a_s;
-            Z<R> wb;
-            if (last) {
-                a_s = a_last[i];
-                wb = abc * a_s;
-            } else {
-                a_s = bn * vn[i] + alr * v_s;
-                if (j >= 2) a_s = a_s + gj * vp[i];
-                vb = vb - alc * r_s;
-                wb = HB + abc * a_s - alr * sb_s;
-                if (carry) {
-                    vb = vb - gnc * rbar_n[i];
-                    wb = wb - bn * sbar_n[i];
+        Z<R> accs[4], accr[4];
+        zero1(accs);
+        zero1(accr);
+        if (!LAST) {
+            const Nbr n = neighbours(g, s);
+            const R ep = (R)emu, em = (R)(1.0 / emu);
+            // field A = sbar_j at +mu (accs), field B = rbar_j at -mu (accr)
+#pragma unroll 1
+            for (int nu = 0; nu < 4; ++nu) {
+                switch (nu) {
+                    case 0: hop_dir_pair1<0>(accs, accr, U, sbar_j, rbar_j, g, s, a, n, ep, em); break;
+                    case 1: hop_dir_pair1<1>(accs, accr, U, sbar_j, rbar_j, g, s, a, n, ep, em); break;
+                    case 2: hop_dir_pair1<2>(accs, accr, U, sbar_j, rbar_j, g, s, a, n, ep, em); break;
+                    default: hop_dir_pair1<3>(accs, accr, U, sbar_j, rbar_j, g, s, a, n, ep, em); break;
                 }
             }
-            vbar_out[i] = vb;
-            wbar_out[i] = wb;
-            abar_out[i] = ab_s;
+            mem_fence_compiler();
+        }
+        const R kap = (R)kappa;
+        const rsrc_t rw = make_rsrc(wj, 12, g.ldv), rv = make_rsrc(vj, 12, g.ldv), ra = make_rsrc(aj, 12, g.ldv),
+                     rb = make_rsrc(bj, 12, g.ldv), re = make_rsrc(eta, 12, g.ldv);
+        Z<R> vbo[4], wbo[4], abo[4];
+        double d1 = 0.0, d2r = 0.0, d2i = 0.0;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            const int pl = sp * 3 + a;
+            const unsigned i = (unsigned)s;
+            const R sg = sp < 2 ? R(1) : R(-1);
+            const Z<R> w_s = bload<R>(rw, g.ldv, pl, i);
+            const Z<R> v_s = bload<R>(rv, g.ldv, pl, i);
+            const Z<R> a_s = bload<R>(ra, g.ldv, pl, i);
+            const Z<R> b_s = bload<R>(rb, g.ldv, pl, i);
+            Z<R> vb = etac * bload<R>(re, g.ldv, pl, i) + ca * b_s;
+            Z<R> wb = abc * a_s;
+            Z<R> ab_s = ca * w_s;
+            if (!LAST) {
+                const Z<R> r_s = bload<R>(make_rsrc(rbar_j, 12, g.ldv), g.ldv, pl, i);
+                const Z<R> sb_s = bload<R>(make_rsrc(sbar_j, 12, g.ldv), g.ldv, pl, i);
+                ab_s = ab_s + r_s;
+                vb = vb + sg * (r_s - kap * accr[sp]) - alc * r_s;
+                wb = wb + sg * (sb_s - kap * accs[sp]) - alr * sb_s;
+                if (carry) {
+                    vb = vb - gnc * bload<R>(make_rsrc(rbar_n, 12, g.ldv), g.ldv, pl, i);
+                    wb = wb - bn * bload<R>(make_rsrc(sbar_n, 12, g.ldv), g.ldv, pl, i);
+                }
+            }
+            vbo[sp] = vb;
+            wbo[sp] = wb;
+            abo[sp] = ab_s;
             const ZD x1 = cjmul(zcast<double>(vb), zcast<double>(v_s));
             const ZD x2 = cjmul(zcast<double>(wb), zcast<double>(w_s));
             d1 += x1.re;
             d2r += x2.re;
             d2i += x2.im;
         }
+        store1(vbar_out, g.ldv, a, s, vbo);
+        store1(wbar_out, g.ldv, a, s, wbo);
+        store1(abar_out, g.ldv, a, s, abo);
         pv[0] = d1;
         pv[1] = d2r;
         pv[2] = d2i;
     }
-    write_partials<kNvRB, kBlock>(part_out, pv);
+    write_partials<kNvRB, kCBlock>(part_out, pv);
 }
 
 template <typename R>
 void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const double* part_in, int npart_in,
                    Coef coef, int j, int k_used, const Z<R>* rbar_j, const Z<R>* rbar_next, const Z<R>* sbar_j,
-                   const Z<R>* sbar_next, const Z<R>* v_prev, const Z<R>* v_j, const Z<R>* v_next, const Z<R>* w_j,
-                   const Z<R>* a_last, const Z<R>* eta, Z<R>* vbar_out, Z<R>* wbar_out, Z<R>* abar_out,
-                   double* part_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_bwd_rb<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, U, g, kappa, std::exp(mu), part_in,
-                       npart_in, coef, j, k_used, rbar_j, rbar_next, sbar_j, sbar_next, v_prev, v_j, v_next, w_j,
-                       a_last, eta, vbar_out, wbar_out, abar_out, part_out);
+                   const Z<R>* sbar_next, const Z<R>* v_j, const Z<R>* w_j, const Z<R>* a_j, const Z<R>* b_j,
+                   const Z<R>* eta, Z<R>* vbar_out, Z<R>* wbar_out, Z<R>* abar_out, double* part_out,
+                   hipStream_t st) {
+    if (j == k_used)
+        hipLaunchKernelGGL((k_bwd_rb<R, true>), dim3(np_stencil(g.V)), dim3(kCBlock), 0, st, U, g, kappa,
+                           std::exp(mu), part_in, npart_in, coef, j, k_used, rbar_j, rbar_next, sbar_j, sbar_next,
+                           v_j, w_j, a_j, b_j, eta, vbar_out, wbar_out, abar_out, part_out);
+    else
+        hipLaunchKernelGGL((k_bwd_rb<R, false>), dim3(np_stencil(g.V)), dim3(kCBlock), 0, st, U, g, kappa,
+                           std::exp(mu), part_in, npart_in, coef, j, k_used, rbar_j, rbar_next, sbar_j, sbar_next,
+                           v_j, w_j, a_j, b_j, eta, vbar_out, wbar_out, abar_out, part_out);
 }
 
 // =============================================================== force contraction
@@ -740,8 +797,8 @@ void launch_source_grad(const Geom& g, const Z<R>* vbar, const Z<R>* wbar, const
                                    int, Z<R>*, Z<R>*, double*, hipStream_t);                                    \
     template void launch_bwd_rb<R>(const Z<R>*, const Geom&, double, double, const double*, int, Coef, int, int, \
                                    const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, \
-                                   const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, Z<R>*, Z<R>*, Z<R>*,     \
-                                   double*, hipStream_t);                                                       \
+                                   const Z<R>*, const Z<R>*, const Z<R>*, Z<R>*, Z<R>*, Z<R>*, double*,         \
+                                   hipStream_t);                                                                \
     template void launch_force<R>(const Geom&, double, double, const Z<R>*, const Z<R>*, const Z<R>*,           \
                                   const Z<R>*, size_t, const int*, int, ZD*, hipStream_t);                      \
     template void launch_source_grad<R>(const Geom&, const Z<R>*, const Z<R>*, const Z<R>*, Coef, double*, ZD*, \

@@ -54,9 +54,9 @@ void launch_bwd_ra(const Geom& g, const Z<R>* vbar, const Z<R>* wbar, const Z<R>
 template <typename R>
 void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const double* part_in, int npart_in,
                    Coef coef, int j, int k_used, const Z<R>* rbar_j, const Z<R>* rbar_next,
-                   const Z<R>* sbar_j, const Z<R>* sbar_next, const Z<R>* v_prev, const Z<R>* v_j,
-                   const Z<R>* v_next, const Z<R>* w_j, const Z<R>* a_last, const Z<R>* eta,
-                   Z<R>* vbar_out, Z<R>* wbar_out, Z<R>* abar_out, double* part_out, hipStream_t st);
+                   const Z<R>* sbar_j, const Z<R>* sbar_next, const Z<R>* v_j, const Z<R>* w_j,
+                   const Z<R>* a_j, const Z<R>* b_j, const Z<R>* eta, Z<R>* vbar_out, Z<R>* wbar_out,
+                   Z<R>* abar_out, double* part_out, hipStream_t st);
 template <typename R>
 void launch_force(const Geom& g, double kappa, double mu, const Z<R>* abar, const Z<R>* sbar, const Z<R>* vb,
                   const Z<R>* wb, size_t field_stride, const int* status, int nchunk, ZD* gpart, hipStream_t st);
