@@ -92,9 +92,15 @@ tslov_status tslov_apply_dw(tslov_ctx* ctx, const void* in, void* out, int dagge
  * Sec. 1 (definition after eq. overlap). */
 tslov_status tslov_apply_h(tslov_ctx* ctx, const void* in, void* out, int dagger);
 
-/* Optional deflation by known eigenpairs of H (Sec. 3 eq. final_res, App. E);
- * R, L: l canonical spinors each (device), biorthonormal L_i^H R_j = delta_ij;
- * lambda: host array of 2*l doubles (re, im).  Not supported yet: pass NULL. */
+/* Optional deflation by known eigenpairs of H (Sec. 3: the standard projection
+ * for a diagonalisable matrix, eq. final_res without the mixing term):
+ *   c_i = L_i^H psi,  psi_p = psi - sum_i c_i R_i,
+ *   sgn(H) psi = TSL(psi_p) + sum_i sgn(Re lambda_i) c_i R_i.
+ * R, L: l canonical spinors each, contiguous ([l][V][4][3] complex128, device),
+ * right and left eigenvectors of H with L_i^H R_j = delta_ij (caller's
+ * normalisation; not checked); lambda: host array of 2*l doubles (re, im);
+ * 0 <= l <= 256.  An eigenvalue with |Re| <= 1e-12 max|lambda| gives
+ * ERR_SIGN_UNDEFINED.  The caller keeps ownership. */
 typedef struct tslov_deflation {
     int l;
     const void* R;
@@ -106,7 +112,8 @@ typedef struct tslov_deflation {
  * (Sec. 2: Krylov spaces of H and H^dagger from the same source; v_1 = w_1 = psi/|psi|),
  * k >= 1 basis vectors (k <= 1024).  A lucky breakdown returns OK with
  * info->k_used < k and the exact result on the invariant space; a serious
- * breakdown returns ERR_BREAKDOWN (out undefined).  info may be NULL. */
+ * breakdown returns ERR_BREAKDOWN (out undefined); a zero (projected) source
+ * gives k_used = 0.  defl may be NULL.  info may be NULL. */
 tslov_status tslov_sign(tslov_ctx* ctx, const void* psi, void* out, int k,
                         const tslov_deflation* defl, tslov_info* info);
 
@@ -122,11 +129,18 @@ tslov_status tslov_overlap(tslov_ctx* ctx, const void* psi, void* out, int k,
  *   so dS = Re tr(dU_out^H dU);  the U(1) link-phase derivative is -Im tr(dU_out^H U).
  * dpsi_out (nullable, canonical spinor) receives dS/dRe psi + i dS/dIm psi.
  * S_out is a host pointer.  recompute_stride must be 0 (all Krylov vectors are
- * stored; 2*k*12*V complex values of workspace).  For D_ov the caller passes
- * g5 eta and adds Re <eta|psi>. */
+ * stored; 6*k*12*V complex values of workspace).  For D_ov the caller passes
+ * g5 eta and adds Re <eta|psi>.  defl must be NULL or have l = 0 (the derivative
+ * of the deflated sign, with its eigenpair motion, is not provided). */
 tslov_status tslov_sign_grad(tslov_ctx* ctx, const void* eta, const void* psi, int k,
                              const tslov_deflation* defl, int recompute_stride,
                              double* S_out, void* dU_out, void* dpsi_out, tslov_info* info);
+
+/* A-posteriori error estimate (Sec. 4.1, eq. error_est): with y = TSL(psi) and
+ * z = TSL(y) (a fresh Krylov space with source y, same k and deflation),
+ * eps_A = |z - psi| / (2 |psi|).  eps_out: host double. */
+tslov_status tslov_error_estimate(tslov_ctx* ctx, const void* psi, int k, const tslov_deflation* defl,
+                                  double* eps_out);
 
 /* Projected-matrix step on its own (for tests): S = sgn(T) for a dense complex128
  * k x k row-major device matrix T by the scaled Newton iteration, and, if E is

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -71,6 +72,7 @@ double now_ms() {
 }
 
 constexpr int kMaxK = 1024;
+constexpr int kMaxDeflSet = 256;
 constexpr int kTimingClasses = 3;
 
 }  // namespace
@@ -92,6 +94,8 @@ struct tslov_ctx {
     Buf coefmem;
     Buf dense, denseInt, denseLog, densePart;
     Buf gpart;
+    Buf canon;       // three canonical spinors: projected source, partial result, error estimate
+    Buf deflw;       // deflation coefficients, signs and partial sums
     double* host_part = nullptr;  // pinned
     int host_part_n = 0;
     int kcap = 0;
@@ -358,25 +362,88 @@ tslov_status check_common(tslov_ctx* c, int k, const tslov_deflation* defl) {
     if (!c) return fail(TSLOV_ERR_ARG, "null context");
     if (!c->links_set) return fail(TSLOV_ERR_ARG, "links not set (call tslov_set_links first)");
     if (k < 1 || k > kMaxK) return fail(TSLOV_ERR_ARG, "k must be in [1, 1024]");
-    if (defl && defl->l != 0) return fail(TSLOV_ERR_ARG, "deflation is not supported by this build (pass NULL)");
+    if (defl && (defl->l < 0 || defl->l > kMaxDeflSet)) return fail(TSLOV_ERR_ARG, "deflation size must be in [0, 256]");
     return TSLOV_OK;
 }
 
+// Deflation set: validated on the host, signs copied to the device.
+struct DeflSet {
+    int l = 0;
+    const ZD* R = nullptr;
+    const ZD* L = nullptr;
+    ZD* c = nullptr;
+    double* sgn = nullptr;
+    double* part = nullptr;
+};
+
+tslov_status prepare_defl(tslov_ctx* c, const tslov_deflation* defl, DeflSet& d) {
+    d = DeflSet();
+    if (!defl || defl->l == 0) return TSLOV_OK;
+    if (defl->l < 0 || defl->l > kMaxDeflSet) return fail(TSLOV_ERR_ARG, "deflation size must be in [0, 256]");
+    if (!defl->R || !defl->L || !defl->lambda) return fail(TSLOV_ERR_ARG, "deflation needs R, L and lambda");
+    const int l = defl->l;
+    std::vector<double> sg(l);
+    double scale = 0.0;
+    for (int i = 0; i < l; ++i) scale = std::max(scale, std::hypot(defl->lambda[2 * i], defl->lambda[2 * i + 1]));
+    for (int i = 0; i < l; ++i) {
+        const double re = defl->lambda[2 * i];
+        if (!(std::fabs(re) > 1e-12 * scale)) return fail(TSLOV_ERR_SIGN_UNDEFINED, "deflated eigenvalue on Re z = 0");
+        sg[i] = re > 0 ? 1.0 : -1.0;
+    }
+    const int nb = c->nblk();
+    CHK(ensure(c->deflw, (size_t)l * sizeof(ZD) + (size_t)l * sizeof(double) + (size_t)nb * 2 * l * sizeof(double)));
+    d.l = l;
+    d.R = (const ZD*)defl->R;
+    d.L = (const ZD*)defl->L;
+    d.c = c->deflw.as<ZD>();
+    d.sgn = (double*)(d.c + l);
+    d.part = d.sgn + l;
+    HIPCHK(hipMemcpyAsync(d.sgn, sg.data(), (size_t)l * sizeof(double), hipMemcpyHostToDevice, c->st));
+    return TSLOV_OK;
+}
+
+ZD* canon_buf(tslov_ctx* c, int i) { return c->canon.as<ZD>() + (size_t)i * 12 * c->g.V; }
+
+// out = [psi +] g5^{overlap} sgn(H) psi by TSL, with optional deflation.
 template <typename R>
-tslov_status sign_impl(tslov_ctx* c, const void* psi, void* out, int k, tslov_info* info, int overlap) {
+tslov_status sign_impl(tslov_ctx* c, const void* psi_in, void* out, int k, const tslov_deflation* defl,
+                       tslov_info* info, int overlap) {
     const double t0 = now_ms();
+    DeflSet d;
+    CHK(prepare_defl(c, defl, d));
+    const ZD* psi = (const ZD*)psi_in;
+    const ZD* src = psi;
+    if (d.l) {
+        CHK(ensure(c->canon, (size_t)3 * 12 * c->g.V * sizeof(ZD)));
+        tslov::launch_defl_coeffs(d.L, psi, c->g.V, d.l, d.part, d.c, c->st);
+        tslov::launch_defl_project(d.R, psi, d.c, c->g.V, d.l, canon_buf(c, 0), c->st);
+        src = canon_buf(c, 0);
+    }
     int k_used = 0, bd = 0;
-    CHK(forward<R>(c, (const ZD*)psi, nullptr, k, &k_used, &bd));
+    CHK(forward<R>(c, src, nullptr, k, &k_used, &bd));
     const double t1 = now_ms();
-    DenseWork w;
-    CHK(ensure_dense(c, k_used, w));
-    tslov::launch_dense_build(c->coef, k_used, 0, w, c->st);
     int iters = 0;
-    CHK(newton(c, k_used, 0, w, &iters));
-    tslov::launch_dense_extract(c->coef, k_used, 0, w, c->st);
+    if (k_used > 0) {
+        DenseWork w;
+        CHK(ensure_dense(c, k_used, w));
+        tslov::launch_dense_build(c->coef, k_used, 0, w, c->st);
+        CHK(newton(c, k_used, 0, w, &iters));
+        tslov::launch_dense_extract(c->coef, k_used, 0, w, c->st);
+    }
     const double t2 = now_ms();
-    tslov::launch_assemble<R>(c->g, c->basisV.as<Z<R>>(), c->field_elems(), c->coef, (const ZD*)psi, overlap,
-                              (ZD*)out, c->st);
+    if (d.l) {
+        ZD* yp = nullptr;
+        if (k_used > 0) {
+            yp = canon_buf(c, 1);
+            tslov::launch_assemble<R>(c->g, c->basisV.as<Z<R>>(), c->field_elems(), c->coef, nullptr, 0, yp, c->st);
+        }
+        tslov::launch_defl_finish(d.R, d.c, d.sgn, yp, psi, c->g.V, d.l, overlap, (ZD*)out, c->st);
+    } else if (k_used > 0) {
+        tslov::launch_assemble<R>(c->g, c->basisV.as<Z<R>>(), c->field_elems(), c->coef, psi, overlap, (ZD*)out,
+                                  c->st);
+    } else {
+        tslov::launch_defl_finish(nullptr, nullptr, nullptr, nullptr, psi, c->g.V, 0, overlap, (ZD*)out, c->st);
+    }
     HIPCHK(hipGetLastError());
     double nx = 0.0;
     HIPCHK(hipMemcpyAsync(&nx, c->coef.misc, sizeof(double), hipMemcpyDeviceToHost, c->st));
@@ -403,6 +470,17 @@ tslov_status grad_impl(tslov_ctx* c, const void* eta, const void* psi, int k, do
     int k_used = 0, bd = 0;
     CHK(forward<R>(c, (const ZD*)psi, (const ZD*)eta, k, &k_used, &bd));
     const double t1 = now_ms();
+    if (k_used == 0) {   // zero source: S = 0 and every derivative vanishes
+        HIPCHK(hipMemsetAsync(dU, 0, (size_t)36 * c->g.V * sizeof(ZD), c->st));
+        if (dpsi) HIPCHK(hipMemsetAsync(dpsi, 0, (size_t)12 * c->g.V * sizeof(ZD), c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        if (S_out) *S_out = 0.0;
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->breakdown = bd;
+        }
+        return TSLOV_OK;
+    }
     DenseWork w;
     CHK(ensure_dense(c, k_used, w));
     tslov::launch_dense_build(c->coef, k_used, 1, w, c->st);
@@ -478,7 +556,7 @@ void tslov_destroy(tslov_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
     for (Buf* b : {&c->U64, &c->U32, &c->fields, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
-                   &c->bwork, &c->part,
+                   &c->bwork, &c->part, &c->canon, &c->deflw,
                    &c->coefmem, &c->dense, &c->denseInt, &c->denseLog, &c->densePart, &c->gpart})
         release(*b);
     if (c->host_part) (void)hipHostFree(c->host_part);
@@ -543,8 +621,8 @@ tslov_status tslov_sign(tslov_ctx* c, const void* psi, void* out, int k, const t
     CHK(check_common(c, k, defl));
     if (!psi || !out) return fail(TSLOV_ERR_ARG, "null argument");
     if (psi == out) return fail(TSLOV_ERR_ARG, "psi and out must not overlap");
-    return c->precision == TSLOV_MIXED ? sign_impl<float>(c, psi, out, k, info, 0)
-                                       : sign_impl<double>(c, psi, out, k, info, 0);
+    return c->precision == TSLOV_MIXED ? sign_impl<float>(c, psi, out, k, defl, info, 0)
+                                       : sign_impl<double>(c, psi, out, k, defl, info, 0);
 }
 
 tslov_status tslov_overlap(tslov_ctx* c, const void* psi, void* out, int k, const tslov_deflation* defl,
@@ -552,17 +630,50 @@ tslov_status tslov_overlap(tslov_ctx* c, const void* psi, void* out, int k, cons
     CHK(check_common(c, k, defl));
     if (!psi || !out) return fail(TSLOV_ERR_ARG, "null argument");
     if (psi == out) return fail(TSLOV_ERR_ARG, "psi and out must not overlap");
-    return c->precision == TSLOV_MIXED ? sign_impl<float>(c, psi, out, k, info, 1)
-                                       : sign_impl<double>(c, psi, out, k, info, 1);
+    return c->precision == TSLOV_MIXED ? sign_impl<float>(c, psi, out, k, defl, info, 1)
+                                       : sign_impl<double>(c, psi, out, k, defl, info, 1);
 }
 
 tslov_status tslov_sign_grad(tslov_ctx* c, const void* eta, const void* psi, int k, const tslov_deflation* defl,
                              int recompute_stride, double* S_out, void* dU_out, void* dpsi_out, tslov_info* info) {
     CHK(check_common(c, k, defl));
     if (!eta || !psi || !dU_out) return fail(TSLOV_ERR_ARG, "null argument");
+    if (defl && defl->l != 0)
+        return fail(TSLOV_ERR_ARG, "the derivative with deflation (eigenpair motion) is not supported; pass NULL");
     if (recompute_stride != 0) return fail(TSLOV_ERR_ARG, "recompute_stride must be 0 (all vectors stored)");
     return c->precision == TSLOV_MIXED ? grad_impl<float>(c, eta, psi, k, S_out, dU_out, dpsi_out, info)
                                        : grad_impl<double>(c, eta, psi, k, S_out, dU_out, dpsi_out, info);
+}
+
+tslov_status tslov_error_estimate(tslov_ctx* c, const void* psi, int k, const tslov_deflation* defl,
+                                  double* eps_out) {
+    CHK(check_common(c, k, defl));
+    if (!psi || !eps_out) return fail(TSLOV_ERR_ARG, "null argument");
+    const size_t n = (size_t)12 * c->g.V;
+    // canonical buffers 0..2 serve the deflated sign; y and z take 3 and 4
+    CHK(ensure(c->canon, (size_t)5 * n * sizeof(ZD)));
+    CHK(ensure_part(c));
+    ZD* y = canon_buf(c, 3);
+    ZD* z = canon_buf(c, 4);
+    tslov_status s = c->precision == TSLOV_MIXED ? sign_impl<float>(c, psi, y, k, defl, nullptr, 0)
+                                                 : sign_impl<double>(c, psi, y, k, defl, nullptr, 0);
+    if (s == TSLOV_OK)
+        s = c->precision == TSLOV_MIXED ? sign_impl<float>(c, y, z, k, defl, nullptr, 0)
+                                        : sign_impl<double>(c, y, z, k, defl, nullptr, 0);
+    if (s != TSLOV_OK) return s;
+    CHK(ensure_host_part(c, 2048));
+    double* part = part_array(c, 2);
+    const int nb = tslov::launch_diff_norm(z, (const ZD*)psi, n, part, c->st);
+    HIPCHK(hipMemcpyAsync(c->host_part, part, (size_t)2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    double dif = 0.0, nrm = 0.0;
+    for (int i = 0; i < nb; ++i) {
+        dif += c->host_part[2 * i];
+        nrm += c->host_part[2 * i + 1];
+    }
+    // sgn(0) = 0 is exact: a zero source has no error
+    *eps_out = nrm > 0.0 ? std::sqrt(dif / nrm) / 2.0 : 0.0;
+    return TSLOV_OK;
 }
 
 tslov_status tslov_dense_sign(tslov_ctx* c, const void* T, int k, const void* E, void* S_out, void* L_out,

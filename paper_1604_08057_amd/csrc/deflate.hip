@@ -1,0 +1,130 @@
+// Deflation by known eigenpairs (Sec. 3, eq. final_res; App. E) and the
+// a-posteriori error estimate (Sec. 4.1, eq. error_est), on canonical
+// [V][4][3] complex128 spinors.
+//
+//   c_i   = L_i^H psi                      (L^H R = 1, left/right eigenvectors of H)
+//   psi_p = psi - sum_i c_i R_i            (the projection P-bar psi)
+//   out   = TSL(psi_p) + sum_i s_i c_i R_i,   s_i = sgn(Re lambda_i)
+#include "kernels.h"
+
+namespace tslov {
+
+// Per-block partial sums of L_i^H psi for i < l: part[b][2 i + {0, 1}].
+__global__ __launch_bounds__(kBlock) void k_defl_dots(const ZD* __restrict__ L, const ZD* __restrict__ psi, int V,
+                                                      int l, double* __restrict__ part) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const size_t n = (size_t)V * 12;
+    ZD x[12];
+#pragma unroll
+    for (int p = 0; p < 12; ++p) x[p] = (s < V) ? psi[(size_t)s * 12 + p] : mk<double>(0, 0);
+    for (int i = 0; i < l; ++i) {
+        double v[2] = {0.0, 0.0};
+        if (s < V) {
+            const ZD* Li = L + (size_t)i * n + (size_t)s * 12;
+#pragma unroll
+            for (int p = 0; p < 12; ++p) {
+                const ZD t = cjmul(Li[p], x[p]);
+                v[0] += t.re;
+                v[1] += t.im;
+            }
+        }
+        block_sum<2, kBlock>(v);
+        if (threadIdx.x == 0) {
+            part[(size_t)blockIdx.x * 2 * l + 2 * i] = v[0];
+            part[(size_t)blockIdx.x * 2 * l + 2 * i + 1] = v[1];
+        }
+    }
+}
+
+// c_i = sum_b part[b][i] (fixed order), one block.
+__global__ __launch_bounds__(kBlock) void k_defl_reduce(const double* __restrict__ part, int nb, int l,
+                                                        ZD* __restrict__ c) {
+    for (int i = 0; i < l; ++i) {
+        double v[2] = {0.0, 0.0};
+        for (int b = threadIdx.x; b < nb; b += kBlock) {
+            v[0] += part[(size_t)b * 2 * l + 2 * i];
+            v[1] += part[(size_t)b * 2 * l + 2 * i + 1];
+        }
+        block_sum<2, kBlock>(v);
+        if (threadIdx.x == 0) c[i] = mk<double>(v[0], v[1]);
+    }
+}
+
+// out = psi - sum_i c_i R_i
+__global__ __launch_bounds__(kBlock) void k_defl_project(const ZD* __restrict__ R, const ZD* __restrict__ psi,
+                                                         const ZD* __restrict__ c, int V, int l, ZD* __restrict__ out) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= V) return;
+    const size_t n = (size_t)V * 12;
+    ZD x[12];
+#pragma unroll
+    for (int p = 0; p < 12; ++p) x[p] = psi[(size_t)s * 12 + p];
+    for (int i = 0; i < l; ++i) {
+        const ZD ci = c[i];
+        const ZD* Ri = R + (size_t)i * n + (size_t)s * 12;
+#pragma unroll
+        for (int p = 0; p < 12; ++p) x[p] = x[p] - ci * Ri[p];
+    }
+#pragma unroll
+    for (int p = 0; p < 12; ++p) out[(size_t)s * 12 + p] = x[p];
+}
+
+// out = [psi +] g5^{overlap} (y_p + sum_i sgn_i c_i R_i)
+__global__ __launch_bounds__(kBlock) void k_defl_finish(const ZD* __restrict__ R, const ZD* __restrict__ c,
+                                                        const double* __restrict__ sgn, const ZD* __restrict__ yp,
+                                                        const ZD* __restrict__ psi, int V, int l, int overlap,
+                                                        ZD* __restrict__ out) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= V) return;
+    const size_t n = (size_t)V * 12;
+    ZD y[12];
+#pragma unroll
+    for (int p = 0; p < 12; ++p) y[p] = yp ? yp[(size_t)s * 12 + p] : mk<double>(0, 0);
+    for (int i = 0; i < l; ++i) {
+        const ZD ci = sgn[i] * c[i];
+        const ZD* Ri = R + (size_t)i * n + (size_t)s * 12;
+#pragma unroll
+        for (int p = 0; p < 12; ++p) y[p] = y[p] + ci * Ri[p];
+    }
+#pragma unroll
+    for (int p = 0; p < 12; ++p) {
+        ZD o = y[p];
+        if (overlap) o = ((p >= 6) ? -1.0 : 1.0) * o + psi[(size_t)s * 12 + p];
+        out[(size_t)s * 12 + p] = o;
+    }
+}
+
+void launch_defl_coeffs(const ZD* L, const ZD* psi, int V, int l, double* part, ZD* c, hipStream_t st) {
+    const int nb = grid_for(V);
+    hipLaunchKernelGGL(k_defl_dots, dim3(nb), dim3(kBlock), 0, st, L, psi, V, l, part);
+    hipLaunchKernelGGL(k_defl_reduce, dim3(1), dim3(kBlock), 0, st, part, nb, l, c);
+}
+
+void launch_defl_project(const ZD* R, const ZD* psi, const ZD* c, int V, int l, ZD* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_defl_project, dim3(grid_for(V)), dim3(kBlock), 0, st, R, psi, c, V, l, out);
+}
+
+void launch_defl_finish(const ZD* R, const ZD* c, const double* sgn, const ZD* yp, const ZD* psi, int V, int l,
+                        int overlap, ZD* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_defl_finish, dim3(grid_for(V)), dim3(kBlock), 0, st, R, c, sgn, yp, psi, V, l, overlap, out);
+}
+
+// Partials of |a - b|^2 and |b|^2 over n complex values (error estimate).
+__global__ __launch_bounds__(kBlock) void k_diff_norm(const ZD* __restrict__ a, const ZD* __restrict__ b, size_t n,
+                                                      double* __restrict__ part) {
+    double v[2] = {0.0, 0.0};
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        v[0] += norm2(a[i] - b[i]);
+        v[1] += norm2(b[i]);
+    }
+    write_partials<2, kBlock>(part, v);
+}
+
+int launch_diff_norm(const ZD* a, const ZD* b, size_t n, double* part, hipStream_t st) {
+    int nb = (int)((n + kBlock - 1) / kBlock);
+    if (nb > 1024) nb = 1024;
+    hipLaunchKernelGGL(k_diff_norm, dim3(nb), dim3(kBlock), 0, st, a, b, n, part);
+    return nb;
+}
+
+}  // namespace tslov

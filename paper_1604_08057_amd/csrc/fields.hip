@@ -259,6 +259,16 @@ __global__ __launch_bounds__(kCBlock) void k_fwd_pair(const Z<R>* __restrict__ U
     const ZD om = mk<double>(red[0], red[1]);
     const double rn2 = red[2], sn2 = red[3];
     const double aom = std::sqrt(norm2(om));
+    if (first && !(rn2 > 0.0)) {   // zero source: empty Krylov space, nothing to do
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            coef.status[1] = 0;
+            coef.status[2] = 1;
+            coef.status[3] = 1;
+            coef.misc[0] = 0.0;
+            *(volatile int*)coef.status = 1;
+        }
+        return;
+    }
     if (!first) {
         const double an2 = coef.anorm2[j - 1];
         const bool lucky = rn2 <= kTauLucky * kTauLucky * an2;

@@ -65,6 +65,13 @@ template <typename R>
 void launch_source_grad(const Geom& g, const Z<R>* vbar, const Z<R>* wbar, const Z<R>* x, Coef coef,
                         double* part, ZD* out, hipStream_t st);
 
+// ---------------------------------------------------------------- deflation / error estimate
+void launch_defl_coeffs(const ZD* L, const ZD* psi, int V, int l, double* part, ZD* c, hipStream_t st);
+void launch_defl_project(const ZD* R, const ZD* psi, const ZD* c, int V, int l, ZD* out, hipStream_t st);
+void launch_defl_finish(const ZD* R, const ZD* c, const double* sgn, const ZD* yp, const ZD* psi, int V, int l,
+                        int overlap, ZD* out, hipStream_t st);
+int launch_diff_norm(const ZD* a, const ZD* b, size_t n, double* part, hipStream_t st);
+
 // ---------------------------------------------------------------- projected-matrix step
 struct DenseWork {
     ZD* X;        // iterate

@@ -29,8 +29,8 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 KERNEL_FWD_PAIR, KERNEL_BWD_PAIR, KERNEL_APPLY = 0, 1, 2
 
 EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links", "tslov_apply_dw",
-           "tslov_apply_h", "tslov_sign", "tslov_overlap", "tslov_sign_grad", "tslov_dense_sign",
-           "tslov_timing_enable", "tslov_timing_read", "tslov_kernel_bytes"]
+           "tslov_apply_h", "tslov_sign", "tslov_overlap", "tslov_sign_grad", "tslov_error_estimate",
+           "tslov_dense_sign", "tslov_timing_enable", "tslov_timing_read", "tslov_kernel_bytes"]
 
 
 class TslovLibraryMissing(ImportError):
@@ -96,6 +96,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_overlap": ([vp, vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(InfoStruct)], ci),
         "tslov_sign_grad": ([vp, vp, vp, ci, ctypes.POINTER(DeflationStruct), ci, ctypes.POINTER(cd), vp, vp,
                              ctypes.POINTER(InfoStruct)], ci),
+        "tslov_error_estimate": ([vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(cd)], ci),
         "tslov_dense_sign": ([vp, vp, ci, vp, vp, vp, ctypes.POINTER(ci)], ci),
         "tslov_timing_enable": ([vp, ci], ci),
         "tslov_timing_read": ([vp, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
@@ -178,22 +179,36 @@ class Context:
         _check(self.lib, self.lib.tslov_apply_h(self.handle, _ptr(x), _ptr(out), int(dagger)))
         return out
 
-    def sign(self, psi: torch.Tensor, k: int, out: torch.Tensor | None = None):
+    def deflation(self, R: torch.Tensor, L: torch.Tensor, lam) -> "Deflation":
+        """Eigenpairs of H for deflation: R, L complex128 (l, V, 4, 3) on the device
+        (L_i^H R_j = delta_ij), lam: l complex eigenvalues (host)."""
+        return Deflation(self, R, L, lam)
+
+    def sign(self, psi: torch.Tensor, k: int, out: torch.Tensor | None = None, defl: "Deflation | None" = None):
         psi = self._spinor(psi, "psi")
         out = self._new_spinor() if out is None else out
         info = InfoStruct()
-        _check(self.lib, self.lib.tslov_sign(self.handle, _ptr(psi), _ptr(out), int(k), None, ctypes.byref(info)))
+        d = None if defl is None else ctypes.byref(defl.struct)
+        _check(self.lib, self.lib.tslov_sign(self.handle, _ptr(psi), _ptr(out), int(k), d, ctypes.byref(info)))
         return out, Info.of(info)
 
-    def overlap(self, psi: torch.Tensor, k: int, out: torch.Tensor | None = None):
+    def overlap(self, psi: torch.Tensor, k: int, out: torch.Tensor | None = None, defl: "Deflation | None" = None):
         psi = self._spinor(psi, "psi")
         out = self._new_spinor() if out is None else out
         info = InfoStruct()
-        _check(self.lib, self.lib.tslov_overlap(self.handle, _ptr(psi), _ptr(out), int(k), None, ctypes.byref(info)))
+        d = None if defl is None else ctypes.byref(defl.struct)
+        _check(self.lib, self.lib.tslov_overlap(self.handle, _ptr(psi), _ptr(out), int(k), d, ctypes.byref(info)))
         return out, Info.of(info)
+
+    def error_estimate(self, psi: torch.Tensor, k: int, defl: "Deflation | None" = None) -> float:
+        psi = self._spinor(psi, "psi")
+        eps = ctypes.c_double()
+        d = None if defl is None else ctypes.byref(defl.struct)
+        _check(self.lib, self.lib.tslov_error_estimate(self.handle, _ptr(psi), int(k), d, ctypes.byref(eps)))
+        return eps.value
 
     def sign_grad(self, eta: torch.Tensor, psi: torch.Tensor, k: int, want_dpsi: bool = False,
-                  dU: torch.Tensor | None = None):
+                  dU: torch.Tensor | None = None, defl: "Deflation | None" = None):
         eta = self._spinor(eta, "eta")
         psi = self._spinor(psi, "psi")
         if dU is None:
@@ -201,7 +216,8 @@ class Context:
         dpsi = self._new_spinor() if want_dpsi else None
         S = ctypes.c_double()
         info = InfoStruct()
-        _check(self.lib, self.lib.tslov_sign_grad(self.handle, _ptr(eta), _ptr(psi), int(k), None, 0,
+        d = None if defl is None else ctypes.byref(defl.struct)
+        _check(self.lib, self.lib.tslov_sign_grad(self.handle, _ptr(eta), _ptr(psi), int(k), d, 0,
                                                   ctypes.byref(S), _ptr(dU), _ptr(dpsi), ctypes.byref(info)))
         return S.value, dU, dpsi, Info.of(info)
 
@@ -227,6 +243,24 @@ class Context:
 
     def kernel_bytes(self, which: int) -> float:
         return float(self.lib.tslov_kernel_bytes(self.handle, int(which)))
+
+
+class Deflation:
+    """Keeps the eigenvector tensors and the eigenvalue array alive for the C struct."""
+
+    def __init__(self, ctx: Context, R: torch.Tensor, L: torch.Tensor, lam):
+        l = int(R.shape[0])
+        shape = (l, ctx.volume, 4, 3)
+        for t, n in ((R, "R"), (L, "L")):
+            if t.dtype != torch.complex128 or t.device != ctx.device or tuple(t.shape) != shape:
+                raise ValueError(f"{n} must be complex128 of shape {shape} on {ctx.device}")
+        self.R = R.contiguous()
+        self.L = L.contiguous()
+        lam = [complex(z) for z in lam]
+        if len(lam) != l:
+            raise ValueError("need one eigenvalue per eigenvector pair")
+        self.lam = (ctypes.c_double * (2 * l))(*[v for z in lam for v in (z.real, z.imag)])
+        self.struct = DeflationStruct(l, _ptr(self.R), _ptr(self.L), self.lam)
 
 
 class SignGrad(torch.autograd.Function):

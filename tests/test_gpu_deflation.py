@@ -1,0 +1,139 @@
+"""GPU deflated sgn(H)psi, D_ov psi and the error estimate eps_A against the oracle.
+
+The eigenpairs come from the oracle's dense eigensolver (left and right
+eigenvectors, L^H R = 1) on small lattices; both sides deflate the same pairs and
+run TSL at the same k on the projected source.  Bar: 1e-10 relative (2-norm), as
+for the undeflated sign.  Cases: l = 10 and l = 20 on two tiny lattices, the
+improvement over plain TSL at fixed k, a source inside the deflated space (TSL
+then sees a source at rounding level and the result is the exact R sgn(lambda) c),
+the zero source (k_used = 0, zero output, eps_A = 0), eps_A against the oracle's,
+and argument checks (l beyond 256, an eigenvalue on the imaginary axis).
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import dev, host, rel, say
+from oracle import deflation as DF
+from oracle import sign as SG
+from oracle import wilson as W
+from synthetic import random_links, z2_complex_source
+
+pytestmark = pytest.mark.gpu
+
+G5 = np.array([1, 1, -1, -1])[None, :, None]
+
+
+def _problem(dims, mass, mu, spread, seed, l):
+    r = np.random.default_rng(seed)
+    V = int(np.prod(dims))
+    U = random_links(dims, spread, r)
+    psi = z2_complex_source(V, r)
+    H = W.dense_h(U, dims, mass, mu)
+    lam, R, L = DF.eigenpairs(H, l)
+    return U, psi, H, lam, R, L
+
+
+def _ctx_defl(dims, mass, mu, U, lam, R, L):
+    from paper_1604_08057_amd import Context
+    V = int(np.prod(dims))
+    l = len(lam)
+    ctx = Context(dims, mass, mu)
+    ctx.set_links(dev(U))
+    Rd = dev(R.T.reshape(l, V, 4, 3))
+    Ld = dev(L.T.reshape(l, V, 4, 3))
+    return ctx, ctx.deflation(Rd, Ld, lam)
+
+
+@pytest.mark.parametrize("dims,l,k", [((2, 2, 2, 4), 10, 24), ((3, 3, 3, 4), 20, 60)])
+def test_deflated_sign_and_overlap(dims, l, k):
+    mass, mu = -2.0, 0.3
+    U, psi, H, lam, R, L = _problem(dims, mass, mu, 0.5, 31, l)
+    op = W.WilsonOperator(dims, mass, mu)
+    ref = DF.deflated_sign(op, U, psi, k, lam, R, L)
+    ctx, defl = _ctx_defl(dims, mass, mu, U, lam, R, L)
+    y, info = ctx.sign(dev(psi), k, defl=defl)
+    d, _ = ctx.overlap(dev(psi), k, defl=defl)
+    y, d = host(y), host(d)
+    ctx.close()
+    say(f"deflated dims={dims} l={l} k={k}: k_used={info.k_used} err {rel(y, ref):.2e}")
+    assert info.k_used == k
+    assert rel(y, ref) < 1e-10
+    assert rel(d, psi + G5 * ref) < 1e-10
+    exact = (SG.sign_schur(H) @ psi.ravel()).reshape(psi.shape)
+    # the deflated approximation is the better one at this k
+    from paper_1604_08057_amd import Context
+    ctx = Context(dims, mass, mu)
+    ctx.set_links(dev(U))
+    y0, _ = ctx.sign(dev(psi), k)
+    ctx.close()
+    assert rel(y, exact) < rel(host(y0), exact)
+
+
+def test_source_inside_deflated_space():
+    dims, l, k = (2, 2, 2, 4), 16, 12
+    mass, mu = -2.0, 0.3
+    U, _, H, lam, R, L = _problem(dims, mass, mu, 0.5, 5, l)
+    V = int(np.prod(dims))
+    c = np.random.default_rng(6).standard_normal((l, 2)) @ np.array([1.0, 1.0j])
+    psi = (R @ c).reshape(V, 4, 3)
+    want = (R @ (np.sign(lam.real) * c)).reshape(V, 4, 3)
+    ctx, defl = _ctx_defl(dims, mass, mu, U, lam, R, L)
+    y, info = ctx.sign(dev(psi), k, defl=defl)
+    ctx.close()
+    say(f"in-space source: k_used={info.k_used} err {rel(host(y), want):.2e}")
+    assert rel(host(y), want) < 1e-10
+
+
+def test_zero_source():
+    from paper_1604_08057_amd import Context
+    dims = (2, 2, 2, 4)
+    U, _, H, lam, R, L = _problem(dims, -2.0, 0.3, 0.5, 5, 8)
+    zero = torch.zeros((32, 4, 3), dtype=torch.complex128, device="cuda")
+    ctx = Context(dims, -2.0, 0.3)
+    ctx.set_links(dev(U))
+    y, info = ctx.sign(zero, 10)
+    assert info.k_used == 0 and torch.count_nonzero(y).item() == 0
+    d, _ = ctx.overlap(zero, 10)
+    assert torch.count_nonzero(d).item() == 0
+    assert ctx.error_estimate(zero, 10) == 0.0
+    ctx.close()
+    ctx, defl = _ctx_defl(dims, -2.0, 0.3, U, lam, R, L)
+    y, info = ctx.sign(zero, 10, defl=defl)
+    assert info.k_used == 0 and torch.count_nonzero(y).item() == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("deflate", [False, True])
+def test_error_estimate(deflate):
+    dims, mass, mu = (2, 2, 2, 4), -1.0, 0.2
+    U, psi, H, lam, R, L = _problem(dims, mass, mu, 0.05, 4, 12 if deflate else 0)
+    op = W.WilsonOperator(dims, mass, mu)
+    from paper_1604_08057_amd import Context
+    for k in (8, 16, 32):
+        if deflate:
+            ctx, defl = _ctx_defl(dims, mass, mu, U, lam, R, L)
+            ref = DF.error_estimate(lambda v: DF.deflated_sign(op, U, v, k, lam, R, L), psi)
+        else:
+            ctx, defl = Context(dims, mass, mu), None
+            ctx.set_links(dev(U))
+            ref = DF.error_estimate(lambda v: DF.deflated_sign(op, U, v, k, lam[:0], R[:, :0], L[:, :0]), psi)
+        got = ctx.error_estimate(dev(psi), k, defl=defl)
+        ctx.close()
+        say(f"eps_A deflate={deflate} k={k}: {got:.6e} oracle {ref:.6e}")
+        assert abs(got - ref) <= 1e-9 * max(ref, 1e-6)
+
+
+def test_deflation_argument_checks():
+    from paper_1604_08057_amd import Context, TslovError
+    dims = (2, 2, 2, 4)
+    U, psi, H, lam, R, L = _problem(dims, -2.0, 0.3, 0.5, 5, 4)
+    ctx, defl = _ctx_defl(dims, -2.0, 0.3, U, lam, R, L)
+    bad = lam.copy()
+    bad[1] = 1j * abs(bad[1])
+    bdefl = ctx.deflation(defl.R, defl.L, bad)
+    with pytest.raises(TslovError):
+        ctx.sign(dev(psi), 8, defl=bdefl)
+    with pytest.raises(TslovError):
+        ctx.sign_grad(dev(psi), dev(psi), 8, defl=defl)
+    ctx.close()
