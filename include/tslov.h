@@ -136,6 +136,41 @@ tslov_status tslov_sign_grad(tslov_ctx* ctx, const void* eta, const void* psi, i
                              const tslov_deflation* defl, int recompute_stride,
                              double* S_out, void* dU_out, void* dpsi_out, tslov_info* info);
 
+/* Batched derivative (many noise sources, uneven Krylov sizes): for s < nsrc,
+ *   S_out[s] = Re <eta_s | TSL_{k[s]}(H(U), psi_s)>,  dU_out[s] = dS_s/dRe U + i dS_s/dIm U,
+ * each exactly as tslov_sign_grad computes it for that source alone.
+ * eta, psi: nsrc canonical spinors, contiguous ([nsrc][V][4][3] complex128, device);
+ * k: host array of nsrc Krylov sizes in [1, 1024]; S_out: host array of nsrc
+ * doubles (nullable); dU_out: [nsrc][4][V][3][3] complex128 (device); dpsi_out:
+ * [nsrc][V][4][3] (nullable); infos: host array of nsrc (nullable).
+ * The library runs the sources in lockstep groups (one launch per Lanczos step
+ * serves every active source of the group; a source leaves the group after its
+ * own k[s] steps or a lucky breakdown), sized to the free device memory.  A
+ * serious breakdown of some sources returns ERR_BREAKDOWN after every other
+ * source has been computed (their outputs are valid; the broken ones' are not;
+ * infos[s].breakdown = 2 names them). */
+tslov_status tslov_sign_grad_batched(tslov_ctx* ctx, int nsrc, const void* eta, const void* psi, const int* k,
+                                     double* S_out, void* dU_out, void* dpsi_out, tslov_info* infos);
+
+/* Stochastic estimator of the link-current trace (Sec. 4, the U(1) vector current
+ * test, eq. lat_vec_cur without the inverse Dirac operator): with Z2 noise xi_s,
+ *   j(x, nu) = (1/nsrc) sum_s dS_s/dTheta_{x,nu},  S_s = Re <g5 xi_s | sgn(H) | xi_s>,
+ * the derivative with respect to the U(1) phase of U_nu(x) -> e^{i Theta} U_nu(x),
+ * i.e. -Im tr(G_s^H U_nu(x)) with G_s the link gradient of tslov_sign_grad.  Since
+ * D_ov = 1 + g5 sgn(H), this estimates Re Tr(dD_ov/dTheta_{x,nu}).
+ * xi: [nsrc][V][4][3] complex128 (device); k: host array of nsrc sizes;
+ * j_out: device double [4][V] (direction-major); div_out, tot_out: device double
+ * [V] (nullable) receive the divergence sum_nu [j(x, nu) - j(x - nu, nu)] and the
+ * total current sum_nu [j(x, nu) + j(x - nu, nu)] (eq. divergence_def and the sum
+ * with the sign flipped).  ward_out (host, nullable): the per-sample Ward
+ * identity of the local U(1) symmetry, max over sources and sites of
+ * |sum_nu [g_s(x,nu) - g_s(x-nu,nu)] - (-Im eta_s^H y_s + Im dpsi_s^H xi_s)(x)|
+ * divided by max |g_s(x, nu)|, with eta_s = g5 xi_s, y_s = TSL(xi_s) and dpsi_s
+ * the source gradient; it is zero up to rounding for the exact derivative.
+ * Requesting it costs one extra assembly and source gradient per source. */
+tslov_status tslov_current_estimate(tslov_ctx* ctx, int nsrc, const void* xi, const int* k, double* j_out,
+                                    double* div_out, double* tot_out, double* ward_out, tslov_info* infos);
+
 /* A-posteriori error estimate (Sec. 4.1, eq. error_est): with y = TSL(psi) and
  * z = TSL(y) (a fresh Krylov space with source y, same k and deflation),
  * eps_A = |z - psi| / (2 |psi|).  eps_out: host double. */

@@ -1,6 +1,8 @@
 // C ABI of the tslov library (declared in include/tslov.h): context and
 // workspace management, and the host drivers of the TSL forward pass, the
-// projected-matrix Newton step and the reverse-mode pass for dS/dU.
+// projected-matrix Newton step and the reverse-mode pass for dS/dU.  Every
+// driver works on a batch of sources held in workspace slots; a single-source
+// call is a batch of one.
 #include "tslov.h"
 
 #include <hip/hip_runtime.h>
@@ -9,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -17,6 +20,9 @@
 using tslov::Coef;
 using tslov::DenseWork;
 using tslov::Geom;
+using tslov::kMaxBatch;
+using tslov::SrcList;
+using tslov::Work;
 using tslov::Z;
 using tslov::ZD;
 
@@ -74,6 +80,7 @@ double now_ms() {
 constexpr int kMaxK = 1024;
 constexpr int kMaxDeflSet = 256;
 constexpr int kTimingClasses = 3;
+constexpr int kMaxSources = 1 << 20;
 
 }  // namespace
 
@@ -86,21 +93,22 @@ struct tslov_ctx {
     size_t lds_max = 65536;
     int links_set = 0;
     Buf U64, U32;
-    Buf fields;      // psi, eta, r, s, a, b in the working precision
-    Buf basisV, basisW, basisA, basisB;   // v_j, w_j, a_j = H v_j, b_j = H^dag w_j
-    Buf abarS, sbarS;
-    Buf bwork;       // vbar, wbar, rbar ring
-    Buf part;        // partial sums (4 arrays)
-    Buf coefmem;
-    Buf dense, denseInt, denseLog, densePart;
-    Buf gpart;
-    Buf canon;       // three canonical spinors: projected source, partial result, error estimate
+    Buf opf;         // two working-precision fields for the plain operator
+    // batch workspace: per slot, kcap steps of v, w, a = Hv, b = H^dag w (and
+    // abar, sbar for the derivative), kNF fields and kNP partial arrays
+    Buf basisV, basisW, basisA, basisB, abarS, sbarS;
+    Buf fields, part, coefmem;
+    Buf dense, denseInt, densePart, denseDelta;
+    Buf gpart, gsrc;
+    Buf bout;        // per-entry canonical y and dpsi (Ward check)
+    Buf wardp;       // Ward block maxima
+    Buf canon;       // canonical spinors: projected source, partial result, error estimate
     Buf deflw;       // deflation coefficients, signs and partial sums
     double* host_part = nullptr;  // pinned
     int host_part_n = 0;
-    int kcap = 0;
+    int slots = 0, kcap = 0, grad_cap = 0;   // shape of the batch workspace
+    int dslots = 0, dkcap = 0;               // shape of the dense workspace
     Coef coef{};
-    int status_init[4] = {0, 0, 0, 0};
     int timing = 0;
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[kTimingClasses];
@@ -109,6 +117,7 @@ struct tslov_ctx {
     size_t field_elems() const { return (size_t)12 * g.ldv; }
     size_t zsize() const { return precision == TSLOV_MIXED ? sizeof(Z<float>) : sizeof(ZD); }
     size_t field_bytes() const { return field_elems() * zsize(); }
+    int pstride() const { return 8 * tslov::np_max(g.V); }
 };
 
 namespace {
@@ -141,35 +150,6 @@ struct TimedLaunch {
     }
 };
 
-tslov_status ensure_coef(tslov_ctx* c, int k) {
-    if (c->kcap >= k && c->coefmem.p) return TSLOV_OK;
-    const int n = k + 2;
-    const size_t bytes = (size_t)n * (7 * sizeof(ZD) + 4 * sizeof(double)) + 16 * sizeof(int) + 16 * sizeof(double);
-    CHK(ensure(c->coefmem, bytes));
-    char* p = c->coefmem.as<char>();
-    auto take = [&](size_t b) {
-        char* q = p;
-        p += b;
-        return q;
-    };
-    Coef& cf = c->coef;
-    cf.alpha = (ZD*)take(n * sizeof(ZD));
-    cf.gamma = (ZD*)take(n * sizeof(ZD));
-    cf.h = (ZD*)take(n * sizeof(ZD));
-    cf.c = (ZD*)take(n * sizeof(ZD));
-    cf.abar_T = (ZD*)take(n * sizeof(ZD));
-    cf.gbar_T = (ZD*)take(n * sizeof(ZD));
-    cf.gbar_tot = (ZD*)take(n * sizeof(ZD));
-    cf.beta = (double*)take(n * sizeof(double));
-    cf.anorm2 = (double*)take(n * sizeof(double));
-    cf.bbar_T = (double*)take(n * sizeof(double));
-    cf.bbar_tot = (double*)take(n * sizeof(double));
-    cf.misc = (double*)take(16 * sizeof(double));
-    cf.status = (int*)take(16 * sizeof(int));
-    c->kcap = k;
-    return TSLOV_OK;
-}
-
 tslov_status ensure_host_part(tslov_ctx* c, int n) {
     if (c->host_part_n >= n) return TSLOV_OK;
     if (c->host_part) (void)hipHostFree(c->host_part);
@@ -180,15 +160,77 @@ tslov_status ensure_host_part(tslov_ctx* c, int n) {
     return TSLOV_OK;
 }
 
-// Partial-sum arrays: [0] forward pair / RB, [1] recurrence / RA, [2] misc, [3] dense.
-double* part_array(tslov_ctx* c, int i) { return c->part.as<double>() + (size_t)i * 8 * tslov::np_max(c->g.V); }
+// ---------------------------------------------------------------- batch workspace
+size_t coef_bytes(int slots, int kcap) {
+    const size_t n = (size_t)kcap + 2;
+    return (size_t)slots * (n * (7 * sizeof(ZD) + 4 * sizeof(double)) + 16 * sizeof(int) + 16 * sizeof(double));
+}
 
-tslov_status ensure_part(tslov_ctx* c) {
-    return ensure(c->part, (size_t)4 * 8 * tslov::np_max(c->g.V) * sizeof(double));
+void carve_coef(tslov_ctx* c, int slots, int kcap) {
+    const size_t n = (size_t)kcap + 2, S = (size_t)slots;
+    char* p = c->coefmem.as<char>();
+    auto take = [&](size_t b) {
+        char* q = p;
+        p += b;
+        return q;
+    };
+    Coef& cf = c->coef;
+    cf.alpha = (ZD*)take(S * n * sizeof(ZD));
+    cf.gamma = (ZD*)take(S * n * sizeof(ZD));
+    cf.h = (ZD*)take(S * n * sizeof(ZD));
+    cf.c = (ZD*)take(S * n * sizeof(ZD));
+    cf.abar_T = (ZD*)take(S * n * sizeof(ZD));
+    cf.gbar_T = (ZD*)take(S * n * sizeof(ZD));
+    cf.gbar_tot = (ZD*)take(S * n * sizeof(ZD));
+    cf.beta = (double*)take(S * n * sizeof(double));
+    cf.anorm2 = (double*)take(S * n * sizeof(double));
+    cf.bbar_T = (double*)take(S * n * sizeof(double));
+    cf.bbar_tot = (double*)take(S * n * sizeof(double));
+    cf.misc = (double*)take(S * 16 * sizeof(double));
+    cf.status = (int*)take(S * 16 * sizeof(int));
+    cf.n = (int)n;
+}
+
+// Workspace for `slots` sources of up to kcap steps (grad: with the reverse-pass arrays).
+tslov_status ensure_work(tslov_ctx* c, int slots, int kcap, int grad) {
+    if (c->slots == slots && c->kcap == kcap && c->grad_cap >= grad && c->coefmem.p) return TSLOV_OK;
+    c->slots = 0;   // invalid until every buffer has the new shape
+    const size_t fb = c->field_bytes();
+    const size_t per = (size_t)slots * kcap * fb;
+    CHK(ensure(c->basisV, per));
+    CHK(ensure(c->basisW, per));
+    CHK(ensure(c->basisA, per));
+    CHK(ensure(c->basisB, per));
+    if (grad) {
+        CHK(ensure(c->abarS, per));
+        CHK(ensure(c->sbarS, per));
+    }
+    CHK(ensure(c->fields, (size_t)slots * tslov::kNF * fb));
+    CHK(ensure(c->part, (size_t)slots * tslov::kNP * c->pstride() * sizeof(double)));
+    CHK(ensure(c->coefmem, coef_bytes(slots, kcap)));
+    carve_coef(c, slots, kcap);
+    c->slots = slots;
+    c->kcap = kcap;
+    c->grad_cap = grad;
+    return TSLOV_OK;
 }
 
 template <typename R>
-Z<R>* fld(const Buf& b, const tslov_ctx* c, int i) { return b.as<Z<R>>() + (size_t)i * c->field_elems(); }
+Work<R> work(const tslov_ctx* c) {
+    Work<R> w;
+    w.V = c->basisV.as<Z<R>>();
+    w.W = c->basisW.as<Z<R>>();
+    w.A = c->basisA.as<Z<R>>();
+    w.B = c->basisB.as<Z<R>>();
+    w.AB = c->abarS.as<Z<R>>();
+    w.SB = c->sbarS.as<Z<R>>();
+    w.F = c->fields.as<Z<R>>();
+    w.part = c->part.as<double>();
+    w.fe = c->field_elems();
+    w.kcap = c->kcap;
+    w.pstride = c->pstride();
+    return w;
+}
 
 template <typename R>
 const Z<R>* links(const tslov_ctx* c) {
@@ -196,78 +238,142 @@ const Z<R>* links(const tslov_ctx* c) {
     else return c->U32.as<Z<R>>();
 }
 
+// Device bytes one source of up to kcap steps needs (workspace sizing).
+size_t bytes_per_source(const tslov_ctx* c, int kcap, int grad) {
+    const size_t fb = c->field_bytes();
+    size_t b = (size_t)(grad ? 6 : 4) * kcap * fb + (size_t)tslov::kNF * fb;
+    b += (size_t)tslov::kNP * c->pstride() * sizeof(double) + coef_bytes(1, kcap);
+    b += (size_t)5 * kcap * kcap * sizeof(ZD) + (size_t)tslov::dense_pstride(kcap) * sizeof(double);
+    if (grad) b += (size_t)2 * 36 * c->g.ldv * sizeof(ZD) + (size_t)2 * 12 * c->g.V * sizeof(ZD);
+    return b;
+}
+
+size_t held_bytes(const tslov_ctx* c) {
+    size_t t = 0;
+    for (const Buf* b : {&c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS, &c->fields, &c->part,
+                         &c->dense, &c->gpart, &c->bout})
+        t += b->n;
+    return t;
+}
+
+// Sources per batch: as many as fit in ~80% of the device memory not otherwise in use.
+int batch_capacity(const tslov_ctx* c, int kcap, int grad) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    const double avail = 0.8 * (double)(fr + held_bytes(c));
+    const double per = (double)bytes_per_source(c, kcap, grad);
+    const int n = (int)std::floor(avail / per);
+    return std::max(1, std::min(n, kMaxBatch));
+}
+
+// ---------------------------------------------------------------- source lists
+// Entries in slots 0..n-1 sorted by decreasing k.
+SrcList make_list(const std::vector<int>& src, const std::vector<int>& k) {
+    SrcList L{};
+    L.n = (int)src.size();
+    for (int e = 0; e < L.n; ++e) {
+        L.slot[e] = e;
+        L.src[e] = src[e];
+        L.k[e] = k[e];
+        L.flag[e] = 0;
+    }
+    return L;
+}
+
+SrcList prefix(const SrcList& L, int n) {
+    SrcList o = L;
+    o.n = n;
+    return o;
+}
+
+SrcList range(const SrcList& L, int b, int e) {
+    SrcList o{};
+    o.n = e - b;
+    for (int i = b; i < e; ++i) {
+        o.slot[i - b] = L.slot[i];
+        o.src[i - b] = L.src[i];
+        o.k[i - b] = L.k[i];
+        o.flag[i - b] = L.flag[i];
+    }
+    return o;
+}
+
 // ---------------------------------------------------------------- forward
-// Fields: 0 psi, 1 eta, 2 r, 3 s, 4 a, 5 b.
+struct EntryStatus {
+    int k_used = 0, breakdown = 0, step = 0;
+    double norm_x = 0.0, S = 0.0;
+    int iters = 0;
+};
+
+// Lanczos process for every entry of L (slots 0..n-1, k in decreasing order);
+// psi and eta canonical arrays indexed by src (eta nullable; eta_g5: eta = g5 psi).
 template <typename R>
-tslov_status forward(tslov_ctx* c, const ZD* psi, const ZD* eta, int k, int* k_used, int* breakdown) {
+tslov_status forward(tslov_ctx* c, const SrcList& L, const ZD* psi, const ZD* eta, int eta_g5,
+                     std::vector<EntryStatus>& es) {
     const Geom& g = c->g;
-    const int np_norm = c->nblk(), np_st = tslov::np_stencil(g.V), np_pt = tslov::np_point(g.V);
-    CHK(ensure(c->fields, 6 * c->field_elems() * sizeof(Z<R>)));
-    CHK(ensure(c->basisV, (size_t)k * c->field_elems() * sizeof(Z<R>)));
-    CHK(ensure(c->basisW, (size_t)k * c->field_elems() * sizeof(Z<R>)));
-    CHK(ensure(c->basisA, (size_t)k * c->field_elems() * sizeof(Z<R>)));
-    CHK(ensure(c->basisB, (size_t)k * c->field_elems() * sizeof(Z<R>)));
-    CHK(ensure_part(c));
-    CHK(ensure_coef(c, k));
-    Z<R>* X = fld<R>(c->fields, c, 0);
-    Z<R>* E = fld<R>(c->fields, c, 1);
-    Z<R>* Rf = fld<R>(c->fields, c, 2);
-    Z<R>* Sf = fld<R>(c->fields, c, 3);
-    double* p_pair = part_array(c, 0);
-    double* p_rec = part_array(c, 1);
-    c->status_init[0] = 0;
-    c->status_init[1] = k;
-    c->status_init[2] = 0;
-    c->status_init[3] = 0;
-    HIPCHK(hipMemcpyAsync(c->coef.status, c->status_init, sizeof(c->status_init), hipMemcpyHostToDevice, c->st));
-    tslov::launch_spinor_to_soa<R>(psi, X, g, p_rec, c->st);
-    if (eta) tslov::launch_spinor_to_soa<R>(eta, E, g, nullptr, c->st);
+    const Work<R> wk = work<R>(c);
+    std::vector<int> init((size_t)16 * L.n, 0);
+    for (int e = 0; e < L.n; ++e) init[(size_t)16 * L.slot[e] + 1] = L.k[e];
+    HIPCHK(hipMemcpyAsync(c->coef.status, init.data(), init.size() * sizeof(int), hipMemcpyHostToDevice, c->st));
+    tslov::launch_sources_to_soa<R>(psi, 0, 0, wk, L, g, c->st);
+    if (eta) tslov::launch_sources_to_soa<R>(eta, 1, eta_g5, wk, L, g, c->st);
     const Z<R>* U = links<R>(c);
-    for (int j = 1; j <= k; ++j) {
-        Z<R>* vj = fld<R>(c->basisV, c, j - 1);
-        Z<R>* wj = fld<R>(c->basisW, c, j - 1);
-        Z<R>* Af = fld<R>(c->basisA, c, j - 1);
-        Z<R>* Bf = fld<R>(c->basisB, c, j - 1);
+    const int kmax = L.k[0];
+    int n = L.n;
+    for (int j = 1; j <= kmax; ++j) {
+        while (n > 0 && L.k[n - 1] < j) --n;
+        const SrcList Lj = prefix(L, n);
         {
             TimedLaunch tl(c, 0);
-            tslov::launch_fwd_pair<R>(U, g, c->kappa, c->mu, j == 1 ? X : Rf, j == 1 ? X : Sf, p_rec,
-                                      j == 1 ? np_norm : np_pt, j == 1, c->coef, j, vj, wj, Af, Bf, eta ? E : nullptr,
-                                      p_pair, c->st);
+            tslov::launch_fwd_pair<R>(U, g, c->kappa, c->mu, wk, Lj, c->coef, j, eta ? 1 : 0, c->st);
         }
-        tslov::launch_recur<R>(g, Af, Bf, vj, wj, j > 1 ? fld<R>(c->basisV, c, j - 2) : nullptr,
-                               j > 1 ? fld<R>(c->basisW, c, j - 2) : nullptr, p_pair, np_st, c->coef, j, j == k, Rf,
-                               Sf, p_rec, c->st);
+        tslov::launch_recur<R>(g, wk, Lj, c->coef, j, c->st);
     }
     HIPCHK(hipGetLastError());
-    int st[4];
-    HIPCHK(hipMemcpyAsync(st, c->coef.status, sizeof(st), hipMemcpyDeviceToHost, c->st));
+    std::vector<int> st((size_t)16 * L.n);
+    std::vector<double> misc((size_t)16 * L.n);
+    HIPCHK(hipMemcpyAsync(st.data(), c->coef.status, st.size() * sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(misc.data(), c->coef.misc, misc.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
-    *k_used = st[1];
-    *breakdown = st[2];
-    if (st[2] == 2)
-        return fail(TSLOV_ERR_BREAKDOWN, "serious Lanczos breakdown at step " + std::to_string(st[3]));
+    es.assign(L.n, EntryStatus());
+    for (int e = 0; e < L.n; ++e) {
+        const int* s = &st[(size_t)16 * L.slot[e]];
+        es[e].k_used = s[1];
+        es[e].breakdown = s[2];
+        es[e].step = s[3];
+        es[e].norm_x = misc[(size_t)16 * L.slot[e]];
+    }
     return TSLOV_OK;
 }
 
 // ---------------------------------------------------------------- projected-matrix step
-tslov_status ensure_dense(tslov_ctx* c, int k, DenseWork& w) {
-    const size_t kk = (size_t)k * k;
-    CHK(ensure(c->dense, 5 * kk * sizeof(ZD)));
-    CHK(ensure(c->denseInt, (size_t)2 * k * sizeof(int)));
-    CHK(ensure(c->denseLog, (size_t)k * sizeof(double)));
-    const int np = tslov::grid_for((int)kk, 256);
-    CHK(ensure(c->densePart, (size_t)(4 * np + 8) * sizeof(double)));
-    CHK(ensure_host_part(c, 2 * np + 8));
+tslov_status ensure_dense(tslov_ctx* c, int slots, int kcap, DenseWork& w) {
+    const size_t kk = (size_t)kcap * kcap;
+    const int ps = tslov::dense_pstride(kcap);
+    CHK(ensure(c->dense, (size_t)slots * 5 * kk * sizeof(ZD)));
+    CHK(ensure(c->denseInt, (size_t)slots * 2 * kcap * sizeof(int)));
+    CHK(ensure(c->densePart, (size_t)slots * ps * sizeof(double)));
+    CHK(ensure(c->denseDelta, (size_t)slots * 2 * sizeof(double)));
+    CHK(ensure_host_part(c, 2 * slots + 8));
     ZD* d = c->dense.as<ZD>();
+    const size_t S = (size_t)slots;
     w.X = d;
-    w.Y = d + kk;
-    w.Wk = d + 2 * kk;
-    w.Xinv = d + 3 * kk;
-    w.Zt = d + 4 * kk;
+    w.Y = d + S * kk;
+    w.Wk = d + 2 * S * kk;
+    w.Xinv = d + 3 * S * kk;
+    w.Zt = d + 4 * S * kk;
     w.rowperm = c->denseInt.as<int>();
-    w.logpiv = c->denseLog.as<double>();
     w.part = c->densePart.as<double>();
-    w.npart_max = np;
+    w.delta = c->denseDelta.as<double>();
+    w.kk = kk;
+    w.kcap = kcap;
+    w.npart_max = tslov::grid_for((int)kk, 256);
+    w.pstride = ps;
+    c->dslots = slots;
+    c->dkcap = kcap;
     return TSLOV_OK;
 }
 
@@ -277,83 +383,141 @@ int choose_nb(const tslov_ctx* c, int k) {
     return 1;
 }
 
-// Newton iteration on X (and Y) until the relative step falls to rounding level.
-tslov_status newton(tslov_ctx* c, int k, int grad, DenseWork& w, int* iters_out) {
-    const int nb = choose_nb(c, k);
-    int scaling = 1, extra = grad ? 1 : 0, it = 0;
-    double prev = INFINITY;
-    bool done = false;
-    for (it = 1; it <= 100 && !done; ++it) {
-        const int np = tslov::dense_newton_step(k, grad, scaling, nb, c->lds_max, w, c->st);
+// Newton iteration on X (and Y) of every entry of L (k = size, decreasing) until
+// each entry's relative step falls to rounding level.  iters[e] receives the count.
+tslov_status newton(tslov_ctx* c, const SrcList& L, int grad, const DenseWork& w, std::vector<int>& iters) {
+    struct St {
+        int scaling = 1, extra = 0, done = 0, it = 0;
+        double prev = INFINITY;
+    };
+    std::vector<St> s(L.n);
+    for (auto& x : s) x.extra = grad ? 1 : 0;
+    for (int it = 1; it <= 100; ++it) {
+        SrcList A{};
+        for (int e = 0; e < L.n; ++e)
+            if (!s[e].done) {
+                A.slot[A.n] = L.slot[e];
+                A.src[A.n] = e;   // back-reference to the entry
+                A.k[A.n] = L.k[e];
+                A.flag[A.n] = s[e].scaling;
+                ++A.n;
+            }
+        if (A.n == 0) break;
+        tslov::dense_newton_step(A, grad, choose_nb(c, A.k[0]), c->lds_max, w, c->st);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(c->host_part, w.part, (size_t)2 * np * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(c->host_part, w.delta, (size_t)2 * c->dslots * sizeof(double), hipMemcpyDeviceToHost,
+                              c->st));
         HIPCHK(hipStreamSynchronize(c->st));
-        double dif = 0.0, nrm = 0.0;
-        for (int i = 0; i < np; ++i) {
-            dif += c->host_part[2 * i];
-            nrm += c->host_part[2 * i + 1];
+        for (int a = 0; a < A.n; ++a) {
+            St& x = s[A.src[a]];
+            x.it = it;
+            const double delta = std::sqrt(c->host_part[2 * A.slot[a]] / c->host_part[2 * A.slot[a] + 1]);
+            if (!std::isfinite(delta))
+                return fail(TSLOV_ERR_SIGN_UNDEFINED, "projected matrix is singular or its sign is undefined");
+            if (delta < 1e-2) x.scaling = 0;
+            // quadratic convergence: once the step is below 1e-8 the new iterate's error
+            // is at rounding level; stagnation above that also ends the iteration
+            const bool conv = delta <= 1e-8 || (delta < 1e-6 && delta > 0.5 * x.prev);
+            if (conv) {
+                if (x.extra) x.extra = 0;
+                else x.done = 1;
+            }
+            x.prev = delta;
         }
-        const double delta = std::sqrt(dif / nrm);
-        if (!std::isfinite(delta))
-            return fail(TSLOV_ERR_SIGN_UNDEFINED, "projected matrix is singular or its sign is undefined");
-        if (delta < 1e-2) scaling = 0;
-        // quadratic convergence: once the step is below 1e-8 the new iterate's error
-        // is at rounding level; stagnation above that also ends the iteration
-        const bool conv = delta <= 1e-8 || (delta < 1e-6 && delta > 0.5 * prev);
-        if (conv) {
-            if (extra) extra = 0;
-            else done = true;
-        }
-        prev = delta;
     }
-    if (iters_out) *iters_out = it - 1;
-    if (!done)
-        return fail(TSLOV_ERR_SIGN_UNDEFINED,
-                    "sign iteration of the projected matrix did not converge (eigenvalue near Re z = 0)");
+    iters.assign(L.n, 0);
+    for (int e = 0; e < L.n; ++e) {
+        if (!s[e].done)
+            return fail(TSLOV_ERR_SIGN_UNDEFINED,
+                        "sign iteration of the projected matrix did not converge (eigenvalue near Re z = 0)");
+        iters[e] = s[e].it;
+    }
+    return TSLOV_OK;
+}
+
+// sgn(T) (and the Frechet step) of every entry, coefficients c_j and adjoint seeds.
+tslov_status dense_step(tslov_ctx* c, const SrcList& L, int grad, std::vector<int>& iters) {
+    DenseWork w;
+    CHK(ensure_dense(c, c->slots, c->kcap, w));
+    tslov::launch_dense_build(c->coef, L, grad, w, c->st);
+    CHK(newton(c, L, grad, w, iters));
+    tslov::launch_dense_extract(c->coef, L, grad, w, c->st);
+    HIPCHK(hipGetLastError());
     return TSLOV_OK;
 }
 
 // ---------------------------------------------------------------- backward
-// bwork fields: 0 vbar, 1 wbar, 2/3 rbar ring.
+struct GradOut {
+    ZD* dU = nullptr;        // [src][4][V][3][3] or null
+    ZD* dpsi = nullptr;      // [src][V][4][3] or null
+    double* jsum = nullptr;  // current estimator: [4][V] sum of U(1) projections
+    int accumulate = 0;
+    int ward = 0;            // compute the Ward check (needs psi)
+    const ZD* psi = nullptr;
+    double ward_max = 0.0, g_max = 0.0;
+};
+
+// Reverse pass and force contraction for every entry of L (k = k_used, decreasing).
 template <typename R>
-tslov_status backward(tslov_ctx* c, int k, ZD* dU, ZD* dpsi) {
+tslov_status backward(tslov_ctx* c, const SrcList& L, GradOut& out) {
     const Geom& g = c->g;
-    const int np_st = tslov::np_stencil(g.V), np_pt = tslov::np_point(g.V);
-    CHK(ensure(c->abarS, (size_t)k * c->field_elems() * sizeof(Z<R>)));
-    CHK(ensure(c->sbarS, (size_t)k * c->field_elems() * sizeof(Z<R>)));
-    CHK(ensure(c->bwork, 4 * c->field_elems() * sizeof(Z<R>)));
-    Z<R>* VB = fld<R>(c->bwork, c, 0);
-    Z<R>* WB = fld<R>(c->bwork, c, 1);
-    Z<R>* X = fld<R>(c->fields, c, 0);
-    Z<R>* E = fld<R>(c->fields, c, 1);
-    double* p_rb = part_array(c, 0);
-    double* p_ra = part_array(c, 1);
+    const Work<R> wk = work<R>(c);
     const Z<R>* U = links<R>(c);
-    auto V = [&](int j) { return fld<R>(c->basisV, c, j - 1); };   // v_j, 1-based
-    auto W = [&](int j) { return fld<R>(c->basisW, c, j - 1); };
-    auto A = [&](int j) { return fld<R>(c->basisA, c, j - 1); };
-    auto B = [&](int j) { return fld<R>(c->basisB, c, j - 1); };
-    auto RB = [&](int j) { return fld<R>(c->bwork, c, 2 + (j & 1)); };
-    auto SB = [&](int j) { return fld<R>(c->sbarS, c, j - 1); };
-    auto AB = [&](int j) { return fld<R>(c->abarS, c, j - 1); };
-    for (int j = k; j >= 1; --j) {
-        if (j < k)
-            tslov::launch_bwd_ra<R>(g, VB, WB, V(j + 1), W(j + 1), V(j), W(j), j > 1 ? V(j - 1) : nullptr,
-                                    j > 1 ? W(j - 1) : nullptr, p_rb, np_st, c->coef, j, RB(j), SB(j), p_ra, c->st);
-        TimedLaunch tl(c, 1);
-        tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, p_ra, np_pt, c->coef, j, k, RB(j), RB(j + 1), SB(j),
-                                j < k ? SB(j + 1) : SB(j), V(j), W(j), A(j), B(j), E, VB, WB, AB(j), p_rb, c->st);
+    const int kmax = L.k[0];
+    int nlt = 0;   // entries with k_used > j form a prefix
+    for (int j = kmax; j >= 1; --j) {
+        int neq_end = nlt;
+        while (neq_end < L.n && L.k[neq_end] == j) ++neq_end;
+        if (nlt > 0) {
+            const SrcList Llt = prefix(L, nlt);
+            tslov::launch_bwd_ra<R>(g, wk, Llt, c->coef, j, c->st);
+            TimedLaunch tl(c, 1);
+            tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, wk, Llt, c->coef, j, 0, c->st);
+        }
+        if (neq_end > nlt) {
+            const SrcList Leq = range(L, nlt, neq_end);
+            tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, wk, Leq, c->coef, j, 1, c->st);
+        }
+        nlt = neq_end;
     }
-    // force contraction over all steps, split in chunks of j for parallelism
-    int nchunk = (1 << 18) / (4 * g.V);
-    if (nchunk < 1) nchunk = 1;
-    if (nchunk > k) nchunk = k;
-    if (nchunk > 64) nchunk = 64;
-    CHK(ensure(c->gpart, (size_t)nchunk * 36 * g.ldv * sizeof(ZD)));
-    tslov::launch_force<R>(g, c->kappa, c->mu, AB(1), SB(1), V(1), W(1), c->field_elems(), c->coef.status, nchunk,
-                           c->gpart.as<ZD>(), c->st);
-    tslov::launch_force_reduce(g, c->gpart.as<ZD>(), nchunk, c->antiperiodic, dU, c->st);
-    if (dpsi) tslov::launch_source_grad<R>(g, VB, WB, X, c->coef, part_array(c, 2), dpsi, c->st);
+    // force contraction over all steps, split in chunks of j for parallelism; the
+    // split depends on the lattice only, so a source's result does not depend on
+    // the batch it shares a launch with
+    const int nchunk = std::max(1, std::min((1 << 18) / (4 * g.V), 64));
+    CHK(ensure(c->gpart, (size_t)c->slots * nchunk * 36 * g.ldv * sizeof(ZD)));
+    tslov::launch_force<R>(g, c->kappa, c->mu, wk, L, nchunk, c->gpart.as<ZD>(), c->st);
+    if (out.dU) tslov::launch_force_reduce(g, c->gpart.as<ZD>(), nchunk, L, c->antiperiodic, out.dU, c->st);
+    double* gsrc = nullptr;
+    if (out.ward) {
+        CHK(ensure(c->gsrc, (size_t)c->slots * 4 * g.ldv * sizeof(double)));
+        gsrc = c->gsrc.as<double>();
+    }
+    if (out.jsum)
+        tslov::launch_force_current(g, c->gpart.as<ZD>(), nchunk, L, c->U64.as<ZD>(), gsrc, out.jsum,
+                                    out.accumulate, c->st);
+    if (out.dpsi) tslov::launch_source_grad<R>(g, wk, L, c->coef, out.dpsi, c->st);
+    if (out.ward) {
+        // per-entry y and dpsi in entry order
+        const size_t n12 = (size_t)12 * g.V;
+        CHK(ensure(c->bout, (size_t)2 * L.n * n12 * sizeof(ZD)));
+        ZD* y = c->bout.as<ZD>();
+        ZD* dp = y + L.n * n12;
+        SrcList Le = L;
+        for (int e = 0; e < L.n; ++e) Le.src[e] = e;
+        tslov::launch_assemble<R>(g, wk, Le, c->coef, nullptr, 0, y, c->st);
+        tslov::launch_source_grad<R>(g, wk, Le, c->coef, dp, c->st);
+        const int nb = c->nblk();
+        CHK(ensure(c->wardp, (size_t)L.n * nb * 2 * sizeof(double)));
+        CHK(ensure_host_part(c, 2 * L.n * nb));
+        tslov::launch_ward(g, gsrc, L, out.psi, y, dp, c->wardp.as<double>(), c->st);
+        HIPCHK(hipMemcpyAsync(c->host_part, c->wardp.p, (size_t)L.n * nb * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                              c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        for (int i = 0; i < L.n * nb; ++i) {
+            out.ward_max = std::max(out.ward_max, c->host_part[2 * i]);
+            out.g_max = std::max(out.g_max, c->host_part[2 * i + 1]);
+        }
+    }
     HIPCHK(hipGetLastError());
     return TSLOV_OK;
 }
@@ -404,6 +568,16 @@ tslov_status prepare_defl(tslov_ctx* c, const tslov_deflation* defl, DeflSet& d)
 
 ZD* canon_buf(tslov_ctx* c, int i) { return c->canon.as<ZD>() + (size_t)i * 12 * c->g.V; }
 
+void fill_info(tslov_info* info, const EntryStatus& s, const double* ms) {
+    if (!info) return;
+    std::memset(info, 0, sizeof(*info));
+    info->k_used = s.k_used;
+    info->breakdown = s.breakdown;
+    info->newton_iters = s.iters;
+    info->norm_x = s.norm_x;
+    for (int i = 0; i < 6; ++i) info->ms[i] = ms[i];
+}
+
 // out = [psi +] g5^{overlap} sgn(H) psi by TSL, with optional deflation.
 template <typename R>
 tslov_status sign_impl(tslov_ctx* c, const void* psi_in, void* out, int k, const tslov_deflation* defl,
@@ -414,97 +588,151 @@ tslov_status sign_impl(tslov_ctx* c, const void* psi_in, void* out, int k, const
     const ZD* psi = (const ZD*)psi_in;
     const ZD* src = psi;
     if (d.l) {
-        CHK(ensure(c->canon, (size_t)3 * 12 * c->g.V * sizeof(ZD)));
+        CHK(ensure(c->canon, (size_t)5 * 12 * c->g.V * sizeof(ZD)));
         tslov::launch_defl_coeffs(d.L, psi, c->g.V, d.l, d.part, d.c, c->st);
         tslov::launch_defl_project(d.R, psi, d.c, c->g.V, d.l, canon_buf(c, 0), c->st);
         src = canon_buf(c, 0);
     }
-    int k_used = 0, bd = 0;
-    CHK(forward<R>(c, src, nullptr, k, &k_used, &bd));
+    CHK(ensure_work(c, 1, k, 0));
+    const SrcList L = make_list({0}, {k});
+    std::vector<EntryStatus> es;
+    CHK(forward<R>(c, L, src, nullptr, 0, es));
+    if (es[0].breakdown == 2)
+        return fail(TSLOV_ERR_BREAKDOWN, "serious Lanczos breakdown at step " + std::to_string(es[0].step));
     const double t1 = now_ms();
-    int iters = 0;
+    const int k_used = es[0].k_used;
+    SrcList Ld = make_list({0}, {k_used});
     if (k_used > 0) {
-        DenseWork w;
-        CHK(ensure_dense(c, k_used, w));
-        tslov::launch_dense_build(c->coef, k_used, 0, w, c->st);
-        CHK(newton(c, k_used, 0, w, &iters));
-        tslov::launch_dense_extract(c->coef, k_used, 0, w, c->st);
+        std::vector<int> iters;
+        CHK(dense_step(c, Ld, 0, iters));
+        es[0].iters = iters[0];
     }
     const double t2 = now_ms();
+    const Work<R> wk = work<R>(c);
     if (d.l) {
         ZD* yp = nullptr;
         if (k_used > 0) {
             yp = canon_buf(c, 1);
-            tslov::launch_assemble<R>(c->g, c->basisV.as<Z<R>>(), c->field_elems(), c->coef, nullptr, 0, yp, c->st);
+            tslov::launch_assemble<R>(c->g, wk, Ld, c->coef, nullptr, 0, yp, c->st);
         }
         tslov::launch_defl_finish(d.R, d.c, d.sgn, yp, psi, c->g.V, d.l, overlap, (ZD*)out, c->st);
     } else if (k_used > 0) {
-        tslov::launch_assemble<R>(c->g, c->basisV.as<Z<R>>(), c->field_elems(), c->coef, psi, overlap, (ZD*)out,
-                                  c->st);
+        tslov::launch_assemble<R>(c->g, wk, Ld, c->coef, psi, overlap, (ZD*)out, c->st);
     } else {
         tslov::launch_defl_finish(nullptr, nullptr, nullptr, nullptr, psi, c->g.V, 0, overlap, (ZD*)out, c->st);
     }
     HIPCHK(hipGetLastError());
-    double nx = 0.0;
-    HIPCHK(hipMemcpyAsync(&nx, c->coef.misc, sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     const double t3 = now_ms();
-    if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->k_used = k_used;
-        info->breakdown = bd;
-        info->newton_iters = iters;
-        info->norm_x = nx;
-        info->ms[0] = t1 - t0;
-        info->ms[1] = t2 - t1;
-        info->ms[2] = t3 - t2;
-        info->ms[5] = t3 - t0;
-    }
+    const double ms[6] = {t1 - t0, t2 - t1, t3 - t2, 0.0, 0.0, t3 - t0};
+    fill_info(info, es[0], ms);
     return TSLOV_OK;
 }
 
+// Batched S_s = Re <eta_s | TSL(psi_s)> and its link derivative for nsrc sources
+// (canonical arrays indexed by source).  Sources are processed in groups of
+// decreasing Krylov size that fit the device memory.
+struct BatchRequest {
+    int nsrc = 0;
+    const ZD* eta = nullptr;   // null with eta_g5: eta = g5 psi
+    int eta_g5 = 0;
+    const ZD* psi = nullptr;
+    const int* k = nullptr;
+    double* S_out = nullptr;
+    ZD* dU = nullptr;
+    ZD* dpsi = nullptr;
+    double* jsum = nullptr;
+    int ward = 0;
+    tslov_info* infos = nullptr;
+    double ward_max = 0.0, g_max = 0.0;
+};
+
 template <typename R>
-tslov_status grad_impl(tslov_ctx* c, const void* eta, const void* psi, int k, double* S_out, void* dU, void* dpsi,
-                       tslov_info* info) {
+tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
     const double t0 = now_ms();
-    int k_used = 0, bd = 0;
-    CHK(forward<R>(c, (const ZD*)psi, (const ZD*)eta, k, &k_used, &bd));
-    const double t1 = now_ms();
-    if (k_used == 0) {   // zero source: S = 0 and every derivative vanishes
-        HIPCHK(hipMemsetAsync(dU, 0, (size_t)36 * c->g.V * sizeof(ZD), c->st));
-        if (dpsi) HIPCHK(hipMemsetAsync(dpsi, 0, (size_t)12 * c->g.V * sizeof(ZD), c->st));
-        HIPCHK(hipStreamSynchronize(c->st));
-        if (S_out) *S_out = 0.0;
-        if (info) {
-            std::memset(info, 0, sizeof(*info));
-            info->breakdown = bd;
+    std::vector<int> order(q.nsrc);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return q.k[a] > q.k[b]; });
+    const size_t n12 = (size_t)12 * c->g.V;
+    int first_group = 1;
+    std::string broken;
+    size_t pos = 0;
+    while (pos < order.size()) {
+        const int kcap = q.k[order[pos]];
+        const int cap = std::min(batch_capacity(c, kcap, 1), (int)(order.size() - pos));
+        std::vector<int> src(order.begin() + pos, order.begin() + pos + cap), ks(cap);
+        for (int e = 0; e < cap; ++e) ks[e] = q.k[src[e]];
+        pos += cap;
+        CHK(ensure_work(c, cap, kcap, 1));
+        const double tg0 = now_ms();
+        const SrcList L = make_list(src, ks);
+        std::vector<EntryStatus> es;
+        CHK(forward<R>(c, L, q.psi, q.eta_g5 ? q.psi : q.eta, q.eta_g5, es));
+        const double tg1 = now_ms();
+        // entries that go on to the derivative, in decreasing k_used
+        std::vector<int> live;
+        for (int e = 0; e < cap; ++e) {
+            const int s = src[e];
+            if (es[e].breakdown == 2) {
+                broken += (broken.empty() ? "" : ", ") + std::to_string(s) + " (step " + std::to_string(es[e].step) + ")";
+                continue;
+            }
+            if (es[e].k_used == 0) {   // zero source: S = 0 and every derivative vanishes
+                if (q.dU) tslov::launch_zero((double*)(q.dU + (size_t)s * 36 * c->g.V), (size_t)72 * c->g.V, c->st);
+                if (q.dpsi) tslov::launch_zero((double*)(q.dpsi + (size_t)s * n12), 2 * n12, c->st);
+                if (q.S_out) q.S_out[s] = 0.0;
+                continue;
+            }
+            live.push_back(e);
         }
-        return TSLOV_OK;
+        std::stable_sort(live.begin(), live.end(), [&](int a, int b) { return es[a].k_used > es[b].k_used; });
+        SrcList Ld{};
+        Ld.n = (int)live.size();
+        for (int i = 0; i < Ld.n; ++i) {
+            Ld.slot[i] = L.slot[live[i]];
+            Ld.src[i] = L.src[live[i]];
+            Ld.k[i] = es[live[i]].k_used;
+        }
+        std::vector<int> iters;
+        double tg2 = now_ms(), tg3 = tg2;
+        if (Ld.n > 0) {
+            CHK(dense_step(c, Ld, 1, iters));
+            tg2 = now_ms();
+            GradOut go;
+            go.dU = q.dU;
+            go.dpsi = q.dpsi;
+            go.jsum = q.jsum;
+            go.accumulate = first_group ? 0 : 1;
+            go.ward = q.ward;
+            go.psi = q.psi;
+            CHK(backward<R>(c, Ld, go));
+            q.ward_max = std::max(q.ward_max, go.ward_max);
+            q.g_max = std::max(q.g_max, go.g_max);
+            first_group = 0;
+            std::vector<double> misc((size_t)16 * cap);
+            HIPCHK(hipMemcpyAsync(misc.data(), c->coef.misc, misc.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->st));
+            HIPCHK(hipStreamSynchronize(c->st));
+            tg3 = now_ms();
+            for (int i = 0; i < Ld.n; ++i) {
+                const int e = live[i];
+                es[e].iters = iters[i];
+                es[e].S = misc[(size_t)16 * L.slot[e] + 1];
+                if (q.S_out) q.S_out[src[e]] = es[e].S;
+            }
+        } else if (q.jsum && first_group) {
+            tslov::launch_zero(q.jsum, (size_t)4 * c->g.V, c->st);
+            first_group = 0;
+        }
+        HIPCHK(hipStreamSynchronize(c->st));
+        const double ms[6] = {tg1 - tg0, tg2 - tg1, 0.0, tg3 - tg2, 0.0, tg3 - tg0};
+        if (q.infos)
+            for (int e = 0; e < cap; ++e) fill_info(&q.infos[src[e]], es[e], ms);
     }
-    DenseWork w;
-    CHK(ensure_dense(c, k_used, w));
-    tslov::launch_dense_build(c->coef, k_used, 1, w, c->st);
-    int iters = 0;
-    CHK(newton(c, k_used, 1, w, &iters));
-    tslov::launch_dense_extract(c->coef, k_used, 1, w, c->st);
-    const double t2 = now_ms();
-    CHK(backward<R>(c, k_used, (ZD*)dU, (ZD*)dpsi));
-    double misc[2] = {0.0, 0.0};
-    HIPCHK(hipMemcpyAsync(misc, c->coef.misc, sizeof(misc), hipMemcpyDeviceToHost, c->st));
+    if (q.jsum && first_group) tslov::launch_zero(q.jsum, (size_t)4 * c->g.V, c->st);
     HIPCHK(hipStreamSynchronize(c->st));
-    const double t3 = now_ms();
-    if (S_out) *S_out = misc[1];
-    if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->k_used = k_used;
-        info->breakdown = bd;
-        info->newton_iters = iters;
-        info->norm_x = misc[0];
-        info->ms[0] = t1 - t0;
-        info->ms[1] = t2 - t1;
-        info->ms[3] = t3 - t2;
-        info->ms[5] = t3 - t0;
-    }
+    (void)t0;
+    if (!broken.empty()) return fail(TSLOV_ERR_BREAKDOWN, "serious Lanczos breakdown for source(s) " + broken);
     return TSLOV_OK;
 }
 
@@ -555,9 +783,9 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
 void tslov_destroy(tslov_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
-    for (Buf* b : {&c->U64, &c->U32, &c->fields, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
-                   &c->bwork, &c->part, &c->canon, &c->deflw,
-                   &c->coefmem, &c->dense, &c->denseInt, &c->denseLog, &c->densePart, &c->gpart})
+    for (Buf* b : {&c->U64, &c->U32, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
+                   &c->fields, &c->part, &c->coefmem, &c->dense, &c->denseInt, &c->densePart, &c->denseDelta,
+                   &c->gpart, &c->gsrc, &c->bout, &c->wardp, &c->canon, &c->deflw})
         release(*b);
     if (c->host_part) (void)hipHostFree(c->host_part);
     for (auto& v : c->ev_used)
@@ -582,10 +810,10 @@ static tslov_status apply_op(tslov_ctx* c, const void* in, void* out, double mu,
     if (!c || !in || !out) return fail(TSLOV_ERR_ARG, "null argument");
     if (!c->links_set) return fail(TSLOV_ERR_ARG, "links not set (call tslov_set_links first)");
     if (in == out) return fail(TSLOV_ERR_ARG, "in and out must not overlap");
-    CHK(ensure(c->fields, 6 * c->field_bytes()));
+    CHK(ensure(c->opf, 2 * c->field_bytes()));
     if (c->precision == TSLOV_MIXED) {
-        Z<float>* a = fld<float>(c->fields, c, 0);
-        Z<float>* b = fld<float>(c->fields, c, 1);
+        Z<float>* a = c->opf.as<Z<float>>();
+        Z<float>* b = a + c->field_elems();
         tslov::launch_spinor_to_soa<float>((const ZD*)in, a, c->g, nullptr, c->st);
         {
             TimedLaunch tl(c, 2);
@@ -593,8 +821,8 @@ static tslov_status apply_op(tslov_ctx* c, const void* in, void* out, double mu,
         }
         tslov::launch_spinor_from_soa<float>(b, (ZD*)out, c->g, c->st);
     } else {
-        ZD* a = fld<double>(c->fields, c, 0);
-        ZD* b = fld<double>(c->fields, c, 1);
+        ZD* a = c->opf.as<ZD>();
+        ZD* b = a + c->field_elems();
         tslov::launch_spinor_to_soa<double>((const ZD*)in, a, c->g, nullptr, c->st);
         {
             TimedLaunch tl(c, 2);
@@ -634,6 +862,10 @@ tslov_status tslov_overlap(tslov_ctx* c, const void* psi, void* out, int k, cons
                                        : sign_impl<double>(c, psi, out, k, defl, info, 1);
 }
 
+static tslov_status run_batched(tslov_ctx* c, BatchRequest& q) {
+    return c->precision == TSLOV_MIXED ? grad_batched<float>(c, q) : grad_batched<double>(c, q);
+}
+
 tslov_status tslov_sign_grad(tslov_ctx* c, const void* eta, const void* psi, int k, const tslov_deflation* defl,
                              int recompute_stride, double* S_out, void* dU_out, void* dpsi_out, tslov_info* info) {
     CHK(check_common(c, k, defl));
@@ -641,8 +873,60 @@ tslov_status tslov_sign_grad(tslov_ctx* c, const void* eta, const void* psi, int
     if (defl && defl->l != 0)
         return fail(TSLOV_ERR_ARG, "the derivative with deflation (eigenpair motion) is not supported; pass NULL");
     if (recompute_stride != 0) return fail(TSLOV_ERR_ARG, "recompute_stride must be 0 (all vectors stored)");
-    return c->precision == TSLOV_MIXED ? grad_impl<float>(c, eta, psi, k, S_out, dU_out, dpsi_out, info)
-                                       : grad_impl<double>(c, eta, psi, k, S_out, dU_out, dpsi_out, info);
+    BatchRequest q;
+    q.nsrc = 1;
+    q.eta = (const ZD*)eta;
+    q.psi = (const ZD*)psi;
+    q.k = &k;
+    q.S_out = S_out;
+    q.dU = (ZD*)dU_out;
+    q.dpsi = (ZD*)dpsi_out;
+    q.infos = info;
+    return run_batched(c, q);
+}
+
+tslov_status tslov_sign_grad_batched(tslov_ctx* c, int nsrc, const void* eta, const void* psi, const int* k,
+                                     double* S_out, void* dU_out, void* dpsi_out, tslov_info* infos) {
+    if (!c) return fail(TSLOV_ERR_ARG, "null context");
+    if (!c->links_set) return fail(TSLOV_ERR_ARG, "links not set (call tslov_set_links first)");
+    if (nsrc < 1 || nsrc > kMaxSources) return fail(TSLOV_ERR_ARG, "nsrc must be in [1, 2^20]");
+    if (!eta || !psi || !k || !dU_out) return fail(TSLOV_ERR_ARG, "null argument");
+    for (int s = 0; s < nsrc; ++s)
+        if (k[s] < 1 || k[s] > kMaxK) return fail(TSLOV_ERR_ARG, "every k must be in [1, 1024]");
+    BatchRequest q;
+    q.nsrc = nsrc;
+    q.eta = (const ZD*)eta;
+    q.psi = (const ZD*)psi;
+    q.k = k;
+    q.S_out = S_out;
+    q.dU = (ZD*)dU_out;
+    q.dpsi = (ZD*)dpsi_out;
+    q.infos = infos;
+    return run_batched(c, q);
+}
+
+tslov_status tslov_current_estimate(tslov_ctx* c, int nsrc, const void* xi, const int* k, double* j_out,
+                                    double* div_out, double* tot_out, double* ward_out, tslov_info* infos) {
+    if (!c) return fail(TSLOV_ERR_ARG, "null context");
+    if (!c->links_set) return fail(TSLOV_ERR_ARG, "links not set (call tslov_set_links first)");
+    if (nsrc < 1 || nsrc > kMaxSources) return fail(TSLOV_ERR_ARG, "nsrc must be in [1, 2^20]");
+    if (!xi || !k || !j_out) return fail(TSLOV_ERR_ARG, "null argument");
+    for (int s = 0; s < nsrc; ++s)
+        if (k[s] < 1 || k[s] > kMaxK) return fail(TSLOV_ERR_ARG, "every k must be in [1, 1024]");
+    BatchRequest q;
+    q.nsrc = nsrc;
+    q.eta_g5 = 1;
+    q.psi = (const ZD*)xi;
+    q.k = k;
+    q.jsum = j_out;
+    q.ward = ward_out ? 1 : 0;
+    q.infos = infos;
+    CHK(run_batched(c, q));
+    tslov::launch_current_finish(c->g, j_out, 1.0 / nsrc, div_out, tot_out, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (ward_out) *ward_out = q.g_max > 0.0 ? q.ward_max / q.g_max : q.ward_max;
+    return TSLOV_OK;
 }
 
 tslov_status tslov_error_estimate(tslov_ctx* c, const void* psi, int k, const tslov_deflation* defl,
@@ -652,7 +936,6 @@ tslov_status tslov_error_estimate(tslov_ctx* c, const void* psi, int k, const ts
     const size_t n = (size_t)12 * c->g.V;
     // canonical buffers 0..2 serve the deflated sign; y and z take 3 and 4
     CHK(ensure(c->canon, (size_t)5 * n * sizeof(ZD)));
-    CHK(ensure_part(c));
     ZD* y = canon_buf(c, 3);
     ZD* z = canon_buf(c, 4);
     tslov_status s = c->precision == TSLOV_MIXED ? sign_impl<float>(c, psi, y, k, defl, nullptr, 0)
@@ -662,7 +945,7 @@ tslov_status tslov_error_estimate(tslov_ctx* c, const void* psi, int k, const ts
                                         : sign_impl<double>(c, y, z, k, defl, nullptr, 0);
     if (s != TSLOV_OK) return s;
     CHK(ensure_host_part(c, 2048));
-    double* part = part_array(c, 2);
+    double* part = c->part.as<double>() + 2 * c->pstride();
     const int nb = tslov::launch_diff_norm(z, (const ZD*)psi, n, part, c->st);
     HIPCHK(hipMemcpyAsync(c->host_part, part, (size_t)2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
@@ -682,13 +965,16 @@ tslov_status tslov_dense_sign(tslov_ctx* c, const void* T, int k, const void* E,
     if (k < 1 || k > kMaxK) return fail(TSLOV_ERR_ARG, "k must be in [1, 1024]");
     if (E && !L_out) return fail(TSLOV_ERR_ARG, "L_out required when E is given");
     DenseWork w;
-    CHK(ensure_dense(c, k, w));
+    CHK(ensure_dense(c, 1, k, w));
     tslov::launch_dense_load((const ZD*)T, (const ZD*)E, k, w, c->st);
-    CHK(newton(c, k, E ? 1 : 0, w, iters));
+    const SrcList L = make_list({0}, {k});
+    std::vector<int> it;
+    CHK(newton(c, L, E ? 1 : 0, w, it));
     const size_t bytes = (size_t)k * k * sizeof(ZD);
     HIPCHK(hipMemcpyAsync(S_out, w.X, bytes, hipMemcpyDeviceToDevice, c->st));
     if (E) HIPCHK(hipMemcpyAsync(L_out, w.Y, bytes, hipMemcpyDeviceToDevice, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
+    if (iters) *iters = it[0];
     return TSLOV_OK;
 }
 

@@ -407,6 +407,29 @@ struct Coef {
     ZD* gbar_tot;
     int* status;    // [0] stop flag, [1] k_used, [2] breakdown code, [3] breakdown step
     double* misc;   // [0] |x|, [1] S, [2] mu (Newton scaling), [3] scratch
+    int n;          // entries per source of every per-step array (sources are stacked)
+
+    // The coefficient set of batch slot `slot` (per-step arrays of n entries,
+    // status and misc of 16 entries per source).
+    __host__ __device__ Coef at(int slot) const {
+        Coef o = *this;
+        const size_t d = (size_t)slot * n, m = (size_t)slot * 16;
+        o.alpha += d; o.beta += d; o.gamma += d; o.anorm2 += d; o.h += d; o.c += d;
+        o.abar_T += d; o.bbar_T += d; o.gbar_T += d; o.bbar_tot += d; o.gbar_tot += d;
+        o.status += m; o.misc += m;
+        return o;
+    }
+};
+
+// Sources of one batched launch: entry e (a grid index) is batch slot slot[e],
+// the caller's source src[e], with per-entry size k[e] (a Krylov size) and flag[e].
+constexpr int kMaxBatch = 64;
+struct SrcList {
+    int n;
+    int slot[kMaxBatch];
+    int src[kMaxBatch];
+    int k[kMaxBatch];
+    int flag[kMaxBatch];
 };
 
 constexpr double kTauLucky = 1e-11;

@@ -6,7 +6,9 @@
 // in-place, blocked Gauss-Jordan elimination with partial pivoting: one block
 // factors a panel of nb columns in LDS, then all blocks apply the panel's
 // transform to the remaining columns; the row permutation is undone by a
-// column scatter.  All arithmetic is float64 complex.
+// column scatter.  All arithmetic is float64 complex.  Every kernel serves a list
+// of independent matrices (one per batch entry, sizes k[e] in decreasing order);
+// grid dimension z runs over the entries.
 #include "kernels.h"
 
 #include <cmath>
@@ -15,8 +17,10 @@ namespace tslov {
 
 constexpr int kDB = 256;   // threads per block of the dense kernels
 
-__global__ __launch_bounds__(kDB) void k_dense_build(Coef coef, int k, int grad, ZD* __restrict__ X,
-                                                     ZD* __restrict__ Wk, ZD* __restrict__ Y) {
+__global__ __launch_bounds__(kDB) void k_dense_build(Coef coef0, SrcList L, int grad, DenseWork w0) {
+    const int e = blockIdx.z, slot = L.slot[e], k = L.k[e];
+    const Coef coef = coef0.at(slot);
+    const DenseWork w = w0.at(slot);
     const int idx = blockIdx.x * kDB + threadIdx.x;
     if (idx >= k * k) return;
     const int i = idx / k, c = idx % k;   // 0-based; Lanczos index j = i + 1
@@ -24,32 +28,35 @@ __global__ __launch_bounds__(kDB) void k_dense_build(Coef coef, int k, int grad,
     if (i == c) v = coef.alpha[i + 1];
     else if (i == c + 1) v = mk<double>(coef.beta[i + 1], 0.0);   // T_{j+1,j} = beta_{j+1}
     else if (c == i + 1) v = coef.gamma[c + 1];                   // T_{j,j+1} = gamma_{j+1}
-    X[idx] = v;
-    Wk[idx] = v;
-    if (grad) Y[idx] = (i == 0) ? coef.misc[0] * coef.h[c + 1] : mk<double>(0, 0);  // E = e_1 cbar^H
+    w.X[idx] = v;
+    w.Wk[idx] = v;
+    if (grad) w.Y[idx] = (i == 0) ? coef.misc[0] * coef.h[c + 1] : mk<double>(0, 0);  // E = e_1 cbar^H
 }
 
-void launch_dense_build(Coef coef, int k, int grad, DenseWork w, hipStream_t st) {
-    hipLaunchKernelGGL(k_dense_build, dim3(grid_for(k * k, kDB)), dim3(kDB), 0, st, coef, k, grad, w.X, w.Wk, w.Y);
+void launch_dense_build(Coef coef, const SrcList& L, int grad, const DenseWork& w, hipStream_t st) {
+    const int k = L.k[0];
+    hipLaunchKernelGGL(k_dense_build, dim3(grid_for(k * k, kDB), 1, L.n), dim3(kDB), 0, st, coef, L, grad, w);
 }
 
 __global__ __launch_bounds__(kDB) void k_dense_load(const ZD* __restrict__ T, const ZD* __restrict__ E, int k,
-                                                    ZD* __restrict__ X, ZD* __restrict__ Wk, ZD* __restrict__ Y) {
+                                                    DenseWork w) {
     const int idx = blockIdx.x * kDB + threadIdx.x;
     if (idx >= k * k) return;
-    X[idx] = T[idx];
-    Wk[idx] = T[idx];
-    if (E) Y[idx] = E[idx];
+    w.X[idx] = T[idx];
+    w.Wk[idx] = T[idx];
+    if (E) w.Y[idx] = E[idx];
 }
 
-void launch_dense_load(const ZD* T, const ZD* E, int k, DenseWork w, hipStream_t st) {
-    hipLaunchKernelGGL(k_dense_load, dim3(grid_for(k * k, kDB)), dim3(kDB), 0, st, T, E, k, w.X, w.Wk, w.Y);
+void launch_dense_load(const ZD* T, const ZD* E, int k, const DenseWork& w, hipStream_t st) {
+    hipLaunchKernelGGL(k_dense_load, dim3(grid_for(k * k, kDB)), dim3(kDB), 0, st, T, E, k, w);
 }
 
 // ------------------------------------------------------------------ Gauss-Jordan
-__global__ __launch_bounds__(kDB) void k_rowperm_init(int* rowperm, int k) {
+__global__ __launch_bounds__(kDB) void k_rowperm_init(SrcList L, DenseWork w0) {
+    const int e = blockIdx.z;
+    const DenseWork w = w0.at(L.slot[e]);
     const int i = blockIdx.x * kDB + threadIdx.x;
-    if (i < k) rowperm[i] = i;
+    if (i < L.k[e]) w.rowperm[i] = i;
 }
 
 // Panel K: columns [c0, c0 + nbK) of Wk, all k rows, held in LDS and factored by
@@ -64,10 +71,15 @@ __global__ __launch_bounds__(kDB) void k_rowperm_init(int* rowperm, int k) {
 // its writes, so two block barriers per pivot suffice; no global memory traffic
 // happens inside the loop (a barrier would wait for it).
 template <int NB>
-__global__ __launch_bounds__(kDB) void k_gj_panel(ZD* __restrict__ Wk, int k, int c0, int* __restrict__ rowperm,
-                                                  int* __restrict__ ipiv) {
+__global__ __launch_bounds__(kDB) void k_gj_panel(DenseWork w0, SrcList L, int c0) {
     extern __shared__ ZD P[];   // k rows of stride NB + 1 (odd: spreads rows over the LDS banks)
     constexpr int LD = NB + 1;
+    const int e = blockIdx.z, k = L.k[e];
+    if (c0 >= k) return;
+    const DenseWork w = w0.at(L.slot[e]);
+    ZD* __restrict__ Wk = w.Wk;
+    int* __restrict__ rowperm = w.rowperm;
+    int* __restrict__ ipiv = w.rowperm + w.kcap;
     int* perm = reinterpret_cast<int*>(P + (size_t)k * LD);
     __shared__ int piv_s[NB];
     __shared__ double wbest[kDB / kWave];
@@ -76,8 +88,8 @@ __global__ __launch_bounds__(kDB) void k_gj_panel(ZD* __restrict__ Wk, int k, in
     const int nbK = min(NB, k - c0);
     for (int i = tid; i < k; i += kDB) perm[i] = rowperm[i];
 #pragma unroll 8
-    for (int e = tid; e < k * NB; e += kDB) {
-        const int i = e / NB, q = e % NB;
+    for (int x = tid; x < k * NB; x += kDB) {
+        const int i = x / NB, q = x % NB;
         P[i * LD + q] = Wk[(size_t)i * k + c0 + (q < nbK ? q : nbK - 1)];
     }
     __syncthreads();
@@ -100,8 +112,8 @@ __global__ __launch_bounds__(kDB) void k_gj_panel(ZD* __restrict__ Wk, int k, in
         double b = wbest[0];
         int imax = wi[0];
 #pragma unroll
-        for (int w = 1; w < kDB / kWave; ++w)
-            if (wbest[w] > b || (wbest[w] == b && wi[w] < imax)) { b = wbest[w]; imax = wi[w]; }
+        for (int v = 1; v < kDB / kWave; ++v)
+            if (wbest[v] > b || (wbest[v] == b && wi[v] < imax)) { b = wbest[v]; imax = wi[v]; }
         if (imax < p || imax >= k) imax = p;   // non-finite column: keep the order, the NaN propagates
         // reads: pivot row (all threads), old row p (owner of row imax), own rows' factors
         const ZD inv = zdiv(mk<double>(1.0, 0.0), P[imax * LD + q]);
@@ -150,8 +162,8 @@ __global__ __launch_bounds__(kDB) void k_gj_panel(ZD* __restrict__ Wk, int k, in
     if (tid < nbK) ipiv[c0 + tid] = piv_s[tid];
     for (int i = tid; i < k; i += kDB) rowperm[i] = perm[i];
 #pragma unroll 8
-    for (int e = tid; e < k * NB; e += kDB) {
-        const int i = e / NB, q = e % NB;
+    for (int x = tid; x < k * NB; x += kDB) {
+        const int i = x / NB, q = x % NB;
         if (q < nbK) Wk[(size_t)i * k + c0 + q] = P[i * LD + q];
     }
 }
@@ -160,24 +172,28 @@ __global__ __launch_bounds__(kDB) void k_gj_panel(ZD* __restrict__ Wk, int k, in
 // x <- swaps(x);  x_new[i] = [i outside panel] x[i] + sum_q P[i][q] x[c0 + q].
 // Thread t owns rows i = t, t + 256, ... of the block's TC columns.
 template <int NB>
-__global__ __launch_bounds__(kDB) void k_gj_trailing(ZD* __restrict__ Wk, int k, int c0, int TC,
-                                                     const int* __restrict__ ipiv) {
+__global__ __launch_bounds__(kDB) void k_gj_trailing(DenseWork w0, SrcList L, int c0, int TC) {
     extern __shared__ ZD smem[];
+    const int e = blockIdx.z, k = L.k[e];
+    if (c0 >= k) return;
     const int nbK = min(NB, k - c0);
-    const int LT = TC + 1;      // odd row stride: rows spread over the LDS banks
-    ZD* xs = smem;              // k rows of stride LT
-    ZD* xp = smem + k * LT;     // nbK * TC
-    const int tid = threadIdx.x;
     const int nother = k - nbK;
     const int cid0 = blockIdx.x * TC;
     const int tcv = min(TC, nother - cid0);
     if (tcv <= 0) return;
+    const DenseWork w = w0.at(L.slot[e]);
+    ZD* __restrict__ Wk = w.Wk;
+    const int* __restrict__ ipiv = w.rowperm + w.kcap;
+    const int LT = TC + 1;      // odd row stride: rows spread over the LDS banks
+    ZD* xs = smem;              // k rows of stride LT
+    ZD* xp = smem + k * LT;     // nbK * TC
+    const int tid = threadIdx.x;
     // flat, unrolled staging (TC is a power of two): columns past the last valid
     // one are clamped instead of branched around, so loads stay in flight
     const int sh = __builtin_ctz(TC);
 #pragma unroll 8
-    for (int e = tid; e < k * TC; e += kDB) {
-        const int i = e >> sh, t = e & (TC - 1);
+    for (int x = tid; x < k * TC; x += kDB) {
+        const int i = x >> sh, t = x & (TC - 1);
         const int cid = cid0 + (t < tcv ? t : tcv - 1);
         const int c = cid < c0 ? cid : cid + nbK;
         xs[i * LT + t] = Wk[(size_t)i * k + c];
@@ -216,36 +232,42 @@ __global__ __launch_bounds__(kDB) void k_gj_trailing(ZD* __restrict__ Wk, int k,
 }
 
 // X^{-1}[:, rowperm[i]] = Wk[:, i], with per-block partials of |X^{-1}|_F^2 and |X|_F^2.
-__global__ __launch_bounds__(kDB) void k_dense_scatter(const ZD* __restrict__ Wk, const int* __restrict__ rowperm,
-                                                       int k, ZD* __restrict__ Xinv, const ZD* __restrict__ X,
-                                                       double* __restrict__ part) {
+__global__ __launch_bounds__(kDB) void k_dense_scatter(DenseWork w0, SrcList L) {
+    const int e = blockIdx.z, k = L.k[e];
+    const DenseWork w = w0.at(L.slot[e]);
     const int idx = blockIdx.x * kDB + threadIdx.x;
     double v[2] = {0.0, 0.0};
     if (idx < k * k) {
         const int r = idx / k, i = idx % k;
-        const ZD w = Wk[idx];
-        Xinv[(size_t)r * k + rowperm[i]] = w;
-        v[0] = norm2(w);
-        v[1] = norm2(X[idx]);
+        const ZD x = w.Wk[idx];
+        w.Xinv[(size_t)r * k + w.rowperm[i]] = x;
+        v[0] = norm2(x);
+        v[1] = norm2(w.X[idx]);
     }
-    write_partials<2, kDB>(part, v);
+    write_partials<2, kDB>(w.part + 2 * w.npart_max, v);
 }
 
-// Newton scaling: mu = sqrt(|X^{-1}|_F / |X|_F) while scaling is on, else 1.
-__global__ __launch_bounds__(kDB) void k_dense_mu(const double* __restrict__ part, int npart, int scaling,
-                                                  double* __restrict__ mu_out) {
+// Newton scaling: mu = sqrt(|X^{-1}|_F / |X|_F) while scaling is on (flag), else 1.
+__global__ __launch_bounds__(kDB) void k_dense_mu(DenseWork w0, SrcList L, int npart) {
+    const int e = blockIdx.z;
+    const DenseWork w = w0.at(L.slot[e]);
     double red[2];
-    reduce_partials<2, kDB>(part, npart, red);
-    if (threadIdx.x == 0) *mu_out = scaling ? std::sqrt(std::sqrt(red[0] / red[1])) : 1.0;
+    reduce_partials<2, kDB>(w.part + 2 * w.npart_max, npart, red);
+    if (threadIdx.x == 0) w.part[4 * w.npart_max] = L.flag[e] ? std::sqrt(std::sqrt(red[0] / red[1])) : 1.0;
 }
 
 // ------------------------------------------------------------------ complex GEMM
-// mode 0: C = A B;  mode 1: C <- (mu C - (A B)/mu)/2  (mu read from device).
+// mode 0: Zt = Xinv Y;  mode 1: Y <- (mu Y - (Zt Xinv)/mu)/2  (mu read from device).
 // 16 x 16 output tiles, one output per thread, 16-deep LDS tiles of A and B.
-__global__ __launch_bounds__(kDB) void k_zgemm(const ZD* __restrict__ A, const ZD* __restrict__ B, ZD* __restrict__ C,
-                                               int k, int mode, const double* __restrict__ mu_p) {
+__global__ __launch_bounds__(kDB) void k_zgemm(DenseWork w0, SrcList L, int mode) {
     __shared__ ZD As[16][17];
     __shared__ ZD Bs[16][17];
+    const int e = blockIdx.z, k = L.k[e];
+    if ((int)blockIdx.x * 16 >= k || (int)blockIdx.y * 16 >= k) return;
+    const DenseWork w = w0.at(L.slot[e]);
+    const ZD* __restrict__ A = mode == 0 ? w.Xinv : w.Zt;
+    const ZD* __restrict__ B = mode == 0 ? w.Y : w.Xinv;
+    ZD* __restrict__ C = mode == 0 ? w.Zt : w.Y;
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     const int r = blockIdx.y * 16 + ty, c = blockIdx.x * 16 + tx;
     ZD acc = mk<double>(0, 0);
@@ -261,7 +283,7 @@ __global__ __launch_bounds__(kDB) void k_zgemm(const ZD* __restrict__ A, const Z
         const size_t o = (size_t)r * k + c;
         if (mode == 0) C[o] = acc;
         else {
-            const double mu = *mu_p;
+            const double mu = w.part[4 * w.npart_max];
             C[o] = 0.5 * (mu * C[o] - (1.0 / mu) * acc);
         }
     }
@@ -269,85 +291,97 @@ __global__ __launch_bounds__(kDB) void k_zgemm(const ZD* __restrict__ A, const Z
 
 // X <- (mu X + X^{-1}/mu)/2, copy into Wk for the next inversion, partials of
 // |X_new - X|^2 and |X_new|^2.
-__global__ __launch_bounds__(kDB) void k_dense_update(ZD* __restrict__ X, ZD* __restrict__ Wk,
-                                                      const ZD* __restrict__ Xinv, int k, const double* __restrict__ mu_p,
-                                                      double* __restrict__ part) {
+__global__ __launch_bounds__(kDB) void k_dense_update(DenseWork w0, SrcList L) {
+    const int e = blockIdx.z, k = L.k[e];
+    const DenseWork w = w0.at(L.slot[e]);
     const int idx = blockIdx.x * kDB + threadIdx.x;
-    const double mu = *mu_p;
+    const double mu = w.part[4 * w.npart_max];
     double v[2] = {0.0, 0.0};
     if (idx < k * k) {
-        const ZD x = X[idx];
-        const ZD xn = 0.5 * (mu * x + (1.0 / mu) * Xinv[idx]);
+        const ZD x = w.X[idx];
+        const ZD xn = 0.5 * (mu * x + (1.0 / mu) * w.Xinv[idx]);
         v[0] = norm2(xn - x);
         v[1] = norm2(xn);
-        X[idx] = xn;
-        Wk[idx] = xn;
+        w.X[idx] = xn;
+        w.Wk[idx] = xn;
     }
-    write_partials<2, kDB>(part, v);
+    write_partials<2, kDB>(w.part, v);
 }
 
-int dense_newton_step(int k, int grad, int scaling, int nb, size_t lds_bytes, DenseWork w, hipStream_t st) {
-    hipLaunchKernelGGL(k_rowperm_init, dim3(grid_for(k, kDB)), dim3(kDB), 0, st, w.rowperm, k);
-    int* ipiv = w.rowperm + k;
-    const size_t panel_lds = (size_t)(k * (nb + 1)) * sizeof(ZD) + (size_t)k * sizeof(int);
-    // trailing tile: TC columns of k + nb complex values each, within the LDS budget
+__global__ __launch_bounds__(kDB) void k_dense_delta(DenseWork w0, SrcList L, int npart) {
+    const int e = blockIdx.z;
+    const DenseWork w = w0.at(L.slot[e]);
+    double red[2];
+    reduce_partials<2, kDB>(w.part, npart, red);
+    if (threadIdx.x == 0) {
+        w.delta[0] = red[0];
+        w.delta[1] = red[1];
+    }
+}
+
+template <int NB>
+void gj_sweep(const SrcList& L, int TC, size_t panel_lds, const DenseWork& w, hipStream_t st) {
+    const int kmax = L.k[0];
+    SrcList act = L;
+    for (int c0 = 0; c0 < kmax; c0 += NB) {
+        while (act.n > 0 && act.k[act.n - 1] <= c0) --act.n;   // entries sorted by decreasing k
+        hipLaunchKernelGGL(k_gj_panel<NB>, dim3(1, 1, act.n), dim3(kDB), panel_lds, st, w, act, c0);
+        const int nbK = (kmax - c0) < NB ? (kmax - c0) : NB;
+        const int nother = kmax - nbK;
+        if (nother > 0) {
+            const size_t tl = (size_t)(kmax * (TC + 1) + NB * TC) * sizeof(ZD);
+            hipLaunchKernelGGL(k_gj_trailing<NB>, dim3(grid_for(nother, TC), 1, act.n), dim3(kDB), tl, st, w, act,
+                               c0, TC);
+        }
+    }
+}
+
+void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, const DenseWork& w, hipStream_t st) {
+    const int kmax = L.k[0];
+    hipLaunchKernelGGL(k_rowperm_init, dim3(grid_for(kmax, kDB), 1, L.n), dim3(kDB), 0, st, L, w);
+    const size_t panel_lds = (size_t)(kmax * (nb + 1)) * sizeof(ZD) + (size_t)kmax * sizeof(int);
     // trailing tile: TC columns per block; small enough to spread over many CUs,
     // large enough to amortise each row's panel load, and within the LDS budget
-    const int tc_want = (k - nb) / 96;
-    const int tc_lds = (int)((lds_bytes - 2048) / ((size_t)(k + nb) * sizeof(ZD))) - 1;
+    const int tc_want = (kmax - nb) / 96;
+    const int tc_lds = (int)((lds_bytes - 2048) / ((size_t)(kmax + nb) * sizeof(ZD))) - 1;
     int TC = 1;   // largest power of two <= min(tc_want, tc_lds, 16)
     while (TC * 2 <= tc_want && TC * 2 <= tc_lds && TC * 2 <= 16) TC *= 2;
-    for (int c0 = 0; c0 < k; c0 += nb) {
-        switch (nb) {
-            case 16: hipLaunchKernelGGL(k_gj_panel<16>, dim3(1), dim3(kDB), panel_lds, st, w.Wk, k, c0, w.rowperm, ipiv); break;
-            case 8: hipLaunchKernelGGL(k_gj_panel<8>, dim3(1), dim3(kDB), panel_lds, st, w.Wk, k, c0, w.rowperm, ipiv); break;
-            case 4: hipLaunchKernelGGL(k_gj_panel<4>, dim3(1), dim3(kDB), panel_lds, st, w.Wk, k, c0, w.rowperm, ipiv); break;
-            case 2: hipLaunchKernelGGL(k_gj_panel<2>, dim3(1), dim3(kDB), panel_lds, st, w.Wk, k, c0, w.rowperm, ipiv); break;
-            default: hipLaunchKernelGGL(k_gj_panel<1>, dim3(1), dim3(kDB), panel_lds, st, w.Wk, k, c0, w.rowperm, ipiv); break;
-        }
-        const int nbK = (k - c0) < nb ? (k - c0) : nb;
-        const int nother = k - nbK;
-        if (nother > 0) {
-            const size_t tl = (size_t)(k * (TC + 1) + nbK * TC) * sizeof(ZD);
-            const dim3 gt(grid_for(nother, TC));
-            switch (nb) {
-                case 16: hipLaunchKernelGGL(k_gj_trailing<16>, gt, dim3(kDB), tl, st, w.Wk, k, c0, TC, ipiv); break;
-                case 8: hipLaunchKernelGGL(k_gj_trailing<8>, gt, dim3(kDB), tl, st, w.Wk, k, c0, TC, ipiv); break;
-                case 4: hipLaunchKernelGGL(k_gj_trailing<4>, gt, dim3(kDB), tl, st, w.Wk, k, c0, TC, ipiv); break;
-                case 2: hipLaunchKernelGGL(k_gj_trailing<2>, gt, dim3(kDB), tl, st, w.Wk, k, c0, TC, ipiv); break;
-                default: hipLaunchKernelGGL(k_gj_trailing<1>, gt, dim3(kDB), tl, st, w.Wk, k, c0, TC, ipiv); break;
-            }
-        }
+    switch (nb) {
+        case 16: gj_sweep<16>(L, TC, panel_lds, w, st); break;
+        case 8: gj_sweep<8>(L, TC, panel_lds, w, st); break;
+        case 4: gj_sweep<4>(L, TC, panel_lds, w, st); break;
+        case 2: gj_sweep<2>(L, TC, panel_lds, w, st); break;
+        default: gj_sweep<1>(L, TC, panel_lds, w, st); break;
     }
-    const int nblk = grid_for(k * k, kDB);
-    double* mu = w.part + 4 * w.npart_max;    // device scalar after the partials
-    double* spart = w.part + 2 * w.npart_max;  // norm partials of the scatter
-    hipLaunchKernelGGL(k_dense_scatter, dim3(nblk), dim3(kDB), 0, st, w.Wk, w.rowperm, k, w.Xinv, w.X, spart);
-    hipLaunchKernelGGL(k_dense_mu, dim3(1), dim3(kDB), 0, st, spart, nblk, scaling, mu);
+    const int nblk = grid_for(kmax * kmax, kDB);
+    hipLaunchKernelGGL(k_dense_scatter, dim3(nblk, 1, L.n), dim3(kDB), 0, st, w, L);
+    hipLaunchKernelGGL(k_dense_mu, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, nblk);
     if (grad) {
-        dim3 g2(grid_for(k, 16), grid_for(k, 16));
-        hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w.Xinv, w.Y, w.Zt, k, 0, mu);
-        hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w.Zt, w.Xinv, w.Y, k, 1, mu);
+        dim3 g2(grid_for(kmax, 16), grid_for(kmax, 16), L.n);
+        hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w, L, 0);
+        hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w, L, 1);
     }
-    hipLaunchKernelGGL(k_dense_update, dim3(nblk), dim3(kDB), 0, st, w.X, w.Wk, w.Xinv, k, mu, w.part);
-    return nblk;
+    hipLaunchKernelGGL(k_dense_update, dim3(nblk, 1, L.n), dim3(kDB), 0, st, w, L);
+    hipLaunchKernelGGL(k_dense_delta, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, nblk);
 }
 
 // c_j = X[j][0]; adjoint seeds alphabar_j = conj(G_jj), betabar_{j+1} = Re G_{j,j+1},
 // gammabar_{j+1} = conj(G_{j+1,j}) from G = Y (so that dS = Re tr(dT G));
 // S = |x| Re sum_j c_j h_j.
-__global__ __launch_bounds__(kDB) void k_dense_extract(Coef coef, int k, int grad, const ZD* __restrict__ X,
-                                                       const ZD* __restrict__ Y) {
+__global__ __launch_bounds__(kDB) void k_dense_extract(Coef coef0, SrcList L, int grad, DenseWork w0) {
+    const int e = blockIdx.z, slot = L.slot[e], k = L.k[e];
+    const Coef coef = coef0.at(slot);
+    const DenseWork w = w0.at(slot);
     double v[1] = {0.0};
     for (int j = threadIdx.x; j < k; j += kDB) {
-        const ZD c = X[(size_t)j * k];
+        const ZD c = w.X[(size_t)j * k];
         coef.c[j + 1] = c;
         if (grad) {
             v[0] += (c * coef.h[j + 1]).re;
-            coef.abar_T[j + 1] = cj(Y[(size_t)j * k + j]);
+            coef.abar_T[j + 1] = cj(w.Y[(size_t)j * k + j]);
             if (j + 1 < k) {
-                const double bb = Y[(size_t)j * k + j + 1].re;
-                const ZD gb = cj(Y[(size_t)(j + 1) * k + j]);
+                const double bb = w.Y[(size_t)j * k + j + 1].re;
+                const ZD gb = cj(w.Y[(size_t)(j + 1) * k + j]);
                 coef.bbar_T[j + 2] = bb;
                 coef.gbar_T[j + 2] = gb;
                 coef.bbar_tot[j + 2] = bb;
@@ -359,8 +393,8 @@ __global__ __launch_bounds__(kDB) void k_dense_extract(Coef coef, int k, int gra
     if (threadIdx.x == 0 && grad) coef.misc[1] = coef.misc[0] * v[0];
 }
 
-void launch_dense_extract(Coef coef, int k, int grad, DenseWork w, hipStream_t st) {
-    hipLaunchKernelGGL(k_dense_extract, dim3(1), dim3(kDB), 0, st, coef, k, grad, w.X, w.Y);
+void launch_dense_extract(Coef coef, const SrcList& L, int grad, const DenseWork& w, hipStream_t st) {
+    hipLaunchKernelGGL(k_dense_extract, dim3(1, 1, L.n), dim3(kDB), 0, st, coef, L, grad, w);
 }
 
 }  // namespace tslov

@@ -240,6 +240,41 @@ void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, doubl
                        (R)std::exp(mu), (R)std::exp(-mu), g5_in, g5_out);
 }
 
+// =============================================================== batched sources
+// Grid dimension y (or z) runs over the entries of a SrcList; the entry's slot
+// selects its workspace and coefficients.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_sources_to_soa(const ZD* __restrict__ canon, int which, int g5, Work<R> wk,
+                                                           SrcList L, Geom g) {
+    const int e = blockIdx.y, slot = L.slot[e];
+    const ZD* in = canon + (size_t)L.src[e] * 12 * g.V;
+    Z<R>* out = wk.f(slot, which);
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double v[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
+    if (s < g.V) {
+        double n2 = 0.0;
+#pragma unroll
+        for (int p = 0; p < 12; ++p) {
+            const Z<R> zr = zcast<R>(((g5 && p >= 6) ? -1.0 : 1.0) * in[(size_t)s * 12 + p]);
+            out[(size_t)p * g.ldv + s] = zr;
+            n2 += (double)zr.re * zr.re + (double)zr.im * zr.im;
+        }
+        // |x|^2 laid out as (omega re, omega im, |r|^2, |s|^2) so that the first
+        // Lanczos step normalises with beta_1 = gamma_1 = |x|.
+        v[0] = n2;
+        v[2] = n2;
+        v[3] = n2;
+    }
+    if (which == 0) write_partials<kNvRecur, kBlock>(wk.p(slot, 1), v);
+}
+
+template <typename R>
+void launch_sources_to_soa(const ZD* canon, int which, int g5, const Work<R>& wk, const SrcList& L, const Geom& g,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_sources_to_soa<R>, dim3(grid_for(g.V), L.n), dim3(kBlock), 0, st, canon, which, g5, wk, L,
+                       g);
+}
+
 // =============================================================== forward Lanczos
 // Step j: normalise the previous residuals (v_j = r/beta_j, w_j = s/conj(gamma_j)),
 // apply a = H(mu) v_j and b = H(-mu) w_j = H^dag w_j with shared link loads, and
@@ -247,15 +282,16 @@ void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, doubl
 // j >= 2 the step first decides breakdown from the previous omega and norms.
 template <typename R>
 __global__ __launch_bounds__(kCBlock) void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
-                                                      const Z<R>* __restrict__ rin, const Z<R>* __restrict__ sin,
-                                                      const double* __restrict__ part_in, int npart_in, int first,
-                                                      Coef coef, int j, Z<R>* __restrict__ vout,
-                                                      Z<R>* __restrict__ wout, Z<R>* __restrict__ aout,
-                                                      Z<R>* __restrict__ bout, const Z<R>* __restrict__ eta,
-                                                      double* __restrict__ part_out) {
+                                                      Work<R> wk, SrcList L, Coef coef0, int j, int npart_in,
+                                                      int has_eta) {
+    const int slot = L.slot[blockIdx.y];
+    const Coef coef = coef0.at(slot);
     if (block_flag(coef.status)) return;
+    const int first = j == 1;
+    const Z<R>* rin = wk.f(slot, first ? 0 : 2);
+    const Z<R>* sin = wk.f(slot, first ? 0 : 3);
     double red[kNvRecur];
-    reduce_partials<kNvRecur, kCBlock>(part_in, npart_in, red);
+    reduce_partials<kNvRecur, kCBlock>(wk.p(slot, 1), npart_in, red);
     const ZD om = mk<double>(red[0], red[1]);
     const double rn2 = red[2], sn2 = red[3];
     const double aom = std::sqrt(norm2(om));
@@ -329,13 +365,13 @@ __global__ __launch_bounds__(kCBlock) void k_fwd_pair(const Z<R>* __restrict__ U
             pv[1] += wa.im;
             pv[2] += norm2(ad);
         }
-        store1(vout, g.ldv, a, s, v);
-        store1(wout, g.ldv, a, s, w);
-        store1(aout, g.ldv, a, s, av);
-        store1(bout, g.ldv, a, s, bv);
-        if (eta) {
+        store1(wk.v(slot, j), g.ldv, a, s, v);
+        store1(wk.w(slot, j), g.ldv, a, s, w);
+        store1(wk.a(slot, j), g.ldv, a, s, av);
+        store1(wk.b(slot, j), g.ldv, a, s, bv);
+        if (has_eta) {
             Z<R> e[4];
-            load1(e, eta, g.ldv, a, s);
+            load1(e, wk.f(slot, 1), g.ldv, a, s);
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp) {
                 const ZD ev = cjmul(zcast<double>(e[sp]), zcast<double>(v[sp]));
@@ -344,41 +380,45 @@ __global__ __launch_bounds__(kCBlock) void k_fwd_pair(const Z<R>* __restrict__ U
             }
         }
     }
-    write_partials<kNvPair, kCBlock>(part_out, pv);
+    write_partials<kNvPair, kCBlock>(wk.p(slot, 0), pv);
 }
 
 template <typename R>
-void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Z<R>* rin, const Z<R>* sin,
-                     const double* part_in, int npart_in, int first, Coef coef, int j, Z<R>* vout, Z<R>* wout,
-                     Z<R>* aout, Z<R>* bout, const Z<R>* eta, double* part_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_fwd_pair<R>, dim3(np_stencil(g.V)), dim3(kCBlock), 0, st, U, g, kappa, std::exp(mu), rin,
-                       sin, part_in, npart_in, first, coef, j, vout, wout, aout, bout, eta, part_out);
+void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+                     Coef coef, int j, int has_eta, hipStream_t st) {
+    const int npart_in = j == 1 ? grid_for(g.V) : np_point(g.V);
+    hipLaunchKernelGGL(k_fwd_pair<R>, dim3(np_stencil(g.V), L.n), dim3(kCBlock), 0, st, U, g, kappa, std::exp(mu),
+                       wk, L, coef, j, npart_in, has_eta);
 }
 
 // r = a - alpha_j v_j - gamma_j v_{j-1},  s = b - conj(alpha_j) w_j - beta_j w_{j-1},
 // with per-block partials of omega = s^H r, |r|^2, |s|^2.  One thread per
-// (plane, site): grid.y runs over the 12 spin-colour planes.
+// (plane, site): grid.y runs over the 12 spin-colour planes, grid.z over the
+// entries.  At the entry's last step (j = k[e]) only alpha_j is recorded.
 template <typename R>
-__global__ __launch_bounds__(kPBlock) void k_recur(Geom g, const Z<R>* __restrict__ a, const Z<R>* __restrict__ b,
-                                                   const Z<R>* __restrict__ v, const Z<R>* __restrict__ w,
-                                                   const Z<R>* __restrict__ vp, const Z<R>* __restrict__ wp,
-                                                   const double* __restrict__ part_in, int npart_in, Coef coef, int j,
-                                                   int last, Z<R>* __restrict__ rout, Z<R>* __restrict__ sout,
-                                                   double* __restrict__ part_out) {
+__global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L, Coef coef0, int j, int npart_in) {
+    const int e = blockIdx.z, slot = L.slot[e];
+    const Coef coef = coef0.at(slot);
     if (block_flag(coef.status)) return;
     double red[kNvPair];
-    reduce_partials<kNvPair, kPBlock>(part_in, npart_in, red);
+    reduce_partials<kNvPair, kPBlock>(wk.p(slot, 0), npart_in, red);
     const ZD alpha = mk<double>(red[0], red[1]);
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         coef.alpha[j] = alpha;
         coef.anorm2[j] = red[2];
         coef.h[j] = mk<double>(red[3], red[4]);
     }
-    if (last) return;
+    if (j >= L.k[e]) return;
     const Z<R> al = zcast<R>(alpha), alc = zcast<R>(cj(alpha));
     const bool has_prev = j > 1;
     const Z<R> gj = has_prev ? zcast<R>(coef.gamma[j]) : mk<R>(0, 0);
     const R bj = has_prev ? (R)coef.beta[j] : R(0);
+    const Z<R>* __restrict__ a = wk.a(slot, j);
+    const Z<R>* __restrict__ b = wk.b(slot, j);
+    const Z<R>* __restrict__ v = wk.v(slot, j);
+    const Z<R>* __restrict__ w = wk.w(slot, j);
+    Z<R>* __restrict__ rout = wk.f(slot, 2);
+    Z<R>* __restrict__ sout = wk.f(slot, 3);
     const int s = blockIdx.x * kPBlock + threadIdx.x;
     double pv[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
     if (s < g.V) {
@@ -386,8 +426,8 @@ __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, const Z<R>* __restric
         Z<R> r = a[i] - al * v[i];
         Z<R> q = b[i] - alc * w[i];
         if (has_prev) {
-            r = r - gj * vp[i];
-            q = q - bj * wp[i];
+            r = r - gj * wk.v(slot, j - 1)[i];
+            q = q - bj * wk.w(slot, j - 1)[i];
         }
         rout[i] = r;
         sout[i] = q;
@@ -397,25 +437,25 @@ __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, const Z<R>* __restric
         pv[2] = rr * rr + ri * ri;
         pv[3] = qr * qr + qi * qi;
     }
-    write_partials_at<kNvRecur, kPBlock>(part_out, blockIdx.y * gridDim.x + blockIdx.x, pv);
+    write_partials_at<kNvRecur, kPBlock>(wk.p(slot, 1), blockIdx.y * gridDim.x + blockIdx.x, pv);
 }
 
 template <typename R>
-void launch_recur(const Geom& g, const Z<R>* a, const Z<R>* b, const Z<R>* v, const Z<R>* w, const Z<R>* vp,
-                  const Z<R>* wp, const double* part_in, int npart_in, Coef coef, int j, int last, Z<R>* rout,
-                  Z<R>* sout, double* part_out, hipStream_t st) {
-    dim3 grid((g.V + kPBlock - 1) / kPBlock, 12);
-    hipLaunchKernelGGL(k_recur<R>, grid, dim3(kPBlock), 0, st, g, a, b, v, w, vp, wp, part_in, npart_in, coef, j,
-                       last, rout, sout, part_out);
+void launch_recur(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st) {
+    dim3 grid((g.V + kPBlock - 1) / kPBlock, 12, L.n);
+    hipLaunchKernelGGL(k_recur<R>, grid, dim3(kPBlock), 0, st, g, wk, L, coef, j, np_stencil(g.V));
 }
 
 // out(s) = [psi(s) +] g5^{overlap} |x| sum_{j <= k_used} c_j v_j(s), canonical layout.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_assemble(Geom g, const Z<R>* __restrict__ basis, size_t fstride,
-                                                     Coef coef, const ZD* __restrict__ psi, int overlap,
-                                                     ZD* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_assemble(Geom g, Work<R> wk, SrcList L, Coef coef0,
+                                                     const ZD* __restrict__ psi_base, int overlap,
+                                                     ZD* __restrict__ out_base) {
+    const int e = blockIdx.y, slot = L.slot[e];
+    const Coef coef = coef0.at(slot);
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= g.V) return;
+    const size_t co = (size_t)L.src[e] * 12 * g.V;
     const int k = coef.status[1];
     const double nx = coef.misc[0];
     ZD acc[12];
@@ -423,7 +463,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Geom g, const Z<R>* __restr
     for (int p = 0; p < 12; ++p) acc[p] = mk<double>(0, 0);
     for (int j = 1; j <= k; ++j) {
         const ZD c = coef.c[j];
-        const Z<R>* f = basis + (size_t)(j - 1) * fstride;
+        const Z<R>* f = wk.v(slot, j);
 #pragma unroll
         for (int p = 0; p < 12; ++p) acc[p] = acc[p] + c * zcast<double>(f[(size_t)p * g.ldv + s]);
     }
@@ -431,16 +471,16 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Geom g, const Z<R>* __restr
     for (int p = 0; p < 12; ++p) {
         const double sg = (overlap && p >= 6) ? -nx : nx;
         ZD o = sg * acc[p];
-        if (overlap) o = o + psi[(size_t)s * 12 + p];
-        out[(size_t)s * 12 + p] = o;
+        if (overlap) o = o + psi_base[co + (size_t)s * 12 + p];
+        out_base[co + (size_t)s * 12 + p] = o;
     }
 }
 
 template <typename R>
-void launch_assemble(const Geom& g, const Z<R>* basis, size_t field_stride, Coef coef, const ZD* psi_canon,
+void launch_assemble(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, const ZD* psi_canon,
                      int overlap, ZD* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_assemble<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, g, basis, field_stride, coef,
-                       psi_canon, overlap, out);
+    hipLaunchKernelGGL(k_assemble<R>, dim3(grid_for(g.V), L.n), dim3(kBlock), 0, st, g, wk, L, coef, psi_canon,
+                       overlap, out);
 }
 
 // =============================================================== backward (reverse mode)
@@ -451,15 +491,11 @@ void launch_assemble(const Geom& g, const Z<R>* basis, size_t field_stride, Coef
 //   sbar_j = wbar_{j+1}/gamma + conj(omegabar) beta v_{j+1},
 // and partials P1 = v_j^H rbar, P2 = sbar^H w_j, P3 = v_{j-1}^H rbar, P4 = w_{j-1}^H sbar.
 template <typename R>
-__global__ __launch_bounds__(kPBlock) void k_bwd_ra(Geom g, const Z<R>* __restrict__ vbar,
-                                                    const Z<R>* __restrict__ wbar, const Z<R>* __restrict__ vn,
-                                                    const Z<R>* __restrict__ wn, const Z<R>* __restrict__ vj,
-                                                    const Z<R>* __restrict__ wj, const Z<R>* __restrict__ vp,
-                                                    const Z<R>* __restrict__ wp, const double* __restrict__ part_in,
-                                                    int npart_in, Coef coef, int j, Z<R>* __restrict__ rbar,
-                                                    Z<R>* __restrict__ sbar, double* __restrict__ part_out) {
+__global__ __launch_bounds__(kPBlock) void k_bwd_ra(Geom g, Work<R> wk, SrcList L, Coef coef0, int j, int npart_in) {
+    const int e = blockIdx.z, slot = L.slot[e];
+    const Coef coef = coef0.at(slot);
     double red[kNvRB];
-    reduce_partials<kNvRB, kPBlock>(part_in, npart_in, red);
+    reduce_partials<kNvRB, kPBlock>(wk.p(slot, 0), npart_in, red);
     const double D1 = red[0];
     const ZD D2 = mk<double>(red[1], red[2]);
     const double beta = coef.beta[j + 1];
@@ -474,7 +510,15 @@ __global__ __launch_bounds__(kPBlock) void k_bwd_ra(Geom g, const Z<R>* __restri
     const Z<R> c2 = zcast<R>(mulcj(ombar, gam));                 // omegabar conj(gamma)
     const Z<R> c3 = zcast<R>(zdiv(mk<double>(1.0, 0.0), gam));   // 1/gamma
     const Z<R> c4 = zcast<R>(beta * cj(ombar));                  // conj(omegabar) beta
-    const bool has_prev = vp != nullptr;
+    const bool has_prev = j > 1;
+    const Z<R>* __restrict__ vbar = wk.f(slot, 4);
+    const Z<R>* __restrict__ wbar = wk.f(slot, 5);
+    const Z<R>* __restrict__ vn = wk.v(slot, j + 1);
+    const Z<R>* __restrict__ wn = wk.w(slot, j + 1);
+    const Z<R>* __restrict__ vj = wk.v(slot, j);
+    const Z<R>* __restrict__ wj = wk.w(slot, j);
+    Z<R>* __restrict__ rbar = wk.f(slot, 6 + (j & 1));
+    Z<R>* __restrict__ sbar = wk.sb(slot, j);
     const int s = blockIdx.x * kPBlock + threadIdx.x;
     double pv[kNvRA] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (s < g.V) {
@@ -489,23 +533,19 @@ __global__ __launch_bounds__(kPBlock) void k_bwd_ra(Geom g, const Z<R>* __restri
         pv[0] = p1.re; pv[1] = p1.im;
         pv[2] = p2.re; pv[3] = p2.im;
         if (has_prev) {
-            const ZD p3 = cjmul(zcast<double>(vp[i]), rd);
-            const ZD p4 = cjmul(zcast<double>(wp[i]), qd);
+            const ZD p3 = cjmul(zcast<double>(wk.v(slot, j - 1)[i]), rd);
+            const ZD p4 = cjmul(zcast<double>(wk.w(slot, j - 1)[i]), qd);
             pv[4] = p3.re; pv[5] = p3.im;
             pv[6] = p4.re; pv[7] = p4.im;
         }
     }
-    write_partials_at<kNvRA, kPBlock>(part_out, blockIdx.y * gridDim.x + blockIdx.x, pv);
+    write_partials_at<kNvRA, kPBlock>(wk.p(slot, 1), blockIdx.y * gridDim.x + blockIdx.x, pv);
 }
 
 template <typename R>
-void launch_bwd_ra(const Geom& g, const Z<R>* vbar, const Z<R>* wbar, const Z<R>* v_next, const Z<R>* w_next,
-                   const Z<R>* v_j, const Z<R>* w_j, const Z<R>* v_prev, const Z<R>* w_prev, const double* part_in,
-                   int npart_in, Coef coef, int j, Z<R>* rbar_out, Z<R>* sbar_out, double* part_out,
-                   hipStream_t st) {
-    dim3 grid((g.V + kPBlock - 1) / kPBlock, 12);
-    hipLaunchKernelGGL(k_bwd_ra<R>, grid, dim3(kPBlock), 0, st, g, vbar, wbar, v_next, w_next, v_j, w_j, v_prev,
-                       w_prev, part_in, npart_in, coef, j, rbar_out, sbar_out, part_out);
+void launch_bwd_ra(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st) {
+    dim3 grid((g.V + kPBlock - 1) / kPBlock, 12, L.n);
+    hipLaunchKernelGGL(k_bwd_ra<R>, grid, dim3(kPBlock), 0, st, g, wk, L, coef, j, np_stencil(g.V));
 }
 
 // Reverse of a_j = H v_j, b_j = H^dag w_j, alpha_j = w_j^H a_j and of the recurrence:
@@ -519,25 +559,25 @@ void launch_bwd_ra(const Geom& g, const Z<R>* vbar, const Z<R>* wbar, const Z<R>
 // wbar = conj(alphabar) a.
 template <typename R, bool LAST>
 __global__ __launch_bounds__(kCBlock) void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
-                                                    const double* __restrict__ part_in, int npart_in, Coef coef,
-                                                    int j, int k_used, const Z<R>* __restrict__ rbar_j,
-                                                    const Z<R>* __restrict__ rbar_n, const Z<R>* __restrict__ sbar_j,
-                                                    const Z<R>* __restrict__ sbar_n, const Z<R>* __restrict__ vj,
-                                                    const Z<R>* __restrict__ wj, const Z<R>* __restrict__ aj,
-                                                    const Z<R>* __restrict__ bj, const Z<R>* __restrict__ eta,
-                                                    Z<R>* __restrict__ vbar_out, Z<R>* __restrict__ wbar_out,
-                                                    Z<R>* __restrict__ abar_out, double* __restrict__ part_out) {
+                                                    Work<R> wk, SrcList L, Coef coef0, int j, int npart_in) {
+    const int e = blockIdx.y, slot = L.slot[e];
+    const Coef coef = coef0.at(slot);
+    const int k_used = L.k[e];
     ZD abar = coef.abar_T[j];
     if (!LAST) {
         double red[kNvRA];
-        reduce_partials<kNvRA, kCBlock>(part_in, npart_in, red);
+        reduce_partials<kNvRA, kCBlock>(wk.p(slot, 1), npart_in, red);
         abar = abar - mk<double>(red[0], red[1]) - mk<double>(red[2], red[3]);
         if (blockIdx.x == 0 && threadIdx.x == 0 && j >= 2) {
             coef.gbar_tot[j] = coef.gbar_T[j] - mk<double>(red[4], red[5]);
             coef.bbar_tot[j] = coef.bbar_T[j] - red[6];
         }
     }
+    const Z<R>* __restrict__ rbar_j = wk.f(slot, 6 + (j & 1));
+    const Z<R>* __restrict__ rbar_n = wk.f(slot, 6 + ((j + 1) & 1));
+    const Z<R>* __restrict__ sbar_j = wk.sb(slot, j);
     const bool carry = j + 1 < k_used;
+    const Z<R>* __restrict__ sbar_n = carry ? wk.sb(slot, j + 1) : sbar_j;
     const Z<R> ca = zcast<R>(abar);
     const ZD alpha = coef.alpha[j];
     const Z<R> alr = zcast<R>(alpha), alc = zcast<R>(cj(alpha)), abc = zcast<R>(cj(abar));
@@ -567,8 +607,9 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb(const Z<R>* __restrict__ U, 
             mem_fence_compiler();
         }
         const R kap = (R)kappa;
-        const rsrc_t rw = make_rsrc(wj, 12, g.ldv), rv = make_rsrc(vj, 12, g.ldv), ra = make_rsrc(aj, 12, g.ldv),
-                     rb = make_rsrc(bj, 12, g.ldv), re = make_rsrc(eta, 12, g.ldv);
+        const rsrc_t rw = make_rsrc(wk.w(slot, j), 12, g.ldv), rv = make_rsrc(wk.v(slot, j), 12, g.ldv),
+                     ra = make_rsrc(wk.a(slot, j), 12, g.ldv), rb = make_rsrc(wk.b(slot, j), 12, g.ldv),
+                     re = make_rsrc(wk.f(slot, 1), 12, g.ldv);
         Z<R> vbo[4], wbo[4], abo[4];
         double d1 = 0.0, d2r = 0.0, d2i = 0.0;
 #pragma unroll
@@ -603,30 +644,26 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb(const Z<R>* __restrict__ U, 
             d2r += x2.re;
             d2i += x2.im;
         }
-        store1(vbar_out, g.ldv, a, s, vbo);
-        store1(wbar_out, g.ldv, a, s, wbo);
-        store1(abar_out, g.ldv, a, s, abo);
+        store1(wk.f(slot, 4), g.ldv, a, s, vbo);
+        store1(wk.f(slot, 5), g.ldv, a, s, wbo);
+        store1(wk.ab(slot, j), g.ldv, a, s, abo);
         pv[0] = d1;
         pv[1] = d2r;
         pv[2] = d2i;
     }
-    write_partials<kNvRB, kCBlock>(part_out, pv);
+    write_partials<kNvRB, kCBlock>(wk.p(slot, 0), pv);
 }
 
 template <typename R>
-void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const double* part_in, int npart_in,
-                   Coef coef, int j, int k_used, const Z<R>* rbar_j, const Z<R>* rbar_next, const Z<R>* sbar_j,
-                   const Z<R>* sbar_next, const Z<R>* v_j, const Z<R>* w_j, const Z<R>* a_j, const Z<R>* b_j,
-                   const Z<R>* eta, Z<R>* vbar_out, Z<R>* wbar_out, Z<R>* abar_out, double* part_out,
-                   hipStream_t st) {
-    if (j == k_used)
-        hipLaunchKernelGGL((k_bwd_rb<R, true>), dim3(np_stencil(g.V)), dim3(kCBlock), 0, st, U, g, kappa,
-                           std::exp(mu), part_in, npart_in, coef, j, k_used, rbar_j, rbar_next, sbar_j, sbar_next,
-                           v_j, w_j, a_j, b_j, eta, vbar_out, wbar_out, abar_out, part_out);
+void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+                   Coef coef, int j, int last, hipStream_t st) {
+    const dim3 grid(np_stencil(g.V), L.n);
+    if (last)
+        hipLaunchKernelGGL((k_bwd_rb<R, true>), grid, dim3(kCBlock), 0, st, U, g, kappa, std::exp(mu), wk, L, coef,
+                           j, np_point(g.V));
     else
-        hipLaunchKernelGGL((k_bwd_rb<R, false>), dim3(np_stencil(g.V)), dim3(kCBlock), 0, st, U, g, kappa,
-                           std::exp(mu), part_in, npart_in, coef, j, k_used, rbar_j, rbar_next, sbar_j, sbar_next,
-                           v_j, w_j, a_j, b_j, eta, vbar_out, wbar_out, abar_out, part_out);
+        hipLaunchKernelGGL((k_bwd_rb<R, false>), grid, dim3(kCBlock), 0, st, U, g, kappa, std::exp(mu), wk, L, coef,
+                           j, np_point(g.V));
 }
 
 // =============================================================== force contraction
@@ -661,9 +698,8 @@ __device__ __forceinline__ void force_pair(ZD (&G)[3][3], const Spinor<R>& p_x, 
 }
 
 template <int NU, typename R>
-__device__ void force_body(const Geom& g, double kappa, double emu, const Z<R>* __restrict__ abar,
-                           const Z<R>* __restrict__ sbar, const Z<R>* __restrict__ vb, const Z<R>* __restrict__ wb,
-                           size_t fs, int k, int j0, int j1, int s, ZD* __restrict__ gout) {
+__device__ void force_body(const Geom& g, double kappa, double emu, const Work<R>& wk, int slot, int k, int j0,
+                           int j1, int s, ZD* __restrict__ gout) {
     const Nbr n = neighbours(g, s);
     const int y = n.fwd[NU];
     const double ef = (NU == 3) ? emu : 1.0, eb = (NU == 3) ? 1.0 / emu : 1.0;
@@ -673,18 +709,17 @@ __device__ void force_body(const Geom& g, double kappa, double emu, const Z<R>* 
 #pragma unroll
         for (int b = 0; b < 3; ++b) G[a][b] = mk<double>(0, 0);
     for (int j = j0; j < j1; ++j) {
-        const size_t o = (size_t)(j - 1) * fs;
         Spinor<R> px, qx, py, qy;
-        load_spinor(px, abar + o, g.ldv, s);
-        load_spinor(qx, vb + o, g.ldv, s);
-        load_spinor(py, abar + o, g.ldv, y);
-        load_spinor(qy, vb + o, g.ldv, y);
+        load_spinor(px, wk.ab(slot, j), g.ldv, s);
+        load_spinor(qx, wk.v(slot, j), g.ldv, s);
+        load_spinor(py, wk.ab(slot, j), g.ldv, y);
+        load_spinor(qy, wk.v(slot, j), g.ldv, y);
         force_pair<NU>(G, px, qx, py, qy, ef, eb);
         if (j < k) {
-            load_spinor(px, wb + o, g.ldv, s);
-            load_spinor(qx, sbar + o, g.ldv, s);
-            load_spinor(py, wb + o, g.ldv, y);
-            load_spinor(qy, sbar + o, g.ldv, y);
+            load_spinor(px, wk.w(slot, j), g.ldv, s);
+            load_spinor(qx, wk.sb(slot, j), g.ldv, s);
+            load_spinor(py, wk.w(slot, j), g.ldv, y);
+            load_spinor(qy, wk.sb(slot, j), g.ldv, y);
             force_pair<NU>(G, px, qx, py, qy, ef, eb);
         }
     }
@@ -695,60 +730,200 @@ __device__ void force_body(const Geom& g, double kappa, double emu, const Z<R>* 
 }
 
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_force(Geom g, double kappa, double emu, const Z<R>* __restrict__ abar,
-                                                  const Z<R>* __restrict__ sbar, const Z<R>* __restrict__ vb,
-                                                  const Z<R>* __restrict__ wb, size_t fs, const int* __restrict__ status,
-                                                  int nchunk, ZD* __restrict__ gpart) {
+__global__ __launch_bounds__(kBlock) void k_force(Geom g, double kappa, double emu, Work<R> wk, SrcList L, int nchunk,
+                                                  ZD* __restrict__ gpart) {
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= g.V) return;
-    const int k = status[1];
+    const int e = blockIdx.z >> 2, nu = blockIdx.z & 3, slot = L.slot[e];
+    const int k = L.k[e];
     const int chunk = blockIdx.y;
     const int j0 = 1 + (int)((long long)k * chunk / nchunk);
     const int j1 = 1 + (int)((long long)k * (chunk + 1) / nchunk);
-    ZD* out = gpart + (size_t)chunk * 36 * g.ldv;
-    switch (blockIdx.z) {
-        case 0: force_body<0>(g, kappa, emu, abar, sbar, vb, wb, fs, k, j0, j1, s, out); break;
-        case 1: force_body<1>(g, kappa, emu, abar, sbar, vb, wb, fs, k, j0, j1, s, out); break;
-        case 2: force_body<2>(g, kappa, emu, abar, sbar, vb, wb, fs, k, j0, j1, s, out); break;
-        default: force_body<3>(g, kappa, emu, abar, sbar, vb, wb, fs, k, j0, j1, s, out); break;
+    ZD* out = gpart + ((size_t)slot * nchunk + chunk) * 36 * g.ldv;
+    switch (nu) {
+        case 0: force_body<0>(g, kappa, emu, wk, slot, k, j0, j1, s, out); break;
+        case 1: force_body<1>(g, kappa, emu, wk, slot, k, j0, j1, s, out); break;
+        case 2: force_body<2>(g, kappa, emu, wk, slot, k, j0, j1, s, out); break;
+        default: force_body<3>(g, kappa, emu, wk, slot, k, j0, j1, s, out); break;
     }
 }
 
 template <typename R>
-void launch_force(const Geom& g, double kappa, double mu, const Z<R>* abar, const Z<R>* sbar, const Z<R>* vb,
-                  const Z<R>* wb, size_t field_stride, const int* status, int nchunk, ZD* gpart, hipStream_t st) {
-    dim3 grid(grid_for(g.V), nchunk, 4);
-    hipLaunchKernelGGL(k_force<R>, grid, dim3(kBlock), 0, st, g, kappa, std::exp(mu), abar, sbar, vb, wb,
-                       field_stride, status, nchunk, gpart);
+void launch_force(const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L, int nchunk, ZD* gpart,
+                  hipStream_t st) {
+    dim3 grid(grid_for(g.V), nchunk, 4 * L.n);
+    hipLaunchKernelGGL(k_force<R>, grid, dim3(kBlock), 0, st, g, kappa, std::exp(mu), wk, L, nchunk, gpart);
 }
 
-__global__ __launch_bounds__(kBlock) void k_force_reduce(Geom g, const ZD* __restrict__ gpart, int nchunk,
-                                                         int antiperiodic, ZD* __restrict__ out) {
+__device__ __forceinline__ double boundary_sign(const Geom& g, int nu, int s, int antiperiodic) {
+    return (nu == 3 && antiperiodic && s / (g.nx * g.ny * g.nz) == g.nt - 1) ? -1.0 : 1.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_force_reduce(Geom g, const ZD* __restrict__ gpart, int nchunk, SrcList L,
+                                                         int antiperiodic, ZD* __restrict__ dU) {
     const int s = blockIdx.x * kBlock + threadIdx.x;
-    const int nu = blockIdx.y;
+    const int nu = blockIdx.y, e = blockIdx.z, slot = L.slot[e];
     if (s >= g.V) return;
     // gradient with respect to the caller's link: undo the folded boundary sign
-    double sign = 1.0;
-    if (nu == 3 && antiperiodic && s / (g.nx * g.ny * g.nz) == g.nt - 1) sign = -1.0;
+    const double sign = boundary_sign(g, nu, s, antiperiodic);
+    const ZD* gp = gpart + (size_t)slot * nchunk * 36 * g.ldv;
+    ZD* out = dU + (size_t)L.src[e] * 36 * g.V;
 #pragma unroll
     for (int ab = 0; ab < 9; ++ab) {
         ZD acc = mk<double>(0, 0);
-        for (int c = 0; c < nchunk; ++c) acc = acc + gpart[(size_t)c * 36 * g.ldv + (size_t)(nu * 9 + ab) * g.ldv + s];
+        for (int c = 0; c < nchunk; ++c) acc = acc + gp[(size_t)c * 36 * g.ldv + (size_t)(nu * 9 + ab) * g.ldv + s];
         out[((size_t)nu * g.V + s) * 9 + ab] = sign * acc;
     }
 }
 
-void launch_force_reduce(const Geom& g, const ZD* gpart, int nchunk, int antiperiodic, ZD* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_force_reduce, dim3(grid_for(g.V), 4), dim3(kBlock), 0, st, g, gpart, nchunk, antiperiodic,
-                       out);
+void launch_force_reduce(const Geom& g, const ZD* gpart, int nchunk, const SrcList& L, int antiperiodic, ZD* dU,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_force_reduce, dim3(grid_for(g.V), 4, L.n), dim3(kBlock), 0, st, g, gpart, nchunk, L,
+                       antiperiodic, dU);
+}
+
+// U(1) projection of the link gradient: with G the gradient for the caller's link
+// U_c = sign U (sign the folded boundary factor), -Im tr(G^H U_c) = -Im tr(acc^H U)
+// for the unsigned accumulator acc and the stored (signed) link U.
+__global__ __launch_bounds__(kBlock) void k_force_current(Geom g, const ZD* __restrict__ gpart, int nchunk, SrcList L,
+                                                          const ZD* __restrict__ U, double* __restrict__ gsrc,
+                                                          double* __restrict__ jsum, int accumulate) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const int nu = blockIdx.y;
+    if (s >= g.V) return;
+    ZD u[9];
+#pragma unroll
+    for (int ab = 0; ab < 9; ++ab) u[ab] = U[(size_t)(nu * 9 + ab) * g.ldv + s];
+    double tot = accumulate ? jsum[(size_t)nu * g.V + s] : 0.0;
+    for (int e = 0; e < L.n; ++e) {
+        const int slot = L.slot[e];
+        const ZD* gp = gpart + (size_t)slot * nchunk * 36 * g.ldv;
+        double im = 0.0;
+#pragma unroll
+        for (int ab = 0; ab < 9; ++ab) {
+            ZD acc = mk<double>(0, 0);
+            for (int c = 0; c < nchunk; ++c) acc = acc + gp[(size_t)c * 36 * g.ldv + (size_t)(nu * 9 + ab) * g.ldv + s];
+            im += cjmul(acc, u[ab]).im;
+        }
+        if (gsrc) gsrc[((size_t)slot * 4 + nu) * g.ldv + s] = -im;
+        tot += -im;
+    }
+    jsum[(size_t)nu * g.V + s] = tot;
+}
+
+void launch_force_current(const Geom& g, const ZD* gpart, int nchunk, const SrcList& L, const ZD* U64,
+                          double* gsrc, double* jsum, int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_force_current, dim3(grid_for(g.V), 4), dim3(kBlock), 0, st, g, gpart, nchunk, L, U64, gsrc,
+                       jsum, accumulate);
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero(double* __restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) p[i] = 0.0;
+}
+
+void launch_zero(double* p, size_t n, hipStream_t st) {
+    if (n == 0) return;
+    size_t nb = (n + kBlock - 1) / kBlock;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)nb), dim3(kBlock), 0, st, p, n);
+}
+
+// =============================================================== current estimator
+__global__ __launch_bounds__(kBlock) void k_current_div(Geom g, const double* __restrict__ j, double scale,
+                                                        double* __restrict__ div, double* __restrict__ tot) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const Nbr n = neighbours(g, s);
+    double d = 0.0, t = 0.0;
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        const double out = j[(size_t)nu * g.V + s], in = j[(size_t)nu * g.V + n.bwd[nu]];
+        d += out - in;
+        t += out + in;
+    }
+    if (div) div[s] = scale * d;
+    if (tot) tot[s] = scale * t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale(double* __restrict__ p, size_t n, double scale) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] *= scale;
+}
+
+void launch_current_finish(const Geom& g, double* j, double scale, double* div, double* tot, hipStream_t st) {
+    if (div || tot)
+        hipLaunchKernelGGL(k_current_div, dim3(grid_for(g.V)), dim3(kBlock), 0, st, g, j, scale, div, tot);
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(4 * g.V)), dim3(kBlock), 0, st, j, (size_t)4 * g.V, scale);
+}
+
+// Ward identity of the local U(1) symmetry (phase rotation of U_nu(x) for all
+// outgoing links, of U_nu(x - nu) for all incoming ones and of psi(x), eta(x)),
+// per entry, for eta = g5 psi: the link derivatives' divergence equals the
+// source terms.  psi is indexed by the entry's source, y and dpsi by the entry.
+__global__ __launch_bounds__(kBlock) void k_ward(Geom g, const double* __restrict__ gsrc, SrcList L,
+                                                 const ZD* __restrict__ psi, const ZD* __restrict__ y,
+                                                 const ZD* __restrict__ dpsi, double* __restrict__ part) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const int e = blockIdx.y, slot = L.slot[e];
+    double mx[2] = {0.0, 0.0};
+    if (s < g.V) {
+        const Nbr n = neighbours(g, s);
+        const double* gs = gsrc + (size_t)slot * 4 * g.ldv;
+        double lhs = 0.0;
+#pragma unroll
+        for (int nu = 0; nu < 4; ++nu) {
+            const double o = gs[(size_t)nu * g.ldv + s], i = gs[(size_t)nu * g.ldv + n.bwd[nu]];
+            lhs += o - i;
+            mx[1] = fmax(mx[1], fabs(o));
+        }
+        const size_t co = (size_t)L.src[e] * 12 * g.V + (size_t)s * 12;
+        const size_t cy = (size_t)e * 12 * g.V + (size_t)s * 12;
+        double rhs = 0.0;
+#pragma unroll
+        for (int p = 0; p < 12; ++p) {   // eta = g5 psi
+            const double g5 = p < 6 ? 1.0 : -1.0;
+            rhs -= g5 * cjmul(psi[co + p], y[cy + p]).im;
+            rhs += cjmul(dpsi[cy + p], psi[co + p]).im;
+        }
+        mx[0] = fabs(lhs - rhs);
+    }
+    // block maxima (wave shuffle tree, then waves in order)
+    __shared__ double red[kBlock / kWave][2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) mx[q] = fmax(mx[q], __shfl_down(mx[q], off, kWave));
+    if (threadIdx.x % kWave == 0) {
+        red[threadIdx.x / kWave][0] = mx[0];
+        red[threadIdx.x / kWave][1] = mx[1];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            a = fmax(a, red[w][0]);
+            b = fmax(b, red[w][1]);
+        }
+        part[((size_t)e * gridDim.x + blockIdx.x) * 2] = a;
+        part[((size_t)e * gridDim.x + blockIdx.x) * 2 + 1] = b;
+    }
+}
+
+int launch_ward(const Geom& g, const double* gsrc, const SrcList& L, const ZD* psi, const ZD* y, const ZD* dpsi,
+                double* part, hipStream_t st) {
+    const int nb = grid_for(g.V);
+    hipLaunchKernelGGL(k_ward, dim3(nb, L.n), dim3(kBlock), 0, st, g, gsrc, L, psi, y, dpsi, part);
+    return nb;
 }
 
 // =============================================================== source gradient
 // x = |x| v_1 with v_1 = w_1 = x/|x|:  xbar = u/|x| + [S/|x| - Re(u^H x)/|x|^2] x/|x|, u = vbar_1 + wbar_1.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_sgrad_dot(Geom g, const Z<R>* __restrict__ vbar,
-                                                      const Z<R>* __restrict__ wbar, const Z<R>* __restrict__ x,
-                                                      double* __restrict__ part) {
+__global__ __launch_bounds__(kBlock) void k_sgrad_dot(Geom g, Work<R> wk, SrcList L) {
+    const int slot = L.slot[blockIdx.y];
+    const Z<R>* __restrict__ vbar = wk.f(slot, 4);
+    const Z<R>* __restrict__ wbar = wk.f(slot, 5);
+    const Z<R>* __restrict__ x = wk.f(slot, 0);
     const int s = blockIdx.x * kBlock + threadIdx.x;
     double v[1] = {0.0};
     if (s < g.V) {
@@ -759,20 +934,24 @@ __global__ __launch_bounds__(kBlock) void k_sgrad_dot(Geom g, const Z<R>* __rest
             v[0] += cjmul(u, zcast<double>(x[i])).re;
         }
     }
-    write_partials<1, kBlock>(part, v);
+    write_partials<1, kBlock>(wk.p(slot, 2), v);
 }
 
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_sgrad_out(Geom g, const Z<R>* __restrict__ vbar,
-                                                      const Z<R>* __restrict__ wbar, const Z<R>* __restrict__ x,
-                                                      const double* __restrict__ part, int npart, Coef coef,
-                                                      ZD* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_sgrad_out(Geom g, Work<R> wk, SrcList L, Coef coef0, int npart,
+                                                      ZD* __restrict__ out_base) {
+    const int e = blockIdx.y, slot = L.slot[e];
+    const Coef coef = coef0.at(slot);
     double red[1];
-    reduce_partials<1, kBlock>(part, npart, red);
+    reduce_partials<1, kBlock>(wk.p(slot, 2), npart, red);
     const double nx = coef.misc[0], S = coef.misc[1];
     const double c2 = (S / nx - red[0] / (nx * nx)) / nx;
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= g.V) return;
+    const Z<R>* __restrict__ vbar = wk.f(slot, 4);
+    const Z<R>* __restrict__ wbar = wk.f(slot, 5);
+    const Z<R>* __restrict__ x = wk.f(slot, 0);
+    ZD* out = out_base + (size_t)L.src[e] * 12 * g.V;
 #pragma unroll
     for (int p = 0; p < 12; ++p) {
         const size_t i = (size_t)p * g.ldv + s;
@@ -782,11 +961,10 @@ __global__ __launch_bounds__(kBlock) void k_sgrad_out(Geom g, const Z<R>* __rest
 }
 
 template <typename R>
-void launch_source_grad(const Geom& g, const Z<R>* vbar, const Z<R>* wbar, const Z<R>* x, Coef coef, double* part,
-                        ZD* out, hipStream_t st) {
+void launch_source_grad(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, ZD* dpsi, hipStream_t st) {
     const int nb = grid_for(g.V);
-    hipLaunchKernelGGL(k_sgrad_dot<R>, dim3(nb), dim3(kBlock), 0, st, g, vbar, wbar, x, part);
-    hipLaunchKernelGGL(k_sgrad_out<R>, dim3(nb), dim3(kBlock), 0, st, g, vbar, wbar, x, part, nb, coef, out);
+    hipLaunchKernelGGL(k_sgrad_dot<R>, dim3(nb, L.n), dim3(kBlock), 0, st, g, wk, L);
+    hipLaunchKernelGGL(k_sgrad_out<R>, dim3(nb, L.n), dim3(kBlock), 0, st, g, wk, L, coef, nb, dpsi);
 }
 
 // =============================================================== instantiations
@@ -795,24 +973,19 @@ void launch_source_grad(const Geom& g, const Z<R>* vbar, const Z<R>* wbar, const
     template void launch_spinor_from_soa<R>(const Z<R>*, ZD*, const Geom&, hipStream_t);                        \
     template void launch_apply<R>(const Z<R>*, const Z<R>*, Z<R>*, const Geom&, double, double, int, int,       \
                                   hipStream_t);                                                                 \
-    template void launch_fwd_pair<R>(const Z<R>*, const Geom&, double, double, const Z<R>*, const Z<R>*,        \
-                                     const double*, int, int, Coef, int, Z<R>*, Z<R>*, Z<R>*, Z<R>*,            \
-                                     const Z<R>*, double*, hipStream_t);                                        \
-    template void launch_recur<R>(const Geom&, const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, \
-                                  const Z<R>*, const double*, int, Coef, int, int, Z<R>*, Z<R>*, double*,       \
+    template void launch_sources_to_soa<R>(const ZD*, int, int, const Work<R>&, const SrcList&, const Geom&,    \
+                                           hipStream_t);                                                        \
+    template void launch_fwd_pair<R>(const Z<R>*, const Geom&, double, double, const Work<R>&, const SrcList&,  \
+                                     Coef, int, int, hipStream_t);                                              \
+    template void launch_recur<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);         \
+    template void launch_assemble<R>(const Geom&, const Work<R>&, const SrcList&, Coef, const ZD*, int, ZD*,    \
+                                     hipStream_t);                                                              \
+    template void launch_bwd_ra<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);        \
+    template void launch_bwd_rb<R>(const Z<R>*, const Geom&, double, double, const Work<R>&, const SrcList&,    \
+                                   Coef, int, int, hipStream_t);                                                \
+    template void launch_force<R>(const Geom&, double, double, const Work<R>&, const SrcList&, int, ZD*,        \
                                   hipStream_t);                                                                 \
-    template void launch_assemble<R>(const Geom&, const Z<R>*, size_t, Coef, const ZD*, int, ZD*, hipStream_t); \
-    template void launch_bwd_ra<R>(const Geom&, const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*,             \
-                                   const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, const double*, int, Coef, \
-                                   int, Z<R>*, Z<R>*, double*, hipStream_t);                                    \
-    template void launch_bwd_rb<R>(const Z<R>*, const Geom&, double, double, const double*, int, Coef, int, int, \
-                                   const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, const Z<R>*, \
-                                   const Z<R>*, const Z<R>*, const Z<R>*, Z<R>*, Z<R>*, Z<R>*, double*,         \
-                                   hipStream_t);                                                                \
-    template void launch_force<R>(const Geom&, double, double, const Z<R>*, const Z<R>*, const Z<R>*,           \
-                                  const Z<R>*, size_t, const int*, int, ZD*, hipStream_t);                      \
-    template void launch_source_grad<R>(const Geom&, const Z<R>*, const Z<R>*, const Z<R>*, Coef, double*, ZD*, \
-                                        hipStream_t);
+    template void launch_source_grad<R>(const Geom&, const Work<R>&, const SrcList&, Coef, ZD*, hipStream_t);
 
 TSLOV_INST(double)
 TSLOV_INST(float)

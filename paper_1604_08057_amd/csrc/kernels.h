@@ -22,48 +22,97 @@ template <typename R>
 void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu,
                   int g5_in, int g5_out, hipStream_t st);
 
+// ---------------------------------------------------------------- batch workspace
+// Per-source lattice fields of a batch in the working precision.  Sources sit in
+// batch slots; every per-step array holds kcap fields per slot (step j at j - 1).
+constexpr int kNF = 8;   // per-slot fields: 0 psi, 1 eta, 2 r, 3 s, 4 vbar, 5 wbar, 6/7 rbar ring
+constexpr int kNP = 4;   // per-slot partial-sum arrays
+
+template <typename R>
+struct Work {
+    Z<R>* V;    // v_j
+    Z<R>* W;    // w_j
+    Z<R>* A;    // a_j = H v_j
+    Z<R>* B;    // b_j = H^dag w_j
+    Z<R>* AB;   // abar_j (reverse pass)
+    Z<R>* SB;   // sbar_j (reverse pass)
+    Z<R>* F;    // [slot][kNF] fields
+    double* part;  // [slot][kNP][pstride]
+    size_t fe;     // complex elements per field (12 ldv)
+    int kcap;
+    int pstride;
+    __host__ __device__ size_t step(int slot, int j) const { return ((size_t)slot * kcap + (j - 1)) * fe; }
+    __host__ __device__ Z<R>* v(int slot, int j) const { return V + step(slot, j); }
+    __host__ __device__ Z<R>* w(int slot, int j) const { return W + step(slot, j); }
+    __host__ __device__ Z<R>* a(int slot, int j) const { return A + step(slot, j); }
+    __host__ __device__ Z<R>* b(int slot, int j) const { return B + step(slot, j); }
+    __host__ __device__ Z<R>* ab(int slot, int j) const { return AB + step(slot, j); }
+    __host__ __device__ Z<R>* sb(int slot, int j) const { return SB + step(slot, j); }
+    __host__ __device__ Z<R>* f(int slot, int i) const { return F + ((size_t)slot * kNF + i) * fe; }
+    __host__ __device__ double* p(int slot, int i) const { return part + ((size_t)slot * kNP + i) * pstride; }
+};
+
 // ---------------------------------------------------------------- forward Lanczos
 // Partials: forward pair writes 5 doubles per block (alpha re/im, |a|^2, h re/im);
 // recurrence writes 4 (omega re/im, |r|^2, |s|^2).
 constexpr int kNvPair = 5;
 constexpr int kNvRecur = 4;
 
+// Batched canonical -> SoA copy of field `which` (0 psi, 1 eta), times g5 if g5 = 1,
+// for every list entry (source src[e] of the canonical array); for psi also the
+// |x|^2 partials.
 template <typename R>
-void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Z<R>* rin,
-                     const Z<R>* sin, const double* part_in, int npart_in, int first, Coef coef, int j,
-                     Z<R>* vout, Z<R>* wout, Z<R>* aout, Z<R>* bout, const Z<R>* eta, double* part_out,
-                     hipStream_t st);
+void launch_sources_to_soa(const ZD* canon, int which, int g5, const Work<R>& wk, const SrcList& L, const Geom& g,
+                           hipStream_t st);
+// Step j of the Lanczos process for every list entry (k[e] = the entry's target size).
 template <typename R>
-void launch_recur(const Geom& g, const Z<R>* a, const Z<R>* b, const Z<R>* v, const Z<R>* w, const Z<R>* vp,
-                  const Z<R>* wp, const double* part_in, int npart_in, Coef coef, int j, int last,
-                  Z<R>* rout, Z<R>* sout, double* part_out, hipStream_t st);
-// out (canonical) = [psi +] g5^{overlap} |x| sum_j c_j v_j
+void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+                     Coef coef, int j, int has_eta, hipStream_t st);
 template <typename R>
-void launch_assemble(const Geom& g, const Z<R>* basis, size_t field_stride, Coef coef, const ZD* psi_canon,
+void launch_recur(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st);
+// out[src] (canonical) = [psi[src] +] g5^{overlap} |x| sum_j c_j v_j
+template <typename R>
+void launch_assemble(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, const ZD* psi_canon,
                      int overlap, ZD* out, hipStream_t st);
 
 // ---------------------------------------------------------------- backward
 constexpr int kNvRA = 8;   // P1..P4 complex
 constexpr int kNvRB = 3;   // Re(vbar^H v), (wbar^H w) re/im
 
+// Reverse step j: k[e] = k_used of the entry.  bwd_ra for entries with j < k_used,
+// bwd_rb for entries with j <= k_used (last = 1: j == k_used for every entry).
 template <typename R>
-void launch_bwd_ra(const Geom& g, const Z<R>* vbar, const Z<R>* wbar, const Z<R>* v_next, const Z<R>* w_next,
-                   const Z<R>* v_j, const Z<R>* w_j, const Z<R>* v_prev, const Z<R>* w_prev,
-                   const double* part_in, int npart_in, Coef coef, int j, Z<R>* rbar_out, Z<R>* sbar_out,
-                   double* part_out, hipStream_t st);
+void launch_bwd_ra(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st);
 template <typename R>
-void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const double* part_in, int npart_in,
-                   Coef coef, int j, int k_used, const Z<R>* rbar_j, const Z<R>* rbar_next,
-                   const Z<R>* sbar_j, const Z<R>* sbar_next, const Z<R>* v_j, const Z<R>* w_j,
-                   const Z<R>* a_j, const Z<R>* b_j, const Z<R>* eta, Z<R>* vbar_out, Z<R>* wbar_out,
-                   Z<R>* abar_out, double* part_out, hipStream_t st);
+void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+                   Coef coef, int j, int last, hipStream_t st);
+// Per-link force partials gpart[slot][chunk][36 planes] over all steps of each entry.
 template <typename R>
-void launch_force(const Geom& g, double kappa, double mu, const Z<R>* abar, const Z<R>* sbar, const Z<R>* vb,
-                  const Z<R>* wb, size_t field_stride, const int* status, int nchunk, ZD* gpart, hipStream_t st);
-void launch_force_reduce(const Geom& g, const ZD* gpart, int nchunk, int antiperiodic, ZD* out, hipStream_t st);
+void launch_force(const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L, int nchunk, ZD* gpart,
+                  hipStream_t st);
+// dU[src] (canonical) from the chunk partials, boundary sign undone.
+void launch_force_reduce(const Geom& g, const ZD* gpart, int nchunk, const SrcList& L, int antiperiodic, ZD* dU,
+                         hipStream_t st);
+// U(1) projections g_e(x, nu) = -Im tr(G^H U) of every entry, into gsrc[slot][4][ldv]
+// (nullable) and, summed over the entries in list order, into jsum[nu][V]
+// (accumulate = 1: added to its contents).
+void launch_force_current(const Geom& g, const ZD* gpart, int nchunk, const SrcList& L, const ZD* U64,
+                          double* gsrc, double* jsum, int accumulate, hipStream_t st);
 template <typename R>
-void launch_source_grad(const Geom& g, const Z<R>* vbar, const Z<R>* wbar, const Z<R>* x, Coef coef,
-                        double* part, ZD* out, hipStream_t st);
+void launch_source_grad(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, ZD* dpsi, hipStream_t st);
+// Fill n doubles with zero (kernel, not a memset node).
+void launch_zero(double* p, size_t n, hipStream_t st);
+
+// ---------------------------------------------------------------- current estimator
+// div(x) = scale sum_nu [j_nu(x) - j_nu(x - nu)], tot(x) = scale sum_nu [j_nu(x) + j_nu(x - nu)]
+// (either nullable), then j <- scale j.
+void launch_current_finish(const Geom& g, double* j, double scale, double* div, double* tot, hipStream_t st);
+// Per-entry Ward residuals of the local U(1) symmetry for eta = g5 psi, block
+// maxima in part[e][block][2]: max |lhs - rhs| and max |g|, where
+// lhs(x) = sum_nu [g(x, nu) - g(x - nu, nu)], rhs(x) = -Im eta^H y (x) + Im dpsi^H psi (x).
+// psi is indexed by src[e], y and dpsi by e.  Returns the number of blocks.
+int launch_ward(const Geom& g, const double* gsrc, const SrcList& L, const ZD* psi, const ZD* y, const ZD* dpsi,
+                double* part, hipStream_t st);
 
 // ---------------------------------------------------------------- deflation / error estimate
 void launch_defl_coeffs(const ZD* L, const ZD* psi, int V, int l, double* part, ZD* c, hipStream_t st);
@@ -74,23 +123,39 @@ int launch_diff_norm(const ZD* a, const ZD* b, size_t n, double* part, hipStream
 
 // ---------------------------------------------------------------- projected-matrix step
 struct DenseWork {
-    ZD* X;        // iterate
+    ZD* X;        // iterate                     [slot][kk]
     ZD* Y;        // Frechet iterate
     ZD* Wk;       // in-place inversion workspace
     ZD* Xinv;     // inverse (columns un-permuted)
     ZD* Zt;       // GEMM temporary
-    int* rowperm;
-    double* logpiv;
-    double* part;
-    int npart_max;
+    int* rowperm; // [slot][2 kcap]: row permutation, then pivot rows
+    double* part; // [slot][pstride]: update partials, scatter partials, mu
+    double* delta;  // [slot][2]: |X_new - X|^2, |X_new|^2 of the last step
+    size_t kk;    // kcap^2
+    int kcap;
+    int npart_max;  // partial blocks per slot (= blocks over kcap^2)
+    int pstride;
+    __host__ __device__ DenseWork at(int slot) const {
+        DenseWork o = *this;
+        const size_t d = (size_t)slot * kk;
+        o.X += d; o.Y += d; o.Wk += d; o.Xinv += d; o.Zt += d;
+        o.rowperm += (size_t)slot * 2 * kcap;
+        o.part += (size_t)slot * pstride;
+        o.delta += (size_t)slot * 2;
+        return o;
+    }
 };
-// Build X = T_k (tridiagonal from coef) and, if grad, Y = e_1 cbar^H with cbar = |x| conj(h).
-void launch_dense_build(Coef coef, int k, int grad, DenseWork w, hipStream_t st);
-// X and Y from caller matrices (test entry point).
-void launch_dense_load(const ZD* T, const ZD* E, int k, DenseWork w, hipStream_t st);
-// One Newton step X <- (mu X + X^{-1}/mu)/2 (and Y); returns host-readable partials count.
-int dense_newton_step(int k, int grad, int scaling, int nb, size_t lds_bytes, DenseWork w, hipStream_t st);
+inline int dense_pstride(int kcap) { return 4 * grid_for(kcap * kcap, 256) + 8; }
+
+// Build X = T_k (tridiagonal from coef) and, if grad, Y = e_1 cbar^H with cbar = |x| conj(h),
+// for every list entry (k[e] = k_used, sorted in decreasing order).
+void launch_dense_build(Coef coef, const SrcList& L, int grad, const DenseWork& w, hipStream_t st);
+// X and Y from caller matrices (test entry point, slot 0).
+void launch_dense_load(const ZD* T, const ZD* E, int k, const DenseWork& w, hipStream_t st);
+// One Newton step X <- (mu X + X^{-1}/mu)/2 (and Y) for every entry; flag[e] = 1
+// turns the entry's norm scaling on.  Leaves delta[slot] for the host.
+void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, const DenseWork& w, hipStream_t st);
 // c = X e_1, adjoint seeds from Y, S = |x| Re sum_j c_j h_j.
-void launch_dense_extract(Coef coef, int k, int grad, DenseWork w, hipStream_t st);
+void launch_dense_extract(Coef coef, const SrcList& L, int grad, const DenseWork& w, hipStream_t st);
 
 }  // namespace tslov

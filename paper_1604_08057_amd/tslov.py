@@ -29,8 +29,9 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 KERNEL_FWD_PAIR, KERNEL_BWD_PAIR, KERNEL_APPLY = 0, 1, 2
 
 EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links", "tslov_apply_dw",
-           "tslov_apply_h", "tslov_sign", "tslov_overlap", "tslov_sign_grad", "tslov_error_estimate",
-           "tslov_dense_sign", "tslov_timing_enable", "tslov_timing_read", "tslov_kernel_bytes"]
+           "tslov_apply_h", "tslov_sign", "tslov_overlap", "tslov_sign_grad", "tslov_sign_grad_batched",
+           "tslov_current_estimate", "tslov_error_estimate", "tslov_dense_sign", "tslov_timing_enable",
+           "tslov_timing_read", "tslov_kernel_bytes"]
 
 
 class TslovLibraryMissing(ImportError):
@@ -96,6 +97,10 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_overlap": ([vp, vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(InfoStruct)], ci),
         "tslov_sign_grad": ([vp, vp, vp, ci, ctypes.POINTER(DeflationStruct), ci, ctypes.POINTER(cd), vp, vp,
                              ctypes.POINTER(InfoStruct)], ci),
+        "tslov_sign_grad_batched": ([vp, ci, vp, vp, ctypes.POINTER(ci), ctypes.POINTER(cd), vp, vp,
+                                     ctypes.POINTER(InfoStruct)], ci),
+        "tslov_current_estimate": ([vp, ci, vp, ctypes.POINTER(ci), vp, vp, vp, ctypes.POINTER(cd),
+                                    ctypes.POINTER(InfoStruct)], ci),
         "tslov_error_estimate": ([vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(cd)], ci),
         "tslov_dense_sign": ([vp, vp, ci, vp, vp, vp, ctypes.POINTER(ci)], ci),
         "tslov_timing_enable": ([vp, ci], ci),
@@ -220,6 +225,45 @@ class Context:
         _check(self.lib, self.lib.tslov_sign_grad(self.handle, _ptr(eta), _ptr(psi), int(k), d, 0,
                                                   ctypes.byref(S), _ptr(dU), _ptr(dpsi), ctypes.byref(info)))
         return S.value, dU, dpsi, Info.of(info)
+
+    def _sources(self, x: torch.Tensor, name: str) -> torch.Tensor:
+        shape = (x.shape[0], self.volume, 4, 3)
+        if x.dtype != torch.complex128 or x.device != self.device or tuple(x.shape) != shape:
+            raise ValueError(f"{name} must be complex128 of shape (nsrc, {self.volume}, 4, 3) on {self.device}")
+        return x.contiguous()
+
+    def sign_grad_batched(self, eta: torch.Tensor, psi: torch.Tensor, ks, want_dpsi: bool = False):
+        """Per-source S_s, dS_s/dU and (optionally) dS_s/dpsi_s for a batch (nsrc, V, 4, 3)."""
+        psi = self._sources(psi, "psi")
+        eta = self._sources(eta, "eta")
+        n = psi.shape[0]
+        if eta.shape[0] != n or len(ks) != n:
+            raise ValueError("eta, psi and ks must have the same number of sources")
+        k = (ctypes.c_int * n)(*[int(v) for v in ks])
+        S = (ctypes.c_double * n)()
+        infos = (InfoStruct * n)()
+        dU = torch.empty((n, 4, self.volume, 3, 3), dtype=torch.complex128, device=self.device)
+        dpsi = torch.empty_like(psi) if want_dpsi else None
+        _check(self.lib, self.lib.tslov_sign_grad_batched(self.handle, n, _ptr(eta), _ptr(psi), k, S, _ptr(dU),
+                                                          _ptr(dpsi), infos))
+        return list(S), dU, dpsi, [Info.of(i) for i in infos]
+
+    def current_estimate(self, xi: torch.Tensor, ks, divergence: bool = True, ward: bool = True):
+        """j (4, V) = mean over sources of the U(1) link derivatives of Re <g5 xi|sgn(H)|xi>,
+        with divergence and total current per site and the per-sample Ward residual."""
+        xi = self._sources(xi, "xi")
+        n = xi.shape[0]
+        if len(ks) != n:
+            raise ValueError("one Krylov size per source")
+        k = (ctypes.c_int * n)(*[int(v) for v in ks])
+        j = torch.empty((4, self.volume), dtype=torch.float64, device=self.device)
+        div = torch.empty(self.volume, dtype=torch.float64, device=self.device) if divergence else None
+        tot = torch.empty(self.volume, dtype=torch.float64, device=self.device) if divergence else None
+        w = ctypes.c_double()
+        infos = (InfoStruct * n)()
+        _check(self.lib, self.lib.tslov_current_estimate(self.handle, n, _ptr(xi), k, _ptr(j), _ptr(div), _ptr(tot),
+                                                         ctypes.byref(w) if ward else None, infos))
+        return j, div, tot, (w.value if ward else None), [Info.of(i) for i in infos]
 
     def dense_sign(self, T: torch.Tensor, E: torch.Tensor | None = None):
         k = T.shape[0]
