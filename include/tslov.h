@@ -177,6 +177,13 @@ tslov_status tslov_current_estimate(tslov_ctx* ctx, int nsrc, const void* xi, co
 tslov_status tslov_error_estimate(tslov_ctx* ctx, const void* psi, int k, const tslov_deflation* defl,
                                   double* eps_out);
 
+/* The projected matrix of the two-sided Lanczos process on its own (Sec. 2):
+ * T_out (host, k x k complex128, row-major) receives T_k with diagonal alpha_j,
+ * T_{j+1,j} = beta_{j+1} and T_{j,j+1} = gamma_{j+1} for j < k_used; rows and
+ * columns past k_used are zero.  Its eigenvalues are the Ritz values whose signs
+ * the approximation interpolates (diagnostics: min |Re theta|). */
+tslov_status tslov_lanczos_matrix(tslov_ctx* ctx, const void* psi, int k, void* T_out, tslov_info* info);
+
 /* Projected-matrix step on its own (for tests): S = sgn(T) for a dense complex128
  * k x k row-major device matrix T by the scaled Newton iteration, and, if E is
  * not NULL, L = L_sgn(T, E), the upper-right block of sgn([[T, E], [0, T]])

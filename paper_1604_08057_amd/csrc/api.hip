@@ -959,6 +959,40 @@ tslov_status tslov_error_estimate(tslov_ctx* c, const void* psi, int k, const ts
     return TSLOV_OK;
 }
 
+tslov_status tslov_lanczos_matrix(tslov_ctx* c, const void* psi, int k, void* T_out, tslov_info* info) {
+    CHK(check_common(c, k, nullptr));
+    if (!psi || !T_out) return fail(TSLOV_ERR_ARG, "null argument");
+    CHK(ensure_work(c, 1, k, 0));
+    const SrcList L = make_list({0}, {k});
+    std::vector<EntryStatus> es;
+    const double t0 = now_ms();
+    if (c->precision == TSLOV_MIXED) CHK(forward<float>(c, L, (const ZD*)psi, nullptr, 0, es));
+    else CHK(forward<double>(c, L, (const ZD*)psi, nullptr, 0, es));
+    const int ku = es[0].k_used;
+    std::vector<ZD> T((size_t)k * k, ZD{0.0, 0.0});
+    if (ku > 0) {
+        std::vector<ZD> al(ku + 2), ga(ku + 2);
+        std::vector<double> be(ku + 2);
+        HIPCHK(hipMemcpyAsync(al.data(), c->coef.alpha, (ku + 1) * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(ga.data(), c->coef.gamma, (ku + 1) * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(be.data(), c->coef.beta, (ku + 1) * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        for (int j = 1; j <= ku; ++j) {
+            T[(size_t)(j - 1) * k + (j - 1)] = al[j];
+            if (j < ku) {
+                T[(size_t)j * k + (j - 1)] = ZD{be[j + 1], 0.0};   // T_{j+1,j} = beta_{j+1}
+                T[(size_t)(j - 1) * k + j] = ga[j + 1];            // T_{j,j+1} = gamma_{j+1}
+            }
+        }
+    }
+    std::memcpy(T_out, T.data(), T.size() * sizeof(ZD));
+    const double ms[6] = {now_ms() - t0, 0, 0, 0, 0, now_ms() - t0};
+    fill_info(info, es[0], ms);
+    if (es[0].breakdown == 2)
+        return fail(TSLOV_ERR_BREAKDOWN, "serious Lanczos breakdown at step " + std::to_string(es[0].step));
+    return TSLOV_OK;
+}
+
 tslov_status tslov_dense_sign(tslov_ctx* c, const void* T, int k, const void* E, void* S_out, void* L_out,
                               int* iters) {
     if (!c || !T || !S_out) return fail(TSLOV_ERR_ARG, "null argument");

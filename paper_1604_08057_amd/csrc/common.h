@@ -108,57 +108,58 @@ struct Spinor {
     Z<R> c[4][3];
 };
 
-// Field access through raw buffer instructions: the field base and the plane
-// offset are wavefront-uniform (scalar registers), the site offset is one
-// 32-bit vector register shared by every load of a thread, and the hardware
-// range check turns an out-of-range site into a zero load / dropped store.
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-constexpr int kRsrcWord3 = 0x00020000;   // raw (untyped) buffer, gfx9-family dword 3
+// Field access: the plane base is wavefront-uniform (scalar registers) and the
+// site offset is one 32-bit vector register shared by every load of a thread,
+// so the compiler emits the scalar-base form of the global load/store
+// instructions (one VGPR of address per thread instead of a 64-bit pointer per
+// plane).  Accesses are in range by construction (sites s < V).
+struct FieldBase {
+    char* p;
+};
 
 template <typename R>
-__device__ __forceinline__ rsrc_t make_rsrc(const Z<R>* base, int nplanes, int ldv) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<Z<R>*>(base), (short)0,
-                                             (int)((unsigned)nplanes * (unsigned)ldv * (unsigned)sizeof(Z<R>)),
-                                             kRsrcWord3);
+__device__ __forceinline__ FieldBase field_base(const Z<R>* base) {
+    return FieldBase{reinterpret_cast<char*>(const_cast<Z<R>*>(base))};
+}
+
+// The plane address passes through readfirstlane: it is uniform by
+// construction, and the intrinsic keeps the compiler from folding the site
+// offset into a per-load 64-bit vector address.
+__device__ __forceinline__ char* uniform_ptr(char* p) {
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return reinterpret_cast<char*>(((unsigned long long)hi << 32) | lo);
 }
 
 template <typename R>
-__device__ __forceinline__ Z<R> bload(rsrc_t r, int ldv, int pl, unsigned s) {
-    const unsigned soff = (unsigned)pl * (unsigned)ldv * (unsigned)sizeof(Z<R>);
-    if constexpr (sizeof(R) == 8)
-        return __builtin_bit_cast(Z<R>, __builtin_amdgcn_raw_buffer_load_b128(r, s * 16u, soff, 0));
-    else
-        return __builtin_bit_cast(Z<R>, __builtin_amdgcn_raw_buffer_load_b64(r, s * 8u, soff, 0));
+__device__ __forceinline__ Z<R> fload(FieldBase f, int ldv, int pl, unsigned s) {
+    const char* plane = uniform_ptr(f.p + (size_t)pl * (size_t)ldv * sizeof(Z<R>));
+    return *reinterpret_cast<const Z<R>*>(plane + (size_t)(unsigned)(s * (unsigned)sizeof(Z<R>)));
 }
 
 template <typename R>
-__device__ __forceinline__ void bstore(rsrc_t r, int ldv, int pl, unsigned s, Z<R> v) {
-    const unsigned soff = (unsigned)pl * (unsigned)ldv * (unsigned)sizeof(Z<R>);
-    if constexpr (sizeof(R) == 8) {
-        using V4 = __attribute__((ext_vector_type(4))) unsigned;
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, s * 16u, soff, 0);
-    } else {
-        using V2 = __attribute__((ext_vector_type(2))) unsigned;
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, s * 8u, soff, 0);
-    }
+__device__ __forceinline__ void fstore(FieldBase f, int ldv, int pl, unsigned s, Z<R> v) {
+    char* plane = uniform_ptr(f.p + (size_t)pl * (size_t)ldv * sizeof(Z<R>));
+    *reinterpret_cast<Z<R>*>(plane + (size_t)(unsigned)(s * (unsigned)sizeof(Z<R>))) = v;
 }
 
 template <typename R>
 __device__ __forceinline__ void load_spinor(Spinor<R>& p, const Z<R>* __restrict__ f, int ldv, int s) {
-    const rsrc_t r = make_rsrc(f, 12, ldv);
+    const FieldBase r = field_base(f);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) p.c[sp][c] = bload<R>(r, ldv, sp * 3 + c, (unsigned)s);
+        for (int c = 0; c < 3; ++c) p.c[sp][c] = fload<R>(r, ldv, sp * 3 + c, (unsigned)s);
 }
 
 template <typename R>
 __device__ __forceinline__ void store_spinor(Z<R>* __restrict__ f, int ldv, int s, const Spinor<R>& p) {
-    const rsrc_t r = make_rsrc(f, 12, ldv);
+    const FieldBase r = field_base(f);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) bstore<R>(r, ldv, sp * 3 + c, (unsigned)s, p.c[sp][c]);
+        for (int c = 0; c < 3; ++c) fstore<R>(r, ldv, sp * 3 + c, (unsigned)s, p.c[sp][c]);
 }
 
 template <typename R>
@@ -174,7 +175,7 @@ __device__ __forceinline__ void load_link(Z<R> (&u)[3][3], const Z<R>* __restric
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) u[a][b] = bload<R>(make_rsrc(U, 36, ldv), ldv, nu * 9 + a * 3 + b, (unsigned)s);
+        for (int b = 0; b < 3; ++b) u[a][b] = fload<R>(field_base(U), ldv, nu * 9 + a * 3 + b, (unsigned)s);
 }
 
 // ------------------------------------------------------------------ spin projection
@@ -296,14 +297,14 @@ __device__ __forceinline__ void hop1(Z<R> (&acc)[4], const Z<R> (&urow)[3], cons
 template <typename R>
 __device__ __forceinline__ void load_row(Z<R> (&u)[3], const Z<R>* __restrict__ U, int ldv, int nu, int a, int s) {
 #pragma unroll
-    for (int b = 0; b < 3; ++b) u[b] = bload<R>(make_rsrc(U, 36, ldv), ldv, nu * 9 + a * 3 + b, (unsigned)s);
+    for (int b = 0; b < 3; ++b) u[b] = fload<R>(field_base(U), ldv, nu * 9 + a * 3 + b, (unsigned)s);
 }
 
 template <typename R>
 __device__ __forceinline__ void load_col_conj(Z<R> (&u)[3], const Z<R>* __restrict__ U, int ldv, int nu, int a,
                                               int s) {
 #pragma unroll
-    for (int b = 0; b < 3; ++b) u[b] = cj(bload<R>(make_rsrc(U, 36, ldv), ldv, nu * 9 + b * 3 + a, (unsigned)s));
+    for (int b = 0; b < 3; ++b) u[b] = cj(fload<R>(field_base(U), ldv, nu * 9 + b * 3 + a, (unsigned)s));
 }
 
 // Colour handled by this thread in the colour-split kernels: one wavefront per

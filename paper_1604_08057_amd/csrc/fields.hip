@@ -146,13 +146,13 @@ struct Spin1 {
 template <typename R>
 __device__ __forceinline__ void load1(Z<R> (&p)[4], const Z<R>* __restrict__ f, int ldv, int a, int s) {
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp) p[sp] = bload<R>(make_rsrc(f, 12, ldv), ldv, sp * 3 + a, (unsigned)s);
+    for (int sp = 0; sp < 4; ++sp) p[sp] = fload<R>(field_base(f), ldv, sp * 3 + a, (unsigned)s);
 }
 
 template <typename R>
 __device__ __forceinline__ void store1(Z<R>* __restrict__ f, int ldv, int a, int s, const Z<R> (&p)[4]) {
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp) bstore<R>(make_rsrc(f, 12, ldv), ldv, sp * 3 + a, (unsigned)s, p[sp]);
+    for (int sp = 0; sp < 4; ++sp) fstore<R>(field_base(f), ldv, sp * 3 + a, (unsigned)s, p[sp]);
 }
 
 template <typename R>
@@ -607,9 +607,9 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb(const Z<R>* __restrict__ U, 
             mem_fence_compiler();
         }
         const R kap = (R)kappa;
-        const rsrc_t rw = make_rsrc(wk.w(slot, j), 12, g.ldv), rv = make_rsrc(wk.v(slot, j), 12, g.ldv),
-                     ra = make_rsrc(wk.a(slot, j), 12, g.ldv), rb = make_rsrc(wk.b(slot, j), 12, g.ldv),
-                     re = make_rsrc(wk.f(slot, 1), 12, g.ldv);
+        const FieldBase rw = field_base(wk.w(slot, j)), rv = field_base(wk.v(slot, j)),
+                     ra = field_base(wk.a(slot, j)), rb = field_base(wk.b(slot, j)),
+                     re = field_base(wk.f(slot, 1));
         Z<R> vbo[4], wbo[4], abo[4];
         double d1 = 0.0, d2r = 0.0, d2i = 0.0;
 #pragma unroll
@@ -617,22 +617,22 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb(const Z<R>* __restrict__ U, 
             const int pl = sp * 3 + a;
             const unsigned i = (unsigned)s;
             const R sg = sp < 2 ? R(1) : R(-1);
-            const Z<R> w_s = bload<R>(rw, g.ldv, pl, i);
-            const Z<R> v_s = bload<R>(rv, g.ldv, pl, i);
-            const Z<R> a_s = bload<R>(ra, g.ldv, pl, i);
-            const Z<R> b_s = bload<R>(rb, g.ldv, pl, i);
-            Z<R> vb = etac * bload<R>(re, g.ldv, pl, i) + ca * b_s;
+            const Z<R> w_s = fload<R>(rw, g.ldv, pl, i);
+            const Z<R> v_s = fload<R>(rv, g.ldv, pl, i);
+            const Z<R> a_s = fload<R>(ra, g.ldv, pl, i);
+            const Z<R> b_s = fload<R>(rb, g.ldv, pl, i);
+            Z<R> vb = etac * fload<R>(re, g.ldv, pl, i) + ca * b_s;
             Z<R> wb = abc * a_s;
             Z<R> ab_s = ca * w_s;
             if (!LAST) {
-                const Z<R> r_s = bload<R>(make_rsrc(rbar_j, 12, g.ldv), g.ldv, pl, i);
-                const Z<R> sb_s = bload<R>(make_rsrc(sbar_j, 12, g.ldv), g.ldv, pl, i);
+                const Z<R> r_s = fload<R>(field_base(rbar_j), g.ldv, pl, i);
+                const Z<R> sb_s = fload<R>(field_base(sbar_j), g.ldv, pl, i);
                 ab_s = ab_s + r_s;
                 vb = vb + sg * (r_s - kap * accr[sp]) - alc * r_s;
                 wb = wb + sg * (sb_s - kap * accs[sp]) - alr * sb_s;
                 if (carry) {
-                    vb = vb - gnc * bload<R>(make_rsrc(rbar_n, 12, g.ldv), g.ldv, pl, i);
-                    wb = wb - bn * bload<R>(make_rsrc(sbar_n, 12, g.ldv), g.ldv, pl, i);
+                    vb = vb - gnc * fload<R>(field_base(rbar_n), g.ldv, pl, i);
+                    wb = wb - bn * fload<R>(field_base(sbar_n), g.ldv, pl, i);
                 }
             }
             vbo[sp] = vb;

@@ -30,7 +30,7 @@ KERNEL_FWD_PAIR, KERNEL_BWD_PAIR, KERNEL_APPLY = 0, 1, 2
 
 EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links", "tslov_apply_dw",
            "tslov_apply_h", "tslov_sign", "tslov_overlap", "tslov_sign_grad", "tslov_sign_grad_batched",
-           "tslov_current_estimate", "tslov_error_estimate", "tslov_dense_sign", "tslov_timing_enable",
+           "tslov_current_estimate", "tslov_error_estimate", "tslov_lanczos_matrix", "tslov_dense_sign", "tslov_timing_enable",
            "tslov_timing_read", "tslov_kernel_bytes"]
 
 
@@ -102,6 +102,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_current_estimate": ([vp, ci, vp, ctypes.POINTER(ci), vp, vp, vp, ctypes.POINTER(cd),
                                     ctypes.POINTER(InfoStruct)], ci),
         "tslov_error_estimate": ([vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(cd)], ci),
+        "tslov_lanczos_matrix": ([vp, vp, ci, vp, ctypes.POINTER(InfoStruct)], ci),
         "tslov_dense_sign": ([vp, vp, ci, vp, vp, vp, ctypes.POINTER(ci)], ci),
         "tslov_timing_enable": ([vp, ci], ci),
         "tslov_timing_read": ([vp, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
@@ -264,6 +265,16 @@ class Context:
         _check(self.lib, self.lib.tslov_current_estimate(self.handle, n, _ptr(xi), k, _ptr(j), _ptr(div), _ptr(tot),
                                                          ctypes.byref(w) if ward else None, infos))
         return j, div, tot, (w.value if ward else None), [Info.of(i) for i in infos]
+
+    def lanczos_matrix(self, psi: torch.Tensor, k: int):
+        """T_k (k x k complex128 on the host) of the two-sided Lanczos process from psi."""
+        import numpy as np
+        psi = self._spinor(psi, "psi")
+        T = np.zeros((k, k), dtype=np.complex128)
+        info = InfoStruct()
+        _check(self.lib, self.lib.tslov_lanczos_matrix(self.handle, _ptr(psi), int(k),
+                                                       T.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info)))
+        return T, Info.of(info)
 
     def dense_sign(self, T: torch.Tensor, E: torch.Tensor | None = None):
         k = T.shape[0]
