@@ -130,8 +130,16 @@ tslov_status tslov_overlap(tslov_ctx* ctx, const void* psi, void* out, int k,
  * dpsi_out (nullable, canonical spinor) receives dS/dRe psi + i dS/dIm psi.
  * S_out is a host pointer.  recompute_stride must be 0 (all Krylov vectors are
  * stored; 6*k*12*V complex values of workspace).  For D_ov the caller passes
- * g5 eta and adds Re <eta|psi>.  defl must be NULL or have l = 0 (the derivative
- * of the deflated sign, with its eigenpair motion, is not provided). */
+ * g5 eta and adds Re <eta|psi>.
+ * With defl (l > 0) S is that of the deflated sign (see tslov_deflation) and the
+ * derivative includes the motion of the deflated eigenpairs with U (Sec. 3, App. E):
+ * for simple eigenvalues dPi_i = Z_i dH Pi_i + Pi_i dH Z_i, Pi_i = R_i L_i^H,
+ * Z_i = (lambda_i - H)^{-1}(1 - Pi_i); the 2l systems for Z_i psi and Z_i^H a_i
+ * (a_i = s_i eta - dS/dpsi_p) are solved on the device by conjugate gradients on
+ * the normal equations to relative residual 1e-11 (ERR_NOT_CONVERGED after 1e5
+ * iterations; info->reserved = iterations used).  R, L must be accurate
+ * eigenvectors of H(U) for the links set (the formula assumes exact eigenpairs);
+ * eigenvalues must be distinct. */
 tslov_status tslov_sign_grad(tslov_ctx* ctx, const void* eta, const void* psi, int k,
                              const tslov_deflation* defl, int recompute_stride,
                              double* S_out, void* dU_out, void* dpsi_out, tslov_info* info);

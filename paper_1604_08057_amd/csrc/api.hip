@@ -104,6 +104,8 @@ struct tslov_ctx {
     Buf wardp;       // Ward block maxima
     Buf canon;       // canonical spinors: projected source, partial result, error estimate
     Buf deflw;       // deflation coefficients, signs and partial sums
+    Buf deflx;       // deflated derivative: R^H eta, R^H psibar, q, -q and dot partials
+    Buf cgf, cgp, cgs;   // shifted solves: fields, partial sums, per-system scalars
     double* host_part = nullptr;  // pinned
     int host_part_n = 0;
     int slots = 0, kcap = 0, grad_cap = 0;   // shape of the batch workspace
@@ -736,6 +738,116 @@ tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
     return TSLOV_OK;
 }
 
+static tslov_status run_batched(tslov_ctx* c, BatchRequest& q) {
+    return c->precision == TSLOV_MIXED ? grad_batched<float>(c, q) : grad_batched<double>(c, q);
+}
+
+constexpr double kCgTol = 1e-11;     // relative residual of the shifted solves
+constexpr int kCgMaxIter = 100000;
+constexpr int kCgCheckEvery = 8;
+
+// Derivative of the deflated S = Re eta^H [sum_i s_i Pi_i psi + TSL(P psi)], P = 1 - sum_i Pi_i,
+// with the eigenpairs moving with U (reduced-resolvent solves; see solve.hip).
+tslov_status deflated_grad(tslov_ctx* c, const ZD* eta, const ZD* psi, int k, const tslov_deflation* defl,
+                           double* S_out, ZD* dU, ZD* dpsi, tslov_info* info) {
+    const double t0 = now_ms();
+    DeflSet d;
+    CHK(prepare_defl(c, defl, d));
+    const int l = d.l, V = c->g.V, nr = 2 * l;
+    const size_t n12 = (size_t)12 * V;
+    CHK(ensure(c->canon, (size_t)5 * n12 * sizeof(ZD)));
+    ZD* psip = canon_buf(c, 0);
+    ZD* pbar = canon_buf(c, 1);
+    const int nb = c->nblk();
+    CHK(ensure(c->deflx, (size_t)4 * l * sizeof(ZD) + (size_t)nb * 2 * l * sizeof(double)));
+    ZD* dRe = c->deflx.as<ZD>();
+    ZD* dRp = dRe + l;
+    ZD* qd = dRp + l;
+    ZD* mqd = qd + l;
+    double* xpart = (double*)(mqd + l);
+    tslov::launch_defl_coeffs(d.L, psi, V, l, d.part, d.c, c->st);          // c_i = L_i^H psi
+    tslov::launch_defl_project(d.R, psi, d.c, V, l, psip, c->st);           // psi_p = psi - R c
+    // TSL part on the projected source (link gradient into dU, source gradient into pbar)
+    double S_tsl = 0.0;
+    BatchRequest q;
+    q.nsrc = 1;
+    q.eta = eta;
+    q.psi = psip;
+    q.k = &k;
+    q.S_out = &S_tsl;
+    q.dU = dU;
+    q.dpsi = pbar;
+    q.infos = info;
+    CHK(run_batched(c, q));
+    tslov::launch_defl_coeffs(d.R, eta, V, l, xpart, dRe, c->st);          // R_i^H eta
+    tslov::launch_defl_coeffs(d.R, pbar, V, l, xpart, dRp, c->st);         // R_i^H psibar_p
+    std::vector<ZD> ch(l), de(l), dp(l), qh(l), mq(l);
+    std::vector<double> sg(l);
+    HIPCHK(hipMemcpyAsync(ch.data(), d.c, l * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(de.data(), dRe, l * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(dp.data(), dRp, l * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(sg.data(), d.sgn, l * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    double S = S_tsl;
+    for (int i = 0; i < l; ++i) {
+        qh[i] = ZD{sg[i] * de[i].re - dp[i].re, sg[i] * de[i].im - dp[i].im};   // R_i^H a_i
+        mq[i] = ZD{-qh[i].re, -qh[i].im};
+        S += sg[i] * (de[i].re * ch[i].re + de[i].im * ch[i].im);             // Re conj(R_i^H eta) c_i
+    }
+    HIPCHK(hipMemcpyAsync(qd, qh.data(), l * sizeof(ZD), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(mqd, mq.data(), l * sizeof(ZD), hipMemcpyHostToDevice, c->st));
+    // shifted solves: e < l: (lambda_i - H) z = (1 - Pi_i) psi;  e >= l: (conj lambda_i - H^dag) z' = (1 - Pi_i^H) a_i
+    const int ps = c->pstride();
+    CHK(ensure(c->cgf, (size_t)nr * tslov::kCgFields * c->field_elems() * sizeof(ZD)));
+    CHK(ensure(c->cgp, (size_t)nr * 4 * ps * sizeof(double)));
+    CHK(ensure(c->cgs, (size_t)nr * sizeof(tslov::CgRhs)));
+    tslov::CgWork cw;
+    cw.f = c->cgf.as<ZD>();
+    cw.part = c->cgp.as<double>();
+    cw.st = c->cgs.as<tslov::CgRhs>();
+    cw.fe = c->field_elems();
+    cw.pstride = ps;
+    std::vector<tslov::CgRhs> st0(nr);
+    for (int e = 0; e < nr; ++e) {
+        const int i = e < l ? e : e - l;
+        const double lr = defl->lambda[2 * i], li = defl->lambda[2 * i + 1];
+        st0[e] = tslov::CgRhs{};
+        st0[e].sigma = e < l ? ZD{lr, li} : ZD{lr, -li};
+        st0[e].msign = e < l ? 1.0 : -1.0;
+    }
+    HIPCHK(hipMemcpyAsync(cw.st, st0.data(), nr * sizeof(tslov::CgRhs), hipMemcpyHostToDevice, c->st));
+    const ZD* U = c->U64.as<ZD>();
+    tslov::launch_cg_rhs(c->g, psi, eta, pbar, d.R, d.L, d.c, qd, d.sgn, l, cw, c->st);
+    tslov::launch_cg_start(U, c->g, c->kappa, c->mu, nr, cw, c->st);
+    int it = 0, all_done = 0;
+    std::vector<tslov::CgRhs> sh(nr);
+    for (; it < kCgMaxIter && !all_done; ++it) {
+        const int check = (it % kCgCheckEvery) == kCgCheckEvery - 1;
+        tslov::launch_cg_iteration(U, c->g, c->kappa, c->mu, nr, it, check, kCgTol, cw, c->st);
+        if (check) {
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(sh.data(), cw.st, nr * sizeof(tslov::CgRhs), hipMemcpyDeviceToHost, c->st));
+            HIPCHK(hipStreamSynchronize(c->st));
+            all_done = 1;
+            for (int e = 0; e < nr; ++e) all_done &= sh[e].done;
+        }
+    }
+    if (!all_done) return fail(TSLOV_ERR_NOT_CONVERGED, "shifted solves of the eigenpair derivative did not converge");
+    tslov::launch_cg_finish(c->g, d.R, d.L, d.c, l, cw, c->st);
+    tslov::launch_defl_force(c->g, c->kappa, c->mu, d.R, d.L, qd, l, cw, c->antiperiodic, dU, c->st);
+    // source gradient: psibar = psibar_p + sum_i q_i L_i
+    if (dpsi) tslov::launch_defl_project(d.L, pbar, mqd, V, l, dpsi, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (S_out) *S_out = S;
+    if (info) {
+        info->reserved = it;
+        info->ms[4] = now_ms() - t0 - info->ms[5];
+        info->ms[5] = now_ms() - t0;
+    }
+    return TSLOV_OK;
+}
+
 }  // namespace
 
 // ===================================================================== C ABI
@@ -785,7 +897,8 @@ void tslov_destroy(tslov_ctx* c) {
     (void)hipStreamSynchronize(c->st);
     for (Buf* b : {&c->U64, &c->U32, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
                    &c->fields, &c->part, &c->coefmem, &c->dense, &c->denseInt, &c->densePart, &c->denseDelta,
-                   &c->gpart, &c->gsrc, &c->bout, &c->wardp, &c->canon, &c->deflw})
+                   &c->gpart, &c->gsrc, &c->bout, &c->wardp, &c->canon, &c->deflw, &c->deflx, &c->cgf, &c->cgp,
+                   &c->cgs})
         release(*b);
     if (c->host_part) (void)hipHostFree(c->host_part);
     for (auto& v : c->ev_used)
@@ -862,17 +975,13 @@ tslov_status tslov_overlap(tslov_ctx* c, const void* psi, void* out, int k, cons
                                        : sign_impl<double>(c, psi, out, k, defl, info, 1);
 }
 
-static tslov_status run_batched(tslov_ctx* c, BatchRequest& q) {
-    return c->precision == TSLOV_MIXED ? grad_batched<float>(c, q) : grad_batched<double>(c, q);
-}
-
 tslov_status tslov_sign_grad(tslov_ctx* c, const void* eta, const void* psi, int k, const tslov_deflation* defl,
                              int recompute_stride, double* S_out, void* dU_out, void* dpsi_out, tslov_info* info) {
     CHK(check_common(c, k, defl));
     if (!eta || !psi || !dU_out) return fail(TSLOV_ERR_ARG, "null argument");
-    if (defl && defl->l != 0)
-        return fail(TSLOV_ERR_ARG, "the derivative with deflation (eigenpair motion) is not supported; pass NULL");
     if (recompute_stride != 0) return fail(TSLOV_ERR_ARG, "recompute_stride must be 0 (all vectors stored)");
+    if (defl && defl->l != 0) return deflated_grad(c, (const ZD*)eta, (const ZD*)psi, k, defl, S_out, (ZD*)dU_out,
+                                                   (ZD*)dpsi_out, info);
     BatchRequest q;
     q.nsrc = 1;
     q.eta = (const ZD*)eta;

@@ -20,15 +20,6 @@ __device__ __forceinline__ int block_flag(const int* p) {
     return r;
 }
 
-template <typename R>
-__device__ __forceinline__ void g5_inplace(Spinor<R>& p) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        p.c[2][c] = -p.c[2][c];
-        p.c[3][c] = -p.c[3][c];
-    }
-}
-
 // Compiler barrier for memory operations: keeps the epilogue's own-site loads from
 // being hoisted above the hopping loop, where they would stay live (and spill).
 __device__ __forceinline__ void mem_fence_compiler() { asm volatile("" ::: "memory"); }
@@ -672,31 +663,6 @@ void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const 
 //   G_ab += -kappa sum_{s=0,1} [ e_f hP[s][a] conj(hQ[s][b]) + e_b hQ2[s][a] conj(hP2[s][b]) ]
 // with hP = P+(g5 p(x)), hQ = P+(q(x+nu)), hP2 = P-(g5 p(x+nu)), hQ2 = P-(q(x)) the
 // half spinors of the (1 +- g_nu) projectors, e_f = e^{+mu}, e_b = e^{-mu} for nu = t.
-template <int NU, typename R>
-__device__ __forceinline__ void force_pair(ZD (&G)[3][3], const Spinor<R>& p_x, const Spinor<R>& q_x,
-                                           const Spinor<R>& p_y, const Spinor<R>& q_y, double ef, double eb) {
-    Spinor<R> gp_x = p_x, gp_y = p_y;
-    g5_inplace(gp_x);
-    g5_inplace(gp_y);
-    Z<R> hP[2][3], hQ[2][3], hP2[2][3], hQ2[2][3];
-    project<NU, +1>(gp_x, hP);
-    project<NU, +1>(q_y, hQ);
-    project<NU, -1>(gp_y, hP2);
-    project<NU, -1>(q_x, hQ2);
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            ZD t = mk<double>(0, 0);
-#pragma unroll
-            for (int sp = 0; sp < 2; ++sp) {
-                t = t + ef * mulcj(zcast<double>(hP[sp][a]), zcast<double>(hQ[sp][b]));
-                t = t + eb * mulcj(zcast<double>(hQ2[sp][a]), zcast<double>(hP2[sp][b]));
-            }
-            G[a][b] = G[a][b] + t;
-        }
-}
-
 template <int NU, typename R>
 __device__ void force_body(const Geom& g, double kappa, double emu, const Work<R>& wk, int slot, int k, int j0,
                            int j1, int s, ZD* __restrict__ gout) {

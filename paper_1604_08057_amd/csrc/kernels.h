@@ -121,6 +121,40 @@ void launch_defl_finish(const ZD* R, const ZD* c, const double* sgn, const ZD* y
                         int overlap, ZD* out, hipStream_t st);
 int launch_diff_norm(const ZD* a, const ZD* b, size_t n, double* part, hipStream_t st);
 
+// ---------------------------------------------------------------- deflated derivative
+// Batched CGNR for (sigma_e - H(m_e mu)) x_e = b_e, one system per grid row e.
+struct CgRhs {
+    ZD sigma;        // shift
+    double msign;    // +1: H(mu); -1: H(-mu) = H(mu)^dag
+    double bnorm2;   // |b|^2
+    double zeta[2];  // |A^dag r|^2, double-buffered by iteration parity
+    double rr;       // |r|^2 at the last check
+    int done;        // converged (frozen)
+    int pad;
+};
+constexpr int kCgX = 0, kCgR = 1, kCgP = 2, kCgW = 3, kCgZ = 4, kCgFields = 5;
+struct CgWork {
+    ZD* f;        // [e][kCgFields] float64 SoA fields
+    double* part; // [e][4][pstride]
+    CgRhs* st;    // [e]
+    size_t fe;
+    int pstride;
+    __host__ __device__ ZD* field(int e, int i) const { return f + ((size_t)e * kCgFields + i) * fe; }
+    __host__ __device__ double* p(int e, int i) const { return part + ((size_t)e * 4 + i) * pstride; }
+};
+// right-hand sides of the 2l systems (Z_i psi, Z_i^H a_i), r = b, x = 0, |b|^2
+void launch_cg_rhs(const Geom& g, const ZD* psi, const ZD* eta, const ZD* pbar, const ZD* R, const ZD* L, const ZD* c,
+                   const ZD* q, const double* sgn, int l, const CgWork& cw, hipStream_t st);
+void launch_cg_start(const ZD* U, const Geom& g, double kappa, double mu, int nr, const CgWork& cw, hipStream_t st);
+// one CGNR iteration (check = 1: evaluate convergence afterwards)
+void launch_cg_iteration(const ZD* U, const Geom& g, double kappa, double mu, int nr, int it, int check, double tol,
+                         const CgWork& cw, hipStream_t st);
+// projections (1 - Pi_i) / (1 - Pi_i^H) of the solutions and the conj(c_i) scaling
+void launch_cg_finish(const Geom& g, const ZD* R, const ZD* L, const ZD* c, int l, const CgWork& cw, hipStream_t st);
+// dU += eigenpair-motion terms (canonical dU, boundary sign undone)
+void launch_defl_force(const Geom& g, double kappa, double mu, const ZD* R, const ZD* L, const ZD* q, int l,
+                       const CgWork& cw, int antiperiodic, ZD* dU, hipStream_t st);
+
 // ---------------------------------------------------------------- projected-matrix step
 struct DenseWork {
     ZD* X;        // iterate                     [slot][kk]

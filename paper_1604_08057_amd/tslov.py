@@ -67,10 +67,11 @@ class Info:
     newton_iters: int
     norm_x: float
     ms: tuple
+    reserved: int = 0   # shifted-solve iterations of the deflated derivative
 
     @classmethod
     def of(cls, s: InfoStruct) -> "Info":
-        return cls(s.k_used, s.breakdown, s.newton_iters, s.norm_x, tuple(s.ms))
+        return cls(s.k_used, s.breakdown, s.newton_iters, s.norm_x, tuple(s.ms), s.reserved)
 
 
 _lib = None

@@ -7,7 +7,8 @@ for the undeflated sign.  Cases: l = 10 and l = 20 on two tiny lattices, the
 improvement over plain TSL at fixed k, a source inside the deflated space (TSL
 then sees a source at rounding level and the result is the exact R sgn(lambda) c),
 the zero source (k_used = 0, zero output, eps_A = 0), eps_A against the oracle's,
-and argument checks (l beyond 256, an eigenvalue on the imaginary axis).
+and argument checks (an eigenvalue on the imaginary axis, for the sign and its
+derivative).
 """
 import numpy as np
 import pytest
@@ -135,5 +136,5 @@ def test_deflation_argument_checks():
     with pytest.raises(TslovError):
         ctx.sign(dev(psi), 8, defl=bdefl)
     with pytest.raises(TslovError):
-        ctx.sign_grad(dev(psi), dev(psi), 8, defl=defl)
+        ctx.sign_grad(dev(psi), dev(psi), 8, defl=bdefl)
     ctx.close()
