@@ -245,7 +245,7 @@ size_t bytes_per_source(const tslov_ctx* c, int kcap, int grad) {
     const size_t fb = c->field_bytes();
     size_t b = (size_t)(grad ? 6 : 4) * kcap * fb + (size_t)tslov::kNF * fb;
     b += (size_t)tslov::kNP * c->pstride() * sizeof(double) + coef_bytes(1, kcap);
-    b += (size_t)5 * kcap * kcap * sizeof(ZD) + (size_t)tslov::dense_pstride(kcap) * sizeof(double);
+    b += (size_t)6 * kcap * kcap * sizeof(ZD) + (size_t)tslov::dense_pstride(kcap) * sizeof(double);
     if (grad) b += (size_t)2 * 36 * c->g.ldv * sizeof(ZD) + (size_t)2 * 12 * c->g.V * sizeof(ZD);
     return b;
 }
@@ -355,7 +355,7 @@ tslov_status forward(tslov_ctx* c, const SrcList& L, const ZD* psi, const ZD* et
 tslov_status ensure_dense(tslov_ctx* c, int slots, int kcap, DenseWork& w) {
     const size_t kk = (size_t)kcap * kcap;
     const int ps = tslov::dense_pstride(kcap);
-    CHK(ensure(c->dense, (size_t)slots * 5 * kk * sizeof(ZD)));
+    CHK(ensure(c->dense, (size_t)slots * 6 * kk * sizeof(ZD)));
     CHK(ensure(c->denseInt, (size_t)slots * 2 * kcap * sizeof(int)));
     CHK(ensure(c->densePart, (size_t)slots * ps * sizeof(double)));
     CHK(ensure(c->denseDelta, (size_t)slots * 2 * sizeof(double)));
@@ -367,6 +367,7 @@ tslov_status ensure_dense(tslov_ctx* c, int slots, int kcap, DenseWork& w) {
     w.Wk = d + 2 * S * kk;
     w.Xinv = d + 3 * S * kk;
     w.Zt = d + 4 * S * kk;
+    w.Y2 = d + 5 * S * kk;
     w.rowperm = c->denseInt.as<int>();
     w.part = c->densePart.as<double>();
     w.delta = c->denseDelta.as<double>();
@@ -386,46 +387,61 @@ int choose_nb(const tslov_ctx* c, int k) {
 }
 
 // Newton iteration on X (and Y) of every entry of L (k = size, decreasing) until
-// each entry's relative step falls to rounding level.  iters[e] receives the count.
+// each entry's relative step falls to rounding level.  Scaled inverse-based steps
+// first; once the step is below kNsSwitch the inverse-free step takes over (and
+// hands back if it ever fails to contract).  iters[e] receives the step count.
+constexpr double kNsSwitch = 1e-2;
+
 tslov_status newton(tslov_ctx* c, const SrcList& L, int grad, const DenseWork& w, std::vector<int>& iters) {
     struct St {
-        int scaling = 1, extra = 0, done = 0, it = 0;
+        int scaling = 1, extra = 0, done = 0, it = 0, ns = 0;
         double prev = INFINITY;
     };
     std::vector<St> s(L.n);
     for (auto& x : s) x.extra = grad ? 1 : 0;
     for (int it = 1; it <= 100; ++it) {
-        SrcList A{};
-        for (int e = 0; e < L.n; ++e)
-            if (!s[e].done) {
-                A.slot[A.n] = L.slot[e];
-                A.src[A.n] = e;   // back-reference to the entry
-                A.k[A.n] = L.k[e];
-                A.flag[A.n] = s[e].scaling;
-                ++A.n;
-            }
-        if (A.n == 0) break;
-        tslov::dense_newton_step(A, grad, choose_nb(c, A.k[0]), c->lds_max, w, c->st);
+        SrcList A{}, B{};   // inverse-based and inverse-free steps this round
+        for (int e = 0; e < L.n; ++e) {
+            if (s[e].done) continue;
+            SrcList& T = s[e].ns ? B : A;
+            T.slot[T.n] = L.slot[e];
+            T.src[T.n] = e;   // back-reference to the entry
+            T.k[T.n] = L.k[e];
+            T.flag[T.n] = s[e].scaling;
+            ++T.n;
+        }
+        if (A.n == 0 && B.n == 0) break;
+        if (A.n) tslov::dense_newton_step(A, grad, choose_nb(c, A.k[0]), c->lds_max, w, c->st);
+        if (B.n) tslov::dense_ns_step(B, grad, w, c->st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(c->host_part, w.delta, (size_t)2 * c->dslots * sizeof(double), hipMemcpyDeviceToHost,
                               c->st));
         HIPCHK(hipStreamSynchronize(c->st));
-        for (int a = 0; a < A.n; ++a) {
-            St& x = s[A.src[a]];
-            x.it = it;
-            const double delta = std::sqrt(c->host_part[2 * A.slot[a]] / c->host_part[2 * A.slot[a] + 1]);
-            if (!std::isfinite(delta))
-                return fail(TSLOV_ERR_SIGN_UNDEFINED, "projected matrix is singular or its sign is undefined");
-            if (delta < 1e-2) x.scaling = 0;
-            // quadratic convergence: once the step is below 1e-8 the new iterate's error
-            // is at rounding level; stagnation above that also ends the iteration
-            const bool conv = delta <= 1e-8 || (delta < 1e-6 && delta > 0.5 * x.prev);
-            if (conv) {
-                if (x.extra) x.extra = 0;
-                else x.done = 1;
+        for (const SrcList* T : {&A, &B})
+            for (int a = 0; a < T->n; ++a) {
+                St& x = s[T->src[a]];
+                x.it = it;
+                const double delta = std::sqrt(c->host_part[2 * T->slot[a]] / c->host_part[2 * T->slot[a] + 1]);
+                if (!std::isfinite(delta))
+                    return fail(TSLOV_ERR_SIGN_UNDEFINED, "projected matrix is singular or its sign is undefined");
+                if (x.ns && delta > x.prev) {   // not contracting: back to inverse-based steps
+                    x.ns = 0;
+                    x.prev = delta;
+                    continue;
+                }
+                if (delta < kNsSwitch) {
+                    x.scaling = 0;
+                    x.ns = 1;
+                }
+                // quadratic convergence: once the step is below 1e-8 the new iterate's error
+                // is at rounding level; stagnation above that also ends the iteration
+                const bool conv = delta <= 1e-8 || (delta < 1e-6 && delta > 0.5 * x.prev);
+                if (conv) {
+                    if (x.extra) x.extra = 0;
+                    else x.done = 1;
+                }
+                x.prev = delta;
             }
-            x.prev = delta;
-        }
     }
     iters.assign(L.n, 0);
     for (int e = 0; e < L.n; ++e) {

@@ -6,7 +6,10 @@
 // in-place, blocked Gauss-Jordan elimination with partial pivoting: one block
 // factors a panel of nb columns in LDS, then all blocks apply the panel's
 // transform to the remaining columns; the row permutation is undone by a
-// column scatter.  All arithmetic is float64 complex.  Every kernel serves a list
+// column scatter.  Once the iterate is close to its limit (X^2 ~ 1) the
+// inverse-free Newton-Schulz step X <- X (3 - X^2)/2 takes over (quadratically
+// convergent there, GEMMs only); on the block matrix it updates
+// Y <- [Y (3 - X^2) - X (X Y + Y X)]/2.  All arithmetic is float64 complex.  Every kernel serves a list
 // of independent matrices (one per batch entry, sizes k[e] in decreasing order);
 // grid dimension z runs over the entries.
 #include "kernels.h"
@@ -257,17 +260,33 @@ __global__ __launch_bounds__(kDB) void k_dense_mu(DenseWork w0, SrcList L, int n
 }
 
 // ------------------------------------------------------------------ complex GEMM
-// mode 0: Zt = Xinv Y;  mode 1: Y <- (mu Y - (Zt Xinv)/mu)/2  (mu read from device).
+// Operands by index into the entry's matrices: 0 X, 1 Y, 2 Wk, 3 Xinv, 4 Zt, 5 Y2.
+__device__ __forceinline__ ZD* dmat(const DenseWork& w, int i) {
+    switch (i) {
+        case 0: return w.X;
+        case 1: return w.Y;
+        case 2: return w.Wk;
+        case 3: return w.Xinv;
+        case 4: return w.Zt;
+        default: return w.Y2;
+    }
+}
+enum { kMX = 0, kMY = 1, kMWk = 2, kMXinv = 3, kMZt = 4, kMY2 = 5 };
+
+// C = a (A B) + b D (D may be C; A, B must not be C).  mode 1 instead forms the
+// Newton Frechet update C <- (mu C - (A B)/mu)/2 with mu read from the device.
 // 16 x 16 output tiles, one output per thread, 16-deep LDS tiles of A and B.
-__global__ __launch_bounds__(kDB) void k_zgemm(DenseWork w0, SrcList L, int mode) {
+__global__ __launch_bounds__(kDB) void k_zgemm(DenseWork w0, SrcList L, int ia, int ib, int ic, int id, double a,
+                                               double b, int mode) {
     __shared__ ZD As[16][17];
     __shared__ ZD Bs[16][17];
     const int e = blockIdx.z, k = L.k[e];
     if ((int)blockIdx.x * 16 >= k || (int)blockIdx.y * 16 >= k) return;
     const DenseWork w = w0.at(L.slot[e]);
-    const ZD* __restrict__ A = mode == 0 ? w.Xinv : w.Zt;
-    const ZD* __restrict__ B = mode == 0 ? w.Y : w.Xinv;
-    ZD* __restrict__ C = mode == 0 ? w.Zt : w.Y;
+    const ZD* __restrict__ A = dmat(w, ia);
+    const ZD* __restrict__ B = dmat(w, ib);
+    ZD* C = dmat(w, ic);
+    const ZD* D = dmat(w, id);
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     const int r = blockIdx.y * 16 + ty, c = blockIdx.x * 16 + tx;
     ZD acc = mk<double>(0, 0);
@@ -281,10 +300,13 @@ __global__ __launch_bounds__(kDB) void k_zgemm(DenseWork w0, SrcList L, int mode
     }
     if (r < k && c < k) {
         const size_t o = (size_t)r * k + c;
-        if (mode == 0) C[o] = acc;
-        else {
+        if (mode == 1) {
             const double mu = w.part[4 * w.npart_max];
             C[o] = 0.5 * (mu * C[o] - (1.0 / mu) * acc);
+        } else {
+            ZD v = a * acc;
+            if (b != 0.0) v = v + b * D[o];
+            C[o] = v;
         }
     }
 }
@@ -358,10 +380,45 @@ void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, con
     hipLaunchKernelGGL(k_dense_mu, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, nblk);
     if (grad) {
         dim3 g2(grid_for(kmax, 16), grid_for(kmax, 16), L.n);
-        hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w, L, 0);
-        hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w, L, 1);
+        hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w, L, kMXinv, kMY, kMZt, kMZt, 1.0, 0.0, 0);
+        hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w, L, kMZt, kMXinv, kMY, kMY, 0.0, 0.0, 1);
     }
     hipLaunchKernelGGL(k_dense_update, dim3(nblk, 1, L.n), dim3(kDB), 0, st, w, L);
+    hipLaunchKernelGGL(k_dense_delta, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, nblk);
+}
+
+// X <- Wk (the new iterate), Y <- Y2 if grad, partials of |X_new - X|^2 and |X_new|^2.
+__global__ __launch_bounds__(kDB) void k_ns_commit(DenseWork w0, SrcList L, int grad) {
+    const int e = blockIdx.z, k = L.k[e];
+    const DenseWork w = w0.at(L.slot[e]);
+    const int idx = blockIdx.x * kDB + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (idx < k * k) {
+        const ZD x = w.X[idx], xn = w.Wk[idx];
+        v[0] = norm2(xn - x);
+        v[1] = norm2(xn);
+        w.X[idx] = xn;
+        if (grad) w.Y[idx] = w.Y2[idx];
+    }
+    write_partials<2, kDB>(w.part, v);
+}
+
+void dense_ns_step(const SrcList& L, int grad, const DenseWork& w, hipStream_t st) {
+    const int kmax = L.k[0];
+    const dim3 g2(grid_for(kmax, 16), grid_for(kmax, 16), L.n);
+    auto gemm = [&](int ia, int ib, int ic, int id, double a, double b) {
+        hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w, L, ia, ib, ic, id, a, b, 0);
+    };
+    gemm(kMX, kMX, kMZt, kMZt, 1.0, 0.0);          // Q = X^2
+    gemm(kMX, kMZt, kMWk, kMX, -0.5, 1.5);         // X_new = 1.5 X - 0.5 X Q
+    if (grad) {
+        gemm(kMX, kMY, kMXinv, kMXinv, 1.0, 0.0);  // P = X Y
+        gemm(kMY, kMX, kMXinv, kMXinv, 1.0, 1.0);  // P += Y X
+        gemm(kMY, kMZt, kMY2, kMY, -0.5, 1.5);     // Y_new = 1.5 Y - 0.5 Y Q
+        gemm(kMX, kMXinv, kMY2, kMY2, -0.5, 1.0);  //       - 0.5 X P
+    }
+    const int nblk = grid_for(kmax * kmax, kDB);
+    hipLaunchKernelGGL(k_ns_commit, dim3(nblk, 1, L.n), dim3(kDB), 0, st, w, L, grad);
     hipLaunchKernelGGL(k_dense_delta, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, nblk);
 }
 

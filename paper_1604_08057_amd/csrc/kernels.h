@@ -162,6 +162,7 @@ struct DenseWork {
     ZD* Wk;       // in-place inversion workspace
     ZD* Xinv;     // inverse (columns un-permuted)
     ZD* Zt;       // GEMM temporary
+    ZD* Y2;       // second temporary (inverse-free steps with the Frechet block)
     int* rowperm; // [slot][2 kcap]: row permutation, then pivot rows
     double* part; // [slot][pstride]: update partials, scatter partials, mu
     double* delta;  // [slot][2]: |X_new - X|^2, |X_new|^2 of the last step
@@ -172,7 +173,7 @@ struct DenseWork {
     __host__ __device__ DenseWork at(int slot) const {
         DenseWork o = *this;
         const size_t d = (size_t)slot * kk;
-        o.X += d; o.Y += d; o.Wk += d; o.Xinv += d; o.Zt += d;
+        o.X += d; o.Y += d; o.Wk += d; o.Xinv += d; o.Zt += d; o.Y2 += d;
         o.rowperm += (size_t)slot * 2 * kcap;
         o.part += (size_t)slot * pstride;
         o.delta += (size_t)slot * 2;
@@ -189,6 +190,9 @@ void launch_dense_load(const ZD* T, const ZD* E, int k, const DenseWork& w, hipS
 // One Newton step X <- (mu X + X^{-1}/mu)/2 (and Y) for every entry; flag[e] = 1
 // turns the entry's norm scaling on.  Leaves delta[slot] for the host.
 void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, const DenseWork& w, hipStream_t st);
+// One inverse-free (Newton-Schulz) step X <- X (3 - X^2)/2 and, if grad, the
+// Frechet block Y <- [Y (3 - X^2) - X (X Y + Y X)]/2; leaves delta[slot].
+void dense_ns_step(const SrcList& L, int grad, const DenseWork& w, hipStream_t st);
 // c = X e_1, adjoint seeds from Y, S = |x| Re sum_j c_j h_j.
 void launch_dense_extract(Coef coef, const SrcList& L, int grad, const DenseWork& w, hipStream_t st);
 
