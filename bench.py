@@ -8,18 +8,26 @@ synthetic SU(3) links (spread 0.4) and Z2-complex sources resident in HBM.
 
 The JSON line carries:
 * value: sources/s of the FP64 path over the timed steps;
-* roofline: the dominant kernel's algorithmic bytes per launch over its mean
-  duration, timed with HIP events on the library stream during the timed steps;
+* roofline: the dominant stencil kernel's algorithmic bytes per launch over its
+  mean duration, timed with HIP events on the library stream during the timed
+  steps; traffic from the committed counter summary when it matches the kernel
+  source;
 * cpu_baseline: the CPU oracle (torch/NumPy float64; forward TSL + autograd
   gradient) on one source of the same workload, on the host cores;
-* mixed: the float32-stencil path on the same workload (sources/s, error vs FP64);
+* batched: the 6x18^3 batching workload (32 Z2 sources, k drawn from [100, 400],
+  mu = 0.5), all sources in one tslov_sign_grad_batched call (FP64), beside the
+  single-source FP64 path on the first four sources;
+* precision: the 14^4 workload (k = 400) single source, FP64, with the
+  float32-vector path's error against it;
+* mixed: the float32-vector path on the 8^4 workload (sources/s, errors vs FP64);
 * stencil_large: the FP64 Wilson stencil alone on a 32^4 lattice (1.15 GB per
   application, above the 256 MB last-level cache) for the HBM-bound figure.
+With --copy-probe a 1 GiB device-to-device copy runs first (HBM counter
+calibration for rocprofv3 --pmc).
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -32,35 +40,28 @@ METRIC = "sgn(H)ψ+dU-derivative sources/s, mixed vs FP64 @≤1e-6 rel; stencil 
 HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {0: "k_fwd_pair<double> (fused Lanczos stencil pair)",
                 1: "k_bwd_rb<double> (reverse-mode stencil pair)"}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_pair_8x8x8x8.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stencil_pair_8x8x8x8.txt")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("common.h", "fields.hip"):
-        with open(os.path.join(ROOT, "paper_1604_08057_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def read_traffic():
-    """HBM bytes per launch of the forward pair kernel from the committed counter summary,
-    or None if absent or taken on a different kernel source."""
+def read_traffic(which: int):
+    """HBM bytes per launch of the given stencil pair kernel (0 forward, 1 reverse) from
+    the committed counter summary, or None if absent or taken on a different kernel source."""
+    from paper_1604_08057_amd.traffic_summary import kernel_source_hash
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
     for line in open(TRAFFIC_FILE):
-        if ":" in line:
+        if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_launch" if which == 1 else "fwd_pair_hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -124,13 +125,108 @@ def stencil_large():
             "achieved_GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
 
 
+def rel_t(a, b):
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def batched_leg(ks_single: int = 4):
+    """32-source 6x18^3 workload in one batched FP64 call, and the single-source path."""
+    import numpy as np
+    import torch
+    from paper_1604_08057_amd import Context
+    from synthetic import workload
+    wl = workload(4)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")  # noqa: E731
+    U, psi, eta = dev(wl.links()), dev(wl.psi()), dev(wl.eta())
+    ks = [int(k) for k in wl.krylov_sizes()]
+    ctx = Context(wl.dims, wl.mass, wl.mu, precision="fp64")
+    ctx.set_links(U)
+    ctx.sign_grad_batched(eta[:2], psi[:2], ks[:2])          # workspace warm-up
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    ctx.timing_read(0)
+    ctx.timing_read(1)
+    t0 = time.perf_counter()
+    S, dU, _, infos = ctx.sign_grad_batched(eta, psi, ks)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n0, ms0 = ctx.timing_read(0)
+    n1, ms1 = ctx.timing_read(1)
+    ctx.timing_enable(False)
+    steps = sum(i.k_used for i in infos)
+    b0, b1 = ctx.kernel_bytes(0), ctx.kernel_bytes(1)
+    fwd_gbs = b0 * steps / (ms0 * 1e-3) / 1e9
+    bwd_gbs = b1 * sum(max(i.k_used - 1, 0) for i in infos) / (ms1 * 1e-3) / 1e9
+    dU0 = dU[0].clone()
+    del dU
+    t1 = time.perf_counter()
+    for s in range(ks_single):
+        Ss, dUs, _, _ = ctx.sign_grad(eta[s], psi[s], ks[s])
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t1
+    same = bool(torch.equal(dUs, dU0)) if ks_single == 1 else None
+    ctx.close()
+    return {"workload": "6x18^3 (V=34992), mu=0.5, link spread 0.35, 32 Z2 sources, k uniform in [100, 400]",
+            "sources": len(ks), "sum_k": int(sum(ks)), "precision": "fp64",
+            "sources_per_s": len(ks) / dt, "ms_per_call": dt * 1e3,
+            "single_source_sources_per_s": ks_single / dt1, "single_source_sample": ks_single,
+            "speedup_vs_single": (len(ks) / dt) / (ks_single / dt1),
+            "fwd_pair_GBs": fwd_gbs, "fwd_pair_frac": fwd_gbs / HBM_PEAK_GBS,
+            "bwd_pair_GBs": bwd_gbs, "bwd_pair_frac": bwd_gbs / HBM_PEAK_GBS,
+            "launches": {"fwd_pair": n0, "bwd_pair": n1}, "identical_to_single": same}
+
+
+def precision_leg():
+    """14^4 workload, k = 400: FP64 single source and the float32-vector path's error."""
+    import numpy as np
+    import torch
+    from paper_1604_08057_amd import Context
+    from synthetic import workload
+    wl = workload(3)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")  # noqa: E731
+    U, psi, eta = dev(wl.links()), dev(wl.psi()), dev(wl.eta())
+    out = {"workload": "14^4 (V=38416), mu=0.3, link spread 0.35, k=400, one Z2 source"}
+    res = {}
+    for prec in ("fp64", "mixed"):
+        ctx = Context(wl.dims, wl.mass, wl.mu, precision=prec)
+        ctx.set_links(U)
+        ctx.sign_grad(eta, psi, wl.k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S, dU, _, info = ctx.sign_grad(eta, psi, wl.k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        y, _ = ctx.sign(psi, wl.k)
+        res[prec] = (S, dU, y)
+        out[f"{prec}_sources_per_s"] = 1.0 / dt
+        out[f"{prec}_newton_iters"] = info.newton_iters
+        ctx.close()
+    S64, dU64, y64 = res["fp64"]
+    Sm, dUm, ym = res["mixed"]
+    out["mixed_rel_err"] = {"y": rel_t(ym, y64), "S": abs(Sm - S64) / abs(S64), "dU": rel_t(dUm, dU64)}
+    return out
+
+
+def copy_probe():
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"bench: copy probe of {n} bytes done (3 launches)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the mixed and 32^4 legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, precision, mixed and 32^4 legs")
+    ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the single-GPU path is what this "
@@ -142,6 +238,8 @@ def main():
     from paper_1604_08057_amd import Context
     from synthetic import workload
 
+    if args.copy_probe:
+        copy_probe()
     wl = workload(2)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")  # noqa: E731
     U, psi, eta = dev(wl.links()), dev(wl.psi()), dev(wl.eta())
@@ -158,7 +256,7 @@ def main():
     n, ms = (n0, ms0) if which == 0 else (n1, ms1)
     per_launch = ctx.kernel_bytes(which)
     achieved = per_launch / (ms / n * 1e-3) / 1e9
-    traffic = read_traffic() if which == 0 else None
+    traffic = read_traffic(which)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": KERNEL_NAMES[which],
                 "bytes_per_launch": per_launch, "launches": n, "mean_us": ms / n * 1e3}
@@ -182,12 +280,16 @@ def main():
         dtm, Sm, _ = time_steps(ctxm, eta, psi, wl.k, max(args.steps // 2, 1), 1, dUm)
         ym, _ = ctxm.sign(psi, wl.k)
         ctxm.close()
-        rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))  # noqa: E731
         out["mixed"] = {"sources_per_s": max(args.steps // 2, 1) / dtm, "precision": "float32 stencil and "
                         "vectors, float64 dots/coefficients/sign step/accumulation",
-                        "rel_err_y_vs_fp64": rel(ym, y64), "rel_err_dU_vs_fp64": rel(dUm, dU64),
+                        "rel_err_y_vs_fp64": rel_t(ym, y64), "rel_err_dU_vs_fp64": rel_t(dUm, dU64),
                         "rel_err_S_vs_fp64": abs(Sm - S) / abs(S)}
         log(f"bench: mixed {out['mixed']['sources_per_s']:.2f} sources/s")
+        out["batched"] = batched_leg()
+        log(f"bench: batched 6x18^3 {out['batched']['sources_per_s']:.2f} sources/s "
+            f"(single-source {out['batched']['single_source_sources_per_s']:.2f})")
+        out["precision"] = precision_leg()
+        log(f"bench: 14^4 fp64 {out['precision']['fp64_sources_per_s']:.2f} sources/s")
         out["stencil_large"] = stencil_large()
         log(f"bench: 32^4 stencil {out['stencil_large']['achieved_GBs']:.0f} GB/s")
 

@@ -1,0 +1,83 @@
+"""Turn two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) of ``bench.py --copy-probe``
+into the per-dispatch HBM traffic summary that bench.py reads.
+
+Each counter is scaled by what it reads for the probe's three 1 GiB device copies
+(the first three dispatches of each run).  Usage:
+    python -m paper_1604_08057_amd.traffic_summary FETCH.csv WRITE.csv OUT.txt
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PROBE_BYTES = 1 << 30
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("common.h", "fields.hip"):
+        with open(os.path.join(ROOT, "paper_1604_08057_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def main(fetch_csv: str, write_csv: str, out: str, volume: int = 4096):
+    F = list(csv.DictReader(open(fetch_csv)))
+    W = list(csv.DictReader(open(write_csv)))
+    probe = [(a, b) for a, b in zip(F, W) if "copyBuffer" in a["Kernel_Name"]][:3]
+    cf = statistics.mean(float(a["Counter_Value"]) for a, _ in probe)
+    cw = statistics.mean(float(b["Counter_Value"]) for _, b in probe)
+    ff, fw = PROBE_BYTES / 1024 / cf, PROBE_BYTES / 1024 / cw
+
+    def per(name, grid):
+        sel = [(a, b) for a, b in zip(F, W) if name in a["Kernel_Name"] and a["Grid_Size"] == grid]
+        return (len(sel), statistics.mean(float(a["Counter_Value"]) for a, _ in sel),
+                statistics.mean(float(b["Counter_Value"]) for _, b in sel))
+
+    V = volume
+    alg = {"k_fwd_pair<double>": V * (6 * 12 + 36) * 16, "k_bwd_rb<double, false>": V * (12 * 12 + 36) * 16,
+           "k_recur<double>": V * 8 * 12 * 16, "k_bwd_ra<double>": V * 10 * 12 * 16}
+    grids = {"k_fwd_pair<double>": str((V + 63) // 64 * 192), "k_bwd_rb<double, false>": str((V + 63) // 64 * 192),
+             "k_recur<double>": str((V + 255) // 256 * 256 * 12), "k_bwd_ra<double>": str((V + 255) // 256 * 256 * 12)}
+    lines = ["# HBM traffic per dispatch from rocprofv3 counters, 8^4 workload (V=4096, k=200, FP64)",
+             "#",
+             "# commands (repository root on the GPU box as $REPO), one counter per pass:",
+             "#   cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \\",
+             "#     \"k_fwd_pair|k_bwd_rb|k_apply|copy|k_recur|k_bwd_ra|k_force\" -f csv -d $REPO/gpurun_out/pmc_fetch"
+             " -o run -- \\",
+             "#     python3 $REPO/bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-probe",
+             "#   (the same with --pmc WRITE_SIZE into $REPO/gpurun_out/pmc_write), then",
+             "#   python -m paper_1604_08057_amd.traffic_summary pmc_fetch/run_counter_collection.csv \\",
+             "#     pmc_write/run_counter_collection.csv profiles/traffic_stencil_pair_8x8x8x8.txt",
+             "#",
+             f"# calibration: the probe's three 1 GiB device copies read FETCH_SIZE {cf:.1f} KiB and",
+             f"#   WRITE_SIZE {cw:.1f} KiB per dispatch: scale factors fetch x{ff:.4f}, write x{fw:.4f}",
+             "#",
+             "# kernel                       grid   dispatches  FETCH_KiB  WRITE_KiB  hbm_bytes(scaled)  algorithmic"]
+    res = {}
+    for name, grid in grids.items():
+        n, f, w = per(name, grid)
+        res[name] = (f * ff + w * fw) * 1024
+        lines.append(f"{name:28s} {grid:>7s} {n:10d} {f:10.1f} {w:10.1f} {res[name]:18.0f} {alg[name]:12d}")
+    try:
+        n, f, w = per("k_apply<double>", str(32 ** 4 // 64 * 192))
+        lines.append(f"{'k_apply<double> (32^4)':28s} {str(32 ** 4 // 64 * 192):>7s} {n:10d} {f:10.1f} {w:10.1f} "
+                     f"{(f * ff + w * fw) * 1024:18.0f} {32 ** 4 * 60 * 16:12d}")
+    except statistics.StatisticsError:
+        pass
+    lines += ["#", "# read by bench.py (the dominant stencil kernel of the timed 8^4 step):",
+              "kernel: k_bwd_rb<double, false>",
+              f"hbm_bytes_per_launch: {res['k_bwd_rb<double, false>']:.0f}",
+              f"fwd_pair_hbm_bytes_per_launch: {res['k_fwd_pair<double>']:.0f}",
+              f"kernel_source_sha256_16: {kernel_source_hash()}"]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main(*sys.argv[1:4])
