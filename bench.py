@@ -41,6 +41,9 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {0: "k_fwd_pair<double> (fused Lanczos stencil pair)",
                 1: "k_bwd_rb<double> (reverse-mode stencil pair)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stencil_pair_8x8x8x8.txt")
+# live kernel timing samples every 16th launch of a class: an event pair adds ~5 us
+# of dispatch latency, which on every launch would slow the timed step by ~25%
+TIMING_EVERY = 16
 
 
 def log(msg):
@@ -72,7 +75,7 @@ def time_steps(ctx, eta, psi, k, steps, warmup, dU, timing=False):
         ctx.sign_grad(eta, psi, k, dU=dU)
     torch.cuda.synchronize()
     if timing:
-        ctx.timing_enable(True)
+        ctx.timing_enable(TIMING_EVERY)
         ctx.timing_read(0)
         ctx.timing_read(1)
     t0 = time.perf_counter()
@@ -81,7 +84,7 @@ def time_steps(ctx, eta, psi, k, steps, warmup, dU, timing=False):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     if timing:
-        ctx.timing_enable(False)
+        ctx.timing_enable(0)
     return (t1 - t0), S, info
 
 
@@ -144,7 +147,7 @@ def batched_leg(ks_single: int = 4):
     ctx.set_links(U)
     ctx.sign_grad_batched(eta[:2], psi[:2], ks[:2])          # workspace warm-up
     torch.cuda.synchronize()
-    ctx.timing_enable(True)
+    ctx.timing_enable(1)      # batched launches are long: timing every one costs < 1%
     ctx.timing_read(0)
     ctx.timing_read(1)
     t0 = time.perf_counter()
@@ -153,7 +156,8 @@ def batched_leg(ks_single: int = 4):
     dt = time.perf_counter() - t0
     n0, ms0 = ctx.timing_read(0)
     n1, ms1 = ctx.timing_read(1)
-    ctx.timing_enable(False)
+    ctx.timing_enable(0)
+    # bytes per launch = per-source bytes x sources in the launch, summed over launches
     steps = sum(i.k_used for i in infos)
     b0, b1 = ctx.kernel_bytes(0), ctx.kernel_bytes(1)
     fwd_gbs = b0 * steps / (ms0 * 1e-3) / 1e9

@@ -199,14 +199,16 @@ tslov_status tslov_lanczos_matrix(tslov_ctx* ctx, const void* psi, int k, void* 
 tslov_status tslov_dense_sign(tslov_ctx* ctx, const void* T, int k, const void* E,
                               void* S_out, void* L_out, int* iters);
 
-/* Kernel timing for roofline measurement.  When enabled, the library records a
- * HIP event pair around every launch of the given kernel class on its stream.
+/* Kernel timing for roofline measurement.  With every = N >= 1 the library records
+ * a HIP event pair around every N-th launch of each kernel class on its stream
+ * (every = 0 turns timing off; each pair adds a few microseconds of dispatch
+ * latency to the stream, so a sparse sample perturbs the timed work least).
  *   which = 0: forward Lanczos stencil pair (the dominant kernel)
  *   which = 1: backward stencil pair
  *   which = 2: plain operator application (tslov_apply_dw / tslov_apply_h)
- * tslov_timing_read synchronises the stream and returns the number of recorded
+ * tslov_timing_read synchronises the stream and returns the number of timed
  * launches and their summed duration, then clears the record. */
-tslov_status tslov_timing_enable(tslov_ctx* ctx, int enable);
+tslov_status tslov_timing_enable(tslov_ctx* ctx, int every);
 tslov_status tslov_timing_read(tslov_ctx* ctx, int which, int* count, double* total_ms);
 
 /* Algorithmic bytes moved by one launch of kernel class `which` (see above) for

@@ -111,7 +111,8 @@ struct tslov_ctx {
     int slots = 0, kcap = 0, grad_cap = 0;   // shape of the batch workspace
     int dslots = 0, dkcap = 0;               // shape of the dense workspace
     Coef coef{};
-    int timing = 0;
+    int timing = 0;            // 0 off, N: time every N-th launch of each class
+    long long tcount[kTimingClasses] = {0, 0, 0};
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[kTimingClasses];
 
@@ -125,17 +126,22 @@ struct tslov_ctx {
 namespace {
 
 // ---------------------------------------------------------------- timing
+// Event pair for one launch of a timing class, recorded by the launch's own
+// dispatch (hipExtLaunchKernel), or none when timing is off or the launch is not
+// in the sample.
 struct TimedLaunch {
-    tslov_ctx* c;
-    int cls;
-    hipEvent_t a = nullptr, b = nullptr;
-    TimedLaunch(tslov_ctx* ctx, int which) : c(ctx), cls(which) {
+    tslov::Timing t;
+    TimedLaunch(tslov_ctx* c, int cls) {
         if (!c->timing) return;
-        a = take();
-        b = take();
-        if (a && b) (void)hipEventRecord(a, c->st);
+        // every c->timing-th launch of the class
+        if (c->tcount[cls]++ % c->timing != 0) return;
+        hipEvent_t a = take(c), b = take(c);
+        if (!a || !b) return;
+        t.a = a;
+        t.b = b;
+        c->ev_used[cls].push_back({a, b});
     }
-    hipEvent_t take() {
+    static hipEvent_t take(tslov_ctx* c) {
         if (c->ev_free.empty()) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) return nullptr;
@@ -144,11 +150,6 @@ struct TimedLaunch {
         hipEvent_t e = c->ev_free.back();
         c->ev_free.pop_back();
         return e;
-    }
-    ~TimedLaunch() {
-        if (!c->timing || !a || !b) return;
-        (void)hipEventRecord(b, c->st);
-        c->ev_used[cls].push_back({a, b});
     }
 };
 
@@ -328,10 +329,7 @@ tslov_status forward(tslov_ctx* c, const SrcList& L, const ZD* psi, const ZD* et
     for (int j = 1; j <= kmax; ++j) {
         while (n > 0 && L.k[n - 1] < j) --n;
         const SrcList Lj = prefix(L, n);
-        {
-            TimedLaunch tl(c, 0);
-            tslov::launch_fwd_pair<R>(U, g, c->kappa, c->mu, wk, Lj, c->coef, j, eta ? 1 : 0, c->st);
-        }
+        tslov::launch_fwd_pair<R>(U, g, c->kappa, c->mu, wk, Lj, c->coef, j, eta ? 1 : 0, c->st, TimedLaunch(c, 0).t);
         tslov::launch_recur<R>(g, wk, Lj, c->coef, j, c->st);
     }
     HIPCHK(hipGetLastError());
@@ -489,8 +487,7 @@ tslov_status backward(tslov_ctx* c, const SrcList& L, GradOut& out) {
         if (nlt > 0) {
             const SrcList Llt = prefix(L, nlt);
             tslov::launch_bwd_ra<R>(g, wk, Llt, c->coef, j, c->st);
-            TimedLaunch tl(c, 1);
-            tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, wk, Llt, c->coef, j, 0, c->st);
+            tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, wk, Llt, c->coef, j, 0, c->st, TimedLaunch(c, 1).t);
         }
         if (neq_end > nlt) {
             const SrcList Leq = range(L, nlt, neq_end);
@@ -944,19 +941,15 @@ static tslov_status apply_op(tslov_ctx* c, const void* in, void* out, double mu,
         Z<float>* a = c->opf.as<Z<float>>();
         Z<float>* b = a + c->field_elems();
         tslov::launch_spinor_to_soa<float>((const ZD*)in, a, c->g, nullptr, c->st);
-        {
-            TimedLaunch tl(c, 2);
-            tslov::launch_apply<float>(c->U32.as<Z<float>>(), a, b, c->g, c->kappa, mu, g5in, g5out, c->st);
-        }
+        tslov::launch_apply<float>(c->U32.as<Z<float>>(), a, b, c->g, c->kappa, mu, g5in, g5out, c->st,
+                                   TimedLaunch(c, 2).t);
         tslov::launch_spinor_from_soa<float>(b, (ZD*)out, c->g, c->st);
     } else {
         ZD* a = c->opf.as<ZD>();
         ZD* b = a + c->field_elems();
         tslov::launch_spinor_to_soa<double>((const ZD*)in, a, c->g, nullptr, c->st);
-        {
-            TimedLaunch tl(c, 2);
-            tslov::launch_apply<double>(c->U64.as<ZD>(), a, b, c->g, c->kappa, mu, g5in, g5out, c->st);
-        }
+        tslov::launch_apply<double>(c->U64.as<ZD>(), a, b, c->g, c->kappa, mu, g5in, g5out, c->st,
+                                    TimedLaunch(c, 2).t);
         tslov::launch_spinor_from_soa<double>(b, (ZD*)out, c->g, c->st);
     }
     HIPCHK(hipGetLastError());
@@ -1137,9 +1130,11 @@ tslov_status tslov_dense_sign(tslov_ctx* c, const void* T, int k, const void* E,
     return TSLOV_OK;
 }
 
-tslov_status tslov_timing_enable(tslov_ctx* c, int enable) {
+tslov_status tslov_timing_enable(tslov_ctx* c, int every) {
     if (!c) return fail(TSLOV_ERR_ARG, "null context");
-    c->timing = enable ? 1 : 0;
+    if (every < 0) return fail(TSLOV_ERR_ARG, "every must be >= 0");
+    c->timing = every;
+    for (auto& n : c->tcount) n = 0;
     return TSLOV_OK;
 }
 

@@ -10,6 +10,13 @@ namespace tslov {
 
 namespace {
 
+// Launch with the timing events recorded by the dispatch itself when given.
+template <typename K, typename... Args>
+void timed_launch(K kernel, dim3 grid, dim3 block, hipStream_t st, Timing t, Args... args) {
+    if (t.a && t.b) hipExtLaunchKernelGGL(kernel, grid, block, 0, st, t.a, t.b, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
+
 // Block-uniform read of a device flag written by other blocks or launches.
 __device__ __forceinline__ int block_flag(const int* p) {
     __shared__ int f;
@@ -226,9 +233,9 @@ __global__ __launch_bounds__(kCBlock) void k_apply(const Z<R>* __restrict__ U, c
 
 template <typename R>
 void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu, int g5_in,
-                  int g5_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_apply<R>, dim3(np_stencil(g.V)), dim3(kCBlock), 0, st, U, in, out, g, (R)kappa,
-                       (R)std::exp(mu), (R)std::exp(-mu), g5_in, g5_out);
+                  int g5_out, hipStream_t st, Timing t) {
+    timed_launch(k_apply<R>, dim3(np_stencil(g.V)), dim3(kCBlock), st, t, U, in, out, g, (R)kappa, (R)std::exp(mu),
+                 (R)std::exp(-mu), g5_in, g5_out);
 }
 
 // =============================================================== batched sources
@@ -376,10 +383,10 @@ __global__ __launch_bounds__(kCBlock) void k_fwd_pair(const Z<R>* __restrict__ U
 
 template <typename R>
 void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
-                     Coef coef, int j, int has_eta, hipStream_t st) {
+                     Coef coef, int j, int has_eta, hipStream_t st, Timing t) {
     const int npart_in = j == 1 ? grid_for(g.V) : np_point(g.V);
-    hipLaunchKernelGGL(k_fwd_pair<R>, dim3(np_stencil(g.V), L.n), dim3(kCBlock), 0, st, U, g, kappa, std::exp(mu),
-                       wk, L, coef, j, npart_in, has_eta);
+    timed_launch(k_fwd_pair<R>, dim3(np_stencil(g.V), L.n), dim3(kCBlock), st, t, U, g, kappa, std::exp(mu), wk, L,
+                 coef, j, npart_in, has_eta);
 }
 
 // r = a - alpha_j v_j - gamma_j v_{j-1},  s = b - conj(alpha_j) w_j - beta_j w_{j-1},
@@ -647,14 +654,14 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb(const Z<R>* __restrict__ U, 
 
 template <typename R>
 void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
-                   Coef coef, int j, int last, hipStream_t st) {
+                   Coef coef, int j, int last, hipStream_t st, Timing t) {
     const dim3 grid(np_stencil(g.V), L.n);
     if (last)
-        hipLaunchKernelGGL((k_bwd_rb<R, true>), grid, dim3(kCBlock), 0, st, U, g, kappa, std::exp(mu), wk, L, coef,
-                           j, np_point(g.V));
+        timed_launch(k_bwd_rb<R, true>, grid, dim3(kCBlock), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
+                     np_point(g.V));
     else
-        hipLaunchKernelGGL((k_bwd_rb<R, false>), grid, dim3(kCBlock), 0, st, U, g, kappa, std::exp(mu), wk, L, coef,
-                           j, np_point(g.V));
+        timed_launch(k_bwd_rb<R, false>, grid, dim3(kCBlock), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
+                     np_point(g.V));
 }
 
 // =============================================================== force contraction
@@ -938,17 +945,17 @@ void launch_source_grad(const Geom& g, const Work<R>& wk, const SrcList& L, Coef
     template void launch_spinor_to_soa<R>(const ZD*, Z<R>*, const Geom&, double*, hipStream_t);                 \
     template void launch_spinor_from_soa<R>(const Z<R>*, ZD*, const Geom&, hipStream_t);                        \
     template void launch_apply<R>(const Z<R>*, const Z<R>*, Z<R>*, const Geom&, double, double, int, int,       \
-                                  hipStream_t);                                                                 \
+                                  hipStream_t, Timing);                                                         \
     template void launch_sources_to_soa<R>(const ZD*, int, int, const Work<R>&, const SrcList&, const Geom&,    \
                                            hipStream_t);                                                        \
     template void launch_fwd_pair<R>(const Z<R>*, const Geom&, double, double, const Work<R>&, const SrcList&,  \
-                                     Coef, int, int, hipStream_t);                                              \
+                                     Coef, int, int, hipStream_t, Timing);                                      \
     template void launch_recur<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);         \
     template void launch_assemble<R>(const Geom&, const Work<R>&, const SrcList&, Coef, const ZD*, int, ZD*,    \
                                      hipStream_t);                                                              \
     template void launch_bwd_ra<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);        \
     template void launch_bwd_rb<R>(const Z<R>*, const Geom&, double, double, const Work<R>&, const SrcList&,    \
-                                   Coef, int, int, hipStream_t);                                                \
+                                   Coef, int, int, hipStream_t, Timing);                                        \
     template void launch_force<R>(const Geom&, double, double, const Work<R>&, const SrcList&, int, ZD*,        \
                                   hipStream_t);                                                                 \
     template void launch_source_grad<R>(const Geom&, const Work<R>&, const SrcList&, Coef, ZD*, hipStream_t);

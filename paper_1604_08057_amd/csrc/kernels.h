@@ -8,6 +8,12 @@ namespace tslov {
 
 inline int grid_for(int n, int blk = kBlock) { return (n + blk - 1) / blk; }
 
+// Optional event pair recorded by the dispatch of one launch (kernel timing).
+struct Timing {
+    hipEvent_t a = nullptr;
+    hipEvent_t b = nullptr;
+};
+
 // ---------------------------------------------------------------- layout
 void launch_links_to_soa(const ZD* Ucanon, ZD* U64, Z<float>* U32, const Geom& g, int antiperiodic,
                          hipStream_t st);
@@ -20,7 +26,7 @@ void launch_spinor_from_soa(const Z<R>* in, ZD* out, const Geom& g, hipStream_t 
 // out = G5out * (G5in in - kappa * hop_{mu}(G5in in))
 template <typename R>
 void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu,
-                  int g5_in, int g5_out, hipStream_t st);
+                  int g5_in, int g5_out, hipStream_t st, Timing t = {});
 
 // ---------------------------------------------------------------- batch workspace
 // Per-source lattice fields of a batch in the working precision.  Sources sit in
@@ -67,7 +73,7 @@ void launch_sources_to_soa(const ZD* canon, int which, int g5, const Work<R>& wk
 // Step j of the Lanczos process for every list entry (k[e] = the entry's target size).
 template <typename R>
 void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
-                     Coef coef, int j, int has_eta, hipStream_t st);
+                     Coef coef, int j, int has_eta, hipStream_t st, Timing t = {});
 template <typename R>
 void launch_recur(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st);
 // out[src] (canonical) = [psi[src] +] g5^{overlap} |x| sum_j c_j v_j
@@ -85,7 +91,7 @@ template <typename R>
 void launch_bwd_ra(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st);
 template <typename R>
 void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
-                   Coef coef, int j, int last, hipStream_t st);
+                   Coef coef, int j, int last, hipStream_t st, Timing t = {});
 // Per-link force partials gpart[slot][chunk][36 planes] over all steps of each entry.
 template <typename R>
 void launch_force(const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L, int nchunk, ZD* gpart,

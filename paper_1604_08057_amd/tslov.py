@@ -288,8 +288,9 @@ class Context:
                                                    ctypes.byref(it)))
         return S, L, it.value
 
-    def timing_enable(self, on: bool = True):
-        _check(self.lib, self.lib.tslov_timing_enable(self.handle, int(on)))
+    def timing_enable(self, every: int = 1):
+        """Time every `every`-th launch of each kernel class (0 or False: off)."""
+        _check(self.lib, self.lib.tslov_timing_enable(self.handle, int(every)))
 
     def timing_read(self, which: int):
         n = ctypes.c_int()
