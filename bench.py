@@ -145,7 +145,9 @@ def batched_leg(ks_single: int = 4):
     ks = [int(k) for k in wl.krylov_sizes()]
     ctx = Context(wl.dims, wl.mass, wl.mu, precision="fp64")
     ctx.set_links(U)
-    ctx.sign_grad_batched(eta[:2], psi[:2], ks[:2])          # workspace warm-up
+    # warm-up with the full batch: the workspace (about 16 GB per source at k = 400)
+    # is allocated here, outside the timed call
+    ctx.sign_grad_batched(eta, psi, ks)
     torch.cuda.synchronize()
     ctx.timing_enable(1)      # batched launches are long: timing every one costs < 1%
     ctx.timing_read(0)
