@@ -15,10 +15,25 @@ constexpr int kSites = 64;     // sites per block of the colour-split stencil ke
 constexpr int kCBlock = 3 * kSites;   // one wavefront per colour
 constexpr int kPBlock = 256;   // pointwise kernels: sites per block, grid.y = 12 planes
 
+constexpr int kXcd = 8;        // accelerator complex dies; workgroups go to them round robin
+
 // Number of per-block partial sums written by each kernel family.
 __host__ __device__ inline int np_stencil(int V) { return (V + kSites - 1) / kSites; }
 __host__ __device__ inline int np_point(int V) { return 12 * ((V + kPBlock - 1) / kPBlock); }
-__host__ __device__ inline int np_max(int V) { return np_stencil(V) > np_point(V) ? np_stencil(V) : np_point(V); }
+// Colour-grid stencil kernels: one single-wavefront block per (colour, 64 sites),
+// colour-major, the site blocks padded to a multiple of the XCD count so that the
+// three colours of a site block run on one XCD and share its L2.
+__host__ __device__ inline int nsb_pad(int V) { return (np_stencil(V) + kXcd - 1) / kXcd * kXcd; }
+__host__ __device__ inline int np_colour(int V) { return 3 * nsb_pad(V); }
+__host__ __device__ inline int np_max(int V) { return np_colour(V) > np_point(V) ? np_colour(V) : np_point(V); }
+// Layout of the stencil kernels, a function of the lattice alone (so that a source
+// gives the same bits in any batch): the colour grid while the lattice has too few
+// site blocks to occupy the chip with three-wavefront blocks, the colour-split
+// blocks (kCBlock threads, colour = wavefront) above that.
+constexpr int kColourGridMaxBlocks = 128;
+__host__ __device__ inline bool colour_grid(int V) { return np_stencil(V) <= kColourGridMaxBlocks; }
+// Blocks (= partial sums) of one stencil launch per source.
+__host__ __device__ inline int np_sten(int V) { return colour_grid(V) ? np_colour(V) : np_stencil(V); }
 
 // ------------------------------------------------------------------ complex
 template <typename R>
@@ -311,6 +326,20 @@ __device__ __forceinline__ void load_col_conj(Z<R> (&u)[3], const Z<R>* __restri
 // Colour handled by this thread in the colour-split kernels: one wavefront per
 // colour, made explicit as a scalar so plane addresses stay uniform.
 __device__ __forceinline__ int wave_colour() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kSites); }
+
+// Colour and site of this thread in a stencil kernel of BLK threads per block:
+// BLK = kSites is the colour grid (grid.x = np_colour, colour-major), BLK = kCBlock
+// the colour split (grid.x = np_stencil, colour = wavefront).
+template <int BLK>
+__device__ __forceinline__ int sten_colour() {
+    if (BLK == kSites) return blockIdx.x / (gridDim.x / 3);
+    return wave_colour();
+}
+template <int BLK>
+__device__ __forceinline__ int sten_site(int a) {
+    if (BLK == kSites) return (blockIdx.x - a * (gridDim.x / 3)) * kSites + threadIdx.x;
+    return blockIdx.x * kSites + threadIdx.x % kSites;
+}
 
 // ------------------------------------------------------------------ force contraction
 template <typename R>

@@ -171,6 +171,160 @@ __global__ __launch_bounds__(kDB) void k_gj_panel(DenseWork w0, SrcList L, int c
     }
 }
 
+// Register-resident panel for k <= BLK: the same elimination as k_gj_panel, with
+// thread i of a BLK-thread block holding row i of the panel in registers.  One
+// block barrier per pivot: before it, each wavefront publishes its best candidate
+// row (largest |P[i][q]|^2, smallest index on ties) and the owner of row p publishes
+// the old row p, in LDS slots that alternate between even and odd pivots; after it,
+// every thread picks the block's pivot from the candidates and updates its own row
+// as row - (f / P[imax][q]) P[imax].  The row swap needs no data movement beyond
+// the published old row p, which the owner of row imax takes over.  The pivot is
+// the unique maximum under that order, so the result does not depend on BLK.
+template <int CTRL>
+__device__ __forceinline__ void dpp_argmax_step(double& v, int& i) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xf, 0xf, false);
+    const double ov = __hiloint2double(hi, lo);
+    if (ov > v || (ov == v && oi < i)) {
+        v = ov;
+        i = oi;
+    }
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Largest v over the wavefront (smallest i among equal v), returned in every lane.
+// Rows of 16 lanes combine through DPP (swap within pairs, within quads, mirror
+// within halves of 8, mirror within 16); the four rows through lane reads.
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+    dpp_argmax_step<0xB1>(v, i);    // quad_perm [1, 0, 3, 2]
+    dpp_argmax_step<0x4E>(v, i);    // quad_perm [2, 3, 0, 1]
+    dpp_argmax_step<0x141>(v, i);   // row_half_mirror
+    dpp_argmax_step<0x140>(v, i);   // row_mirror
+    double bv = readlane_d(v, 0);
+    int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+    for (int r = 16; r < kWave; r += 16) {
+        const double ov = readlane_d(v, r);
+        const int oi = __builtin_amdgcn_readlane(i, r);
+        if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    v = bv;
+    i = bi;
+}
+
+constexpr int kGjRegMax = 512;   // largest k served by the register-resident panel
+
+template <int NB, int BLK>
+__global__ __launch_bounds__(BLK) void k_gj_panel_reg(DenseWork w0, SrcList L, int c0) {
+    constexpr int kNW = BLK / kWave;
+    __shared__ ZD cand[2][kNW][NB];
+    __shared__ double cval[2][kNW];
+    __shared__ int cidx[2][kNW];
+    __shared__ ZD rowp[2][NB];
+    __shared__ int perm[BLK];
+    __shared__ int piv_s[NB];
+    const int e = blockIdx.z, k = L.k[e];
+    if (c0 >= k) return;
+    const DenseWork w = w0.at(L.slot[e]);
+    ZD* __restrict__ Wk = w.Wk;
+    int* __restrict__ rowperm = w.rowperm;
+    int* __restrict__ ipiv = w.rowperm + w.kcap;
+    const int i = threadIdx.x, wave = i / kWave, lane = i % kWave;
+    const bool mine = i < k;   // this thread holds row i
+    const int nbK = min(NB, k - c0);
+    if (mine) perm[i] = rowperm[i];
+    ZD row[NB];
+#pragma unroll
+    for (int qq = 0; qq < NB; ++qq) row[qq] = (mine && qq < nbK) ? Wk[(size_t)i * k + c0 + qq] : mk<double>(0, 0);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        if (q < nbK) {   // uniform; the loop unrolls fully so that row[q] stays in registers
+            const int p = c0 + q, b = q & 1;
+            const double m = norm2(row[q]);
+            double best = (mine && i >= p && m >= 0.0) ? m : -1.0;   // a NaN entry is never a candidate
+            int bi = best >= 0.0 ? i : k;
+            wave_argmax(best, bi);
+            if (lane == 0) {
+                cval[b][wave] = best;
+                cidx[b][wave] = bi;
+            }
+            if (i == bi)
+#pragma unroll
+                for (int qq = 0; qq < NB; ++qq) cand[b][wave][qq] = row[qq];
+            if (i == p)
+#pragma unroll
+                for (int qq = 0; qq < NB; ++qq) rowp[b][qq] = row[qq];
+            __syncthreads();
+            // all candidates in one round of LDS reads, then a branch-free choice
+            double cv[kNW];
+            int ci[kNW];
+#pragma unroll
+            for (int v = 0; v < kNW; ++v) {
+                cv[v] = cval[b][v];
+                ci[v] = cidx[b][v];
+            }
+            double bv = cv[0];
+            int imax = ci[0], wwin = 0;
+#pragma unroll
+            for (int v = 1; v < kNW; ++v) {
+                const bool t = cv[v] > bv || (cv[v] == bv && ci[v] < imax);
+                bv = t ? cv[v] : bv;
+                imax = t ? ci[v] : imax;
+                wwin = t ? v : wwin;
+            }
+            const bool valid = imax >= p && imax < k;   // else a non-finite column: keep the order
+            if (!valid) imax = p;
+            const ZD* __restrict__ src = valid ? &cand[b][wwin][0] : &rowp[b][0];
+            const ZD inv = zdiv(mk<double>(1.0, 0.0), src[q]);
+            ZD piv[NB];
+#pragma unroll
+            for (int qq = 0; qq < NB; ++qq) piv[qq] = src[qq];
+            if (i == 0) piv_s[q] = imax;
+            if (i == p) {
+#pragma unroll
+                for (int qq = 0; qq < NB; ++qq) row[qq] = piv[qq] * inv;
+                row[q] = inv;
+            } else if (mine) {
+                if (i == imax)
+#pragma unroll
+                    for (int qq = 0; qq < NB; ++qq) row[qq] = rowp[b][qq];
+                const ZD f = row[q] * inv;
+#pragma unroll
+                for (int qq = 0; qq < NB; ++qq) row[qq] = row[qq] - f * piv[qq];
+                row[q] = -f;
+            }
+        }
+    }
+    __syncthreads();
+    if (i == 0)
+        for (int q = 0; q < nbK; ++q) {
+            const int p = c0 + q, im = piv_s[q];
+            ipiv[p] = im;
+            if (im != p) {
+                const int t = perm[p];
+                perm[p] = perm[im];
+                perm[im] = t;
+            }
+        }
+    if (mine)
+#pragma unroll
+        for (int qq = 0; qq < NB; ++qq)
+            if (qq < nbK) Wk[(size_t)i * k + c0 + qq] = row[qq];
+    __syncthreads();
+    if (mine) rowperm[i] = perm[i];
+}
+
 // Apply panel K's row swaps and transform to TC columns outside the panel:
 // x <- swaps(x);  x_new[i] = [i outside panel] x[i] + sum_q P[i][q] x[c0 + q].
 // Thread t owns rows i = t, t + 256, ... of the block's TC columns.
@@ -341,13 +495,41 @@ __global__ __launch_bounds__(kDB) void k_dense_delta(DenseWork w0, SrcList L, in
     }
 }
 
+// Panel launches for the active entries (sorted by decreasing k): entries with
+// k > kGjRegMax use the LDS panel, the rest the register-resident one (whose result
+// does not depend on how many rows each thread holds).
+template <int NB>
+void launch_panels(const SrcList& act, int c0, size_t panel_lds, const DenseWork& w, hipStream_t st) {
+    int m = 0;
+    while (m < act.n && act.k[m] > kGjRegMax) ++m;
+    if (m > 0) {
+        SrcList big = act;
+        big.n = m;
+        hipLaunchKernelGGL(k_gj_panel<NB>, dim3(1, 1, m), dim3(kDB), panel_lds, st, w, big, c0);
+    }
+    if (m < act.n) {
+        SrcList small{};
+        small.n = act.n - m;
+        for (int e = 0; e < small.n; ++e) {
+            small.slot[e] = act.slot[m + e];
+            small.src[e] = act.src[m + e];
+            small.k[e] = act.k[m + e];
+            small.flag[e] = act.flag[m + e];
+        }
+        if (small.k[0] > kDB)
+            hipLaunchKernelGGL((k_gj_panel_reg<NB, 2 * kDB>), dim3(1, 1, small.n), dim3(2 * kDB), 0, st, w, small, c0);
+        else
+            hipLaunchKernelGGL((k_gj_panel_reg<NB, kDB>), dim3(1, 1, small.n), dim3(kDB), 0, st, w, small, c0);
+    }
+}
+
 template <int NB>
 void gj_sweep(const SrcList& L, int TC, size_t panel_lds, const DenseWork& w, hipStream_t st) {
     const int kmax = L.k[0];
     SrcList act = L;
     for (int c0 = 0; c0 < kmax; c0 += NB) {
         while (act.n > 0 && act.k[act.n - 1] <= c0) --act.n;   // entries sorted by decreasing k
-        hipLaunchKernelGGL(k_gj_panel<NB>, dim3(1, 1, act.n), dim3(kDB), panel_lds, st, w, act, c0);
+        launch_panels<NB>(act, c0, panel_lds, w, st);
         const int nbK = (kmax - c0) < NB ? (kmax - c0) : NB;
         const int nother = kmax - nbK;
         if (nother > 0) {

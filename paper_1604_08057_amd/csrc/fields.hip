@@ -133,14 +133,12 @@ void launch_spinor_from_soa(const Z<R>* in, ZD* out, const Geom& g, hipStream_t 
     hipLaunchKernelGGL(k_spinor_from_soa<R>, dim3(grid_for(g.V)), dim3(kBlock), 0, st, in, out, g);
 }
 
-// =============================================================== colour-split stencil
-// Blocks of 3 wavefronts: wavefront a handles colour a of 64 consecutive sites, so
-// every load instruction of a wavefront touches 64 consecutive sites of one plane.
-template <typename R>
-struct Spin1 {
-    Z<R> c[4];   // the four spin components of one colour
-};
-
+// =============================================================== stencil layouts
+// One thread per (site, colour), 64 consecutive sites per wavefront, so that every
+// load instruction touches 64 consecutive sites of one plane.  Colour split: blocks
+// of 3 wavefronts, wavefront a handles colour a.  Colour grid (small lattices):
+// single-wavefront blocks, block (a, b) handles colour a of site block b, which
+// spreads the three colours of a site over three compute units.
 template <typename R>
 __device__ __forceinline__ void load1(Z<R> (&p)[4], const Z<R>* __restrict__ f, int ldv, int a, int s) {
 #pragma unroll
@@ -197,28 +195,113 @@ __device__ __forceinline__ void hop_dir_pair1(Z<R> (&acca)[4], Z<R> (&accb)[4], 
     hop1<NU, -1>(accb, u, p, up);
 }
 
+// The same two directions' worth of hops with every load of the direction issued
+// before any arithmetic (the compiler barrier keeps the scheduler from sinking the
+// loads to their uses): one memory round trip per direction instead of one per
+// loaded operand, at the cost of holding all operands of a direction in registers.
+template <int NU, typename R>
+__device__ __forceinline__ void hop_dir1_eager(Z<R> (&acc)[4], const Z<R>* __restrict__ U,
+                                               const Z<R>* __restrict__ f, const Geom& g, int s, int a, const Nbr& n,
+                                               R cf, R cb, int g5_in) {
+    Z<R> uf[3], ub[3];
+    Spinor<R> pf, pb;
+    load_row(uf, U, g.ldv, NU, a, s);
+    load_spinor(pf, f, g.ldv, n.fwd[NU]);
+    load_col_conj(ub, U, g.ldv, NU, a, n.bwd[NU]);
+    load_spinor(pb, f, g.ldv, n.bwd[NU]);
+    mem_fence_compiler();
+    if (g5_in) {
+        g5_inplace(pf);
+        g5_inplace(pb);
+    }
+    hop1<NU, +1>(acc, uf, pf, cf);
+    hop1<NU, -1>(acc, ub, pb, cb);
+}
+
+template <int NU, typename R>
+__device__ __forceinline__ void hop_dir_pair1_eager(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
+                                                    const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
+                                                    const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
+    const R up = (NU == 3) ? ep : R(1), dn = (NU == 3) ? em : R(1);
+    Z<R> uf[3], ub[3];
+    Spinor<R> paf, pbf, pab, pbb;
+    load_row(uf, U, g.ldv, NU, a, s);
+    load_spinor(paf, fa, g.ldv, n.fwd[NU]);
+    load_spinor(pbf, fb, g.ldv, n.fwd[NU]);
+    load_col_conj(ub, U, g.ldv, NU, a, n.bwd[NU]);
+    load_spinor(pab, fa, g.ldv, n.bwd[NU]);
+    load_spinor(pbb, fb, g.ldv, n.bwd[NU]);
+    mem_fence_compiler();
+    hop1<NU, +1>(acca, uf, paf, up);
+    hop1<NU, +1>(accb, uf, pbf, dn);
+    hop1<NU, -1>(acca, ub, pab, dn);
+    hop1<NU, -1>(accb, ub, pbb, up);
+}
+
+// All eight hops of one field (colour a), a rolled loop over a wavefront-uniform
+// switch.  Colour split (several wavefronts per SIMD): one operand's loads in
+// flight at a time, few registers.  Colour grid (small lattices, where a wavefront
+// has its SIMD to itself): a whole direction's loads in flight at a time.
+template <int BLK, typename R>
+__device__ __forceinline__ void hop_all1(Z<R> (&acc)[4], const Z<R>* __restrict__ U, const Z<R>* __restrict__ f,
+                                         const Geom& g, int s, int a, const Nbr& n, R ep, R em, int g5_in) {
+#pragma unroll 1
+    for (int nu = 0; nu < 4; ++nu) {
+        if constexpr (BLK == kSites) {
+            switch (nu) {
+                case 0: hop_dir1_eager<0>(acc, U, f, g, s, a, n, R(1), R(1), g5_in); break;
+                case 1: hop_dir1_eager<1>(acc, U, f, g, s, a, n, R(1), R(1), g5_in); break;
+                case 2: hop_dir1_eager<2>(acc, U, f, g, s, a, n, R(1), R(1), g5_in); break;
+                default: hop_dir1_eager<3>(acc, U, f, g, s, a, n, ep, em, g5_in); break;
+            }
+        } else {
+            switch (nu) {
+                case 0: hop_dir1<0>(acc, U, f, g, s, a, n, R(1), R(1), g5_in); break;
+                case 1: hop_dir1<1>(acc, U, f, g, s, a, n, R(1), R(1), g5_in); break;
+                case 2: hop_dir1<2>(acc, U, f, g, s, a, n, R(1), R(1), g5_in); break;
+                default: hop_dir1<3>(acc, U, f, g, s, a, n, ep, em, g5_in); break;
+            }
+        }
+    }
+}
+
+// Same for two fields sharing the link rows (A at +mu, B at -mu).
+template <int BLK, typename R>
+__device__ __forceinline__ void hop_all_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
+                                             const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
+                                             const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
+#pragma unroll 1
+    for (int nu = 0; nu < 4; ++nu) {
+        if constexpr (BLK == kSites) {
+            switch (nu) {
+                case 0: hop_dir_pair1_eager<0>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
+                case 1: hop_dir_pair1_eager<1>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
+                case 2: hop_dir_pair1_eager<2>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
+                default: hop_dir_pair1_eager<3>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
+            }
+        } else {
+            switch (nu) {
+                case 0: hop_dir_pair1<0>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
+                case 1: hop_dir_pair1<1>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
+                case 2: hop_dir_pair1<2>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
+                default: hop_dir_pair1<3>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
+            }
+        }
+    }
+}
+
 // =============================================================== operator
-template <typename R>
-__global__ __launch_bounds__(kCBlock) void k_apply(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
-                                                   Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em, int g5_in,
-                                                   int g5_out) {
-    const int a = wave_colour();
-    const int s = blockIdx.x * kSites + threadIdx.x % kSites;
+template <typename R, int BLK>
+__global__ __launch_bounds__(BLK) void k_apply(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+                                               Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em, int g5_in,
+                                               int g5_out) {
+    const int a = sten_colour<BLK>();
+    const int s = sten_site<BLK>(a);
     if (s >= g.V) return;
     const Nbr n = neighbours(g, s);
     Z<R> acc[4];
     zero1(acc);
-    // A rolled loop over a wavefront-uniform switch keeps one direction's loads
-    // in flight at a time instead of all eight hops' worth of registers.
-#pragma unroll 1
-    for (int nu = 0; nu < 4; ++nu) {
-        switch (nu) {
-            case 0: hop_dir1<0>(acc, U, in, g, s, a, n, R(1), R(1), g5_in); break;
-            case 1: hop_dir1<1>(acc, U, in, g, s, a, n, R(1), R(1), g5_in); break;
-            case 2: hop_dir1<2>(acc, U, in, g, s, a, n, R(1), R(1), g5_in); break;
-            default: hop_dir1<3>(acc, U, in, g, s, a, n, ep, em, g5_in); break;
-        }
-    }
+    hop_all1<BLK>(acc, U, in, g, s, a, n, ep, em, g5_in);
     mem_fence_compiler();
     Z<R> x[4];
     load1(x, in, g.ldv, a, s);
@@ -234,8 +317,12 @@ __global__ __launch_bounds__(kCBlock) void k_apply(const Z<R>* __restrict__ U, c
 template <typename R>
 void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu, int g5_in,
                   int g5_out, hipStream_t st, Timing t) {
-    timed_launch(k_apply<R>, dim3(np_stencil(g.V)), dim3(kCBlock), st, t, U, in, out, g, (R)kappa, (R)std::exp(mu),
-                 (R)std::exp(-mu), g5_in, g5_out);
+    if (colour_grid(g.V))
+        timed_launch(k_apply<R, kSites>, dim3(np_sten(g.V)), dim3(kSites), st, t, U, in, out, g, (R)kappa,
+                     (R)std::exp(mu), (R)std::exp(-mu), g5_in, g5_out);
+    else
+        timed_launch(k_apply<R, kCBlock>, dim3(np_sten(g.V)), dim3(kCBlock), st, t, U, in, out, g, (R)kappa,
+                     (R)std::exp(mu), (R)std::exp(-mu), g5_in, g5_out);
 }
 
 // =============================================================== batched sources
@@ -278,8 +365,8 @@ void launch_sources_to_soa(const ZD* canon, int which, int g5, const Work<R>& wk
 // apply a = H(mu) v_j and b = H(-mu) w_j = H^dag w_j with shared link loads, and
 // emit per-block partial sums of alpha_j = w_j^H a, |a|^2 and eta^H v_j.  At
 // j >= 2 the step first decides breakdown from the previous omega and norms.
-template <typename R>
-__global__ __launch_bounds__(kCBlock) void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
+template <typename R, int BLK>
+__global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
                                                       Work<R> wk, SrcList L, Coef coef0, int j, int npart_in,
                                                       int has_eta) {
     const int slot = L.slot[blockIdx.y];
@@ -289,7 +376,7 @@ __global__ __launch_bounds__(kCBlock) void k_fwd_pair(const Z<R>* __restrict__ U
     const Z<R>* rin = wk.f(slot, first ? 0 : 2);
     const Z<R>* sin = wk.f(slot, first ? 0 : 3);
     double red[kNvRecur];
-    reduce_partials<kNvRecur, kCBlock>(wk.p(slot, 1), npart_in, red);
+    reduce_partials<kNvRecur, BLK>(wk.p(slot, 1), npart_in, red);
     const ZD om = mk<double>(red[0], red[1]);
     const double rn2 = red[2], sn2 = red[3];
     const double aom = std::sqrt(norm2(om));
@@ -327,8 +414,8 @@ __global__ __launch_bounds__(kCBlock) void k_fwd_pair(const Z<R>* __restrict__ U
     }
     const R ib = (R)(1.0 / beta);
     const Z<R> icg = zcast<R>(zdiv(mk<double>(1.0, 0.0), cj(gam)));
-    const int a = wave_colour();
-    const int s = blockIdx.x * kSites + threadIdx.x % kSites;
+    const int a = sten_colour<BLK>();
+    const int s = sten_site<BLK>(a);
     double pv[kNvPair] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (s < g.V) {
         const Nbr n = neighbours(g, s);
@@ -336,15 +423,7 @@ __global__ __launch_bounds__(kCBlock) void k_fwd_pair(const Z<R>* __restrict__ U
         zero1(acca);
         zero1(accb);
         const R ep = (R)emu, em = (R)(1.0 / emu);
-#pragma unroll 1
-        for (int nu = 0; nu < 4; ++nu) {
-            switch (nu) {
-                case 0: hop_dir_pair1<0>(acca, accb, U, rin, sin, g, s, a, n, ep, em); break;
-                case 1: hop_dir_pair1<1>(acca, accb, U, rin, sin, g, s, a, n, ep, em); break;
-                case 2: hop_dir_pair1<2>(acca, accb, U, rin, sin, g, s, a, n, ep, em); break;
-                default: hop_dir_pair1<3>(acca, accb, U, rin, sin, g, s, a, n, ep, em); break;
-            }
-        }
+        hop_all_pair<BLK>(acca, accb, U, rin, sin, g, s, a, n, ep, em);
         mem_fence_compiler();
         Z<R> r0[4], s0[4], v[4], w[4], av[4], bv[4];
         load1(r0, rin, g.ldv, a, s);
@@ -378,15 +457,20 @@ __global__ __launch_bounds__(kCBlock) void k_fwd_pair(const Z<R>* __restrict__ U
             }
         }
     }
-    write_partials<kNvPair, kCBlock>(wk.p(slot, 0), pv);
+    write_partials<kNvPair, BLK>(wk.p(slot, 0), pv);
 }
 
 template <typename R>
 void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
                      Coef coef, int j, int has_eta, hipStream_t st, Timing t) {
     const int npart_in = j == 1 ? grid_for(g.V) : np_point(g.V);
-    timed_launch(k_fwd_pair<R>, dim3(np_stencil(g.V), L.n), dim3(kCBlock), st, t, U, g, kappa, std::exp(mu), wk, L,
-                 coef, j, npart_in, has_eta);
+    const dim3 grid(np_sten(g.V), L.n);
+    if (colour_grid(g.V))
+        timed_launch(k_fwd_pair<R, kSites>, grid, dim3(kSites), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
+                     npart_in, has_eta);
+    else
+        timed_launch(k_fwd_pair<R, kCBlock>, grid, dim3(kCBlock), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
+                     npart_in, has_eta);
 }
 
 // r = a - alpha_j v_j - gamma_j v_{j-1},  s = b - conj(alpha_j) w_j - beta_j w_{j-1},
@@ -441,7 +525,7 @@ __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L
 template <typename R>
 void launch_recur(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st) {
     dim3 grid((g.V + kPBlock - 1) / kPBlock, 12, L.n);
-    hipLaunchKernelGGL(k_recur<R>, grid, dim3(kPBlock), 0, st, g, wk, L, coef, j, np_stencil(g.V));
+    hipLaunchKernelGGL(k_recur<R>, grid, dim3(kPBlock), 0, st, g, wk, L, coef, j, np_sten(g.V));
 }
 
 // out(s) = [psi(s) +] g5^{overlap} |x| sum_{j <= k_used} c_j v_j(s), canonical layout.
@@ -543,7 +627,7 @@ __global__ __launch_bounds__(kPBlock) void k_bwd_ra(Geom g, Work<R> wk, SrcList 
 template <typename R>
 void launch_bwd_ra(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st) {
     dim3 grid((g.V + kPBlock - 1) / kPBlock, 12, L.n);
-    hipLaunchKernelGGL(k_bwd_ra<R>, grid, dim3(kPBlock), 0, st, g, wk, L, coef, j, np_stencil(g.V));
+    hipLaunchKernelGGL(k_bwd_ra<R>, grid, dim3(kPBlock), 0, st, g, wk, L, coef, j, np_sten(g.V));
 }
 
 // Reverse of a_j = H v_j, b_j = H^dag w_j, alpha_j = w_j^H a_j and of the recurrence:
@@ -555,8 +639,8 @@ void launch_bwd_ra(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef
 // partials of Re vbar_j^H v_j and wbar_j^H w_j.  The last step (j = k_used) has
 // no residual adjoints: abar = alphabar w, vbar = |x| conj(c) eta + alphabar b,
 // wbar = conj(alphabar) a.
-template <typename R, bool LAST>
-__global__ __launch_bounds__(kCBlock) void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
+template <typename R, bool LAST, int BLK>
+__global__ __launch_bounds__(BLK) void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
                                                     Work<R> wk, SrcList L, Coef coef0, int j, int npart_in) {
     const int e = blockIdx.y, slot = L.slot[e];
     const Coef coef = coef0.at(slot);
@@ -564,7 +648,7 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb(const Z<R>* __restrict__ U, 
     ZD abar = coef.abar_T[j];
     if (!LAST) {
         double red[kNvRA];
-        reduce_partials<kNvRA, kCBlock>(wk.p(slot, 1), npart_in, red);
+        reduce_partials<kNvRA, BLK>(wk.p(slot, 1), npart_in, red);
         abar = abar - mk<double>(red[0], red[1]) - mk<double>(red[2], red[3]);
         if (blockIdx.x == 0 && threadIdx.x == 0 && j >= 2) {
             coef.gbar_tot[j] = coef.gbar_T[j] - mk<double>(red[4], red[5]);
@@ -582,8 +666,8 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb(const Z<R>* __restrict__ U, 
     const Z<R> etac = zcast<R>(coef.misc[0] * cj(coef.c[j]));
     const Z<R> gnc = carry ? zcast<R>(cj(coef.gamma[j + 1])) : mk<R>(0, 0);
     const R bn = carry ? (R)coef.beta[j + 1] : R(0);
-    const int a = wave_colour();
-    const int s = blockIdx.x * kSites + threadIdx.x % kSites;
+    const int a = sten_colour<BLK>();
+    const int s = sten_site<BLK>(a);
     double pv[kNvRB] = {0.0, 0.0, 0.0};
     if (s < g.V) {
         Z<R> accs[4], accr[4];
@@ -593,15 +677,7 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb(const Z<R>* __restrict__ U, 
             const Nbr n = neighbours(g, s);
             const R ep = (R)emu, em = (R)(1.0 / emu);
             // field A = sbar_j at +mu (accs), field B = rbar_j at -mu (accr)
-#pragma unroll 1
-            for (int nu = 0; nu < 4; ++nu) {
-                switch (nu) {
-                    case 0: hop_dir_pair1<0>(accs, accr, U, sbar_j, rbar_j, g, s, a, n, ep, em); break;
-                    case 1: hop_dir_pair1<1>(accs, accr, U, sbar_j, rbar_j, g, s, a, n, ep, em); break;
-                    case 2: hop_dir_pair1<2>(accs, accr, U, sbar_j, rbar_j, g, s, a, n, ep, em); break;
-                    default: hop_dir_pair1<3>(accs, accr, U, sbar_j, rbar_j, g, s, a, n, ep, em); break;
-                }
-            }
+            hop_all_pair<BLK>(accs, accr, U, sbar_j, rbar_j, g, s, a, n, ep, em);
             mem_fence_compiler();
         }
         const R kap = (R)kappa;
@@ -649,19 +725,26 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb(const Z<R>* __restrict__ U, 
         pv[1] = d2r;
         pv[2] = d2i;
     }
-    write_partials<kNvRB, kCBlock>(wk.p(slot, 0), pv);
+    write_partials<kNvRB, BLK>(wk.p(slot, 0), pv);
 }
 
 template <typename R>
 void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
                    Coef coef, int j, int last, hipStream_t st, Timing t) {
-    const dim3 grid(np_stencil(g.V), L.n);
-    if (last)
-        timed_launch(k_bwd_rb<R, true>, grid, dim3(kCBlock), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
-                     np_point(g.V));
+    const dim3 grid(np_sten(g.V), L.n);
+    const int np = np_point(g.V);
+    const bool cg = colour_grid(g.V);
+    if (last && cg)
+        timed_launch(k_bwd_rb<R, true, kSites>, grid, dim3(kSites), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j, np);
+    else if (last)
+        timed_launch(k_bwd_rb<R, true, kCBlock>, grid, dim3(kCBlock), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
+                     np);
+    else if (cg)
+        timed_launch(k_bwd_rb<R, false, kSites>, grid, dim3(kSites), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
+                     np);
     else
-        timed_launch(k_bwd_rb<R, false>, grid, dim3(kCBlock), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
-                     np_point(g.V));
+        timed_launch(k_bwd_rb<R, false, kCBlock>, grid, dim3(kCBlock), st, t, U, g, kappa, std::exp(mu), wk, L, coef,
+                     j, np);
 }
 
 // =============================================================== force contraction

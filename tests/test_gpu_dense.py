@@ -2,10 +2,12 @@
 against the oracle's Schur method and block-Schur Frechet derivative.
 
 Sizes span one panel (k = 1, 7), several panels with a ragged last panel
-(k = 37, 130) and the workload sizes 64 and 200; a Lanczos matrix from the
-4^4 workload is included.  Tolerance: 1e-11 relative (Frobenius) for these
-well-separated spectra (Newton and Schur differ by rounding times the
-condition number of the sign).
+(k = 37, 130), the workload sizes 64 and 200, the 512-thread register panel
+(k = 300, 450) and the LDS panel beyond it (k = 600); a Lanczos matrix from the
+4^4 workload is included, and matrices with zero diagonal blocks, whose every
+elimination step needs a row exchange (a wrong pivot choice meets a zero pivot).
+Tolerance: 1e-11 relative (Frobenius) for these well-separated spectra (Newton
+and Schur differ by rounding times the condition number of the sign).
 """
 import numpy as np
 import pytest
@@ -34,7 +36,7 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("k", [1, 7, 37, 64, 130, 200])
+@pytest.mark.parametrize("k", [1, 7, 37, 64, 130, 200, 300, 450, 600])
 def test_dense_sign_and_frechet(ctx, k):
     say(f"dense sign k={k}")
     rng = np.random.default_rng(k)
@@ -50,6 +52,24 @@ def test_dense_sign_and_frechet(ctx, k):
     say(f"  iters={iters} sign err {rel(S, S_ref):.2e} frechet err {rel(L, L_ref):.2e}")
     assert rel(S, S_ref) < 1e-11
     assert rel(L, L_ref) < 1e-10
+
+
+@pytest.mark.parametrize("k", [200, 300])
+def test_dense_sign_needs_pivoting(ctx, k):
+    # A = [[0, B], [C, 0]]: A^2 = diag(BC, CB), so sgn(A) = A (A^2)^{-1/2} is defined
+    # when BC has no eigenvalue on the negative real axis; B, C near the identity
+    h = k // 2
+    rng = np.random.default_rng(k + 1)
+    B = np.eye(h) + 0.3 * (rng.standard_normal((h, h)) + 1j * rng.standard_normal((h, h))) / np.sqrt(h)
+    C = np.eye(h) + 0.3 * (rng.standard_normal((h, h)) + 1j * rng.standard_normal((h, h))) / np.sqrt(h)
+    A = np.zeros((k, k), dtype=complex)
+    A[:h, h:] = B
+    A[h:, :h] = C
+    say(f"dense sign with zero diagonal blocks k={k}")
+    S, _, iters = ctx.dense_sign(dev(A))
+    e = rel(host(S), SG.sign_schur(A))
+    say(f"  iters={iters} sign err {e:.2e}")
+    assert e < 1e-11
 
 
 def test_dense_sign_of_lanczos_matrix(ctx):
