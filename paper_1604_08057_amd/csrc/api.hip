@@ -356,8 +356,8 @@ tslov_status ensure_dense(tslov_ctx* c, int slots, int kcap, DenseWork& w) {
     CHK(ensure(c->dense, (size_t)slots * 6 * kk * sizeof(ZD)));
     CHK(ensure(c->denseInt, (size_t)slots * 2 * kcap * sizeof(int)));
     CHK(ensure(c->densePart, (size_t)slots * ps * sizeof(double)));
-    CHK(ensure(c->denseDelta, (size_t)slots * 2 * sizeof(double)));
-    CHK(ensure_host_part(c, 2 * slots + 8));
+    CHK(ensure(c->denseDelta, (size_t)slots * 4 * sizeof(double)));
+    CHK(ensure_host_part(c, 4 * slots + 8));
     ZD* d = c->dense.as<ZD>();
     const size_t S = (size_t)slots;
     w.X = d;
@@ -386,9 +386,14 @@ int choose_nb(const tslov_ctx* c, int k) {
 
 // Newton iteration on X (and Y) of every entry of L (k = size, decreasing) until
 // each entry's relative step falls to rounding level.  Scaled inverse-based steps
-// first; once the step is below kNsSwitch the inverse-free step takes over (and
-// hands back if it ever fails to contract).  iters[e] receives the step count.
+// first; the inverse-free step takes over once |I - X^2|_F < kNsSafe, where it is
+// guaranteed to converge quadratically (checked after inverse-based steps whose
+// predecessor moved X by less than kResidCheck), or once the step is below
+// kNsSwitch; it hands back if it ever fails to contract.  iters[e] receives the
+// step count.
 constexpr double kNsSwitch = 1e-2;
+constexpr double kNsSafe = 0.9;
+constexpr double kResidCheck = 0.3;
 
 tslov_status newton(tslov_ctx* c, const SrcList& L, int grad, const DenseWork& w, std::vector<int>& iters) {
     struct St {
@@ -409,17 +414,28 @@ tslov_status newton(tslov_ctx* c, const SrcList& L, int grad, const DenseWork& w
             ++T.n;
         }
         if (A.n == 0 && B.n == 0) break;
+        SrcList R{};   // inverse-based entries close enough to test |I - X^2| afterwards
+        for (int a = 0; a < A.n; ++a)
+            if (s[A.src[a]].prev < kResidCheck) {
+                R.slot[R.n] = A.slot[a];
+                R.src[R.n] = A.src[a];
+                R.k[R.n] = A.k[a];
+                R.flag[R.n] = A.flag[a];
+                ++R.n;
+            }
         if (A.n) tslov::dense_newton_step(A, grad, choose_nb(c, A.k[0]), c->lds_max, w, c->st);
+        if (R.n) tslov::dense_residual(R, w, c->st);
         if (B.n) tslov::dense_ns_step(B, grad, w, c->st);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(c->host_part, w.delta, (size_t)2 * c->dslots * sizeof(double), hipMemcpyDeviceToHost,
+        HIPCHK(hipMemcpyAsync(c->host_part, w.delta, (size_t)4 * c->dslots * sizeof(double), hipMemcpyDeviceToHost,
                               c->st));
         HIPCHK(hipStreamSynchronize(c->st));
         for (const SrcList* T : {&A, &B})
             for (int a = 0; a < T->n; ++a) {
                 St& x = s[T->src[a]];
                 x.it = it;
-                const double delta = std::sqrt(c->host_part[2 * T->slot[a]] / c->host_part[2 * T->slot[a] + 1]);
+                const double* dl = c->host_part + 4 * T->slot[a];
+                const double delta = std::sqrt(dl[0] / dl[1]);
                 if (!std::isfinite(delta))
                     return fail(TSLOV_ERR_SIGN_UNDEFINED, "projected matrix is singular or its sign is undefined");
                 if (x.ns && delta > x.prev) {   // not contracting: back to inverse-based steps
@@ -427,7 +443,8 @@ tslov_status newton(tslov_ctx* c, const SrcList& L, int grad, const DenseWork& w
                     x.prev = delta;
                     continue;
                 }
-                if (delta < kNsSwitch) {
+                const bool tested = T == &A && x.prev < kResidCheck;   // residual taken this round
+                if (delta < kNsSwitch || (tested && std::sqrt(dl[2]) < kNsSafe)) {
                     x.scaling = 0;
                     x.ns = 1;
                 }

@@ -382,11 +382,36 @@ __device__ __forceinline__ void force_pair(ZD (&G)[3][3], const Spinor<R>& p_x, 
 }
 
 // ------------------------------------------------------------------ reductions
-// Deterministic: fixed shuffle tree inside a wave, then waves in index order.
+// Cross-lane moves of a double: DPP within rows of 16 lanes, lane reads across rows.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __hiloint2double(hi, lo);
+}
+
+constexpr int kDppSwap1 = 0xB1;       // quad_perm [1, 0, 3, 2]
+constexpr int kDppSwap2 = 0x4E;       // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141; // lane j <-> 7 - j within 8
+constexpr int kDppMirror = 0x140;     // lane j <-> 15 - j within 16
+
+// Wavefront sum, the same bits in every lane and a fixed order: butterflies within
+// rows of 16 lanes (both lanes of a pair add the same two operands, so they agree
+// exactly), then the four row sums in row order.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
-    return v;
+    v = v + dpp_d<kDppSwap1>(v);
+    v = v + dpp_d<kDppSwap2>(v);
+    v = v + dpp_d<kDppHalfMirror>(v);
+    v = v + dpp_d<kDppMirror>(v);
+    return ((readlane_d(v, 0) + readlane_d(v, 16)) + readlane_d(v, 32)) + readlane_d(v, 48);
 }
 
 // Block sum of NV values per thread; result valid in every thread.

@@ -62,6 +62,39 @@ __global__ __launch_bounds__(kDB) void k_rowperm_init(SrcList L, DenseWork w0) {
     if (i < L.k[e]) w.rowperm[i] = i;
 }
 
+template <int CTRL>
+__device__ __forceinline__ void dpp_argmax_step(double& v, int& i) {
+    const double ov = dpp_d<CTRL>(v);
+    const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xf, 0xf, false);
+    if (ov > v || (ov == v && oi < i)) {
+        v = ov;
+        i = oi;
+    }
+}
+
+// Largest v over the wavefront (smallest i among equal v), returned in every lane.
+// Rows of 16 lanes combine through DPP (swap within pairs, within quads, mirror
+// within halves of 8, mirror within 16); the four rows through lane reads.
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+    dpp_argmax_step<kDppSwap1>(v, i);
+    dpp_argmax_step<kDppSwap2>(v, i);
+    dpp_argmax_step<kDppHalfMirror>(v, i);
+    dpp_argmax_step<kDppMirror>(v, i);
+    double bv = readlane_d(v, 0);
+    int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+    for (int r = 16; r < kWave; r += 16) {
+        const double ov = readlane_d(v, r);
+        const int oi = __builtin_amdgcn_readlane(i, r);
+        if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    v = bv;
+    i = bi;
+}
+
 // Panel K: columns [c0, c0 + nbK) of Wk, all k rows, held in LDS and factored by
 // one block of four wavefronts; thread t owns rows t, t + 256, ...  For each pivot
 // p = c0 + q: the largest |P[i][q]| over rows i >= p (smallest index on ties) is
@@ -104,12 +137,7 @@ __global__ __launch_bounds__(kDB) void k_gj_panel(DenseWork w0, SrcList L, int c
             const double m = (i >= p) ? norm2(P[i * LD + q]) : -1.0;
             if (m > best) { best = m; bi = i; }
         }
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            const double ob = __shfl_xor(best, off, kWave);
-            const int oi = __shfl_xor(bi, off, kWave);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
+        wave_argmax(best, bi);
         if (tid % kWave == 0) { wbest[tid / kWave] = best; wi[tid / kWave] = bi; }
         __syncthreads();
         double b = wbest[0];
@@ -180,49 +208,6 @@ __global__ __launch_bounds__(kDB) void k_gj_panel(DenseWork w0, SrcList L, int c
 // as row - (f / P[imax][q]) P[imax].  The row swap needs no data movement beyond
 // the published old row p, which the owner of row imax takes over.  The pivot is
 // the unique maximum under that order, so the result does not depend on BLK.
-template <int CTRL>
-__device__ __forceinline__ void dpp_argmax_step(double& v, int& i) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
-    const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xf, 0xf, false);
-    const double ov = __hiloint2double(hi, lo);
-    if (ov > v || (ov == v && oi < i)) {
-        v = ov;
-        i = oi;
-    }
-}
-
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __hiloint2double(hi, lo);
-}
-
-// Largest v over the wavefront (smallest i among equal v), returned in every lane.
-// Rows of 16 lanes combine through DPP (swap within pairs, within quads, mirror
-// within halves of 8, mirror within 16); the four rows through lane reads.
-__device__ __forceinline__ void wave_argmax(double& v, int& i) {
-    dpp_argmax_step<0xB1>(v, i);    // quad_perm [1, 0, 3, 2]
-    dpp_argmax_step<0x4E>(v, i);    // quad_perm [2, 3, 0, 1]
-    dpp_argmax_step<0x141>(v, i);   // row_half_mirror
-    dpp_argmax_step<0x140>(v, i);   // row_mirror
-    double bv = readlane_d(v, 0);
-    int bi = __builtin_amdgcn_readlane(i, 0);
-#pragma unroll
-    for (int r = 16; r < kWave; r += 16) {
-        const double ov = readlane_d(v, r);
-        const int oi = __builtin_amdgcn_readlane(i, r);
-        if (ov > bv || (ov == bv && oi < bi)) {
-            bv = ov;
-            bi = oi;
-        }
-    }
-    v = bv;
-    i = bi;
-}
-
 constexpr int kGjRegMax = 512;   // largest k served by the register-resident panel
 
 template <int NB, int BLK>
@@ -602,6 +587,38 @@ void dense_ns_step(const SrcList& L, int grad, const DenseWork& w, hipStream_t s
     const int nblk = grid_for(kmax * kmax, kDB);
     hipLaunchKernelGGL(k_ns_commit, dim3(nblk, 1, L.n), dim3(kDB), 0, st, w, L, grad);
     hipLaunchKernelGGL(k_dense_delta, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, nblk);
+}
+
+// Partials of |I - Q|_F^2 for Q = Zt (X^2 from the preceding GEMM), then their sum
+// into delta[2]: once below 1, E = I - X^2 obeys E' = E^2 (3 + E)/4 under the
+// inverse-free step (X commutes with E), so that step converges quadratically.
+__global__ __launch_bounds__(kDB) void k_dense_resid(DenseWork w0, SrcList L) {
+    const int e = blockIdx.z, k = L.k[e];
+    const DenseWork w = w0.at(L.slot[e]);
+    const int idx = blockIdx.x * kDB + threadIdx.x;
+    double v[1] = {0.0};
+    if (idx < k * k) {
+        ZD q = w.Zt[idx];
+        if (idx / k == idx % k) q.re -= 1.0;
+        v[0] = norm2(q);
+    }
+    write_partials<1, kDB>(w.part + 4 * w.npart_max + 8, v);
+}
+
+__global__ __launch_bounds__(kDB) void k_dense_resid_sum(DenseWork w0, SrcList L, int npart) {
+    const DenseWork w = w0.at(L.slot[blockIdx.z]);
+    double red[1];
+    reduce_partials<1, kDB>(w.part + 4 * w.npart_max + 8, npart, red);
+    if (threadIdx.x == 0) w.delta[2] = red[0];
+}
+
+void dense_residual(const SrcList& L, const DenseWork& w, hipStream_t st) {
+    const int kmax = L.k[0];
+    const dim3 g2(grid_for(kmax, 16), grid_for(kmax, 16), L.n);
+    hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w, L, kMX, kMX, kMZt, kMZt, 1.0, 0.0, 0);
+    const int nblk = grid_for(kmax * kmax, kDB);
+    hipLaunchKernelGGL(k_dense_resid, dim3(nblk, 1, L.n), dim3(kDB), 0, st, w, L);
+    hipLaunchKernelGGL(k_dense_resid_sum, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, nblk);
 }
 
 // c_j = X[j][0]; adjoint seeds alphabar_j = conj(G_jj), betabar_{j+1} = Re G_{j,j+1},

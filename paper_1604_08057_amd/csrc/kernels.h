@@ -170,8 +170,8 @@ struct DenseWork {
     ZD* Zt;       // GEMM temporary
     ZD* Y2;       // second temporary (inverse-free steps with the Frechet block)
     int* rowperm; // [slot][2 kcap]: row permutation, then pivot rows
-    double* part; // [slot][pstride]: update partials, scatter partials, mu
-    double* delta;  // [slot][2]: |X_new - X|^2, |X_new|^2 of the last step
+    double* part; // [slot][pstride]: update partials, scatter partials, mu, residual partials
+    double* delta;  // [slot][4]: |X_new - X|^2, |X_new|^2 of the last step, |I - X_new^2|_F^2, unused
     size_t kk;    // kcap^2
     int kcap;
     int npart_max;  // partial blocks per slot (= blocks over kcap^2)
@@ -182,11 +182,11 @@ struct DenseWork {
         o.X += d; o.Y += d; o.Wk += d; o.Xinv += d; o.Zt += d; o.Y2 += d;
         o.rowperm += (size_t)slot * 2 * kcap;
         o.part += (size_t)slot * pstride;
-        o.delta += (size_t)slot * 2;
+        o.delta += (size_t)slot * 4;
         return o;
     }
 };
-inline int dense_pstride(int kcap) { return 4 * grid_for(kcap * kcap, 256) + 8; }
+inline int dense_pstride(int kcap) { return 5 * grid_for(kcap * kcap, 256) + 8; }
 
 // Build X = T_k (tridiagonal from coef) and, if grad, Y = e_1 cbar^H with cbar = |x| conj(h),
 // for every list entry (k[e] = k_used, sorted in decreasing order).
@@ -199,6 +199,8 @@ void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, con
 // One inverse-free (Newton-Schulz) step X <- X (3 - X^2)/2 and, if grad, the
 // Frechet block Y <- [Y (3 - X^2) - X (X Y + Y X)]/2; leaves delta[slot].
 void dense_ns_step(const SrcList& L, int grad, const DenseWork& w, hipStream_t st);
+// |I - X^2|_F^2 of every entry into delta[2] (one GEMM into Zt and a reduction).
+void dense_residual(const SrcList& L, const DenseWork& w, hipStream_t st);
 // c = X e_1, adjoint seeds from Y, S = |x| Re sum_j c_j h_j.
 void launch_dense_extract(Coef coef, const SrcList& L, int grad, const DenseWork& w, hipStream_t st);
 
