@@ -29,11 +29,16 @@ __host__ __device__ inline int np_max(int V) { return np_colour(V) > np_point(V)
 // Layout of the stencil kernels, a function of the lattice alone (so that a source
 // gives the same bits in any batch): the colour grid while the lattice has too few
 // site blocks to occupy the chip with three-wavefront blocks, the colour-split
-// blocks (kCBlock threads, colour = wavefront) above that.
+// blocks (kCBlock threads, colour = wavefront) above that, with the site blocks
+// padded to a multiple of the XCD count and dealt out so that each XCD works
+// through a contiguous run of them (neighbouring site blocks share an L2).
 constexpr int kColourGridMaxBlocks = 128;
 __host__ __device__ inline bool colour_grid(int V) { return np_stencil(V) <= kColourGridMaxBlocks; }
 // Blocks (= partial sums) of one stencil launch per source.
-__host__ __device__ inline int np_sten(int V) { return colour_grid(V) ? np_colour(V) : np_stencil(V); }
+__host__ __device__ inline int np_sten(int V) { return colour_grid(V) ? np_colour(V) : nsb_pad(V); }
+// Block b of a grid of nb blocks (nb a multiple of kXcd) -> the b-th block in XCD
+// order: XCD b % kXcd takes the contiguous run of nb / kXcd blocks.
+__host__ __device__ inline int xcd_block(int b, int nb) { return (b % kXcd) * (nb / kXcd) + b / kXcd; }
 
 // ------------------------------------------------------------------ complex
 template <typename R>
@@ -329,7 +334,7 @@ __device__ __forceinline__ int wave_colour() { return __builtin_amdgcn_readfirst
 
 // Colour and site of this thread in a stencil kernel of BLK threads per block:
 // BLK = kSites is the colour grid (grid.x = np_colour, colour-major), BLK = kCBlock
-// the colour split (grid.x = np_stencil, colour = wavefront).
+// the colour split (grid.x = nsb_pad, colour = wavefront, blocks in XCD order).
 template <int BLK>
 __device__ __forceinline__ int sten_colour() {
     if (BLK == kSites) return blockIdx.x / (gridDim.x / 3);
@@ -338,7 +343,7 @@ __device__ __forceinline__ int sten_colour() {
 template <int BLK>
 __device__ __forceinline__ int sten_site(int a) {
     if (BLK == kSites) return (blockIdx.x - a * (gridDim.x / 3)) * kSites + threadIdx.x;
-    return blockIdx.x * kSites + threadIdx.x % kSites;
+    return xcd_block(blockIdx.x, gridDim.x) * kSites + threadIdx.x % kSites;
 }
 
 // ------------------------------------------------------------------ force contraction

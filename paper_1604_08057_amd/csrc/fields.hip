@@ -314,15 +314,86 @@ __global__ __launch_bounds__(BLK) void k_apply(const Z<R>* __restrict__ U, const
     store1(out, g.ldv, a, s, x);
 }
 
+// Site per thread (lattices above the colour grid's range): each thread forms all
+// three colours of its site, so every neighbour spinor and link passes through the
+// compute unit's L1 once per site instead of once per colour wavefront; blocks go
+// out in XCD order.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_apply_site(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+                                                       Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em,
+                                                       int g5_in, int g5_out) {
+    const int s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const Nbr n = neighbours(g, s);
+    Spinor<R> acc;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc.c[sp][c] = mk<R>(0, 0);
+#pragma unroll 1
+    for (int nu = 0; nu < 4; ++nu) {
+        Z<R> u[3][3];
+        Spinor<R> p;
+        switch (nu) {
+            case 0:
+                load_link(u, U, g.ldv, 0, s); load_spinor(p, in, g.ldv, n.fwd[0]); if (g5_in) g5_inplace(p);
+                hop_fwd<0>(acc, u, p, R(1));
+                load_link(u, U, g.ldv, 0, n.bwd[0]); load_spinor(p, in, g.ldv, n.bwd[0]); if (g5_in) g5_inplace(p);
+                hop_bwd<0>(acc, u, p, R(1));
+                break;
+            case 1:
+                load_link(u, U, g.ldv, 1, s); load_spinor(p, in, g.ldv, n.fwd[1]); if (g5_in) g5_inplace(p);
+                hop_fwd<1>(acc, u, p, R(1));
+                load_link(u, U, g.ldv, 1, n.bwd[1]); load_spinor(p, in, g.ldv, n.bwd[1]); if (g5_in) g5_inplace(p);
+                hop_bwd<1>(acc, u, p, R(1));
+                break;
+            case 2:
+                load_link(u, U, g.ldv, 2, s); load_spinor(p, in, g.ldv, n.fwd[2]); if (g5_in) g5_inplace(p);
+                hop_fwd<2>(acc, u, p, R(1));
+                load_link(u, U, g.ldv, 2, n.bwd[2]); load_spinor(p, in, g.ldv, n.bwd[2]); if (g5_in) g5_inplace(p);
+                hop_bwd<2>(acc, u, p, R(1));
+                break;
+            default:
+                load_link(u, U, g.ldv, 3, s); load_spinor(p, in, g.ldv, n.fwd[3]); if (g5_in) g5_inplace(p);
+                hop_fwd<3>(acc, u, p, ep);
+                load_link(u, U, g.ldv, 3, n.bwd[3]); load_spinor(p, in, g.ldv, n.bwd[3]); if (g5_in) g5_inplace(p);
+                hop_bwd<3>(acc, u, p, em);
+                break;
+        }
+    }
+    mem_fence_compiler();
+    Spinor<R> x;
+    load_spinor(x, in, g.ldv, s);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+        const R s_in = (g5_in && sp >= 2) ? R(-1) : R(1);
+        const R s_out = (g5_out && sp >= 2) ? R(-1) : R(1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) x.c[sp][c] = s_out * (s_in * x.c[sp][c] - kappa * acc.c[sp][c]);
+    }
+    // streaming stores: the result is not read again here and would only displace
+    // neighbour spinors and links from L2
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            R* q = reinterpret_cast<R*>(out + (size_t)(sp * 3 + c) * g.ldv + s);
+            __builtin_nontemporal_store(x.c[sp][c].re, q);
+            __builtin_nontemporal_store(x.c[sp][c].im, q + 1);
+        }
+}
+
 template <typename R>
 void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu, int g5_in,
                   int g5_out, hipStream_t st, Timing t) {
-    if (colour_grid(g.V))
+    if (colour_grid(g.V)) {
         timed_launch(k_apply<R, kSites>, dim3(np_sten(g.V)), dim3(kSites), st, t, U, in, out, g, (R)kappa,
                      (R)std::exp(mu), (R)std::exp(-mu), g5_in, g5_out);
-    else
-        timed_launch(k_apply<R, kCBlock>, dim3(np_sten(g.V)), dim3(kCBlock), st, t, U, in, out, g, (R)kappa,
-                     (R)std::exp(mu), (R)std::exp(-mu), g5_in, g5_out);
+    } else {
+        const int nb = (grid_for(g.V) + kXcd - 1) / kXcd * kXcd;
+        timed_launch(k_apply_site<R>, dim3(nb), dim3(kBlock), st, t, U, in, out, g, (R)kappa, (R)std::exp(mu),
+                     (R)std::exp(-mu), g5_in, g5_out);
+    }
 }
 
 // =============================================================== batched sources

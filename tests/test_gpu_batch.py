@@ -2,7 +2,9 @@
 
 * every source of a batch gives bit-for-bit the single-source result (the
   kernels reduce in a fixed order per source, whatever else shares the launch),
-  at the 4^4 workload (k = 64, 17, 40, 64, 1) and at 8^4 (k from 150 to 200);
+  at the 4^4 workload (k = 64, 17, 40, 64, 1), at 8^4 (k from 150 to 200) and
+  on a 10^4 lattice, which runs the colour-split stencil layout on an
+  XCD-ordered, padded grid (k = 40, 25, 33, with the oracle for one source);
 * against the oracle per source: S, dS/dU, dS/dpsi to 1e-10 relative;
 * a zero source inside a batch: S = 0 and zero derivatives, the others unchanged;
 * the current estimator against the oracle estimator (mean of per-source U(1)
@@ -74,6 +76,20 @@ def test_batch_equals_single_8():
     ks = [200, 150, 187, 163]
     say(f"batched 8^4 ks={ks}")
     _batch_vs_single(wl.dims, wl.mass, wl.mu, wl.links(), _sources(4, 4096, 43), _sources(4, 4096, 44), ks)
+
+
+def test_batch_equals_single_colour_split():
+    dims, mass, mu = (10, 10, 10, 10), -2.0, 0.3
+    U = random_links(dims, 0.4, np.random.default_rng(9))
+    ks = [40, 25, 33]
+    psis, etas = _sources(3, 10000, 47), _sources(3, 10000, 48)
+    say(f"batched 10^4 ks={ks}")
+    S, dU, dpsi, infos = _batch_vs_single(dims, mass, mu, U, psis, etas, ks)
+    ref = GR.grad_autograd(WilsonOperator(dims, mass, mu), U, psis[1], etas[1], ks[1])
+    eS = abs(S[1] - ref["S"]) / abs(ref["S"])
+    eG, eP = rel(dU[1], ref["G"]), rel(dpsi[1], ref["dpsi"])
+    say(f"  source 1 vs oracle: S {eS:.2e} G {eG:.2e} dpsi {eP:.2e}")
+    assert eS < 1e-10 and eG < 1e-10 and eP < 1e-10
 
 
 def test_zero_source_in_batch():

@@ -1,7 +1,10 @@
 """GPU Wilson stencil against the oracle (App. A, eq. WD_op): D_w, D_w^dag, H, H^dag.
 
 Lattices: 4^4, a ragged 3x5x7x6 (V = 630, not a multiple of the block size)
-and 8^4.  FP64 is compared element by element to 1e-14 relative (max norm);
+and 8^4 (colour-grid layout); 10^4 and a ragged 9x11x13x7 (V = 9009) above it
+(site-per-thread operator, colour-split Lanczos kernels, XCD-padded grids); and
+the 32^4 lattice of the stencil benchmark with its own link and source
+generator.  FP64 is compared element by element to 1e-14 relative (max norm);
 the float32 path to 2e-6.
 """
 import numpy as np
@@ -16,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-14), ("mixed", 2e-6)])
-@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 7, 6), (8, 8, 8, 8)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 7, 6), (8, 8, 8, 8), (10, 10, 10, 10), (9, 11, 13, 7)])
 @pytest.mark.parametrize("mu", [0.0, 0.3])
 def test_operators_match_oracle(dims, mu, precision, tol):
     from paper_1604_08057_amd import Context
@@ -57,3 +60,23 @@ def test_antiperiodic_flag_off():
     got = host(ctx.apply_h(dev(x)))
     assert rel_max(got, op.h(torch.from_numpy(U), torch.from_numpy(x)).numpy()) < 1e-14
     ctx.close()
+
+
+def test_benchmark_lattice_32():
+    # the operator exactly as the stencil benchmark times it (links and source from
+    # torch's generator on the device, not SU(3)), against the oracle on the host
+    from paper_1604_08057_amd import Context
+    dims = (32, 32, 32, 32)
+    V = 32 ** 4
+    g = torch.Generator(device="cuda").manual_seed(1604)
+    U = torch.randn((4, V, 3, 3), dtype=torch.complex128, device="cuda", generator=g)
+    x = torch.randn((V, 4, 3), dtype=torch.complex128, device="cuda", generator=g)
+    say("stencil 32^4 (benchmark configuration)")
+    ctx = Context(dims, -2.0, 0.3)
+    ctx.set_links(U)
+    got = host(ctx.apply_h(x))
+    ctx.close()
+    want = WilsonOperator(dims, -2.0, 0.3).h(U.cpu(), x.cpu()).numpy()
+    err = rel_max(got, want)
+    say(f"  h: rel max err {err:.2e}")
+    assert err < 1e-14
