@@ -856,12 +856,17 @@ __device__ void force_body(const Geom& g, double kappa, double emu, const Work<R
         for (int b = 0; b < 3; ++b) gout[(size_t)(NU * 9 + a * 3 + b) * g.ldv + s] = (-kappa) * G[a][b];
 }
 
+// Blocks of 64 sites x 4 directions, one wavefront per direction: the four links of
+// a site read its spinors at nearly the same time on one compute unit (from L1/L2
+// rather than from memory four times over), and the blocks go out in XCD order so
+// that neighbour spinors are mostly still in L2.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_force(Geom g, double kappa, double emu, Work<R> wk, SrcList L, int nchunk,
-                                                  ZD* __restrict__ gpart) {
-    const int s = blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(4 * kSites) void k_force(Geom g, double kappa, double emu, Work<R> wk, SrcList L,
+                                                      int nchunk, ZD* __restrict__ gpart) {
+    const int nu = __builtin_amdgcn_readfirstlane(threadIdx.x / kSites);
+    const int s = xcd_block(blockIdx.x, gridDim.x) * kSites + threadIdx.x % kSites;
     if (s >= g.V) return;
-    const int e = blockIdx.z >> 2, nu = blockIdx.z & 3, slot = L.slot[e];
+    const int e = blockIdx.z, slot = L.slot[e];
     const int k = L.k[e];
     const int chunk = blockIdx.y;
     const int j0 = 1 + (int)((long long)k * chunk / nchunk);
@@ -878,8 +883,8 @@ __global__ __launch_bounds__(kBlock) void k_force(Geom g, double kappa, double e
 template <typename R>
 void launch_force(const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L, int nchunk, ZD* gpart,
                   hipStream_t st) {
-    dim3 grid(grid_for(g.V), nchunk, 4 * L.n);
-    hipLaunchKernelGGL(k_force<R>, grid, dim3(kBlock), 0, st, g, kappa, std::exp(mu), wk, L, nchunk, gpart);
+    dim3 grid(nsb_pad(g.V), nchunk, L.n);
+    hipLaunchKernelGGL(k_force<R>, grid, dim3(4 * kSites), 0, st, g, kappa, std::exp(mu), wk, L, nchunk, gpart);
 }
 
 __device__ __forceinline__ double boundary_sign(const Geom& g, int nu, int s, int antiperiodic) {
