@@ -38,8 +38,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sgn(H)ψ+dU-derivative sources/s, mixed vs FP64 @≤1e-6 rel; stencil HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAMES = {0: "k_fwd_pair<double> (fused Lanczos stencil pair)",
-                1: "k_bwd_rb<double> (reverse-mode stencil pair)"}
+KERNEL_NAMES = {0: "k_fwd_pair<double, 64> (fused Lanczos stencil pair, colour grid)",
+                1: "k_bwd_rb<double, false, 64> (reverse-mode stencil pair, colour grid)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stencil_pair_8x8x8x8.txt")
 # live kernel timing samples every 16th launch of a class: an event pair adds ~5 us
 # of dispatch latency, which on every launch would slow the timed step by ~25%
@@ -124,7 +124,7 @@ def stencil_large():
     b = ctx.kernel_bytes(KERNEL_APPLY)
     ctx.close()
     gbs = b / (ms / n * 1e-3) / 1e9
-    return {"lattice": "32^4", "kernel": "k_apply<double>", "bytes_per_launch": b, "mean_ms": ms / n,
+    return {"lattice": "32^4", "kernel": "k_apply_site<double>", "bytes_per_launch": b, "mean_ms": ms / n,
             "achieved_GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
 
 

@@ -33,16 +33,22 @@ def main(fetch_csv: str, write_csv: str, out: str, volume: int = 4096):
     cw = statistics.mean(float(b["Counter_Value"]) for _, b in probe)
     ff, fw = PROBE_BYTES / 1024 / cf, PROBE_BYTES / 1024 / cw
 
+    def sel(name, grid=None):
+        return [(a, b) for a, b in zip(F, W) if a["Kernel_Name"].startswith(f"void tslov::{name}(")
+                and (grid is None or a["Grid_Size"] == grid)]
+
     def per(name, grid):
-        sel = [(a, b) for a, b in zip(F, W) if name in a["Kernel_Name"] and a["Grid_Size"] == grid]
-        return (len(sel), statistics.mean(float(a["Counter_Value"]) for a, _ in sel),
-                statistics.mean(float(b["Counter_Value"]) for _, b in sel))
+        s = sel(name, grid)
+        return (len(s), statistics.mean(float(a["Counter_Value"]) for a, _ in s),
+                statistics.mean(float(b["Counter_Value"]) for _, b in s))
 
     V = volume
-    alg = {"k_fwd_pair<double>": V * (6 * 12 + 36) * 16, "k_bwd_rb<double, false>": V * (12 * 12 + 36) * 16,
-           "k_recur<double>": V * 8 * 12 * 16, "k_bwd_ra<double>": V * 10 * 12 * 16}
-    grids = {"k_fwd_pair<double>": str((V + 63) // 64 * 192), "k_bwd_rb<double, false>": str((V + 63) // 64 * 192),
-             "k_recur<double>": str((V + 255) // 256 * 256 * 12), "k_bwd_ra<double>": str((V + 255) // 256 * 256 * 12)}
+    ncol = 3 * (((V + 63) // 64 + 7) // 8 * 8) * 64    # colour-grid threads at this volume
+    npt = (V + 255) // 256 * 256 * 12                  # pointwise kernels
+    rows = {"k_fwd_pair<double, 64>": (str(ncol), V * (6 * 12 + 36) * 16),
+            "k_bwd_rb<double, false, 64>": (str(ncol), V * (12 * 12 + 36) * 16),
+            "k_recur<double>": (str(npt), V * 8 * 12 * 16),
+            "k_bwd_ra<double>": (str(npt), V * 10 * 12 * 16)}
     lines = ["# HBM traffic per dispatch from rocprofv3 counters, 8^4 workload (V=4096, k=200, FP64)",
              "#",
              "# commands (repository root on the GPU box as $REPO), one counter per pass:",
@@ -57,22 +63,36 @@ def main(fetch_csv: str, write_csv: str, out: str, volume: int = 4096):
              f"# calibration: the probe's three 1 GiB device copies read FETCH_SIZE {cf:.1f} KiB and",
              f"#   WRITE_SIZE {cw:.1f} KiB per dispatch: scale factors fetch x{ff:.4f}, write x{fw:.4f}",
              "#",
-             "# kernel                       grid   dispatches  FETCH_KiB  WRITE_KiB  hbm_bytes(scaled)  algorithmic"]
+             "# kernel                          grid   dispatches  FETCH_KiB  WRITE_KiB  hbm_bytes(scaled)  algorithmic"]
     res = {}
-    for name, grid in grids.items():
+    for name, (grid, alg) in rows.items():
         n, f, w = per(name, grid)
         res[name] = (f * ff + w * fw) * 1024
-        lines.append(f"{name:28s} {grid:>7s} {n:10d} {f:10.1f} {w:10.1f} {res[name]:18.0f} {alg[name]:12d}")
+        lines.append(f"{name:31s} {grid:>7s} {n:10d} {f:10.1f} {w:10.1f} {res[name]:18.0f} {alg:12d}")
+    # the 32^4 operator of the stencil benchmark (site per thread, XCD-padded grid)
+    V4 = 32 ** 4
+    g4 = str((V4 // 128 + 7) // 8 * 8 * 128)
     try:
-        n, f, w = per("k_apply<double>", str(32 ** 4 // 64 * 192))
-        lines.append(f"{'k_apply<double> (32^4)':28s} {str(32 ** 4 // 64 * 192):>7s} {n:10d} {f:10.1f} {w:10.1f} "
-                     f"{(f * ff + w * fw) * 1024:18.0f} {32 ** 4 * 60 * 16:12d}")
+        n, f, w = per("k_apply_site<double>", g4)
+        lines.append(f"{'k_apply_site<double> (32^4)':31s} {g4:>7s} {n:10d} {f:10.1f} {w:10.1f} "
+                     f"{(f * ff + w * fw) * 1024:18.0f} {V4 * 60 * 16:12d}")
     except statistics.StatisticsError:
         pass
+    # the batched 6x18^3 workload's stencil pair (colour split, XCD-padded grid of
+    # 552 site blocks per source): per source and step, over all its dispatches
+    Vb, per_src = 6 * 18 ** 3, 552 * 192
+    for name, planes in (("k_fwd_pair<double, 192>", 6 * 12 + 36), ("k_bwd_rb<double, false, 192>", 12 * 12 + 36)):
+        s_ = sel(name)
+        steps = sum(int(a["Grid_Size"]) // per_src for a, _ in s_)
+        if steps:
+            f = sum(float(a["Counter_Value"]) for a, _ in s_) / steps
+            w = sum(float(b["Counter_Value"]) for _, b in s_) / steps
+            lines.append(f"{name + ' (6x18^3)':31s} {'/src':>7s} {steps:10d} {f:10.1f} {w:10.1f} "
+                         f"{(f * ff + w * fw) * 1024:18.0f} {Vb * planes * 16:12d}")
     lines += ["#", "# read by bench.py (the dominant stencil kernel of the timed 8^4 step):",
-              "kernel: k_bwd_rb<double, false>",
-              f"hbm_bytes_per_launch: {res['k_bwd_rb<double, false>']:.0f}",
-              f"fwd_pair_hbm_bytes_per_launch: {res['k_fwd_pair<double>']:.0f}",
+              "kernel: k_bwd_rb<double, false, 64>",
+              f"hbm_bytes_per_launch: {res['k_bwd_rb<double, false, 64>']:.0f}",
+              f"fwd_pair_hbm_bytes_per_launch: {res['k_fwd_pair<double, 64>']:.0f}",
               f"kernel_source_sha256_16: {kernel_source_hash()}"]
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
