@@ -165,6 +165,17 @@ __device__ __forceinline__ void fstore(FieldBase f, int ldv, int pl, unsigned s,
     *reinterpret_cast<Z<R>*>(plane + (size_t)(unsigned)(s * (unsigned)sizeof(Z<R>))) = v;
 }
 
+// Streaming store: for results that the next reader, a kernel whose blocks sit on
+// other XCDs, takes from memory anyway; they then do not displace operands that
+// this kernel's neighbouring blocks still read from L2.
+template <typename R>
+__device__ __forceinline__ void fstore_nt(FieldBase f, int ldv, int pl, unsigned s, Z<R> v) {
+    char* plane = uniform_ptr(f.p + (size_t)pl * (size_t)ldv * sizeof(Z<R>));
+    R* q = reinterpret_cast<R*>(plane + (size_t)(unsigned)(s * (unsigned)sizeof(Z<R>)));
+    __builtin_nontemporal_store(v.re, q);
+    __builtin_nontemporal_store(v.im, q + 1);
+}
+
 template <typename R>
 __device__ __forceinline__ void load_spinor(Spinor<R>& p, const Z<R>* __restrict__ f, int ldv, int s) {
     const FieldBase r = field_base(f);
@@ -204,25 +215,28 @@ __device__ __forceinline__ void load_link(Z<R> (&u)[3][3], const Z<R>* __restric
 // (1 + S g_nu) psi has rank 2: it equals [h; L h] with the half spinor
 // h = psi_up + S * (-i s_k or 1) psi_dn and L the lower-block map.  PROJ<NU, S>
 // gives h from psi and the two lower spin components from h.
+// One colour: (h0, h1) from the spin components (p0, p1, p2, p3).
+template <int NU, int S, typename R>
+__device__ __forceinline__ void project_col(Z<R> p0, Z<R> p1, Z<R> p2, Z<R> p3, Z<R>& h0, Z<R>& h1) {
+    if (NU == 0) {          // -i s_1 psi_dn = (-i p3, -i p2)
+        h0 = (S > 0) ? p0 + timesMinusI(p3) : p0 + timesI(p3);
+        h1 = (S > 0) ? p1 + timesMinusI(p2) : p1 + timesI(p2);
+    } else if (NU == 1) {   // -i s_2 psi_dn = (-p3, p2)
+        h0 = (S > 0) ? p0 - p3 : p0 + p3;
+        h1 = (S > 0) ? p1 + p2 : p1 - p2;
+    } else if (NU == 2) {   // -i s_3 psi_dn = (-i p2, i p3)
+        h0 = (S > 0) ? p0 + timesMinusI(p2) : p0 + timesI(p2);
+        h1 = (S > 0) ? p1 + timesI(p3) : p1 + timesMinusI(p3);
+    } else {                // g_4: psi_dn
+        h0 = (S > 0) ? p0 + p2 : p0 - p2;
+        h1 = (S > 0) ? p1 + p3 : p1 - p3;
+    }
+}
+
 template <int NU, int S, typename R>
 __device__ __forceinline__ void project(const Spinor<R>& p, Z<R> (&h)[2][3]) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const Z<R> p0 = p.c[0][c], p1 = p.c[1][c], p2 = p.c[2][c], p3 = p.c[3][c];
-        if (NU == 0) {          // -i s_1 psi_dn = (-i p3, -i p2)
-            h[0][c] = (S > 0) ? p0 + timesMinusI(p3) : p0 + timesI(p3);
-            h[1][c] = (S > 0) ? p1 + timesMinusI(p2) : p1 + timesI(p2);
-        } else if (NU == 1) {   // -i s_2 psi_dn = (-p3, p2)
-            h[0][c] = (S > 0) ? p0 - p3 : p0 + p3;
-            h[1][c] = (S > 0) ? p1 + p2 : p1 - p2;
-        } else if (NU == 2) {   // -i s_3 psi_dn = (-i p2, i p3)
-            h[0][c] = (S > 0) ? p0 + timesMinusI(p2) : p0 + timesI(p2);
-            h[1][c] = (S > 0) ? p1 + timesI(p3) : p1 + timesMinusI(p3);
-        } else {                // g_4: psi_dn
-            h[0][c] = (S > 0) ? p0 + p2 : p0 - p2;
-            h[1][c] = (S > 0) ? p1 + p3 : p1 - p3;
-        }
-    }
+    for (int c = 0; c < 3; ++c) project_col<NU, S>(p.c[0][c], p.c[1][c], p.c[2][c], p.c[3][c], h[0][c], h[1][c]);
 }
 
 // acc += coef * [h; L h]

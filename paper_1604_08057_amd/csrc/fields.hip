@@ -152,6 +152,12 @@ __device__ __forceinline__ void store1(Z<R>* __restrict__ f, int ldv, int a, int
 }
 
 template <typename R>
+__device__ __forceinline__ void store1_nt(Z<R>* __restrict__ f, int ldv, int a, int s, const Z<R> (&p)[4]) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) fstore_nt<R>(field_base(f), ldv, sp * 3 + a, (unsigned)s, p[sp]);
+}
+
+template <typename R>
 __device__ __forceinline__ void zero1(Z<R> (&p)[4]) {
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp) p[sp] = mk<R>(0, 0);
@@ -513,10 +519,10 @@ __global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Ge
             pv[1] += wa.im;
             pv[2] += norm2(ad);
         }
-        store1(wk.v(slot, j), g.ldv, a, s, v);
-        store1(wk.w(slot, j), g.ldv, a, s, w);
-        store1(wk.a(slot, j), g.ldv, a, s, av);
-        store1(wk.b(slot, j), g.ldv, a, s, bv);
+        store1_nt(wk.v(slot, j), g.ldv, a, s, v);
+        store1_nt(wk.w(slot, j), g.ldv, a, s, w);
+        store1_nt(wk.a(slot, j), g.ldv, a, s, av);
+        store1_nt(wk.b(slot, j), g.ldv, a, s, bv);
         if (has_eta) {
             Z<R> e[4];
             load1(e, wk.f(slot, 1), g.ldv, a, s);
@@ -789,9 +795,9 @@ __global__ __launch_bounds__(BLK) void k_bwd_rb(const Z<R>* __restrict__ U, Geom
             d2r += x2.re;
             d2i += x2.im;
         }
-        store1(wk.f(slot, 4), g.ldv, a, s, vbo);
-        store1(wk.f(slot, 5), g.ldv, a, s, wbo);
-        store1(wk.ab(slot, j), g.ldv, a, s, abo);
+        store1_nt(wk.f(slot, 4), g.ldv, a, s, vbo);
+        store1_nt(wk.f(slot, 5), g.ldv, a, s, wbo);
+        store1_nt(wk.ab(slot, j), g.ldv, a, s, abo);
         pv[0] = d1;
         pv[1] = d2r;
         pv[2] = d2i;
