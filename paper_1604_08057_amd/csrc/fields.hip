@@ -163,23 +163,6 @@ __device__ __forceinline__ void zero1(Z<R> (&p)[4]) {
     for (int sp = 0; sp < 4; ++sp) p[sp] = mk<R>(0, 0);
 }
 
-// Both hops of direction NU for one field (colour a):
-// acc += cf (1+g) U(x) f(x+nu) + cb (1-g) U(x-nu)^dag f(x-nu); f optionally g5-multiplied.
-template <int NU, typename R>
-__device__ __forceinline__ void hop_dir1(Z<R> (&acc)[4], const Z<R>* __restrict__ U, const Z<R>* __restrict__ f,
-                                         const Geom& g, int s, int a, const Nbr& n, R cf, R cb, int g5_in) {
-    Z<R> u[3];
-    Spinor<R> p;
-    load_row(u, U, g.ldv, NU, a, s);
-    load_spinor(p, f, g.ldv, n.fwd[NU]);
-    if (g5_in) g5_inplace(p);
-    hop1<NU, +1>(acc, u, p, cf);
-    load_col_conj(u, U, g.ldv, NU, a, n.bwd[NU]);
-    load_spinor(p, f, g.ldv, n.bwd[NU]);
-    if (g5_in) g5_inplace(p);
-    hop1<NU, -1>(acc, u, p, cb);
-}
-
 // Both hops of direction NU for two fields sharing the link rows: field A at +mu,
 // field B at -mu (the temporal factors swap).
 template <int NU, typename R>
@@ -201,10 +184,13 @@ __device__ __forceinline__ void hop_dir_pair1(Z<R> (&acca)[4], Z<R> (&accb)[4], 
     hop1<NU, -1>(accb, u, p, up);
 }
 
-// The same two directions' worth of hops with every load of the direction issued
-// before any arithmetic (the compiler barrier keeps the scheduler from sinking the
-// loads to their uses): one memory round trip per direction instead of one per
-// loaded operand, at the cost of holding all operands of a direction in registers.
+// Both hops of direction NU for one field (colour a):
+//   acc += cf (1+g) U(x) f(x+nu) + cb (1-g) U(x-nu)^dag f(x-nu), f optionally g5-multiplied,
+// with every load of the direction issued before any arithmetic (the compiler
+// barrier keeps the scheduler from sinking the loads to their uses): one memory
+// round trip per direction instead of one per loaded operand, at the cost of
+// holding all operands of a direction in registers.  The pair version below does
+// the same for two fields sharing the link rows.
 template <int NU, typename R>
 __device__ __forceinline__ void hop_dir1_eager(Z<R> (&acc)[4], const Z<R>* __restrict__ U,
                                                const Z<R>* __restrict__ f, const Geom& g, int s, int a, const Nbr& n,
@@ -244,34 +230,11 @@ __device__ __forceinline__ void hop_dir_pair1_eager(Z<R> (&acca)[4], Z<R> (&accb
     hop1<NU, -1>(accb, ub, pbb, up);
 }
 
-// All eight hops of one field (colour a), a rolled loop over a wavefront-uniform
-// switch.  Colour split (several wavefronts per SIMD): one operand's loads in
-// flight at a time, few registers.  Colour grid (small lattices, where a wavefront
-// has its SIMD to itself): a whole direction's loads in flight at a time.
-template <int BLK, typename R>
-__device__ __forceinline__ void hop_all1(Z<R> (&acc)[4], const Z<R>* __restrict__ U, const Z<R>* __restrict__ f,
-                                         const Geom& g, int s, int a, const Nbr& n, R ep, R em, int g5_in) {
-#pragma unroll 1
-    for (int nu = 0; nu < 4; ++nu) {
-        if constexpr (BLK == kSites) {
-            switch (nu) {
-                case 0: hop_dir1_eager<0>(acc, U, f, g, s, a, n, R(1), R(1), g5_in); break;
-                case 1: hop_dir1_eager<1>(acc, U, f, g, s, a, n, R(1), R(1), g5_in); break;
-                case 2: hop_dir1_eager<2>(acc, U, f, g, s, a, n, R(1), R(1), g5_in); break;
-                default: hop_dir1_eager<3>(acc, U, f, g, s, a, n, ep, em, g5_in); break;
-            }
-        } else {
-            switch (nu) {
-                case 0: hop_dir1<0>(acc, U, f, g, s, a, n, R(1), R(1), g5_in); break;
-                case 1: hop_dir1<1>(acc, U, f, g, s, a, n, R(1), R(1), g5_in); break;
-                case 2: hop_dir1<2>(acc, U, f, g, s, a, n, R(1), R(1), g5_in); break;
-                default: hop_dir1<3>(acc, U, f, g, s, a, n, ep, em, g5_in); break;
-            }
-        }
-    }
-}
-
-// Same for two fields sharing the link rows (A at +mu, B at -mu).
+// All eight hops of two fields (colour a) sharing the link rows (A at +mu, B at
+// -mu), a rolled loop over a wavefront-uniform switch.  Colour split (several
+// wavefronts per SIMD): one operand's loads in flight at a time, few registers.
+// Colour grid (small lattices, where a wavefront has its SIMD to itself): a whole
+// direction's loads in flight at a time.
 template <int BLK, typename R>
 __device__ __forceinline__ void hop_all_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
                                              const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
@@ -297,17 +260,26 @@ __device__ __forceinline__ void hop_all_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], c
 }
 
 // =============================================================== operator
-template <typename R, int BLK>
-__global__ __launch_bounds__(BLK) void k_apply(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
-                                               Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em, int g5_in,
-                                               int g5_out) {
-    const int a = sten_colour<BLK>();
-    const int s = sten_site<BLK>(a);
+// Colour grid (small lattices): block (a, b) forms colour a of site block b.
+template <typename R>
+__global__ __launch_bounds__(kSites) void k_apply(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+                                                  Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em, int g5_in,
+                                                  int g5_out) {
+    const int a = sten_colour<kSites>();
+    const int s = sten_site<kSites>(a);
     if (s >= g.V) return;
     const Nbr n = neighbours(g, s);
     Z<R> acc[4];
     zero1(acc);
-    hop_all1<BLK>(acc, U, in, g, s, a, n, ep, em, g5_in);
+#pragma unroll 1
+    for (int nu = 0; nu < 4; ++nu) {
+        switch (nu) {
+            case 0: hop_dir1_eager<0>(acc, U, in, g, s, a, n, R(1), R(1), g5_in); break;
+            case 1: hop_dir1_eager<1>(acc, U, in, g, s, a, n, R(1), R(1), g5_in); break;
+            case 2: hop_dir1_eager<2>(acc, U, in, g, s, a, n, R(1), R(1), g5_in); break;
+            default: hop_dir1_eager<3>(acc, U, in, g, s, a, n, ep, em, g5_in); break;
+        }
+    }
     mem_fence_compiler();
     Z<R> x[4];
     load1(x, in, g.ldv, a, s);
@@ -322,13 +294,25 @@ __global__ __launch_bounds__(BLK) void k_apply(const Z<R>* __restrict__ U, const
 
 // Site per thread (lattices above the colour grid's range): each thread forms all
 // three colours of its site, so every neighbour spinor and link passes through the
-// compute unit's L1 once per site instead of once per colour wavefront; blocks go
-// out in XCD order.
+// compute unit's L1 once per site instead of once per colour wavefront.  Blocks go
+// out in XCD order: when the site blocks of a t-slice split evenly over the XCDs,
+// each XCD takes the same run of them in every slice, slice after slice, so that a
+// site's t-neighbours were read one run earlier on the same L2; otherwise each
+// XCD takes a contiguous run of the lattice.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_apply_site(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
                                                        Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em,
-                                                       int g5_in, int g5_out) {
-    const int s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+                                                       int g5_in, int g5_out, int slice_order) {
+    int sb;
+    if (slice_order) {
+        // each XCD takes the same run of site blocks in every t-slice, t outermost:
+        // a site's t-neighbours were touched one slice's run earlier on this XCD
+        const int n3 = g.nx * g.ny * g.nz / kBlock, per = n3 / kXcd, m = blockIdx.x / kXcd;
+        sb = (m / per) * n3 + (blockIdx.x % kXcd) * per + m % per;
+    } else {
+        sb = xcd_block(blockIdx.x, gridDim.x);
+    }
+    const int s = sb * kBlock + threadIdx.x;
     if (s >= g.V) return;
     const Nbr n = neighbours(g, s);
     Spinor<R> acc;
@@ -393,12 +377,13 @@ template <typename R>
 void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu, int g5_in,
                   int g5_out, hipStream_t st, Timing t) {
     if (colour_grid(g.V)) {
-        timed_launch(k_apply<R, kSites>, dim3(np_sten(g.V)), dim3(kSites), st, t, U, in, out, g, (R)kappa,
+        timed_launch(k_apply<R>, dim3(np_sten(g.V)), dim3(kSites), st, t, U, in, out, g, (R)kappa,
                      (R)std::exp(mu), (R)std::exp(-mu), g5_in, g5_out);
     } else {
         const int nb = (grid_for(g.V) + kXcd - 1) / kXcd * kXcd;
+        const int slice = (g.nx * g.ny * g.nz) % (kBlock * kXcd) == 0;   // t-slices split evenly over XCDs
         timed_launch(k_apply_site<R>, dim3(nb), dim3(kBlock), st, t, U, in, out, g, (R)kappa, (R)std::exp(mu),
-                     (R)std::exp(-mu), g5_in, g5_out);
+                     (R)std::exp(-mu), g5_in, g5_out, slice);
     }
 }
 
