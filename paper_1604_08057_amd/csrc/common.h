@@ -11,8 +11,8 @@ namespace tslov {
 
 constexpr int kWave = 64;      // CDNA wavefront
 constexpr int kBlock = 128;    // threads per block of the simple per-site kernels
-constexpr int kSites = 64;     // sites per block of the colour-split stencil kernels
-constexpr int kCBlock = 3 * kSites;   // one wavefront per colour
+constexpr int kSites = 64;     // sites per wavefront (and site block) of the colour-layout stencil kernels
+constexpr int kCBlock = 3 * kSites;   // colour split: one wavefront per colour
 constexpr int kPBlock = 256;   // pointwise kernels: sites per block, grid.y = 12 planes
 
 constexpr int kXcd = 8;        // accelerator complex dies; workgroups go to them round robin
@@ -302,8 +302,8 @@ __device__ __forceinline__ void hop_bwd(Spinor<R>& acc, const Z<R> (&u)[3][3], c
 }
 
 // ------------------------------------------------------------------ one colour
-// Colour-split stencil: a thread owns colour a of a site.  For a hop it needs
-// the neighbour's full half spinor h[2][3] and one row of the (adjoint) link.
+// Colour layouts: a thread owns colour a of a site.  For a hop it needs the
+// neighbour's full half spinor h[2][3] and one row of the (adjoint) link.
 template <int NU, int S, typename R>
 __device__ __forceinline__ void recon1_add(Z<R> (&acc)[4], const Z<R> (&o)[2], R coef) {
     const Z<R> h0 = coef * o[0], h1 = coef * o[1];
@@ -342,8 +342,8 @@ __device__ __forceinline__ void load_col_conj(Z<R> (&u)[3], const Z<R>* __restri
     for (int b = 0; b < 3; ++b) u[b] = cj(fload<R>(field_base(U), ldv, nu * 9 + b * 3 + a, (unsigned)s));
 }
 
-// Colour handled by this thread in the colour-split kernels: one wavefront per
-// colour, made explicit as a scalar so plane addresses stay uniform.
+// Colour handled by this thread in the colour split: one wavefront per colour,
+// made explicit as a scalar so plane addresses stay uniform.
 __device__ __forceinline__ int wave_colour() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kSites); }
 
 // Colour and site of this thread in a stencil kernel of BLK threads per block:

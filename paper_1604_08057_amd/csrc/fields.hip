@@ -135,10 +135,12 @@ void launch_spinor_from_soa(const Z<R>* in, ZD* out, const Geom& g, hipStream_t 
 
 // =============================================================== stencil layouts
 // One thread per (site, colour), 64 consecutive sites per wavefront, so that every
-// load instruction touches 64 consecutive sites of one plane.  Colour split: blocks
-// of 3 wavefronts, wavefront a handles colour a.  Colour grid (small lattices):
-// single-wavefront blocks, block (a, b) handles colour a of site block b, which
-// spreads the three colours of a site over three compute units.
+// load instruction touches 64 consecutive sites of one plane.  Colour grid (small
+// lattices): single-wavefront blocks, block (a, b) handles colour a of site block b,
+// which spreads the three colours of a site over three compute units.  Colour split
+// (the Lanczos pair kernels on larger lattices): blocks of 3 wavefronts, wavefront a
+// handles colour a.  The operator on larger lattices uses one thread per site
+// (k_apply_site).
 template <typename R>
 __device__ __forceinline__ void load1(Z<R> (&p)[4], const Z<R>* __restrict__ f, int ldv, int a, int s) {
 #pragma unroll
