@@ -455,14 +455,21 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
 }
 
 // Sum of per-block partials part[b*NV + i], b < nparts, in a fixed order; every
-// block that calls this gets bit-identical results.
+// block that calls this gets bit-identical results.  gather_partials is the first
+// half (each thread's strided share, no barrier), so that a kernel can issue these
+// loads together with others and finish the sum with block_sum later.
 template <int NV, int BLK>
-__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nparts, double (&out)[NV]) {
+__device__ __forceinline__ void gather_partials(const double* __restrict__ part, int nparts, double (&out)[NV]) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) out[i] = 0.0;
     for (int b = threadIdx.x; b < nparts; b += BLK)
 #pragma unroll
         for (int i = 0; i < NV; ++i) out[i] += part[b * NV + i];
+}
+
+template <int NV, int BLK>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nparts, double (&out)[NV]) {
+    gather_partials<NV, BLK>(part, nparts, out);
     block_sum<NV, BLK>(out);
 }
 

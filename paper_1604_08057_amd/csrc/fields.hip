@@ -435,12 +435,25 @@ __global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Ge
                                                       int has_eta) {
     const int slot = L.slot[blockIdx.y];
     const Coef coef = coef0.at(slot);
-    if (block_flag(coef.status)) return;
     const int first = j == 1;
     const Z<R>* rin = wk.f(slot, first ? 0 : 2);
     const Z<R>* sin = wk.f(slot, first ? 0 : 3);
+    // the partial sums' loads share a round trip with the flag read; the hops do not
+    // depend on the sums (normalisation and breakdown act in the epilogue), so they
+    // run before the sums are combined, and a breakdown step discards them
     double red[kNvRecur];
-    reduce_partials<kNvRecur, BLK>(wk.p(slot, 1), npart_in, red);
+    gather_partials<kNvRecur, BLK>(wk.p(slot, 1), npart_in, red);
+    if (block_flag(coef.status)) return;
+    const int a = sten_colour<BLK>();
+    const int s = sten_site<BLK>(a);
+    Z<R> acca[4], accb[4];
+    zero1(acca);
+    zero1(accb);
+    if (s < g.V) {
+        hop_all_pair<BLK>(acca, accb, U, rin, sin, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu));
+        mem_fence_compiler();
+    }
+    block_sum<kNvRecur, BLK>(red);
     const ZD om = mk<double>(red[0], red[1]);
     const double rn2 = red[2], sn2 = red[3];
     const double aom = std::sqrt(norm2(om));
@@ -478,17 +491,8 @@ __global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Ge
     }
     const R ib = (R)(1.0 / beta);
     const Z<R> icg = zcast<R>(zdiv(mk<double>(1.0, 0.0), cj(gam)));
-    const int a = sten_colour<BLK>();
-    const int s = sten_site<BLK>(a);
     double pv[kNvPair] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (s < g.V) {
-        const Nbr n = neighbours(g, s);
-        Z<R> acca[4], accb[4];
-        zero1(acca);
-        zero1(accb);
-        const R ep = (R)emu, em = (R)(1.0 / emu);
-        hop_all_pair<BLK>(acca, accb, U, rin, sin, g, s, a, n, ep, em);
-        mem_fence_compiler();
         Z<R> r0[4], s0[4], v[4], w[4], av[4], bv[4];
         load1(r0, rin, g.ldv, a, s);
         load1(s0, sin, g.ldv, a, s);
@@ -545,9 +549,26 @@ template <typename R>
 __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L, Coef coef0, int j, int npart_in) {
     const int e = blockIdx.z, slot = L.slot[e];
     const Coef coef = coef0.at(slot);
-    if (block_flag(coef.status)) return;
+    const int s = blockIdx.x * kPBlock + threadIdx.x;
+    const size_t i = (size_t)blockIdx.y * g.ldv + s;
+    const bool has_prev = j > 1, live = s < g.V && j < L.k[e];
+    // the site's operands and the partial sums first: their loads share one round
+    // trip with the flag read (whose barrier the compiler may not move them across)
+    Z<R> a_i = mk<R>(0, 0), b_i = a_i, v_i = a_i, w_i = a_i, vp_i = a_i, wp_i = a_i;
+    if (live) {
+        a_i = wk.a(slot, j)[i];
+        b_i = wk.b(slot, j)[i];
+        v_i = wk.v(slot, j)[i];
+        w_i = wk.w(slot, j)[i];
+        if (has_prev) {
+            vp_i = wk.v(slot, j - 1)[i];
+            wp_i = wk.w(slot, j - 1)[i];
+        }
+    }
     double red[kNvPair];
-    reduce_partials<kNvPair, kPBlock>(wk.p(slot, 0), npart_in, red);
+    gather_partials<kNvPair, kPBlock>(wk.p(slot, 0), npart_in, red);
+    if (block_flag(coef.status)) return;
+    block_sum<kNvPair, kPBlock>(red);
     const ZD alpha = mk<double>(red[0], red[1]);
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         coef.alpha[j] = alpha;
@@ -556,27 +577,18 @@ __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L
     }
     if (j >= L.k[e]) return;
     const Z<R> al = zcast<R>(alpha), alc = zcast<R>(cj(alpha));
-    const bool has_prev = j > 1;
     const Z<R> gj = has_prev ? zcast<R>(coef.gamma[j]) : mk<R>(0, 0);
     const R bj = has_prev ? (R)coef.beta[j] : R(0);
-    const Z<R>* __restrict__ a = wk.a(slot, j);
-    const Z<R>* __restrict__ b = wk.b(slot, j);
-    const Z<R>* __restrict__ v = wk.v(slot, j);
-    const Z<R>* __restrict__ w = wk.w(slot, j);
-    Z<R>* __restrict__ rout = wk.f(slot, 2);
-    Z<R>* __restrict__ sout = wk.f(slot, 3);
-    const int s = blockIdx.x * kPBlock + threadIdx.x;
     double pv[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
-    if (s < g.V) {
-        const size_t i = (size_t)blockIdx.y * g.ldv + s;
-        Z<R> r = a[i] - al * v[i];
-        Z<R> q = b[i] - alc * w[i];
+    if (live) {
+        Z<R> r = a_i - al * v_i;
+        Z<R> q = b_i - alc * w_i;
         if (has_prev) {
-            r = r - gj * wk.v(slot, j - 1)[i];
-            q = q - bj * wk.w(slot, j - 1)[i];
+            r = r - gj * vp_i;
+            q = q - bj * wp_i;
         }
-        rout[i] = r;
-        sout[i] = q;
+        wk.f(slot, 2)[i] = r;
+        wk.f(slot, 3)[i] = q;
         const double rr = r.re, ri = r.im, qr = q.re, qi = q.im;
         pv[0] = qr * rr + qi * ri;
         pv[1] = qr * ri - qi * rr;
@@ -640,8 +652,26 @@ template <typename R>
 __global__ __launch_bounds__(kPBlock) void k_bwd_ra(Geom g, Work<R> wk, SrcList L, Coef coef0, int j, int npart_in) {
     const int e = blockIdx.z, slot = L.slot[e];
     const Coef coef = coef0.at(slot);
+    const int s = blockIdx.x * kPBlock + threadIdx.x;
+    const size_t i = (size_t)blockIdx.y * g.ldv + s;
+    const bool has_prev = j > 1, live = s < g.V;
+    // the site's operands first: their loads overlap the partial-sum reads below
+    Z<R> vb_i = mk<R>(0, 0), wb_i = vb_i, vn_i = vb_i, wn_i = vb_i, vj_i = vb_i, wj_i = vb_i, vp_i = vb_i,
+         wp_i = vb_i;
+    if (live) {
+        vb_i = wk.f(slot, 4)[i];
+        wb_i = wk.f(slot, 5)[i];
+        vn_i = wk.v(slot, j + 1)[i];
+        wn_i = wk.w(slot, j + 1)[i];
+        vj_i = wk.v(slot, j)[i];
+        wj_i = wk.w(slot, j)[i];
+        if (has_prev) {
+            vp_i = wk.v(slot, j - 1)[i];
+            wp_i = wk.w(slot, j - 1)[i];
+        }
+    }
     double red[kNvRB];
-    reduce_partials<kNvRB, kPBlock>(wk.p(slot, 0), npart_in, red);
+    reduce_partials<kNvRB, kPBlock>(wk.p(slot, 0), npart_in, red);   // its loads join the operands'
     const double D1 = red[0];
     const ZD D2 = mk<double>(red[1], red[2]);
     const double beta = coef.beta[j + 1];
@@ -656,31 +686,20 @@ __global__ __launch_bounds__(kPBlock) void k_bwd_ra(Geom g, Work<R> wk, SrcList 
     const Z<R> c2 = zcast<R>(mulcj(ombar, gam));                 // omegabar conj(gamma)
     const Z<R> c3 = zcast<R>(zdiv(mk<double>(1.0, 0.0), gam));   // 1/gamma
     const Z<R> c4 = zcast<R>(beta * cj(ombar));                  // conj(omegabar) beta
-    const bool has_prev = j > 1;
-    const Z<R>* __restrict__ vbar = wk.f(slot, 4);
-    const Z<R>* __restrict__ wbar = wk.f(slot, 5);
-    const Z<R>* __restrict__ vn = wk.v(slot, j + 1);
-    const Z<R>* __restrict__ wn = wk.w(slot, j + 1);
-    const Z<R>* __restrict__ vj = wk.v(slot, j);
-    const Z<R>* __restrict__ wj = wk.w(slot, j);
-    Z<R>* __restrict__ rbar = wk.f(slot, 6 + (j & 1));
-    Z<R>* __restrict__ sbar = wk.sb(slot, j);
-    const int s = blockIdx.x * kPBlock + threadIdx.x;
     double pv[kNvRA] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (s < g.V) {
-        const size_t i = (size_t)blockIdx.y * g.ldv + s;
-        const Z<R> r = c1 * vbar[i] + c2 * wn[i];
-        const Z<R> q = c3 * wbar[i] + c4 * vn[i];
-        rbar[i] = r;
-        sbar[i] = q;
+    if (live) {
+        const Z<R> r = c1 * vb_i + c2 * wn_i;
+        const Z<R> q = c3 * wb_i + c4 * vn_i;
+        wk.f(slot, 6 + (j & 1))[i] = r;
+        wk.sb(slot, j)[i] = q;
         const ZD rd = zcast<double>(r), qd = zcast<double>(q);
-        const ZD p1 = cjmul(zcast<double>(vj[i]), rd);
-        const ZD p2 = cjmul(qd, zcast<double>(wj[i]));
+        const ZD p1 = cjmul(zcast<double>(vj_i), rd);
+        const ZD p2 = cjmul(qd, zcast<double>(wj_i));
         pv[0] = p1.re; pv[1] = p1.im;
         pv[2] = p2.re; pv[3] = p2.im;
         if (has_prev) {
-            const ZD p3 = cjmul(zcast<double>(wk.v(slot, j - 1)[i]), rd);
-            const ZD p4 = cjmul(zcast<double>(wk.w(slot, j - 1)[i]), qd);
+            const ZD p3 = cjmul(zcast<double>(vp_i), rd);
+            const ZD p4 = cjmul(zcast<double>(wp_i), qd);
             pv[4] = p3.re; pv[5] = p3.im;
             pv[6] = p4.re; pv[7] = p4.im;
         }
@@ -709,41 +728,43 @@ __global__ __launch_bounds__(BLK) void k_bwd_rb(const Z<R>* __restrict__ U, Geom
     const int e = blockIdx.y, slot = L.slot[e];
     const Coef coef = coef0.at(slot);
     const int k_used = L.k[e];
+    const Z<R>* __restrict__ rbar_j = wk.f(slot, 6 + (j & 1));
+    const Z<R>* __restrict__ rbar_n = wk.f(slot, 6 + ((j + 1) & 1));
+    const Z<R>* __restrict__ sbar_j = wk.sb(slot, j);
+    const bool carry = j + 1 < k_used;
+    const Z<R>* __restrict__ sbar_n = carry ? wk.sb(slot, j + 1) : sbar_j;
+    const int a = sten_colour<BLK>();
+    const int s = sten_site<BLK>(a);
+    // the partial sums' loads go out with the hops' loads; only the epilogue needs
+    // the sums, so they are combined after the hops
+    double red[kNvRA];
+    Z<R> accs[4], accr[4];   // field A = sbar_j at +mu, field B = rbar_j at -mu
+    zero1(accs);
+    zero1(accr);
+    if (!LAST) {
+        gather_partials<kNvRA, BLK>(wk.p(slot, 1), npart_in, red);
+        if (s < g.V) {
+            hop_all_pair<BLK>(accs, accr, U, sbar_j, rbar_j, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu));
+            mem_fence_compiler();
+        }
+    }
     ZD abar = coef.abar_T[j];
     if (!LAST) {
-        double red[kNvRA];
-        reduce_partials<kNvRA, BLK>(wk.p(slot, 1), npart_in, red);
+        block_sum<kNvRA, BLK>(red);
         abar = abar - mk<double>(red[0], red[1]) - mk<double>(red[2], red[3]);
         if (blockIdx.x == 0 && threadIdx.x == 0 && j >= 2) {
             coef.gbar_tot[j] = coef.gbar_T[j] - mk<double>(red[4], red[5]);
             coef.bbar_tot[j] = coef.bbar_T[j] - red[6];
         }
     }
-    const Z<R>* __restrict__ rbar_j = wk.f(slot, 6 + (j & 1));
-    const Z<R>* __restrict__ rbar_n = wk.f(slot, 6 + ((j + 1) & 1));
-    const Z<R>* __restrict__ sbar_j = wk.sb(slot, j);
-    const bool carry = j + 1 < k_used;
-    const Z<R>* __restrict__ sbar_n = carry ? wk.sb(slot, j + 1) : sbar_j;
     const Z<R> ca = zcast<R>(abar);
     const ZD alpha = coef.alpha[j];
     const Z<R> alr = zcast<R>(alpha), alc = zcast<R>(cj(alpha)), abc = zcast<R>(cj(abar));
     const Z<R> etac = zcast<R>(coef.misc[0] * cj(coef.c[j]));
     const Z<R> gnc = carry ? zcast<R>(cj(coef.gamma[j + 1])) : mk<R>(0, 0);
     const R bn = carry ? (R)coef.beta[j + 1] : R(0);
-    const int a = sten_colour<BLK>();
-    const int s = sten_site<BLK>(a);
     double pv[kNvRB] = {0.0, 0.0, 0.0};
     if (s < g.V) {
-        Z<R> accs[4], accr[4];
-        zero1(accs);
-        zero1(accr);
-        if (!LAST) {
-            const Nbr n = neighbours(g, s);
-            const R ep = (R)emu, em = (R)(1.0 / emu);
-            // field A = sbar_j at +mu (accs), field B = rbar_j at -mu (accr)
-            hop_all_pair<BLK>(accs, accr, U, sbar_j, rbar_j, g, s, a, n, ep, em);
-            mem_fence_compiler();
-        }
         const R kap = (R)kappa;
         const FieldBase rw = field_base(wk.w(slot, j)), rv = field_base(wk.v(slot, j)),
                      ra = field_base(wk.a(slot, j)), rb = field_base(wk.b(slot, j)),
