@@ -395,7 +395,8 @@ constexpr double kNsSwitch = 1e-2;
 constexpr double kNsSafe = 0.9;
 constexpr double kResidCheck = 0.3;
 
-tslov_status newton(tslov_ctx* c, const SrcList& L, int grad, const DenseWork& w, std::vector<int>& iters) {
+tslov_status newton(tslov_ctx* c, const SrcList& L, int grad, const DenseWork& w, std::vector<int>& iters,
+                    int tridiag_start) {
     struct St {
         int scaling = 1, extra = 0, done = 0, it = 0, ns = 0;
         double prev = INFINITY;
@@ -423,7 +424,7 @@ tslov_status newton(tslov_ctx* c, const SrcList& L, int grad, const DenseWork& w
                 R.flag[R.n] = A.flag[a];
                 ++R.n;
             }
-        if (A.n) tslov::dense_newton_step(A, grad, choose_nb(c, A.k[0]), c->lds_max, w, c->st);
+        if (A.n) tslov::dense_newton_step(A, grad, choose_nb(c, A.k[0]), c->lds_max, w, c->st, tridiag_start && it == 1);
         if (R.n) tslov::dense_residual(R, w, c->st);
         if (B.n) tslov::dense_ns_step(B, grad, w, c->st);
         HIPCHK(hipGetLastError());
@@ -473,7 +474,7 @@ tslov_status dense_step(tslov_ctx* c, const SrcList& L, int grad, std::vector<in
     DenseWork w;
     CHK(ensure_dense(c, c->slots, c->kcap, w));
     tslov::launch_dense_build(c->coef, L, grad, w, c->st);
-    CHK(newton(c, L, grad, w, iters));
+    CHK(newton(c, L, grad, w, iters, 1));   // X_0 = T_k is tridiagonal
     tslov::launch_dense_extract(c->coef, L, grad, w, c->st);
     HIPCHK(hipGetLastError());
     return TSLOV_OK;
@@ -1138,7 +1139,7 @@ tslov_status tslov_dense_sign(tslov_ctx* c, const void* T, int k, const void* E,
     tslov::launch_dense_load((const ZD*)T, (const ZD*)E, k, w, c->st);
     const SrcList L = make_list({0}, {k});
     std::vector<int> it;
-    CHK(newton(c, L, E ? 1 : 0, w, it));
+    CHK(newton(c, L, E ? 1 : 0, w, it, 0));
     const size_t bytes = (size_t)k * k * sizeof(ZD);
     HIPCHK(hipMemcpyAsync(S_out, w.X, bytes, hipMemcpyDeviceToDevice, c->st));
     if (E) HIPCHK(hipMemcpyAsync(L_out, w.Y, bytes, hipMemcpyDeviceToDevice, c->st));

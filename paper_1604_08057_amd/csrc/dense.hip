@@ -525,26 +525,119 @@ void gj_sweep(const SrcList& L, int TC, size_t panel_lds, const DenseWork& w, hi
     }
 }
 
-void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, const DenseWork& w, hipStream_t st) {
-    const int kmax = L.k[0];
-    hipLaunchKernelGGL(k_rowperm_init, dim3(grid_for(kmax, kDB), 1, L.n), dim3(kDB), 0, st, L, w);
-    const size_t panel_lds = (size_t)(kmax * (nb + 1)) * sizeof(ZD) + (size_t)kmax * sizeof(int);
-    // trailing tile: TC columns per block; small enough to spread over many CUs,
-    // large enough to amortise each row's panel load, and within the LDS budget
-    const int tc_want = (kmax - nb) / 96;
-    const int tc_lds = (int)((lds_bytes - 2048) / ((size_t)(kmax + nb) * sizeof(ZD))) - 1;
-    int TC = 1;   // largest power of two <= min(tc_want, tc_lds, 16)
-    while (TC * 2 <= tc_want && TC * 2 <= tc_lds && TC * 2 <= 16) TC *= 2;
-    switch (nb) {
-        case 16: gj_sweep<16>(L, TC, panel_lds, w, st); break;
-        case 8: gj_sweep<8>(L, TC, panel_lds, w, st); break;
-        case 4: gj_sweep<4>(L, TC, panel_lds, w, st); break;
-        case 2: gj_sweep<2>(L, TC, panel_lds, w, st); break;
-        default: gj_sweep<1>(L, TC, panel_lds, w, st); break;
+// Inverse of a tridiagonal X (the first Newton step, X = T_k): Gaussian elimination
+// with partial pivoting on the band (thread 0, O(k): a swap puts a second
+// superdiagonal into U), then one forward and back substitution per column of the
+// identity (thread c, O(k)), written straight into Xinv.  Also the partials of
+// |X^{-1}|_F^2 and |X|_F^2 for the scaling (slot 0 of the scatter partials).
+// Dynamic LDS: k x (multiplier, 1/diagonal, first and second superdiagonal) + k flags.
+__global__ __launch_bounds__(kDB) void k_tridiag_inv(DenseWork w0, SrcList L) {
+    extern __shared__ ZD tb[];
+    const int e = blockIdx.z, k = L.k[e];
+    const DenseWork w = w0.at(L.slot[e]);
+    ZD* mlt = tb;            // elimination multipliers
+    ZD* idd = tb + k;        // 1 / diagonal of U
+    ZD* du = tb + 2 * k;     // first superdiagonal of U
+    ZD* u2 = tb + 3 * k;     // second superdiagonal of U (from row exchanges)
+    int* swp = reinterpret_cast<int*>(tb + 4 * k);
+    const ZD* X = w.X;
+    if (threadIdx.x == 0) {
+        ZD d = X[0];                                       // running diagonal entry of row i
+        ZD up = k > 1 ? X[1] : mk<double>(0, 0);           // running X[i][i+1]
+        for (int i = 0; i + 1 < k; ++i) {
+            const ZD l = X[(size_t)(i + 1) * k + i];       // X[i+1][i]
+            const ZD dn = X[(size_t)(i + 1) * k + i + 1];  // X[i+1][i+1]
+            const ZD un = i + 2 < k ? X[(size_t)(i + 1) * k + i + 2] : mk<double>(0, 0);
+            if (norm2(l) > norm2(d)) {   // exchange rows i and i+1
+                const ZD m = zdiv(d, l);
+                mlt[i] = m;
+                swp[i] = 1;
+                idd[i] = zdiv(mk<double>(1.0, 0.0), l);
+                du[i] = dn;
+                u2[i] = un;
+                d = up - m * dn;
+                up = mk<double>(0, 0) - m * un;
+            } else {
+                const ZD m = zdiv(l, d);
+                mlt[i] = m;
+                swp[i] = 0;
+                idd[i] = zdiv(mk<double>(1.0, 0.0), d);
+                du[i] = up;
+                u2[i] = mk<double>(0, 0);
+                d = dn - m * up;
+                up = un;
+            }
+        }
+        idd[k - 1] = zdiv(mk<double>(1.0, 0.0), d);
+        du[k - 1] = mk<double>(0, 0);
+        u2[k - 1] = mk<double>(0, 0);
     }
+    __syncthreads();
+    double v[2] = {0.0, 0.0};
+    for (int c = threadIdx.x; c < k; c += kDB) {
+        ZD* col = w.Xinv + c;   // column c, stride k (holds y, then x)
+        // forward: the right-hand side e_c is zero above row c, so elimination starts
+        // at step c - 1 (the only earlier step that can move the 1, via an exchange)
+        ZD cur = mk<double>(0, 0);   // running y[i]
+        for (int i = 0; i < c - 1; ++i) col[(size_t)i * k] = mk<double>(0, 0);
+        int i0 = c > 0 ? c - 1 : 0;
+        if (c == 0) cur = mk<double>(1.0, 0.0);
+        for (int i = i0; i + 1 < k; ++i) {
+            ZD nxt = (i + 1 == c) ? mk<double>(1.0, 0.0) : mk<double>(0, 0);   // original y[i+1]
+            if (swp[i]) {
+                const ZD t = cur;
+                cur = nxt;
+                nxt = t;
+            }
+            col[(size_t)i * k] = cur;
+            cur = nxt - mlt[i] * cur;
+        }
+        col[(size_t)(k - 1) * k] = cur;
+        // back substitution with the three diagonals of U
+        ZD x1 = mk<double>(0, 0), x2 = mk<double>(0, 0);   // x[i+1], x[i+2]
+        for (int i = k - 1; i >= 0; --i) {
+            const ZD x = (col[(size_t)i * k] - du[i] * x1 - u2[i] * x2) * idd[i];
+            col[(size_t)i * k] = x;
+            v[0] += norm2(x);
+            x2 = x1;
+            x1 = x;
+        }
+    }
+    for (int idx = threadIdx.x; idx < k * k; idx += kDB) v[1] += norm2(X[idx]);
+    block_sum<2, kDB>(v);
+    if (threadIdx.x == 0) {
+        w.part[2 * w.npart_max] = v[0];
+        w.part[2 * w.npart_max + 1] = v[1];
+    }
+}
+
+void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, const DenseWork& w, hipStream_t st,
+                       int tridiag) {
+    const int kmax = L.k[0];
     const int nblk = grid_for(kmax * kmax, kDB);
-    hipLaunchKernelGGL(k_dense_scatter, dim3(nblk, 1, L.n), dim3(kDB), 0, st, w, L);
-    hipLaunchKernelGGL(k_dense_mu, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, nblk);
+    if (tridiag) {
+        const size_t tl = (size_t)4 * kmax * sizeof(ZD) + (size_t)kmax * sizeof(int);
+        hipLaunchKernelGGL(k_tridiag_inv, dim3(1, 1, L.n), dim3(kDB), tl, st, w, L);
+        hipLaunchKernelGGL(k_dense_mu, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, 1);
+    } else {
+        hipLaunchKernelGGL(k_rowperm_init, dim3(grid_for(kmax, kDB), 1, L.n), dim3(kDB), 0, st, L, w);
+        const size_t panel_lds = (size_t)(kmax * (nb + 1)) * sizeof(ZD) + (size_t)kmax * sizeof(int);
+        // trailing tile: TC columns per block; small enough to spread over many CUs,
+        // large enough to amortise each row's panel load, and within the LDS budget
+        const int tc_want = (kmax - nb) / 96;
+        const int tc_lds = (int)((lds_bytes - 2048) / ((size_t)(kmax + nb) * sizeof(ZD))) - 1;
+        int TC = 1;   // largest power of two <= min(tc_want, tc_lds, 16)
+        while (TC * 2 <= tc_want && TC * 2 <= tc_lds && TC * 2 <= 16) TC *= 2;
+        switch (nb) {
+            case 16: gj_sweep<16>(L, TC, panel_lds, w, st); break;
+            case 8: gj_sweep<8>(L, TC, panel_lds, w, st); break;
+            case 4: gj_sweep<4>(L, TC, panel_lds, w, st); break;
+            case 2: gj_sweep<2>(L, TC, panel_lds, w, st); break;
+            default: gj_sweep<1>(L, TC, panel_lds, w, st); break;
+        }
+        hipLaunchKernelGGL(k_dense_scatter, dim3(nblk, 1, L.n), dim3(kDB), 0, st, w, L);
+        hipLaunchKernelGGL(k_dense_mu, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, nblk);
+    }
     if (grad) {
         dim3 g2(grid_for(kmax, 16), grid_for(kmax, 16), L.n);
         hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w, L, kMXinv, kMY, kMZt, kMZt, 1.0, 0.0, 0);

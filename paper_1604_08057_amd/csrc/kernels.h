@@ -195,7 +195,10 @@ void launch_dense_build(Coef coef, const SrcList& L, int grad, const DenseWork& 
 void launch_dense_load(const ZD* T, const ZD* E, int k, const DenseWork& w, hipStream_t st);
 // One Newton step X <- (mu X + X^{-1}/mu)/2 (and Y) for every entry; flag[e] = 1
 // turns the entry's norm scaling on.  Leaves delta[slot] for the host.
-void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, const DenseWork& w, hipStream_t st);
+// tridiag: X is tridiagonal (the first step from T_k); its inverse then comes from a
+// banded elimination instead of the Gauss-Jordan sweep.
+void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, const DenseWork& w, hipStream_t st,
+                       int tridiag);
 // One inverse-free (Newton-Schulz) step X <- X (3 - X^2)/2 and, if grad, the
 // Frechet block Y <- [Y (3 - X^2) - X (X Y + Y X)]/2; leaves delta[slot].
 void dense_ns_step(const SrcList& L, int grad, const DenseWork& w, hipStream_t st);
