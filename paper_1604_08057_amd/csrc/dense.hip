@@ -534,6 +534,7 @@ void gj_sweep(const SrcList& L, int TC, size_t panel_lds, const DenseWork& w, hi
 __global__ __launch_bounds__(kDB) void k_tridiag_inv(DenseWork w0, SrcList L) {
     extern __shared__ ZD tb[];
     const int e = blockIdx.z, k = L.k[e];
+    if (k <= 0) return;   // empty entries never reach the dense step; keep the indexing safe anyway
     const DenseWork w = w0.at(L.slot[e]);
     ZD* mlt = tb;            // elimination multipliers
     ZD* idd = tb + k;        // 1 / diagonal of U
