@@ -82,6 +82,33 @@ constexpr int kMaxDeflSet = 256;
 constexpr int kTimingClasses = 3;
 constexpr int kMaxSources = 1 << 20;
 
+// Site-block order of the colour-split and force kernels (Geom::sbmap; workgroup i
+// runs on XCD i % 8).  When one XCD's share of a t-slice, at the stencil pair's
+// bytes per site, fits in half an XCD's L2, each XCD takes the same segment of
+// every t-slice with t outermost: a site's t-neighbours were then touched one
+// segment earlier on the same L2, and only z-neighbours across segment edges come
+// from memory.  Otherwise each XCD takes a contiguous run of the lattice.  The lists
+// are padded to equal length with -1 (idle workgroups).
+std::vector<int> site_block_order(const Geom& g, int& nwg) {
+    const int nsb = tslov::nsb_pad(g.V), kx = tslov::kXcd;
+    const long long V3 = (long long)g.nx * g.ny * g.nz;
+    constexpr double kPairBytesPerSite = 1728.0;          // links + six fields, FP64
+    constexpr double kL2Budget = 2.0 * 1024.0 * 1024.0;   // half of an XCD's 4 MB
+    const bool seg = (double)V3 / kx * kPairBytesPerSite <= kL2Budget;
+    std::vector<std::vector<int>> per(kx);
+    for (int b = 0; b < nsb; ++b) {
+        const long long pos = ((long long)b * tslov::kSites) % V3;   // first site's place in its slice
+        per[seg ? (int)(pos * kx / V3) : b / (nsb / kx)].push_back(b);
+    }
+    size_t m = 0;
+    for (const auto& v : per) m = std::max(m, v.size());
+    nwg = (int)m * kx;
+    std::vector<int> map((size_t)nwg, -1);
+    for (int x = 0; x < kx; ++x)
+        for (size_t i = 0; i < per[x].size(); ++i) map[i * kx + x] = per[x][i];
+    return map;
+}
+
 }  // namespace
 
 struct tslov_ctx {
@@ -93,6 +120,7 @@ struct tslov_ctx {
     size_t lds_max = 65536;
     int links_set = 0;
     Buf U64, U32;
+    Buf sbmap;       // Geom::sbmap
     Buf opf;         // two working-precision fields for the plain operator
     // batch workspace: per slot, kcap steps of v, w, a = Hv, b = H^dag w (and
     // abar, sbar for the derivative), kNF fields and kNP partial arrays
@@ -915,6 +943,16 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
     c->st = (hipStream_t)stream;
     tslov_status s = ensure(c->U64, (size_t)36 * c->g.ldv * sizeof(ZD));
     if (s == TSLOV_OK && c->precision == TSLOV_MIXED) s = ensure(c->U32, (size_t)36 * c->g.ldv * sizeof(Z<float>));
+    if (s == TSLOV_OK) {
+        int nwg = 0;
+        const std::vector<int> map = site_block_order(c->g, nwg);
+        s = ensure(c->sbmap, map.size() * sizeof(int));
+        if (s == TSLOV_OK && hipMemcpy(c->sbmap.p, map.data(), map.size() * sizeof(int), hipMemcpyHostToDevice) !=
+                                 hipSuccess)
+            s = fail(TSLOV_ERR_HIP, "copy of the site-block order failed");
+        c->g.sbmap = c->sbmap.as<int>();
+        c->g.nwg = nwg;
+    }
     if (s != TSLOV_OK) {
         tslov_destroy(c);
         return s;
@@ -926,7 +964,7 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
 void tslov_destroy(tslov_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
-    for (Buf* b : {&c->U64, &c->U32, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
+    for (Buf* b : {&c->U64, &c->U32, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
                    &c->fields, &c->part, &c->coefmem, &c->dense, &c->denseInt, &c->densePart, &c->denseDelta,
                    &c->gpart, &c->gsrc, &c->bout, &c->wardp, &c->canon, &c->deflw, &c->deflx, &c->cgf, &c->cgp,
                    &c->cgs})

@@ -30,8 +30,7 @@ __host__ __device__ inline int np_max(int V) { return np_colour(V) > np_point(V)
 // gives the same bits in any batch): the colour grid while the lattice has too few
 // site blocks to occupy the chip with three-wavefront blocks, the colour-split
 // blocks (kCBlock threads, colour = wavefront) above that, with the site blocks
-// padded to a multiple of the XCD count and dealt out so that each XCD works
-// through a contiguous run of them (neighbouring site blocks share an L2).
+// padded to a multiple of the XCD count and dealt out to the XCDs by Geom::sbmap.
 constexpr int kColourGridMaxBlocks = 128;
 __host__ __device__ inline bool colour_grid(int V) { return np_stencil(V) <= kColourGridMaxBlocks; }
 // Blocks (= partial sums) of one stencil launch per source.
@@ -94,6 +93,11 @@ struct Geom {
     int nx, ny, nz, nt;
     int V;      // sites
     int ldv;    // plane stride (V rounded up to 64)
+    // Site-block order of the colour-split and force kernels on larger lattices:
+    // workgroup i works on site block sbmap[i] (-1: nothing).  Workgroup i runs on
+    // XCD i % 8, so the map decides which site blocks share an L2 and in what order.
+    const int* sbmap;
+    int nwg;    // workgroups per entry (a multiple of 8, >= nsb_pad(V))
 };
 
 struct Nbr {
@@ -346,18 +350,20 @@ __device__ __forceinline__ void load_col_conj(Z<R> (&u)[3], const Z<R>* __restri
 // made explicit as a scalar so plane addresses stay uniform.
 __device__ __forceinline__ int wave_colour() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kSites); }
 
-// Colour and site of this thread in a stencil kernel of BLK threads per block:
+// Colour and site block of this thread in a stencil kernel of BLK threads per block:
 // BLK = kSites is the colour grid (grid.x = np_colour, colour-major), BLK = kCBlock
-// the colour split (grid.x = nsb_pad, colour = wavefront, blocks in XCD order).
+// the colour split (grid.x = Geom::nwg, colour = wavefront, site block from
+// Geom::sbmap, -1 for a padding workgroup).  A block's partial-sum slot is its
+// grid index in the colour grid and its site block in the colour split.
 template <int BLK>
 __device__ __forceinline__ int sten_colour() {
     if (BLK == kSites) return blockIdx.x / (gridDim.x / 3);
     return wave_colour();
 }
 template <int BLK>
-__device__ __forceinline__ int sten_site(int a) {
-    if (BLK == kSites) return (blockIdx.x - a * (gridDim.x / 3)) * kSites + threadIdx.x;
-    return xcd_block(blockIdx.x, gridDim.x) * kSites + threadIdx.x % kSites;
+__device__ __forceinline__ int sten_block(const Geom& g) {
+    if (BLK == kSites) return blockIdx.x % (gridDim.x / 3);
+    return g.sbmap[blockIdx.x];
 }
 
 // ------------------------------------------------------------------ force contraction

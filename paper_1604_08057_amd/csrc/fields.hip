@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kSites) void k_apply(const Z<R>* __restrict__ U, co
                                                   Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em, int g5_in,
                                                   int g5_out) {
     const int a = sten_colour<kSites>();
-    const int s = sten_site<kSites>(a);
+    const int s = sten_block<kSites>(g) * kSites + threadIdx.x;
     if (s >= g.V) return;
     const Nbr n = neighbours(g, s);
     Z<R> acc[4];
@@ -443,9 +443,11 @@ __global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Ge
     // run before the sums are combined, and a breakdown step discards them
     double red[kNvRecur];
     gather_partials<kNvRecur, BLK>(wk.p(slot, 1), npart_in, red);
+    const int sb = sten_block<BLK>(g);
+    if (sb < 0) return;   // padding workgroup (uniform over the block)
     if (block_flag(coef.status)) return;
     const int a = sten_colour<BLK>();
-    const int s = sten_site<BLK>(a);
+    const int s = sb * kSites + threadIdx.x % kSites;
     Z<R> acca[4], accb[4];
     zero1(acca);
     zero1(accb);
@@ -525,14 +527,14 @@ __global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Ge
             }
         }
     }
-    write_partials<kNvPair, BLK>(wk.p(slot, 0), pv);
+    write_partials_at<kNvPair, BLK>(wk.p(slot, 0), BLK == kSites ? (int)blockIdx.x : sb, pv);
 }
 
 template <typename R>
 void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
                      Coef coef, int j, int has_eta, hipStream_t st, Timing t) {
     const int npart_in = j == 1 ? grid_for(g.V) : np_point(g.V);
-    const dim3 grid(np_sten(g.V), L.n);
+    const dim3 grid(colour_grid(g.V) ? np_colour(g.V) : g.nwg, L.n);
     if (colour_grid(g.V))
         timed_launch(k_fwd_pair<R, kSites>, grid, dim3(kSites), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
                      npart_in, has_eta);
@@ -733,8 +735,10 @@ __global__ __launch_bounds__(BLK) void k_bwd_rb(const Z<R>* __restrict__ U, Geom
     const Z<R>* __restrict__ sbar_j = wk.sb(slot, j);
     const bool carry = j + 1 < k_used;
     const Z<R>* __restrict__ sbar_n = carry ? wk.sb(slot, j + 1) : sbar_j;
+    const int sb = sten_block<BLK>(g);
+    if (sb < 0) return;   // padding workgroup (uniform over the block)
     const int a = sten_colour<BLK>();
-    const int s = sten_site<BLK>(a);
+    const int s = sb * kSites + threadIdx.x % kSites;
     // the partial sums' loads go out with the hops' loads; only the epilogue needs
     // the sums, so they are combined after the hops
     double red[kNvRA];
@@ -810,13 +814,13 @@ __global__ __launch_bounds__(BLK) void k_bwd_rb(const Z<R>* __restrict__ U, Geom
         pv[1] = d2r;
         pv[2] = d2i;
     }
-    write_partials<kNvRB, BLK>(wk.p(slot, 0), pv);
+    write_partials_at<kNvRB, BLK>(wk.p(slot, 0), BLK == kSites ? (int)blockIdx.x : sb, pv);
 }
 
 template <typename R>
 void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
                    Coef coef, int j, int last, hipStream_t st, Timing t) {
-    const dim3 grid(np_sten(g.V), L.n);
+    const dim3 grid(colour_grid(g.V) ? np_colour(g.V) : g.nwg, L.n);
     const int np = np_point(g.V);
     const bool cg = colour_grid(g.V);
     if (last && cg)
@@ -878,8 +882,9 @@ template <typename R>
 __global__ __launch_bounds__(4 * kSites) void k_force(Geom g, double kappa, double emu, Work<R> wk, SrcList L,
                                                       int nchunk, ZD* __restrict__ gpart) {
     const int nu = __builtin_amdgcn_readfirstlane(threadIdx.x / kSites);
-    const int s = xcd_block(blockIdx.x, gridDim.x) * kSites + threadIdx.x % kSites;
-    if (s >= g.V) return;
+    const int sb = g.sbmap ? g.sbmap[blockIdx.x] : (int)blockIdx.x;
+    const int s = sb * kSites + threadIdx.x % kSites;
+    if (sb < 0 || s >= g.V) return;
     const int e = blockIdx.z, slot = L.slot[e];
     const int k = L.k[e];
     const int chunk = blockIdx.y;
@@ -897,7 +902,7 @@ __global__ __launch_bounds__(4 * kSites) void k_force(Geom g, double kappa, doub
 template <typename R>
 void launch_force(const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L, int nchunk, ZD* gpart,
                   hipStream_t st) {
-    dim3 grid(nsb_pad(g.V), nchunk, L.n);
+    dim3 grid(g.sbmap ? g.nwg : np_stencil(g.V), nchunk, L.n);
     hipLaunchKernelGGL(k_force<R>, grid, dim3(4 * kSites), 0, st, g, kappa, std::exp(mu), wk, L, nchunk, gpart);
 }
 
