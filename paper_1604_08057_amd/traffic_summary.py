@@ -25,6 +25,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def site_workgroups(dims) -> int:
+    """Workgroups per source of the colour-split kernels: the library's site-block
+    order (segments of every t-slice per XCD when a segment's stencil-pair data fits
+    in half an XCD's L2, else contiguous runs), lists padded to equal length."""
+    nx, ny, nz, nt = dims
+    V, V3 = nx * ny * nz * nt, nx * ny * nz
+    nsb = ((V + 63) // 64 + 7) // 8 * 8
+    if V3 / 8 * 1728 > 2 * 1024 * 1024:
+        return nsb
+    per = [0] * 8
+    for b in range(nsb):
+        per[((b * 64) % V3) * 8 // V3] += 1
+    return max(per) * 8
+
+
 def main(fetch_csv: str, write_csv: str, out: str, volume: int = 4096):
     F = list(csv.DictReader(open(fetch_csv)))
     W = list(csv.DictReader(open(write_csv)))
@@ -78,11 +93,11 @@ def main(fetch_csv: str, write_csv: str, out: str, volume: int = 4096):
                      f"{(f * ff + w * fw) * 1024:18.0f} {V4 * 60 * 16:12d}")
     except statistics.StatisticsError:
         pass
-    # the batched 6x18^3 workload's stencil pair (colour split, XCD-padded grid of
-    # 552 site blocks per source): per source and step, over all its dispatches
-    Vb, per_src = 6 * 18 ** 3, 552 * 192
+    # the batched 6x18^3 workload's stencil pair (colour split, site-block order
+    # padded per XCD): per source and step, over all its dispatches
+    Vb, per_src = 6 * 18 ** 3, site_workgroups((18, 18, 18, 6)) * 192
     for name, planes in (("k_fwd_pair<double, 192>", 6 * 12 + 36), ("k_bwd_rb<double, false, 192>", 12 * 12 + 36)):
-        s_ = sel(name)
+        s_ = [(a, b) for a, b in sel(name) if int(a["Grid_Size"]) % per_src == 0]   # this lattice only
         steps = sum(int(a["Grid_Size"]) // per_src for a, _ in s_)
         if steps:
             f = sum(float(a["Counter_Value"]) for a, _ in s_) / steps
