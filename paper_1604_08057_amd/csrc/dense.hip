@@ -526,65 +526,78 @@ void gj_sweep(const SrcList& L, int TC, size_t panel_lds, const DenseWork& w, hi
 }
 
 // Inverse of a tridiagonal X (the first Newton step, X = T_k): Gaussian elimination
-// with partial pivoting on the band (thread 0, O(k): a swap puts a second
-// superdiagonal into U), then one forward and back substitution per column of the
-// identity (thread c, O(k)), written straight into Xinv.  Also the partials of
-// |X^{-1}|_F^2 and |X|_F^2 for the scaling (slot 0 of the scatter partials).
-// Dynamic LDS: k x (multiplier, 1/diagonal, first and second superdiagonal) + k flags.
+// with partial pivoting on the band (thread 0, O(k), operands staged in LDS; a row
+// exchange puts a second superdiagonal into U), then one forward and back
+// substitution per column of the identity (thread c, O(k)), written straight into
+// Xinv; the back substitution reads its stored column in batches of kTriBatch so
+// that the loads overlap.  Also the partials of |X^{-1}|_F^2 and |X|_F^2 for the
+// scaling (slot 0 of the scatter partials).
+// Dynamic LDS: k x (diagonal, sub- and superdiagonal of X, multiplier, 1/diagonal,
+// first and second superdiagonal of U) + k flags.
+constexpr int kTriBatch = 16;
+
+__device__ __forceinline__ ZD zrcp(ZD d) { return (1.0 / norm2(d)) * cj(d); }
+
 __global__ __launch_bounds__(kDB) void k_tridiag_inv(DenseWork w0, SrcList L) {
     extern __shared__ ZD tb[];
     const int e = blockIdx.z, k = L.k[e];
     if (k <= 0) return;   // empty entries never reach the dense step; keep the indexing safe anyway
     const DenseWork w = w0.at(L.slot[e]);
-    ZD* mlt = tb;            // elimination multipliers
-    ZD* idd = tb + k;        // 1 / diagonal of U
-    ZD* du = tb + 2 * k;     // first superdiagonal of U
-    ZD* u2 = tb + 3 * k;     // second superdiagonal of U (from row exchanges)
-    int* swp = reinterpret_cast<int*>(tb + 4 * k);
+    ZD* dg = tb;             // X[i][i]
+    ZD* lo = tb + k;         // X[i+1][i]
+    ZD* hi = tb + 2 * k;     // X[i][i+1]
+    ZD* mlt = tb + 3 * k;    // elimination multipliers
+    ZD* idd = tb + 4 * k;    // 1 / diagonal of U
+    ZD* du = tb + 5 * k;     // first superdiagonal of U
+    ZD* u2 = tb + 6 * k;     // second superdiagonal of U (from row exchanges)
+    int* swp = reinterpret_cast<int*>(tb + 7 * k);
     const ZD* X = w.X;
+    const ZD zero = mk<double>(0, 0);
+    double v[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < k; i += kDB) {
+        dg[i] = X[(size_t)i * k + i];
+        lo[i] = i + 1 < k ? X[(size_t)(i + 1) * k + i] : zero;
+        hi[i] = i + 1 < k ? X[(size_t)i * k + i + 1] : zero;
+        v[1] += norm2(dg[i]) + norm2(lo[i]) + norm2(hi[i]);
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        ZD d = X[0];                                       // running diagonal entry of row i
-        ZD up = k > 1 ? X[1] : mk<double>(0, 0);           // running X[i][i+1]
+        ZD d = dg[0], up = hi[0];   // running row i: X-entries at columns i and i+1
         for (int i = 0; i + 1 < k; ++i) {
-            const ZD l = X[(size_t)(i + 1) * k + i];       // X[i+1][i]
-            const ZD dn = X[(size_t)(i + 1) * k + i + 1];  // X[i+1][i+1]
-            const ZD un = i + 2 < k ? X[(size_t)(i + 1) * k + i + 2] : mk<double>(0, 0);
+            const ZD l = lo[i], dn = dg[i + 1], un = hi[i + 1];
             if (norm2(l) > norm2(d)) {   // exchange rows i and i+1
-                const ZD m = zdiv(d, l);
+                const ZD r = zrcp(l), m = d * r;
                 mlt[i] = m;
                 swp[i] = 1;
-                idd[i] = zdiv(mk<double>(1.0, 0.0), l);
+                idd[i] = r;
                 du[i] = dn;
                 u2[i] = un;
                 d = up - m * dn;
-                up = mk<double>(0, 0) - m * un;
+                up = zero - m * un;
             } else {
-                const ZD m = zdiv(l, d);
+                const ZD r = zrcp(d), m = l * r;
                 mlt[i] = m;
                 swp[i] = 0;
-                idd[i] = zdiv(mk<double>(1.0, 0.0), d);
+                idd[i] = r;
                 du[i] = up;
-                u2[i] = mk<double>(0, 0);
+                u2[i] = zero;
                 d = dn - m * up;
                 up = un;
             }
         }
-        idd[k - 1] = zdiv(mk<double>(1.0, 0.0), d);
-        du[k - 1] = mk<double>(0, 0);
-        u2[k - 1] = mk<double>(0, 0);
+        idd[k - 1] = zrcp(d);
+        du[k - 1] = zero;
+        u2[k - 1] = zero;
     }
     __syncthreads();
-    double v[2] = {0.0, 0.0};
     for (int c = threadIdx.x; c < k; c += kDB) {
         ZD* col = w.Xinv + c;   // column c, stride k (holds y, then x)
         // forward: the right-hand side e_c is zero above row c, so elimination starts
         // at step c - 1 (the only earlier step that can move the 1, via an exchange)
-        ZD cur = mk<double>(0, 0);   // running y[i]
-        for (int i = 0; i < c - 1; ++i) col[(size_t)i * k] = mk<double>(0, 0);
-        int i0 = c > 0 ? c - 1 : 0;
-        if (c == 0) cur = mk<double>(1.0, 0.0);
-        for (int i = i0; i + 1 < k; ++i) {
-            ZD nxt = (i + 1 == c) ? mk<double>(1.0, 0.0) : mk<double>(0, 0);   // original y[i+1]
+        for (int i = 0; i < c - 1; ++i) col[(size_t)i * k] = zero;
+        ZD cur = c == 0 ? mk<double>(1.0, 0.0) : zero;   // running y[i]
+        for (int i = c > 0 ? c - 1 : 0; i + 1 < k; ++i) {
+            ZD nxt = (i + 1 == c) ? mk<double>(1.0, 0.0) : zero;   // untouched y[i+1]
             if (swp[i]) {
                 const ZD t = cur;
                 cur = nxt;
@@ -593,18 +606,28 @@ __global__ __launch_bounds__(kDB) void k_tridiag_inv(DenseWork w0, SrcList L) {
             col[(size_t)i * k] = cur;
             cur = nxt - mlt[i] * cur;
         }
-        col[(size_t)(k - 1) * k] = cur;
-        // back substitution with the three diagonals of U
-        ZD x1 = mk<double>(0, 0), x2 = mk<double>(0, 0);   // x[i+1], x[i+2]
-        for (int i = k - 1; i >= 0; --i) {
-            const ZD x = (col[(size_t)i * k] - du[i] * x1 - u2[i] * x2) * idd[i];
-            col[(size_t)i * k] = x;
-            v[0] += norm2(x);
-            x2 = x1;
-            x1 = x;
+        // back substitution with the three diagonals of U; y[k-1] is still in cur
+        ZD x1 = zero, x2 = zero;   // x[i+1], x[i+2]
+        for (int top = k - 1; top >= 0; top -= kTriBatch) {
+            ZD yb[kTriBatch];
+#pragma unroll
+            for (int t = 0; t < kTriBatch; ++t) {
+                const int r = top - t;
+                yb[t] = r == k - 1 ? cur : (r >= 0 ? col[(size_t)r * k] : zero);
+            }
+#pragma unroll
+            for (int t = 0; t < kTriBatch; ++t) {
+                const int r = top - t;
+                if (r >= 0) {
+                    const ZD x = (yb[t] - du[r] * x1 - u2[r] * x2) * idd[r];
+                    col[(size_t)r * k] = x;
+                    v[0] += norm2(x);
+                    x2 = x1;
+                    x1 = x;
+                }
+            }
         }
     }
-    for (int idx = threadIdx.x; idx < k * k; idx += kDB) v[1] += norm2(X[idx]);
     block_sum<2, kDB>(v);
     if (threadIdx.x == 0) {
         w.part[2 * w.npart_max] = v[0];
@@ -617,7 +640,7 @@ void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, con
     const int kmax = L.k[0];
     const int nblk = grid_for(kmax * kmax, kDB);
     if (tridiag) {
-        const size_t tl = (size_t)4 * kmax * sizeof(ZD) + (size_t)kmax * sizeof(int);
+        const size_t tl = (size_t)7 * kmax * sizeof(ZD) + (size_t)kmax * sizeof(int);
         hipLaunchKernelGGL(k_tridiag_inv, dim3(1, 1, L.n), dim3(kDB), tl, st, w, L);
         hipLaunchKernelGGL(k_dense_mu, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, 1);
     } else {
