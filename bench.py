@@ -16,10 +16,13 @@ The JSON line carries:
   gradient) on one source of the same workload, on the host cores;
 * batched: the 6x18^3 batching workload (32 Z2 sources, k drawn from [100, 400],
   mu = 0.5), all sources in one tslov_sign_grad_batched call (FP64), beside the
-  single-source FP64 path on the first four sources;
+  single-source FP64 path on the first four sources and the same batch with the
+  float32-vector path (sources/s and its error against the FP64 batch);
 * precision: the 14^4 workload (k = 400) single source, FP64, with the
   float32-vector path's error against it;
 * mixed: the float32-vector path on the 8^4 workload (sources/s, errors vs FP64);
+* graphs: the 8^4 step with its Lanczos loops launched and replayed as HIP
+  graphs, both without kernel timing;
 * stencil_large: the FP64 Wilson stencil alone on a 32^4 lattice (1.15 GB per
   application, above the 256 MB last-level cache) for the HBM-bound figure.
 With --copy-probe a 1 GiB device-to-device copy runs first (HBM counter
@@ -86,6 +89,31 @@ def time_steps(ctx, eta, psi, k, steps, warmup, dU, timing=False):
     if timing:
         ctx.timing_enable(0)
     return (t1 - t0), S, info
+
+
+def graph_leg(steps: int = 20):
+    """The 8^4 step with the Lanczos loops launched and replayed as HIP graphs (no
+    kernel timing; the context on a side stream, which capture needs)."""
+    import numpy as np
+    import torch
+    from paper_1604_08057_amd import Context
+    from synthetic import workload
+    wl = workload(2)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")  # noqa: E731
+    U, psi, eta = dev(wl.links()), dev(wl.psi()), dev(wl.eta())
+    dU = torch.empty((4, wl.volume, 3, 3), dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    out = {}
+    for graphs in (False, True):
+        with torch.cuda.stream(torch.cuda.Stream()):
+            ctx = Context(wl.dims, wl.mass, wl.mu)
+        torch.cuda.synchronize()
+        ctx.set_links(U)
+        ctx.set_graphs(graphs)
+        dt, _, _ = time_steps(ctx, eta, psi, wl.k, steps, 2, dU)
+        ctx.close()
+        out["graph_sources_per_s" if graphs else "launched_sources_per_s"] = steps / dt
+    return out
 
 
 def cpu_baseline(wl):
@@ -159,13 +187,16 @@ def batched_leg(ks_single: int = 4):
     n0, ms0 = ctx.timing_read(0)
     n1, ms1 = ctx.timing_read(1)
     ctx.timing_enable(0)
-    # bytes per launch = per-source bytes x sources in the launch, summed over launches
+    # algorithmic bytes of a launch over n entries: the fields of every entry and the
+    # links once (entries of a workgroup share the link loads), summed over launches
     steps = sum(i.k_used for i in infos)
-    b0, b1 = ctx.kernel_bytes(0), ctx.kernel_bytes(1)
-    fwd_gbs = b0 * steps / (ms0 * 1e-3) / 1e9
-    bwd_gbs = b1 * sum(max(i.k_used - 1, 0) for i in infos) / (ms1 * 1e-3) / 1e9
+    bsteps = sum(max(i.k_used - 1, 0) for i in infos)
+    link_b = int(np.prod(wl.dims)) * 36 * 16
+    b0, b1 = ctx.kernel_bytes(0) - link_b, ctx.kernel_bytes(1) - link_b
+    fwd_gbs = (b0 * steps + link_b * n0) / (ms0 * 1e-3) / 1e9
+    bwd_gbs = (b1 * bsteps + link_b * n1) / (ms1 * 1e-3) / 1e9
+    picks = ctx.pair_ns()
     dU0 = dU[0].clone()
-    del dU
     t1 = time.perf_counter()
     for s in range(ks_single):
         Ss, dUs, _, _ = ctx.sign_grad(eta[s], psi[s], ks[s])
@@ -173,6 +204,21 @@ def batched_leg(ks_single: int = 4):
     dt1 = time.perf_counter() - t1
     same = bool(torch.equal(dUs, dU0)) if ks_single == 1 else None
     ctx.close()
+    # the same batch with the float32 stencil and vectors (FP64 dots, coefficients,
+    # projected-matrix step and accumulation): throughput and error against FP64
+    ctxm = Context(wl.dims, wl.mass, wl.mu, precision="mixed")
+    ctxm.set_links(U)
+    ctxm.sign_grad_batched(eta, psi, ks)
+    torch.cuda.synchronize()
+    tm = time.perf_counter()
+    Sm, dUm, _, _ = ctxm.sign_grad_batched(eta, psi, ks)
+    torch.cuda.synchronize()
+    dtm = time.perf_counter() - tm
+    ctxm.close()
+    err_S = max(abs(a - b) / abs(b) for a, b in zip(Sm, S))
+    err_dU = max(float(torch.linalg.vector_norm(dUm[s] - dU[s]) / torch.linalg.vector_norm(dU[s]))
+                 for s in range(len(ks)))
+    del dU, dUm
     return {"workload": "6x18^3 (V=34992), mu=0.5, link spread 0.35, 32 Z2 sources, k uniform in [100, 400]",
             "sources": len(ks), "sum_k": int(sum(ks)), "precision": "fp64",
             "sources_per_s": len(ks) / dt, "ms_per_call": dt * 1e3,
@@ -180,7 +226,9 @@ def batched_leg(ks_single: int = 4):
             "speedup_vs_single": (len(ks) / dt) / (ks_single / dt1),
             "fwd_pair_GBs": fwd_gbs, "fwd_pair_frac": fwd_gbs / HBM_PEAK_GBS,
             "bwd_pair_GBs": bwd_gbs, "bwd_pair_frac": bwd_gbs / HBM_PEAK_GBS,
-            "launches": {"fwd_pair": n0, "bwd_pair": n1}, "identical_to_single": same}
+            "launches": {"fwd_pair": n0, "bwd_pair": n1}, "identical_to_single": same,
+            "entries_per_workgroup": {"fwd_pair": picks[0], "bwd_pair": picks[1]},
+            "mixed_sources_per_s": len(ks) / dtm, "mixed_max_rel_err_S": err_S, "mixed_max_rel_err_dU": err_dU}
 
 
 def precision_leg():
@@ -291,6 +339,9 @@ def main():
                         "rel_err_y_vs_fp64": rel_t(ym, y64), "rel_err_dU_vs_fp64": rel_t(dUm, dU64),
                         "rel_err_S_vs_fp64": abs(Sm - S) / abs(S)}
         log(f"bench: mixed {out['mixed']['sources_per_s']:.2f} sources/s")
+        out["graphs"] = graph_leg()
+        log(f"bench: 8^4 launched {out['graphs']['launched_sources_per_s']:.2f}, "
+            f"graph-replayed {out['graphs']['graph_sources_per_s']:.2f} sources/s")
         out["batched"] = batched_leg()
         log(f"bench: batched 6x18^3 {out['batched']['sources_per_s']:.2f} sources/s "
             f"(single-source {out['batched']['single_source_sources_per_s']:.2f})")

@@ -128,9 +128,17 @@ tslov_status tslov_overlap(tslov_ctx* ctx, const void* psi, void* out, int k,
  *   dU_out[mu][s] = dS/dRe U_mu(s) + i dS/dIm U_mu(s)  (canonical complex128, device),
  *   so dS = Re tr(dU_out^H dU);  the U(1) link-phase derivative is -Im tr(dU_out^H U).
  * dpsi_out (nullable, canonical spinor) receives dS/dRe psi + i dS/dIm psi.
- * S_out is a host pointer.  recompute_stride must be 0 (all Krylov vectors are
- * stored; 6*k*12*V complex values of workspace).  For D_ov the caller passes
- * g5 eta and adds Re <eta|psi>.
+ * S_out is a host pointer.  For D_ov the caller passes g5 eta and adds Re <eta|psi>.
+ * recompute_stride = 0 stores every Krylov vector (6*k*12*V complex values of
+ * workspace: v_j, w_j, H v_j, H^dag w_j and two reverse-pass fields per step).
+ * recompute_stride = m > 0 with m + 2 < k holds m + 2 steps instead, plus four
+ * fields per m steps (the Lanczos state at every m-th step): the reverse pass
+ * runs in segments of m steps from the top, and each segment first regenerates
+ * its vectors by repeating its forward steps with the recorded coefficients, one
+ * more stencil pair per step in all.  S is that of recompute_stride = 0 exactly
+ * (the forward pass is the same); the regenerated vectors, and with them dU_out
+ * and dpsi_out, agree with the stored ones to rounding (measured about 1e-15
+ * relative).  ERR_ARG for a negative stride.
  * With defl (l > 0) S is that of the deflated sign (see tslov_deflation) and the
  * derivative includes the motion of the deflated eigenpairs with U (Sec. 3, App. E):
  * for simple eigenvalues dPi_i = Z_i dH Pi_i + Pi_i dH Z_i, Pi_i = R_i L_i^H,
@@ -210,6 +218,28 @@ tslov_status tslov_dense_sign(tslov_ctx* ctx, const void* T, int k, const void* 
  * launches and their summed duration, then clears the record. */
 tslov_status tslov_timing_enable(tslov_ctx* ctx, int every);
 tslov_status tslov_timing_read(tslov_ctx* ctx, int which, int* count, double* total_ms);
+
+/* Captured iteration loops.  With on = 1 the forward and reverse Lanczos loops of
+ * the derivative and sign calls (two launches per step each) are captured as HIP
+ * graphs on first use and replayed by later calls with the same source sizes,
+ * workspace and launch shapes; anything else recaptures.  Results are identical
+ * to the launched loops.  Capture is skipped while kernel timing is on, while
+ * the batched pair-kernel shape is still being timed and in recompute mode.
+ * Needs a context created on a non-null stream (ERR_ARG otherwise); the stream
+ * must not be captured by the caller.  on = 0 (the default) frees the graphs. */
+tslov_status tslov_set_graphs(tslov_ctx* ctx, int on);
+
+/* Launch shape of the batched stencil pair kernels on lattices of more than 128
+ * blocks of 64 sites (the colour-split layout): ns entries of a batch per
+ * workgroup, which share every link load.  ns = 0 (the default) lets the library
+ * time 1, 2 and 4 on the first steps of a batched call and keep the fastest for
+ * the context's later calls; ns = 1, 2 or 4 forces that value (fewer when a
+ * launch has fewer entries).  Results do not depend on it: each entry's
+ * arithmetic is the same for every ns.  ERR_ARG for any other ns.
+ * tslov_get_pair_ns returns the timed picks (0 while none is made) of the
+ * forward (fwd_ns) and reverse (bwd_ns) kernels; either pointer may be NULL. */
+tslov_status tslov_set_pair_ns(tslov_ctx* ctx, int ns);
+tslov_status tslov_get_pair_ns(const tslov_ctx* ctx, int* fwd_ns, int* bwd_ns);
 
 /* Algorithmic bytes moved by one launch of kernel class `which` (see above) for
  * this context's lattice and precision (minimal traffic, each field once). */

@@ -111,6 +111,18 @@ std::vector<int> site_block_order(const Geom& g, int& nwg) {
 
 }  // namespace
 
+// A captured launch sequence and the key (list, sizes, buffers, launch shapes) it
+// was captured for.
+struct LoopGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<char> key;
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        key.clear();
+    }
+};
+
 struct tslov_ctx {
     Geom g{};
     double kappa = 0.0, mu = 0.0;
@@ -137,12 +149,25 @@ struct tslov_ctx {
     double* host_part = nullptr;  // pinned
     int host_part_n = 0;
     int slots = 0, kcap = 0, grad_cap = 0;   // shape of the batch workspace
+    // recompute mode: steps of v, w, a, b, abar, sbar held per slot (a ring; 0:
+    // all kcap steps), the segment length and the checkpoint fields
+    int ring = 0, ring_m = 0;
+    Buf ckpt;
+    // captured forward and reverse loops (tslov_set_graphs)
+    int graphs = 0;
+    LoopGraph gfwd, gbwd;
     int dslots = 0, dkcap = 0;               // shape of the dense workspace
     Coef coef{};
     int timing = 0;            // 0 off, N: time every N-th launch of each class
     long long tcount[kTimingClasses] = {0, 0, 0};
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[kTimingClasses];
+    // entries per workgroup of the colour-split pair kernels ([0] forward, [1]
+    // reverse): the timed pick (0 = none yet) and the list length it was timed
+    // at; pair_ns_forced > 0 overrides the pick
+    int pair_ns[2] = {0, 0};
+    int pair_ns_n[2] = {0, 0};
+    int pair_ns_forced = 0;
 
     int nblk() const { return tslov::grid_for(g.V); }
     size_t field_elems() const { return (size_t)12 * g.ldv; }
@@ -180,6 +205,137 @@ struct TimedLaunch {
         return e;
     }
 };
+
+// ---------------------------------------------------------------- launch-shape tuner
+// Entries per workgroup of a colour-split pair kernel (1, 2 or 4).  The choice
+// only decides how many entries share each link load; every entry's arithmetic
+// and partial-sum slots are the same for all of them, so it changes the time of
+// a step, never its result.  The first steps over a list of the target length
+// cycle through the candidates (at most the list length) with an event pair
+// around each launch, kTuneReps rounds; the fastest of each candidate's best
+// times becomes the pick, kept for the context's later calls.  A pick timed on a
+// list shorter than 4 is timed again once a list of 4 or more comes along.
+struct PairTuner {
+    static constexpr int kCand[3] = {1, 2, 4};
+    static constexpr int kTuneReps = 3;
+    tslov_ctx* c;
+    int cls, target, ncand = 0, step = 0;
+    std::vector<hipEvent_t> ev;
+
+    PairTuner(tslov_ctx* ctx, int which, int n_target) : c(ctx), cls(which), target(n_target) {
+        if (c->pair_ns_forced || tslov::colour_grid(c->g.V) || target < 2) return;
+        if (c->pair_ns[cls] && !(c->pair_ns_n[cls] < 4 && target >= 4)) return;
+        ncand = target >= 4 ? 3 : 2;
+        ev.assign((size_t)2 * ncand * kTuneReps, nullptr);
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                e = nullptr;
+                ncand = 0;
+            }
+        if (!ncand) release();
+    }
+    ~PairTuner() { release(); }
+    void release() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        ev.clear();
+    }
+    static int fit(int ns, int n) {
+        while (ns > 1 && ns > n) ns /= 2;
+        return ns;
+    }
+    bool tuning(int n) const { return ncand && n == target && step < ncand * kTuneReps; }
+    bool active() const { return ncand != 0; }
+    // entries per workgroup for the next launch over a list of n entries
+    int ns(int n) const {
+        if (c->pair_ns_forced) return fit(c->pair_ns_forced, n);
+        if (tuning(n)) return kCand[step % ncand];
+        return fit(c->pair_ns[cls] ? c->pair_ns[cls] : 1, n);
+    }
+    void before(int n) {
+        if (tuning(n)) (void)hipEventRecord(ev[2 * step], c->st);
+    }
+    void after(int n) {
+        if (!tuning(n)) return;
+        (void)hipEventRecord(ev[2 * step + 1], c->st);
+        if (++step < ncand * kTuneReps) return;
+        float best[3] = {1e30f, 1e30f, 1e30f};
+        if (hipEventSynchronize(ev.back()) != hipSuccess) {
+            (void)hipGetLastError();
+            ncand = 0;
+            return;
+        }
+        for (int i = 0; i < step; ++i) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess)
+                best[i % ncand] = std::min(best[i % ncand], ms);
+        }
+        int pick = 0;
+        for (int q = 1; q < ncand; ++q)
+            if (best[q] < best[pick]) pick = q;
+        c->pair_ns[cls] = kCand[pick];
+        c->pair_ns_n[cls] = target;
+        ncand = 0;
+    }
+};
+
+// ---------------------------------------------------------------- captured loops
+// The forward and reverse Lanczos loops of a source list are kernel launches only,
+// and every decision inside them (breakdown, retirement) is taken on the device, so
+// with graphs on each loop is captured once as a HIP graph and replayed while the
+// list, the sizes, the buffers and the launch shapes stay the same (the key holds
+// exactly these).  Not while kernels are timed, while the pair-kernel shape is still
+// being timed, in recompute mode (its checkpoints are copies) or on the null stream.
+struct LoopKey {
+    std::vector<char> b;
+    template <typename T>
+    LoopKey& add(const T& v) {
+        const char* p = reinterpret_cast<const char*>(&v);
+        b.insert(b.end(), p, p + sizeof(T));
+        return *this;
+    }
+    LoopKey& list(const SrcList& L) {
+        add(L.n);
+        for (int e = 0; e < L.n; ++e) add(L.slot[e]).add(L.k[e]);
+        return *this;
+    }
+    // the workspace, links and launch shapes the loops' kernels receive
+    template <typename R>
+    LoopKey& buffers(const tslov_ctx* c, const Work<R>& wk, const Z<R>* U, int cls) {
+        add(wk.V).add(wk.W).add(wk.A).add(wk.B).add(wk.AB).add(wk.SB).add(wk.F).add(wk.part);
+        add(wk.fe).add(wk.kcap).add(wk.ring).add(wk.pstride);
+        add(c->coefmem.p).add(c->slots).add(c->kcap).add(U);
+        return add(c->pair_ns[cls]).add(c->pair_ns_forced);
+    }
+};
+
+bool graphs_usable(const tslov_ctx* c) { return c->graphs && !c->timing && c->st && !c->ring; }
+
+template <typename F>
+tslov_status run_captured(tslov_ctx* c, LoopGraph& lg, const LoopKey& key, F&& launches) {
+    if (!lg.exec || lg.key != key.b) {
+        lg.reset();
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+        const tslov_status st = launches();
+        const hipError_t e = hipStreamEndCapture(c->st, &graph);
+        if (st != TSLOV_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        HIPCHK(e);
+        const hipError_t ei = hipGraphInstantiate(&lg.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            lg.exec = nullptr;
+            return fail(TSLOV_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        }
+        lg.key = key.b;
+    }
+    HIPCHK(hipGraphLaunch(lg.exec, c->st));
+    return TSLOV_OK;
+}
 
 tslov_status ensure_host_part(tslov_ctx* c, int n) {
     if (c->host_part_n >= n) return TSLOV_OK;
@@ -222,12 +378,24 @@ void carve_coef(tslov_ctx* c, int slots, int kcap) {
     cf.n = (int)n;
 }
 
-// Workspace for `slots` sources of up to kcap steps (grad: with the reverse-pass arrays).
-tslov_status ensure_work(tslov_ctx* c, int slots, int kcap, int grad) {
-    if (c->slots == slots && c->kcap == kcap && c->grad_cap >= grad && c->coefmem.p) return TSLOV_OK;
+// Steps of basis vectors held per slot for segments of m steps (m = 0: all kcap):
+// a segment's reverse steps read v, w at j0 - 1 .. j1 + 1.
+int ring_steps(int kcap, int m) { return (m > 0 && m + 2 < kcap) ? m + 2 : 0; }
+int n_segments(int kcap, int m) { return (kcap + m - 1) / m; }
+
+// Workspace for `slots` sources of up to kcap steps (grad: with the reverse-pass
+// arrays; m > 0: recompute mode with segments of m steps).
+tslov_status ensure_work(tslov_ctx* c, int slots, int kcap, int grad, int m = 0) {
+    const int ring = ring_steps(kcap, m);
+    if (c->slots == slots && c->kcap == kcap && c->grad_cap >= grad && c->ring == ring &&
+        (!ring || c->ring_m == m) && c->coefmem.p)
+        return TSLOV_OK;
     c->slots = 0;   // invalid until every buffer has the new shape
     const size_t fb = c->field_bytes();
-    const size_t per = (size_t)slots * kcap * fb;
+    const size_t per = (size_t)slots * (ring ? ring : kcap) * fb;
+    if (ring) CHK(ensure(c->ckpt, (size_t)slots * n_segments(kcap, m) * 4 * fb));
+    c->ring = ring;
+    c->ring_m = ring ? m : 0;
     CHK(ensure(c->basisV, per));
     CHK(ensure(c->basisW, per));
     CHK(ensure(c->basisA, per));
@@ -258,8 +426,9 @@ Work<R> work(const tslov_ctx* c) {
     w.F = c->fields.as<Z<R>>();
     w.part = c->part.as<double>();
     w.fe = c->field_elems();
-    w.kcap = c->kcap;
+    w.kcap = c->ring ? c->ring : c->kcap;
     w.pstride = c->pstride();
+    w.ring = c->ring ? 1 : 0;
     return w;
 }
 
@@ -270,9 +439,11 @@ const Z<R>* links(const tslov_ctx* c) {
 }
 
 // Device bytes one source of up to kcap steps needs (workspace sizing).
-size_t bytes_per_source(const tslov_ctx* c, int kcap, int grad) {
+size_t bytes_per_source(const tslov_ctx* c, int kcap, int grad, int m = 0) {
     const size_t fb = c->field_bytes();
-    size_t b = (size_t)(grad ? 6 : 4) * kcap * fb + (size_t)tslov::kNF * fb;
+    const int ring = ring_steps(kcap, m);
+    size_t b = (size_t)(grad ? 6 : 4) * (ring ? ring : kcap) * fb + (size_t)tslov::kNF * fb;
+    if (ring) b += (size_t)4 * n_segments(kcap, m) * fb;
     b += (size_t)tslov::kNP * c->pstride() * sizeof(double) + coef_bytes(1, kcap);
     b += (size_t)6 * kcap * kcap * sizeof(ZD) + (size_t)tslov::dense_pstride(kcap) * sizeof(double);
     if (grad) b += (size_t)2 * 36 * c->g.ldv * sizeof(ZD) + (size_t)2 * 12 * c->g.V * sizeof(ZD);
@@ -282,20 +453,20 @@ size_t bytes_per_source(const tslov_ctx* c, int kcap, int grad) {
 size_t held_bytes(const tslov_ctx* c) {
     size_t t = 0;
     for (const Buf* b : {&c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS, &c->fields, &c->part,
-                         &c->dense, &c->gpart, &c->bout})
+                         &c->dense, &c->gpart, &c->bout, &c->ckpt})
         t += b->n;
     return t;
 }
 
 // Sources per batch: as many as fit in ~80% of the device memory not otherwise in use.
-int batch_capacity(const tslov_ctx* c, int kcap, int grad) {
+int batch_capacity(const tslov_ctx* c, int kcap, int grad, int m = 0) {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
     const double avail = 0.8 * (double)(fr + held_bytes(c));
-    const double per = (double)bytes_per_source(c, kcap, grad);
+    const double per = (double)bytes_per_source(c, kcap, grad, m);
     const int n = (int)std::floor(avail / per);
     return std::max(1, std::min(n, kMaxBatch));
 }
@@ -339,6 +510,27 @@ struct EntryStatus {
     int iters = 0;
 };
 
+// Recompute mode: the state before forward step j0 = 1 + seg m of every entry of
+// L (the residuals r, s of step j0 - 1 and v_{j0-1}, w_{j0-1}), saved (restore = 0)
+// to or restored (restore = 1) from checkpoint seg of the entry's slot.
+template <typename R>
+tslov_status checkpoint(tslov_ctx* c, const SrcList& L, int seg, int j0, int restore) {
+    const Work<R> wk = work<R>(c);
+    const size_t fb = c->field_bytes();
+    const int nseg = n_segments(c->kcap, c->ring_m);
+    for (int e = 0; e < L.n; ++e) {
+        const int slot = L.slot[e];
+        char* base = c->ckpt.as<char>() + ((size_t)slot * nseg + seg) * 4 * fb;
+        void* live[4] = {wk.f(slot, 2), wk.f(slot, 3), wk.v(slot, j0 - 1), wk.w(slot, j0 - 1)};
+        for (int i = 0; i < 4; ++i) {
+            void* saved = base + (size_t)i * fb;
+            HIPCHK(hipMemcpyAsync(restore ? live[i] : saved, restore ? saved : live[i], fb, hipMemcpyDeviceToDevice,
+                                  c->st));
+        }
+    }
+    return TSLOV_OK;
+}
+
 // Lanczos process for every entry of L (slots 0..n-1, k in decreasing order);
 // psi and eta canonical arrays indexed by src (eta nullable; eta_g5: eta = g5 psi).
 template <typename R>
@@ -353,12 +545,28 @@ tslov_status forward(tslov_ctx* c, const SrcList& L, const ZD* psi, const ZD* et
     if (eta) tslov::launch_sources_to_soa<R>(eta, 1, eta_g5, wk, L, g, c->st);
     const Z<R>* U = links<R>(c);
     const int kmax = L.k[0];
-    int n = L.n;
-    for (int j = 1; j <= kmax; ++j) {
-        while (n > 0 && L.k[n - 1] < j) --n;
-        const SrcList Lj = prefix(L, n);
-        tslov::launch_fwd_pair<R>(U, g, c->kappa, c->mu, wk, Lj, c->coef, j, eta ? 1 : 0, c->st, TimedLaunch(c, 0).t);
-        tslov::launch_recur<R>(g, wk, Lj, c->coef, j, c->st);
+    PairTuner tune(c, 0, L.n);
+    const int m = c->ring ? c->ring_m : 0;
+    auto loop = [&]() -> tslov_status {
+        int n = L.n;
+        for (int j = 1; j <= kmax; ++j) {
+            while (n > 0 && L.k[n - 1] < j) --n;
+            const SrcList Lj = prefix(L, n);
+            if (m && j > 1 && (j - 1) % m == 0) CHK(checkpoint<R>(c, Lj, (j - 1) / m, j, 0));
+            tune.before(n);
+            tslov::launch_fwd_pair<R>(U, g, c->kappa, c->mu, wk, Lj, c->coef, j, eta ? 1 : 0, tune.ns(n), c->st,
+                                      TimedLaunch(c, 0).t);
+            tune.after(n);
+            tslov::launch_recur<R>(g, wk, Lj, c->coef, j, c->st);
+        }
+        return TSLOV_OK;
+    };
+    if (graphs_usable(c) && !tune.active()) {
+        LoopKey key;
+        key.list(L).add(kmax).add(eta ? 1 : 0).buffers(c, wk, U, 0);
+        CHK(run_captured(c, c->gfwd, key, loop));
+    } else {
+        CHK(loop());
     }
     HIPCHK(hipGetLastError());
     std::vector<int> st((size_t)16 * L.n);
@@ -520,33 +728,76 @@ struct GradOut {
 };
 
 // Reverse pass and force contraction for every entry of L (k = k_used, decreasing).
+// In recompute mode (c->ring) the steps run in segments of m from the top; each
+// segment first regenerates its basis vectors by replaying the forward steps from
+// its checkpoint, then runs its reverse steps and adds its force terms.
 template <typename R>
 tslov_status backward(tslov_ctx* c, const SrcList& L, GradOut& out) {
     const Geom& g = c->g;
     const Work<R> wk = work<R>(c);
     const Z<R>* U = links<R>(c);
     const int kmax = L.k[0];
+    const int m = c->ring ? c->ring_m : 0;
+    if (m && out.ward) return fail(TSLOV_ERR_ARG, "the Ward check needs every Krylov vector stored");
+    // force contraction split in chunks of j for parallelism; the split depends on
+    // the lattice (and the segment) only, so a source's result does not depend on
+    // the batch it shares a launch with
+    const int nchunk = std::max(1, std::min((1 << 18) / (4 * g.V), 64));
+    CHK(ensure(c->gpart, (size_t)c->slots * nchunk * 36 * g.ldv * sizeof(ZD)));
     int nlt = 0;   // entries with k_used > j form a prefix
-    for (int j = kmax; j >= 1; --j) {
+    PairTuner tune(c, 1, L.n);
+    auto reverse_step = [&](int j) {
         int neq_end = nlt;
         while (neq_end < L.n && L.k[neq_end] == j) ++neq_end;
         if (nlt > 0) {
             const SrcList Llt = prefix(L, nlt);
             tslov::launch_bwd_ra<R>(g, wk, Llt, c->coef, j, c->st);
-            tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, wk, Llt, c->coef, j, 0, c->st, TimedLaunch(c, 1).t);
+            tune.before(nlt);
+            tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, wk, Llt, c->coef, j, 0, tune.ns(nlt), c->st,
+                                    TimedLaunch(c, 1).t);
+            tune.after(nlt);
         }
         if (neq_end > nlt) {
             const SrcList Leq = range(L, nlt, neq_end);
-            tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, wk, Leq, c->coef, j, 1, c->st);
+            tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, wk, Leq, c->coef, j, 1, 1, c->st);
         }
         nlt = neq_end;
+    };
+    // entries with k_used >= j form a prefix
+    auto reaching = [&](int j) {
+        int n = 0;
+        while (n < L.n && L.k[n] >= j) ++n;
+        return prefix(L, n);
+    };
+    if (!m) {
+        auto loop = [&]() -> tslov_status {
+            nlt = 0;
+            for (int j = kmax; j >= 1; --j) reverse_step(j);
+            return TSLOV_OK;
+        };
+        if (graphs_usable(c) && !tune.active()) {
+            LoopKey key;
+            key.list(L).buffers(c, wk, U, 1);
+            CHK(run_captured(c, c->gbwd, key, loop));
+        } else {
+            CHK(loop());
+        }
+        tslov::launch_force<R>(g, c->kappa, c->mu, wk, L, nchunk, c->gpart.as<ZD>(), c->st);
+    } else {
+        tslov::launch_zero(c->gpart.as<double>(), (size_t)c->slots * nchunk * 72 * g.ldv, c->st);
+        for (int seg = n_segments(kmax, m) - 1; seg >= 0; --seg) {
+            const int j0 = 1 + seg * m, j1 = std::min(j0 + m - 1, kmax);
+            if (seg > 0) CHK(checkpoint<R>(c, reaching(j0), seg, j0, 1));
+            for (int j = j0; j <= std::min(j1 + 1, kmax); ++j) {
+                const SrcList Lr = reaching(j);
+                tslov::launch_fwd_replay<R>(U, g, c->kappa, c->mu, wk, Lr, c->coef, j, c->st);
+                if (j <= j1) tslov::launch_recur_replay<R>(g, wk, Lr, c->coef, j, c->st);
+            }
+            for (int j = j1; j >= j0; --j) reverse_step(j);
+            tslov::launch_force<R>(g, c->kappa, c->mu, wk, reaching(j0), nchunk, c->gpart.as<ZD>(), c->st, j0, j1,
+                                   1);
+        }
     }
-    // force contraction over all steps, split in chunks of j for parallelism; the
-    // split depends on the lattice only, so a source's result does not depend on
-    // the batch it shares a launch with
-    const int nchunk = std::max(1, std::min((1 << 18) / (4 * g.V), 64));
-    CHK(ensure(c->gpart, (size_t)c->slots * nchunk * 36 * g.ldv * sizeof(ZD)));
-    tslov::launch_force<R>(g, c->kappa, c->mu, wk, L, nchunk, c->gpart.as<ZD>(), c->st);
     if (out.dU) tslov::launch_force_reduce(g, c->gpart.as<ZD>(), nchunk, L, c->antiperiodic, out.dU, c->st);
     double* gsrc = nullptr;
     if (out.ward) {
@@ -695,6 +946,7 @@ tslov_status sign_impl(tslov_ctx* c, const void* psi_in, void* out, int k, const
 // decreasing Krylov size that fit the device memory.
 struct BatchRequest {
     int nsrc = 0;
+    int recompute = 0;         // segment length of the Krylov-vector recompute (0: all stored)
     const ZD* eta = nullptr;   // null with eta_g5: eta = g5 psi
     int eta_g5 = 0;
     const ZD* psi = nullptr;
@@ -720,11 +972,11 @@ tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
     size_t pos = 0;
     while (pos < order.size()) {
         const int kcap = q.k[order[pos]];
-        const int cap = std::min(batch_capacity(c, kcap, 1), (int)(order.size() - pos));
+        const int cap = std::min(batch_capacity(c, kcap, 1, q.recompute), (int)(order.size() - pos));
         std::vector<int> src(order.begin() + pos, order.begin() + pos + cap), ks(cap);
         for (int e = 0; e < cap; ++e) ks[e] = q.k[src[e]];
         pos += cap;
-        CHK(ensure_work(c, cap, kcap, 1));
+        CHK(ensure_work(c, cap, kcap, 1, q.recompute));
         const double tg0 = now_ms();
         const SrcList L = make_list(src, ks);
         std::vector<EntryStatus> es;
@@ -808,7 +1060,7 @@ constexpr int kCgCheckEvery = 8;
 // Derivative of the deflated S = Re eta^H [sum_i s_i Pi_i psi + TSL(P psi)], P = 1 - sum_i Pi_i,
 // with the eigenpairs moving with U (reduced-resolvent solves; see solve.hip).
 tslov_status deflated_grad(tslov_ctx* c, const ZD* eta, const ZD* psi, int k, const tslov_deflation* defl,
-                           double* S_out, ZD* dU, ZD* dpsi, tslov_info* info) {
+                           int recompute, double* S_out, ZD* dU, ZD* dpsi, tslov_info* info) {
     const double t0 = now_ms();
     DeflSet d;
     CHK(prepare_defl(c, defl, d));
@@ -837,6 +1089,7 @@ tslov_status deflated_grad(tslov_ctx* c, const ZD* eta, const ZD* psi, int k, co
     q.dU = dU;
     q.dpsi = pbar;
     q.infos = info;
+    q.recompute = recompute;
     CHK(run_batched(c, q));
     tslov::launch_defl_coeffs(d.R, eta, V, l, xpart, dRe, c->st);          // R_i^H eta
     tslov::launch_defl_coeffs(d.R, pbar, V, l, xpart, dRp, c->st);         // R_i^H psibar_p
@@ -967,8 +1220,10 @@ void tslov_destroy(tslov_ctx* c) {
     for (Buf* b : {&c->U64, &c->U32, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
                    &c->fields, &c->part, &c->coefmem, &c->dense, &c->denseInt, &c->densePart, &c->denseDelta,
                    &c->gpart, &c->gsrc, &c->bout, &c->wardp, &c->canon, &c->deflw, &c->deflx, &c->cgf, &c->cgp,
-                   &c->cgs})
+                   &c->cgs, &c->ckpt})
         release(*b);
+    c->gfwd.reset();
+    c->gbwd.reset();
     if (c->host_part) (void)hipHostFree(c->host_part);
     for (auto& v : c->ev_used)
         for (auto& pr : v) {
@@ -1044,9 +1299,10 @@ tslov_status tslov_sign_grad(tslov_ctx* c, const void* eta, const void* psi, int
                              int recompute_stride, double* S_out, void* dU_out, void* dpsi_out, tslov_info* info) {
     CHK(check_common(c, k, defl));
     if (!eta || !psi || !dU_out) return fail(TSLOV_ERR_ARG, "null argument");
-    if (recompute_stride != 0) return fail(TSLOV_ERR_ARG, "recompute_stride must be 0 (all vectors stored)");
-    if (defl && defl->l != 0) return deflated_grad(c, (const ZD*)eta, (const ZD*)psi, k, defl, S_out, (ZD*)dU_out,
-                                                   (ZD*)dpsi_out, info);
+    if (recompute_stride < 0) return fail(TSLOV_ERR_ARG, "recompute_stride must be >= 0");
+    if (defl && defl->l != 0)
+        return deflated_grad(c, (const ZD*)eta, (const ZD*)psi, k, defl, recompute_stride, S_out, (ZD*)dU_out,
+                             (ZD*)dpsi_out, info);
     BatchRequest q;
     q.nsrc = 1;
     q.eta = (const ZD*)eta;
@@ -1056,6 +1312,7 @@ tslov_status tslov_sign_grad(tslov_ctx* c, const void* eta, const void* psi, int
     q.dU = (ZD*)dU_out;
     q.dpsi = (ZD*)dpsi_out;
     q.infos = info;
+    q.recompute = recompute_stride;
     return run_batched(c, q);
 }
 
@@ -1211,6 +1468,32 @@ tslov_status tslov_timing_read(tslov_ctx* c, int which, int* count, double* tota
     c->ev_used[which].clear();
     if (count) *count = n;
     if (total_ms) *total_ms = tot;
+    return TSLOV_OK;
+}
+
+tslov_status tslov_set_graphs(tslov_ctx* c, int on) {
+    if (!c) return fail(TSLOV_ERR_ARG, "null context");
+    if (on && !c->st) return fail(TSLOV_ERR_ARG, "graph capture needs a context created on a non-null stream");
+    HIPCHK(hipStreamSynchronize(c->st));
+    c->graphs = on ? 1 : 0;
+    if (!on) {
+        c->gfwd.reset();
+        c->gbwd.reset();
+    }
+    return TSLOV_OK;
+}
+
+tslov_status tslov_set_pair_ns(tslov_ctx* c, int ns) {
+    if (!c) return fail(TSLOV_ERR_ARG, "null context");
+    if (ns != 0 && ns != 1 && ns != 2 && ns != 4) return fail(TSLOV_ERR_ARG, "ns must be 0, 1, 2 or 4");
+    c->pair_ns_forced = ns;
+    return TSLOV_OK;
+}
+
+tslov_status tslov_get_pair_ns(const tslov_ctx* c, int* fwd_ns, int* bwd_ns) {
+    if (!c) return fail(TSLOV_ERR_ARG, "null context");
+    if (fwd_ns) *fwd_ns = c->pair_ns[0];
+    if (bwd_ns) *bwd_ns = c->pair_ns[1];
     return TSLOV_OK;
 }
 

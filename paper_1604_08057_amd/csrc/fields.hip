@@ -261,6 +261,72 @@ __device__ __forceinline__ void hop_all_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], c
     }
 }
 
+// The colour-split pair hops for NS entries of a batch at once: every link row is
+// loaded once and applied to the 2*NS fields (A_q at +mu, B_q at -mu) of the
+// entries whose bit is set in the block-uniform mask `live`.  Each accumulator
+// receives the same operations in the same order as with one entry.
+template <int NU, int NS, typename R>
+__device__ __forceinline__ void hop_dir_pairN(Z<R> (&acca)[NS][4], Z<R> (&accb)[NS][4], const Z<R>* __restrict__ U,
+                                              const Z<R>* const (&fa)[NS], const Z<R>* const (&fb)[NS],
+                                              unsigned live, const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
+    const R up = (NU == 3) ? ep : R(1), dn = (NU == 3) ? em : R(1);
+    Z<R> u[3];
+    Spinor<R> p;
+    load_row(u, U, g.ldv, NU, a, s);
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        if (live & (1u << q)) {
+            load_spinor(p, fa[q], g.ldv, n.fwd[NU]);
+            hop1<NU, +1>(acca[q], u, p, up);
+            load_spinor(p, fb[q], g.ldv, n.fwd[NU]);
+            hop1<NU, +1>(accb[q], u, p, dn);
+        }
+    }
+    load_col_conj(u, U, g.ldv, NU, a, n.bwd[NU]);
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        if (live & (1u << q)) {
+            load_spinor(p, fa[q], g.ldv, n.bwd[NU]);
+            hop1<NU, -1>(acca[q], u, p, dn);
+            load_spinor(p, fb[q], g.ldv, n.bwd[NU]);
+            hop1<NU, -1>(accb[q], u, p, up);
+        }
+    }
+}
+
+template <int NS, typename R>
+__device__ __forceinline__ void hop_all_pairN(Z<R> (&acca)[NS][4], Z<R> (&accb)[NS][4], const Z<R>* __restrict__ U,
+                                              const Z<R>* const (&fa)[NS], const Z<R>* const (&fb)[NS],
+                                              unsigned live, const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
+#pragma unroll 1
+    for (int nu = 0; nu < 4; ++nu) {
+        switch (nu) {
+            case 0: hop_dir_pairN<0, NS>(acca, accb, U, fa, fb, live, g, s, a, n, ep, em); break;
+            case 1: hop_dir_pairN<1, NS>(acca, accb, U, fa, fb, live, g, s, a, n, ep, em); break;
+            case 2: hop_dir_pairN<2, NS>(acca, accb, U, fa, fb, live, g, s, a, n, ep, em); break;
+            default: hop_dir_pairN<3, NS>(acca, accb, U, fa, fb, live, g, s, a, n, ep, em); break;
+        }
+    }
+}
+
+// Block-uniform reads of the stop flags of NS entries (1 for an entry past the
+// end of the list), with one pair of barriers for all of them.
+template <int NS>
+__device__ __forceinline__ unsigned block_live(const Coef& coef0, const SrcList& L, int e0) {
+    __shared__ int f[NS];
+    if (threadIdx.x < NS) {
+        const int e = e0 + (int)threadIdx.x;
+        f[threadIdx.x] = e < L.n ? *(volatile const int*)coef0.at(L.slot[e]).status : 1;
+    }
+    __syncthreads();
+    unsigned live = 0;
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+        if (!f[q]) live |= 1u << q;
+    __syncthreads();
+    return live;
+}
+
 // =============================================================== operator
 // Colour grid (small lattices): block (a, b) forms colour a of site block b.
 template <typename R>
@@ -429,33 +495,26 @@ void launch_sources_to_soa(const ZD* canon, int which, int g5, const Work<R>& wk
 // apply a = H(mu) v_j and b = H(-mu) w_j = H^dag w_j with shared link loads, and
 // emit per-block partial sums of alpha_j = w_j^H a, |a|^2 and eta^H v_j.  At
 // j >= 2 the step first decides breakdown from the previous omega and norms.
+// Epilogue of step j for one entry, after the hops: breakdown decisions from the
+// block-summed previous (omega, |r|^2, |s|^2) in `red`, the coefficient records,
+// the stores of v_j, w_j, a_j, b_j and the step's partial sums.  Every branch
+// depends on block-uniform values only, so a block takes it as a whole.
+// replay: the step's coefficients are the recorded beta_j, gamma_j, and nothing but
+// the four fields is written (a runtime flag, so that a replayed step runs the
+// very instructions of the original one).
 template <typename R, int BLK>
-__global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
-                                                      Work<R> wk, SrcList L, Coef coef0, int j, int npart_in,
-                                                      int has_eta) {
-    const int slot = L.slot[blockIdx.y];
-    const Coef coef = coef0.at(slot);
+__device__ __forceinline__ void fwd_pair_finish(const Geom& g, double kappa, const Work<R>& wk, const Coef& coef,
+                                                int slot, int j, int pslot, int a, int s,
+                                                const double (&red)[kNvRecur], const Z<R> (&acca)[4],
+                                                const Z<R> (&accb)[4], const Z<R>* __restrict__ rin,
+                                                const Z<R>* __restrict__ sin, int has_eta, int replay) {
     const int first = j == 1;
-    const Z<R>* rin = wk.f(slot, first ? 0 : 2);
-    const Z<R>* sin = wk.f(slot, first ? 0 : 3);
-    // the partial sums' loads share a round trip with the flag read; the hops do not
-    // depend on the sums (normalisation and breakdown act in the epilogue), so they
-    // run before the sums are combined, and a breakdown step discards them
-    double red[kNvRecur];
-    gather_partials<kNvRecur, BLK>(wk.p(slot, 1), npart_in, red);
-    const int sb = sten_block<BLK>(g);
-    if (sb < 0) return;   // padding workgroup (uniform over the block)
-    if (block_flag(coef.status)) return;
-    const int a = sten_colour<BLK>();
-    const int s = sb * kSites + threadIdx.x % kSites;
-    Z<R> acca[4], accb[4];
-    zero1(acca);
-    zero1(accb);
-    if (s < g.V) {
-        hop_all_pair<BLK>(acca, accb, U, rin, sin, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu));
-        mem_fence_compiler();
-    }
-    block_sum<kNvRecur, BLK>(red);
+    double beta;
+    ZD gam;
+    if (replay) {
+        beta = coef.beta[j];
+        gam = coef.gamma[j];
+    } else {
     const ZD om = mk<double>(red[0], red[1]);
     const double rn2 = red[2], sn2 = red[3];
     const double aom = std::sqrt(norm2(om));
@@ -484,12 +543,13 @@ __global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Ge
             return;
         }
     }
-    const double beta = std::sqrt(aom);
-    const ZD gam = (1.0 / beta) * om;
+    beta = std::sqrt(aom);
+    gam = (1.0 / beta) * om;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         coef.beta[j] = beta;
         coef.gamma[j] = gam;
         if (first) coef.misc[0] = beta;
+    }
     }
     const R ib = (R)(1.0 / beta);
     const Z<R> icg = zcast<R>(zdiv(mk<double>(1.0, 0.0), cj(gam)));
@@ -516,7 +576,7 @@ __global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Ge
         store1_nt(wk.w(slot, j), g.ldv, a, s, w);
         store1_nt(wk.a(slot, j), g.ldv, a, s, av);
         store1_nt(wk.b(slot, j), g.ldv, a, s, bv);
-        if (has_eta) {
+        if (!replay && has_eta) {
             Z<R> e[4];
             load1(e, wk.f(slot, 1), g.ldv, a, s);
 #pragma unroll
@@ -527,20 +587,138 @@ __global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Ge
             }
         }
     }
-    write_partials_at<kNvPair, BLK>(wk.p(slot, 0), BLK == kSites ? (int)blockIdx.x : sb, pv);
+    if (!replay) write_partials_at<kNvPair, BLK>(wk.p(slot, 0), pslot, pv);
+}
+
+// Step j: normalise the previous residuals (v_j = r/beta_j, w_j = s/conj(gamma_j)),
+// apply a = H(mu) v_j and b = H(-mu) w_j = H^dag w_j with shared link loads, and
+// emit per-block partial sums of alpha_j = w_j^H a, |a|^2 and eta^H v_j.  At
+// j >= 2 the step first decides breakdown from the previous omega and norms.
+// Colour grid: one entry per workgroup (grid.y = entry).
+template <typename R, int BLK>
+__global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
+                                                  Work<R> wk, SrcList L, Coef coef0, int j, int npart_in,
+                                                  int has_eta, int replay) {
+    static_assert(BLK == kSites, "colour-grid kernel");
+    const int slot = L.slot[blockIdx.y];
+    const Coef coef = coef0.at(slot);
+    const int first = j == 1;
+    const Z<R>* rin = wk.f(slot, first ? 0 : 2);
+    const Z<R>* sin = wk.f(slot, first ? 0 : 3);
+    // the partial sums' loads share a round trip with the flag read; the hops do not
+    // depend on the sums (normalisation and breakdown act in the epilogue), so they
+    // run before the sums are combined, and a breakdown step discards them
+    double red[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
+    if (!replay) gather_partials<kNvRecur, kSites>(wk.p(slot, 1), npart_in, red);
+    const int sb = sten_block<kSites>(g);
+    if (!replay && block_flag(coef.status)) return;
+    const int a = sten_colour<kSites>();
+    const int s = sb * kSites + threadIdx.x % kSites;
+    Z<R> acca[4], accb[4];
+    zero1(acca);
+    zero1(accb);
+    if (s < g.V) {
+        hop_all_pair<kSites>(acca, accb, U, rin, sin, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu));
+        mem_fence_compiler();
+    }
+    if (!replay) block_sum<kNvRecur, kSites>(red);
+    fwd_pair_finish<R, kSites>(g, kappa, wk, coef, slot, j, (int)blockIdx.x, a, s, red, acca, accb, rin, sin,
+                               has_eta, replay);
+}
+
+// Colour split: NS entries per workgroup (entries NS*blockIdx.y + q), which share
+// every link load; the partial-sum slot is the site block.
+template <typename R, int NS>
+__global__ __launch_bounds__(kCBlock) void k_fwd_pair_ms(const Z<R>* __restrict__ U, Geom g, double kappa,
+                                                         double emu, Work<R> wk, SrcList L, Coef coef0, int j,
+                                                         int npart_in, int has_eta, int replay_arg) {
+    const int replay = NS == 1 ? replay_arg : 0;   // regeneration runs one entry per workgroup
+    const int e0 = (int)blockIdx.y * NS;
+    const int first = j == 1;
+    int slot[NS];
+    const Z<R>* rin[NS];
+    const Z<R>* sin[NS];
+    double red[NS][kNvRecur];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        slot[q] = L.slot[min(e0 + q, L.n - 1)];
+        rin[q] = wk.f(slot[q], first ? 0 : 2);
+        sin[q] = wk.f(slot[q], first ? 0 : 3);
+#pragma unroll
+        for (int i = 0; i < kNvRecur; ++i) red[q][i] = 0.0;
+        if (!replay) gather_partials<kNvRecur, kCBlock>(wk.p(slot[q], 1), npart_in, red[q]);
+    }
+    const int sb = sten_block<kCBlock>(g);
+    if (sb < 0) return;   // padding workgroup (uniform over the block)
+    unsigned live = 0;
+    if (replay) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+            if (e0 + q < L.n) live |= 1u << q;
+    } else {
+        live = block_live<NS>(coef0, L, e0);
+    }
+    if (!live) return;
+    const int a = sten_colour<kCBlock>();
+    const int s = sb * kSites + threadIdx.x % kSites;
+    Z<R> acca[NS][4], accb[NS][4];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        zero1(acca[q]);
+        zero1(accb[q]);
+    }
+    if (s < g.V) {
+        hop_all_pairN<NS>(acca, accb, U, rin, sin, live, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu));
+        mem_fence_compiler();
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        if (live & (1u << q)) {
+            if (!replay) block_sum<kNvRecur, kCBlock>(red[q]);
+            fwd_pair_finish<R, kCBlock>(g, kappa, wk, coef0.at(slot[q]), slot[q], j, sb, a, s, red[q], acca[q],
+                                        accb[q], rin[q], sin[q], has_eta, replay);
+        }
+    }
+}
+
+template <typename R>
+void fwd_pair_launch(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+                     Coef coef, int j, int has_eta, int ns, int replay, hipStream_t st, Timing t) {
+    const int npart_in = j == 1 ? grid_for(g.V) : np_point(g.V);
+    const double emu = std::exp(mu);
+    if (colour_grid(g.V)) {
+        timed_launch(k_fwd_pair<R, kSites>, dim3(np_colour(g.V), L.n), dim3(kSites), st, t, U, g, kappa, emu, wk, L,
+                     coef, j, npart_in, has_eta, replay);
+        return;
+    }
+    const dim3 block(kCBlock);
+    switch (ns) {
+        case 4:
+            timed_launch(k_fwd_pair_ms<R, 4>, dim3(g.nwg, (L.n + 3) / 4), block, st, t, U, g, kappa, emu, wk, L, coef,
+                         j, npart_in, has_eta, replay);
+            break;
+        case 2:
+            timed_launch(k_fwd_pair_ms<R, 2>, dim3(g.nwg, (L.n + 1) / 2), block, st, t, U, g, kappa, emu, wk, L, coef,
+                         j, npart_in, has_eta, replay);
+            break;
+        default:
+            timed_launch(k_fwd_pair_ms<R, 1>, dim3(g.nwg, L.n), block, st, t, U, g, kappa, emu, wk, L, coef, j,
+                         npart_in, has_eta, replay);
+    }
 }
 
 template <typename R>
 void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
-                     Coef coef, int j, int has_eta, hipStream_t st, Timing t) {
-    const int npart_in = j == 1 ? grid_for(g.V) : np_point(g.V);
-    const dim3 grid(colour_grid(g.V) ? np_colour(g.V) : g.nwg, L.n);
-    if (colour_grid(g.V))
-        timed_launch(k_fwd_pair<R, kSites>, grid, dim3(kSites), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
-                     npart_in, has_eta);
-    else
-        timed_launch(k_fwd_pair<R, kCBlock>, grid, dim3(kCBlock), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
-                     npart_in, has_eta);
+                     Coef coef, int j, int has_eta, int ns, hipStream_t st, Timing t) {
+    fwd_pair_launch<R>(U, g, kappa, mu, wk, L, coef, j, has_eta, ns, 0, st, t);
+}
+
+// Replay of step j for regeneration: the step's own kernel with the replay flag,
+// one entry per workgroup (the shape a single-source step runs with).
+template <typename R>
+void launch_fwd_replay(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+                       Coef coef, int j, hipStream_t st) {
+    fwd_pair_launch<R>(U, g, kappa, mu, wk, L, coef, j, 0, 1, 1, st, Timing{});
 }
 
 // r = a - alpha_j v_j - gamma_j v_{j-1},  s = b - conj(alpha_j) w_j - beta_j w_{j-1},
@@ -548,7 +726,19 @@ void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, cons
 // (plane, site): grid.y runs over the 12 spin-colour planes, grid.z over the
 // entries.  At the entry's last step (j = k[e]) only alpha_j is recorded.
 template <typename R>
-__global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L, Coef coef0, int j, int npart_in) {
+__device__ __forceinline__ void recur_update(Z<R> a_i, Z<R> b_i, Z<R> v_i, Z<R> w_i, Z<R> vp_i, Z<R> wp_i, Z<R> al,
+                                             Z<R> alc, Z<R> gj, R bj, bool has_prev, Z<R>& r, Z<R>& q) {
+    r = a_i - al * v_i;
+    q = b_i - alc * w_i;
+    if (has_prev) {
+        r = r - gj * vp_i;
+        q = q - bj * wp_i;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L, Coef coef0, int j, int npart_in,
+                                                   int replay) {
     const int e = blockIdx.z, slot = L.slot[e];
     const Coef coef = coef0.at(slot);
     const int s = blockIdx.x * kPBlock + threadIdx.x;
@@ -567,15 +757,20 @@ __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L
             wp_i = wk.w(slot, j - 1)[i];
         }
     }
-    double red[kNvPair];
-    gather_partials<kNvPair, kPBlock>(wk.p(slot, 0), npart_in, red);
-    if (block_flag(coef.status)) return;
-    block_sum<kNvPair, kPBlock>(red);
-    const ZD alpha = mk<double>(red[0], red[1]);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-        coef.alpha[j] = alpha;
-        coef.anorm2[j] = red[2];
-        coef.h[j] = mk<double>(red[3], red[4]);
+    double red[kNvPair] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (!replay) gather_partials<kNvPair, kPBlock>(wk.p(slot, 0), npart_in, red);
+    if (!replay && block_flag(coef.status)) return;
+    ZD alpha;
+    if (replay) {   // regeneration: alpha_j as recorded, nothing written but r and s
+        alpha = coef.alpha[j];
+    } else {
+        block_sum<kNvPair, kPBlock>(red);
+        alpha = mk<double>(red[0], red[1]);
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+            coef.alpha[j] = alpha;
+            coef.anorm2[j] = red[2];
+            coef.h[j] = mk<double>(red[3], red[4]);
+        }
     }
     if (j >= L.k[e]) return;
     const Z<R> al = zcast<R>(alpha), alc = zcast<R>(cj(alpha));
@@ -583,12 +778,8 @@ __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L
     const R bj = has_prev ? (R)coef.beta[j] : R(0);
     double pv[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
     if (live) {
-        Z<R> r = a_i - al * v_i;
-        Z<R> q = b_i - alc * w_i;
-        if (has_prev) {
-            r = r - gj * vp_i;
-            q = q - bj * wp_i;
-        }
+        Z<R> r, q;
+        recur_update(a_i, b_i, v_i, w_i, vp_i, wp_i, al, alc, gj, bj, has_prev, r, q);
         wk.f(slot, 2)[i] = r;
         wk.f(slot, 3)[i] = q;
         const double rr = r.re, ri = r.im, qr = q.re, qi = q.im;
@@ -597,13 +788,19 @@ __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L
         pv[2] = rr * rr + ri * ri;
         pv[3] = qr * qr + qi * qi;
     }
-    write_partials_at<kNvRecur, kPBlock>(wk.p(slot, 1), blockIdx.y * gridDim.x + blockIdx.x, pv);
+    if (!replay) write_partials_at<kNvRecur, kPBlock>(wk.p(slot, 1), blockIdx.y * gridDim.x + blockIdx.x, pv);
 }
 
 template <typename R>
 void launch_recur(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st) {
     dim3 grid((g.V + kPBlock - 1) / kPBlock, 12, L.n);
-    hipLaunchKernelGGL(k_recur<R>, grid, dim3(kPBlock), 0, st, g, wk, L, coef, j, np_sten(g.V));
+    hipLaunchKernelGGL(k_recur<R>, grid, dim3(kPBlock), 0, st, g, wk, L, coef, j, np_sten(g.V), 0);
+}
+
+template <typename R>
+void launch_recur_replay(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st) {
+    dim3 grid((g.V + kPBlock - 1) / kPBlock, 12, L.n);
+    hipLaunchKernelGGL(k_recur<R>, grid, dim3(kPBlock), 0, st, g, wk, L, coef, j, np_sten(g.V), 1);
 }
 
 // out(s) = [psi(s) +] g5^{overlap} |x| sum_{j <= k_used} c_j v_j(s), canonical layout.
@@ -724,37 +921,21 @@ void launch_bwd_ra(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef
 // partials of Re vbar_j^H v_j and wbar_j^H w_j.  The last step (j = k_used) has
 // no residual adjoints: abar = alphabar w, vbar = |x| conj(c) eta + alphabar b,
 // wbar = conj(alphabar) a.
+// Epilogue of reverse step j for one entry, after the hops: the coefficient
+// adjoints from the block-summed partials `red` (not LAST), the adjoint fields'
+// stores and the step's partial sums.
 template <typename R, bool LAST, int BLK>
-__global__ __launch_bounds__(BLK) void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
-                                                    Work<R> wk, SrcList L, Coef coef0, int j, int npart_in) {
-    const int e = blockIdx.y, slot = L.slot[e];
-    const Coef coef = coef0.at(slot);
-    const int k_used = L.k[e];
+__device__ __forceinline__ void bwd_rb_finish(const Geom& g, double kappa, const Work<R>& wk, const Coef& coef,
+                                              int slot, int j, int k_used, int pslot, int a, int s,
+                                              const double (&red)[kNvRA], const Z<R> (&accs)[4],
+                                              const Z<R> (&accr)[4]) {
     const Z<R>* __restrict__ rbar_j = wk.f(slot, 6 + (j & 1));
     const Z<R>* __restrict__ rbar_n = wk.f(slot, 6 + ((j + 1) & 1));
     const Z<R>* __restrict__ sbar_j = wk.sb(slot, j);
     const bool carry = j + 1 < k_used;
     const Z<R>* __restrict__ sbar_n = carry ? wk.sb(slot, j + 1) : sbar_j;
-    const int sb = sten_block<BLK>(g);
-    if (sb < 0) return;   // padding workgroup (uniform over the block)
-    const int a = sten_colour<BLK>();
-    const int s = sb * kSites + threadIdx.x % kSites;
-    // the partial sums' loads go out with the hops' loads; only the epilogue needs
-    // the sums, so they are combined after the hops
-    double red[kNvRA];
-    Z<R> accs[4], accr[4];   // field A = sbar_j at +mu, field B = rbar_j at -mu
-    zero1(accs);
-    zero1(accr);
-    if (!LAST) {
-        gather_partials<kNvRA, BLK>(wk.p(slot, 1), npart_in, red);
-        if (s < g.V) {
-            hop_all_pair<BLK>(accs, accr, U, sbar_j, rbar_j, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu));
-            mem_fence_compiler();
-        }
-    }
     ZD abar = coef.abar_T[j];
     if (!LAST) {
-        block_sum<kNvRA, BLK>(red);
         abar = abar - mk<double>(red[0], red[1]) - mk<double>(red[2], red[3]);
         if (blockIdx.x == 0 && threadIdx.x == 0 && j >= 2) {
             coef.gbar_tot[j] = coef.gbar_T[j] - mk<double>(red[4], red[5]);
@@ -814,26 +995,109 @@ __global__ __launch_bounds__(BLK) void k_bwd_rb(const Z<R>* __restrict__ U, Geom
         pv[1] = d2r;
         pv[2] = d2i;
     }
-    write_partials_at<kNvRB, BLK>(wk.p(slot, 0), BLK == kSites ? (int)blockIdx.x : sb, pv);
+    write_partials_at<kNvRB, BLK>(wk.p(slot, 0), pslot, pv);
+}
+
+// Reverse step j (one entry per workgroup, grid.y = entry):
+//   vbar_j = |x| conj(c_j) eta + H^dag rbar_j + alphabar_j b_j - conj(alpha_j) rbar_j - conj(gamma_{j+1}) rbar_{j+1},
+//   wbar_j = H sbar_j + conj(alphabar_j) a_j - alpha_j sbar_j - beta_{j+1} sbar_{j+1},
+// using the forward pass's a_j and b_j = H^dag w_j, so the stencil acts on rbar_j
+// (at -mu) and sbar_j (at +mu) only.  Stores abar_j for the force and emits
+// partials of Re vbar_j^H v_j and wbar_j^H w_j.  The last step (j = k_used) has
+// no residual adjoints: abar = alphabar w, vbar = |x| conj(c) eta + alphabar b,
+// wbar = conj(alphabar) a.
+template <typename R, bool LAST, int BLK>
+__global__ __launch_bounds__(BLK) void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
+                                                    Work<R> wk, SrcList L, Coef coef0, int j, int npart_in) {
+    const int e = blockIdx.y, slot = L.slot[e];
+    const Coef coef = coef0.at(slot);
+    const int sb = sten_block<BLK>(g);
+    if (sb < 0) return;   // padding workgroup (uniform over the block)
+    const int a = sten_colour<BLK>();
+    const int s = sb * kSites + threadIdx.x % kSites;
+    // the partial sums' loads go out with the hops' loads; only the epilogue needs
+    // the sums, so they are combined after the hops
+    double red[kNvRA];
+    Z<R> accs[4], accr[4];   // field A = sbar_j at +mu, field B = rbar_j at -mu
+    zero1(accs);
+    zero1(accr);
+    if (!LAST) {
+        gather_partials<kNvRA, BLK>(wk.p(slot, 1), npart_in, red);
+        if (s < g.V) {
+            hop_all_pair<BLK>(accs, accr, U, wk.sb(slot, j), wk.f(slot, 6 + (j & 1)), g, s, a, neighbours(g, s),
+                              (R)emu, (R)(1.0 / emu));
+            mem_fence_compiler();
+        }
+        block_sum<kNvRA, BLK>(red);
+    }
+    bwd_rb_finish<R, LAST, BLK>(g, kappa, wk, coef, slot, j, L.k[e], BLK == kSites ? (int)blockIdx.x : sb, a, s,
+                                red, accs, accr);
+}
+
+// Colour split, not the last step: NS entries per workgroup sharing the link loads.
+template <typename R, int NS>
+__global__ __launch_bounds__(kCBlock) void k_bwd_rb_ms(const Z<R>* __restrict__ U, Geom g, double kappa,
+                                                       double emu, Work<R> wk, SrcList L, Coef coef0, int j,
+                                                       int npart_in) {
+    const int e0 = (int)blockIdx.y * NS;
+    const int sb = sten_block<kCBlock>(g);
+    if (sb < 0) return;   // padding workgroup (uniform over the block)
+    unsigned live = 0;
+    int slot[NS];
+    const Z<R>* fs[NS];
+    const Z<R>* fr[NS];
+    double red[NS][kNvRA];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        if (e0 + q < L.n) live |= 1u << q;
+        slot[q] = L.slot[min(e0 + q, L.n - 1)];
+        fs[q] = wk.sb(slot[q], j);
+        fr[q] = wk.f(slot[q], 6 + (j & 1));
+        gather_partials<kNvRA, kCBlock>(wk.p(slot[q], 1), npart_in, red[q]);
+    }
+    const int a = sten_colour<kCBlock>();
+    const int s = sb * kSites + threadIdx.x % kSites;
+    Z<R> accs[NS][4], accr[NS][4];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        zero1(accs[q]);
+        zero1(accr[q]);
+    }
+    if (s < g.V) {
+        hop_all_pairN<NS>(accs, accr, U, fs, fr, live, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu));
+        mem_fence_compiler();
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        if (live & (1u << q)) {
+            block_sum<kNvRA, kCBlock>(red[q]);
+            bwd_rb_finish<R, false, kCBlock>(g, kappa, wk, coef0.at(slot[q]), slot[q], j, L.k[e0 + q], sb, a, s,
+                                             red[q], accs[q], accr[q]);
+        }
+    }
 }
 
 template <typename R>
 void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
-                   Coef coef, int j, int last, hipStream_t st, Timing t) {
-    const dim3 grid(colour_grid(g.V) ? np_colour(g.V) : g.nwg, L.n);
+                   Coef coef, int j, int last, int ns, hipStream_t st, Timing t) {
     const int np = np_point(g.V);
     const bool cg = colour_grid(g.V);
+    const double emu = std::exp(mu);
+    const dim3 grid(cg ? np_colour(g.V) : g.nwg, L.n);
     if (last && cg)
-        timed_launch(k_bwd_rb<R, true, kSites>, grid, dim3(kSites), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j, np);
+        timed_launch(k_bwd_rb<R, true, kSites>, grid, dim3(kSites), st, t, U, g, kappa, emu, wk, L, coef, j, np);
     else if (last)
-        timed_launch(k_bwd_rb<R, true, kCBlock>, grid, dim3(kCBlock), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
-                     np);
+        timed_launch(k_bwd_rb<R, true, kCBlock>, grid, dim3(kCBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
     else if (cg)
-        timed_launch(k_bwd_rb<R, false, kSites>, grid, dim3(kSites), st, t, U, g, kappa, std::exp(mu), wk, L, coef, j,
-                     np);
+        timed_launch(k_bwd_rb<R, false, kSites>, grid, dim3(kSites), st, t, U, g, kappa, emu, wk, L, coef, j, np);
+    else if (ns == 4)
+        timed_launch(k_bwd_rb_ms<R, 4>, dim3(g.nwg, (L.n + 3) / 4), dim3(kCBlock), st, t, U, g, kappa, emu, wk, L,
+                     coef, j, np);
+    else if (ns == 2)
+        timed_launch(k_bwd_rb_ms<R, 2>, dim3(g.nwg, (L.n + 1) / 2), dim3(kCBlock), st, t, U, g, kappa, emu, wk, L,
+                     coef, j, np);
     else
-        timed_launch(k_bwd_rb<R, false, kCBlock>, grid, dim3(kCBlock), st, t, U, g, kappa, std::exp(mu), wk, L, coef,
-                     j, np);
+        timed_launch(k_bwd_rb_ms<R, 1>, dim3(g.nwg, L.n), dim3(kCBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
 }
 
 // =============================================================== force contraction
@@ -844,7 +1108,7 @@ void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const 
 // half spinors of the (1 +- g_nu) projectors, e_f = e^{+mu}, e_b = e^{-mu} for nu = t.
 template <int NU, typename R>
 __device__ void force_body(const Geom& g, double kappa, double emu, const Work<R>& wk, int slot, int k, int j0,
-                           int j1, int s, ZD* __restrict__ gout) {
+                           int j1, int s, ZD* __restrict__ gout, int accumulate) {
     const Nbr n = neighbours(g, s);
     const int y = n.fwd[NU];
     const double ef = (NU == 3) ? emu : 1.0, eb = (NU == 3) ? 1.0 / emu : 1.0;
@@ -871,7 +1135,10 @@ __device__ void force_body(const Geom& g, double kappa, double emu, const Work<R
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) gout[(size_t)(NU * 9 + a * 3 + b) * g.ldv + s] = (-kappa) * G[a][b];
+        for (int b = 0; b < 3; ++b) {
+            ZD& o = gout[(size_t)(NU * 9 + a * 3 + b) * g.ldv + s];
+            o = accumulate ? o + (-kappa) * G[a][b] : (-kappa) * G[a][b];
+        }
 }
 
 // Blocks of 64 sites x 4 directions, one wavefront per direction: the four links of
@@ -880,30 +1147,34 @@ __device__ void force_body(const Geom& g, double kappa, double emu, const Work<R
 // that neighbour spinors are mostly still in L2.
 template <typename R>
 __global__ __launch_bounds__(4 * kSites) void k_force(Geom g, double kappa, double emu, Work<R> wk, SrcList L,
-                                                      int nchunk, ZD* __restrict__ gpart) {
+                                                      int nchunk, ZD* __restrict__ gpart, int jlo, int jhi,
+                                                      int accumulate) {
     const int nu = __builtin_amdgcn_readfirstlane(threadIdx.x / kSites);
     const int sb = g.sbmap ? g.sbmap[blockIdx.x] : (int)blockIdx.x;
     const int s = sb * kSites + threadIdx.x % kSites;
     if (sb < 0 || s >= g.V) return;
     const int e = blockIdx.z, slot = L.slot[e];
     const int k = L.k[e];
+    const int top = jhi > 0 ? min(jhi, k) : k;   // steps jlo..top
+    const int n = top - jlo + 1;
     const int chunk = blockIdx.y;
-    const int j0 = 1 + (int)((long long)k * chunk / nchunk);
-    const int j1 = 1 + (int)((long long)k * (chunk + 1) / nchunk);
+    const int j0 = jlo + (int)((long long)n * chunk / nchunk);
+    const int j1 = jlo + (int)((long long)n * (chunk + 1) / nchunk);
     ZD* out = gpart + ((size_t)slot * nchunk + chunk) * 36 * g.ldv;
     switch (nu) {
-        case 0: force_body<0>(g, kappa, emu, wk, slot, k, j0, j1, s, out); break;
-        case 1: force_body<1>(g, kappa, emu, wk, slot, k, j0, j1, s, out); break;
-        case 2: force_body<2>(g, kappa, emu, wk, slot, k, j0, j1, s, out); break;
-        default: force_body<3>(g, kappa, emu, wk, slot, k, j0, j1, s, out); break;
+        case 0: force_body<0>(g, kappa, emu, wk, slot, k, j0, j1, s, out, accumulate); break;
+        case 1: force_body<1>(g, kappa, emu, wk, slot, k, j0, j1, s, out, accumulate); break;
+        case 2: force_body<2>(g, kappa, emu, wk, slot, k, j0, j1, s, out, accumulate); break;
+        default: force_body<3>(g, kappa, emu, wk, slot, k, j0, j1, s, out, accumulate); break;
     }
 }
 
 template <typename R>
 void launch_force(const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L, int nchunk, ZD* gpart,
-                  hipStream_t st) {
+                  hipStream_t st, int jlo, int jhi, int accumulate) {
     dim3 grid(g.sbmap ? g.nwg : np_stencil(g.V), nchunk, L.n);
-    hipLaunchKernelGGL(k_force<R>, grid, dim3(4 * kSites), 0, st, g, kappa, std::exp(mu), wk, L, nchunk, gpart);
+    hipLaunchKernelGGL(k_force<R>, grid, dim3(4 * kSites), 0, st, g, kappa, std::exp(mu), wk, L, nchunk, gpart, jlo,
+                       jhi, accumulate);
 }
 
 __device__ __forceinline__ double boundary_sign(const Geom& g, int nu, int s, int antiperiodic) {
@@ -1127,15 +1398,18 @@ void launch_source_grad(const Geom& g, const Work<R>& wk, const SrcList& L, Coef
     template void launch_sources_to_soa<R>(const ZD*, int, int, const Work<R>&, const SrcList&, const Geom&,    \
                                            hipStream_t);                                                        \
     template void launch_fwd_pair<R>(const Z<R>*, const Geom&, double, double, const Work<R>&, const SrcList&,  \
-                                     Coef, int, int, hipStream_t, Timing);                                      \
+                                     Coef, int, int, int, hipStream_t, Timing);                                 \
     template void launch_recur<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);         \
+    template void launch_fwd_replay<R>(const Z<R>*, const Geom&, double, double, const Work<R>&,                \
+                                       const SrcList&, Coef, int, hipStream_t);                                 \
+    template void launch_recur_replay<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);  \
     template void launch_assemble<R>(const Geom&, const Work<R>&, const SrcList&, Coef, const ZD*, int, ZD*,    \
                                      hipStream_t);                                                              \
     template void launch_bwd_ra<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);        \
     template void launch_bwd_rb<R>(const Z<R>*, const Geom&, double, double, const Work<R>&, const SrcList&,    \
-                                   Coef, int, int, hipStream_t, Timing);                                        \
+                                   Coef, int, int, int, hipStream_t, Timing);                                   \
     template void launch_force<R>(const Geom&, double, double, const Work<R>&, const SrcList&, int, ZD*,        \
-                                  hipStream_t);                                                                 \
+                                  hipStream_t, int, int, int);                                                  \
     template void launch_source_grad<R>(const Geom&, const Work<R>&, const SrcList&, Coef, ZD*, hipStream_t);
 
 TSLOV_INST(double)

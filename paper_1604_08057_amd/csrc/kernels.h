@@ -45,9 +45,13 @@ struct Work {
     Z<R>* F;    // [slot][kNF] fields
     double* part;  // [slot][kNP][pstride]
     size_t fe;     // complex elements per field (12 ldv)
-    int kcap;
+    int kcap;      // steps held per slot
     int pstride;
-    __host__ __device__ size_t step(int slot, int j) const { return ((size_t)slot * kcap + (j - 1)) * fe; }
+    int ring;      // 0: step j at index j - 1; 1: at (j - 1) mod kcap (vectors regenerated in segments)
+    __host__ __device__ size_t step(int slot, int j) const {
+        const int i = ring ? (j - 1) % kcap : j - 1;
+        return ((size_t)slot * kcap + i) * fe;
+    }
     __host__ __device__ Z<R>* v(int slot, int j) const { return V + step(slot, j); }
     __host__ __device__ Z<R>* w(int slot, int j) const { return W + step(slot, j); }
     __host__ __device__ Z<R>* a(int slot, int j) const { return A + step(slot, j); }
@@ -71,11 +75,23 @@ template <typename R>
 void launch_sources_to_soa(const ZD* canon, int which, int g5, const Work<R>& wk, const SrcList& L, const Geom& g,
                            hipStream_t st);
 // Step j of the Lanczos process for every list entry (k[e] = the entry's target size).
+// ns: entries per workgroup on the colour-split layout (1, 2 or 4), which share the
+// link loads; an entry's results do not depend on it.
 template <typename R>
 void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
-                     Coef coef, int j, int has_eta, hipStream_t st, Timing t = {});
+                     Coef coef, int j, int has_eta, int ns, hipStream_t st, Timing t = {});
 template <typename R>
 void launch_recur(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st);
+// Replay of step j for regeneration: the step's own kernels (one entry per
+// workgroup) with the recorded coefficients (beta_j, gamma_j; alpha_j) in place of
+// their reductions, rewriting v_j, w_j, a_j, b_j (fwd) and the residuals of step j
+// for entries with j < k[e] (recur) bit for bit, and no partial sums, flags or
+// coefficient records.
+template <typename R>
+void launch_fwd_replay(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+                       Coef coef, int j, hipStream_t st);
+template <typename R>
+void launch_recur_replay(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st);
 // out[src] (canonical) = [psi[src] +] g5^{overlap} |x| sum_j c_j v_j
 template <typename R>
 void launch_assemble(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, const ZD* psi_canon,
@@ -91,11 +107,13 @@ template <typename R>
 void launch_bwd_ra(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st);
 template <typename R>
 void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
-                   Coef coef, int j, int last, hipStream_t st, Timing t = {});
-// Per-link force partials gpart[slot][chunk][36 planes] over all steps of each entry.
+                   Coef coef, int j, int last, int ns, hipStream_t st, Timing t = {});
+// Per-link force partials gpart[slot][chunk][36 planes] over the steps j of
+// [jlo, min(jhi, k[e])] of each entry (jhi = 0: every step), stored, or added to
+// the partials already there (accumulate = 1).
 template <typename R>
 void launch_force(const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L, int nchunk, ZD* gpart,
-                  hipStream_t st);
+                  hipStream_t st, int jlo = 1, int jhi = 0, int accumulate = 0);
 // dU[src] (canonical) from the chunk partials, boundary sign undone.
 void launch_force_reduce(const Geom& g, const ZD* gpart, int nchunk, const SrcList& L, int antiperiodic, ZD* dU,
                          hipStream_t st);

@@ -31,7 +31,7 @@ KERNEL_FWD_PAIR, KERNEL_BWD_PAIR, KERNEL_APPLY = 0, 1, 2
 EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links", "tslov_apply_dw",
            "tslov_apply_h", "tslov_sign", "tslov_overlap", "tslov_sign_grad", "tslov_sign_grad_batched",
            "tslov_current_estimate", "tslov_error_estimate", "tslov_lanczos_matrix", "tslov_dense_sign", "tslov_timing_enable",
-           "tslov_timing_read", "tslov_kernel_bytes"]
+           "tslov_timing_read", "tslov_kernel_bytes", "tslov_set_pair_ns", "tslov_get_pair_ns", "tslov_set_graphs"]
 
 
 class TslovLibraryMissing(ImportError):
@@ -108,6 +108,9 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_timing_enable": ([vp, ci], ci),
         "tslov_timing_read": ([vp, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
         "tslov_kernel_bytes": ([vp, ci], cd),
+        "tslov_set_pair_ns": ([vp, ci], ci),
+        "tslov_set_graphs": ([vp, ci], ci),
+        "tslov_get_pair_ns": ([vp, ctypes.POINTER(ci), ctypes.POINTER(ci)], ci),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -215,7 +218,9 @@ class Context:
         return eps.value
 
     def sign_grad(self, eta: torch.Tensor, psi: torch.Tensor, k: int, want_dpsi: bool = False,
-                  dU: torch.Tensor | None = None, defl: "Deflation | None" = None):
+                  dU: torch.Tensor | None = None, defl: "Deflation | None" = None, recompute: int = 0):
+        """S = Re <eta|TSL_k(psi)>, dS/dU (and dS/dpsi); recompute = m > 0 holds m + 2
+        steps of Krylov vectors and regenerates them in segments of m for the reverse pass."""
         eta = self._spinor(eta, "eta")
         psi = self._spinor(psi, "psi")
         if dU is None:
@@ -224,7 +229,7 @@ class Context:
         S = ctypes.c_double()
         info = InfoStruct()
         d = None if defl is None else ctypes.byref(defl.struct)
-        _check(self.lib, self.lib.tslov_sign_grad(self.handle, _ptr(eta), _ptr(psi), int(k), d, 0,
+        _check(self.lib, self.lib.tslov_sign_grad(self.handle, _ptr(eta), _ptr(psi), int(k), d, int(recompute),
                                                   ctypes.byref(S), _ptr(dU), _ptr(dpsi), ctypes.byref(info)))
         return S.value, dU, dpsi, Info.of(info)
 
@@ -301,6 +306,20 @@ class Context:
     def kernel_bytes(self, which: int) -> float:
         return float(self.lib.tslov_kernel_bytes(self.handle, int(which)))
 
+    def set_graphs(self, on: bool = True):
+        """Capture the Lanczos loops as HIP graphs and replay them (needs a non-null stream)."""
+        _check(self.lib, self.lib.tslov_set_graphs(self.handle, int(bool(on))))
+
+    def set_pair_ns(self, ns: int = 0):
+        """Entries per workgroup of the batched colour-split pair kernels (0: timed pick)."""
+        _check(self.lib, self.lib.tslov_set_pair_ns(self.handle, int(ns)))
+
+    def pair_ns(self):
+        """The timed picks (forward, reverse); 0 while none is made."""
+        f, b = ctypes.c_int(), ctypes.c_int()
+        _check(self.lib, self.lib.tslov_get_pair_ns(self.handle, ctypes.byref(f), ctypes.byref(b)))
+        return f.value, b.value
+
 
 class Deflation:
     """Keeps the eigenvector tensors and the eigenvalue array alive for the C struct."""
@@ -323,20 +342,22 @@ class Deflation:
 class SignGrad(torch.autograd.Function):
     """S = Re <eta | TSL_k(H(U), psi)> with a hand-written backward (HIP).
 
-    ``forward(U, psi, eta, ctx, k)`` loads U into the context, runs the forward
-    pass and the reverse-mode recursion once, and keeps dS/dU and dS/dpsi;
+    ``forward(U, psi, eta, ctx, k, recompute=0)`` loads U into the context, runs the
+    forward pass and the reverse-mode recursion once (regenerating the Krylov
+    vectors in segments of ``recompute`` steps if it is positive), and keeps
+    dS/dU and dS/dpsi;
     ``backward`` scales them by the incoming gradient (torch's convention for
     real outputs of complex inputs: grad = dS/dRe + i dS/dIm).
     """
 
     @staticmethod
-    def forward(ctx, U, psi, eta, context: Context, k: int):
+    def forward(ctx, U, psi, eta, context: Context, k: int, recompute: int = 0):
         context.set_links(U.detach())
-        S, dU, dpsi, _ = context.sign_grad(eta.detach(), psi.detach(), k, want_dpsi=True)
+        S, dU, dpsi, _ = context.sign_grad(eta.detach(), psi.detach(), k, want_dpsi=True, recompute=recompute)
         ctx.save_for_backward(dU, dpsi)
         return torch.tensor(S, dtype=torch.float64, device=U.device)
 
     @staticmethod
     def backward(ctx, grad):
         dU, dpsi = ctx.saved_tensors
-        return grad * dU, grad * dpsi, None, None, None
+        return grad * dU, grad * dpsi, None, None, None, None

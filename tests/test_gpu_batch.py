@@ -5,6 +5,8 @@
   at the 4^4 workload (k = 64, 17, 40, 64, 1), at 8^4 (k from 150 to 200) and
   on a 10^4 lattice, which runs the colour-split stencil layout on an
   XCD-ordered, padded grid (k = 40, 25, 33, with the oracle for one source);
+* on that layout, 1, 2 or 4 entries per workgroup and the timed pick give the
+  same bits (five entries: a ragged last workgroup);
 * against the oracle per source: S, dS/dU, dS/dpsi to 1e-10 relative;
 * a zero source inside a batch: S = 0 and zero derivatives, the others unchanged;
 * the current estimator against the oracle estimator (mean of per-source U(1)
@@ -90,6 +92,40 @@ def test_batch_equals_single_colour_split():
     eG, eP = rel(dU[1], ref["G"]), rel(dpsi[1], ref["dpsi"])
     say(f"  source 1 vs oracle: S {eS:.2e} G {eG:.2e} dpsi {eP:.2e}")
     assert eS < 1e-10 and eG < 1e-10 and eP < 1e-10
+
+
+def test_batch_pair_ns_identical():
+    # the colour-split pair kernels with 1, 2 or 4 entries per workgroup (sharing
+    # every link load) and the timed pick give the same bits; five entries leave a
+    # ragged last workgroup for 2 and 4, and the list shrinks as entries finish
+    dims, mass, mu = (10, 10, 10, 10), -2.0, 0.3
+    U = random_links(dims, 0.4, np.random.default_rng(19))
+    ks = [30, 12, 27, 30, 19]
+    psis, etas = _sources(5, 10000, 49), _sources(5, 10000, 50)
+    ctx = _ctx(dims, mass, mu, U)
+    runs = {}
+    for ns in (0, 1, 2, 4):
+        say(f"batched 10^4 ks={ks} entries per workgroup {ns or 'timed'}")
+        ctx.set_pair_ns(ns)
+        S, dU, dpsi, _ = ctx.sign_grad_batched(dev(etas), dev(psis), ks, want_dpsi=True)
+        runs[ns] = (S, dU, dpsi)
+    fwd, bwd = ctx.pair_ns()
+    say(f"  timed picks: forward {fwd}, reverse {bwd}")
+    ctx.close()
+    assert fwd in (1, 2, 4) and bwd in (1, 2, 4)
+    S0, dU0, dpsi0 = runs[1]
+    for ns in (0, 2, 4):
+        S, dU, dpsi = runs[ns]
+        assert S == S0, ns
+        assert torch.equal(dU, dU0) and torch.equal(dpsi, dpsi0), ns
+
+
+def test_pair_ns_rejects_bad_value():
+    from paper_1604_08057_amd.tslov import TslovError
+    ctx = _ctx((2, 2, 2, 4), -2.0, 0.3, random_links((2, 2, 2, 4), 0.5, np.random.default_rng(1)))
+    with pytest.raises(TslovError):
+        ctx.set_pair_ns(3)
+    ctx.close()
 
 
 def test_zero_source_in_batch():

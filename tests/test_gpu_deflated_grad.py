@@ -5,7 +5,8 @@ reduced resolvents built from the full dense spectrum; the GPU solves the
 reduced-resolvent systems by CGNR to relative residual 1e-11.  Bar: S to 1e-10,
 dS/dU and dS/dpsi to 1e-8 relative (the solves' residual times the conditioning
 of lambda_i - H on the complement of R_i, measured below 1e-9 on these cases).
-Cases: l = 10 (k = 24) on 2^3x4 and l = 20 (k = 60) on 3^3x4.
+Cases: l = 10 (k = 24) on 2^3x4 and l = 20 (k = 60) on 3^3x4, the latter also
+with the Krylov vectors regenerated in segments of 11 steps.
 """
 import numpy as np
 import pytest
@@ -18,8 +19,9 @@ from synthetic import random_links, z2_complex_source
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("dims,l,k", [((2, 2, 2, 4), 10, 24), ((3, 3, 3, 4), 20, 60)])
-def test_deflated_gradient(dims, l, k):
+@pytest.mark.parametrize("dims,l,k,m", [((2, 2, 2, 4), 10, 24, 0), ((3, 3, 3, 4), 20, 60, 0),
+                                        ((3, 3, 3, 4), 20, 60, 11)])
+def test_deflated_gradient(dims, l, k, m):
     from paper_1604_08057_amd import Context
     mass, mu = -2.0, 0.3
     r = np.random.default_rng(31)
@@ -32,8 +34,8 @@ def test_deflated_gradient(dims, l, k):
     ctx = Context(dims, mass, mu)
     ctx.set_links(dev(U))
     defl = ctx.deflation(dev(R.T.reshape(l, V, 4, 3)), dev(L.T.reshape(l, V, 4, 3)), lam)
-    Sg, dU, dpsi, info = ctx.sign_grad(dev(eta), dev(psi), k, want_dpsi=True, defl=defl)
+    Sg, dU, dpsi, info = ctx.sign_grad(dev(eta), dev(psi), k, want_dpsi=True, defl=defl, recompute=m)
     ctx.close()
     eS, eG, eP = abs(Sg - S) / abs(S), rel(host(dU), G), rel(host(dpsi), pb)
-    say(f"deflated grad {dims} l={l} k={k}: S {eS:.2e} G {eG:.2e} dpsi {eP:.2e} cg iterations {info.reserved}")
+    say(f"deflated grad {dims} l={l} k={k} recompute={m}: S {eS:.2e} G {eG:.2e} dpsi {eP:.2e} cg iterations {info.reserved}")
     assert eS < 1e-10 and eG < 1e-8 and eP < 1e-8

@@ -11,7 +11,13 @@
   random su(3)/U(1) link directions at 8^4 (a property that holds at any size;
   steps of 2e-3 and 1e-3 keep the forward's ~1e-11 relative rounding noise
   out of the difference quotient);
-* bitwise determinism of repeated calls (fixed-order reductions, no atomics).
+* bitwise determinism of repeated calls (fixed-order reductions, no atomics);
+* Krylov-vector recompute (segments of m steps regenerated from checkpoints):
+  S bit-identical to storing every vector (same forward pass), dS/dpsi and
+  dS/dU to 1e-12 (regenerated vectors and per-segment force sums agree to
+  rounding), on the colour grid (8^4, m = 7 with a ragged last segment, m = 16)
+  and the colour split (10^4); through the autograd function against the
+  oracle at 4^4.
 """
 import numpy as np
 import pytest
@@ -139,4 +145,43 @@ def test_autograd_function():
     ref = GR.grad_autograd(WilsonOperator(wl.dims, wl.mass, wl.mu), wl.links(), wl.psi(), wl.eta(), wl.k)
     assert rel(host(U.grad), 3.0 * ref["G"]) < 1e-10
     assert rel(host(psi.grad), 3.0 * ref["dpsi"]) < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("dims,k,m", [((8, 8, 8, 8), 60, 7), ((8, 8, 8, 8), 60, 16), ((10, 10, 10, 10), 40, 9)])
+def test_recompute_matches_stored(dims, k, m):
+    from paper_1604_08057_amd import Context
+    rng = np.random.default_rng(sum(dims) + k + m)
+    V = int(np.prod(dims))
+    U = random_links(dims, 0.4, rng)
+    psi, eta = dev(z2_complex_source(V, rng)), dev(z2_complex_source(V, rng))
+    ctx = Context(dims, -2.0, 0.2)
+    ctx.set_links(dev(U))
+    say(f"recompute dims={dims} k={k} m={m}")
+    S0, dU0, dp0, i0 = ctx.sign_grad(eta, psi, k, want_dpsi=True)
+    S1, dU1, dp1, i1 = ctx.sign_grad(eta, psi, k, want_dpsi=True, recompute=m)
+    S2, dU2, _, _ = ctx.sign_grad(eta, psi, k, want_dpsi=True)   # back to storing every vector
+    ctx.close()
+    e, ep = rel(host(dU1), host(dU0)), rel(host(dp1), host(dp0))
+    say(f"  k_used {i0.k_used}/{i1.k_used}: S equal {S1 == S0}, dpsi rel diff {ep:.2e}, dU rel diff {e:.2e}")
+    assert i1.k_used == i0.k_used
+    assert S1 == S0          # the forward pass is the same
+    assert e < 1e-12 and ep < 1e-12
+    assert S2 == S0 and torch.equal(dU2, dU0)
+
+
+def test_recompute_autograd_function():
+    from paper_1604_08057_amd import Context, SignGrad
+    wl = workload(1)
+    ctx = Context(wl.dims, wl.mass, wl.mu)
+    U = dev(wl.links()).requires_grad_(True)
+    psi = dev(wl.psi()).requires_grad_(True)
+    say(f"recompute through the autograd function, 4^4 k={wl.k} m=5")
+    S = SignGrad.apply(U, psi, dev(wl.eta()), ctx, wl.k, 5)
+    S.backward()
+    ref = GR.grad_autograd(WilsonOperator(wl.dims, wl.mass, wl.mu), wl.links(), wl.psi(), wl.eta(), wl.k)
+    eG, eP = rel(host(U.grad), ref["G"]), rel(host(psi.grad), ref["dpsi"])
+    say(f"  G {eG:.2e} dpsi {eP:.2e}")
+    assert abs(S.item() - ref["S"]) / abs(ref["S"]) < 1e-10
+    assert eG < 1e-10 and eP < 1e-10
     ctx.close()
