@@ -41,7 +41,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sgn(H)ψ+dU-derivative sources/s, mixed vs FP64 @≤1e-6 rel; stencil HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAMES = {0: "k_fwd_pair<double, 64> (fused Lanczos stencil pair, colour grid)",
+KERNEL_NAMES = {0: "k_fwd_pair<double, 128> (fused Lanczos stencil pair, colour grid, directions over two wavefronts)",
                 1: "k_bwd_rb<double, false, 64> (reverse-mode stencil pair, colour grid)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stencil_pair_8x8x8x8.txt")
 # live kernel timing samples every 16th launch of a class: an event pair adds ~5 us
@@ -216,8 +216,9 @@ def batched_leg(ks_single: int = 4):
     dtm = time.perf_counter() - tm
     ctxm.close()
     err_S = max(abs(a - b) / abs(b) for a, b in zip(Sm, S))
-    err_dU = max(float(torch.linalg.vector_norm(dUm[s] - dU[s]) / torch.linalg.vector_norm(dU[s]))
-                 for s in range(len(ks)))
+    errs = sorted(float(torch.linalg.vector_norm(dUm[s] - dU[s]) / torch.linalg.vector_norm(dU[s]))
+                  for s in range(len(ks)))
+    err_dU, med_dU = errs[-1], errs[len(errs) // 2]
     del dU, dUm
     return {"workload": "6x18^3 (V=34992), mu=0.5, link spread 0.35, 32 Z2 sources, k uniform in [100, 400]",
             "sources": len(ks), "sum_k": int(sum(ks)), "precision": "fp64",
@@ -228,7 +229,8 @@ def batched_leg(ks_single: int = 4):
             "bwd_pair_GBs": bwd_gbs, "bwd_pair_frac": bwd_gbs / HBM_PEAK_GBS,
             "launches": {"fwd_pair": n0, "bwd_pair": n1}, "identical_to_single": same,
             "entries_per_workgroup": {"fwd_pair": picks[0], "bwd_pair": picks[1]},
-            "mixed_sources_per_s": len(ks) / dtm, "mixed_max_rel_err_S": err_S, "mixed_max_rel_err_dU": err_dU}
+            "mixed_sources_per_s": len(ks) / dtm, "mixed_max_rel_err_S": err_S, "mixed_max_rel_err_dU": err_dU,
+            "mixed_median_rel_err_dU": med_dU}
 
 
 def precision_leg():

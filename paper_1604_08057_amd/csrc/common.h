@@ -13,6 +13,7 @@ constexpr int kWave = 64;      // CDNA wavefront
 constexpr int kBlock = 128;    // threads per block of the simple per-site kernels
 constexpr int kSites = 64;     // sites per wavefront (and site block) of the colour-layout stencil kernels
 constexpr int kCBlock = 3 * kSites;   // colour split: one wavefront per colour
+constexpr int kHBlock = 2 * kSites;   // colour grid, forward pair: the directions split over two wavefronts
 constexpr int kPBlock = 256;   // pointwise kernels: sites per block, grid.y = 12 planes
 
 constexpr int kXcd = 8;        // accelerator complex dies; workgroups go to them round robin
@@ -357,12 +358,12 @@ __device__ __forceinline__ int wave_colour() { return __builtin_amdgcn_readfirst
 // grid index in the colour grid and its site block in the colour split.
 template <int BLK>
 __device__ __forceinline__ int sten_colour() {
-    if (BLK == kSites) return blockIdx.x / (gridDim.x / 3);
+    if (BLK != kCBlock) return blockIdx.x / (gridDim.x / 3);
     return wave_colour();
 }
 template <int BLK>
 __device__ __forceinline__ int sten_block(const Geom& g) {
-    if (BLK == kSites) return blockIdx.x % (gridDim.x / 3);
+    if (BLK != kCBlock) return blockIdx.x % (gridDim.x / 3);
     return g.sbmap[blockIdx.x];
 }
 

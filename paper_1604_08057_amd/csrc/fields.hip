@@ -261,6 +261,42 @@ __device__ __forceinline__ void hop_all_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], c
     }
 }
 
+// Colour grid with two wavefronts per block: wavefront h takes directions 2h and
+// 2h + 1 (eager loads), halving the chain of dependent memory round trips.
+template <typename R>
+__device__ __forceinline__ void hop_half_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
+                                              const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
+                                              const Geom& g, int s, int a, const Nbr& n, R ep, R em, int half) {
+    if (half == 0) {
+        hop_dir_pair1_eager<0>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
+        hop_dir_pair1_eager<1>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
+    } else {
+        hop_dir_pair1_eager<2>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
+        hop_dir_pair1_eager<3>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
+    }
+}
+
+// Adds wavefront 1's sums to wavefront 0's (through LDS, one barrier): afterwards
+// wavefront 0 holds the full sums (directions 0, 1 then 2, 3).
+template <typename R>
+__device__ __forceinline__ void combine_halves(Z<R> (&acca)[4], Z<R> (&accb)[4], int half) {
+    __shared__ Z<R> xa[4][kSites], xb[4][kSites];
+    const int l = threadIdx.x % kSites;
+    if (half == 1)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            xa[sp][l] = acca[sp];
+            xb[sp][l] = accb[sp];
+        }
+    __syncthreads();
+    if (half == 0)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            acca[sp] = acca[sp] + xa[sp][l];
+            accb[sp] = accb[sp] + xb[sp][l];
+        }
+}
+
 // The colour-split pair hops for NS entries of a batch at once: every link row is
 // loaded once and applied to the 2*NS fields (A_q at +mu, B_q at -mu) of the
 // entries whose bit is set in the block-uniform mask `live`.  Each accumulator
@@ -594,12 +630,15 @@ __device__ __forceinline__ void fwd_pair_finish(const Geom& g, double kappa, con
 // apply a = H(mu) v_j and b = H(-mu) w_j = H^dag w_j with shared link loads, and
 // emit per-block partial sums of alpha_j = w_j^H a, |a|^2 and eta^H v_j.  At
 // j >= 2 the step first decides breakdown from the previous omega and norms.
-// Colour grid: one entry per workgroup (grid.y = entry).
+// Colour grid: one entry per workgroup (grid.y = entry), two wavefronts per
+// workgroup, each with two of the four directions (half the chain of dependent
+// memory round trips); wavefront 0 adds the halves and runs the epilogue.
 template <typename R, int BLK>
 __global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
                                                   Work<R> wk, SrcList L, Coef coef0, int j, int npart_in,
                                                   int has_eta, int replay) {
-    static_assert(BLK == kSites, "colour-grid kernel");
+    static_assert(BLK == kHBlock, "colour-grid kernel: two wavefronts share the directions");
+    const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kSites);
     const int slot = L.slot[blockIdx.y];
     const Coef coef = coef0.at(slot);
     const int first = j == 1;
@@ -609,21 +648,23 @@ __global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Ge
     // depend on the sums (normalisation and breakdown act in the epilogue), so they
     // run before the sums are combined, and a breakdown step discards them
     double red[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
-    if (!replay) gather_partials<kNvRecur, kSites>(wk.p(slot, 1), npart_in, red);
-    const int sb = sten_block<kSites>(g);
+    if (!replay) gather_partials<kNvRecur, BLK>(wk.p(slot, 1), npart_in, red);
+    const int sb = sten_block<BLK>(g);
     if (!replay && block_flag(coef.status)) return;
-    const int a = sten_colour<kSites>();
+    const int a = sten_colour<BLK>();
     const int s = sb * kSites + threadIdx.x % kSites;
     Z<R> acca[4], accb[4];
     zero1(acca);
     zero1(accb);
     if (s < g.V) {
-        hop_all_pair<kSites>(acca, accb, U, rin, sin, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu));
+        hop_half_pair(acca, accb, U, rin, sin, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu), half);
         mem_fence_compiler();
     }
-    if (!replay) block_sum<kNvRecur, kSites>(red);
-    fwd_pair_finish<R, kSites>(g, kappa, wk, coef, slot, j, (int)blockIdx.x, a, s, red, acca, accb, rin, sin,
-                               has_eta, replay);
+    combine_halves(acca, accb, half);
+    if (!replay) block_sum<kNvRecur, BLK>(red);
+    // wavefront 1 has handed over its sums: no site of its own in the epilogue
+    fwd_pair_finish<R, BLK>(g, kappa, wk, coef, slot, j, (int)blockIdx.x, a, half ? g.V : s, red, acca, accb, rin,
+                            sin, has_eta, replay);
 }
 
 // Colour split: NS entries per workgroup (entries NS*blockIdx.y + q), which share
@@ -687,8 +728,8 @@ void fwd_pair_launch(const Z<R>* U, const Geom& g, double kappa, double mu, cons
     const int npart_in = j == 1 ? grid_for(g.V) : np_point(g.V);
     const double emu = std::exp(mu);
     if (colour_grid(g.V)) {
-        timed_launch(k_fwd_pair<R, kSites>, dim3(np_colour(g.V), L.n), dim3(kSites), st, t, U, g, kappa, emu, wk, L,
-                     coef, j, npart_in, has_eta, replay);
+        timed_launch(k_fwd_pair<R, kHBlock>, dim3(np_colour(g.V), L.n), dim3(kHBlock), st, t, U, g, kappa, emu, wk,
+                     L, coef, j, npart_in, has_eta, replay);
         return;
     }
     const dim3 block(kCBlock);
