@@ -93,20 +93,21 @@ def main(fetch_csv: str, write_csv: str, out: str, volume: int = 4096):
                      f"{(f * ff + w * fw) * 1024:18.0f} {V4 * 60 * 16:12d}")
     except statistics.StatisticsError:
         pass
-    # the batched 6x18^3 workload's stencil pairs (colour split, ns entries per
-    # workgroup sharing the link loads): the dispatches over the whole batch of 32
-    # entries, per entry; algorithmic = the entry's fields + 1/32 of the links
-    Vb, nwg, nb = 6 * 18 ** 3, site_workgroups((18, 18, 18, 6)), 32
+    # the batched 6x18^3 workload's FP64 stencil pairs (colour split, one entry per
+    # workgroup as the tuner picks, sources in memory-sized groups): every dispatch
+    # on this lattice, per entry-step; algorithmic = the entry's fields + the links
+    # once per launch, spread over the launch's entries
+    Vb, per_src = 6 * 18 ** 3, site_workgroups((18, 18, 18, 6)) * 192
     for base, planes in (("k_fwd_pair_ms", 6 * 12), ("k_bwd_rb_ms", 12 * 12)):
-        for ns in (1, 2, 4):
-            name = f"{base}<double, {ns}>"
-            s_ = sel(name, str(nwg * 192 * ((nb + ns - 1) // ns)))
-            if s_:
-                f = statistics.mean(float(a["Counter_Value"]) for a, _ in s_) / nb
-                w = statistics.mean(float(b["Counter_Value"]) for _, b in s_) / nb
-                alg = Vb * planes * 16 + Vb * 36 * 16 // nb
-                lines.append(f"{name + ' (6x18^3)':31s} {'/entry':>7s} {len(s_):10d} {f:10.1f} {w:10.1f} "
-                             f"{(f * ff + w * fw) * 1024:18.0f} {alg:12d}")
+        name = f"{base}<double, 1>"
+        s_ = [(a, b) for a, b in sel(name) if int(a["Grid_Size"]) % per_src == 0]   # this lattice only
+        entries = sum(int(a["Grid_Size"]) // per_src for a, _ in s_)
+        if entries:
+            f = sum(float(a["Counter_Value"]) for a, _ in s_) / entries
+            w = sum(float(b["Counter_Value"]) for _, b in s_) / entries
+            alg = Vb * planes * 16 + Vb * 36 * 16 * len(s_) // entries
+            lines.append(f"{name + ' (6x18^3)':31s} {'/entry':>7s} {len(s_):10d} {f:10.1f} {w:10.1f} "
+                         f"{(f * ff + w * fw) * 1024:18.0f} {alg:12d}")
     lines += ["#", "# read by bench.py (the dominant stencil kernel of the timed 8^4 step):",
               "kernel: k_bwd_rb<double, false, 64>",
               f"hbm_bytes_per_launch: {res['k_bwd_rb<double, false, 64>']:.0f}",
