@@ -439,6 +439,12 @@ const Z<R>* links(const tslov_ctx* c) {
 }
 
 // Device bytes one source of up to kcap steps needs (workspace sizing).
+// Chunks of steps the force contraction splits each entry into (its partials are
+// summed afterwards): about 2^18 threads in all, and at least 16 chunks so that a
+// large lattice does not leave each thread a loop over every step.  A function of
+// the lattice only, so an entry's result does not depend on its batch.
+int force_chunks(int V) { return std::max(16, std::min((1 << 18) / (4 * V), 64)); }
+
 size_t bytes_per_source(const tslov_ctx* c, int kcap, int grad, int m = 0) {
     const size_t fb = c->field_bytes();
     const int ring = ring_steps(kcap, m);
@@ -446,7 +452,8 @@ size_t bytes_per_source(const tslov_ctx* c, int kcap, int grad, int m = 0) {
     if (ring) b += (size_t)4 * n_segments(kcap, m) * fb;
     b += (size_t)tslov::kNP * c->pstride() * sizeof(double) + coef_bytes(1, kcap);
     b += (size_t)6 * kcap * kcap * sizeof(ZD) + (size_t)tslov::dense_pstride(kcap) * sizeof(double);
-    if (grad) b += (size_t)2 * 36 * c->g.ldv * sizeof(ZD) + (size_t)2 * 12 * c->g.V * sizeof(ZD);
+    if (grad)
+        b += (size_t)(force_chunks(c->g.V) + 1) * 36 * c->g.ldv * sizeof(ZD) + (size_t)2 * 12 * c->g.V * sizeof(ZD);
     return b;
 }
 
@@ -469,6 +476,19 @@ int batch_capacity(const tslov_ctx* c, int kcap, int grad, int m = 0) {
     const double per = (double)bytes_per_source(c, kcap, grad, m);
     const int n = (int)std::floor(avail / per);
     return std::max(1, std::min(n, kMaxBatch));
+}
+
+// Sources per group: the capacity estimate, except that a workspace already
+// holding within a quarter of that many sources at this size is reused as it is.
+// The estimate follows the free memory, which moves between calls, and growing
+// the workspace means reallocating many GB inside the call.
+int group_size(const tslov_ctx* c, int kcap, int grad, int m, int remaining) {
+    int cap = batch_capacity(c, kcap, grad, m);
+    const int ring = ring_steps(kcap, m);
+    const size_t per_slot = (size_t)(ring ? ring : kcap) * c->field_bytes();
+    const int held = c->basisV.p && per_slot ? (int)std::min<size_t>(c->basisV.n / per_slot, kMaxBatch) : 0;
+    if (held >= 1 && cap > held && 4 * (cap - held) <= held) cap = held;
+    return std::min(cap, remaining);
 }
 
 // ---------------------------------------------------------------- source lists
@@ -742,7 +762,7 @@ tslov_status backward(tslov_ctx* c, const SrcList& L, GradOut& out) {
     // force contraction split in chunks of j for parallelism; the split depends on
     // the lattice (and the segment) only, so a source's result does not depend on
     // the batch it shares a launch with
-    const int nchunk = std::max(1, std::min((1 << 18) / (4 * g.V), 64));
+    const int nchunk = force_chunks(g.V);
     CHK(ensure(c->gpart, (size_t)c->slots * nchunk * 36 * g.ldv * sizeof(ZD)));
     int nlt = 0;   // entries with k_used > j form a prefix
     PairTuner tune(c, 1, L.n);
@@ -972,7 +992,7 @@ tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
     size_t pos = 0;
     while (pos < order.size()) {
         const int kcap = q.k[order[pos]];
-        const int cap = std::min(batch_capacity(c, kcap, 1, q.recompute), (int)(order.size() - pos));
+        const int cap = group_size(c, kcap, 1, q.recompute, (int)(order.size() - pos));
         std::vector<int> src(order.begin() + pos, order.begin() + pos + cap), ks(cap);
         for (int e = 0; e < cap; ++e) ks[e] = q.k[src[e]];
         pos += cap;
