@@ -477,12 +477,157 @@ __global__ __launch_bounds__(kBlock) void k_apply_site(const Z<R>* __restrict__ 
         }
 }
 
+// Site per thread with a march along t: a thread owns one (x, y, z) site of a
+// 128-site tile and runs through a chunk of T consecutive t-slices.  The forward
+// t-hop's operands at slice t, psi(t+1) and U_t(t), are loaded once: psi(t+1) is
+// the own spinor of slice t+1, and U_t(t)^dag P- psi(t) (the backward t-hop of
+// slice t+1 before reconstruction) is carried in registers.  So along t every
+// spinor and link is read once per chunk instead of up to three times.  The hop
+// sum runs in the same order as k_apply_site (x, y, z, t; forward then backward),
+// with the same operations, so the two kernels give identical results.  Block
+// b works on tile (b mod 8) * per + (b / 8) mod per of chunk b / (8 per): each XCD
+// takes the same run of tiles (a slab of z-planes) in every chunk.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_apply_tmarch(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+                                                         Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em,
+                                                         int g5_in, int g5_out, int T) {
+    const int V3 = g.nx * g.ny * g.nz, per = V3 / kBlock / kXcd, m = blockIdx.x / kXcd;
+    const int tile = (blockIdx.x % kXcd) * per + m % per, chunk = m / per;
+    const int s3 = tile * kBlock + threadIdx.x;   // the (x, y, z) site; t = 0
+    const int t0 = chunk * T;
+    const Nbr n3 = neighbours(g, s3);
+    const R s_in_lo = R(1), s_in_hi = g5_in ? R(-1) : R(1), s_out_hi = g5_out ? R(-1) : R(1);
+    // the own spinor waits in a slot of LDS private to the thread (it is needed
+    // only after the x, y, z hops, whose operands take the registers)
+    __shared__ Z<R> stash[12][kBlock];
+    auto park = [&](const Spinor<R>& p) {
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) stash[sp * 3 + c][threadIdx.x] = p.c[sp][c];
+    };
+    {
+        Spinor<R> own0;
+        load_spinor(own0, in, g.ldv, s3 + t0 * V3);
+        park(own0);
+    }
+    // the carried backward t-hop from slice t0 - 1
+    Z<R> hb[2][3];
+    {
+        const int sp = s3 + ((t0 + g.nt - 1) % g.nt) * V3;
+        Z<R> u[3][3], h[2][3];
+        Spinor<R> p;
+        load_link(u, U, g.ldv, 3, sp);
+        load_spinor(p, in, g.ldv, sp);
+        if (g5_in) g5_inplace(p);
+        project<3, -1>(p, h);
+        adj_mat_vec(u, h, hb);
+    }
+#pragma unroll 1
+    for (int t = t0; t < t0 + T; ++t) {
+        const int s = s3 + t * V3;
+        Spinor<R> acc;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc.c[sp][c] = mk<R>(0, 0);
+#pragma unroll 1
+        for (int nu = 0; nu < 3; ++nu) {
+            Z<R> u[3][3];
+            Spinor<R> p;
+            switch (nu) {
+                case 0:
+                    load_link(u, U, g.ldv, 0, s); load_spinor(p, in, g.ldv, n3.fwd[0] + t * V3);
+                    if (g5_in) g5_inplace(p);
+                    hop_fwd<0>(acc, u, p, R(1));
+                    load_link(u, U, g.ldv, 0, n3.bwd[0] + t * V3); load_spinor(p, in, g.ldv, n3.bwd[0] + t * V3);
+                    if (g5_in) g5_inplace(p);
+                    hop_bwd<0>(acc, u, p, R(1));
+                    break;
+                case 1:
+                    load_link(u, U, g.ldv, 1, s); load_spinor(p, in, g.ldv, n3.fwd[1] + t * V3);
+                    if (g5_in) g5_inplace(p);
+                    hop_fwd<1>(acc, u, p, R(1));
+                    load_link(u, U, g.ldv, 1, n3.bwd[1] + t * V3); load_spinor(p, in, g.ldv, n3.bwd[1] + t * V3);
+                    if (g5_in) g5_inplace(p);
+                    hop_bwd<1>(acc, u, p, R(1));
+                    break;
+                default:
+                    load_link(u, U, g.ldv, 2, s); load_spinor(p, in, g.ldv, n3.fwd[2] + t * V3);
+                    if (g5_in) g5_inplace(p);
+                    hop_fwd<2>(acc, u, p, R(1));
+                    load_link(u, U, g.ldv, 2, n3.bwd[2] + t * V3); load_spinor(p, in, g.ldv, n3.bwd[2] + t * V3);
+                    if (g5_in) g5_inplace(p);
+                    hop_bwd<2>(acc, u, p, R(1));
+                    break;
+            }
+        }
+        // t: forward hop with psi(t+1), then the carried backward hop
+        Spinor<R> own;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) own.c[sp][c] = stash[sp * 3 + c][threadIdx.x];
+        Z<R> ut[3][3];
+        Spinor<R> nxt;
+        load_link(ut, U, g.ldv, 3, s);
+        load_spinor(nxt, in, g.ldv, s3 + ((t + 1) % g.nt) * V3);
+        {
+            Spinor<R> p = nxt;
+            if (g5_in) g5_inplace(p);
+            hop_fwd<3>(acc, ut, p, ep);
+        }
+        reconstruct_add<3, -1>(acc, hb, em);
+        // the next slice's backward t-hop: U_t(t)^dag P- psi(t)
+        {
+            Spinor<R> p = own;
+            if (g5_in) g5_inplace(p);
+            Z<R> h[2][3];
+            project<3, -1>(p, h);
+            adj_mat_vec(ut, h, hb);
+        }
+        mem_fence_compiler();
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            const R s_in = sp >= 2 ? s_in_hi : s_in_lo;
+            const R s_out = sp >= 2 ? s_out_hi : R(1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const Z<R> x = s_out * (s_in * own.c[sp][c] - kappa * acc.c[sp][c]);
+                R* q = reinterpret_cast<R*>(out + (size_t)(sp * 3 + c) * g.ldv + s);
+                __builtin_nontemporal_store(x.re, q);
+                __builtin_nontemporal_store(x.im, q + 1);
+            }
+        }
+        park(nxt);
+    }
+}
+
+// t-slices per chunk of the t-march: the largest divisor of nt that still gives
+// 512 workgroups, i.e. one wavefront on every SIMD (the kernel's 256 registers
+// allow one; measured at 32^4, 512 beat 256, 1024 and 2048); 0 when the tiles do
+// not split evenly over the XCDs.
+constexpr int kTmarchGroups = 512;
+inline int tmarch_chunk(const Geom& g) {
+    const int V3 = g.nx * g.ny * g.nz;
+    if (V3 % (kBlock * kXcd) != 0) return 0;
+    const int nb3 = V3 / kBlock;
+    int T = 0;
+    for (int c = 1; c <= g.nt; ++c)
+        if (g.nt % c == 0 && (long long)nb3 * (g.nt / c) >= kTmarchGroups) T = c;
+    return T > 0 ? T : 1;
+}
+
 template <typename R>
 void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu, int g5_in,
                   int g5_out, hipStream_t st, Timing t) {
     if (colour_grid(g.V)) {
         timed_launch(k_apply<R>, dim3(np_sten(g.V)), dim3(kSites), st, t, U, in, out, g, (R)kappa,
                      (R)std::exp(mu), (R)std::exp(-mu), g5_in, g5_out);
+    } else if (const int T = tmarch_chunk(g)) {
+        const int nb = g.nx * g.ny * g.nz / kBlock * (g.nt / T);
+        timed_launch(k_apply_tmarch<R>, dim3(nb), dim3(kBlock), st, t, U, in, out, g, (R)kappa, (R)std::exp(mu),
+                     (R)std::exp(-mu), g5_in, g5_out, T);
     } else {
         const int nb = (grid_for(g.V) + kXcd - 1) / kXcd * kXcd;
         const int slice = (g.nx * g.ny * g.nz) % (kBlock * kXcd) == 0;   // t-slices split evenly over XCDs

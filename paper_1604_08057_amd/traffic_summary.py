@@ -84,12 +84,12 @@ def main(fetch_csv: str, write_csv: str, out: str, volume: int = 4096):
         n, f, w = per(name, grid)
         res[name] = (f * ff + w * fw) * 1024
         lines.append(f"{name:31s} {grid:>7s} {n:10d} {f:10.1f} {w:10.1f} {res[name]:18.0f} {alg:12d}")
-    # the 32^4 operator of the stencil benchmark (site per thread, XCD-padded grid)
+    # the 32^4 operator of the stencil benchmark (t-march: 256 tiles x 2 chunks of 16 slices)
     V4 = 32 ** 4
-    g4 = str((V4 // 128 + 7) // 8 * 8 * 128)
+    g4 = str(32 ** 3 // 128 * 2 * 128)
     try:
-        n, f, w = per("k_apply_site<double>", g4)
-        lines.append(f"{'k_apply_site<double> (32^4)':31s} {g4:>7s} {n:10d} {f:10.1f} {w:10.1f} "
+        n, f, w = per("k_apply_tmarch<double>", g4)
+        lines.append(f"{'k_apply_tmarch<double> (32^4)':31s} {g4:>7s} {n:10d} {f:10.1f} {w:10.1f} "
                      f"{(f * ff + w * fw) * 1024:18.0f} {V4 * 60 * 16:12d}")
     except statistics.StatisticsError:
         pass

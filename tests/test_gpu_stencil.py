@@ -2,9 +2,10 @@
 
 Lattices: 4^4, a ragged 3x5x7x6 (V = 630, not a multiple of the block size)
 and 8^4 (colour-grid layout); 10^4 and a ragged 9x11x13x7 (V = 9009) above it
-(site-per-thread operator, colour-split Lanczos kernels, XCD-padded grids); and
-the 32^4 lattice of the stencil benchmark with its own link and source
-generator.  FP64 is compared element by element to 1e-14 relative (max norm);
+(site-per-thread operator, colour-split Lanczos kernels, XCD-padded grids);
+16^3x32 and 32^3x8 (the t-march operator, chunks of 2 and 4 slices with the
+wrap in t); and the 32^4 lattice of the stencil benchmark (t-march, chunks of
+16) with its own link and source generator.  FP64 is compared element by element to 1e-14 relative (max norm);
 the float32 path to 2e-6.
 """
 import numpy as np
@@ -19,7 +20,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-14), ("mixed", 2e-6)])
-@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 7, 6), (8, 8, 8, 8), (10, 10, 10, 10), (9, 11, 13, 7)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 7, 6), (8, 8, 8, 8), (10, 10, 10, 10), (9, 11, 13, 7),
+                                  (16, 16, 16, 32)])
 @pytest.mark.parametrize("mu", [0.0, 0.3])
 def test_operators_match_oracle(dims, mu, precision, tol):
     from paper_1604_08057_amd import Context
@@ -80,3 +82,25 @@ def test_benchmark_lattice_32():
     err = rel_max(got, want)
     say(f"  h: rel max err {err:.2e}")
     assert err < 1e-14
+
+
+def test_tmarch_lattice_32x8():
+    from paper_1604_08057_amd import Context
+    dims = (32, 32, 32, 8)
+    rng = np.random.default_rng(328)
+    V = int(np.prod(dims))
+    U = random_links(dims, 0.5, rng)
+    x = rng.standard_normal((V, 4, 3)) + 1j * rng.standard_normal((V, 4, 3))
+    op = WilsonOperator(dims, -2.0, 0.3)
+    Ut, xt = torch.from_numpy(U), torch.from_numpy(x)
+    say("stencil 32^3x8 (t-march, chunks of 4 slices)")
+    ctx = Context(dims, -2.0, 0.3)
+    ctx.set_links(dev(U))
+    xd = dev(x)
+    cases = [("dw", ctx.apply_dw(xd), op.dw(Ut, xt)), ("h_dag", ctx.apply_h(xd, dagger=True), op.h_dag(Ut, xt))]
+    torch.cuda.synchronize()
+    ctx.close()
+    for name, got, want in cases:
+        err = rel_max(host(got), want.numpy())
+        say(f"  {name}: rel max err {err:.2e}")
+        assert err < 1e-14, name
