@@ -477,6 +477,26 @@ __global__ __launch_bounds__(kBlock) void k_apply_site(const Z<R>* __restrict__ 
         }
 }
 
+// Both hops of direction NU for a whole site, with the four operands' loads
+// issued before any arithmetic (one memory round trip per direction).
+template <int NU, typename R>
+__device__ __forceinline__ void tm_hops_eager(Spinor<R>& acc, const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+                                              const Geom& g, int s, int sf, int sb, int g5_in) {
+    Z<R> uf[3][3], ub[3][3];
+    Spinor<R> pf, pb;
+    load_link(uf, U, g.ldv, NU, s);
+    load_spinor(pf, in, g.ldv, sf);
+    load_link(ub, U, g.ldv, NU, sb);
+    load_spinor(pb, in, g.ldv, sb);
+    mem_fence_compiler();
+    if (g5_in) {
+        g5_inplace(pf);
+        g5_inplace(pb);
+    }
+    hop_fwd<NU>(acc, uf, pf, R(1));
+    hop_bwd<NU>(acc, ub, pb, R(1));
+}
+
 // Site per thread with a march along t: a thread owns one (x, y, z) site of a
 // 128-site tile and runs through a chunk of T consecutive t-slices.  The forward
 // t-hop's operands at slice t, psi(t+1) and U_t(t), are loaded once: psi(t+1) is
@@ -500,6 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_tmarch(const Z<R>* __restrict_
     // the own spinor waits in a slot of LDS private to the thread (it is needed
     // only after the x, y, z hops, whose operands take the registers)
     __shared__ Z<R> stash[12][kBlock];
+    __shared__ Z<R> hstash[6][kBlock];
     auto park = [&](const Spinor<R>& p) {
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
@@ -511,9 +532,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_tmarch(const Z<R>* __restrict_
         load_spinor(own0, in, g.ldv, s3 + t0 * V3);
         park(own0);
     }
-    // the carried backward t-hop from slice t0 - 1
-    Z<R> hb[2][3];
+    // the carried backward t-hop from slice t0 - 1 (also parked in LDS)
+    auto park_h = [&](const Z<R> (&h)[2][3]) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) hstash[q * 3 + c][threadIdx.x] = h[q][c];
+    };
     {
+        Z<R> hb[2][3];
         const int sp = s3 + ((t0 + g.nt - 1) % g.nt) * V3;
         Z<R> u[3][3], h[2][3];
         Spinor<R> p;
@@ -522,6 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_tmarch(const Z<R>* __restrict_
         if (g5_in) g5_inplace(p);
         project<3, -1>(p, h);
         adj_mat_vec(u, h, hb);
+        park_h(hb);
     }
 #pragma unroll 1
     for (int t = t0; t < t0 + T; ++t) {
@@ -533,33 +561,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_tmarch(const Z<R>* __restrict_
             for (int c = 0; c < 3; ++c) acc.c[sp][c] = mk<R>(0, 0);
 #pragma unroll 1
         for (int nu = 0; nu < 3; ++nu) {
-            Z<R> u[3][3];
-            Spinor<R> p;
             switch (nu) {
-                case 0:
-                    load_link(u, U, g.ldv, 0, s); load_spinor(p, in, g.ldv, n3.fwd[0] + t * V3);
-                    if (g5_in) g5_inplace(p);
-                    hop_fwd<0>(acc, u, p, R(1));
-                    load_link(u, U, g.ldv, 0, n3.bwd[0] + t * V3); load_spinor(p, in, g.ldv, n3.bwd[0] + t * V3);
-                    if (g5_in) g5_inplace(p);
-                    hop_bwd<0>(acc, u, p, R(1));
-                    break;
-                case 1:
-                    load_link(u, U, g.ldv, 1, s); load_spinor(p, in, g.ldv, n3.fwd[1] + t * V3);
-                    if (g5_in) g5_inplace(p);
-                    hop_fwd<1>(acc, u, p, R(1));
-                    load_link(u, U, g.ldv, 1, n3.bwd[1] + t * V3); load_spinor(p, in, g.ldv, n3.bwd[1] + t * V3);
-                    if (g5_in) g5_inplace(p);
-                    hop_bwd<1>(acc, u, p, R(1));
-                    break;
-                default:
-                    load_link(u, U, g.ldv, 2, s); load_spinor(p, in, g.ldv, n3.fwd[2] + t * V3);
-                    if (g5_in) g5_inplace(p);
-                    hop_fwd<2>(acc, u, p, R(1));
-                    load_link(u, U, g.ldv, 2, n3.bwd[2] + t * V3); load_spinor(p, in, g.ldv, n3.bwd[2] + t * V3);
-                    if (g5_in) g5_inplace(p);
-                    hop_bwd<2>(acc, u, p, R(1));
-                    break;
+                case 0: tm_hops_eager<0>(acc, U, in, g, s, n3.fwd[0] + t * V3, n3.bwd[0] + t * V3, g5_in); break;
+                case 1: tm_hops_eager<1>(acc, U, in, g, s, n3.fwd[1] + t * V3, n3.bwd[1] + t * V3, g5_in); break;
+                default: tm_hops_eager<2>(acc, U, in, g, s, n3.fwd[2] + t * V3, n3.bwd[2] + t * V3, g5_in); break;
             }
         }
         // t: forward hop with psi(t+1), then the carried backward hop
@@ -577,14 +582,22 @@ __global__ __launch_bounds__(kBlock) void k_apply_tmarch(const Z<R>* __restrict_
             if (g5_in) g5_inplace(p);
             hop_fwd<3>(acc, ut, p, ep);
         }
-        reconstruct_add<3, -1>(acc, hb, em);
+        {
+            Z<R> hb[2][3];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) hb[q][c] = hstash[q * 3 + c][threadIdx.x];
+            reconstruct_add<3, -1>(acc, hb, em);
+        }
         // the next slice's backward t-hop: U_t(t)^dag P- psi(t)
         {
             Spinor<R> p = own;
             if (g5_in) g5_inplace(p);
-            Z<R> h[2][3];
+            Z<R> h[2][3], hb[2][3];
             project<3, -1>(p, h);
             adj_mat_vec(ut, h, hb);
+            park_h(hb);
         }
         mem_fence_compiler();
 #pragma unroll
