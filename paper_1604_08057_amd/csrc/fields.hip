@@ -943,8 +943,11 @@ __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L
     const int s = blockIdx.x * kPBlock + threadIdx.x;
     const size_t i = (size_t)blockIdx.y * g.ldv + s;
     const bool has_prev = j > 1, live = s < g.V && j < L.k[e];
-    // the site's operands and the partial sums first: their loads share one round
-    // trip with the flag read (whose barrier the compiler may not move them across)
+    // the site's operands, the step's scalars and the partial sums first: their
+    // loads share one round trip with the flag read (whose barrier the compiler may
+    // not move them across)
+    const Z<R> gj = has_prev ? zcast<R>(coef.gamma[j]) : mk<R>(0, 0);
+    const R bj = has_prev ? (R)coef.beta[j] : R(0);
     Z<R> a_i = mk<R>(0, 0), b_i = a_i, v_i = a_i, w_i = a_i, vp_i = a_i, wp_i = a_i;
     if (live) {
         a_i = wk.a(slot, j)[i];
@@ -973,8 +976,6 @@ __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L
     }
     if (j >= L.k[e]) return;
     const Z<R> al = zcast<R>(alpha), alc = zcast<R>(cj(alpha));
-    const Z<R> gj = has_prev ? zcast<R>(coef.gamma[j]) : mk<R>(0, 0);
-    const R bj = has_prev ? (R)coef.beta[j] : R(0);
     double pv[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
     if (live) {
         Z<R> r, q;
@@ -1068,15 +1069,17 @@ __global__ __launch_bounds__(kPBlock) void k_bwd_ra(Geom g, Work<R> wk, SrcList 
             wp_i = wk.w(slot, j - 1)[i];
         }
     }
+    const double beta = coef.beta[j + 1];
+    const ZD gam = coef.gamma[j + 1];
+    const double bbar_n = coef.bbar_tot[j + 1];
+    const ZD gbar_n = coef.gbar_tot[j + 1];
     double red[kNvRB];
     reduce_partials<kNvRB, kPBlock>(wk.p(slot, 0), npart_in, red);   // its loads join the operands'
     const double D1 = red[0];
     const ZD D2 = mk<double>(red[1], red[2]);
-    const double beta = coef.beta[j + 1];
-    const ZD gam = coef.gamma[j + 1];
     const ZD om = beta * gam;
-    const double bbarR = coef.bbar_tot[j + 1] - D1 / beta;
-    const ZD gbar = coef.gbar_tot[j + 1] - zdiv(D2, cj(gam));
+    const double bbarR = bbar_n - D1 / beta;
+    const ZD gbar = gbar_n - zdiv(D2, cj(gam));
     const ZD cgo = cjmul(gbar, om);   // conj(gbar) * omega
     const double K = (bbarR - cgo.re / (beta * beta)) / (2.0 * beta * beta * beta);
     const ZD ombar = (1.0 / beta) * gbar + K * om;
@@ -1120,6 +1123,24 @@ void launch_bwd_ra(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef
 // partials of Re vbar_j^H v_j and wbar_j^H w_j.  The last step (j = k_used) has
 // no residual adjoints: abar = alphabar w, vbar = |x| conj(c) eta + alphabar b,
 // wbar = conj(alphabar) a.
+// The recorded scalars of reverse step j, read at the top of the kernel so that
+// their loads share a round trip with the hops' instead of following the block sum.
+struct BwdCoefs {
+    ZD abar_T, gbar_T, alpha, etac, gnc;
+    double bbar_T, bn;
+};
+__device__ __forceinline__ BwdCoefs bwd_coefs(const Coef& coef, int j, bool carry) {
+    BwdCoefs c;
+    c.abar_T = coef.abar_T[j];
+    c.gbar_T = coef.gbar_T[j];
+    c.bbar_T = coef.bbar_T[j];
+    c.alpha = coef.alpha[j];
+    c.etac = coef.misc[0] * cj(coef.c[j]);
+    c.gnc = carry ? cj(coef.gamma[j + 1]) : mk<double>(0, 0);
+    c.bn = carry ? coef.beta[j + 1] : 0.0;
+    return c;
+}
+
 // Epilogue of reverse step j for one entry, after the hops: the coefficient
 // adjoints from the block-summed partials `red` (not LAST), the adjoint fields'
 // stores and the step's partial sums.
@@ -1127,26 +1148,26 @@ template <typename R, bool LAST, int BLK>
 __device__ __forceinline__ void bwd_rb_finish(const Geom& g, double kappa, const Work<R>& wk, const Coef& coef,
                                               int slot, int j, int k_used, int pslot, int a, int s,
                                               const double (&red)[kNvRA], const Z<R> (&accs)[4],
-                                              const Z<R> (&accr)[4]) {
+                                              const Z<R> (&accr)[4], const BwdCoefs& cf) {
     const Z<R>* __restrict__ rbar_j = wk.f(slot, 6 + (j & 1));
     const Z<R>* __restrict__ rbar_n = wk.f(slot, 6 + ((j + 1) & 1));
     const Z<R>* __restrict__ sbar_j = wk.sb(slot, j);
     const bool carry = j + 1 < k_used;
     const Z<R>* __restrict__ sbar_n = carry ? wk.sb(slot, j + 1) : sbar_j;
-    ZD abar = coef.abar_T[j];
+    ZD abar = cf.abar_T;
     if (!LAST) {
         abar = abar - mk<double>(red[0], red[1]) - mk<double>(red[2], red[3]);
         if (blockIdx.x == 0 && threadIdx.x == 0 && j >= 2) {
-            coef.gbar_tot[j] = coef.gbar_T[j] - mk<double>(red[4], red[5]);
-            coef.bbar_tot[j] = coef.bbar_T[j] - red[6];
+            coef.gbar_tot[j] = cf.gbar_T - mk<double>(red[4], red[5]);
+            coef.bbar_tot[j] = cf.bbar_T - red[6];
         }
     }
     const Z<R> ca = zcast<R>(abar);
-    const ZD alpha = coef.alpha[j];
+    const ZD alpha = cf.alpha;
     const Z<R> alr = zcast<R>(alpha), alc = zcast<R>(cj(alpha)), abc = zcast<R>(cj(abar));
-    const Z<R> etac = zcast<R>(coef.misc[0] * cj(coef.c[j]));
-    const Z<R> gnc = carry ? zcast<R>(cj(coef.gamma[j + 1])) : mk<R>(0, 0);
-    const R bn = carry ? (R)coef.beta[j + 1] : R(0);
+    const Z<R> etac = zcast<R>(cf.etac);
+    const Z<R> gnc = zcast<R>(cf.gnc);
+    const R bn = (R)cf.bn;
     double pv[kNvRB] = {0.0, 0.0, 0.0};
     if (s < g.V) {
         const R kap = (R)kappa;
@@ -1214,6 +1235,7 @@ __global__ __launch_bounds__(BLK) void k_bwd_rb(const Z<R>* __restrict__ U, Geom
     if (sb < 0) return;   // padding workgroup (uniform over the block)
     const int a = sten_colour<BLK>();
     const int s = sb * kSites + threadIdx.x % kSites;
+    const BwdCoefs cf = bwd_coefs(coef, j, j + 1 < L.k[e]);
     // the partial sums' loads go out with the hops' loads; only the epilogue needs
     // the sums, so they are combined after the hops
     double red[kNvRA];
@@ -1230,7 +1252,7 @@ __global__ __launch_bounds__(BLK) void k_bwd_rb(const Z<R>* __restrict__ U, Geom
         block_sum<kNvRA, BLK>(red);
     }
     bwd_rb_finish<R, LAST, BLK>(g, kappa, wk, coef, slot, j, L.k[e], BLK == kSites ? (int)blockIdx.x : sb, a, s,
-                                red, accs, accr);
+                                red, accs, accr, cf);
 }
 
 // Colour split, not the last step: NS entries per workgroup sharing the link loads.
@@ -1246,12 +1268,15 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb_ms(const Z<R>* __restrict__ 
     const Z<R>* fs[NS];
     const Z<R>* fr[NS];
     double red[NS][kNvRA];
+    BwdCoefs cf[NS];
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
+        const int e = min(e0 + q, L.n - 1);
         if (e0 + q < L.n) live |= 1u << q;
-        slot[q] = L.slot[min(e0 + q, L.n - 1)];
+        slot[q] = L.slot[e];
         fs[q] = wk.sb(slot[q], j);
         fr[q] = wk.f(slot[q], 6 + (j & 1));
+        cf[q] = bwd_coefs(coef0.at(slot[q]), j, j + 1 < L.k[e]);
         gather_partials<kNvRA, kCBlock>(wk.p(slot[q], 1), npart_in, red[q]);
     }
     const int a = sten_colour<kCBlock>();
@@ -1271,7 +1296,7 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb_ms(const Z<R>* __restrict__ 
         if (live & (1u << q)) {
             block_sum<kNvRA, kCBlock>(red[q]);
             bwd_rb_finish<R, false, kCBlock>(g, kappa, wk, coef0.at(slot[q]), slot[q], j, L.k[e0 + q], sb, a, s,
-                                             red[q], accs[q], accr[q]);
+                                             red[q], accs[q], accr[q], cf[q]);
         }
     }
 }

@@ -49,7 +49,15 @@ struct Work {
     int pstride;
     int ring;      // 0: step j at index j - 1; 1: at (j - 1) mod kcap (vectors regenerated in segments)
     __host__ __device__ size_t step(int slot, int j) const {
-        const int i = ring ? (j - 1) % kcap : j - 1;
+        int i = j - 1;
+        if (ring) {
+            i %= kcap;
+#if defined(__HIP_DEVICE_COMPILE__)
+            // the index is uniform; the division runs on the vector unit, and without
+            // this every address derived from it would leave the scalar registers
+            i = __builtin_amdgcn_readfirstlane(i);
+#endif
+        }
         return ((size_t)slot * kcap + i) * fe;
     }
     __host__ __device__ Z<R>* v(int slot, int j) const { return V + step(slot, j); }
