@@ -229,6 +229,18 @@ tslov_status tslov_timing_read(tslov_ctx* ctx, int which, int* count, double* to
  * must not be captured by the caller.  on = 0 (the default) frees the graphs. */
 tslov_status tslov_set_graphs(tslov_ctx* ctx, int on);
 
+/* Launch shape of the operator (tslov_apply_dw / tslov_apply_h) on lattices whose
+ * t-slices split into whole tiles of 128 sites over the 8 XCDs (e.g. 32^4): each
+ * thread marches through T consecutive t-slices.  T = 0 (the default) lets the
+ * first call time the candidates (divisors of N_t giving 128 to 4096 workgroups,
+ * best of three launches each) and keep the fastest for the context; T > 0
+ * forces that chunk length.  Results do not depend on T.  ERR_ARG unless T = 0
+ * or T divides N_t (the value is ignored where the operator does not march).
+ * tslov_get_apply_chunk returns the timed pick (0 while none is made or where
+ * the operator does not march). */
+tslov_status tslov_set_apply_chunk(tslov_ctx* ctx, int T);
+tslov_status tslov_get_apply_chunk(const tslov_ctx* ctx, int* T);
+
 /* Launch shape of the batched stencil pair kernels on lattices of more than 128
  * blocks of 64 sites (the colour-split layout): ns entries of a batch per
  * workgroup, which share every link load.  ns = 0 (the default) lets the library

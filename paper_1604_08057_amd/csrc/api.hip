@@ -168,6 +168,9 @@ struct tslov_ctx {
     int pair_ns[2] = {0, 0};
     int pair_ns_n[2] = {0, 0};
     int pair_ns_forced = 0;
+    // t-slices per chunk of the t-march operator: the timed pick (0: none yet,
+    // -1: the operator does not march on this lattice) and a forced value
+    int tm_T = 0, tm_T_forced = 0;
 
     int nblk() const { return tslov::grid_for(g.V); }
     size_t field_elems() const { return (size_t)12 * g.ldv; }
@@ -1183,6 +1186,61 @@ tslov_status deflated_grad(tslov_ctx* c, const ZD* eta, const ZD* psi, int k, co
 }  // namespace
 
 // ===================================================================== C ABI
+namespace {
+
+// Chunk length of the t-march operator, picked on the first call by timing each
+// candidate (best of three launches) on the call's own internal buffers: every
+// candidate gives the same result, so the pick changes the time only.
+template <typename R>
+tslov_status pick_apply_chunk(tslov_ctx* c, const Z<R>* U, const Z<R>* a, Z<R>* b, double mu, int g5in, int g5out) {
+    if (c->tm_T != 0) return TSLOV_OK;
+    int cand[16];
+    const int n = tslov::tmarch_chunks(c->g, cand, 16);
+    if (n <= 1) {
+        c->tm_T = n == 1 ? cand[0] : -1;
+        return TSLOV_OK;
+    }
+    constexpr int kReps = 3;
+    std::vector<hipEvent_t> ev((size_t)2 * n * kReps, nullptr);
+    auto release_events = [&]() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            e = nullptr;
+            release_events();
+            return TSLOV_OK;   // no timing: the built-in choice stays
+        }
+    for (int r = 0; r < kReps; ++r)
+        for (int i = 0; i < n; ++i) {
+            const size_t x = (size_t)2 * (r * n + i);
+            (void)hipEventRecord(ev[x], c->st);
+            tslov::launch_apply<R>(U, a, b, c->g, c->kappa, mu, g5in, g5out, c->st, tslov::Timing{}, cand[i]);
+            (void)hipEventRecord(ev[x + 1], c->st);
+        }
+    const hipError_t es = hipEventSynchronize(ev.back());
+    if (es == hipSuccess) {
+        std::vector<float> best((size_t)n, 1e30f);
+        for (int r = 0; r < kReps; ++r)
+            for (int i = 0; i < n; ++i) {
+                float ms = 0.0f;
+                const size_t x = (size_t)2 * (r * n + i);
+                if (hipEventElapsedTime(&ms, ev[x], ev[x + 1]) == hipSuccess) best[i] = std::min(best[i], ms);
+            }
+        int p = 0;
+        for (int i = 1; i < n; ++i)
+            if (best[i] < best[p]) p = i;
+        c->tm_T = cand[p];
+    }
+    release_events();
+    HIPCHK(es);
+    return TSLOV_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* tslov_last_error(void) { return g_err.c_str(); }
@@ -1272,15 +1330,17 @@ static tslov_status apply_op(tslov_ctx* c, const void* in, void* out, double mu,
         Z<float>* a = c->opf.as<Z<float>>();
         Z<float>* b = a + c->field_elems();
         tslov::launch_spinor_to_soa<float>((const ZD*)in, a, c->g, nullptr, c->st);
+        if (!c->tm_T_forced) CHK(pick_apply_chunk<float>(c, c->U32.as<Z<float>>(), a, b, mu, g5in, g5out));
         tslov::launch_apply<float>(c->U32.as<Z<float>>(), a, b, c->g, c->kappa, mu, g5in, g5out, c->st,
-                                   TimedLaunch(c, 2).t);
+                                   TimedLaunch(c, 2).t, c->tm_T_forced ? c->tm_T_forced : std::max(c->tm_T, 0));
         tslov::launch_spinor_from_soa<float>(b, (ZD*)out, c->g, c->st);
     } else {
         ZD* a = c->opf.as<ZD>();
         ZD* b = a + c->field_elems();
         tslov::launch_spinor_to_soa<double>((const ZD*)in, a, c->g, nullptr, c->st);
+        if (!c->tm_T_forced) CHK(pick_apply_chunk<double>(c, c->U64.as<ZD>(), a, b, mu, g5in, g5out));
         tslov::launch_apply<double>(c->U64.as<ZD>(), a, b, c->g, c->kappa, mu, g5in, g5out, c->st,
-                                    TimedLaunch(c, 2).t);
+                                    TimedLaunch(c, 2).t, c->tm_T_forced ? c->tm_T_forced : std::max(c->tm_T, 0));
         tslov::launch_spinor_from_soa<double>(b, (ZD*)out, c->g, c->st);
     }
     HIPCHK(hipGetLastError());
@@ -1500,6 +1560,19 @@ tslov_status tslov_set_graphs(tslov_ctx* c, int on) {
         c->gfwd.reset();
         c->gbwd.reset();
     }
+    return TSLOV_OK;
+}
+
+tslov_status tslov_set_apply_chunk(tslov_ctx* c, int T) {
+    if (!c) return fail(TSLOV_ERR_ARG, "null context");
+    if (T < 0 || (T > 0 && c->g.nt % T != 0)) return fail(TSLOV_ERR_ARG, "T must be 0 or divide the time extent");
+    c->tm_T_forced = T;
+    return TSLOV_OK;
+}
+
+tslov_status tslov_get_apply_chunk(const tslov_ctx* c, int* T) {
+    if (!c || !T) return fail(TSLOV_ERR_ARG, "null argument");
+    *T = c->tm_T > 0 ? c->tm_T : 0;
     return TSLOV_OK;
 }
 

@@ -631,13 +631,22 @@ inline int tmarch_chunk(const Geom& g) {
     return T > 0 ? T : 1;
 }
 
+int tmarch_chunks(const Geom& g, int* T, int maxn) {
+    if (colour_grid(g.V) || tmarch_chunk(g) == 0) return 0;
+    const long long nb3 = g.nx * g.ny * g.nz / kBlock;
+    int n = 0;
+    for (int c = 1; c <= g.nt && n < maxn; ++c)
+        if (g.nt % c == 0 && nb3 * (g.nt / c) >= 128 && nb3 * (g.nt / c) <= 4096) T[n++] = c;
+    return n;
+}
+
 template <typename R>
 void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu, int g5_in,
-                  int g5_out, hipStream_t st, Timing t) {
+                  int g5_out, hipStream_t st, Timing t, int tm_T) {
     if (colour_grid(g.V)) {
         timed_launch(k_apply<R>, dim3(np_sten(g.V)), dim3(kSites), st, t, U, in, out, g, (R)kappa,
                      (R)std::exp(mu), (R)std::exp(-mu), g5_in, g5_out);
-    } else if (const int T = tmarch_chunk(g)) {
+    } else if (const int T = tmarch_chunk(g) ? (tm_T > 0 && g.nt % tm_T == 0 ? tm_T : tmarch_chunk(g)) : 0) {
         const int nb = g.nx * g.ny * g.nz / kBlock * (g.nt / T);
         timed_launch(k_apply_tmarch<R>, dim3(nb), dim3(kBlock), st, t, U, in, out, g, (R)kappa, (R)std::exp(mu),
                      (R)std::exp(-mu), g5_in, g5_out, T);
@@ -1618,7 +1627,7 @@ void launch_source_grad(const Geom& g, const Work<R>& wk, const SrcList& L, Coef
     template void launch_spinor_to_soa<R>(const ZD*, Z<R>*, const Geom&, double*, hipStream_t);                 \
     template void launch_spinor_from_soa<R>(const Z<R>*, ZD*, const Geom&, hipStream_t);                        \
     template void launch_apply<R>(const Z<R>*, const Z<R>*, Z<R>*, const Geom&, double, double, int, int,       \
-                                  hipStream_t, Timing);                                                         \
+                                  hipStream_t, Timing, int);                                                    \
     template void launch_sources_to_soa<R>(const ZD*, int, int, const Work<R>&, const SrcList&, const Geom&,    \
                                            hipStream_t);                                                        \
     template void launch_fwd_pair<R>(const Z<R>*, const Geom&, double, double, const Work<R>&, const SrcList&,  \

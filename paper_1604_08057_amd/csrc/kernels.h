@@ -26,7 +26,11 @@ void launch_spinor_from_soa(const Z<R>* in, ZD* out, const Geom& g, hipStream_t 
 // out = G5out * (G5in in - kappa * hop_{mu}(G5in in))
 template <typename R>
 void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu,
-                  int g5_in, int g5_out, hipStream_t st, Timing t = {});
+                  int g5_in, int g5_out, hipStream_t st, Timing t = {}, int tm_T = 0);
+// The t-slices per chunk the t-march operator can run this lattice with (each
+// gives the same result), at most maxn of them into T; 0 when it does not apply.
+// launch_apply's tm_T picks one (0: the built-in choice).
+int tmarch_chunks(const Geom& g, int* T, int maxn);
 
 // ---------------------------------------------------------------- batch workspace
 // Per-source lattice fields of a batch in the working precision.  Sources sit in

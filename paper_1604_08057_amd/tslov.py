@@ -31,7 +31,8 @@ KERNEL_FWD_PAIR, KERNEL_BWD_PAIR, KERNEL_APPLY = 0, 1, 2
 EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links", "tslov_apply_dw",
            "tslov_apply_h", "tslov_sign", "tslov_overlap", "tslov_sign_grad", "tslov_sign_grad_batched",
            "tslov_current_estimate", "tslov_error_estimate", "tslov_lanczos_matrix", "tslov_dense_sign", "tslov_timing_enable",
-           "tslov_timing_read", "tslov_kernel_bytes", "tslov_set_pair_ns", "tslov_get_pair_ns", "tslov_set_graphs"]
+           "tslov_timing_read", "tslov_kernel_bytes", "tslov_set_pair_ns", "tslov_get_pair_ns", "tslov_set_graphs", "tslov_set_apply_chunk",
+           "tslov_get_apply_chunk"]
 
 
 class TslovLibraryMissing(ImportError):
@@ -110,6 +111,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_kernel_bytes": ([vp, ci], cd),
         "tslov_set_pair_ns": ([vp, ci], ci),
         "tslov_set_graphs": ([vp, ci], ci),
+        "tslov_set_apply_chunk": ([vp, ci], ci),
+        "tslov_get_apply_chunk": ([vp, ctypes.POINTER(ci)], ci),
         "tslov_get_pair_ns": ([vp, ctypes.POINTER(ci), ctypes.POINTER(ci)], ci),
     }
     for name, (args, res) in sig.items():
@@ -309,6 +312,16 @@ class Context:
     def set_graphs(self, on: bool = True):
         """Capture the Lanczos loops as HIP graphs and replay them (needs a non-null stream)."""
         _check(self.lib, self.lib.tslov_set_graphs(self.handle, int(bool(on))))
+
+    def set_apply_chunk(self, T: int = 0):
+        """t-slices per chunk of the marching operator (0: timed pick on the first call)."""
+        _check(self.lib, self.lib.tslov_set_apply_chunk(self.handle, int(T)))
+
+    def apply_chunk(self) -> int:
+        """The timed chunk length of the marching operator (0: none yet, or not marching)."""
+        t = ctypes.c_int()
+        _check(self.lib, self.lib.tslov_get_apply_chunk(self.handle, ctypes.byref(t)))
+        return t.value
 
     def set_pair_ns(self, ns: int = 0):
         """Entries per workgroup of the batched colour-split pair kernels (0: timed pick)."""

@@ -3,9 +3,10 @@
 Lattices: 4^4, a ragged 3x5x7x6 (V = 630, not a multiple of the block size)
 and 8^4 (colour-grid layout); 10^4 and a ragged 9x11x13x7 (V = 9009) above it
 (site-per-thread operator, colour-split Lanczos kernels, XCD-padded grids);
-16^3x32 and 32^3x8 (the t-march operator, chunks of 2 and 4 slices with the
-wrap in t); and the 32^4 lattice of the stencil benchmark (t-march, chunks of
-16) with its own link and source generator.  FP64 is compared element by element to 1e-14 relative (max norm);
+16^3x32 and 32^3x8 (the t-march operator with the wrap in t, its chunk length
+timed on the first call), where every forced chunk length (1, 2, 4, 8 slices)
+gives the same bits; and the 32^4 lattice of the stencil benchmark (t-march)
+with its own link and source generator.  FP64 is compared element by element to 1e-14 relative (max norm);
 the float32 path to 2e-6.
 """
 import numpy as np
@@ -104,3 +105,35 @@ def test_tmarch_lattice_32x8():
         err = rel_max(host(got), want.numpy())
         say(f"  {name}: rel max err {err:.2e}")
         assert err < 1e-14, name
+
+
+def test_tmarch_chunk_lengths_identical():
+    # every chunk length of the marching operator gives the same bits (the first
+    # slice of a chunk forms its backward t-hop with the same arithmetic as the
+    # carried one), and the timed pick is one of them
+    from paper_1604_08057_amd import Context
+    from paper_1604_08057_amd.tslov import TslovError
+    dims = (32, 32, 32, 8)
+    rng = np.random.default_rng(329)
+    V = int(np.prod(dims))
+    U, x = dev(random_links(dims, 0.5, rng)), dev(rng.standard_normal((V, 4, 3)) + 1j * rng.standard_normal((V, 4, 3)))
+    ctx = Context(dims, -2.0, 0.3)
+    ctx.set_links(U)
+    outs = {}
+    for T in (1, 2, 4, 8):
+        say(f"stencil 32^3x8, chunk of {T} slices")
+        ctx.set_apply_chunk(T)
+        outs[T] = ctx.apply_h(x)
+    with pytest.raises(TslovError):
+        ctx.set_apply_chunk(3)
+    ctx.close()
+    ctx = Context(dims, -2.0, 0.3)
+    ctx.set_links(U)
+    timed = ctx.apply_h(x)
+    pick = ctx.apply_chunk()
+    ctx.close()
+    say(f"  timed pick: {pick} slices per chunk")
+    assert pick in (1, 2, 4, 8)
+    for T in (2, 4, 8):
+        assert torch.equal(outs[T], outs[1]), T
+    assert torch.equal(timed, outs[1])
