@@ -261,19 +261,51 @@ __device__ __forceinline__ void hop_all_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], c
     }
 }
 
+// Two directions at once for two fields sharing the link rows: all sixteen
+// operands (four link rows, eight neighbour spinors) issued before any arithmetic,
+// one memory round trip for both directions.  Needs more than 256 registers: for
+// kernels whose grid leaves one wavefront per SIMD anyway (the colour grid).
+template <int NU0, int NU1, typename R>
+__device__ __forceinline__ void hop_two_dirs_pair_eager(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
+                                                        const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
+                                                        const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
+    const R up0 = (NU0 == 3) ? ep : R(1), dn0 = (NU0 == 3) ? em : R(1);
+    const R up1 = (NU1 == 3) ? ep : R(1), dn1 = (NU1 == 3) ? em : R(1);
+    Z<R> uf0[3], ub0[3], uf1[3], ub1[3];
+    Spinor<R> paf0, pbf0, pab0, pbb0, paf1, pbf1, pab1, pbb1;
+    load_row(uf0, U, g.ldv, NU0, a, s);
+    load_spinor(paf0, fa, g.ldv, n.fwd[NU0]);
+    load_spinor(pbf0, fb, g.ldv, n.fwd[NU0]);
+    load_col_conj(ub0, U, g.ldv, NU0, a, n.bwd[NU0]);
+    load_spinor(pab0, fa, g.ldv, n.bwd[NU0]);
+    load_spinor(pbb0, fb, g.ldv, n.bwd[NU0]);
+    load_row(uf1, U, g.ldv, NU1, a, s);
+    load_spinor(paf1, fa, g.ldv, n.fwd[NU1]);
+    load_spinor(pbf1, fb, g.ldv, n.fwd[NU1]);
+    load_col_conj(ub1, U, g.ldv, NU1, a, n.bwd[NU1]);
+    load_spinor(pab1, fa, g.ldv, n.bwd[NU1]);
+    load_spinor(pbb1, fb, g.ldv, n.bwd[NU1]);
+    mem_fence_compiler();
+    hop1<NU0, +1>(acca, uf0, paf0, up0);
+    hop1<NU0, +1>(accb, uf0, pbf0, dn0);
+    hop1<NU0, -1>(acca, ub0, pab0, dn0);
+    hop1<NU0, -1>(accb, ub0, pbb0, up0);
+    hop1<NU1, +1>(acca, uf1, paf1, up1);
+    hop1<NU1, +1>(accb, uf1, pbf1, dn1);
+    hop1<NU1, -1>(acca, ub1, pab1, dn1);
+    hop1<NU1, -1>(accb, ub1, pbb1, up1);
+}
+
 // Colour grid with two wavefronts per block: wavefront h takes directions 2h and
-// 2h + 1 (eager loads), halving the chain of dependent memory round trips.
+// 2h + 1, all their operands in one round trip.
 template <typename R>
 __device__ __forceinline__ void hop_half_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
                                               const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
                                               const Geom& g, int s, int a, const Nbr& n, R ep, R em, int half) {
-    if (half == 0) {
-        hop_dir_pair1_eager<0>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
-        hop_dir_pair1_eager<1>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
-    } else {
-        hop_dir_pair1_eager<2>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
-        hop_dir_pair1_eager<3>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
-    }
+    if (half == 0)
+        hop_two_dirs_pair_eager<0, 1>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
+    else
+        hop_two_dirs_pair_eager<2, 3>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
 }
 
 // Adds wavefront 1's sums to wavefront 0's (through LDS, one barrier): afterwards
@@ -801,7 +833,8 @@ __device__ __forceinline__ void fwd_pair_finish(const Geom& g, double kappa, con
 // workgroup, each with two of the four directions (half the chain of dependent
 // memory round trips); wavefront 0 adds the halves and runs the epilogue.
 template <typename R, int BLK>
-__global__ __launch_bounds__(BLK) void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
                                                   Work<R> wk, SrcList L, Coef coef0, int j, int npart_in,
                                                   int has_eta, int replay) {
     static_assert(BLK == kHBlock, "colour-grid kernel: two wavefronts share the directions");
@@ -1236,7 +1269,8 @@ __device__ __forceinline__ void bwd_rb_finish(const Geom& g, double kappa, const
 // no residual adjoints: abar = alphabar w, vbar = |x| conj(c) eta + alphabar b,
 // wbar = conj(alphabar) a.
 template <typename R, bool LAST, int BLK>
-__global__ __launch_bounds__(BLK) void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(1, BLK == kSites && !LAST ? 1 : 8)))
+void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
                                                     Work<R> wk, SrcList L, Coef coef0, int j, int npart_in) {
     const int e = blockIdx.y, slot = L.slot[e];
     const Coef coef = coef0.at(slot);
@@ -1254,8 +1288,16 @@ __global__ __launch_bounds__(BLK) void k_bwd_rb(const Z<R>* __restrict__ U, Geom
     if (!LAST) {
         gather_partials<kNvRA, BLK>(wk.p(slot, 1), npart_in, red);
         if (s < g.V) {
-            hop_all_pair<BLK>(accs, accr, U, wk.sb(slot, j), wk.f(slot, 6 + (j & 1)), g, s, a, neighbours(g, s),
-                              (R)emu, (R)(1.0 / emu));
+            const Z<R>* fs = wk.sb(slot, j);
+            const Z<R>* fr = wk.f(slot, 6 + (j & 1));
+            const Nbr n = neighbours(g, s);
+            if constexpr (BLK == kSites) {   // one wavefront per SIMD: two directions per round trip
+                hop_two_dirs_pair_eager<0, 1>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
+                mem_fence_compiler();
+                hop_two_dirs_pair_eager<2, 3>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
+            } else {
+                hop_all_pair<BLK>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
+            }
             mem_fence_compiler();
         }
         block_sum<kNvRA, BLK>(red);
