@@ -450,6 +450,63 @@ __global__ __launch_bounds__(kDB) void k_zgemm(DenseWork w0, SrcList L, int ia, 
     }
 }
 
+// Several outputs of one inverse-free step in one launch: grid dimension z runs
+// over (entry, output) pairs.  Output o forms C = a (A B + A2 B2) + b D, the second
+// product only when ia2 >= 0, with the two products in separate accumulators
+// (A, B, A2, B2 must not be C; D may be C).  Same tiles as k_zgemm.
+struct GemmOut {
+    int ia, ib, ia2, ib2, ic, id;
+    double a, b;
+};
+struct GemmOuts {
+    GemmOut o0, o1;
+    int n;
+};
+
+__global__ __launch_bounds__(kDB) void k_zgemm_outs(DenseWork w0, SrcList L, GemmOuts outs) {
+    __shared__ ZD As[16][17], Bs[16][17], A2s[16][17], B2s[16][17];
+    const int e = (int)blockIdx.z / outs.n, k = L.k[e];
+    if ((int)blockIdx.x * 16 >= k || (int)blockIdx.y * 16 >= k) return;
+    const bool first = (int)blockIdx.z % outs.n == 0;   // uniform: pick the output's fields without indexing
+    const int ia = first ? outs.o0.ia : outs.o1.ia, ib = first ? outs.o0.ib : outs.o1.ib;
+    const int ia2 = first ? outs.o0.ia2 : outs.o1.ia2, ib2 = first ? outs.o0.ib2 : outs.o1.ib2;
+    const int ic = first ? outs.o0.ic : outs.o1.ic, id = first ? outs.o0.id : outs.o1.id;
+    const double a = first ? outs.o0.a : outs.o1.a, b = first ? outs.o0.b : outs.o1.b;
+    const DenseWork w = w0.at(L.slot[e]);
+    const bool two = ia2 >= 0;
+    const ZD* __restrict__ A = dmat(w, ia);
+    const ZD* __restrict__ B = dmat(w, ib);
+    const ZD* __restrict__ A2 = dmat(w, two ? ia2 : ia);
+    const ZD* __restrict__ B2 = dmat(w, two ? ib2 : ib);
+    ZD* C = dmat(w, ic);
+    const ZD* D = dmat(w, id);
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int r = blockIdx.y * 16 + ty, c = blockIdx.x * 16 + tx;
+    ZD acc = mk<double>(0, 0), acc2 = mk<double>(0, 0);
+    for (int kk = 0; kk < k; kk += 16) {
+        const bool ra = r < k && kk + tx < k, rb = kk + ty < k && c < k;
+        As[ty][tx] = ra ? A[(size_t)r * k + kk + tx] : mk<double>(0, 0);
+        Bs[ty][tx] = rb ? B[(size_t)(kk + ty) * k + c] : mk<double>(0, 0);
+        if (two) {
+            A2s[ty][tx] = ra ? A2[(size_t)r * k + kk + tx] : mk<double>(0, 0);
+            B2s[ty][tx] = rb ? B2[(size_t)(kk + ty) * k + c] : mk<double>(0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc = acc + As[ty][q] * Bs[q][tx];
+        if (two)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc2 = acc2 + A2s[ty][q] * B2s[q][tx];
+        __syncthreads();
+    }
+    if (r < k && c < k) {
+        const size_t o = (size_t)r * k + c;
+        ZD v = a * (two ? acc + acc2 : acc);
+        if (b != 0.0) v = v + b * D[o];
+        C[o] = v;
+    }
+}
+
 // X <- (mu X + X^{-1}/mu)/2, copy into Wk for the next inversion, partials of
 // |X_new - X|^2 and |X_new|^2.
 __global__ __launch_bounds__(kDB) void k_dense_update(DenseWork w0, SrcList L) {
@@ -693,13 +750,24 @@ void dense_ns_step(const SrcList& L, int grad, const DenseWork& w, hipStream_t s
     auto gemm = [&](int ia, int ib, int ic, int id, double a, double b) {
         hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w, L, ia, ib, ic, id, a, b, 0);
     };
-    gemm(kMX, kMX, kMZt, kMZt, 1.0, 0.0);          // Q = X^2
-    gemm(kMX, kMZt, kMWk, kMX, -0.5, 1.5);         // X_new = 1.5 X - 0.5 X Q
     if (grad) {
-        gemm(kMX, kMY, kMXinv, kMXinv, 1.0, 0.0);  // P = X Y
-        gemm(kMY, kMX, kMXinv, kMXinv, 1.0, 1.0);  // P += Y X
-        gemm(kMY, kMZt, kMY2, kMY, -0.5, 1.5);     // Y_new = 1.5 Y - 0.5 Y Q
-        gemm(kMX, kMXinv, kMY2, kMY2, -0.5, 1.0);  //       - 0.5 X P
+        // two launches of two outputs: first the products of the current X and Y,
+        // then the new iterates from them
+        const int nz = 2 * L.n;
+        const dim3 g3(g2.x, g2.y, nz);
+        GemmOuts p1{};
+        p1.n = 2;
+        p1.o0 = GemmOut{kMX, kMX, -1, -1, kMZt, kMZt, 1.0, 0.0};          // Q = X^2
+        p1.o1 = GemmOut{kMX, kMY, kMY, kMX, kMXinv, kMXinv, 1.0, 0.0};    // P = X Y + Y X
+        hipLaunchKernelGGL(k_zgemm_outs, g3, dim3(kDB), 0, st, w, L, p1);
+        GemmOuts p2{};
+        p2.n = 2;
+        p2.o0 = GemmOut{kMX, kMZt, -1, -1, kMWk, kMX, -0.5, 1.5};         // X_new = 1.5 X - 0.5 X Q
+        p2.o1 = GemmOut{kMY, kMZt, kMX, kMXinv, kMY2, kMY, -0.5, 1.5};    // Y_new = 1.5 Y - 0.5 (Y Q + X P)
+        hipLaunchKernelGGL(k_zgemm_outs, g3, dim3(kDB), 0, st, w, L, p2);
+    } else {
+        gemm(kMX, kMX, kMZt, kMZt, 1.0, 0.0);   // Q = X^2
+        gemm(kMX, kMZt, kMWk, kMX, -0.5, 1.5);  // X_new = 1.5 X - 0.5 X Q
     }
     const int nblk = grid_for(kmax * kmax, kDB);
     hipLaunchKernelGGL(k_ns_commit, dim3(nblk, 1, L.n), dim3(kDB), 0, st, w, L, grad);
