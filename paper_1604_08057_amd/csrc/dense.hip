@@ -312,9 +312,10 @@ __global__ __launch_bounds__(BLK) void k_gj_panel_reg(DenseWork w0, SrcList L, i
 
 // Apply panel K's row swaps and transform to TC columns outside the panel:
 // x <- swaps(x);  x_new[i] = [i outside panel] x[i] + sum_q P[i][q] x[c0 + q].
-// Thread t owns rows i = t, t + 256, ... of the block's TC columns.
+// Thread t owns rows i = t, t + 256, ... of the block's TC columns.  Any k: the
+// columns are staged in LDS and swapped there.
 template <int NB>
-__global__ __launch_bounds__(kDB) void k_gj_trailing(DenseWork w0, SrcList L, int c0, int TC) {
+__global__ __launch_bounds__(kDB) void k_gj_trailing_staged(DenseWork w0, SrcList L, int c0, int TC) {
     extern __shared__ ZD smem[];
     const int e = blockIdx.z, k = L.k[e];
     if (c0 >= k) return;
@@ -371,6 +372,68 @@ __global__ __launch_bounds__(kDB) void k_gj_trailing(DenseWork w0, SrcList L, in
             Wk[(size_t)i * k + c] = acc;
         }
     }
+}
+
+// The same for k <= kDB (thread i owns row i): the swaps are not carried out.  Row
+// i of the swapped column is row src(i) of the stored one, found by undoing the
+// panel's exchanges in reverse order; every global load (panel row, the row's
+// column entries, the pivot rows' entries) is issued before the one block barrier,
+// and every entry is read before any is written.  Same arithmetic, same order.
+__device__ __forceinline__ int gj_swapped_row(int i, const int* __restrict__ ipiv, int c0, int nbK) {
+    int src = i;
+    for (int q = nbK - 1; q >= 0; --q) {
+        const int p = c0 + q, im = ipiv[p];
+        src = src == p ? im : (src == im ? p : src);
+    }
+    return src;
+}
+
+constexpr int kTrailTC = 16;   // largest TC of the register trailing kernel
+
+template <int NB>
+__global__ __launch_bounds__(kDB) void k_gj_trailing(DenseWork w0, SrcList L, int c0, int TC) {
+    __shared__ ZD xp[NB * kTrailTC];   // the pivot rows' entries of the swapped columns
+    const int e = blockIdx.z, k = L.k[e];
+    if (c0 >= k) return;
+    const int nbK = min(NB, k - c0);
+    const int nother = k - nbK;
+    const int cid0 = blockIdx.x * TC;
+    const int tcv = min(TC, nother - cid0);
+    if (tcv <= 0) return;
+    const DenseWork w = w0.at(L.slot[e]);
+    ZD* __restrict__ Wk = w.Wk;
+    const int* __restrict__ ipiv = w.rowperm + w.kcap;
+    const int i = threadIdx.x;
+    auto col = [&](int t) {
+        const int cid = cid0 + t;
+        return cid < c0 ? cid : cid + nbK;
+    };
+    if (i < nbK * tcv) {
+        const int q = i / tcv, t = i % tcv;
+        xp[q * kTrailTC + t] = Wk[(size_t)gj_swapped_row(c0 + q, ipiv, c0, nbK) * k + col(t)];
+    }
+    const bool mine = i < k;
+    const bool inblk = i >= c0 && i < c0 + nbK;
+    const int src = mine ? gj_swapped_row(i, ipiv, c0, nbK) : 0;
+    const ZD* prow = Wk + (size_t)(mine ? i : 0) * k + c0;
+    ZD pr[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) pr[q] = (q < nbK) ? prow[q] : mk<double>(0, 0);
+    ZD xv[kTrailTC];
+#pragma unroll
+    for (int t = 0; t < kTrailTC; ++t)
+        xv[t] = (mine && !inblk && t < tcv) ? Wk[(size_t)src * k + col(t)] : mk<double>(0, 0);
+    __syncthreads();
+    if (mine)
+#pragma unroll
+        for (int t = 0; t < kTrailTC; ++t)
+            if (t < tcv) {
+                ZD acc = xv[t];
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+                    if (q < nbK) acc = acc + pr[q] * xp[q * kTrailTC + t];
+                Wk[(size_t)i * k + col(t)] = acc;
+            }
 }
 
 // X^{-1}[:, rowperm[i]] = Wk[:, i], with per-block partials of |X^{-1}|_F^2 and |X|_F^2.
@@ -575,9 +638,14 @@ void gj_sweep(const SrcList& L, int TC, size_t panel_lds, const DenseWork& w, hi
         const int nbK = (kmax - c0) < NB ? (kmax - c0) : NB;
         const int nother = kmax - nbK;
         if (nother > 0) {
-            const size_t tl = (size_t)(kmax * (TC + 1) + NB * TC) * sizeof(ZD);
-            hipLaunchKernelGGL(k_gj_trailing<NB>, dim3(grid_for(nother, TC), 1, act.n), dim3(kDB), tl, st, w, act,
-                               c0, TC);
+            if (kmax <= kDB && TC <= kTrailTC) {
+                hipLaunchKernelGGL(k_gj_trailing<NB>, dim3(grid_for(nother, TC), 1, act.n), dim3(kDB), 0, st, w,
+                                   act, c0, TC);
+            } else {
+                const size_t tl = (size_t)(kmax * (TC + 1) + NB * TC) * sizeof(ZD);
+                hipLaunchKernelGGL(k_gj_trailing_staged<NB>, dim3(grid_for(nother, TC), 1, act.n), dim3(kDB), tl, st,
+                                   w, act, c0, TC);
+            }
         }
     }
 }
