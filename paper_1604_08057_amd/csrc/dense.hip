@@ -199,15 +199,18 @@ __global__ __launch_bounds__(kDB) void k_gj_panel(DenseWork w0, SrcList L, int c
     }
 }
 
-// Register-resident panel for k <= BLK: the same elimination as k_gj_panel, with
-// thread i of a BLK-thread block holding row i of the panel in registers.  One
+// Register-resident panel for k <= BLK: the same elimination as k_gj_panel, each
+// thread of a BLK-thread block holding one row of the panel in registers.  One
 // block barrier per pivot: before it, each wavefront publishes its best candidate
-// row (largest |P[i][q]|^2, smallest index on ties) and the owner of row p publishes
-// the old row p, in LDS slots that alternate between even and odd pivots; after it,
-// every thread picks the block's pivot from the candidates and updates its own row
-// as row - (f / P[imax][q]) P[imax].  The row swap needs no data movement beyond
-// the published old row p, which the owner of row imax takes over.  The pivot is
-// the unique maximum under that order, so the result does not depend on BLK.
+// row (largest |P[i][q]|^2, smallest row index on ties) in LDS slots that alternate
+// between even and odd pivots; after it, every thread picks the block's pivot from
+// the candidates and updates its own row as row - (f / P[imax][q]) P[imax].  The
+// row exchange moves no data: threads carry the index of the row they hold, the
+// pivot row's thread takes index p and the old row p's thread index imax (whose
+// update, with its own f, is the exchanged row's).  Rows are written back under
+// their final indices.  The pivot is the unique maximum under that order, so the
+// result does not depend on BLK.  A column without a finite candidate makes every
+// row NaN (the matrix has no usable inverse; the caller's finiteness check reports it).
 constexpr int kGjRegMax = 512;   // largest k served by the register-resident panel
 
 template <int NB, int BLK>
@@ -216,7 +219,6 @@ __global__ __launch_bounds__(BLK) void k_gj_panel_reg(DenseWork w0, SrcList L, i
     __shared__ ZD cand[2][kNW][NB];
     __shared__ double cval[2][kNW];
     __shared__ int cidx[2][kNW];
-    __shared__ ZD rowp[2][NB];
     __shared__ int perm[BLK];
     __shared__ int piv_s[NB];
     const int e = blockIdx.z, k = L.k[e];
@@ -226,7 +228,8 @@ __global__ __launch_bounds__(BLK) void k_gj_panel_reg(DenseWork w0, SrcList L, i
     int* __restrict__ rowperm = w.rowperm;
     int* __restrict__ ipiv = w.rowperm + w.kcap;
     const int i = threadIdx.x, wave = i / kWave, lane = i % kWave;
-    const bool mine = i < k;   // this thread holds row i
+    const bool mine = i < k;   // this thread holds a row
+    int lr = i;                // the index of the row it holds
     const int nbK = min(NB, k - c0);
     if (mine) perm[i] = rowperm[i];
     ZD row[NB];
@@ -237,19 +240,16 @@ __global__ __launch_bounds__(BLK) void k_gj_panel_reg(DenseWork w0, SrcList L, i
         if (q < nbK) {   // uniform; the loop unrolls fully so that row[q] stays in registers
             const int p = c0 + q, b = q & 1;
             const double m = norm2(row[q]);
-            double best = (mine && i >= p && m >= 0.0) ? m : -1.0;   // a NaN entry is never a candidate
-            int bi = best >= 0.0 ? i : k;
+            double best = (mine && lr >= p && m >= 0.0) ? m : -1.0;   // a NaN entry is never a candidate
+            int bi = best >= 0.0 ? lr : k;
             wave_argmax(best, bi);
             if (lane == 0) {
                 cval[b][wave] = best;
                 cidx[b][wave] = bi;
             }
-            if (i == bi)
+            if (mine && lr == bi)
 #pragma unroll
                 for (int qq = 0; qq < NB; ++qq) cand[b][wave][qq] = row[qq];
-            if (i == p)
-#pragma unroll
-                for (int qq = 0; qq < NB; ++qq) rowp[b][qq] = row[qq];
             __syncthreads();
             // all candidates in one round of LDS reads, then a branch-free choice
             double cv[kNW];
@@ -268,22 +268,25 @@ __global__ __launch_bounds__(BLK) void k_gj_panel_reg(DenseWork w0, SrcList L, i
                 imax = t ? ci[v] : imax;
                 wwin = t ? v : wwin;
             }
-            const bool valid = imax >= p && imax < k;   // else a non-finite column: keep the order
-            if (!valid) imax = p;
-            const ZD* __restrict__ src = valid ? &cand[b][wwin][0] : &rowp[b][0];
+            const bool valid = imax >= p && imax < k;
+            if (i == 0) piv_s[q] = valid ? imax : p;
+            if (!valid) {   // uniform
+#pragma unroll
+                for (int qq = 0; qq < NB; ++qq) row[qq] = mk<double>(__builtin_nan(""), __builtin_nan(""));
+                continue;
+            }
+            const ZD* __restrict__ src = &cand[b][wwin][0];
             const ZD inv = zdiv(mk<double>(1.0, 0.0), src[q]);
-            ZD piv[NB];
+            if (mine && lr == imax) {   // the pivot row becomes row p
 #pragma unroll
-            for (int qq = 0; qq < NB; ++qq) piv[qq] = src[qq];
-            if (i == 0) piv_s[q] = imax;
-            if (i == p) {
-#pragma unroll
-                for (int qq = 0; qq < NB; ++qq) row[qq] = piv[qq] * inv;
+                for (int qq = 0; qq < NB; ++qq) row[qq] = row[qq] * inv;
                 row[q] = inv;
+                lr = p;
             } else if (mine) {
-                if (i == imax)
+                if (lr == p) lr = imax;   // the old row p takes the pivot row's place
+                ZD piv[NB];
 #pragma unroll
-                    for (int qq = 0; qq < NB; ++qq) row[qq] = rowp[b][qq];
+                for (int qq = 0; qq < NB; ++qq) piv[qq] = src[qq];
                 const ZD f = row[q] * inv;
 #pragma unroll
                 for (int qq = 0; qq < NB; ++qq) row[qq] = row[qq] - f * piv[qq];
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(BLK) void k_gj_panel_reg(DenseWork w0, SrcList L, i
     if (mine)
 #pragma unroll
         for (int qq = 0; qq < NB; ++qq)
-            if (qq < nbK) Wk[(size_t)i * k + c0 + qq] = row[qq];
+            if (qq < nbK) Wk[(size_t)lr * k + c0 + qq] = row[qq];
     __syncthreads();
     if (mine) rowperm[i] = perm[i];
 }
