@@ -652,7 +652,7 @@ int choose_nb(const tslov_ctx* c, int k) {
 // step count.
 constexpr double kNsSwitch = 1e-2;
 constexpr double kNsSafe = 0.9;
-constexpr double kResidCheck = 0.3;
+constexpr double kResidCheck = 2.0;
 
 tslov_status newton(tslov_ctx* c, const SrcList& L, int grad, const DenseWork& w, std::vector<int>& iters,
                     int tridiag_start) {

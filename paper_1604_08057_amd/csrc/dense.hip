@@ -455,13 +455,59 @@ __global__ __launch_bounds__(kDB) void k_dense_scatter(DenseWork w0, SrcList L) 
     write_partials<2, kDB>(w.part + 2 * w.npart_max, v);
 }
 
-// Newton scaling: mu = sqrt(|X^{-1}|_F / |X|_F) while scaling is on (flag), else 1.
-__global__ __launch_bounds__(kDB) void k_dense_mu(DenseWork w0, SrcList L, int npart) {
+// Largest column sum of |x| (the 1-norm) of X^{-1} and of X, per block of 64
+// columns: four row groups sum a column in a fixed order, then the block's maximum.
+__global__ __launch_bounds__(kDB) void k_dense_colnorm(DenseWork w0, SrcList L) {
+    __shared__ double cs[2][4][64];
+    const int e = blockIdx.z, k = L.k[e];
+    const DenseWork w = w0.at(L.slot[e]);
+    const int l = threadIdx.x % 64, grp = threadIdx.x / 64;
+    const int c = blockIdx.x * 64 + l;
+    double si = 0.0, sx = 0.0;
+    if (c < k)
+        for (int r = grp; r < k; r += 4) {
+            si += std::sqrt(norm2(w.Xinv[(size_t)r * k + c]));
+            sx += std::sqrt(norm2(w.X[(size_t)r * k + c]));
+        }
+    cs[0][grp][l] = si;
+    cs[1][grp][l] = sx;
+    __syncthreads();
+    if (threadIdx.x < 64) {   // one wavefront: column sums, then their maximum over the lanes
+        double mi = ((cs[0][0][l] + cs[0][1][l]) + cs[0][2][l]) + cs[0][3][l];
+        double mx = ((cs[1][0][l] + cs[1][1][l]) + cs[1][2][l]) + cs[1][3][l];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            mi = std::fmax(mi, __shfl_xor(mi, o));
+            mx = std::fmax(mx, __shfl_xor(mx, o));
+        }
+        if (l == 0) {
+            double* q = w.part + 5 * w.npart_max + 8 + 2 * blockIdx.x;
+            q[0] = mi;
+            q[1] = mx;
+        }
+    }
+}
+
+// Newton scaling while it is on (flag), else 1: mu = sqrt(mu_F mu_1), the geometric
+// mean of the Frobenius-norm scaling mu_F = sqrt(|X^{-1}|_F / |X|_F) and the 1-norm
+// scaling mu_1 = sqrt(|X^{-1}|_1 / |X|_1).  Either alone is a cheap stand-in for the
+// spectral-norm scaling; their mean needs fewer inverse-based steps than either on the
+// Krylov matrices of the lattice workloads.
+__global__ __launch_bounds__(kDB) void k_dense_mu(DenseWork w0, SrcList L, int npart, int ncb) {
     const int e = blockIdx.z;
     const DenseWork w = w0.at(L.slot[e]);
     double red[2];
     reduce_partials<2, kDB>(w.part + 2 * w.npart_max, npart, red);
-    if (threadIdx.x == 0) w.part[4 * w.npart_max] = L.flag[e] ? std::sqrt(std::sqrt(red[0] / red[1])) : 1.0;
+    if (threadIdx.x == 0) {
+        const double* q = w.part + 5 * w.npart_max + 8;
+        double n1i = 0.0, n1x = 0.0;
+        for (int b = 0; b < ncb; ++b) {
+            n1i = std::fmax(n1i, q[2 * b]);
+            n1x = std::fmax(n1x, q[2 * b + 1]);
+        }
+        const double mf = std::sqrt(std::sqrt(red[0] / red[1])), m1 = std::sqrt(n1i / n1x);
+        w.part[4 * w.npart_max] = L.flag[e] ? std::sqrt(mf * m1) : 1.0;
+    }
 }
 
 // ------------------------------------------------------------------ complex GEMM
@@ -767,10 +813,12 @@ void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, con
                        int tridiag) {
     const int kmax = L.k[0];
     const int nblk = grid_for(kmax * kmax, kDB);
+    const int ncb = dense_colnorm_blocks(kmax);
     if (tridiag) {
         const size_t tl = (size_t)7 * kmax * sizeof(ZD) + (size_t)kmax * sizeof(int);
         hipLaunchKernelGGL(k_tridiag_inv, dim3(1, 1, L.n), dim3(kDB), tl, st, w, L);
-        hipLaunchKernelGGL(k_dense_mu, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, 1);
+        hipLaunchKernelGGL(k_dense_colnorm, dim3(ncb, 1, L.n), dim3(kDB), 0, st, w, L);
+        hipLaunchKernelGGL(k_dense_mu, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, 1, ncb);
     } else {
         hipLaunchKernelGGL(k_rowperm_init, dim3(grid_for(kmax, kDB), 1, L.n), dim3(kDB), 0, st, L, w);
         const size_t panel_lds = (size_t)(kmax * (nb + 1)) * sizeof(ZD) + (size_t)kmax * sizeof(int);
@@ -788,7 +836,8 @@ void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, con
             default: gj_sweep<1>(L, TC, panel_lds, w, st); break;
         }
         hipLaunchKernelGGL(k_dense_scatter, dim3(nblk, 1, L.n), dim3(kDB), 0, st, w, L);
-        hipLaunchKernelGGL(k_dense_mu, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, nblk);
+        hipLaunchKernelGGL(k_dense_colnorm, dim3(ncb, 1, L.n), dim3(kDB), 0, st, w, L);
+        hipLaunchKernelGGL(k_dense_mu, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, nblk, ncb);
     }
     if (grad) {
         dim3 g2(grid_for(kmax, 16), grid_for(kmax, 16), L.n);

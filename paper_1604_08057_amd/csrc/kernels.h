@@ -200,7 +200,8 @@ struct DenseWork {
     ZD* Zt;       // GEMM temporary
     ZD* Y2;       // second temporary (inverse-free steps with the Frechet block)
     int* rowperm; // [slot][2 kcap]: row permutation, then pivot rows
-    double* part; // [slot][pstride]: update partials, scatter partials, mu, residual partials
+    double* part; // [slot][pstride]: update partials, scatter partials, mu, residual partials,
+                  // column-norm partials
     double* delta;  // [slot][4]: |X_new - X|^2, |X_new|^2 of the last step, |I - X_new^2|_F^2, unused
     size_t kk;    // kcap^2
     int kcap;
@@ -216,7 +217,8 @@ struct DenseWork {
         return o;
     }
 };
-inline int dense_pstride(int kcap) { return 5 * grid_for(kcap * kcap, 256) + 8; }
+inline int dense_colnorm_blocks(int k) { return (k + 63) / 64; }
+inline int dense_pstride(int kcap) { return 5 * grid_for(kcap * kcap, 256) + 8 + 2 * dense_colnorm_blocks(kcap); }
 
 // Build X = T_k (tridiagonal from coef) and, if grad, Y = e_1 cbar^H with cbar = |x| conj(h),
 // for every list entry (k[e] = k_used, sorted in decreasing order).
