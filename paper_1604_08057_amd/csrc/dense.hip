@@ -455,32 +455,38 @@ __global__ __launch_bounds__(kDB) void k_dense_scatter(DenseWork w0, SrcList L) 
     write_partials<2, kDB>(w.part + 2 * w.npart_max, v);
 }
 
-// Largest column sum of |x| (the 1-norm) of X^{-1} and of X, per block of 64
-// columns: four row groups sum a column in a fixed order, then the block's maximum.
+// Largest column sum of |x| (the 1-norm) of X^{-1} and of X, per block of 16
+// columns: sixteen row groups sum a column, the group sums are added in group order,
+// then the block takes the maximum over its columns.
 __global__ __launch_bounds__(kDB) void k_dense_colnorm(DenseWork w0, SrcList L) {
-    __shared__ double cs[2][4][64];
+    __shared__ double cs[2][16][17];
     const int e = blockIdx.z, k = L.k[e];
     const DenseWork w = w0.at(L.slot[e]);
-    const int l = threadIdx.x % 64, grp = threadIdx.x / 64;
-    const int c = blockIdx.x * 64 + l;
+    const int tx = threadIdx.x % 16, grp = threadIdx.x / 16;
+    const int c = blockIdx.x * 16 + tx;
     double si = 0.0, sx = 0.0;
     if (c < k)
-        for (int r = grp; r < k; r += 4) {
+#pragma unroll 4
+        for (int r = grp; r < k; r += 16) {
             si += std::sqrt(norm2(w.Xinv[(size_t)r * k + c]));
             sx += std::sqrt(norm2(w.X[(size_t)r * k + c]));
         }
-    cs[0][grp][l] = si;
-    cs[1][grp][l] = sx;
+    cs[0][grp][tx] = si;
+    cs[1][grp][tx] = sx;
     __syncthreads();
-    if (threadIdx.x < 64) {   // one wavefront: column sums, then their maximum over the lanes
-        double mi = ((cs[0][0][l] + cs[0][1][l]) + cs[0][2][l]) + cs[0][3][l];
-        double mx = ((cs[1][0][l] + cs[1][1][l]) + cs[1][2][l]) + cs[1][3][l];
+    if (threadIdx.x < 16) {   // lanes 0-15 of wavefront 0: column sums, then their maximum
+        double mi = 0.0, mx = 0.0;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            mi = std::fmax(mi, __shfl_xor(mi, o));
-            mx = std::fmax(mx, __shfl_xor(mx, o));
+        for (int g = 0; g < 16; ++g) {
+            mi += cs[0][g][tx];
+            mx += cs[1][g][tx];
         }
-        if (l == 0) {
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            mi = std::fmax(mi, __shfl_xor(mi, o, 16));
+            mx = std::fmax(mx, __shfl_xor(mx, o, 16));
+        }
+        if (tx == 0) {
             double* q = w.part + 5 * w.npart_max + 8 + 2 * blockIdx.x;
             q[0] = mi;
             q[1] = mx;

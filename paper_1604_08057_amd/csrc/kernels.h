@@ -217,7 +217,7 @@ struct DenseWork {
         return o;
     }
 };
-inline int dense_colnorm_blocks(int k) { return (k + 63) / 64; }
+inline int dense_colnorm_blocks(int k) { return (k + 15) / 16; }
 inline int dense_pstride(int kcap) { return 5 * grid_for(kcap * kcap, 256) + 8 + 2 * dense_colnorm_blocks(kcap); }
 
 // Build X = T_k (tridiagonal from coef) and, if grad, Y = e_1 cbar^H with cbar = |x| conj(h),
