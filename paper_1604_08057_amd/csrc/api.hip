@@ -612,7 +612,7 @@ tslov_status forward(tslov_ctx* c, const SrcList& L, const ZD* psi, const ZD* et
 tslov_status ensure_dense(tslov_ctx* c, int slots, int kcap, DenseWork& w) {
     const size_t kk = (size_t)kcap * kcap;
     const int ps = tslov::dense_pstride(kcap);
-    CHK(ensure(c->dense, (size_t)slots * 6 * kk * sizeof(ZD)));
+    CHK(ensure(c->dense, (size_t)slots * 8 * kk * sizeof(ZD)));
     CHK(ensure(c->denseInt, (size_t)slots * 2 * kcap * sizeof(int)));
     CHK(ensure(c->densePart, (size_t)slots * ps * sizeof(double)));
     CHK(ensure(c->denseDelta, (size_t)slots * 4 * sizeof(double)));
@@ -625,6 +625,8 @@ tslov_status ensure_dense(tslov_ctx* c, int slots, int kcap, DenseWork& w) {
     w.Xinv = d + 3 * S * kk;
     w.Zt = d + 4 * S * kk;
     w.Y2 = d + 5 * S * kk;
+    w.P2 = d + 6 * S * kk;
+    w.Y3 = d + 7 * S * kk;
     w.rowperm = c->denseInt.as<int>();
     w.part = c->densePart.as<double>();
     w.delta = c->denseDelta.as<double>();

@@ -517,7 +517,7 @@ __global__ __launch_bounds__(kDB) void k_dense_mu(DenseWork w0, SrcList L, int n
 }
 
 // ------------------------------------------------------------------ complex GEMM
-// Operands by index into the entry's matrices: 0 X, 1 Y, 2 Wk, 3 Xinv, 4 Zt, 5 Y2.
+// Operands by index into the entry's matrices: 0 X, 1 Y, 2 Wk, 3 Xinv, 4 Zt, 5 Y2, 6 P2, 7 Y3.
 __device__ __forceinline__ ZD* dmat(const DenseWork& w, int i) {
     switch (i) {
         case 0: return w.X;
@@ -525,10 +525,12 @@ __device__ __forceinline__ ZD* dmat(const DenseWork& w, int i) {
         case 2: return w.Wk;
         case 3: return w.Xinv;
         case 4: return w.Zt;
-        default: return w.Y2;
+        case 5: return w.Y2;
+        case 6: return w.P2;
+        default: return w.Y3;
     }
 }
-enum { kMX = 0, kMY = 1, kMWk = 2, kMXinv = 3, kMZt = 4, kMY2 = 5 };
+enum { kMX = 0, kMY = 1, kMWk = 2, kMXinv = 3, kMZt = 4, kMY2 = 5, kMP2 = 6, kMY3 = 7 };
 
 // C = a (A B) + b D (D may be C; A, B must not be C).  mode 1 instead forms the
 // Newton Frechet update C <- (mu C - (A B)/mu)/2 with mu read from the device.
@@ -569,59 +571,54 @@ __global__ __launch_bounds__(kDB) void k_zgemm(DenseWork w0, SrcList L, int ia, 
 }
 
 // Several outputs of one inverse-free step in one launch: grid dimension z runs
-// over (entry, output) pairs.  Output o forms C = a (A B + A2 B2) + b D, the second
-// product only when ia2 >= 0, with the two products in separate accumulators
-// (A, B, A2, B2 must not be C; D may be C).  Same tiles as k_zgemm.
+// over (entry, output) pairs.  Output o forms C = a (A B) + b D, where B is the sum
+// of two matrices, taken as its tiles load, when ibs >= 0 (A, B, Bs must not be C;
+// D may be C).  Same tiles as k_zgemm.
 struct GemmOut {
-    int ia, ib, ia2, ib2, ic, id;
+    int ia, ib, ibs, ic, id;
     double a, b;
 };
 struct GemmOuts {
-    GemmOut o0, o1;
+    GemmOut o0, o1, o2;
     int n;
 };
 
 __global__ __launch_bounds__(kDB) void k_zgemm_outs(DenseWork w0, SrcList L, GemmOuts outs) {
-    __shared__ ZD As[16][17], Bs[16][17], A2s[16][17], B2s[16][17];
+    __shared__ ZD As[16][17], Bs[16][17];
     const int e = (int)blockIdx.z / outs.n, k = L.k[e];
     if ((int)blockIdx.x * 16 >= k || (int)blockIdx.y * 16 >= k) return;
-    const bool first = (int)blockIdx.z % outs.n == 0;   // uniform: pick the output's fields without indexing
-    const int ia = first ? outs.o0.ia : outs.o1.ia, ib = first ? outs.o0.ib : outs.o1.ib;
-    const int ia2 = first ? outs.o0.ia2 : outs.o1.ia2, ib2 = first ? outs.o0.ib2 : outs.o1.ib2;
-    const int ic = first ? outs.o0.ic : outs.o1.ic, id = first ? outs.o0.id : outs.o1.id;
-    const double a = first ? outs.o0.a : outs.o1.a, b = first ? outs.o0.b : outs.o1.b;
+    const int o = (int)blockIdx.z % outs.n;   // uniform: each field picked without indexing
+    auto pick = [&](int f0, int f1, int f2) { return o == 0 ? f0 : (o == 1 ? f1 : f2); };
+    auto pickd = [&](double f0, double f1, double f2) { return o == 0 ? f0 : (o == 1 ? f1 : f2); };
+    const int ia = pick(outs.o0.ia, outs.o1.ia, outs.o2.ia), ib = pick(outs.o0.ib, outs.o1.ib, outs.o2.ib);
+    const int ibs = pick(outs.o0.ibs, outs.o1.ibs, outs.o2.ibs);
+    const int ic = pick(outs.o0.ic, outs.o1.ic, outs.o2.ic), id = pick(outs.o0.id, outs.o1.id, outs.o2.id);
+    const double a = pickd(outs.o0.a, outs.o1.a, outs.o2.a), b = pickd(outs.o0.b, outs.o1.b, outs.o2.b);
     const DenseWork w = w0.at(L.slot[e]);
-    const bool two = ia2 >= 0;
+    const bool sum = ibs >= 0;
     const ZD* __restrict__ A = dmat(w, ia);
     const ZD* __restrict__ B = dmat(w, ib);
-    const ZD* __restrict__ A2 = dmat(w, two ? ia2 : ia);
-    const ZD* __restrict__ B2 = dmat(w, two ? ib2 : ib);
+    const ZD* __restrict__ B2 = dmat(w, sum ? ibs : ib);
     ZD* C = dmat(w, ic);
     const ZD* D = dmat(w, id);
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     const int r = blockIdx.y * 16 + ty, c = blockIdx.x * 16 + tx;
-    ZD acc = mk<double>(0, 0), acc2 = mk<double>(0, 0);
+    ZD acc = mk<double>(0, 0);
     for (int kk = 0; kk < k; kk += 16) {
-        const bool ra = r < k && kk + tx < k, rb = kk + ty < k && c < k;
-        As[ty][tx] = ra ? A[(size_t)r * k + kk + tx] : mk<double>(0, 0);
-        Bs[ty][tx] = rb ? B[(size_t)(kk + ty) * k + c] : mk<double>(0, 0);
-        if (two) {
-            A2s[ty][tx] = ra ? A2[(size_t)r * k + kk + tx] : mk<double>(0, 0);
-            B2s[ty][tx] = rb ? B2[(size_t)(kk + ty) * k + c] : mk<double>(0, 0);
-        }
+        const bool rb = kk + ty < k && c < k;
+        As[ty][tx] = (r < k && kk + tx < k) ? A[(size_t)r * k + kk + tx] : mk<double>(0, 0);
+        const size_t ob = (size_t)(kk + ty) * k + c;
+        Bs[ty][tx] = rb ? (sum ? B[ob] + B2[ob] : B[ob]) : mk<double>(0, 0);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc = acc + As[ty][q] * Bs[q][tx];
-        if (two)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc2 = acc2 + A2s[ty][q] * B2s[q][tx];
         __syncthreads();
     }
     if (r < k && c < k) {
-        const size_t o = (size_t)r * k + c;
-        ZD v = a * (two ? acc + acc2 : acc);
-        if (b != 0.0) v = v + b * D[o];
-        C[o] = v;
+        const size_t oc = (size_t)r * k + c;
+        ZD v = a * acc;
+        if (b != 0.0) v = v + b * D[oc];
+        C[oc] = v;
     }
 }
 
@@ -865,7 +862,7 @@ __global__ __launch_bounds__(kDB) void k_ns_commit(DenseWork w0, SrcList L, int 
         v[0] = norm2(xn - x);
         v[1] = norm2(xn);
         w.X[idx] = xn;
-        if (grad) w.Y[idx] = w.Y2[idx];
+        if (grad) w.Y[idx] = w.Y2[idx] + w.Y3[idx];
     }
     write_partials<2, kDB>(w.part, v);
 }
@@ -877,19 +874,21 @@ void dense_ns_step(const SrcList& L, int grad, const DenseWork& w, hipStream_t s
         hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w, L, ia, ib, ic, id, a, b, 0);
     };
     if (grad) {
-        // two launches of two outputs: first the products of the current X and Y,
-        // then the new iterates from them
-        const int nz = 2 * L.n;
-        const dim3 g3(g2.x, g2.y, nz);
+        // two launches of three single-product outputs: first the products of the
+        // current X and Y, then the new iterates from them (Y in two parts, added by
+        // the commit)
+        const dim3 g3(g2.x, g2.y, 3 * L.n);
         GemmOuts p1{};
-        p1.n = 2;
-        p1.o0 = GemmOut{kMX, kMX, -1, -1, kMZt, kMZt, 1.0, 0.0};          // Q = X^2
-        p1.o1 = GemmOut{kMX, kMY, kMY, kMX, kMXinv, kMXinv, 1.0, 0.0};    // P = X Y + Y X
+        p1.n = 3;
+        p1.o0 = GemmOut{kMX, kMX, -1, kMZt, kMZt, 1.0, 0.0};       // Q = X^2
+        p1.o1 = GemmOut{kMX, kMY, -1, kMXinv, kMXinv, 1.0, 0.0};   // P_a = X Y
+        p1.o2 = GemmOut{kMY, kMX, -1, kMP2, kMP2, 1.0, 0.0};       // P_b = Y X
         hipLaunchKernelGGL(k_zgemm_outs, g3, dim3(kDB), 0, st, w, L, p1);
         GemmOuts p2{};
-        p2.n = 2;
-        p2.o0 = GemmOut{kMX, kMZt, -1, -1, kMWk, kMX, -0.5, 1.5};         // X_new = 1.5 X - 0.5 X Q
-        p2.o1 = GemmOut{kMY, kMZt, kMX, kMXinv, kMY2, kMY, -0.5, 1.5};    // Y_new = 1.5 Y - 0.5 (Y Q + X P)
+        p2.n = 3;
+        p2.o0 = GemmOut{kMX, kMZt, -1, kMWk, kMX, -0.5, 1.5};      // X_new = 1.5 X - 0.5 X Q
+        p2.o1 = GemmOut{kMY, kMZt, -1, kMY2, kMY, -0.5, 1.5};      // 1.5 Y - 0.5 Y Q
+        p2.o2 = GemmOut{kMX, kMXinv, kMP2, kMY3, kMY3, -0.5, 0.0}; // -0.5 X (P_a + P_b)
         hipLaunchKernelGGL(k_zgemm_outs, g3, dim3(kDB), 0, st, w, L, p2);
     } else {
         gemm(kMX, kMX, kMZt, kMZt, 1.0, 0.0);   // Q = X^2

@@ -199,6 +199,8 @@ struct DenseWork {
     ZD* Xinv;     // inverse (columns un-permuted)
     ZD* Zt;       // GEMM temporary
     ZD* Y2;       // second temporary (inverse-free steps with the Frechet block)
+    ZD* P2;       // third and fourth temporaries (the same steps' split products)
+    ZD* Y3;
     int* rowperm; // [slot][2 kcap]: row permutation, then pivot rows
     double* part; // [slot][pstride]: update partials, scatter partials, mu, residual partials,
                   // column-norm partials
@@ -210,7 +212,7 @@ struct DenseWork {
     __host__ __device__ DenseWork at(int slot) const {
         DenseWork o = *this;
         const size_t d = (size_t)slot * kk;
-        o.X += d; o.Y += d; o.Wk += d; o.Xinv += d; o.Zt += d; o.Y2 += d;
+        o.X += d; o.Y += d; o.Wk += d; o.Xinv += d; o.Zt += d; o.Y2 += d; o.P2 += d; o.Y3 += d;
         o.rowperm += (size_t)slot * 2 * kcap;
         o.part += (size_t)slot * pstride;
         o.delta += (size_t)slot * 4;
