@@ -14,6 +14,7 @@
 // grid dimension z runs over the entries.
 #include "kernels.h"
 
+#include <cfloat>
 #include <cmath>
 
 namespace tslov {
@@ -93,6 +94,27 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
     }
     v = bv;
     i = bi;
+}
+
+// Pivot candidate key of the register panel: |P[i][q]|^2 (at most DBL_MAX) with its
+// low 9 mantissa bits replaced by 511 - i.  Non-negative doubles order like their
+// bit patterns, so the largest key is the largest value (to 2^-43 relative) and,
+// among values equal to that precision, the smallest row index; rows that are not
+// candidates take -1.  One v_max_f64 per reduction stage instead of a value and an
+// index compared and selected.
+__device__ __forceinline__ double gj_key(double m, int row) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(std::fmin(m, DBL_MAX));
+    return __longlong_as_double((long long)((b & ~0x1FFull) | (unsigned long long)(511 - row)));
+}
+__device__ __forceinline__ int gj_key_row(double key) { return 511 - (int)(__double_as_longlong(key) & 0x1FF); }
+
+// Largest v over the wavefront, in every lane (rows of 16 through DPP, then lane reads).
+__device__ __forceinline__ double wave_max_d(double v) {
+    v = std::fmax(v, dpp_d<kDppSwap1>(v));
+    v = std::fmax(v, dpp_d<kDppSwap2>(v));
+    v = std::fmax(v, dpp_d<kDppHalfMirror>(v));
+    v = std::fmax(v, dpp_d<kDppMirror>(v));
+    return std::fmax(std::fmax(readlane_d(v, 0), readlane_d(v, 16)), std::fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
 
 // Panel K: columns [c0, c0 + nbK) of Wk, all k rows, held in LDS and factored by
@@ -202,7 +224,7 @@ __global__ __launch_bounds__(kDB) void k_gj_panel(DenseWork w0, SrcList L, int c
 // Register-resident panel for k <= BLK: the same elimination as k_gj_panel, each
 // thread of a BLK-thread block holding one row of the panel in registers.  One
 // block barrier per pivot: before it, each wavefront publishes its best candidate
-// row (largest |P[i][q]|^2, smallest row index on ties) in LDS slots that alternate
+// row (the largest candidate key of gj_key) in LDS slots that alternate
 // between even and odd pivots; after it, every thread picks the block's pivot from
 // the candidates and updates its own row as row - (f / P[imax][q]) P[imax].  The
 // row exchange moves no data: threads carry the index of the row they hold, the
@@ -216,9 +238,9 @@ constexpr int kGjRegMax = 512;   // largest k served by the register-resident pa
 template <int NB, int BLK>
 __global__ __launch_bounds__(BLK) void k_gj_panel_reg(DenseWork w0, SrcList L, int c0) {
     constexpr int kNW = BLK / kWave;
+    static_assert(BLK <= 512, "candidate keys hold 9 bits of row index");
     __shared__ ZD cand[2][kNW][NB];
     __shared__ double cval[2][kNW];
-    __shared__ int cidx[2][kNW];
     __shared__ int perm[BLK];
     __shared__ int piv_s[NB];
     const int e = blockIdx.z, k = L.k[e];
@@ -240,34 +262,26 @@ __global__ __launch_bounds__(BLK) void k_gj_panel_reg(DenseWork w0, SrcList L, i
         if (q < nbK) {   // uniform; the loop unrolls fully so that row[q] stays in registers
             const int p = c0 + q, b = q & 1;
             const double m = norm2(row[q]);
-            double best = (mine && lr >= p && m >= 0.0) ? m : -1.0;   // a NaN entry is never a candidate
-            int bi = best >= 0.0 ? lr : k;
-            wave_argmax(best, bi);
-            if (lane == 0) {
-                cval[b][wave] = best;
-                cidx[b][wave] = bi;
-            }
-            if (mine && lr == bi)
+            const double key = (mine && lr >= p && m >= 0.0) ? gj_key(m, lr) : -1.0;   // NaN: never a candidate
+            const double wbest = wave_max_d(key);
+            if (lane == 0) cval[b][wave] = wbest;
+            if (wbest >= 0.0 && key == wbest)   // keys are unique: the wavefront's candidate
 #pragma unroll
                 for (int qq = 0; qq < NB; ++qq) cand[b][wave][qq] = row[qq];
             __syncthreads();
             // all candidates in one round of LDS reads, then a branch-free choice
             double cv[kNW];
-            int ci[kNW];
 #pragma unroll
-            for (int v = 0; v < kNW; ++v) {
-                cv[v] = cval[b][v];
-                ci[v] = cidx[b][v];
-            }
+            for (int v = 0; v < kNW; ++v) cv[v] = cval[b][v];
             double bv = cv[0];
-            int imax = ci[0], wwin = 0;
+            int wwin = 0;
 #pragma unroll
             for (int v = 1; v < kNW; ++v) {
-                const bool t = cv[v] > bv || (cv[v] == bv && ci[v] < imax);
+                const bool t = cv[v] > bv;
                 bv = t ? cv[v] : bv;
-                imax = t ? ci[v] : imax;
                 wwin = t ? v : wwin;
             }
+            const int imax = bv >= 0.0 ? gj_key_row(bv) : k;
             const bool valid = imax >= p && imax < k;
             if (i == 0) piv_s[q] = valid ? imax : p;
             if (!valid) {   // uniform
