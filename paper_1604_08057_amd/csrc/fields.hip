@@ -1186,6 +1186,125 @@ __device__ __forceinline__ BwdCoefs bwd_coefs(const Coef& coef, int j, bool carr
 // Epilogue of reverse step j for one entry, after the hops: the coefficient
 // adjoints from the block-summed partials `red` (not LAST), the adjoint fields'
 // stores and the step's partial sums.
+// block_sum over a one-wavefront block without its barriers (0 + the wavefront's
+// sum, as block_sum forms it), for a wavefront whose partner has left the block.
+template <int NV>
+__device__ __forceinline__ void wave_block_sum(double (&v)[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = 0.0 + wave_sum(v[i]);
+}
+template <int NV>
+__device__ __forceinline__ void wave_partials_at(double* __restrict__ part, int slot, double (&v)[NV]) {
+    wave_block_sum<NV>(v);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) part[slot * NV + i] = v[i];
+}
+
+// The epilogue's own-site operands (colour a, four spins), loaded by bwd_rb_load.
+template <typename R>
+struct BwdRbIn {
+    Z<R> w[4], v[4], a[4], b[4], e[4], r[4], sb[4], rn[4], sn[4];
+};
+
+template <typename R>
+__device__ __forceinline__ void bwd_rb_load(const Geom& g, const Work<R>& wk, int slot, int j, int k_used, int a,
+                                            int s, BwdRbIn<R>& in) {
+    const bool carry = j + 1 < k_used;
+    const FieldBase rw = field_base(wk.w(slot, j)), rv = field_base(wk.v(slot, j)), ra = field_base(wk.a(slot, j)),
+                    rb = field_base(wk.b(slot, j)), re = field_base(wk.f(slot, 1));
+    const FieldBase rr = field_base(wk.f(slot, 6 + (j & 1))), rs = field_base(wk.sb(slot, j));
+    const FieldBase rrn = field_base(wk.f(slot, 6 + ((j + 1) & 1))), rsn = field_base(carry ? wk.sb(slot, j + 1)
+                                                                                          : wk.sb(slot, j));
+    const unsigned i = (unsigned)s;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+        const int pl = sp * 3 + a;
+        in.w[sp] = fload<R>(rw, g.ldv, pl, i);
+        in.v[sp] = fload<R>(rv, g.ldv, pl, i);
+        in.a[sp] = fload<R>(ra, g.ldv, pl, i);
+        in.b[sp] = fload<R>(rb, g.ldv, pl, i);
+        in.e[sp] = fload<R>(re, g.ldv, pl, i);
+        {
+            in.r[sp] = fload<R>(rr, g.ldv, pl, i);
+            in.sb[sp] = fload<R>(rs, g.ldv, pl, i);
+            if (carry) {
+                in.rn[sp] = fload<R>(rrn, g.ldv, pl, i);
+                in.sn[sp] = fload<R>(rsn, g.ldv, pl, i);
+            }
+        }
+    }
+}
+
+// The epilogue of bwd_rb_finish (not the last step) on operands loaded beforehand, for
+// the two-wavefront colour-grid kernel: its wavefront 0 runs it alone, so the sums
+// are formed without barriers.
+template <typename R>
+__device__ __forceinline__ void bwd_rb_finish_pre(const Geom& g, double kappa, const Work<R>& wk, const Coef& coef,
+                                                  int slot, int j, int k_used, int pslot, int a, int s,
+                                                  const double (&red)[kNvRA], const Z<R> (&accs)[4],
+                                                  const Z<R> (&accr)[4], const BwdCoefs& cf, const BwdRbIn<R>& in) {
+    constexpr bool LAST = false;
+    const bool carry = j + 1 < k_used;
+    ZD abar = cf.abar_T;
+    if (!LAST) {
+        abar = abar - mk<double>(red[0], red[1]) - mk<double>(red[2], red[3]);
+        if (blockIdx.x == 0 && threadIdx.x == 0 && j >= 2) {
+            coef.gbar_tot[j] = cf.gbar_T - mk<double>(red[4], red[5]);
+            coef.bbar_tot[j] = cf.bbar_T - red[6];
+        }
+    }
+    const Z<R> ca = zcast<R>(abar);
+    const ZD alpha = cf.alpha;
+    const Z<R> alr = zcast<R>(alpha), alc = zcast<R>(cj(alpha)), abc = zcast<R>(cj(abar));
+    const Z<R> etac = zcast<R>(cf.etac);
+    const Z<R> gnc = zcast<R>(cf.gnc);
+    const R bn = (R)cf.bn;
+    double pv[kNvRB] = {0.0, 0.0, 0.0};
+    if (s < g.V) {
+        const R kap = (R)kappa;
+        Z<R> vbo[4], wbo[4], abo[4];
+        double d1 = 0.0, d2r = 0.0, d2i = 0.0;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            const R sg = sp < 2 ? R(1) : R(-1);
+            const Z<R> w_s = in.w[sp];
+            const Z<R> v_s = in.v[sp];
+            const Z<R> a_s = in.a[sp];
+            const Z<R> b_s = in.b[sp];
+            Z<R> vb = etac * in.e[sp] + ca * b_s;
+            Z<R> wb = abc * a_s;
+            Z<R> ab_s = ca * w_s;
+            if (!LAST) {
+                const Z<R> r_s = in.r[sp];
+                const Z<R> sb_s = in.sb[sp];
+                ab_s = ab_s + r_s;
+                vb = vb + sg * (r_s - kap * accr[sp]) - alc * r_s;
+                wb = wb + sg * (sb_s - kap * accs[sp]) - alr * sb_s;
+                if (carry) {
+                    vb = vb - gnc * in.rn[sp];
+                    wb = wb - bn * in.sn[sp];
+                }
+            }
+            vbo[sp] = vb;
+            wbo[sp] = wb;
+            abo[sp] = ab_s;
+            const ZD x1 = cjmul(zcast<double>(vb), zcast<double>(v_s));
+            const ZD x2 = cjmul(zcast<double>(wb), zcast<double>(w_s));
+            d1 += x1.re;
+            d2r += x2.re;
+            d2i += x2.im;
+        }
+        store1_nt(wk.f(slot, 4), g.ldv, a, s, vbo);
+        store1_nt(wk.f(slot, 5), g.ldv, a, s, wbo);
+        store1_nt(wk.ab(slot, j), g.ldv, a, s, abo);
+        pv[0] = d1;
+        pv[1] = d2r;
+        pv[2] = d2i;
+    }
+    wave_partials_at<kNvRB>(wk.p(slot, 0), pslot, pv);
+}
+
 template <typename R, bool LAST, int BLK>
 __device__ __forceinline__ void bwd_rb_finish(const Geom& g, double kappa, const Work<R>& wk, const Coef& coef,
                                               int slot, int j, int k_used, int pslot, int a, int s,
@@ -1269,7 +1388,7 @@ __device__ __forceinline__ void bwd_rb_finish(const Geom& g, double kappa, const
 // no residual adjoints: abar = alphabar w, vbar = |x| conj(c) eta + alphabar b,
 // wbar = conj(alphabar) a.
 template <typename R, bool LAST, int BLK>
-__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(1, BLK == kSites && !LAST ? 1 : 8)))
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(1, 8)))
 void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
                                                     Work<R> wk, SrcList L, Coef coef0, int j, int npart_in) {
     const int e = blockIdx.y, slot = L.slot[e];
@@ -1291,19 +1410,68 @@ void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
             const Z<R>* fs = wk.sb(slot, j);
             const Z<R>* fr = wk.f(slot, 6 + (j & 1));
             const Nbr n = neighbours(g, s);
-            if constexpr (BLK == kSites) {   // one wavefront per SIMD: two directions per round trip
-                hop_two_dirs_pair_eager<0, 1>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
-                mem_fence_compiler();
-                hop_two_dirs_pair_eager<2, 3>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
-            } else {
-                hop_all_pair<BLK>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
-            }
+            hop_all_pair<BLK>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
             mem_fence_compiler();
         }
         block_sum<kNvRA, BLK>(red);
     }
     bwd_rb_finish<R, LAST, BLK>(g, kappa, wk, coef, slot, j, L.k[e], BLK == kSites ? (int)blockIdx.x : sb, a, s,
                                 red, accs, accr, cf);
+}
+
+// Colour grid, not the last step: blocks of two wavefronts.  Wavefront 1 runs the
+// eight hops, two directions per memory round trip (up to 512 registers at one
+// wavefront per SIMD), and hands its sums over through LDS.  Wavefront 0 meanwhile
+// gathers the partial sums and loads the epilogue's nine own-site fields, so that
+// round trip overlaps the hops; after the one barrier it runs the epilogue.  Every
+// value receives the same operations in the same order as in the one-wavefront form.
+template <typename R>
+__global__ __launch_bounds__(kHBlock) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_bwd_rb_cg(const Z<R>* __restrict__ U, Geom g, double kappa, double emu, Work<R> wk, SrcList L, Coef coef0,
+                 int j, int npart_in) {
+    const int e = blockIdx.y, slot = L.slot[e];
+    const int sb = sten_block<kHBlock>(g);
+    const int a = sten_colour<kHBlock>();
+    const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kSites);
+    const int l = threadIdx.x % kSites;
+    const int s = sb * kSites + l;
+    __shared__ Z<R> xs[4][kSites], xr[4][kSites];
+    if (half == 1) {
+        Z<R> accs[4], accr[4];   // field A = sbar_j at +mu, field B = rbar_j at -mu
+        zero1(accs);
+        zero1(accr);
+        if (s < g.V) {
+            const Z<R>* fs = wk.sb(slot, j);
+            const Z<R>* fr = wk.f(slot, 6 + (j & 1));
+            const Nbr n = neighbours(g, s);
+            hop_two_dirs_pair_eager<0, 1>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
+            mem_fence_compiler();
+            hop_two_dirs_pair_eager<2, 3>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
+            mem_fence_compiler();
+        }
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            xs[sp][l] = accs[sp];
+            xr[sp][l] = accr[sp];
+        }
+        __syncthreads();
+        return;
+    }
+    const Coef coef = coef0.at(slot);
+    const BwdCoefs cf = bwd_coefs(coef, j, j + 1 < L.k[e]);
+    double red[kNvRA];
+    gather_partials<kNvRA, kSites>(wk.p(slot, 1), npart_in, red);
+    BwdRbIn<R> in;
+    if (s < g.V) bwd_rb_load<R>(g, wk, slot, j, L.k[e], a, s, in);
+    wave_block_sum<kNvRA>(red);
+    __syncthreads();
+    Z<R> accs[4], accr[4];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+        accs[sp] = xs[sp][l];
+        accr[sp] = xr[sp][l];
+    }
+    bwd_rb_finish_pre<R>(g, kappa, wk, coef, slot, j, L.k[e], (int)blockIdx.x, a, s, red, accs, accr, cf, in);
 }
 
 // Colour split, not the last step: NS entries per workgroup sharing the link loads.
@@ -1364,7 +1532,7 @@ void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const 
     else if (last)
         timed_launch(k_bwd_rb<R, true, kCBlock>, grid, dim3(kCBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
     else if (cg)
-        timed_launch(k_bwd_rb<R, false, kSites>, grid, dim3(kSites), st, t, U, g, kappa, emu, wk, L, coef, j, np);
+        timed_launch(k_bwd_rb_cg<R>, grid, dim3(kHBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
     else if (ns == 4)
         timed_launch(k_bwd_rb_ms<R, 4>, dim3(g.nwg, (L.n + 3) / 4), dim3(kCBlock), st, t, U, g, kappa, emu, wk, L,
                      coef, j, np);
