@@ -850,7 +850,13 @@ void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
     double red[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
     if (!replay) gather_partials<kNvRecur, BLK>(wk.p(slot, 1), npart_in, red);
     const int sb = sten_block<BLK>(g);
-    if (!replay && block_flag(coef.status)) return;
+    // the stop flag goes out with the partial sums too, and is tested only after the
+    // hops (a stopped entry's hops are discarded): thread 0's early read reaches the
+    // block through LDS across combine_halves' barrier, so the test is uniform even
+    // if another block of this launch sets the flag meanwhile
+    __shared__ int stop_s;
+    int stop0 = 0;
+    if (!replay && threadIdx.x == 0) stop0 = *(volatile const int*)coef.status;
     const int a = sten_colour<BLK>();
     const int s = sb * kSites + threadIdx.x % kSites;
     Z<R> acca[4], accb[4];
@@ -860,7 +866,9 @@ void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
         hop_half_pair(acca, accb, U, rin, sin, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu), half);
         mem_fence_compiler();
     }
+    if (threadIdx.x == 0) stop_s = stop0;
     combine_halves(acca, accb, half);
+    if (stop_s) return;
     if (!replay) block_sum<kNvRecur, BLK>(red);
     // wavefront 1 has handed over its sums: no site of its own in the epilogue
     fwd_pair_finish<R, BLK>(g, kappa, wk, coef, slot, j, (int)blockIdx.x, a, half ? g.V : s, red, acca, accb, rin,
