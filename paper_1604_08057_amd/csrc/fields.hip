@@ -1245,8 +1245,8 @@ __device__ __forceinline__ void bwd_rb_load(const Geom& g, const Work<R>& wk, in
 }
 
 // The epilogue of bwd_rb_finish (not the last step) on operands loaded beforehand, for
-// the two-wavefront colour-grid kernel: its wavefront 0 runs it alone, so the sums
-// are formed without barriers.
+// the colour-grid kernel: its wavefront 0 runs it alone, so the sums are formed
+// without barriers.
 template <typename R>
 __device__ __forceinline__ void bwd_rb_finish_pre(const Geom& g, double kappa, const Work<R>& wk, const Coef& coef,
                                                   int slot, int j, int k_used, int pslot, int a, int s,
@@ -1427,24 +1427,25 @@ void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
                                 red, accs, accr, cf);
 }
 
-// Colour grid, not the last step: blocks of two wavefronts.  Wavefront 1 runs the
-// eight hops, two directions per memory round trip (up to 512 registers at one
-// wavefront per SIMD), and hands its sums over through LDS.  Wavefront 0 meanwhile
-// gathers the partial sums and loads the epilogue's nine own-site fields, so that
-// round trip overlaps the hops; after the one barrier it runs the epilogue.  Every
-// value receives the same operations in the same order as in the one-wavefront form.
+// Colour grid, not the last step: blocks of three wavefronts.  Wavefronts 1 and 2
+// run the hops of directions 0, 1 and 2, 3, each pair in one memory round trip (up
+// to 512 registers at one wavefront per SIMD), and hand their sums over through
+// LDS.  Wavefront 0 meanwhile gathers the partial sums and loads the epilogue's nine
+// own-site fields, so that round trip overlaps the hops; after the one barrier it
+// adds the two halves (directions 0, 1 first) and runs the epilogue.
+constexpr int kRBlock = 3 * kSites;
 template <typename R>
-__global__ __launch_bounds__(kHBlock) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_bwd_rb_cg(const Z<R>* __restrict__ U, Geom g, double kappa, double emu, Work<R> wk, SrcList L, Coef coef0,
                  int j, int npart_in) {
     const int e = blockIdx.y, slot = L.slot[e];
-    const int sb = sten_block<kHBlock>(g);
-    const int a = sten_colour<kHBlock>();
-    const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kSites);
+    const int ncb = gridDim.x / 3;   // colour-major grid, as sten_block / sten_colour for the colour grid
+    const int sb = blockIdx.x % ncb, a = blockIdx.x / ncb;
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kSites);
     const int l = threadIdx.x % kSites;
     const int s = sb * kSites + l;
-    __shared__ Z<R> xs[4][kSites], xr[4][kSites];
-    if (half == 1) {
+    __shared__ Z<R> xs[2][4][kSites], xr[2][4][kSites];
+    if (wv > 0) {
         Z<R> accs[4], accr[4];   // field A = sbar_j at +mu, field B = rbar_j at -mu
         zero1(accs);
         zero1(accr);
@@ -1452,15 +1453,16 @@ void k_bwd_rb_cg(const Z<R>* __restrict__ U, Geom g, double kappa, double emu, W
             const Z<R>* fs = wk.sb(slot, j);
             const Z<R>* fr = wk.f(slot, 6 + (j & 1));
             const Nbr n = neighbours(g, s);
-            hop_two_dirs_pair_eager<0, 1>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
-            mem_fence_compiler();
-            hop_two_dirs_pair_eager<2, 3>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
+            if (wv == 1)
+                hop_two_dirs_pair_eager<0, 1>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
+            else
+                hop_two_dirs_pair_eager<2, 3>(accs, accr, U, fs, fr, g, s, a, n, (R)emu, (R)(1.0 / emu));
             mem_fence_compiler();
         }
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp) {
-            xs[sp][l] = accs[sp];
-            xr[sp][l] = accr[sp];
+            xs[wv - 1][sp][l] = accs[sp];
+            xr[wv - 1][sp][l] = accr[sp];
         }
         __syncthreads();
         return;
@@ -1476,8 +1478,8 @@ void k_bwd_rb_cg(const Z<R>* __restrict__ U, Geom g, double kappa, double emu, W
     Z<R> accs[4], accr[4];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp) {
-        accs[sp] = xs[sp][l];
-        accr[sp] = xr[sp][l];
+        accs[sp] = xs[0][sp][l] + xs[1][sp][l];
+        accr[sp] = xr[0][sp][l] + xr[1][sp][l];
     }
     bwd_rb_finish_pre<R>(g, kappa, wk, coef, slot, j, L.k[e], (int)blockIdx.x, a, s, red, accs, accr, cf, in);
 }
@@ -1540,7 +1542,7 @@ void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const 
     else if (last)
         timed_launch(k_bwd_rb<R, true, kCBlock>, grid, dim3(kCBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
     else if (cg)
-        timed_launch(k_bwd_rb_cg<R>, grid, dim3(kHBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
+        timed_launch(k_bwd_rb_cg<R>, grid, dim3(kRBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
     else if (ns == 4)
         timed_launch(k_bwd_rb_ms<R, 4>, dim3(g.nwg, (L.n + 3) / 4), dim3(kCBlock), st, t, U, g, kappa, emu, wk, L,
                      coef, j, np);
