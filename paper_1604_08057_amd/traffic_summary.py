@@ -61,7 +61,7 @@ def main(fetch_csv: str, write_csv: str, out: str, volume: int = 4096):
     ncol = 3 * (((V + 63) // 64 + 7) // 8 * 8) * 64    # colour-grid threads at this volume
     npt = (V + 255) // 256 * 256 * 12                  # pointwise kernels
     rows = {"k_fwd_pair<double, 128>": (str(2 * ncol), V * (6 * 12 + 36) * 16),
-            "k_bwd_rb_cg<double>": (str(2 * ncol), V * (12 * 12 + 36) * 16),
+            "k_bwd_rb_cg<double>": (str(3 * ncol), V * (12 * 12 + 36) * 16),
             "k_recur<double>": (str(npt), V * 8 * 12 * 16),
             "k_bwd_ra<double>": (str(npt), V * 10 * 12 * 16)}
     lines = ["# HBM traffic per dispatch from rocprofv3 counters, 8^4 workload (V=4096, k=200, FP64)",
