@@ -13,7 +13,7 @@ constexpr int kWave = 64;      // CDNA wavefront
 constexpr int kBlock = 128;    // threads per block of the simple per-site kernels
 constexpr int kSites = 64;     // sites per wavefront (and site block) of the colour-layout stencil kernels
 constexpr int kCBlock = 3 * kSites;   // colour split: one wavefront per colour
-constexpr int kHBlock = 2 * kSites;   // colour grid, forward pair: the directions split over two wavefronts
+constexpr int kRBlock = 3 * kSites;   // colour grid, pair kernels: two hop wavefronts and an epilogue wavefront
 constexpr int kPBlock = 256;   // pointwise kernels: sites per block, grid.y = 12 planes
 
 constexpr int kXcd = 8;        // accelerator complex dies; workgroups go to them round robin

@@ -296,8 +296,8 @@ __device__ __forceinline__ void hop_two_dirs_pair_eager(Z<R> (&acca)[4], Z<R> (&
     hop1<NU1, -1>(accb, ub1, pbb1, up1);
 }
 
-// Colour grid with two wavefronts per block: wavefront h takes directions 2h and
-// 2h + 1, all their operands in one round trip.
+// Colour-grid pair kernels: hop wavefront h (0 or 1) takes directions 2h and 2h + 1,
+// all their operands in one round trip.
 template <typename R>
 __device__ __forceinline__ void hop_half_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
                                               const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
@@ -306,27 +306,6 @@ __device__ __forceinline__ void hop_half_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], 
         hop_two_dirs_pair_eager<0, 1>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
     else
         hop_two_dirs_pair_eager<2, 3>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
-}
-
-// Adds wavefront 1's sums to wavefront 0's (through LDS, one barrier): afterwards
-// wavefront 0 holds the full sums (directions 0, 1 then 2, 3).
-template <typename R>
-__device__ __forceinline__ void combine_halves(Z<R> (&acca)[4], Z<R> (&accb)[4], int half) {
-    __shared__ Z<R> xa[4][kSites], xb[4][kSites];
-    const int l = threadIdx.x % kSites;
-    if (half == 1)
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp) {
-            xa[sp][l] = acca[sp];
-            xb[sp][l] = accb[sp];
-        }
-    __syncthreads();
-    if (half == 0)
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp) {
-            acca[sp] = acca[sp] + xa[sp][l];
-            accb[sp] = accb[sp] + xb[sp][l];
-        }
 }
 
 // The colour-split pair hops for NS entries of a batch at once: every link row is
@@ -730,6 +709,21 @@ void launch_sources_to_soa(const ZD* canon, int which, int g5, const Work<R>& wk
 // apply a = H(mu) v_j and b = H(-mu) w_j = H^dag w_j with shared link loads, and
 // emit per-block partial sums of alpha_j = w_j^H a, |a|^2 and eta^H v_j.  At
 // j >= 2 the step first decides breakdown from the previous omega and norms.
+// block_sum over a one-wavefront block without its barriers (0 + the wavefront's
+// sum, as block_sum forms it), for a wavefront whose partner has left the block.
+template <int NV>
+__device__ __forceinline__ void wave_block_sum(double (&v)[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = 0.0 + wave_sum(v[i]);
+}
+template <int NV>
+__device__ __forceinline__ void wave_partials_at(double* __restrict__ part, int slot, double (&v)[NV]) {
+    wave_block_sum<NV>(v);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) part[slot * NV + i] = v[i];
+}
+
 // Epilogue of step j for one entry, after the hops: breakdown decisions from the
 // block-summed previous (omega, |r|^2, |s|^2) in `red`, the coefficient records,
 // the stores of v_j, w_j, a_j, b_j and the step's partial sums.  Every branch
@@ -825,54 +819,158 @@ __device__ __forceinline__ void fwd_pair_finish(const Geom& g, double kappa, con
     if (!replay) write_partials_at<kNvPair, BLK>(wk.p(slot, 0), pslot, pv);
 }
 
+// fwd_pair_finish on own-site operands loaded beforehand (r0 = r, s0 = s, e = eta at
+// colour a), for the colour-grid kernel: its wavefront 0 runs it alone, so the sums
+// are formed without barriers.
+template <typename R>
+__device__ __forceinline__ void fwd_pair_finish_pre(const Geom& g, double kappa, const Work<R>& wk, const Coef& coef,
+                                                    int slot, int j, int pslot, int a, int s,
+                                                    const double (&red)[kNvRecur], const Z<R> (&acca)[4],
+                                                    const Z<R> (&accb)[4], const Z<R> (&r0)[4],
+                                                    const Z<R> (&s0)[4], const Z<R> (&e)[4], int has_eta,
+                                                    int replay) {
+    const int first = j == 1;
+    double beta;
+    ZD gam;
+    if (replay) {
+        beta = coef.beta[j];
+        gam = coef.gamma[j];
+    } else {
+    const ZD om = mk<double>(red[0], red[1]);
+    const double rn2 = red[2], sn2 = red[3];
+    const double aom = std::sqrt(norm2(om));
+    if (first && !(rn2 > 0.0)) {   // zero source: empty Krylov space, nothing to do
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            coef.status[1] = 0;
+            coef.status[2] = 1;
+            coef.status[3] = 1;
+            coef.misc[0] = 0.0;
+            *(volatile int*)coef.status = 1;
+        }
+        return;
+    }
+    if (!first) {
+        const double an2 = coef.anorm2[j - 1];
+        const bool lucky = rn2 <= kTauLucky * kTauLucky * an2;
+        const bool finite = std::isfinite(om.re) && std::isfinite(om.im);
+        const bool serious = !lucky && (!finite || aom <= kTauSerious * std::sqrt(rn2 * sn2));
+        if (lucky || serious) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                coef.status[1] = j - 1;
+                coef.status[2] = lucky ? 1 : 2;
+                coef.status[3] = j;
+                *(volatile int*)coef.status = 1;
+            }
+            return;
+        }
+    }
+    beta = std::sqrt(aom);
+    gam = (1.0 / beta) * om;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        coef.beta[j] = beta;
+        coef.gamma[j] = gam;
+        if (first) coef.misc[0] = beta;
+    }
+    }
+    const R ib = (R)(1.0 / beta);
+    const Z<R> icg = zcast<R>(zdiv(mk<double>(1.0, 0.0), cj(gam)));
+    double pv[kNvPair] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (s < g.V) {
+        Z<R> v[4], w[4], av[4], bv[4];
+        const R kap = (R)kappa;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            const R sg = sp < 2 ? R(1) : R(-1);
+            v[sp] = ib * r0[sp];
+            w[sp] = icg * s0[sp];
+            av[sp] = (sg * ib) * (r0[sp] - kap * acca[sp]);
+            bv[sp] = icg * (sg * (s0[sp] - kap * accb[sp]));
+            const ZD wd = zcast<double>(w[sp]), ad = zcast<double>(av[sp]);
+            const ZD wa = cjmul(wd, ad);
+            pv[0] += wa.re;
+            pv[1] += wa.im;
+            pv[2] += norm2(ad);
+        }
+        store1_nt(wk.v(slot, j), g.ldv, a, s, v);
+        store1_nt(wk.w(slot, j), g.ldv, a, s, w);
+        store1_nt(wk.a(slot, j), g.ldv, a, s, av);
+        store1_nt(wk.b(slot, j), g.ldv, a, s, bv);
+        if (!replay && has_eta) {
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+                const ZD ev = cjmul(zcast<double>(e[sp]), zcast<double>(v[sp]));
+                pv[3] += ev.re;
+                pv[4] += ev.im;
+            }
+        }
+    }
+    if (!replay) wave_partials_at<kNvPair>(wk.p(slot, 0), pslot, pv);
+}
+
 // Step j: normalise the previous residuals (v_j = r/beta_j, w_j = s/conj(gamma_j)),
 // apply a = H(mu) v_j and b = H(-mu) w_j = H^dag w_j with shared link loads, and
 // emit per-block partial sums of alpha_j = w_j^H a, |a|^2 and eta^H v_j.  At
 // j >= 2 the step first decides breakdown from the previous omega and norms.
-// Colour grid: one entry per workgroup (grid.y = entry), two wavefronts per
-// workgroup, each with two of the four directions (half the chain of dependent
-// memory round trips); wavefront 0 adds the halves and runs the epilogue.
-template <typename R, int BLK>
-__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
-                                                  Work<R> wk, SrcList L, Coef coef0, int j, int npart_in,
-                                                  int has_eta, int replay) {
-    static_assert(BLK == kHBlock, "colour-grid kernel: two wavefronts share the directions");
-    const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kSites);
+// Colour grid: one entry per workgroup (grid.y = entry), three wavefronts per
+// workgroup (kRBlock).  Wavefronts 1 and 2 apply directions 0, 1 and 2, 3 (one
+// memory round trip each) and hand their sums over through LDS.  Wavefront 0
+// meanwhile gathers the previous step's partial sums, reads the stop flag and loads
+// the epilogue's own-site operands; after the one barrier it adds the halves
+// (directions 0, 1 first) and runs the epilogue.  The hops do not depend on the sums
+// or the flag (normalisation and breakdown act in the epilogue): a stopped entry's
+// hops are discarded.
+template <typename R>
+__global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu, Work<R> wk, SrcList L, Coef coef0,
+                int j, int npart_in, int has_eta, int replay) {
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kSites);
     const int slot = L.slot[blockIdx.y];
-    const Coef coef = coef0.at(slot);
     const int first = j == 1;
     const Z<R>* rin = wk.f(slot, first ? 0 : 2);
     const Z<R>* sin = wk.f(slot, first ? 0 : 3);
-    // the partial sums' loads share a round trip with the flag read; the hops do not
-    // depend on the sums (normalisation and breakdown act in the epilogue), so they
-    // run before the sums are combined, and a breakdown step discards them
-    double red[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
-    if (!replay) gather_partials<kNvRecur, BLK>(wk.p(slot, 1), npart_in, red);
-    const int sb = sten_block<BLK>(g);
-    // the stop flag goes out with the partial sums too, and is tested only after the
-    // hops (a stopped entry's hops are discarded): thread 0's early read reaches the
-    // block through LDS across combine_halves' barrier, so the test is uniform even
-    // if another block of this launch sets the flag meanwhile
-    __shared__ int stop_s;
-    int stop0 = 0;
-    if (!replay && threadIdx.x == 0) stop0 = *(volatile const int*)coef.status;
-    const int a = sten_colour<BLK>();
-    const int s = sb * kSites + threadIdx.x % kSites;
-    Z<R> acca[4], accb[4];
-    zero1(acca);
-    zero1(accb);
-    if (s < g.V) {
-        hop_half_pair(acca, accb, U, rin, sin, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu), half);
-        mem_fence_compiler();
+    const int ncb = gridDim.x / 3;   // colour-major grid, as sten_block / sten_colour for the colour grid
+    const int sb = blockIdx.x % ncb, a = blockIdx.x / ncb;
+    const int l = threadIdx.x % kSites;
+    const int s = sb * kSites + l;
+    __shared__ Z<R> xa[2][4][kSites], xb[2][4][kSites];
+    if (wv > 0) {
+        Z<R> acca[4], accb[4];
+        zero1(acca);
+        zero1(accb);
+        if (s < g.V) {
+            hop_half_pair(acca, accb, U, rin, sin, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu), wv - 1);
+            mem_fence_compiler();
+        }
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            xa[wv - 1][sp][l] = acca[sp];
+            xb[wv - 1][sp][l] = accb[sp];
+        }
+        __syncthreads();
+        return;
     }
-    if (threadIdx.x == 0) stop_s = stop0;
-    combine_halves(acca, accb, half);
-    if (stop_s) return;
-    if (!replay) block_sum<kNvRecur, BLK>(red);
-    // wavefront 1 has handed over its sums: no site of its own in the epilogue
-    fwd_pair_finish<R, BLK>(g, kappa, wk, coef, slot, j, (int)blockIdx.x, a, half ? g.V : s, red, acca, accb, rin,
-                            sin, has_eta, replay);
+    const Coef coef = coef0.at(slot);
+    double red[kNvRecur] = {0.0, 0.0, 0.0, 0.0};
+    if (!replay) gather_partials<kNvRecur, kSites>(wk.p(slot, 1), npart_in, red);
+    // one load for the whole wavefront: every lane sees the same flag
+    const int stop = replay ? 0 : __builtin_amdgcn_readfirstlane(*(volatile const int*)coef.status);
+    Z<R> r0[4], s0[4], e[4];
+    if (s < g.V) {
+        load1(r0, rin, g.ldv, a, s);
+        load1(s0, sin, g.ldv, a, s);
+        if (!replay && has_eta) load1(e, wk.f(slot, 1), g.ldv, a, s);
+    }
+    if (!replay) wave_block_sum<kNvRecur>(red);
+    __syncthreads();
+    if (stop) return;
+    Z<R> acca[4], accb[4];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+        acca[sp] = xa[0][sp][l] + xa[1][sp][l];
+        accb[sp] = xb[0][sp][l] + xb[1][sp][l];
+    }
+    fwd_pair_finish_pre<R>(g, kappa, wk, coef, slot, j, (int)blockIdx.x, a, s, red, acca, accb, r0, s0, e, has_eta,
+                           replay);
 }
 
 // Colour split: NS entries per workgroup (entries NS*blockIdx.y + q), which share
@@ -936,7 +1034,7 @@ void fwd_pair_launch(const Z<R>* U, const Geom& g, double kappa, double mu, cons
     const int npart_in = j == 1 ? grid_for(g.V) : np_point(g.V);
     const double emu = std::exp(mu);
     if (colour_grid(g.V)) {
-        timed_launch(k_fwd_pair<R, kHBlock>, dim3(np_colour(g.V), L.n), dim3(kHBlock), st, t, U, g, kappa, emu, wk,
+        timed_launch(k_fwd_pair<R>, dim3(np_colour(g.V), L.n), dim3(kRBlock), st, t, U, g, kappa, emu, wk,
                      L, coef, j, npart_in, has_eta, replay);
         return;
     }
@@ -1194,21 +1292,6 @@ __device__ __forceinline__ BwdCoefs bwd_coefs(const Coef& coef, int j, bool carr
 // Epilogue of reverse step j for one entry, after the hops: the coefficient
 // adjoints from the block-summed partials `red` (not LAST), the adjoint fields'
 // stores and the step's partial sums.
-// block_sum over a one-wavefront block without its barriers (0 + the wavefront's
-// sum, as block_sum forms it), for a wavefront whose partner has left the block.
-template <int NV>
-__device__ __forceinline__ void wave_block_sum(double (&v)[NV]) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = 0.0 + wave_sum(v[i]);
-}
-template <int NV>
-__device__ __forceinline__ void wave_partials_at(double* __restrict__ part, int slot, double (&v)[NV]) {
-    wave_block_sum<NV>(v);
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int i = 0; i < NV; ++i) part[slot * NV + i] = v[i];
-}
-
 // The epilogue's own-site operands (colour a, four spins), loaded by bwd_rb_load.
 template <typename R>
 struct BwdRbIn {
@@ -1427,13 +1510,12 @@ void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
                                 red, accs, accr, cf);
 }
 
-// Colour grid, not the last step: blocks of three wavefronts.  Wavefronts 1 and 2
+// Colour grid, not the last step: blocks of three wavefronts (kRBlock).  Wavefronts 1 and 2
 // run the hops of directions 0, 1 and 2, 3, each pair in one memory round trip (up
 // to 512 registers at one wavefront per SIMD), and hand their sums over through
 // LDS.  Wavefront 0 meanwhile gathers the partial sums and loads the epilogue's nine
 // own-site fields, so that round trip overlaps the hops; after the one barrier it
 // adds the two halves (directions 0, 1 first) and runs the epilogue.
-constexpr int kRBlock = 3 * kSites;
 template <typename R>
 __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_bwd_rb_cg(const Z<R>* __restrict__ U, Geom g, double kappa, double emu, Work<R> wk, SrcList L, Coef coef0,
