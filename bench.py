@@ -42,7 +42,7 @@ sys.path.insert(0, ROOT)
 METRIC = "sgn(H)ψ+dU-derivative sources/s, mixed vs FP64 @≤1e-6 rel; stencil HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {0: "k_fwd_pair<double> (fused Lanczos stencil pair, colour grid, hops on two wavefronts, epilogue operands on a third)",
-                1: "k_bwd_rb_cg<double> (reverse-mode stencil pair, colour grid, hops and epilogue loads on two wavefronts)"}
+                1: "k_bwd_rb_cg<double> (reverse-mode stencil pair, colour grid, hops on two wavefronts, epilogue operands on a third)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stencil_pair_8x8x8x8.txt")
 # live kernel timing samples every 16th launch of a class: an event pair adds ~5 us
 # of dispatch latency, which on every launch would slow the timed step by ~25%
