@@ -461,6 +461,27 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
     __syncthreads();
 }
 
+// block_sum for the last use of its LDS slots in a kernel (no other call with the
+// same NV follows): the same sums, without the barrier that guards the slots' reuse.
+template <int NV, int BLK>
+__device__ __forceinline__ void block_sum_last(double (&v)[NV]) {
+    __shared__ double red[BLK / kWave][NV];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[wave][i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < BLK / kWave; ++w) s += red[w][i];
+        v[i] = s;
+    }
+}
+
 // Sum of per-block partials part[b*NV + i], b < nparts, in a fixed order; every
 // block that calls this gets bit-identical results.  gather_partials is the first
 // half (each thread's strided share, no barrier), so that a kernel can issue these
@@ -486,6 +507,15 @@ __device__ __forceinline__ void write_partials(double* __restrict__ part, double
     if (threadIdx.x == 0)
 #pragma unroll
         for (int i = 0; i < NV; ++i) part[blockIdx.x * NV + i] = v[i];
+}
+
+// write_partials_at with block_sum_last (the kernel's last sum with this NV).
+template <int NV, int BLK>
+__device__ __forceinline__ void write_partials_at_last(double* __restrict__ part, int slot, double (&v)[NV]) {
+    block_sum_last<NV, BLK>(v);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) part[slot * NV + i] = v[i];
 }
 
 // Same with the partial slot given explicitly (2-D grids).

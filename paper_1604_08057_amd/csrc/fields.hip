@@ -17,16 +17,6 @@ void timed_launch(K kernel, dim3 grid, dim3 block, hipStream_t st, Timing t, Arg
     else hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
 }
 
-// Block-uniform read of a device flag written by other blocks or launches.
-__device__ __forceinline__ int block_flag(const int* p) {
-    __shared__ int f;
-    if (threadIdx.x == 0) f = *(volatile const int*)p;
-    __syncthreads();
-    const int r = f;
-    __syncthreads();
-    return r;
-}
-
 // Compiler barrier for memory operations: keeps the epilogue's own-site loads from
 // being hoisted above the hopping loop, where they would stay live (and spill).
 __device__ __forceinline__ void mem_fence_compiler() { asm volatile("" ::: "memory"); }
@@ -1092,8 +1082,8 @@ __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L
     const size_t i = (size_t)blockIdx.y * g.ldv + s;
     const bool has_prev = j > 1, live = s < g.V && j < L.k[e];
     // the site's operands, the step's scalars and the partial sums first: their
-    // loads share one round trip with the flag read (whose barrier the compiler may
-    // not move them across)
+    // loads share one round trip with the flag read (a compiler fence keeps them
+    // ahead of the flag test)
     const Z<R> gj = has_prev ? zcast<R>(coef.gamma[j]) : mk<R>(0, 0);
     const R bj = has_prev ? (R)coef.beta[j] : R(0);
     Z<R> a_i = mk<R>(0, 0), b_i = a_i, v_i = a_i, w_i = a_i, vp_i = a_i, wp_i = a_i;
@@ -1109,12 +1099,15 @@ __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L
     }
     double red[kNvPair] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (!replay) gather_partials<kNvPair, kPBlock>(wk.p(slot, 0), npart_in, red);
-    if (!replay && block_flag(coef.status)) return;
+    mem_fence_compiler();
+    // the flag is written by the forward pair only, never during this launch, so a
+    // read per wavefront is uniform over the block
+    if (!replay && __builtin_amdgcn_readfirstlane(*(volatile const int*)coef.status)) return;
     ZD alpha;
     if (replay) {   // regeneration: alpha_j as recorded, nothing written but r and s
         alpha = coef.alpha[j];
     } else {
-        block_sum<kNvPair, kPBlock>(red);
+        block_sum_last<kNvPair, kPBlock>(red);
         alpha = mk<double>(red[0], red[1]);
         if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
             coef.alpha[j] = alpha;
@@ -1136,7 +1129,7 @@ __global__ __launch_bounds__(kPBlock) void k_recur(Geom g, Work<R> wk, SrcList L
         pv[2] = rr * rr + ri * ri;
         pv[3] = qr * qr + qi * qi;
     }
-    if (!replay) write_partials_at<kNvRecur, kPBlock>(wk.p(slot, 1), blockIdx.y * gridDim.x + blockIdx.x, pv);
+    if (!replay) write_partials_at_last<kNvRecur, kPBlock>(wk.p(slot, 1), blockIdx.y * gridDim.x + blockIdx.x, pv);
 }
 
 template <typename R>
@@ -1222,7 +1215,8 @@ __global__ __launch_bounds__(kPBlock) void k_bwd_ra(Geom g, Work<R> wk, SrcList 
     const double bbar_n = coef.bbar_tot[j + 1];
     const ZD gbar_n = coef.gbar_tot[j + 1];
     double red[kNvRB];
-    reduce_partials<kNvRB, kPBlock>(wk.p(slot, 0), npart_in, red);   // its loads join the operands'
+    gather_partials<kNvRB, kPBlock>(wk.p(slot, 0), npart_in, red);   // its loads join the operands'
+    block_sum_last<kNvRB, kPBlock>(red);
     const double D1 = red[0];
     const ZD D2 = mk<double>(red[1], red[2]);
     const ZD om = beta * gam;
@@ -1253,7 +1247,7 @@ __global__ __launch_bounds__(kPBlock) void k_bwd_ra(Geom g, Work<R> wk, SrcList 
             pv[6] = p4.re; pv[7] = p4.im;
         }
     }
-    write_partials_at<kNvRA, kPBlock>(wk.p(slot, 1), blockIdx.y * gridDim.x + blockIdx.x, pv);
+    write_partials_at_last<kNvRA, kPBlock>(wk.p(slot, 1), blockIdx.y * gridDim.x + blockIdx.x, pv);
 }
 
 template <typename R>
