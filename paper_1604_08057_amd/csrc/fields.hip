@@ -202,51 +202,21 @@ __device__ __forceinline__ void hop_dir1_eager(Z<R> (&acc)[4], const Z<R>* __res
     hop1<NU, -1>(acc, ub, pb, cb);
 }
 
-template <int NU, typename R>
-__device__ __forceinline__ void hop_dir_pair1_eager(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
-                                                    const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
-                                                    const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
-    const R up = (NU == 3) ? ep : R(1), dn = (NU == 3) ? em : R(1);
-    Z<R> uf[3], ub[3];
-    Spinor<R> paf, pbf, pab, pbb;
-    load_row(uf, U, g.ldv, NU, a, s);
-    load_spinor(paf, fa, g.ldv, n.fwd[NU]);
-    load_spinor(pbf, fb, g.ldv, n.fwd[NU]);
-    load_col_conj(ub, U, g.ldv, NU, a, n.bwd[NU]);
-    load_spinor(pab, fa, g.ldv, n.bwd[NU]);
-    load_spinor(pbb, fb, g.ldv, n.bwd[NU]);
-    mem_fence_compiler();
-    hop1<NU, +1>(acca, uf, paf, up);
-    hop1<NU, +1>(accb, uf, pbf, dn);
-    hop1<NU, -1>(acca, ub, pab, dn);
-    hop1<NU, -1>(accb, ub, pbb, up);
-}
-
 // All eight hops of two fields (colour a) sharing the link rows (A at +mu, B at
-// -mu), a rolled loop over a wavefront-uniform switch.  Colour split (several
-// wavefronts per SIMD): one operand's loads in flight at a time, few registers.
-// Colour grid (small lattices, where a wavefront has its SIMD to itself): a whole
-// direction's loads in flight at a time.
+// -mu), a rolled loop over a wavefront-uniform switch: the colour split, with
+// several wavefronts per SIMD, so one operand's loads in flight at a time and few
+// registers.  (The colour grid's pair kernels use hop_two_dirs_pair_eager.)
 template <int BLK, typename R>
 __device__ __forceinline__ void hop_all_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
                                              const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
                                              const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
 #pragma unroll 1
     for (int nu = 0; nu < 4; ++nu) {
-        if constexpr (BLK == kSites) {
-            switch (nu) {
-                case 0: hop_dir_pair1_eager<0>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
-                case 1: hop_dir_pair1_eager<1>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
-                case 2: hop_dir_pair1_eager<2>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
-                default: hop_dir_pair1_eager<3>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
-            }
-        } else {
-            switch (nu) {
-                case 0: hop_dir_pair1<0>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
-                case 1: hop_dir_pair1<1>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
-                case 2: hop_dir_pair1<2>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
-                default: hop_dir_pair1<3>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
-            }
+        switch (nu) {
+            case 0: hop_dir_pair1<0>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
+            case 1: hop_dir_pair1<1>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
+            case 2: hop_dir_pair1<2>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
+            default: hop_dir_pair1<3>(acca, accb, U, fa, fb, g, s, a, n, ep, em); break;
         }
     }
 }
@@ -1712,24 +1682,24 @@ __device__ __forceinline__ double boundary_sign(const Geom& g, int nu, int s, in
 
 __global__ __launch_bounds__(kBlock) void k_force_reduce(Geom g, const ZD* __restrict__ gpart, int nchunk, SrcList L,
                                                          int antiperiodic, ZD* __restrict__ dU) {
+    // one thread per (site, direction, colour entry): the chunks' loads all go out at
+    // once and are summed in chunk order
     const int s = blockIdx.x * kBlock + threadIdx.x;
-    const int nu = blockIdx.y, e = blockIdx.z, slot = L.slot[e];
+    const int nu = blockIdx.y / 9, ab = blockIdx.y % 9, e = blockIdx.z, slot = L.slot[e];
     if (s >= g.V) return;
     // gradient with respect to the caller's link: undo the folded boundary sign
     const double sign = boundary_sign(g, nu, s, antiperiodic);
-    const ZD* gp = gpart + (size_t)slot * nchunk * 36 * g.ldv;
+    const ZD* gp = gpart + (size_t)slot * nchunk * 36 * g.ldv + (size_t)(nu * 9 + ab) * g.ldv + s;
     ZD* out = dU + (size_t)L.src[e] * 36 * g.V;
-#pragma unroll
-    for (int ab = 0; ab < 9; ++ab) {
-        ZD acc = mk<double>(0, 0);
-        for (int c = 0; c < nchunk; ++c) acc = acc + gp[(size_t)c * 36 * g.ldv + (size_t)(nu * 9 + ab) * g.ldv + s];
-        out[((size_t)nu * g.V + s) * 9 + ab] = sign * acc;
-    }
+    ZD acc = mk<double>(0, 0);
+#pragma unroll 16
+    for (int c = 0; c < nchunk; ++c) acc = acc + gp[(size_t)c * 36 * g.ldv];
+    out[((size_t)nu * g.V + s) * 9 + ab] = sign * acc;
 }
 
 void launch_force_reduce(const Geom& g, const ZD* gpart, int nchunk, const SrcList& L, int antiperiodic, ZD* dU,
                          hipStream_t st) {
-    hipLaunchKernelGGL(k_force_reduce, dim3(grid_for(g.V), 4, L.n), dim3(kBlock), 0, st, g, gpart, nchunk, L,
+    hipLaunchKernelGGL(k_force_reduce, dim3(grid_for(g.V), 36, L.n), dim3(kBlock), 0, st, g, gpart, nchunk, L,
                        antiperiodic, dU);
 }
 
