@@ -754,8 +754,12 @@ __global__ __launch_bounds__(kDB) void k_tridiag_inv(DenseWork w0, SrcList L) {
     __syncthreads();
     if (threadIdx.x == 0) {
         ZD d = dg[0], up = hi[0];   // running row i: X-entries at columns i and i+1
+        // step i's band values, each step reading the next one's before its own
+        // stores (the band is never written here), so no LDS round trip sits on the chain
+        ZD l = lo[0], dn = dg[k > 1 ? 1 : 0], un = hi[k > 1 ? 1 : 0];
         for (int i = 0; i + 1 < k; ++i) {
-            const ZD l = lo[i], dn = dg[i + 1], un = hi[i + 1];
+            const int in = i + 2 < k ? i + 1 : i;   // the last step reads in-range dummies
+            const ZD l_n = lo[in], dn_n = dg[in + 1], un_n = hi[in + 1];
             if (norm2(l) > norm2(d)) {   // exchange rows i and i+1
                 const ZD r = zrcp(l), m = d * r;
                 mlt[i] = m;
@@ -775,6 +779,9 @@ __global__ __launch_bounds__(kDB) void k_tridiag_inv(DenseWork w0, SrcList L) {
                 d = dn - m * up;
                 up = un;
             }
+            l = l_n;
+            dn = dn_n;
+            un = un_n;
         }
         idd[k - 1] = zrcp(d);
         du[k - 1] = zero;
@@ -783,11 +790,12 @@ __global__ __launch_bounds__(kDB) void k_tridiag_inv(DenseWork w0, SrcList L) {
     __syncthreads();
     for (int c = threadIdx.x; c < k; c += kDB) {
         ZD* col = w.Xinv + c;   // column c, stride k (holds y, then x)
-        // forward: the right-hand side e_c is zero above row c, so elimination starts
-        // at step c - 1 (the only earlier step that can move the 1, via an exchange)
-        for (int i = 0; i < c - 1; ++i) col[(size_t)i * k] = zero;
+        // forward, every lane through every step in step with the others, so that each
+        // store covers consecutive columns of one row: the right-hand side e_c is zero
+        // above row c, and y stays exactly +0 until step c - 1 (the only earlier step
+        // that can move the 1, via an exchange) brings the 1 in
         ZD cur = c == 0 ? mk<double>(1.0, 0.0) : zero;   // running y[i]
-        for (int i = c > 0 ? c - 1 : 0; i + 1 < k; ++i) {
+        for (int i = 0; i + 1 < k; ++i) {
             ZD nxt = (i + 1 == c) ? mk<double>(1.0, 0.0) : zero;   // untouched y[i+1]
             if (swp[i]) {
                 const ZD t = cur;
