@@ -391,7 +391,7 @@ __global__ __launch_bounds__(kDB) void k_gj_trailing_staged(DenseWork w0, SrcLis
     }
 }
 
-// The same for k <= kDB (thread i owns row i): the swaps are not carried out.  Row
+// The same for k <= BLK (thread i owns row i): the swaps are not carried out.  Row
 // i of the swapped column is row src(i) of the stored one, found by undoing the
 // panel's exchanges in reverse order; every global load (panel row, the row's
 // column entries, the pivot rows' entries) is issued before the one block barrier,
@@ -407,8 +407,8 @@ __device__ __forceinline__ int gj_swapped_row(int i, const int* __restrict__ ipi
 
 constexpr int kTrailTC = 16;   // largest TC of the register trailing kernel
 
-template <int NB>
-__global__ __launch_bounds__(kDB) void k_gj_trailing(DenseWork w0, SrcList L, int c0, int TC) {
+template <int NB, int BLK>
+__global__ __launch_bounds__(BLK) void k_gj_trailing(DenseWork w0, SrcList L, int c0, int TC) {
     __shared__ ZD xp[NB * kTrailTC];   // the pivot rows' entries of the swapped columns
     const int e = blockIdx.z, k = L.k[e];
     if (c0 >= k) return;
@@ -705,8 +705,11 @@ void gj_sweep(const SrcList& L, int TC, size_t panel_lds, const DenseWork& w, hi
         const int nother = kmax - nbK;
         if (nother > 0) {
             if (kmax <= kDB && TC <= kTrailTC) {
-                hipLaunchKernelGGL(k_gj_trailing<NB>, dim3(grid_for(nother, TC), 1, act.n), dim3(kDB), 0, st, w,
-                                   act, c0, TC);
+                hipLaunchKernelGGL((k_gj_trailing<NB, kDB>), dim3(grid_for(nother, TC), 1, act.n), dim3(kDB), 0, st,
+                                   w, act, c0, TC);
+            } else if (kmax <= 2 * kDB && TC <= kTrailTC) {
+                hipLaunchKernelGGL((k_gj_trailing<NB, 2 * kDB>), dim3(grid_for(nother, TC), 1, act.n), dim3(2 * kDB),
+                                   0, st, w, act, c0, TC);
             } else {
                 const size_t tl = (size_t)(kmax * (TC + 1) + NB * TC) * sizeof(ZD);
                 hipLaunchKernelGGL(k_gj_trailing_staged<NB>, dim3(grid_for(nother, TC), 1, act.n), dim3(kDB), tl, st,
