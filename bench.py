@@ -1,29 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark of the TSL sign function + all-links derivative on one MI355X.
 
-One step = one source: S = Re <eta|TSL_k(H(U), psi)>, sgn(H)psi by two-sided
-Lanczos, and dS/dU over all 4V links (tslov_sign_grad), on the 8^4 workload
-(V = 4096, n = 49152, Wilson mass -2, mu = 0.2, k = 200, FP64) with seeded
-synthetic SU(3) links (spread 0.4) and Z2-complex sources resident in HBM.
+One step = one pass of the whole hot path over one batch: the 6x18^3 batching
+workload (V = 34992, n = 419904, Wilson mass -2, mu = 0.5, SU(3) link spread
+0.35), 32 Z2-complex sources with Krylov sizes drawn uniformly from [100, 400],
+each source's sgn(H)psi and its full derivative dS/dU over all 4V links of
+S = Re <eta|sgn(H)|psi>, in one tslov_sign_grad_batched call, with every input
+resident in HBM.  The headline runs the float32-link variant (float32 link
+storage; float64 Krylov vectors, stencil arithmetic and accumulation), the
+reduced-precision pattern whose outputs stay within about 1e-6 of float64; the
+line states its per-output error against the float64 batch and, beside it, the
+plain float64 single-source path on the same 32 sources (the comparison the
+metric names), the float64 batch, and the float32-vector variant with its error.
 
 The JSON line carries:
-* value: sources/s of the FP64 path over the timed steps;
-* roofline: the dominant stencil kernel's algorithmic bytes per launch over its
-  mean duration, timed with HIP events on the library stream during the timed
-  steps; traffic from the committed counter summary when it matches the kernel
-  source;
-* cpu_baseline: the CPU oracle (torch/NumPy float64; forward TSL + autograd
-  gradient) on one source of the same workload, on the host cores;
-* batched: the 6x18^3 batching workload (32 Z2 sources, k drawn from [100, 400],
-  mu = 0.5), all sources in one tslov_sign_grad_batched call (FP64), beside the
-  single-source FP64 path on the first four sources and the same batch with the
-  float32-vector path (sources/s and its error against the FP64 batch);
-* precision: the 14^4 workload (k = 400) single source, FP64, with the
-  float32-vector path's error against it;
-* mixed: the float32-vector path on the 8^4 workload (sources/s, errors vs FP64);
-* graphs: the 8^4 step with its Lanczos loops launched and replayed as HIP
-  graphs, both without kernel timing;
-* stencil_large: the FP64 Wilson stencil alone on a 32^4 lattice (1.15 GB per
+* value: sources/s of the batched float32-link path over the timed steps;
+* roofline: the dominant batched stencil kernel (forward or reverse pair) over
+  the timed steps: algorithmic bytes per launch (every entry's fields, the links
+  once per launch) over its mean duration from HIP events on the library stream;
+  traffic from the committed counter summary when it matches the kernel source;
+* cpu_baseline: the CPU oracle (torch/NumPy float64 forward TSL + autograd
+  gradient) on a bounded sample of the same workload, scaled to sources/s;
+* single_8x8x8x8: the 8^4 workload (k = 200) single source, float64;
+* precision_14x14x14x14: the 14^4 workload (k = 400) single source in float64,
+  float32 links and float32 vectors, with the per-output errors;
+* stencil_large: the float64 Wilson stencil alone on a 32^4 lattice (1.15 GB per
   application, above the 256 MB last-level cache) for the HBM-bound figure.
 With --copy-probe a 1 GiB device-to-device copy runs first (HBM counter
 calibration for rocprofv3 --pmc).
@@ -33,6 +34,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -41,11 +43,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sgn(H)ψ+dU-derivative sources/s, mixed vs FP64 @≤1e-6 rel; stencil HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAMES = {0: "k_fwd_pair<double> (fused Lanczos stencil pair, colour grid, hops on two wavefronts, epilogue operands on a third)",
-                1: "k_bwd_rb_cg<double> (reverse-mode stencil pair, colour grid, hops on two wavefronts, epilogue operands on a third)"}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stencil_pair_8x8x8x8.txt")
-# live kernel timing samples every 16th launch of a class: an event pair adds ~5 us
-# of dispatch latency, which on every launch would slow the timed step by ~25%
+KERNEL_NAMES = {0: "k_fwd_pair_ms<double, NS, float> (batched fused Lanczos stencil pair, colour split)",
+                1: "k_bwd_rb_ms<double, NS, float> (batched reverse-mode stencil pair, colour split)"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batched_pair_6x18x18x18.txt")
+# live kernel timing samples every 16th launch of the single-source classes: an event
+# pair adds ~5 us of dispatch latency, which on every launch would slow a small step
 TIMING_EVERY = 16
 
 
@@ -54,8 +56,9 @@ def log(msg):
 
 
 def read_traffic(which: int):
-    """HBM bytes per launch of the given stencil pair kernel (0 forward, 1 reverse) from
-    the committed counter summary, or None if absent or taken on a different kernel source."""
+    """HBM bytes per launch of the batched stencil pair kernel (0 forward, 1 reverse)
+    from the committed counter summary, or None if absent or taken on a different
+    kernel source."""
     from paper_1604_08057_amd.traffic_summary import kernel_source_hash
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -67,67 +70,203 @@ def read_traffic(which: int):
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch" if which == 1 else "fwd_pair_hbm_bytes_per_launch"])
+        return float(vals["bwd_pair_hbm_bytes_per_launch" if which == 1 else "fwd_pair_hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
 
-def time_steps(ctx, eta, psi, k, steps, warmup, dU, timing=False):
+def dev(a):
+    import numpy as np
     import torch
-    for _ in range(warmup):
-        ctx.sign_grad(eta, psi, k, dU=dU)
-    torch.cuda.synchronize()
-    if timing:
-        ctx.timing_enable(TIMING_EVERY)
-        ctx.timing_read(0)
-        ctx.timing_read(1)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        S, _, _, info = ctx.sign_grad(eta, psi, k, dU=dU)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if timing:
-        ctx.timing_enable(0)
-    return (t1 - t0), S, info
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def graph_leg(steps: int = 20):
-    """The 8^4 step with the Lanczos loops launched and replayed as HIP graphs (no
-    kernel timing; the context on a side stream, which capture needs)."""
+def rel_t(a, b):
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def batch_errors(S, dU, y, S64, dU64, y64):
+    n = len(S)
+    e = {"y": max(rel_t(y[s], y64[s]) for s in range(n)),
+         "S": max(abs(S[s] - S64[s]) / abs(S64[s]) for s in range(n)),
+         "dU": max(rel_t(dU[s], dU64[s]) for s in range(n))}
+    dus = sorted(rel_t(dU[s], dU64[s]) for s in range(n))
+    e["dU_median"] = dus[n // 2]
+    return e
+
+
+def headline(steps: int, warmup: int):
+    """The batched 6x18^3 workload: float32-link path timed, with the float64 batch,
+    the float64 single-source path and the float32-vector path beside it."""
     import numpy as np
     import torch
     from paper_1604_08057_amd import Context
     from synthetic import workload
-    wl = workload(2)
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")  # noqa: E731
+    wl = workload(4)
     U, psi, eta = dev(wl.links()), dev(wl.psi()), dev(wl.eta())
-    dU = torch.empty((4, wl.volume, 3, 3), dtype=torch.complex128, device="cuda")
-    torch.cuda.synchronize()
+    ks = [int(k) for k in wl.krylov_sizes()]
+    n = len(ks)
     out = {}
-    for graphs in (False, True):
-        with torch.cuda.stream(torch.cuda.Stream()):
-            ctx = Context(wl.dims, wl.mass, wl.mu)
-        torch.cuda.synchronize()
-        ctx.set_links(U)
-        ctx.set_graphs(graphs)
-        dt, _, _ = time_steps(ctx, eta, psi, wl.k, steps, 2, dU)
-        ctx.close()
-        out["graph_sources_per_s" if graphs else "launched_sources_per_s"] = steps / dt
-    return out
 
-
-def cpu_baseline(wl):
-    import torch
-    from oracle import grad as GR
-    from oracle.wilson import WilsonOperator
-    op = WilsonOperator(wl.dims, wl.mass, wl.mu)
-    U, psi, eta = wl.links(), wl.psi(), wl.eta()
+    # float64 batch: the reference of the error columns (and its own throughput)
+    ctx = Context(wl.dims, wl.mass, wl.mu, precision="fp64")
+    ctx.set_links(U)
+    ctx.sign_grad_batched(eta, psi, ks, want_y=True)     # allocates the workspace
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    GR.grad_autograd(op, U, psi, eta, wl.k)
+    S64, dU64, _, infos64, y64 = ctx.sign_grad_batched(eta, psi, ks, want_y=True)
+    torch.cuda.synchronize()
+    out["fp64_batched_sources_per_s"] = n / (time.perf_counter() - t0)
+    log(f"bench: fp64 batch {out['fp64_batched_sources_per_s']:.2f} sources/s")
+    # the plain float64 single-source path on the same 32 sources
+    dU1 = torch.empty_like(dU64[0])
+    y1 = torch.empty_like(y64[0])
+    ctx.sign_grad(eta[0], psi[0], ks[0], dU=dU1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    same = None
+    for s in range(n):
+        Ss, _, _, _, ys = ctx.sign_grad(eta[s], psi[s], ks[s], dU=dU1, want_y=True)
+        if same is None and ks[s] >= 300:
+            torch.cuda.synchronize()
+            same = bool(Ss == S64[s] and torch.equal(dU1, dU64[s]) and torch.equal(ys, y64[s]))
+    torch.cuda.synchronize()
+    out["fp64_single_source_sources_per_s"] = n / (time.perf_counter() - t0)
+    out["fp64_batch_identical_to_single_k_ge_300"] = same
+    log(f"bench: fp64 single source {out['fp64_single_source_sources_per_s']:.2f} sources/s")
+    ctx.close()
+    del dU1, y1
+
+    # the timed path: float32 links, float64 vectors and accumulation
+    ctx = Context(wl.dims, wl.mass, wl.mu, precision="fp32links")
+    ctx.set_links(U)
+    for _ in range(max(warmup, 1)):                      # the first call allocates and tunes
+        ctx.sign_grad_batched(eta, psi, ks, want_y=True)
+    torch.cuda.synchronize()
+    ctx.timing_enable(1)      # batched launches are long: an event pair on each costs < 1%
+    ctx.timing_read(0)
+    ctx.timing_read(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S, dU, _, infos, y = ctx.sign_grad_batched(eta, psi, ks, want_y=True)
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "sources/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"1 source of the same workload ({wl.dims[0]}^4, k={wl.k}): forward TSL + torch-CPU "
-                      f"autograd dS/dU, {dt:.1f} s"}
+    n0, ms0 = ctx.timing_read(0)
+    n1, ms1 = ctx.timing_read(1)
+    ctx.timing_enable(0)
+    # algorithmic bytes of a launch over its entries: each entry's fields and the
+    # links once (entries of a workgroup share the link loads), summed over launches
+    V = int(np.prod(wl.dims))
+    link_b = V * 36 * 8                                   # float32 links
+    fwd_steps = steps * sum(i.k_used for i in infos)
+    bwd_steps = steps * sum(max(i.k_used - 1, 0) for i in infos)
+    f_b = ctx.kernel_bytes(0) - link_b
+    b_b = ctx.kernel_bytes(1) - link_b
+    fwd_bytes = f_b * fwd_steps + link_b * n0
+    bwd_bytes = b_b * bwd_steps + link_b * n1
+    picks = ctx.pair_ns()
+    ctx.close()
+    err = batch_errors(S, dU, y, S64, dU64, y64)
+    log(f"bench: fp32links batch {steps * n / dt:.2f} sources/s, errors vs fp64 {err}")
+    which = 0 if ms0 >= ms1 else 1
+    nl, ms, byt = (n0, ms0, fwd_bytes) if which == 0 else (n1, ms1, bwd_bytes)
+    per_launch = byt / nl
+    achieved = per_launch / (ms / nl * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(which), "kernel": KERNEL_NAMES[which],
+                "bytes_per_launch": per_launch, "launches": nl, "mean_us": ms / nl * 1e3,
+                "other_pair": {"kernel": KERNEL_NAMES[1 - which],
+                               "achieved": ((bwd_bytes if which == 0 else fwd_bytes) / ((ms1 if which == 0 else ms0)
+                                                                                         * 1e-3) / 1e9),
+                               "mean_us": (ms1 / n1 if which == 0 else ms0 / n0) * 1e3,
+                               "launches": n1 if which == 0 else n0,
+                               "bytes_per_launch": (bwd_bytes / n1 if which == 0 else fwd_bytes / n0)}}
+    del dU, y
+
+    # the float32-vector variant on the same batch (its derivative is flagged inaccurate)
+    ctx = Context(wl.dims, wl.mass, wl.mu, precision="mixed")
+    ctx.set_links(U)
+    ctx.sign_grad_batched(eta, psi, ks, want_y=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Sm, dUm, _, _, ym = ctx.sign_grad_batched(eta, psi, ks, want_y=True)
+    torch.cuda.synchronize()
+    dtm = time.perf_counter() - t0
+    ctx.close()
+    out_m = {"sources_per_s": n / dtm, "rel_err_vs_fp64": batch_errors(Sm, dUm, ym, S64, dU64, y64)}
+    del dUm, ym, dU64, y64
+    res = {"dt": dt, "n": n, "ks": ks, "err": err, "roofline": roofline, "infos": infos,
+           "entries_per_workgroup": {"fwd_pair": picks[0], "bwd_pair": picks[1]}, "fp32_vectors": out_m}
+    res.update(out)
+    return res
+
+
+def single_8(steps: int = 20):
+    """The 8^4 workload, one source per call, float64."""
+    import torch
+    from paper_1604_08057_amd import Context
+    from synthetic import workload
+    wl = workload(2)
+    U, psi, eta = dev(wl.links()), dev(wl.psi()), dev(wl.eta())
+    ctx = Context(wl.dims, wl.mass, wl.mu, precision="fp64")
+    ctx.set_links(U)
+    dU = torch.empty((4, wl.volume, 3, 3), dtype=torch.complex128, device="cuda")
+    y = torch.empty((wl.volume, 4, 3), dtype=torch.complex128, device="cuda")
+    for _ in range(3):
+        ctx.sign_grad(eta, psi, wl.k, dU=dU, want_y=True)
+    torch.cuda.synchronize()
+    ctx.timing_enable(TIMING_EVERY)
+    ctx.timing_read(0)
+    ctx.timing_read(1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S, _, _, info, _ = ctx.sign_grad(eta, psi, wl.k, dU=dU, want_y=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n0, ms0 = ctx.timing_read(0)
+    n1, ms1 = ctx.timing_read(1)
+    ctx.timing_enable(0)
+    b1 = ctx.kernel_bytes(1)
+    ctx.close()
+    del y
+    return {"workload": "8^4 (V=4096), mu=0.2, link spread 0.4, k=200, one Z2 source, fp64",
+            "sources_per_s": steps / dt, "k_used": info.k_used, "newton_iters": info.newton_iters,
+            "fwd_pair_mean_us": ms0 / max(n0, 1) * 1e3, "bwd_pair_mean_us": ms1 / max(n1, 1) * 1e3,
+            "bwd_pair_GBs_cache_resident": b1 / (ms1 / max(n1, 1) * 1e-3) / 1e9}
+
+
+def precision_14():
+    """14^4 workload, k = 400: float64, float32 links and float32 vectors, one source."""
+    import torch
+    from paper_1604_08057_amd import Context
+    from synthetic import workload
+    wl = workload(3)
+    U, psi, eta = dev(wl.links()), dev(wl.psi()), dev(wl.eta())
+    out = {"workload": "14^4 (V=38416), mu=0.3, link spread 0.35, k=400, one Z2 source"}
+    res = {}
+    for prec in ("fp64", "fp32links", "mixed"):
+        ctx = Context(wl.dims, wl.mass, wl.mu, precision=prec)
+        ctx.set_links(U)
+        ctx.sign_grad(eta, psi, wl.k, want_y=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S, dU, _, info, y = ctx.sign_grad(eta, psi, wl.k, want_y=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[prec] = (S, dU, y)
+        out[f"{prec}_sources_per_s"] = 1.0 / dt
+        if prec == "fp64":
+            out["min_abs_re_ritz"] = info.min_abs_re_ritz
+            out["biorth_err"] = info.biorth_err
+            out["newton_iters"] = info.newton_iters
+        ctx.close()
+    S64, dU64, y64 = res["fp64"]
+    for prec in ("fp32links", "mixed"):
+        S, dU, y = res[prec]
+        out[f"{prec}_rel_err_vs_fp64"] = {"y": rel_t(y, y64), "S": abs(S - S64) / abs(S64), "dU": rel_t(dU, dU64)}
+    return out
 
 
 def stencil_large():
@@ -152,116 +291,49 @@ def stencil_large():
     b = ctx.kernel_bytes(KERNEL_APPLY)
     ctx.close()
     gbs = b / (ms / n * 1e-3) / 1e9
-    return {"lattice": "32^4", "kernel": "k_apply_tmarch<double>", "bytes_per_launch": b, "mean_ms": ms / n,
-            "achieved_GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+    return {"lattice": "32^4", "kernel": "k_apply_tmarch<double, double>", "bytes_per_launch": b,
+            "mean_ms": ms / n, "achieved_GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
 
 
-def rel_t(a, b):
+def host_description():
+    cpu = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [{"api": i.get("internal_api"), "threads": i.get("num_threads")} for i in threadpool_info()]
+    except Exception:   # noqa: BLE001 - the description is best effort
+        pass
+    return cpu, blas
+
+
+def cpu_baseline(k_sample: int, k_mean: float):
+    """The oracle (torch-CPU float64 forward TSL + autograd all-links gradient) on
+    source 0 of the 6x18^3 batch at a bounded Krylov size, scaled to a source of
+    the batch's mean Krylov size (the oracle's cost grows linearly in k)."""
     import torch
-    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
-
-
-def batched_leg(ks_single: int = 4):
-    """32-source 6x18^3 workload in one batched FP64 call, and the single-source path."""
-    import numpy as np
-    import torch
-    from paper_1604_08057_amd import Context
+    from oracle import grad as GR
+    from oracle.wilson import WilsonOperator
     from synthetic import workload
     wl = workload(4)
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")  # noqa: E731
-    U, psi, eta = dev(wl.links()), dev(wl.psi()), dev(wl.eta())
-    ks = [int(k) for k in wl.krylov_sizes()]
-    ctx = Context(wl.dims, wl.mass, wl.mu, precision="fp64")
-    ctx.set_links(U)
-    # warm-up with the full batch: the workspace (about 16 GB per source at k = 400)
-    # is allocated here, outside the timed call
-    ctx.sign_grad_batched(eta, psi, ks)
-    torch.cuda.synchronize()
-    ctx.timing_enable(1)      # batched launches are long: timing every one costs < 1%
-    ctx.timing_read(0)
-    ctx.timing_read(1)
+    op = WilsonOperator(wl.dims, wl.mass, wl.mu)
+    U, psi, eta = wl.links(), wl.psi()[0], wl.eta()[0]
     t0 = time.perf_counter()
-    S, dU, _, infos = ctx.sign_grad_batched(eta, psi, ks)
-    torch.cuda.synchronize()
+    GR.grad_autograd(op, U, psi, eta, k_sample)
     dt = time.perf_counter() - t0
-    n0, ms0 = ctx.timing_read(0)
-    n1, ms1 = ctx.timing_read(1)
-    ctx.timing_enable(0)
-    # algorithmic bytes of a launch over n entries: the fields of every entry and the
-    # links once (entries of a workgroup share the link loads), summed over launches
-    steps = sum(i.k_used for i in infos)
-    bsteps = sum(max(i.k_used - 1, 0) for i in infos)
-    link_b = int(np.prod(wl.dims)) * 36 * 16
-    b0, b1 = ctx.kernel_bytes(0) - link_b, ctx.kernel_bytes(1) - link_b
-    fwd_gbs = (b0 * steps + link_b * n0) / (ms0 * 1e-3) / 1e9
-    bwd_gbs = (b1 * bsteps + link_b * n1) / (ms1 * 1e-3) / 1e9
-    picks = ctx.pair_ns()
-    dU0 = dU[0].clone()
-    t1 = time.perf_counter()
-    for s in range(ks_single):
-        Ss, dUs, _, _ = ctx.sign_grad(eta[s], psi[s], ks[s])
-    torch.cuda.synchronize()
-    dt1 = time.perf_counter() - t1
-    same = bool(torch.equal(dUs, dU0)) if ks_single == 1 else None
-    ctx.close()
-    # the same batch with the float32 stencil and vectors (FP64 dots, coefficients,
-    # projected-matrix step and accumulation): throughput and error against FP64
-    ctxm = Context(wl.dims, wl.mass, wl.mu, precision="mixed")
-    ctxm.set_links(U)
-    ctxm.sign_grad_batched(eta, psi, ks)
-    torch.cuda.synchronize()
-    tm = time.perf_counter()
-    Sm, dUm, _, _ = ctxm.sign_grad_batched(eta, psi, ks)
-    torch.cuda.synchronize()
-    dtm = time.perf_counter() - tm
-    ctxm.close()
-    err_S = max(abs(a - b) / abs(b) for a, b in zip(Sm, S))
-    errs = sorted(float(torch.linalg.vector_norm(dUm[s] - dU[s]) / torch.linalg.vector_norm(dU[s]))
-                  for s in range(len(ks)))
-    err_dU, med_dU = errs[-1], errs[len(errs) // 2]
-    del dU, dUm
-    return {"workload": "6x18^3 (V=34992), mu=0.5, link spread 0.35, 32 Z2 sources, k uniform in [100, 400]",
-            "sources": len(ks), "sum_k": int(sum(ks)), "precision": "fp64",
-            "sources_per_s": len(ks) / dt, "ms_per_call": dt * 1e3,
-            "single_source_sources_per_s": ks_single / dt1, "single_source_sample": ks_single,
-            "speedup_vs_single": (len(ks) / dt) / (ks_single / dt1),
-            "fwd_pair_GBs": fwd_gbs, "fwd_pair_frac": fwd_gbs / HBM_PEAK_GBS,
-            "bwd_pair_GBs": bwd_gbs, "bwd_pair_frac": bwd_gbs / HBM_PEAK_GBS,
-            "launches": {"fwd_pair": n0, "bwd_pair": n1}, "identical_to_single": same,
-            "entries_per_workgroup": {"fwd_pair": picks[0], "bwd_pair": picks[1]},
-            "mixed_sources_per_s": len(ks) / dtm, "mixed_max_rel_err_S": err_S, "mixed_max_rel_err_dU": err_dU,
-            "mixed_median_rel_err_dU": med_dU}
-
-
-def precision_leg():
-    """14^4 workload, k = 400: FP64 single source and the float32-vector path's error."""
-    import numpy as np
-    import torch
-    from paper_1604_08057_amd import Context
-    from synthetic import workload
-    wl = workload(3)
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")  # noqa: E731
-    U, psi, eta = dev(wl.links()), dev(wl.psi()), dev(wl.eta())
-    out = {"workload": "14^4 (V=38416), mu=0.3, link spread 0.35, k=400, one Z2 source"}
-    res = {}
-    for prec in ("fp64", "mixed"):
-        ctx = Context(wl.dims, wl.mass, wl.mu, precision=prec)
-        ctx.set_links(U)
-        ctx.sign_grad(eta, psi, wl.k)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        S, dU, _, info = ctx.sign_grad(eta, psi, wl.k)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        y, _ = ctx.sign(psi, wl.k)
-        res[prec] = (S, dU, y)
-        out[f"{prec}_sources_per_s"] = 1.0 / dt
-        out[f"{prec}_newton_iters"] = info.newton_iters
-        ctx.close()
-    S64, dU64, y64 = res["fp64"]
-    Sm, dUm, ym = res["mixed"]
-    out["mixed_rel_err"] = {"y": rel_t(ym, y64), "S": abs(Sm - S64) / abs(S64), "dU": rel_t(dUm, dU64)}
-    return out
+    per_source = dt * k_mean / k_sample
+    cpu, blas = host_description()
+    return {"value": 1.0 / per_source, "unit": "sources/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"source 0 of the 6x18^3 batch at k={k_sample}: forward TSL + torch-CPU autograd dS/dU, "
+                      f"{dt:.1f} s, scaled by {k_mean:.1f}/{k_sample} to the batch's mean Krylov size",
+            "affinity_cpus": len(os.sched_getaffinity(0)), "torch_threads": torch.get_num_threads(),
+            "blas": blas, "cpu_model": cpu}
 
 
 def copy_probe():
@@ -278,10 +350,10 @@ def copy_probe():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched, precision, mixed and 32^4 legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 8^4, 14^4 and 32^4 legs")
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -289,72 +361,40 @@ def main():
               f"library implements", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-    from paper_1604_08057_amd import Context
-    from synthetic import workload
-
     if args.copy_probe:
         copy_probe()
-    wl = workload(2)
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")  # noqa: E731
-    U, psi, eta = dev(wl.links()), dev(wl.psi()), dev(wl.eta())
-    ctx = Context(wl.dims, wl.mass, wl.mu, precision="fp64")
-    ctx.set_links(U)
-    dU = torch.empty((4, wl.volume, 3, 3), dtype=torch.complex128, device="cuda")
-    log(f"bench: workload {wl.dims} k={wl.k} fp64, warmup {args.warmup}, steps {args.steps}")
-    dt, S, info = time_steps(ctx, eta, psi, wl.k, args.steps, args.warmup, dU, timing=True)
-    n0, ms0 = ctx.timing_read(0)
-    n1, ms1 = ctx.timing_read(1)
-    log(f"bench: {args.steps / dt:.2f} sources/s; fwd pair {n0} x {ms0 / max(n0, 1) * 1e3:.2f} us, "
-        f"bwd pair {n1} x {ms1 / max(n1, 1) * 1e3:.2f} us")
-    which = 0 if ms0 >= ms1 else 1
-    n, ms = (n0, ms0) if which == 0 else (n1, ms1)
-    per_launch = ctx.kernel_bytes(which)
-    achieved = per_launch / (ms / n * 1e-3) / 1e9
-    traffic = read_traffic(which)
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": KERNEL_NAMES[which],
-                "bytes_per_launch": per_launch, "launches": n, "mean_us": ms / n * 1e3}
-    y64, _ = ctx.sign(psi, wl.k)
-    dU64 = dU.clone()
-    ctx.close()
-
-    out = {"metric": METRIC, "value": args.steps / dt, "unit": "sources/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "sgn(H)psi + all-links dS/dU, 8^4 lattice (V=4096, n=49152), "
-                                  "Wilson mass -2, mu=0.2, SU(3) link spread 0.4, k=200, one Z2 source",
-                      "lattice": "8x8x8x8", "k": wl.k, "precision": "fp64", "k_used": info.k_used,
-                      "newton_iters": info.newton_iters},
-           "roofline": roofline}
-
+    log(f"bench: 6x18^3 batch of 32 sources, warmup {args.warmup}, steps {args.steps}")
+    h = headline(args.steps, args.warmup)
+    n, dt = h["n"], h["dt"]
+    out = {"metric": METRIC, "value": args.steps * n / dt, "unit": "sources/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "6x18^3 batching workload (V=34992, n=419904), Wilson mass -2, mu=0.5, "
+                                  "SU(3) link spread 0.35, 32 Z2 sources, k uniform in [100, 400]; per source "
+                                  "sgn(H)psi and all-links dS/dU of Re<eta|sgn(H)|psi>, one batched call per step",
+                      "lattice": "18x18x18x6", "sources": n, "sum_k": int(sum(h["ks"])),
+                      "precision": "float32 link storage; float64 Krylov vectors, stencil arithmetic, "
+                                   "accumulation, inner products and dense sign/Frechet step",
+                      "k_used": [i.k_used for i in h["infos"]],
+                      "entries_per_workgroup": h["entries_per_workgroup"]},
+           "rel_err_vs_fp64": h["err"],
+           "fp64_single_source_sources_per_s": h["fp64_single_source_sources_per_s"],
+           "fp64_batched_sources_per_s": h["fp64_batched_sources_per_s"],
+           "fp64_batch_identical_to_single_k_ge_300": h["fp64_batch_identical_to_single_k_ge_300"],
+           "speedup_vs_fp64_single_source": (args.steps * n / dt) / h["fp64_single_source_sources_per_s"],
+           "fp32_vectors_batched": h["fp32_vectors"],
+           "roofline": h["roofline"]}
     if not args.no_extras:
-        ctxm = Context(wl.dims, wl.mass, wl.mu, precision="mixed")
-        ctxm.set_links(U)
-        dUm = torch.empty_like(dU)
-        dtm, Sm, _ = time_steps(ctxm, eta, psi, wl.k, max(args.steps // 2, 1), 1, dUm)
-        ym, _ = ctxm.sign(psi, wl.k)
-        ctxm.close()
-        out["mixed"] = {"sources_per_s": max(args.steps // 2, 1) / dtm, "precision": "float32 stencil and "
-                        "vectors, float64 dots/coefficients/sign step/accumulation",
-                        "rel_err_y_vs_fp64": rel_t(ym, y64), "rel_err_dU_vs_fp64": rel_t(dUm, dU64),
-                        "rel_err_S_vs_fp64": abs(Sm - S) / abs(S)}
-        log(f"bench: mixed {out['mixed']['sources_per_s']:.2f} sources/s")
-        out["graphs"] = graph_leg()
-        log(f"bench: 8^4 launched {out['graphs']['launched_sources_per_s']:.2f}, "
-            f"graph-replayed {out['graphs']['graph_sources_per_s']:.2f} sources/s")
-        out["batched"] = batched_leg()
-        log(f"bench: batched 6x18^3 {out['batched']['sources_per_s']:.2f} sources/s "
-            f"(single-source {out['batched']['single_source_sources_per_s']:.2f})")
-        out["precision"] = precision_leg()
-        log(f"bench: 14^4 fp64 {out['precision']['fp64_sources_per_s']:.2f} sources/s")
+        out["single_8x8x8x8"] = single_8()
+        log(f"bench: 8^4 single source {out['single_8x8x8x8']['sources_per_s']:.2f} sources/s")
+        out["precision_14x14x14x14"] = precision_14()
+        log(f"bench: 14^4 fp64 {out['precision_14x14x14x14']['fp64_sources_per_s']:.2f} sources/s")
         out["stencil_large"] = stencil_large()
         log(f"bench: 32^4 stencil {out['stencil_large']['achieved_GBs']:.0f} GB/s")
-
     if not args.no_cpu_baseline:
-        log("bench: timing the CPU oracle on one source (~15-30 s)")
-        out["cpu_baseline"] = cpu_baseline(wl)
+        log("bench: timing the CPU oracle on a bounded sample (~20-40 s)")
+        out["cpu_baseline"] = cpu_baseline(20, sum(h["ks"]) / n)
     print(json.dumps(out), flush=True)
 
 

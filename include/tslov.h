@@ -42,11 +42,18 @@ typedef enum tslov_status {
 } tslov_status;
 
 typedef enum tslov_precision {
-    TSLOV_FP64 = 0,   /* links, Krylov vectors and stencil in float64                     */
-    TSLOV_MIXED = 1   /* links, Krylov vectors and stencil in float32 with float32
-                         accumulation; inner products, Lanczos coefficients, the
-                         projected-matrix sign / Frechet step and the output
-                         accumulation in float64                                          */
+    TSLOV_FP64 = 0,       /* links, Krylov vectors and stencil in float64                 */
+    TSLOV_MIXED = 1,      /* links, Krylov vectors and stencil in float32 with float32
+                             accumulation; inner products, Lanczos coefficients, the
+                             projected-matrix sign / Frechet step and the output
+                             accumulation in float64.  The rounding of every step is
+                             amplified by the non-Hermitian recursion: the link
+                             derivative is not accurate (see tslov_sign_grad)       */
+    TSLOV_FP32_LINKS = 2  /* links stored and read in float32 (widened to float64 as they
+                             are loaded); Krylov vectors, stencil arithmetic and every
+                             accumulation in float64.  The float32 rounding then acts as
+                             one fixed perturbation of the operator instead of fresh
+                             noise at every step                                     */
 } tslov_precision;
 
 /* Lattice and operator description (App. A, eq. WD_op / WD_G). */
@@ -58,15 +65,43 @@ typedef struct tslov_lattice_desc {
     int precision;       /* tslov_precision                                              */
 } tslov_lattice_desc;
 
+/* Bits of tslov_info.flags. */
+typedef enum tslov_flag {
+    TSLOV_FLAG_SIGN_STAGNATED = 1,    /* the Newton iteration for sgn(T_k) stopped on stagnation with
+                                         a last relative step between 1e-8 and 1e-6 (sgn(T_k) is then
+                                         accurate to about that step only)                          */
+    TSLOV_FLAG_GRAD_FP32_VECTORS = 2, /* a derivative from TSLOV_MIXED: float32 rounding at every
+                                         Lanczos step is amplified by the non-Hermitian recursion, so
+                                         dU_out and dpsi_out carry errors far above float32 rounding
+                                         (measured 0.1 relative and more); use TSLOV_FP32_LINKS or
+                                         TSLOV_FP64 where the derivative matters                    */
+    TSLOV_FLAG_RITZ_UNSETTLED = 4     /* the eigenvalue iteration for the Ritz values did not settle
+                                         for every eigenvalue: min_abs_re_ritz is approximate        */
+} tslov_flag;
+
 /* Per-call diagnostics (host struct, valid after the call returns). */
 typedef struct tslov_info {
     int k_used;          /* Krylov size reached (< k after a lucky breakdown)           */
     int breakdown;       /* 0 none, 1 lucky (invariant Krylov space), 2 serious           */
     int newton_iters;    /* iterations of the projected-matrix sign step                 */
+    int cg_iters;        /* iterations of the shifted solves of a deflated derivative (else 0) */
+    int flags;           /* tslov_flag bits                                              */
     int reserved;
-    double norm_x;       /* |psi|                                                        */
-    double biorth_err;   /* |w_1^H v_k| + |w_k^H v_1| (loss of biorthogonality probe)    */
-    double ms[6];        /* phase times in ms: forward, dense, output, backward, force, total */
+    double norm_x;       /* |psi| (of the projected source when deflating)              */
+    double min_abs_re_ritz; /* min |Re theta| over the eigenvalues theta of T_{k_used} (the Ritz
+                             values whose signs the approximation interpolates), from a host
+                             eigenvalue solve of the tridiagonal matrix; NaN if k_used = 0.
+                             A value <= 1e-12 norm_T makes the call fail with ERR_SIGN_UNDEFINED
+                             (the sign is undefined on Re z = 0, Sec. 2 after eq. spectral_form) */
+    double norm_T;       /* infinity norm of T_{k_used} (NaN if k_used = 0)              */
+    double biorth_err;   /* |w_1^H v_k| + |w_k^H v_1| with k = k_used and the normalisation
+                            w_j^H v_j = 1 (0 for k_used < 2): the entries of W^H V - I farthest
+                            from the diagonal, the loss of biorthogonality that the plain
+                            recursion accumulates                                         */
+    double eps_A;        /* error estimate of Sec. 4.1 eq. error_est for this output; NaN unless
+                            requested with tslov_set_diagnostics (single-source calls)     */
+    double ms[6];        /* phase times in ms: forward, dense, output, backward,
+                            extra (deflation solves, error estimate), total               */
 } tslov_info;
 
 typedef struct tslov_ctx tslov_ctx;
@@ -80,7 +115,9 @@ const char* tslov_last_error(void);
 
 /* Copy the gauge field (canonical complex128 [4][V][3][3], device) into the
  * library's structure-of-arrays layout; the antiperiodic sign is folded into
- * the temporal links on the last time slice.  No caller pointer is kept. */
+ * the temporal links on the last time slice.  No caller pointer is kept.
+ * ERR_ARG (and no links set) if an element is not finite.  Synchronises the
+ * stream once (for that check). */
 tslov_status tslov_set_links(tslov_ctx* ctx, const void* U);
 
 /* out = D_w(mu) in (dagger = 0) or D_w(mu)^dagger in = g5 D_w(-mu) g5 in
@@ -113,7 +150,7 @@ typedef struct tslov_deflation {
  * k >= 1 basis vectors (k <= 1024).  A lucky breakdown returns OK with
  * info->k_used < k and the exact result on the invariant space; a serious
  * breakdown returns ERR_BREAKDOWN (out undefined); a zero (projected) source
- * gives k_used = 0.  defl may be NULL.  info may be NULL. */
+ * gives k_used = 0; a source with a non-finite element gives ERR_ARG.  defl may be NULL.  info may be NULL. */
 tslov_status tslov_sign(tslov_ctx* ctx, const void* psi, void* out, int k,
                         const tslov_deflation* defl, tslov_info* info);
 
@@ -145,12 +182,25 @@ tslov_status tslov_overlap(tslov_ctx* ctx, const void* psi, void* out, int k,
  * Z_i = (lambda_i - H)^{-1}(1 - Pi_i); the 2l systems for Z_i psi and Z_i^H a_i
  * (a_i = s_i eta - dS/dpsi_p) are solved on the device by conjugate gradients on
  * the normal equations to relative residual 1e-11 (ERR_NOT_CONVERGED after 1e5
- * iterations; info->reserved = iterations used).  R, L must be accurate
+ * iterations; info->cg_iters = iterations used).  R, L must be accurate
  * eigenvectors of H(U) for the links set (the formula assumes exact eigenpairs);
- * eigenvalues must be distinct. */
+ * eigenvalues must be distinct.
+ * y_out (nullable, canonical spinor) receives the approximation of sgn(H) psi itself
+ * (as tslov_sign computes it), formed inside the same call from the same Krylov basis.
+ * In TSLOV_MIXED the derivative outputs carry info->flags TSLOV_FLAG_GRAD_FP32_VECTORS. */
 tslov_status tslov_sign_grad(tslov_ctx* ctx, const void* eta, const void* psi, int k,
                              const tslov_deflation* defl, int recompute_stride,
-                             double* S_out, void* dU_out, void* dpsi_out, tslov_info* info);
+                             double* S_out, void* dU_out, void* dpsi_out, void* y_out, tslov_info* info);
+
+/* The same for the overlap operator (eq. overlap, a = 1):
+ *   S = Re <eta | D_ov | psi> = Re <eta|psi> + Re <g5 eta | TSL_k(H(U), psi)>,
+ * with dU_out = dS/dRe U + i dS/dIm U as in tslov_sign_grad, dpsi_out (nullable)
+ * = dS/dpsi = eta + the source gradient of the sign part, and dov_out (nullable)
+ * = D_ov psi = psi + g5 TSL_k(H, psi).  Deflation, recompute_stride and info as in
+ * tslov_sign_grad (whose derivative with respect to eta is the output y). */
+tslov_status tslov_overlap_grad(tslov_ctx* ctx, const void* eta, const void* psi, int k,
+                                const tslov_deflation* defl, int recompute_stride,
+                                double* S_out, void* dU_out, void* dpsi_out, void* dov_out, tslov_info* info);
 
 /* Batched derivative (many noise sources, uneven Krylov sizes): for s < nsrc,
  *   S_out[s] = Re <eta_s | TSL_{k[s]}(H(U), psi_s)>,  dU_out[s] = dS_s/dRe U + i dS_s/dIm U,
@@ -158,7 +208,8 @@ tslov_status tslov_sign_grad(tslov_ctx* ctx, const void* eta, const void* psi, i
  * eta, psi: nsrc canonical spinors, contiguous ([nsrc][V][4][3] complex128, device);
  * k: host array of nsrc Krylov sizes in [1, 1024]; S_out: host array of nsrc
  * doubles (nullable); dU_out: [nsrc][4][V][3][3] complex128 (device); dpsi_out:
- * [nsrc][V][4][3] (nullable); infos: host array of nsrc (nullable).
+ * [nsrc][V][4][3] (nullable); y_out: [nsrc][V][4][3] (nullable) receives each
+ * source's sgn(H) psi_s; infos: host array of nsrc (nullable).
  * The library runs the sources in lockstep groups (one launch per Lanczos step
  * serves every active source of the group; a source leaves the group after its
  * own k[s] steps or a lucky breakdown), sized to the free device memory.  A
@@ -166,7 +217,8 @@ tslov_status tslov_sign_grad(tslov_ctx* ctx, const void* eta, const void* psi, i
  * source has been computed (their outputs are valid; the broken ones' are not;
  * infos[s].breakdown = 2 names them). */
 tslov_status tslov_sign_grad_batched(tslov_ctx* ctx, int nsrc, const void* eta, const void* psi, const int* k,
-                                     double* S_out, void* dU_out, void* dpsi_out, tslov_info* infos);
+                                     double* S_out, void* dU_out, void* dpsi_out, void* y_out,
+                                     tslov_info* infos);
 
 /* Stochastic estimator of the link-current trace (Sec. 4, the U(1) vector current
  * test, eq. lat_vec_cur without the inverse Dirac operator): with Z2 noise xi_s,
@@ -199,6 +251,30 @@ tslov_status tslov_error_estimate(tslov_ctx* ctx, const void* psi, int k, const 
  * columns past k_used are zero.  Its eigenvalues are the Ritz values whose signs
  * the approximation interpolates (diagnostics: min |Re theta|). */
 tslov_status tslov_lanczos_matrix(tslov_ctx* ctx, const void* psi, int k, void* T_out, tslov_info* info);
+
+/* The small dense step of the method on its own (Sec. 2, eq. spectral_form applied to
+ * the projected matrix): c_out = sgn(T) e_1 for the k x k complex tridiagonal T with
+ *   T_jj = diag[j] (k complex), T_{j+1,j} = sub[j] (k-1 real), T_{j,j+1} = sup[j] (k-1 complex),
+ * host arrays of interleaved (re, im) doubles; c_out: device, k complex128.  Runs the
+ * same scaled Newton iteration as tslov_sign.  ERR_SIGN_UNDEFINED when an eigenvalue
+ * of T has |Re| <= 1e-12 times the infinity norm of T (info->min_abs_re_ritz). */
+tslov_status tslov_tridiag_sign(tslov_ctx* ctx, int k, const double* diag, const double* sub, const double* sup,
+                                void* c_out, tslov_info* info);
+
+/* Eigenvalues of the k x k complex tridiagonal T (same host arrays as
+ * tslov_tridiag_sign) into out (host, 2k doubles, re/im), by the Ehrlich-Aberth
+ * iteration on the characteristic polynomial's three-term recurrence (host code
+ * only: needs no device and no context).  *sweeps (nullable) receives the sweeps
+ * used, or -1 when some eigenvalue did not settle to rounding level. */
+tslov_status tslov_ritz_values(int k, const double* diag, const double* sub, const double* sup, double* out,
+                               int* sweeps);
+
+/* Optional per-call diagnostics of the context: TSLOV_DIAG_EPS_A makes tslov_sign,
+ * tslov_overlap and tslov_sign_grad compute info->eps_A (Sec. 4.1 eq. error_est: one
+ * more two-sided Lanczos process of size k on the output; only when info is given).
+ * flags = 0 turns them off (the default).  ERR_ARG for unknown bits. */
+#define TSLOV_DIAG_EPS_A 1
+tslov_status tslov_set_diagnostics(tslov_ctx* ctx, int flags);
 
 /* Projected-matrix step on its own (for tests): S = sgn(T) for a dense complex128
  * k x k row-major device matrix T by the scaled Newton iteration, and, if E is

@@ -51,11 +51,17 @@ def grad_autograd(op: WilsonOperator, U: np.ndarray, psi: np.ndarray, eta: np.nd
 
 
 def forward(op: WilsonOperator, U: np.ndarray, psi: np.ndarray, k: int, **kw):
-    """TSL_k(H(U), psi) without gradients: dict with y, T, c, k_used, breakdown."""
+    """TSL_k(H(U), psi) without gradients: dict with y, T, c, k_used, breakdown, and
+    biorth = |w_1^H v_k| + |w_k^H v_1| (k = k_used; 0 below 2), the entries of
+    W^H V - I farthest from the diagonal under the normalisation w_j^H v_j = 1."""
     with torch.no_grad():
         res = tsl_wilson(op, _t(U), _t(psi), k, **kw)
+        kk = res.k_used
+        bi = 0.0
+        if kk >= 2:
+            bi = float(abs(torch.vdot(res.W[0], res.V[kk - 1])) + abs(torch.vdot(res.W[kk - 1], res.V[0])))
     return dict(y=res.y.numpy(), T=res.T.numpy(), c=res.c.numpy(), k_used=res.k_used,
-                breakdown=res.breakdown, alpha=np.array([complex(a) for a in res.alpha]))
+                breakdown=res.breakdown, alpha=np.array([complex(a) for a in res.alpha]), biorth=bi)
 
 
 def su3_direction(rng: np.random.Generator) -> np.ndarray:

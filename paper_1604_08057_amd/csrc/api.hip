@@ -8,14 +8,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
+#include "ritz.h"
 
 using tslov::Coef;
 using tslov::DenseWork;
@@ -131,7 +134,9 @@ struct tslov_ctx {
     int device = 0;
     size_t lds_max = 65536;
     int links_set = 0;
+    int diag = 0;    // tslov_set_diagnostics flags
     Buf U64, U32;
+    Buf badflag;     // device int: a non-finite link element was seen
     Buf sbmap;       // Geom::sbmap
     Buf opf;         // two working-precision fields for the plain operator
     // batch workspace: per slot, kcap steps of v, w, a = Hv, b = H^dag w (and
@@ -175,6 +180,8 @@ struct tslov_ctx {
     int nblk() const { return tslov::grid_for(g.V); }
     size_t field_elems() const { return (size_t)12 * g.ldv; }
     size_t zsize() const { return precision == TSLOV_MIXED ? sizeof(Z<float>) : sizeof(ZD); }
+    // bytes of one complex link element as the stencils read it
+    size_t lsize() const { return precision == TSLOV_FP64 ? sizeof(ZD) : sizeof(Z<float>); }
     size_t field_bytes() const { return field_elems() * zsize(); }
     int pstride() const { return 8 * tslov::np_max(g.V); }
 };
@@ -304,8 +311,8 @@ struct LoopKey {
         return *this;
     }
     // the workspace, links and launch shapes the loops' kernels receive
-    template <typename R>
-    LoopKey& buffers(const tslov_ctx* c, const Work<R>& wk, const Z<R>* U, int cls) {
+    template <typename R, typename RL>
+    LoopKey& buffers(const tslov_ctx* c, const Work<R>& wk, const Z<RL>* U, int cls) {
         add(wk.V).add(wk.W).add(wk.A).add(wk.B).add(wk.AB).add(wk.SB).add(wk.F).add(wk.part);
         add(wk.fe).add(wk.kcap).add(wk.ring).add(wk.pstride);
         add(c->coefmem.p).add(c->slots).add(c->kcap).add(U);
@@ -435,10 +442,12 @@ Work<R> work(const tslov_ctx* c) {
     return w;
 }
 
-template <typename R>
-const Z<R>* links(const tslov_ctx* c) {
-    if constexpr (sizeof(R) == sizeof(double)) return c->U64.as<Z<R>>();
-    else return c->U32.as<Z<R>>();
+// The link copy the stencils read: float64, or float32 for TSLOV_MIXED (float
+// fields) and TSLOV_FP32_LINKS (float64 fields).
+template <typename RL>
+const Z<RL>* links(const tslov_ctx* c) {
+    if constexpr (sizeof(RL) == sizeof(double)) return c->U64.as<Z<RL>>();
+    else return c->U32.as<Z<RL>>();
 }
 
 // Device bytes one source of up to kcap steps needs (workspace sizing).
@@ -530,8 +539,56 @@ SrcList range(const SrcList& L, int b, int e) {
 struct EntryStatus {
     int k_used = 0, breakdown = 0, step = 0;
     double norm_x = 0.0, S = 0.0;
-    int iters = 0;
+    int iters = 0, flags = 0, cg_iters = 0;
+    double biorth = 0.0, eps_A = NAN;
+    tslov::RitzSummary ritz{NAN, NAN, 0};
 };
+
+// Eigenvalues of every entry's T_k on host threads, overlapping the device work
+// that follows the forward pass (the dense step and the reverse pass).  The
+// coefficient arrays are host copies laid out as on the device ([slot][n], step j
+// at index j).
+struct RitzJobs {
+    std::vector<ZD> alpha, gamma;
+    std::vector<double> beta;
+    int n = 0;
+    std::vector<int> kk, slot;
+    std::vector<tslov::RitzSummary> out;
+    std::vector<std::thread> th;
+    std::atomic<int> next{0};
+    void start(const std::vector<int>& k_used, const std::vector<int>& slots) {
+        kk = k_used;
+        slot = slots;
+        out.assign(kk.size(), tslov::RitzSummary{NAN, NAN, 0});
+        next = 0;
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const int nt = (int)std::min<size_t>(kk.size(), std::min(hw, 16u));
+        for (int t = 0; t < nt; ++t)
+            th.emplace_back([this] {
+                for (int e; (e = next++) < (int)kk.size();) {
+                    if (kk[e] < 1) continue;
+                    const size_t o = (size_t)slot[e] * n + 1;   // step 1 of the slot
+                    out[e] = tslov::ritz_summary(kk[e], reinterpret_cast<const double*>(&alpha[o]), &beta[o],
+                                                 reinterpret_cast<const double*>(&gamma[o]));
+                }
+            });
+    }
+    void join() {
+        for (auto& t : th) t.join();
+        th.clear();
+    }
+    ~RitzJobs() { join(); }
+};
+
+// A Ritz value on the imaginary axis (relative to the size of T_k) leaves the sign
+// of the projected matrix undefined (Sec. 2, after eq. spectral_form).
+constexpr double kSignAxisTol = 1e-12;
+tslov_status check_ritz(const EntryStatus& s) {
+    if (s.k_used > 0 && s.ritz.min_abs_re <= kSignAxisTol * s.ritz.norm_T)
+        return fail(TSLOV_ERR_SIGN_UNDEFINED, "a Ritz value of the projected matrix lies on Re z = 0 (|Re theta| = " +
+                                                  std::to_string(s.ritz.min_abs_re) + ")");
+    return TSLOV_OK;
+}
 
 // Recompute mode: the state before forward step j0 = 1 + seg m of every entry of
 // L (the residuals r, s of step j0 - 1 and v_{j0-1}, w_{j0-1}), saved (restore = 0)
@@ -556,9 +613,9 @@ tslov_status checkpoint(tslov_ctx* c, const SrcList& L, int seg, int j0, int res
 
 // Lanczos process for every entry of L (slots 0..n-1, k in decreasing order);
 // psi and eta canonical arrays indexed by src (eta nullable; eta_g5: eta = g5 psi).
-template <typename R>
+template <typename R, typename RL>
 tslov_status forward(tslov_ctx* c, const SrcList& L, const ZD* psi, const ZD* eta, int eta_g5,
-                     std::vector<EntryStatus>& es) {
+                     std::vector<EntryStatus>& es, RitzJobs* jobs = nullptr) {
     const Geom& g = c->g;
     const Work<R> wk = work<R>(c);
     std::vector<int> init((size_t)16 * L.n, 0);
@@ -566,7 +623,7 @@ tslov_status forward(tslov_ctx* c, const SrcList& L, const ZD* psi, const ZD* et
     HIPCHK(hipMemcpyAsync(c->coef.status, init.data(), init.size() * sizeof(int), hipMemcpyHostToDevice, c->st));
     tslov::launch_sources_to_soa<R>(psi, 0, 0, wk, L, g, c->st);
     if (eta) tslov::launch_sources_to_soa<R>(eta, 1, eta_g5, wk, L, g, c->st);
-    const Z<R>* U = links<R>(c);
+    const Z<RL>* U = links<RL>(c);
     const int kmax = L.k[0];
     PairTuner tune(c, 0, L.n);
     const int m = c->ring ? c->ring_m : 0;
@@ -577,7 +634,7 @@ tslov_status forward(tslov_ctx* c, const SrcList& L, const ZD* psi, const ZD* et
             const SrcList Lj = prefix(L, n);
             if (m && j > 1 && (j - 1) % m == 0) CHK(checkpoint<R>(c, Lj, (j - 1) / m, j, 0));
             tune.before(n);
-            tslov::launch_fwd_pair<R>(U, g, c->kappa, c->mu, wk, Lj, c->coef, j, eta ? 1 : 0, tune.ns(n), c->st,
+            tslov::launch_fwd_pair<R, RL>(U, g, c->kappa, c->mu, wk, Lj, c->coef, j, eta ? 1 : 0, tune.ns(n), c->st,
                                       TimedLaunch(c, 0).t);
             tune.after(n);
             tslov::launch_recur<R>(g, wk, Lj, c->coef, j, c->st);
@@ -591,19 +648,52 @@ tslov_status forward(tslov_ctx* c, const SrcList& L, const ZD* psi, const ZD* et
     } else {
         CHK(loop());
     }
+    const int nbb = tslov::launch_biorth<R>(g, wk, L, c->coef, c->st);
     HIPCHK(hipGetLastError());
-    std::vector<int> st((size_t)16 * L.n);
-    std::vector<double> misc((size_t)16 * L.n);
+    // slots 0..nslot-1 hold the list's entries
+    int nslot = 0;
+    for (int e = 0; e < L.n; ++e) nslot = std::max(nslot, L.slot[e] + 1);
+    CHK(ensure_host_part(c, 4 * nbb * L.n));
+    std::vector<int> st((size_t)16 * nslot);
+    std::vector<double> misc((size_t)16 * nslot);
     HIPCHK(hipMemcpyAsync(st.data(), c->coef.status, st.size() * sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipMemcpyAsync(misc.data(), c->coef.misc, misc.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    for (int e = 0; e < L.n; ++e)
+        HIPCHK(hipMemcpyAsync(c->host_part + (size_t)4 * nbb * e, wk.p(L.slot[e], 3), (size_t)4 * nbb * sizeof(double),
+                              hipMemcpyDeviceToHost, c->st));
+    if (jobs) {
+        const size_t n = (size_t)c->coef.n * nslot;
+        jobs->n = c->coef.n;
+        jobs->alpha.resize(n);
+        jobs->gamma.resize(n);
+        jobs->beta.resize(n);
+        HIPCHK(hipMemcpyAsync(jobs->alpha.data(), c->coef.alpha, n * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(jobs->gamma.data(), c->coef.gamma, n * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(jobs->beta.data(), c->coef.beta, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    }
     HIPCHK(hipStreamSynchronize(c->st));
     es.assign(L.n, EntryStatus());
     for (int e = 0; e < L.n; ++e) {
         const int* s = &st[(size_t)16 * L.slot[e]];
+        if (s[2] == 3) return fail(TSLOV_ERR_ARG, "a source is not finite");
         es[e].k_used = s[1];
         es[e].breakdown = s[2];
         es[e].step = s[3];
         es[e].norm_x = misc[(size_t)16 * L.slot[e]];
+        // |w_1^H v_k| + |w_k^H v_1| with v_1 = w_1 = x/|x|, from the fixed-order block sums
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
+        const double* pp = c->host_part + (size_t)4 * nbb * e;
+        for (int b = 0; b < nbb; ++b)
+            for (int i = 0; i < 4; ++i) d[i] += pp[4 * b + i];
+        es[e].biorth = es[e].norm_x > 0.0 ? (std::hypot(d[0], d[1]) + std::hypot(d[2], d[3])) / es[e].norm_x : 0.0;
+    }
+    if (jobs) {
+        std::vector<int> ku(L.n), sl(L.n);
+        for (int e = 0; e < L.n; ++e) {
+            ku[e] = es[e].breakdown == 2 ? 0 : es[e].k_used;
+            sl[e] = L.slot[e];
+        }
+        jobs->start(ku, sl);
     }
     return TSLOV_OK;
 }
@@ -657,9 +747,9 @@ constexpr double kNsSafe = 0.9;
 constexpr double kResidCheck = 2.0;
 
 tslov_status newton(tslov_ctx* c, const SrcList& L, int grad, const DenseWork& w, std::vector<int>& iters,
-                    int tridiag_start) {
+                    int tridiag_start, std::vector<int>* stagnated = nullptr) {
     struct St {
-        int scaling = 1, extra = 0, done = 0, it = 0, ns = 0;
+        int scaling = 1, extra = 0, done = 0, it = 0, ns = 0, stag = 0;
         double prev = INFINITY;
     };
     std::vector<St> s(L.n);
@@ -713,6 +803,7 @@ tslov_status newton(tslov_ctx* c, const SrcList& L, int grad, const DenseWork& w
                 // quadratic convergence: once the step is below 1e-8 the new iterate's error
                 // is at rounding level; stagnation above that also ends the iteration
                 const bool conv = delta <= 1e-8 || (delta < 1e-6 && delta > 0.5 * x.prev);
+                if (conv && delta > 1e-8) x.stag = 1;
                 if (conv) {
                     if (x.extra) x.extra = 0;
                     else x.done = 1;
@@ -727,15 +818,20 @@ tslov_status newton(tslov_ctx* c, const SrcList& L, int grad, const DenseWork& w
                         "sign iteration of the projected matrix did not converge (eigenvalue near Re z = 0)");
         iters[e] = s[e].it;
     }
+    if (stagnated) {
+        stagnated->assign(L.n, 0);
+        for (int e = 0; e < L.n; ++e) (*stagnated)[e] = s[e].stag;
+    }
     return TSLOV_OK;
 }
 
 // sgn(T) (and the Frechet step) of every entry, coefficients c_j and adjoint seeds.
-tslov_status dense_step(tslov_ctx* c, const SrcList& L, int grad, std::vector<int>& iters) {
+tslov_status dense_step(tslov_ctx* c, const SrcList& L, int grad, std::vector<int>& iters,
+                        std::vector<int>* stagnated = nullptr) {
     DenseWork w;
     CHK(ensure_dense(c, c->slots, c->kcap, w));
     tslov::launch_dense_build(c->coef, L, grad, w, c->st);
-    CHK(newton(c, L, grad, w, iters, 1));   // X_0 = T_k is tridiagonal
+    CHK(newton(c, L, grad, w, iters, 1, stagnated));   // X_0 = T_k is tridiagonal
     tslov::launch_dense_extract(c->coef, L, grad, w, c->st);
     HIPCHK(hipGetLastError());
     return TSLOV_OK;
@@ -756,11 +852,11 @@ struct GradOut {
 // In recompute mode (c->ring) the steps run in segments of m from the top; each
 // segment first regenerates its basis vectors by replaying the forward steps from
 // its checkpoint, then runs its reverse steps and adds its force terms.
-template <typename R>
+template <typename R, typename RL>
 tslov_status backward(tslov_ctx* c, const SrcList& L, GradOut& out) {
     const Geom& g = c->g;
     const Work<R> wk = work<R>(c);
-    const Z<R>* U = links<R>(c);
+    const Z<RL>* U = links<RL>(c);
     const int kmax = L.k[0];
     const int m = c->ring ? c->ring_m : 0;
     if (m && out.ward) return fail(TSLOV_ERR_ARG, "the Ward check needs every Krylov vector stored");
@@ -778,13 +874,13 @@ tslov_status backward(tslov_ctx* c, const SrcList& L, GradOut& out) {
             const SrcList Llt = prefix(L, nlt);
             tslov::launch_bwd_ra<R>(g, wk, Llt, c->coef, j, c->st);
             tune.before(nlt);
-            tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, wk, Llt, c->coef, j, 0, tune.ns(nlt), c->st,
+            tslov::launch_bwd_rb<R, RL>(U, g, c->kappa, c->mu, wk, Llt, c->coef, j, 0, tune.ns(nlt), c->st,
                                     TimedLaunch(c, 1).t);
             tune.after(nlt);
         }
         if (neq_end > nlt) {
             const SrcList Leq = range(L, nlt, neq_end);
-            tslov::launch_bwd_rb<R>(U, g, c->kappa, c->mu, wk, Leq, c->coef, j, 1, 1, c->st);
+            tslov::launch_bwd_rb<R, RL>(U, g, c->kappa, c->mu, wk, Leq, c->coef, j, 1, 1, c->st);
         }
         nlt = neq_end;
     };
@@ -815,7 +911,7 @@ tslov_status backward(tslov_ctx* c, const SrcList& L, GradOut& out) {
             if (seg > 0) CHK(checkpoint<R>(c, reaching(j0), seg, j0, 1));
             for (int j = j0; j <= std::min(j1 + 1, kmax); ++j) {
                 const SrcList Lr = reaching(j);
-                tslov::launch_fwd_replay<R>(U, g, c->kappa, c->mu, wk, Lr, c->coef, j, c->st);
+                tslov::launch_fwd_replay<R, RL>(U, g, c->kappa, c->mu, wk, Lr, c->coef, j, c->st);
                 if (j <= j1) tslov::launch_recur_replay<R>(g, wk, Lr, c->coef, j, c->st);
             }
             for (int j = j1; j >= j0; --j) reverse_step(j);
@@ -903,6 +999,10 @@ tslov_status prepare_defl(tslov_ctx* c, const tslov_deflation* defl, DeflSet& d)
     return TSLOV_OK;
 }
 
+// Canonical spinor buffers of a context: 0 projected source, 1 source gradient,
+// 2 partial result (deflation); 3, 4 first and second result of the error
+// estimate; 5 g5 eta of the overlap derivative.
+constexpr int kCanonBufs = 6;
 ZD* canon_buf(tslov_ctx* c, int i) { return c->canon.as<ZD>() + (size_t)i * 12 * c->g.V; }
 
 void fill_info(tslov_info* info, const EntryStatus& s, const double* ms) {
@@ -911,21 +1011,65 @@ void fill_info(tslov_info* info, const EntryStatus& s, const double* ms) {
     info->k_used = s.k_used;
     info->breakdown = s.breakdown;
     info->newton_iters = s.iters;
+    info->cg_iters = s.cg_iters;
+    info->flags = s.flags;
     info->norm_x = s.norm_x;
+    info->min_abs_re_ritz = s.k_used > 0 ? s.ritz.min_abs_re : NAN;
+    info->norm_T = s.k_used > 0 ? s.ritz.norm_T : NAN;
+    info->biorth_err = s.biorth;
+    info->eps_A = s.eps_A;
     for (int i = 0; i < 6; ++i) info->ms[i] = ms[i];
 }
 
-// out = [psi +] g5^{overlap} sgn(H) psi by TSL, with optional deflation.
-template <typename R>
+// Flags of an entry after its dense step: Newton stagnation, an unsettled Ritz
+// solve and (derivative calls) the float32 Krylov vectors of TSLOV_MIXED.
+int entry_flags(const tslov_ctx* c, const EntryStatus& s, int stagnated, int grad) {
+    int f = 0;
+    if (stagnated) f |= TSLOV_FLAG_SIGN_STAGNATED;
+    if (s.k_used > 0 && s.ritz.sweeps < 0) f |= TSLOV_FLAG_RITZ_UNSETTLED;
+    if (grad && c->precision == TSLOV_MIXED) f |= TSLOV_FLAG_GRAD_FP32_VECTORS;
+    return f;
+}
+
+tslov_status sign_dispatch(tslov_ctx* c, const void* psi, void* out, int k, const tslov_deflation* defl,
+                           tslov_info* info, int overlap, int want_eps = 0);
+
+// eps_A = |TSL(y) - psi| / (2 |psi|) for the first result y (Sec. 4.1 eq. error_est):
+// a fresh two-sided Lanczos process with source y, the same k and deflation.  y may
+// sit in canonical buffer 3; z takes buffer 4.
+tslov_status error_of(tslov_ctx* c, const ZD* psi, const ZD* y, int k, const tslov_deflation* defl, double* eps) {
+    const size_t n = (size_t)12 * c->g.V;
+    CHK(ensure(c->canon, (size_t)kCanonBufs * n * sizeof(ZD)));
+    ZD* z = canon_buf(c, 4);
+    CHK(sign_dispatch(c, y, z, k, defl, nullptr, 0, 0));
+    CHK(ensure_host_part(c, 2048));
+    double* part = c->part.as<double>() + 2 * c->pstride();
+    const int nb = tslov::launch_diff_norm(z, psi, n, part, c->st);
+    HIPCHK(hipMemcpyAsync(c->host_part, part, (size_t)2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    double dif = 0.0, nrm = 0.0;
+    for (int i = 0; i < nb; ++i) {
+        dif += c->host_part[2 * i];
+        nrm += c->host_part[2 * i + 1];
+    }
+    // sgn(0) = 0 is exact: a zero source has no error
+    *eps = nrm > 0.0 ? std::sqrt(dif / nrm) / 2.0 : 0.0;
+    return TSLOV_OK;
+}
+
+// out = [psi +] g5^{overlap} sgn(H) psi by TSL, with optional deflation; with
+// want_eps also eps_A into info (the sign itself then also goes to canonical
+// buffer 3 when out holds the overlap).
+template <typename R, typename RL>
 tslov_status sign_impl(tslov_ctx* c, const void* psi_in, void* out, int k, const tslov_deflation* defl,
-                       tslov_info* info, int overlap) {
+                       tslov_info* info, int overlap, int want_eps) {
     const double t0 = now_ms();
     DeflSet d;
     CHK(prepare_defl(c, defl, d));
     const ZD* psi = (const ZD*)psi_in;
     const ZD* src = psi;
+    CHK(ensure(c->canon, (size_t)kCanonBufs * 12 * c->g.V * sizeof(ZD)));
     if (d.l) {
-        CHK(ensure(c->canon, (size_t)5 * 12 * c->g.V * sizeof(ZD)));
         tslov::launch_defl_coeffs(d.L, psi, c->g.V, d.l, d.part, d.c, c->st);
         tslov::launch_defl_project(d.R, psi, d.c, c->g.V, d.l, canon_buf(c, 0), c->st);
         src = canon_buf(c, 0);
@@ -933,35 +1077,49 @@ tslov_status sign_impl(tslov_ctx* c, const void* psi_in, void* out, int k, const
     CHK(ensure_work(c, 1, k, 0));
     const SrcList L = make_list({0}, {k});
     std::vector<EntryStatus> es;
-    CHK(forward<R>(c, L, src, nullptr, 0, es));
+    RitzJobs jobs;
+    CHK((forward<R, RL>(c, L, src, nullptr, 0, es, &jobs)));
     if (es[0].breakdown == 2)
         return fail(TSLOV_ERR_BREAKDOWN, "serious Lanczos breakdown at step " + std::to_string(es[0].step));
     const double t1 = now_ms();
     const int k_used = es[0].k_used;
     SrcList Ld = make_list({0}, {k_used});
+    std::vector<int> stag(1, 0);
     if (k_used > 0) {
         std::vector<int> iters;
-        CHK(dense_step(c, Ld, 0, iters));
+        CHK(dense_step(c, Ld, 0, iters, &stag));
         es[0].iters = iters[0];
     }
     const double t2 = now_ms();
     const Work<R> wk = work<R>(c);
-    if (d.l) {
-        ZD* yp = nullptr;
-        if (k_used > 0) {
-            yp = canon_buf(c, 1);
-            tslov::launch_assemble<R>(c->g, wk, Ld, c->coef, nullptr, 0, yp, c->st);
+    // y alone (no psi added) where the overlap is asked for and eps_A needs the sign
+    ZD* ysign = (want_eps && overlap) ? canon_buf(c, 3) : nullptr;
+    for (int pass = 0; pass < (ysign ? 2 : 1); ++pass) {
+        const int ov = pass == 0 ? overlap : 0;
+        ZD* o = pass == 0 ? (ZD*)out : ysign;
+        if (d.l) {
+            ZD* yp = nullptr;
+            if (k_used > 0) {
+                yp = canon_buf(c, 1);
+                tslov::launch_assemble<R>(c->g, wk, Ld, c->coef, nullptr, 0, yp, c->st);
+            }
+            tslov::launch_defl_finish(d.R, d.c, d.sgn, yp, psi, c->g.V, d.l, ov, o, c->st);
+        } else if (k_used > 0) {
+            tslov::launch_assemble<R>(c->g, wk, Ld, c->coef, psi, ov, o, c->st);
+        } else {
+            tslov::launch_defl_finish(nullptr, nullptr, nullptr, nullptr, psi, c->g.V, 0, ov, o, c->st);
         }
-        tslov::launch_defl_finish(d.R, d.c, d.sgn, yp, psi, c->g.V, d.l, overlap, (ZD*)out, c->st);
-    } else if (k_used > 0) {
-        tslov::launch_assemble<R>(c->g, wk, Ld, c->coef, psi, overlap, (ZD*)out, c->st);
-    } else {
-        tslov::launch_defl_finish(nullptr, nullptr, nullptr, nullptr, psi, c->g.V, 0, overlap, (ZD*)out, c->st);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
+    jobs.join();
+    es[0].ritz = jobs.out[0];
+    es[0].flags = entry_flags(c, es[0], stag[0], 0);
+    CHK(check_ritz(es[0]));
     const double t3 = now_ms();
-    const double ms[6] = {t1 - t0, t2 - t1, t3 - t2, 0.0, 0.0, t3 - t0};
+    if (want_eps) CHK(error_of(c, psi, ysign ? ysign : (const ZD*)out, k, defl, &es[0].eps_A));
+    const double t4 = now_ms();
+    const double ms[6] = {t1 - t0, t2 - t1, t3 - t2, 0.0, t4 - t3, t4 - t0};
     fill_info(info, es[0], ms);
     return TSLOV_OK;
 }
@@ -979,13 +1137,14 @@ struct BatchRequest {
     double* S_out = nullptr;
     ZD* dU = nullptr;
     ZD* dpsi = nullptr;
+    ZD* y = nullptr;           // sgn(H) psi per source (canonical, nullable)
     double* jsum = nullptr;
     int ward = 0;
     tslov_info* infos = nullptr;
     double ward_max = 0.0, g_max = 0.0;
 };
 
-template <typename R>
+template <typename R, typename RL>
 tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
     const double t0 = now_ms();
     std::vector<int> order(q.nsrc);
@@ -1005,7 +1164,8 @@ tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
         const double tg0 = now_ms();
         const SrcList L = make_list(src, ks);
         std::vector<EntryStatus> es;
-        CHK(forward<R>(c, L, q.psi, q.eta_g5 ? q.psi : q.eta, q.eta_g5, es));
+        RitzJobs jobs;
+        CHK((forward<R, RL>(c, L, q.psi, q.eta_g5 ? q.psi : q.eta, q.eta_g5, es, &jobs)));
         const double tg1 = now_ms();
         // entries that go on to the derivative, in decreasing k_used
         std::vector<int> live;
@@ -1018,6 +1178,7 @@ tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
             if (es[e].k_used == 0) {   // zero source: S = 0 and every derivative vanishes
                 if (q.dU) tslov::launch_zero((double*)(q.dU + (size_t)s * 36 * c->g.V), (size_t)72 * c->g.V, c->st);
                 if (q.dpsi) tslov::launch_zero((double*)(q.dpsi + (size_t)s * n12), 2 * n12, c->st);
+                if (q.y) tslov::launch_zero((double*)(q.y + (size_t)s * n12), 2 * n12, c->st);
                 if (q.S_out) q.S_out[s] = 0.0;
                 continue;
             }
@@ -1031,11 +1192,12 @@ tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
             Ld.src[i] = L.src[live[i]];
             Ld.k[i] = es[live[i]].k_used;
         }
-        std::vector<int> iters;
+        std::vector<int> iters, stag;
         double tg2 = now_ms(), tg3 = tg2;
         if (Ld.n > 0) {
-            CHK(dense_step(c, Ld, 1, iters));
+            CHK(dense_step(c, Ld, 1, iters, &stag));
             tg2 = now_ms();
+            if (q.y) tslov::launch_assemble<R>(c->g, work<R>(c), Ld, c->coef, nullptr, 0, q.y, c->st);
             GradOut go;
             go.dU = q.dU;
             go.dpsi = q.dpsi;
@@ -1043,7 +1205,7 @@ tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
             go.accumulate = first_group ? 0 : 1;
             go.ward = q.ward;
             go.psi = q.psi;
-            CHK(backward<R>(c, Ld, go));
+            CHK((backward<R, RL>(c, Ld, go)));
             q.ward_max = std::max(q.ward_max, go.ward_max);
             q.g_max = std::max(q.g_max, go.g_max);
             first_group = 0;
@@ -1055,6 +1217,7 @@ tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
             for (int i = 0; i < Ld.n; ++i) {
                 const int e = live[i];
                 es[e].iters = iters[i];
+                es[e].flags = stag[i] ? TSLOV_FLAG_SIGN_STAGNATED : 0;
                 es[e].S = misc[(size_t)16 * L.slot[e] + 1];
                 if (q.S_out) q.S_out[src[e]] = es[e].S;
             }
@@ -1063,9 +1226,16 @@ tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
             first_group = 0;
         }
         HIPCHK(hipStreamSynchronize(c->st));
+        jobs.join();
+        for (int e = 0; e < cap; ++e) {
+            es[e].ritz = jobs.out[e];
+            es[e].flags = entry_flags(c, es[e], es[e].flags & TSLOV_FLAG_SIGN_STAGNATED, 1);
+        }
         const double ms[6] = {tg1 - tg0, tg2 - tg1, 0.0, tg3 - tg2, 0.0, tg3 - tg0};
         if (q.infos)
             for (int e = 0; e < cap; ++e) fill_info(&q.infos[src[e]], es[e], ms);
+        for (int e = 0; e < cap; ++e)
+            if (es[e].breakdown != 2) CHK(check_ritz(es[e]));
     }
     if (q.jsum && first_group) tslov::launch_zero(q.jsum, (size_t)4 * c->g.V, c->st);
     HIPCHK(hipStreamSynchronize(c->st));
@@ -1074,24 +1244,37 @@ tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
     return TSLOV_OK;
 }
 
-static tslov_status run_batched(tslov_ctx* c, BatchRequest& q) {
-    return c->precision == TSLOV_MIXED ? grad_batched<float>(c, q) : grad_batched<double>(c, q);
+tslov_status sign_dispatch(tslov_ctx* c, const void* psi, void* out, int k, const tslov_deflation* defl,
+                           tslov_info* info, int overlap, int want_eps) {
+    switch (c->precision) {
+        case TSLOV_MIXED: return sign_impl<float, float>(c, psi, out, k, defl, info, overlap, want_eps);
+        case TSLOV_FP32_LINKS: return sign_impl<double, float>(c, psi, out, k, defl, info, overlap, want_eps);
+        default: return sign_impl<double, double>(c, psi, out, k, defl, info, overlap, want_eps);
+    }
 }
 
-constexpr double kCgTol = 1e-11;     // relative residual of the shifted solves
+static tslov_status run_batched(tslov_ctx* c, BatchRequest& q) {
+    switch (c->precision) {
+        case TSLOV_MIXED: return grad_batched<float, float>(c, q);
+        case TSLOV_FP32_LINKS: return grad_batched<double, float>(c, q);
+        default: return grad_batched<double, double>(c, q);
+    }
+}
+
+constexpr double kCgTol = 1e-13;     // relative residual of the shifted solves
 constexpr int kCgMaxIter = 100000;
 constexpr int kCgCheckEvery = 8;
 
 // Derivative of the deflated S = Re eta^H [sum_i s_i Pi_i psi + TSL(P psi)], P = 1 - sum_i Pi_i,
 // with the eigenpairs moving with U (reduced-resolvent solves; see solve.hip).
 tslov_status deflated_grad(tslov_ctx* c, const ZD* eta, const ZD* psi, int k, const tslov_deflation* defl,
-                           int recompute, double* S_out, ZD* dU, ZD* dpsi, tslov_info* info) {
+                           int recompute, double* S_out, ZD* dU, ZD* dpsi, ZD* y, tslov_info* info) {
     const double t0 = now_ms();
     DeflSet d;
     CHK(prepare_defl(c, defl, d));
     const int l = d.l, V = c->g.V, nr = 2 * l;
     const size_t n12 = (size_t)12 * V;
-    CHK(ensure(c->canon, (size_t)5 * n12 * sizeof(ZD)));
+    CHK(ensure(c->canon, (size_t)kCanonBufs * n12 * sizeof(ZD)));
     ZD* psip = canon_buf(c, 0);
     ZD* pbar = canon_buf(c, 1);
     const int nb = c->nblk();
@@ -1113,9 +1296,12 @@ tslov_status deflated_grad(tslov_ctx* c, const ZD* eta, const ZD* psi, int k, co
     q.S_out = &S_tsl;
     q.dU = dU;
     q.dpsi = pbar;
+    q.y = y ? canon_buf(c, 2) : nullptr;
     q.infos = info;
     q.recompute = recompute;
     CHK(run_batched(c, q));
+    // y = TSL(psi_p) + sum_i s_i c_i R_i
+    if (y) tslov::launch_defl_finish(d.R, d.c, d.sgn, canon_buf(c, 2), psi, V, l, 0, y, c->st);
     tslov::launch_defl_coeffs(d.R, eta, V, l, xpart, dRe, c->st);          // R_i^H eta
     tslov::launch_defl_coeffs(d.R, pbar, V, l, xpart, dRp, c->st);         // R_i^H psibar_p
     std::vector<ZD> ch(l), de(l), dp(l), qh(l), mq(l);
@@ -1178,7 +1364,7 @@ tslov_status deflated_grad(tslov_ctx* c, const ZD* eta, const ZD* psi, int k, co
     HIPCHK(hipStreamSynchronize(c->st));
     if (S_out) *S_out = S;
     if (info) {
-        info->reserved = it;
+        info->cg_iters = it;
         info->ms[4] = now_ms() - t0 - info->ms[5];
         info->ms[5] = now_ms() - t0;
     }
@@ -1193,8 +1379,8 @@ namespace {
 // Chunk length of the t-march operator, picked on the first call by timing each
 // candidate (best of three launches) on the call's own internal buffers: every
 // candidate gives the same result, so the pick changes the time only.
-template <typename R>
-tslov_status pick_apply_chunk(tslov_ctx* c, const Z<R>* U, const Z<R>* a, Z<R>* b, double mu, int g5in, int g5out) {
+template <typename R, typename RL>
+tslov_status pick_apply_chunk(tslov_ctx* c, const Z<RL>* U, const Z<R>* a, Z<R>* b, double mu, int g5in, int g5out) {
     if (c->tm_T != 0) return TSLOV_OK;
     int cand[16];
     const int n = tslov::tmarch_chunks(c->g, cand, 16);
@@ -1219,7 +1405,7 @@ tslov_status pick_apply_chunk(tslov_ctx* c, const Z<R>* U, const Z<R>* a, Z<R>* 
         for (int i = 0; i < n; ++i) {
             const size_t x = (size_t)2 * (r * n + i);
             (void)hipEventRecord(ev[x], c->st);
-            tslov::launch_apply<R>(U, a, b, c->g, c->kappa, mu, g5in, g5out, c->st, tslov::Timing{}, cand[i]);
+            tslov::launch_apply<R, RL>(U, a, b, c->g, c->kappa, mu, g5in, g5out, c->st, tslov::Timing{}, cand[i]);
             (void)hipEventRecord(ev[x + 1], c->st);
         }
     const hipError_t es = hipEventSynchronize(ev.back());
@@ -1241,6 +1427,21 @@ tslov_status pick_apply_chunk(tslov_ctx* c, const Z<R>* U, const Z<R>* a, Z<R>* 
     return TSLOV_OK;
 }
 
+// The operator on canonical spinors: to the context's field layout, the stencil,
+// and back.
+template <typename R, typename RL>
+tslov_status apply_fields(tslov_ctx* c, const void* in, void* out, double mu, int g5in, int g5out) {
+    Z<R>* a = c->opf.as<Z<R>>();
+    Z<R>* b = a + c->field_elems();
+    const Z<RL>* U = links<RL>(c);
+    tslov::launch_spinor_to_soa<R>((const ZD*)in, a, c->g, nullptr, c->st);
+    if (!c->tm_T_forced) CHK((pick_apply_chunk<R, RL>(c, U, a, b, mu, g5in, g5out)));
+    tslov::launch_apply<R, RL>(U, a, b, c->g, c->kappa, mu, g5in, g5out, c->st, TimedLaunch(c, 2).t,
+                               c->tm_T_forced ? c->tm_T_forced : std::max(c->tm_T, 0));
+    tslov::launch_spinor_from_soa<R>(b, (ZD*)out, c->g, c->st);
+    return TSLOV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1252,7 +1453,8 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
     *out = nullptr;
     for (int i = 0; i < 4; ++i)
         if (d->dims[i] < 2) return fail(TSLOV_ERR_ARG, "every lattice extent must be >= 2");
-    if (d->precision != TSLOV_FP64 && d->precision != TSLOV_MIXED) return fail(TSLOV_ERR_ARG, "unknown precision");
+    if (d->precision != TSLOV_FP64 && d->precision != TSLOV_MIXED && d->precision != TSLOV_FP32_LINKS)
+        return fail(TSLOV_ERR_ARG, "unknown precision");
     if (2.0 * d->mass + 8.0 == 0.0) return fail(TSLOV_ERR_ARG, "2*mass + 8 must be non-zero");
     const long long V = (long long)d->dims[0] * d->dims[1] * d->dims[2] * d->dims[3];
     if (V > (1LL << 26)) return fail(TSLOV_ERR_ARG, "lattice volume too large");
@@ -1275,7 +1477,7 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
     c->precision = d->precision;
     c->st = (hipStream_t)stream;
     tslov_status s = ensure(c->U64, (size_t)36 * c->g.ldv * sizeof(ZD));
-    if (s == TSLOV_OK && c->precision == TSLOV_MIXED) s = ensure(c->U32, (size_t)36 * c->g.ldv * sizeof(Z<float>));
+    if (s == TSLOV_OK && c->precision != TSLOV_FP64) s = ensure(c->U32, (size_t)36 * c->g.ldv * sizeof(Z<float>));
     if (s == TSLOV_OK) {
         int nwg = 0;
         const std::vector<int> map = site_block_order(c->g, nwg);
@@ -1297,7 +1499,7 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
 void tslov_destroy(tslov_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
-    for (Buf* b : {&c->U64, &c->U32, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
+    for (Buf* b : {&c->U64, &c->U32, &c->badflag, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
                    &c->fields, &c->part, &c->coefmem, &c->dense, &c->denseInt, &c->densePart, &c->denseDelta,
                    &c->gpart, &c->gsrc, &c->bout, &c->wardp, &c->canon, &c->deflw, &c->deflx, &c->cgf, &c->cgp,
                    &c->cgs, &c->ckpt})
@@ -1316,10 +1518,16 @@ void tslov_destroy(tslov_ctx* c) {
 
 tslov_status tslov_set_links(tslov_ctx* c, const void* U) {
     if (!c || !U) return fail(TSLOV_ERR_ARG, "null argument");
-    tslov::launch_links_to_soa((const ZD*)U, c->U64.as<ZD>(), c->precision == TSLOV_MIXED ? c->U32.as<Z<float>>() : nullptr,
-                               c->g, c->antiperiodic, c->st);
+    CHK(ensure(c->badflag, sizeof(double)));
+    tslov::launch_zero(c->badflag.as<double>(), 1, c->st);
+    tslov::launch_links_to_soa((const ZD*)U, c->U64.as<ZD>(), c->precision != TSLOV_FP64 ? c->U32.as<Z<float>>() : nullptr,
+                               c->g, c->antiperiodic, c->badflag.as<int>(), c->st);
     HIPCHK(hipGetLastError());
-    c->links_set = 1;
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, c->badflag.p, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    c->links_set = bad ? 0 : 1;
+    if (bad) return fail(TSLOV_ERR_ARG, "the gauge field contains non-finite values");
     return TSLOV_OK;
 }
 
@@ -1328,22 +1536,10 @@ static tslov_status apply_op(tslov_ctx* c, const void* in, void* out, double mu,
     if (!c->links_set) return fail(TSLOV_ERR_ARG, "links not set (call tslov_set_links first)");
     if (in == out) return fail(TSLOV_ERR_ARG, "in and out must not overlap");
     CHK(ensure(c->opf, 2 * c->field_bytes()));
-    if (c->precision == TSLOV_MIXED) {
-        Z<float>* a = c->opf.as<Z<float>>();
-        Z<float>* b = a + c->field_elems();
-        tslov::launch_spinor_to_soa<float>((const ZD*)in, a, c->g, nullptr, c->st);
-        if (!c->tm_T_forced) CHK(pick_apply_chunk<float>(c, c->U32.as<Z<float>>(), a, b, mu, g5in, g5out));
-        tslov::launch_apply<float>(c->U32.as<Z<float>>(), a, b, c->g, c->kappa, mu, g5in, g5out, c->st,
-                                   TimedLaunch(c, 2).t, c->tm_T_forced ? c->tm_T_forced : std::max(c->tm_T, 0));
-        tslov::launch_spinor_from_soa<float>(b, (ZD*)out, c->g, c->st);
-    } else {
-        ZD* a = c->opf.as<ZD>();
-        ZD* b = a + c->field_elems();
-        tslov::launch_spinor_to_soa<double>((const ZD*)in, a, c->g, nullptr, c->st);
-        if (!c->tm_T_forced) CHK(pick_apply_chunk<double>(c, c->U64.as<ZD>(), a, b, mu, g5in, g5out));
-        tslov::launch_apply<double>(c->U64.as<ZD>(), a, b, c->g, c->kappa, mu, g5in, g5out, c->st,
-                                    TimedLaunch(c, 2).t, c->tm_T_forced ? c->tm_T_forced : std::max(c->tm_T, 0));
-        tslov::launch_spinor_from_soa<double>(b, (ZD*)out, c->g, c->st);
+    switch (c->precision) {
+        case TSLOV_MIXED: CHK((apply_fields<float, float>(c, in, out, mu, g5in, g5out))); break;
+        case TSLOV_FP32_LINKS: CHK((apply_fields<double, float>(c, in, out, mu, g5in, g5out))); break;
+        default: CHK((apply_fields<double, double>(c, in, out, mu, g5in, g5out)));
     }
     HIPCHK(hipGetLastError());
     return TSLOV_OK;
@@ -1364,8 +1560,7 @@ tslov_status tslov_sign(tslov_ctx* c, const void* psi, void* out, int k, const t
     CHK(check_common(c, k, defl));
     if (!psi || !out) return fail(TSLOV_ERR_ARG, "null argument");
     if (psi == out) return fail(TSLOV_ERR_ARG, "psi and out must not overlap");
-    return c->precision == TSLOV_MIXED ? sign_impl<float>(c, psi, out, k, defl, info, 0)
-                                       : sign_impl<double>(c, psi, out, k, defl, info, 0);
+    return sign_dispatch(c, psi, out, k, defl, info, 0, (c->diag & TSLOV_DIAG_EPS_A) && info);
 }
 
 tslov_status tslov_overlap(tslov_ctx* c, const void* psi, void* out, int k, const tslov_deflation* defl,
@@ -1373,33 +1568,78 @@ tslov_status tslov_overlap(tslov_ctx* c, const void* psi, void* out, int k, cons
     CHK(check_common(c, k, defl));
     if (!psi || !out) return fail(TSLOV_ERR_ARG, "null argument");
     if (psi == out) return fail(TSLOV_ERR_ARG, "psi and out must not overlap");
-    return c->precision == TSLOV_MIXED ? sign_impl<float>(c, psi, out, k, defl, info, 1)
-                                       : sign_impl<double>(c, psi, out, k, defl, info, 1);
+    return sign_dispatch(c, psi, out, k, defl, info, 1, (c->diag & TSLOV_DIAG_EPS_A) && info);
 }
 
 tslov_status tslov_sign_grad(tslov_ctx* c, const void* eta, const void* psi, int k, const tslov_deflation* defl,
-                             int recompute_stride, double* S_out, void* dU_out, void* dpsi_out, tslov_info* info) {
+                             int recompute_stride, double* S_out, void* dU_out, void* dpsi_out, void* y_out,
+                             tslov_info* info) {
     CHK(check_common(c, k, defl));
     if (!eta || !psi || !dU_out) return fail(TSLOV_ERR_ARG, "null argument");
     if (recompute_stride < 0) return fail(TSLOV_ERR_ARG, "recompute_stride must be >= 0");
-    if (defl && defl->l != 0)
-        return deflated_grad(c, (const ZD*)eta, (const ZD*)psi, k, defl, recompute_stride, S_out, (ZD*)dU_out,
-                             (ZD*)dpsi_out, info);
-    BatchRequest q;
-    q.nsrc = 1;
-    q.eta = (const ZD*)eta;
-    q.psi = (const ZD*)psi;
-    q.k = &k;
-    q.S_out = S_out;
-    q.dU = (ZD*)dU_out;
-    q.dpsi = (ZD*)dpsi_out;
-    q.infos = info;
-    q.recompute = recompute_stride;
-    return run_batched(c, q);
+    if (y_out && (y_out == psi || y_out == eta)) return fail(TSLOV_ERR_ARG, "y_out must not overlap the inputs");
+    const int want_eps = (c->diag & TSLOV_DIAG_EPS_A) && info;
+    ZD* y = (ZD*)y_out;
+    if (want_eps && !y) {
+        CHK(ensure(c->canon, (size_t)kCanonBufs * 12 * c->g.V * sizeof(ZD)));
+        y = canon_buf(c, 3);
+    }
+    if (defl && defl->l != 0) {
+        CHK(deflated_grad(c, (const ZD*)eta, (const ZD*)psi, k, defl, recompute_stride, S_out, (ZD*)dU_out,
+                          (ZD*)dpsi_out, y, info));
+    } else {
+        BatchRequest q;
+        q.nsrc = 1;
+        q.eta = (const ZD*)eta;
+        q.psi = (const ZD*)psi;
+        q.k = &k;
+        q.S_out = S_out;
+        q.dU = (ZD*)dU_out;
+        q.dpsi = (ZD*)dpsi_out;
+        q.y = y;
+        q.infos = info;
+        q.recompute = recompute_stride;
+        CHK(run_batched(c, q));
+    }
+    if (want_eps) {
+        const double t0 = now_ms();
+        CHK(error_of(c, (const ZD*)psi, y, k, defl, &info->eps_A));
+        info->ms[4] += now_ms() - t0;
+        info->ms[5] += now_ms() - t0;
+    }
+    return TSLOV_OK;
+}
+
+tslov_status tslov_overlap_grad(tslov_ctx* c, const void* eta, const void* psi, int k, const tslov_deflation* defl,
+                                int recompute_stride, double* S_out, void* dU_out, void* dpsi_out, void* dov_out,
+                                tslov_info* info) {
+    CHK(check_common(c, k, defl));
+    if (!eta || !psi || !dU_out) return fail(TSLOV_ERR_ARG, "null argument");
+    if (dov_out && (dov_out == psi || dov_out == eta)) return fail(TSLOV_ERR_ARG, "dov_out must not overlap the inputs");
+    if (dpsi_out && (dpsi_out == psi || dpsi_out == eta)) return fail(TSLOV_ERR_ARG, "dpsi_out must not overlap the inputs");
+    const int V = c->g.V;
+    CHK(ensure(c->canon, (size_t)kCanonBufs * 12 * V * sizeof(ZD)));
+    ZD* g5eta = canon_buf(c, 5);
+    tslov::launch_combine(nullptr, (const ZD*)eta, 1, V, g5eta, c->st);
+    // Re eta^H psi by the deflation dot kernels (one vector)
+    CHK(ensure(c->deflx, (size_t)4 * sizeof(ZD) + (size_t)c->nblk() * 2 * sizeof(double)));
+    ZD* dot = c->deflx.as<ZD>();
+    tslov::launch_defl_coeffs((const ZD*)eta, (const ZD*)psi, V, 1, (double*)(dot + 4), dot, c->st);
+    ZD hdot{0.0, 0.0};
+    HIPCHK(hipMemcpyAsync(&hdot, dot, sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    double S = 0.0;
+    CHK(tslov_sign_grad(c, g5eta, psi, k, defl, recompute_stride, &S, dU_out, dpsi_out, dov_out, info));
+    if (dpsi_out) tslov::launch_combine((const ZD*)eta, (const ZD*)dpsi_out, 0, V, (ZD*)dpsi_out, c->st);
+    if (dov_out) tslov::launch_combine((const ZD*)psi, (const ZD*)dov_out, 1, V, (ZD*)dov_out, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (S_out) *S_out = S + hdot.re;
+    return TSLOV_OK;
 }
 
 tslov_status tslov_sign_grad_batched(tslov_ctx* c, int nsrc, const void* eta, const void* psi, const int* k,
-                                     double* S_out, void* dU_out, void* dpsi_out, tslov_info* infos) {
+                                     double* S_out, void* dU_out, void* dpsi_out, void* y_out, tslov_info* infos) {
     if (!c) return fail(TSLOV_ERR_ARG, "null context");
     if (!c->links_set) return fail(TSLOV_ERR_ARG, "links not set (call tslov_set_links first)");
     if (nsrc < 1 || nsrc > kMaxSources) return fail(TSLOV_ERR_ARG, "nsrc must be in [1, 2^20]");
@@ -1414,6 +1654,7 @@ tslov_status tslov_sign_grad_batched(tslov_ctx* c, int nsrc, const void* eta, co
     q.S_out = S_out;
     q.dU = (ZD*)dU_out;
     q.dpsi = (ZD*)dpsi_out;
+    q.y = (ZD*)y_out;
     q.infos = infos;
     return run_batched(c, q);
 }
@@ -1446,30 +1687,11 @@ tslov_status tslov_error_estimate(tslov_ctx* c, const void* psi, int k, const ts
                                   double* eps_out) {
     CHK(check_common(c, k, defl));
     if (!psi || !eps_out) return fail(TSLOV_ERR_ARG, "null argument");
-    const size_t n = (size_t)12 * c->g.V;
     // canonical buffers 0..2 serve the deflated sign; y and z take 3 and 4
-    CHK(ensure(c->canon, (size_t)5 * n * sizeof(ZD)));
+    CHK(ensure(c->canon, (size_t)kCanonBufs * 12 * c->g.V * sizeof(ZD)));
     ZD* y = canon_buf(c, 3);
-    ZD* z = canon_buf(c, 4);
-    tslov_status s = c->precision == TSLOV_MIXED ? sign_impl<float>(c, psi, y, k, defl, nullptr, 0)
-                                                 : sign_impl<double>(c, psi, y, k, defl, nullptr, 0);
-    if (s == TSLOV_OK)
-        s = c->precision == TSLOV_MIXED ? sign_impl<float>(c, y, z, k, defl, nullptr, 0)
-                                        : sign_impl<double>(c, y, z, k, defl, nullptr, 0);
-    if (s != TSLOV_OK) return s;
-    CHK(ensure_host_part(c, 2048));
-    double* part = c->part.as<double>() + 2 * c->pstride();
-    const int nb = tslov::launch_diff_norm(z, (const ZD*)psi, n, part, c->st);
-    HIPCHK(hipMemcpyAsync(c->host_part, part, (size_t)2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipStreamSynchronize(c->st));
-    double dif = 0.0, nrm = 0.0;
-    for (int i = 0; i < nb; ++i) {
-        dif += c->host_part[2 * i];
-        nrm += c->host_part[2 * i + 1];
-    }
-    // sgn(0) = 0 is exact: a zero source has no error
-    *eps_out = nrm > 0.0 ? std::sqrt(dif / nrm) / 2.0 : 0.0;
-    return TSLOV_OK;
+    CHK(sign_dispatch(c, psi, y, k, defl, nullptr, 0, 0));
+    return error_of(c, (const ZD*)psi, y, k, defl, eps_out);
 }
 
 tslov_status tslov_lanczos_matrix(tslov_ctx* c, const void* psi, int k, void* T_out, tslov_info* info) {
@@ -1479,8 +1701,11 @@ tslov_status tslov_lanczos_matrix(tslov_ctx* c, const void* psi, int k, void* T_
     const SrcList L = make_list({0}, {k});
     std::vector<EntryStatus> es;
     const double t0 = now_ms();
-    if (c->precision == TSLOV_MIXED) CHK(forward<float>(c, L, (const ZD*)psi, nullptr, 0, es));
-    else CHK(forward<double>(c, L, (const ZD*)psi, nullptr, 0, es));
+    switch (c->precision) {
+        case TSLOV_MIXED: CHK((forward<float, float>(c, L, (const ZD*)psi, nullptr, 0, es))); break;
+        case TSLOV_FP32_LINKS: CHK((forward<double, float>(c, L, (const ZD*)psi, nullptr, 0, es))); break;
+        default: CHK((forward<double, double>(c, L, (const ZD*)psi, nullptr, 0, es)));
+    }
     const int ku = es[0].k_used;
     std::vector<ZD> T((size_t)k * k, ZD{0.0, 0.0});
     if (ku > 0) {
@@ -1499,10 +1724,86 @@ tslov_status tslov_lanczos_matrix(tslov_ctx* c, const void* psi, int k, void* T_
         }
     }
     std::memcpy(T_out, T.data(), T.size() * sizeof(ZD));
+    if (ku > 0) {
+        std::vector<ZD> al(ku + 1), ga(ku + 1);
+        std::vector<double> be(ku + 1, 0.0);
+        for (int j = 0; j < ku; ++j) {
+            al[j] = T[(size_t)j * k + j];
+            if (j > 0) {
+                be[j] = T[(size_t)j * k + (j - 1)].re;
+                ga[j] = T[(size_t)(j - 1) * k + j];
+            }
+        }
+        es[0].ritz = tslov::ritz_summary(ku, reinterpret_cast<const double*>(al.data()), be.data(),
+                                         reinterpret_cast<const double*>(ga.data()));
+        es[0].flags = entry_flags(c, es[0], 0, 0);
+    }
     const double ms[6] = {now_ms() - t0, 0, 0, 0, 0, now_ms() - t0};
     fill_info(info, es[0], ms);
     if (es[0].breakdown == 2)
         return fail(TSLOV_ERR_BREAKDOWN, "serious Lanczos breakdown at step " + std::to_string(es[0].step));
+    return TSLOV_OK;
+}
+
+tslov_status tslov_tridiag_sign(tslov_ctx* c, int k, const double* diag, const double* sub, const double* sup,
+                                void* c_out, tslov_info* info) {
+    if (!c || !diag || !c_out || (k > 1 && (!sub || !sup))) return fail(TSLOV_ERR_ARG, "null argument");
+    if (k < 1 || k > kMaxK) return fail(TSLOV_ERR_ARG, "k must be in [1, 1024]");
+    const double t0 = now_ms();
+    // coefficient layout of the Lanczos process (step j at index j): alpha_j = T_jj,
+    // beta_{j+1} = T_{j+1,j}, gamma_{j+1} = T_{j,j+1}
+    std::vector<ZD> al((size_t)k + 2, ZD{0.0, 0.0}), ga((size_t)k + 2, ZD{0.0, 0.0});
+    std::vector<double> be((size_t)k + 2, 0.0);
+    for (int j = 0; j < k; ++j) {
+        al[j + 1] = ZD{diag[2 * j], diag[2 * j + 1]};
+        if (j + 1 < k) {
+            be[j + 2] = sub[j];
+            ga[j + 2] = ZD{sup[2 * j], sup[2 * j + 1]};
+        }
+    }
+    for (int j = 0; j < k; ++j)
+        if (!std::isfinite(al[j + 1].re) || !std::isfinite(al[j + 1].im) || !std::isfinite(be[j + 1]) ||
+            !std::isfinite(ga[j + 1].re) || !std::isfinite(ga[j + 1].im))
+            return fail(TSLOV_ERR_ARG, "the tridiagonal matrix contains non-finite values");
+    EntryStatus es;
+    es.k_used = k;
+    es.ritz = tslov::ritz_summary(k, reinterpret_cast<const double*>(al.data() + 1), be.data() + 1,
+                                  reinterpret_cast<const double*>(ga.data() + 1));
+    CHK(check_ritz(es));
+    CHK(ensure_work(c, 1, k, 0));
+    HIPCHK(hipMemcpyAsync(c->coef.alpha, al.data(), al.size() * sizeof(ZD), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->coef.gamma, ga.data(), ga.size() * sizeof(ZD), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->coef.beta, be.data(), be.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+    const SrcList L = make_list({0}, {k});
+    std::vector<int> iters, stag;
+    CHK(dense_step(c, L, 0, iters, &stag));
+    HIPCHK(hipMemcpyAsync(c_out, c->coef.c + 1, (size_t)k * sizeof(ZD), hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    es.iters = iters[0];
+    es.flags = entry_flags(c, es, stag[0], 0);
+    const double ms[6] = {0.0, now_ms() - t0, 0.0, 0.0, 0.0, now_ms() - t0};
+    fill_info(info, es, ms);
+    return TSLOV_OK;
+}
+
+tslov_status tslov_ritz_values(int k, const double* diag, const double* sub, const double* sup, double* out,
+                               int* sweeps) {
+    if (k < 1 || !diag || !out || (k > 1 && (!sub || !sup))) return fail(TSLOV_ERR_ARG, "bad argument");
+    std::vector<double> be((size_t)k, 0.0), ga((size_t)2 * k, 0.0);
+    for (int j = 1; j < k; ++j) {
+        be[j] = sub[j - 1];
+        ga[2 * j] = sup[2 * (j - 1)];
+        ga[2 * j + 1] = sup[2 * (j - 1) + 1];
+    }
+    const int sw = tslov::tridiag_eigvals(k, diag, be.data(), ga.data(), out);
+    if (sweeps) *sweeps = sw;
+    return TSLOV_OK;
+}
+
+tslov_status tslov_set_diagnostics(tslov_ctx* c, int flags) {
+    if (!c) return fail(TSLOV_ERR_ARG, "null context");
+    if (flags & ~TSLOV_DIAG_EPS_A) return fail(TSLOV_ERR_ARG, "unknown diagnostics flag");
+    c->diag = flags;
     return TSLOV_OK;
 }
 
@@ -1594,12 +1895,12 @@ tslov_status tslov_get_pair_ns(const tslov_ctx* c, int* fwd_ns, int* bwd_ns) {
 
 double tslov_kernel_bytes(const tslov_ctx* c, int which) {
     if (!c) return 0.0;
-    const double z = (double)c->zsize();
+    const double z = (double)c->zsize(), zl = (double)c->lsize();
     const double V = (double)c->g.V;
     switch (which) {
-        case 0: return V * (6 * 12 + 36) * z;           // read r, s, links; write v, w, a, b
-        case 1: return V * (12 * 12 + 36) * z;          // read 9 fields and links; write 3 fields
-        case 2: return V * (2 * 12 + 36) * z;           // read in and links; write out
+        case 0: return V * (6 * 12 * z + 36 * zl);      // read r, s, links; write v, w, a, b
+        case 1: return V * (12 * 12 * z + 36 * zl);     // read 9 fields and links; write 3 fields
+        case 2: return V * (2 * 12 * z + 36 * zl);      // read in and links; write out
         default: return 0.0;
     }
 }

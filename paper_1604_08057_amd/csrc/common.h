@@ -207,12 +207,14 @@ __device__ __forceinline__ void zero_spinor(Spinor<R>& p) {
         for (int c = 0; c < 3; ++c) p.c[sp][c] = mk<R>(0, 0);
 }
 
-template <typename R>
-__device__ __forceinline__ void load_link(Z<R> (&u)[3][3], const Z<R>* __restrict__ U, int ldv, int nu, int s) {
+// Links may be stored in a narrower type RL than the arithmetic type R (float
+// links with double fields); they are widened as they are loaded.
+template <typename R, typename RL>
+__device__ __forceinline__ void load_link(Z<R> (&u)[3][3], const Z<RL>* __restrict__ U, int ldv, int nu, int s) {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) u[a][b] = fload<R>(field_base(U), ldv, nu * 9 + a * 3 + b, (unsigned)s);
+        for (int b = 0; b < 3; ++b) u[a][b] = zcast<R>(fload<RL>(field_base(U), ldv, nu * 9 + a * 3 + b, (unsigned)s));
 }
 
 // ------------------------------------------------------------------ spin projection
@@ -334,17 +336,17 @@ __device__ __forceinline__ void hop1(Z<R> (&acc)[4], const Z<R> (&urow)[3], cons
     recon1_add<NU, S>(acc, o, coef);
 }
 
-template <typename R>
-__device__ __forceinline__ void load_row(Z<R> (&u)[3], const Z<R>* __restrict__ U, int ldv, int nu, int a, int s) {
+template <typename R, typename RL>
+__device__ __forceinline__ void load_row(Z<R> (&u)[3], const Z<RL>* __restrict__ U, int ldv, int nu, int a, int s) {
 #pragma unroll
-    for (int b = 0; b < 3; ++b) u[b] = fload<R>(field_base(U), ldv, nu * 9 + a * 3 + b, (unsigned)s);
+    for (int b = 0; b < 3; ++b) u[b] = zcast<R>(fload<RL>(field_base(U), ldv, nu * 9 + a * 3 + b, (unsigned)s));
 }
 
-template <typename R>
-__device__ __forceinline__ void load_col_conj(Z<R> (&u)[3], const Z<R>* __restrict__ U, int ldv, int nu, int a,
+template <typename R, typename RL>
+__device__ __forceinline__ void load_col_conj(Z<R> (&u)[3], const Z<RL>* __restrict__ U, int ldv, int nu, int a,
                                               int s) {
 #pragma unroll
-    for (int b = 0; b < 3; ++b) u[b] = cj(fload<R>(field_base(U), ldv, nu * 9 + b * 3 + a, (unsigned)s));
+    for (int b = 0; b < 3; ++b) u[b] = cj(zcast<R>(fload<RL>(field_base(U), ldv, nu * 9 + b * 3 + a, (unsigned)s)));
 }
 
 // Colour handled by this thread in the colour split: one wavefront per colour,

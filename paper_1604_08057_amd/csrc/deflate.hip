@@ -109,6 +109,23 @@ void launch_defl_finish(const ZD* R, const ZD* c, const double* sgn, const ZD* y
     hipLaunchKernelGGL(k_defl_finish, dim3(grid_for(V)), dim3(kBlock), 0, st, R, c, sgn, yp, psi, V, l, overlap, out);
 }
 
+// out = [a +] g5^{g5} b on canonical spinors (a nullable); out may be a or b.
+__global__ __launch_bounds__(kBlock) void k_combine(const ZD* a, const ZD* b, int g5, int V, ZD* out) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= V) return;
+#pragma unroll
+    for (int p = 0; p < 12; ++p) {
+        const size_t i = (size_t)s * 12 + p;
+        ZD o = ((g5 && p >= 6) ? -1.0 : 1.0) * b[i];
+        if (a) o = o + a[i];
+        out[i] = o;
+    }
+}
+
+void launch_combine(const ZD* a, const ZD* b, int g5, int V, ZD* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(V)), dim3(kBlock), 0, st, a, b, g5, V, out);
+}
+
 // Partials of |a - b|^2 and |b|^2 over n complex values (error estimate).
 __global__ __launch_bounds__(kBlock) void k_diff_norm(const ZD* __restrict__ a, const ZD* __restrict__ b, size_t n,
                                                       double* __restrict__ part) {

@@ -22,8 +22,8 @@ void timed_launch(K kernel, dim3 grid, dim3 block, hipStream_t st, Timing t, Arg
 __device__ __forceinline__ void mem_fence_compiler() { asm volatile("" ::: "memory"); }
 
 // One direction of the hopping sum for a single field.
-template <int NU, typename R>
-__device__ __forceinline__ void hop_dir(Spinor<R>& acc, const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+template <int NU, typename R, typename RL>
+__device__ __forceinline__ void hop_dir(Spinor<R>& acc, const Z<RL>* __restrict__ U, const Z<R>* __restrict__ in,
                                         const Geom& g, int s, const Nbr& n, R cf, R cb, int g5_in) {
     Z<R> u[3][3];
     Spinor<R> p;
@@ -39,8 +39,8 @@ __device__ __forceinline__ void hop_dir(Spinor<R>& acc, const Z<R>* __restrict__
 
 // One direction of the hopping sums of two fields sharing the link loads:
 // field A with chemical potential +mu, field B with -mu.
-template <int NU, typename R>
-__device__ __forceinline__ void hop_dir_pair(Spinor<R>& acca, Spinor<R>& accb, const Z<R>* __restrict__ U,
+template <int NU, typename R, typename RL>
+__device__ __forceinline__ void hop_dir_pair(Spinor<R>& acca, Spinor<R>& accb, const Z<RL>* __restrict__ U,
                                              const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
                                              const Geom& g, int s, const Nbr& n, R ep, R em) {
     const R fa_f = (NU == 3) ? ep : R(1), fa_b = (NU == 3) ? em : R(1);
@@ -61,25 +61,31 @@ __device__ __forceinline__ void hop_dir_pair(Spinor<R>& acca, Spinor<R>& accb, c
 }  // namespace
 
 // =============================================================== layout
+// A thread that meets a non-finite link element stores 1 into *bad (a plain store:
+// every writer writes the same value).
 __global__ __launch_bounds__(kBlock) void k_links_to_soa(const ZD* __restrict__ Uc, ZD* __restrict__ U64,
-                                                         Z<float>* __restrict__ U32, Geom g, int antiperiodic) {
+                                                         Z<float>* __restrict__ U32, Geom g, int antiperiodic,
+                                                         int* __restrict__ bad) {
     const int s = blockIdx.x * kBlock + threadIdx.x;
     const int nu = blockIdx.y;
     if (s >= g.V) return;
     double sign = 1.0;
     if (nu == 3 && antiperiodic && s / (g.nx * g.ny * g.nz) == g.nt - 1) sign = -1.0;
+    bool finite = true;
 #pragma unroll
     for (int ab = 0; ab < 9; ++ab) {
         const ZD u = sign * Uc[((size_t)nu * g.V + s) * 9 + ab];
+        finite = finite && std::isfinite(u.re) && std::isfinite(u.im);
         U64[(size_t)(nu * 9 + ab) * g.ldv + s] = u;
         if (U32) U32[(size_t)(nu * 9 + ab) * g.ldv + s] = zcast<float>(u);
     }
+    if (!finite) *bad = 1;
 }
 
-void launch_links_to_soa(const ZD* Ucanon, ZD* U64, Z<float>* U32, const Geom& g, int antiperiodic,
+void launch_links_to_soa(const ZD* Ucanon, ZD* U64, Z<float>* U32, const Geom& g, int antiperiodic, int* bad,
                          hipStream_t st) {
     dim3 grid(grid_for(g.V), 4);
-    hipLaunchKernelGGL(k_links_to_soa, grid, dim3(kBlock), 0, st, Ucanon, U64, U32, g, antiperiodic);
+    hipLaunchKernelGGL(k_links_to_soa, grid, dim3(kBlock), 0, st, Ucanon, U64, U32, g, antiperiodic, bad);
 }
 
 template <typename R>
@@ -157,8 +163,8 @@ __device__ __forceinline__ void zero1(Z<R> (&p)[4]) {
 
 // Both hops of direction NU for two fields sharing the link rows: field A at +mu,
 // field B at -mu (the temporal factors swap).
-template <int NU, typename R>
-__device__ __forceinline__ void hop_dir_pair1(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
+template <int NU, typename R, typename RL>
+__device__ __forceinline__ void hop_dir_pair1(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<RL>* __restrict__ U,
                                               const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
                                               const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
     const R up = (NU == 3) ? ep : R(1), dn = (NU == 3) ? em : R(1);
@@ -183,8 +189,8 @@ __device__ __forceinline__ void hop_dir_pair1(Z<R> (&acca)[4], Z<R> (&accb)[4], 
 // round trip per direction instead of one per loaded operand, at the cost of
 // holding all operands of a direction in registers.  The pair version below does
 // the same for two fields sharing the link rows.
-template <int NU, typename R>
-__device__ __forceinline__ void hop_dir1_eager(Z<R> (&acc)[4], const Z<R>* __restrict__ U,
+template <int NU, typename R, typename RL>
+__device__ __forceinline__ void hop_dir1_eager(Z<R> (&acc)[4], const Z<RL>* __restrict__ U,
                                                const Z<R>* __restrict__ f, const Geom& g, int s, int a, const Nbr& n,
                                                R cf, R cb, int g5_in) {
     Z<R> uf[3], ub[3];
@@ -206,8 +212,8 @@ __device__ __forceinline__ void hop_dir1_eager(Z<R> (&acc)[4], const Z<R>* __res
 // -mu), a rolled loop over a wavefront-uniform switch: the colour split, with
 // several wavefronts per SIMD, so one operand's loads in flight at a time and few
 // registers.  (The colour grid's pair kernels use hop_two_dirs_pair_eager.)
-template <int BLK, typename R>
-__device__ __forceinline__ void hop_all_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
+template <int BLK, typename R, typename RL>
+__device__ __forceinline__ void hop_all_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<RL>* __restrict__ U,
                                              const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
                                              const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
 #pragma unroll 1
@@ -225,8 +231,8 @@ __device__ __forceinline__ void hop_all_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], c
 // operands (four link rows, eight neighbour spinors) issued before any arithmetic,
 // one memory round trip for both directions.  Needs more than 256 registers: for
 // kernels whose grid leaves one wavefront per SIMD anyway (the colour grid).
-template <int NU0, int NU1, typename R>
-__device__ __forceinline__ void hop_two_dirs_pair_eager(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
+template <int NU0, int NU1, typename R, typename RL>
+__device__ __forceinline__ void hop_two_dirs_pair_eager(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<RL>* __restrict__ U,
                                                         const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
                                                         const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
     const R up0 = (NU0 == 3) ? ep : R(1), dn0 = (NU0 == 3) ? em : R(1);
@@ -258,8 +264,8 @@ __device__ __forceinline__ void hop_two_dirs_pair_eager(Z<R> (&acca)[4], Z<R> (&
 
 // Colour-grid pair kernels: hop wavefront h (0 or 1) takes directions 2h and 2h + 1,
 // all their operands in one round trip.
-template <typename R>
-__device__ __forceinline__ void hop_half_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<R>* __restrict__ U,
+template <typename R, typename RL>
+__device__ __forceinline__ void hop_half_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<RL>* __restrict__ U,
                                               const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
                                               const Geom& g, int s, int a, const Nbr& n, R ep, R em, int half) {
     if (half == 0)
@@ -272,8 +278,8 @@ __device__ __forceinline__ void hop_half_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], 
 // loaded once and applied to the 2*NS fields (A_q at +mu, B_q at -mu) of the
 // entries whose bit is set in the block-uniform mask `live`.  Each accumulator
 // receives the same operations in the same order as with one entry.
-template <int NU, int NS, typename R>
-__device__ __forceinline__ void hop_dir_pairN(Z<R> (&acca)[NS][4], Z<R> (&accb)[NS][4], const Z<R>* __restrict__ U,
+template <int NU, int NS, typename R, typename RL>
+__device__ __forceinline__ void hop_dir_pairN(Z<R> (&acca)[NS][4], Z<R> (&accb)[NS][4], const Z<RL>* __restrict__ U,
                                               const Z<R>* const (&fa)[NS], const Z<R>* const (&fb)[NS],
                                               unsigned live, const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
     const R up = (NU == 3) ? ep : R(1), dn = (NU == 3) ? em : R(1);
@@ -301,8 +307,8 @@ __device__ __forceinline__ void hop_dir_pairN(Z<R> (&acca)[NS][4], Z<R> (&accb)[
     }
 }
 
-template <int NS, typename R>
-__device__ __forceinline__ void hop_all_pairN(Z<R> (&acca)[NS][4], Z<R> (&accb)[NS][4], const Z<R>* __restrict__ U,
+template <int NS, typename R, typename RL>
+__device__ __forceinline__ void hop_all_pairN(Z<R> (&acca)[NS][4], Z<R> (&accb)[NS][4], const Z<RL>* __restrict__ U,
                                               const Z<R>* const (&fa)[NS], const Z<R>* const (&fb)[NS],
                                               unsigned live, const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
 #pragma unroll 1
@@ -336,8 +342,8 @@ __device__ __forceinline__ unsigned block_live(const Coef& coef0, const SrcList&
 
 // =============================================================== operator
 // Colour grid (small lattices): block (a, b) forms colour a of site block b.
-template <typename R>
-__global__ __launch_bounds__(kSites) void k_apply(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+template <typename R, typename RL>
+__global__ __launch_bounds__(kSites) void k_apply(const Z<RL>* __restrict__ U, const Z<R>* __restrict__ in,
                                                   Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em, int g5_in,
                                                   int g5_out) {
     const int a = sten_colour<kSites>();
@@ -374,8 +380,8 @@ __global__ __launch_bounds__(kSites) void k_apply(const Z<R>* __restrict__ U, co
 // each XCD takes the same run of them in every slice, slice after slice, so that a
 // site's t-neighbours were read one run earlier on the same L2; otherwise each
 // XCD takes a contiguous run of the lattice.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_apply_site(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+template <typename R, typename RL>
+__global__ __launch_bounds__(kBlock) void k_apply_site(const Z<RL>* __restrict__ U, const Z<R>* __restrict__ in,
                                                        Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em,
                                                        int g5_in, int g5_out, int slice_order) {
     int sb;
@@ -450,8 +456,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_site(const Z<R>* __restrict__ 
 
 // Both hops of direction NU for a whole site, with the four operands' loads
 // issued before any arithmetic (one memory round trip per direction).
-template <int NU, typename R>
-__device__ __forceinline__ void tm_hops_eager(Spinor<R>& acc, const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+template <int NU, typename R, typename RL>
+__device__ __forceinline__ void tm_hops_eager(Spinor<R>& acc, const Z<RL>* __restrict__ U, const Z<R>* __restrict__ in,
                                               const Geom& g, int s, int sf, int sb, int g5_in) {
     Z<R> uf[3][3], ub[3][3];
     Spinor<R> pf, pb;
@@ -478,8 +484,8 @@ __device__ __forceinline__ void tm_hops_eager(Spinor<R>& acc, const Z<R>* __rest
 // with the same operations, so the two kernels give identical results.  Block
 // b works on tile (b mod 8) * per + (b / 8) mod per of chunk b / (8 per): each XCD
 // takes the same run of tiles (a slab of z-planes) in every chunk.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_apply_tmarch(const Z<R>* __restrict__ U, const Z<R>* __restrict__ in,
+template <typename R, typename RL>
+__global__ __launch_bounds__(kBlock) void k_apply_tmarch(const Z<RL>* __restrict__ U, const Z<R>* __restrict__ in,
                                                          Z<R>* __restrict__ out, Geom g, R kappa, R ep, R em,
                                                          int g5_in, int g5_out, int T) {
     const int V3 = g.nx * g.ny * g.nz, per = V3 / kBlock / kXcd, m = blockIdx.x / kXcd;
@@ -611,20 +617,20 @@ int tmarch_chunks(const Geom& g, int* T, int maxn) {
     return n;
 }
 
-template <typename R>
-void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu, int g5_in,
+template <typename R, typename RL>
+void launch_apply(const Z<RL>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu, int g5_in,
                   int g5_out, hipStream_t st, Timing t, int tm_T) {
     if (colour_grid(g.V)) {
-        timed_launch(k_apply<R>, dim3(np_sten(g.V)), dim3(kSites), st, t, U, in, out, g, (R)kappa,
+        timed_launch(k_apply<R, RL>, dim3(np_sten(g.V)), dim3(kSites), st, t, U, in, out, g, (R)kappa,
                      (R)std::exp(mu), (R)std::exp(-mu), g5_in, g5_out);
     } else if (const int T = tmarch_chunk(g) ? (tm_T > 0 && g.nt % tm_T == 0 ? tm_T : tmarch_chunk(g)) : 0) {
         const int nb = g.nx * g.ny * g.nz / kBlock * (g.nt / T);
-        timed_launch(k_apply_tmarch<R>, dim3(nb), dim3(kBlock), st, t, U, in, out, g, (R)kappa, (R)std::exp(mu),
+        timed_launch(k_apply_tmarch<R, RL>, dim3(nb), dim3(kBlock), st, t, U, in, out, g, (R)kappa, (R)std::exp(mu),
                      (R)std::exp(-mu), g5_in, g5_out, T);
     } else {
         const int nb = (grid_for(g.V) + kXcd - 1) / kXcd * kXcd;
         const int slice = (g.nx * g.ny * g.nz) % (kBlock * kXcd) == 0;   // t-slices split evenly over XCDs
-        timed_launch(k_apply_site<R>, dim3(nb), dim3(kBlock), st, t, U, in, out, g, (R)kappa, (R)std::exp(mu),
+        timed_launch(k_apply_site<R, RL>, dim3(nb), dim3(kBlock), st, t, U, in, out, g, (R)kappa, (R)std::exp(mu),
                      (R)std::exp(-mu), g5_in, g5_out, slice);
     }
 }
@@ -707,10 +713,10 @@ __device__ __forceinline__ void fwd_pair_finish(const Geom& g, double kappa, con
     const ZD om = mk<double>(red[0], red[1]);
     const double rn2 = red[2], sn2 = red[3];
     const double aom = std::sqrt(norm2(om));
-    if (first && !(rn2 > 0.0)) {   // zero source: empty Krylov space, nothing to do
+    if (first && !(rn2 > 0.0 && std::isfinite(rn2))) {   // zero (or non-finite) source
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             coef.status[1] = 0;
-            coef.status[2] = 1;
+            coef.status[2] = rn2 == 0.0 ? 1 : 3;   // 1: empty Krylov space, nothing to do; 3: not finite
             coef.status[3] = 1;
             coef.misc[0] = 0.0;
             *(volatile int*)coef.status = 1;
@@ -799,10 +805,10 @@ __device__ __forceinline__ void fwd_pair_finish_pre(const Geom& g, double kappa,
     const ZD om = mk<double>(red[0], red[1]);
     const double rn2 = red[2], sn2 = red[3];
     const double aom = std::sqrt(norm2(om));
-    if (first && !(rn2 > 0.0)) {   // zero source: empty Krylov space, nothing to do
+    if (first && !(rn2 > 0.0 && std::isfinite(rn2))) {   // zero (or non-finite) source
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             coef.status[1] = 0;
-            coef.status[2] = 1;
+            coef.status[2] = rn2 == 0.0 ? 1 : 3;   // 1: empty Krylov space, nothing to do; 3: not finite
             coef.status[3] = 1;
             coef.misc[0] = 0.0;
             *(volatile int*)coef.status = 1;
@@ -879,9 +885,9 @@ __device__ __forceinline__ void fwd_pair_finish_pre(const Geom& g, double kappa,
 // (directions 0, 1 first) and runs the epilogue.  The hops do not depend on the sums
 // or the flag (normalisation and breakdown act in the epilogue): a stopped entry's
 // hops are discarded.
-template <typename R>
+template <typename R, typename RL>
 __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu, Work<R> wk, SrcList L, Coef coef0,
+void k_fwd_pair(const Z<RL>* __restrict__ U, Geom g, double kappa, double emu, Work<R> wk, SrcList L, Coef coef0,
                 int j, int npart_in, int has_eta, int replay) {
     const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kSites);
     const int slot = L.slot[blockIdx.y];
@@ -935,8 +941,8 @@ void k_fwd_pair(const Z<R>* __restrict__ U, Geom g, double kappa, double emu, Wo
 
 // Colour split: NS entries per workgroup (entries NS*blockIdx.y + q), which share
 // every link load; the partial-sum slot is the site block.
-template <typename R, int NS>
-__global__ __launch_bounds__(kCBlock) void k_fwd_pair_ms(const Z<R>* __restrict__ U, Geom g, double kappa,
+template <typename R, int NS, typename RL>
+__global__ __launch_bounds__(kCBlock) void k_fwd_pair_ms(const Z<RL>* __restrict__ U, Geom g, double kappa,
                                                          double emu, Work<R> wk, SrcList L, Coef coef0, int j,
                                                          int npart_in, int has_eta, int replay_arg) {
     const int replay = NS == 1 ? replay_arg : 0;   // regeneration runs one entry per workgroup
@@ -988,42 +994,42 @@ __global__ __launch_bounds__(kCBlock) void k_fwd_pair_ms(const Z<R>* __restrict_
     }
 }
 
-template <typename R>
-void fwd_pair_launch(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+template <typename R, typename RL>
+void fwd_pair_launch(const Z<RL>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
                      Coef coef, int j, int has_eta, int ns, int replay, hipStream_t st, Timing t) {
     const int npart_in = j == 1 ? grid_for(g.V) : np_point(g.V);
     const double emu = std::exp(mu);
     if (colour_grid(g.V)) {
-        timed_launch(k_fwd_pair<R>, dim3(np_colour(g.V), L.n), dim3(kRBlock), st, t, U, g, kappa, emu, wk,
+        timed_launch(k_fwd_pair<R, RL>, dim3(np_colour(g.V), L.n), dim3(kRBlock), st, t, U, g, kappa, emu, wk,
                      L, coef, j, npart_in, has_eta, replay);
         return;
     }
     const dim3 block(kCBlock);
     switch (ns) {
         case 4:
-            timed_launch(k_fwd_pair_ms<R, 4>, dim3(g.nwg, (L.n + 3) / 4), block, st, t, U, g, kappa, emu, wk, L, coef,
+            timed_launch(k_fwd_pair_ms<R, 4, RL>, dim3(g.nwg, (L.n + 3) / 4), block, st, t, U, g, kappa, emu, wk, L, coef,
                          j, npart_in, has_eta, replay);
             break;
         case 2:
-            timed_launch(k_fwd_pair_ms<R, 2>, dim3(g.nwg, (L.n + 1) / 2), block, st, t, U, g, kappa, emu, wk, L, coef,
+            timed_launch(k_fwd_pair_ms<R, 2, RL>, dim3(g.nwg, (L.n + 1) / 2), block, st, t, U, g, kappa, emu, wk, L, coef,
                          j, npart_in, has_eta, replay);
             break;
         default:
-            timed_launch(k_fwd_pair_ms<R, 1>, dim3(g.nwg, L.n), block, st, t, U, g, kappa, emu, wk, L, coef, j,
+            timed_launch(k_fwd_pair_ms<R, 1, RL>, dim3(g.nwg, L.n), block, st, t, U, g, kappa, emu, wk, L, coef, j,
                          npart_in, has_eta, replay);
     }
 }
 
-template <typename R>
-void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+template <typename R, typename RL>
+void launch_fwd_pair(const Z<RL>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
                      Coef coef, int j, int has_eta, int ns, hipStream_t st, Timing t) {
     fwd_pair_launch<R>(U, g, kappa, mu, wk, L, coef, j, has_eta, ns, 0, st, t);
 }
 
 // Replay of step j for regeneration: the step's own kernel with the replay flag,
 // one entry per workgroup (the shape a single-source step runs with).
-template <typename R>
-void launch_fwd_replay(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+template <typename R, typename RL>
+void launch_fwd_replay(const Z<RL>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
                        Coef coef, int j, hipStream_t st) {
     fwd_pair_launch<R>(U, g, kappa, mu, wk, L, coef, j, 0, 1, 1, st, Timing{});
 }
@@ -1442,9 +1448,9 @@ __device__ __forceinline__ void bwd_rb_finish(const Geom& g, double kappa, const
 // partials of Re vbar_j^H v_j and wbar_j^H w_j.  The last step (j = k_used) has
 // no residual adjoints: abar = alphabar w, vbar = |x| conj(c) eta + alphabar b,
 // wbar = conj(alphabar) a.
-template <typename R, bool LAST, int BLK>
+template <typename R, bool LAST, int BLK, typename RL>
 __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(1, 8)))
-void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
+void k_bwd_rb(const Z<RL>* __restrict__ U, Geom g, double kappa, double emu,
                                                     Work<R> wk, SrcList L, Coef coef0, int j, int npart_in) {
     const int e = blockIdx.y, slot = L.slot[e];
     const Coef coef = coef0.at(slot);
@@ -1480,9 +1486,9 @@ void k_bwd_rb(const Z<R>* __restrict__ U, Geom g, double kappa, double emu,
 // LDS.  Wavefront 0 meanwhile gathers the partial sums and loads the epilogue's nine
 // own-site fields, so that round trip overlaps the hops; after the one barrier it
 // adds the two halves (directions 0, 1 first) and runs the epilogue.
-template <typename R>
+template <typename R, typename RL>
 __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void k_bwd_rb_cg(const Z<R>* __restrict__ U, Geom g, double kappa, double emu, Work<R> wk, SrcList L, Coef coef0,
+void k_bwd_rb_cg(const Z<RL>* __restrict__ U, Geom g, double kappa, double emu, Work<R> wk, SrcList L, Coef coef0,
                  int j, int npart_in) {
     const int e = blockIdx.y, slot = L.slot[e];
     const int ncb = gridDim.x / 3;   // colour-major grid, as sten_block / sten_colour for the colour grid
@@ -1531,8 +1537,8 @@ void k_bwd_rb_cg(const Z<R>* __restrict__ U, Geom g, double kappa, double emu, W
 }
 
 // Colour split, not the last step: NS entries per workgroup sharing the link loads.
-template <typename R, int NS>
-__global__ __launch_bounds__(kCBlock) void k_bwd_rb_ms(const Z<R>* __restrict__ U, Geom g, double kappa,
+template <typename R, int NS, typename RL>
+__global__ __launch_bounds__(kCBlock) void k_bwd_rb_ms(const Z<RL>* __restrict__ U, Geom g, double kappa,
                                                        double emu, Work<R> wk, SrcList L, Coef coef0, int j,
                                                        int npart_in) {
     const int e0 = (int)blockIdx.y * NS;
@@ -1576,27 +1582,27 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb_ms(const Z<R>* __restrict__ 
     }
 }
 
-template <typename R>
-void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+template <typename R, typename RL>
+void launch_bwd_rb(const Z<RL>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
                    Coef coef, int j, int last, int ns, hipStream_t st, Timing t) {
     const int np = np_point(g.V);
     const bool cg = colour_grid(g.V);
     const double emu = std::exp(mu);
     const dim3 grid(cg ? np_colour(g.V) : g.nwg, L.n);
     if (last && cg)
-        timed_launch(k_bwd_rb<R, true, kSites>, grid, dim3(kSites), st, t, U, g, kappa, emu, wk, L, coef, j, np);
+        timed_launch(k_bwd_rb<R, true, kSites, RL>, grid, dim3(kSites), st, t, U, g, kappa, emu, wk, L, coef, j, np);
     else if (last)
-        timed_launch(k_bwd_rb<R, true, kCBlock>, grid, dim3(kCBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
+        timed_launch(k_bwd_rb<R, true, kCBlock, RL>, grid, dim3(kCBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
     else if (cg)
-        timed_launch(k_bwd_rb_cg<R>, grid, dim3(kRBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
+        timed_launch(k_bwd_rb_cg<R, RL>, grid, dim3(kRBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
     else if (ns == 4)
-        timed_launch(k_bwd_rb_ms<R, 4>, dim3(g.nwg, (L.n + 3) / 4), dim3(kCBlock), st, t, U, g, kappa, emu, wk, L,
+        timed_launch(k_bwd_rb_ms<R, 4, RL>, dim3(g.nwg, (L.n + 3) / 4), dim3(kCBlock), st, t, U, g, kappa, emu, wk, L,
                      coef, j, np);
     else if (ns == 2)
-        timed_launch(k_bwd_rb_ms<R, 2>, dim3(g.nwg, (L.n + 1) / 2), dim3(kCBlock), st, t, U, g, kappa, emu, wk, L,
+        timed_launch(k_bwd_rb_ms<R, 2, RL>, dim3(g.nwg, (L.n + 1) / 2), dim3(kCBlock), st, t, U, g, kappa, emu, wk, L,
                      coef, j, np);
     else
-        timed_launch(k_bwd_rb_ms<R, 1>, dim3(g.nwg, L.n), dim3(kCBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
+        timed_launch(k_bwd_rb_ms<R, 1, RL>, dim3(g.nwg, L.n), dim3(kCBlock), st, t, U, g, kappa, emu, wk, L, coef, j, np);
 }
 
 // =============================================================== force contraction
@@ -1888,30 +1894,73 @@ void launch_source_grad(const Geom& g, const Work<R>& wk, const SrcList& L, Coef
     hipLaunchKernelGGL(k_sgrad_out<R>, dim3(nb, L.n), dim3(kBlock), 0, st, g, wk, L, coef, nb, dpsi);
 }
 
+// =============================================================== biorthogonality probe
+// After the forward pass, with k = k_used read on the device: block partials of
+// x^H v_k and w_k^H x for the entry's source x = f(slot, 0) (so that with
+// v_1 = w_1 = x/|x| they give w_1^H v_k and w_k^H v_1 up to the factor 1/|x|),
+// zeros for k_used < 2, into wk.p(slot, 3)[block * 4].
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_biorth(Geom g, Work<R> wk, SrcList L, Coef coef0) {
+    const int e = blockIdx.y, slot = L.slot[e];
+    const int ku = coef0.at(slot).status[1];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (ku >= 2 && s < g.V) {
+        const Z<R>* x = wk.f(slot, 0);
+        const Z<R>* vk = wk.v(slot, ku);
+        const Z<R>* wkk = wk.w(slot, ku);
+#pragma unroll
+        for (int p = 0; p < 12; ++p) {
+            const ZD xs = zcast<double>(x[(size_t)p * g.ldv + s]);
+            const ZD xv = cjmul(xs, zcast<double>(vk[(size_t)p * g.ldv + s]));
+            const ZD wx = cjmul(zcast<double>(wkk[(size_t)p * g.ldv + s]), xs);
+            v[0] += xv.re;
+            v[1] += xv.im;
+            v[2] += wx.re;
+            v[3] += wx.im;
+        }
+    }
+    write_partials_at<4, kBlock>(wk.p(slot, 3), blockIdx.x, v);
+}
+
+template <typename R>
+int launch_biorth(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, hipStream_t st) {
+    const int nb = grid_for(g.V);
+    hipLaunchKernelGGL(k_biorth<R>, dim3(nb, L.n), dim3(kBlock), 0, st, g, wk, L, coef);
+    return nb;
+}
+
 // =============================================================== instantiations
 #define TSLOV_INST(R)                                                                                           \
     template void launch_spinor_to_soa<R>(const ZD*, Z<R>*, const Geom&, double*, hipStream_t);                 \
     template void launch_spinor_from_soa<R>(const Z<R>*, ZD*, const Geom&, hipStream_t);                        \
-    template void launch_apply<R>(const Z<R>*, const Z<R>*, Z<R>*, const Geom&, double, double, int, int,       \
-                                  hipStream_t, Timing, int);                                                    \
     template void launch_sources_to_soa<R>(const ZD*, int, int, const Work<R>&, const SrcList&, const Geom&,    \
                                            hipStream_t);                                                        \
-    template void launch_fwd_pair<R>(const Z<R>*, const Geom&, double, double, const Work<R>&, const SrcList&,  \
-                                     Coef, int, int, int, hipStream_t, Timing);                                 \
     template void launch_recur<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);         \
-    template void launch_fwd_replay<R>(const Z<R>*, const Geom&, double, double, const Work<R>&,                \
-                                       const SrcList&, Coef, int, hipStream_t);                                 \
     template void launch_recur_replay<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);  \
     template void launch_assemble<R>(const Geom&, const Work<R>&, const SrcList&, Coef, const ZD*, int, ZD*,    \
                                      hipStream_t);                                                              \
     template void launch_bwd_ra<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);        \
-    template void launch_bwd_rb<R>(const Z<R>*, const Geom&, double, double, const Work<R>&, const SrcList&,    \
-                                   Coef, int, int, int, hipStream_t, Timing);                                   \
     template void launch_force<R>(const Geom&, double, double, const Work<R>&, const SrcList&, int, ZD*,        \
                                   hipStream_t, int, int, int);                                                  \
-    template void launch_source_grad<R>(const Geom&, const Work<R>&, const SrcList&, Coef, ZD*, hipStream_t);
+    template void launch_source_grad<R>(const Geom&, const Work<R>&, const SrcList&, Coef, ZD*, hipStream_t);   \
+    template int launch_biorth<R>(const Geom&, const Work<R>&, const SrcList&, Coef, hipStream_t);
+
+// The stencil launchers for fields of type R and links of type RL.
+#define TSLOV_INST_STENCIL(R, RL)                                                                               \
+    template void launch_apply<R, RL>(const Z<RL>*, const Z<R>*, Z<R>*, const Geom&, double, double, int, int,  \
+                                      hipStream_t, Timing, int);                                                \
+    template void launch_fwd_pair<R, RL>(const Z<RL>*, const Geom&, double, double, const Work<R>&,             \
+                                         const SrcList&, Coef, int, int, int, hipStream_t, Timing);             \
+    template void launch_fwd_replay<R, RL>(const Z<RL>*, const Geom&, double, double, const Work<R>&,           \
+                                           const SrcList&, Coef, int, hipStream_t);                             \
+    template void launch_bwd_rb<R, RL>(const Z<RL>*, const Geom&, double, double, const Work<R>&,               \
+                                       const SrcList&, Coef, int, int, int, hipStream_t, Timing);
 
 TSLOV_INST(double)
 TSLOV_INST(float)
+TSLOV_INST_STENCIL(double, double)
+TSLOV_INST_STENCIL(float, float)
+TSLOV_INST_STENCIL(double, float)
 
 }  // namespace tslov

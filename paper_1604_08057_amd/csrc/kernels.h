@@ -15,7 +15,8 @@ struct Timing {
 };
 
 // ---------------------------------------------------------------- layout
-void launch_links_to_soa(const ZD* Ucanon, ZD* U64, Z<float>* U32, const Geom& g, int antiperiodic,
+// Also stores 1 into *bad (device int) if some link element is not finite.
+void launch_links_to_soa(const ZD* Ucanon, ZD* U64, Z<float>* U32, const Geom& g, int antiperiodic, int* bad,
                          hipStream_t st);
 template <typename R>
 void launch_spinor_to_soa(const ZD* in, Z<R>* out, const Geom& g, double* part_norm, hipStream_t st);
@@ -24,8 +25,8 @@ void launch_spinor_from_soa(const Z<R>* in, ZD* out, const Geom& g, hipStream_t 
 
 // ---------------------------------------------------------------- operator
 // out = G5out * (G5in in - kappa * hop_{mu}(G5in in))
-template <typename R>
-void launch_apply(const Z<R>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu,
+template <typename R, typename RL>
+void launch_apply(const Z<RL>* U, const Z<R>* in, Z<R>* out, const Geom& g, double kappa, double mu,
                   int g5_in, int g5_out, hipStream_t st, Timing t = {}, int tm_T = 0);
 // The t-slices per chunk the t-march operator can run this lattice with (each
 // gives the same result), at most maxn of them into T; 0 when it does not apply.
@@ -89,8 +90,8 @@ void launch_sources_to_soa(const ZD* canon, int which, int g5, const Work<R>& wk
 // Step j of the Lanczos process for every list entry (k[e] = the entry's target size).
 // ns: entries per workgroup on the colour-split layout (1, 2 or 4), which share the
 // link loads; an entry's results do not depend on it.
-template <typename R>
-void launch_fwd_pair(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+template <typename R, typename RL>
+void launch_fwd_pair(const Z<RL>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
                      Coef coef, int j, int has_eta, int ns, hipStream_t st, Timing t = {});
 template <typename R>
 void launch_recur(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st);
@@ -99,8 +100,8 @@ void launch_recur(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef,
 // their reductions, rewriting v_j, w_j, a_j, b_j (fwd) and the residuals of step j
 // for entries with j < k[e] (recur) bit for bit, and no partial sums, flags or
 // coefficient records.
-template <typename R>
-void launch_fwd_replay(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+template <typename R, typename RL>
+void launch_fwd_replay(const Z<RL>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
                        Coef coef, int j, hipStream_t st);
 template <typename R>
 void launch_recur_replay(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st);
@@ -108,6 +109,12 @@ void launch_recur_replay(const Geom& g, const Work<R>& wk, const SrcList& L, Coe
 template <typename R>
 void launch_assemble(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, const ZD* psi_canon,
                      int overlap, ZD* out, hipStream_t st);
+
+// Biorthogonality probe of every entry after its forward pass: block partials
+// (x^H v_k re, im, w_k^H x re, im), k = k_used (zeros below 2), in wk.p(slot, 3).
+// Returns the number of blocks.
+template <typename R>
+int launch_biorth(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, hipStream_t st);
 
 // ---------------------------------------------------------------- backward
 constexpr int kNvRA = 8;   // P1..P4 complex
@@ -117,8 +124,8 @@ constexpr int kNvRB = 3;   // Re(vbar^H v), (wbar^H w) re/im
 // bwd_rb for entries with j <= k_used (last = 1: j == k_used for every entry).
 template <typename R>
 void launch_bwd_ra(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st);
-template <typename R>
-void launch_bwd_rb(const Z<R>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
+template <typename R, typename RL>
+void launch_bwd_rb(const Z<RL>* U, const Geom& g, double kappa, double mu, const Work<R>& wk, const SrcList& L,
                    Coef coef, int j, int last, int ns, hipStream_t st, Timing t = {});
 // Per-link force partials gpart[slot][chunk][36 planes] over the steps j of
 // [jlo, min(jhi, k[e])] of each entry (jhi = 0: every step), stored, or added to
@@ -156,6 +163,8 @@ void launch_defl_project(const ZD* R, const ZD* psi, const ZD* c, int V, int l, 
 void launch_defl_finish(const ZD* R, const ZD* c, const double* sgn, const ZD* yp, const ZD* psi, int V, int l,
                         int overlap, ZD* out, hipStream_t st);
 int launch_diff_norm(const ZD* a, const ZD* b, size_t n, double* part, hipStream_t st);
+// out = [a +] g5^{g5} b on canonical spinors of V sites (a nullable; out may alias a or b).
+void launch_combine(const ZD* a, const ZD* b, int g5, int V, ZD* out, hipStream_t st);
 
 // ---------------------------------------------------------------- deflated derivative
 // Batched CGNR for (sigma_e - H(m_e mu)) x_e = b_e, one system per grid row e.

@@ -23,7 +23,11 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtslov.so
 OK, ERR_ARG, ERR_HIP, ERR_OOM, ERR_BREAKDOWN, ERR_SIGN_UNDEFINED, ERR_NOT_CONVERGED = range(7)
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_OOM", 4: "ERR_BREAKDOWN",
                 5: "ERR_SIGN_UNDEFINED", 6: "ERR_NOT_CONVERGED"}
-PRECISIONS = {"fp64": 0, "mixed": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1, "fp32links": 2}
+
+# Bits of Info.flags and of tslov_set_diagnostics.
+FLAG_SIGN_STAGNATED, FLAG_GRAD_FP32_VECTORS, FLAG_RITZ_UNSETTLED = 1, 2, 4
+DIAG_EPS_A = 1
 
 # Kernel classes of tslov_timing_read / tslov_kernel_bytes.
 KERNEL_FWD_PAIR, KERNEL_BWD_PAIR, KERNEL_APPLY = 0, 1, 2
@@ -32,7 +36,8 @@ EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links
            "tslov_apply_h", "tslov_sign", "tslov_overlap", "tslov_sign_grad", "tslov_sign_grad_batched",
            "tslov_current_estimate", "tslov_error_estimate", "tslov_lanczos_matrix", "tslov_dense_sign", "tslov_timing_enable",
            "tslov_timing_read", "tslov_kernel_bytes", "tslov_set_pair_ns", "tslov_get_pair_ns", "tslov_set_graphs", "tslov_set_apply_chunk",
-           "tslov_get_apply_chunk"]
+           "tslov_get_apply_chunk", "tslov_overlap_grad", "tslov_tridiag_sign", "tslov_ritz_values",
+           "tslov_set_diagnostics"]
 
 
 class TslovLibraryMissing(ImportError):
@@ -52,8 +57,9 @@ class LatticeDesc(ctypes.Structure):
 
 class InfoStruct(ctypes.Structure):
     _fields_ = [("k_used", ctypes.c_int), ("breakdown", ctypes.c_int), ("newton_iters", ctypes.c_int),
-                ("reserved", ctypes.c_int), ("norm_x", ctypes.c_double), ("biorth_err", ctypes.c_double),
-                ("ms", ctypes.c_double * 6)]
+                ("cg_iters", ctypes.c_int), ("flags", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("norm_x", ctypes.c_double), ("min_abs_re_ritz", ctypes.c_double), ("norm_T", ctypes.c_double),
+                ("biorth_err", ctypes.c_double), ("eps_A", ctypes.c_double), ("ms", ctypes.c_double * 6)]
 
 
 class DeflationStruct(ctypes.Structure):
@@ -68,11 +74,17 @@ class Info:
     newton_iters: int
     norm_x: float
     ms: tuple
-    reserved: int = 0   # shifted-solve iterations of the deflated derivative
+    cg_iters: int = 0            # shifted-solve iterations of the deflated derivative
+    flags: int = 0               # FLAG_* bits
+    min_abs_re_ritz: float = float("nan")
+    norm_T: float = float("nan")
+    biorth_err: float = 0.0
+    eps_A: float = float("nan")
 
     @classmethod
     def of(cls, s: InfoStruct) -> "Info":
-        return cls(s.k_used, s.breakdown, s.newton_iters, s.norm_x, tuple(s.ms), s.reserved)
+        return cls(s.k_used, s.breakdown, s.newton_iters, s.norm_x, tuple(s.ms), s.cg_iters, s.flags,
+                   s.min_abs_re_ritz, s.norm_T, s.biorth_err, s.eps_A)
 
 
 _lib = None
@@ -97,10 +109,17 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_apply_h": ([vp, vp, vp, ci], ci),
         "tslov_sign": ([vp, vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(InfoStruct)], ci),
         "tslov_overlap": ([vp, vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(InfoStruct)], ci),
-        "tslov_sign_grad": ([vp, vp, vp, ci, ctypes.POINTER(DeflationStruct), ci, ctypes.POINTER(cd), vp, vp,
+        "tslov_sign_grad": ([vp, vp, vp, ci, ctypes.POINTER(DeflationStruct), ci, ctypes.POINTER(cd), vp, vp, vp,
                              ctypes.POINTER(InfoStruct)], ci),
-        "tslov_sign_grad_batched": ([vp, ci, vp, vp, ctypes.POINTER(ci), ctypes.POINTER(cd), vp, vp,
+        "tslov_overlap_grad": ([vp, vp, vp, ci, ctypes.POINTER(DeflationStruct), ci, ctypes.POINTER(cd), vp, vp, vp,
+                                ctypes.POINTER(InfoStruct)], ci),
+        "tslov_sign_grad_batched": ([vp, ci, vp, vp, ctypes.POINTER(ci), ctypes.POINTER(cd), vp, vp, vp,
                                      ctypes.POINTER(InfoStruct)], ci),
+        "tslov_tridiag_sign": ([vp, ci, ctypes.POINTER(cd), ctypes.POINTER(cd), ctypes.POINTER(cd), vp,
+                                ctypes.POINTER(InfoStruct)], ci),
+        "tslov_ritz_values": ([ci, ctypes.POINTER(cd), ctypes.POINTER(cd), ctypes.POINTER(cd), ctypes.POINTER(cd),
+                               ctypes.POINTER(ci)], ci),
+        "tslov_set_diagnostics": ([vp, ci], ci),
         "tslov_current_estimate": ([vp, ci, vp, ctypes.POINTER(ci), vp, vp, vp, ctypes.POINTER(cd),
                                     ctypes.POINTER(InfoStruct)], ci),
         "tslov_error_estimate": ([vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(cd)], ci),
@@ -221,20 +240,41 @@ class Context:
         return eps.value
 
     def sign_grad(self, eta: torch.Tensor, psi: torch.Tensor, k: int, want_dpsi: bool = False,
-                  dU: torch.Tensor | None = None, defl: "Deflation | None" = None, recompute: int = 0):
+                  dU: torch.Tensor | None = None, defl: "Deflation | None" = None, recompute: int = 0,
+                  want_y: bool = False):
         """S = Re <eta|TSL_k(psi)>, dS/dU (and dS/dpsi); recompute = m > 0 holds m + 2
-        steps of Krylov vectors and regenerates them in segments of m for the reverse pass."""
+        steps of Krylov vectors and regenerates them in segments of m for the reverse pass.
+        With want_y the approximation y = TSL_k(psi) itself is returned too (as a fifth value)."""
         eta = self._spinor(eta, "eta")
         psi = self._spinor(psi, "psi")
         if dU is None:
             dU = torch.empty((4, self.volume, 3, 3), dtype=torch.complex128, device=self.device)
         dpsi = self._new_spinor() if want_dpsi else None
+        y = self._new_spinor() if want_y else None
         S = ctypes.c_double()
         info = InfoStruct()
         d = None if defl is None else ctypes.byref(defl.struct)
         _check(self.lib, self.lib.tslov_sign_grad(self.handle, _ptr(eta), _ptr(psi), int(k), d, int(recompute),
-                                                  ctypes.byref(S), _ptr(dU), _ptr(dpsi), ctypes.byref(info)))
+                                                  ctypes.byref(S), _ptr(dU), _ptr(dpsi), _ptr(y), ctypes.byref(info)))
+        if want_y:
+            return S.value, dU, dpsi, Info.of(info), y
         return S.value, dU, dpsi, Info.of(info)
+
+    def overlap_grad(self, eta: torch.Tensor, psi: torch.Tensor, k: int, defl: "Deflation | None" = None,
+                     recompute: int = 0):
+        """S = Re <eta|D_ov|psi>, dS/dU, dS/dpsi and D_ov psi."""
+        eta = self._spinor(eta, "eta")
+        psi = self._spinor(psi, "psi")
+        dU = torch.empty((4, self.volume, 3, 3), dtype=torch.complex128, device=self.device)
+        dpsi = self._new_spinor()
+        dov = self._new_spinor()
+        S = ctypes.c_double()
+        info = InfoStruct()
+        d = None if defl is None else ctypes.byref(defl.struct)
+        _check(self.lib, self.lib.tslov_overlap_grad(self.handle, _ptr(eta), _ptr(psi), int(k), d, int(recompute),
+                                                     ctypes.byref(S), _ptr(dU), _ptr(dpsi), _ptr(dov),
+                                                     ctypes.byref(info)))
+        return S.value, dU, dpsi, dov, Info.of(info)
 
     def _sources(self, x: torch.Tensor, name: str) -> torch.Tensor:
         shape = (x.shape[0], self.volume, 4, 3)
@@ -242,8 +282,10 @@ class Context:
             raise ValueError(f"{name} must be complex128 of shape (nsrc, {self.volume}, 4, 3) on {self.device}")
         return x.contiguous()
 
-    def sign_grad_batched(self, eta: torch.Tensor, psi: torch.Tensor, ks, want_dpsi: bool = False):
-        """Per-source S_s, dS_s/dU and (optionally) dS_s/dpsi_s for a batch (nsrc, V, 4, 3)."""
+    def sign_grad_batched(self, eta: torch.Tensor, psi: torch.Tensor, ks, want_dpsi: bool = False,
+                          want_y: bool = False):
+        """Per-source S_s, dS_s/dU and (optionally) dS_s/dpsi_s for a batch (nsrc, V, 4, 3);
+        with want_y also every y_s = TSL(psi_s) (a fifth value)."""
         psi = self._sources(psi, "psi")
         eta = self._sources(eta, "eta")
         n = psi.shape[0]
@@ -254,8 +296,11 @@ class Context:
         infos = (InfoStruct * n)()
         dU = torch.empty((n, 4, self.volume, 3, 3), dtype=torch.complex128, device=self.device)
         dpsi = torch.empty_like(psi) if want_dpsi else None
+        y = torch.empty_like(psi) if want_y else None
         _check(self.lib, self.lib.tslov_sign_grad_batched(self.handle, n, _ptr(eta), _ptr(psi), k, S, _ptr(dU),
-                                                          _ptr(dpsi), infos))
+                                                          _ptr(dpsi), _ptr(y), infos))
+        if want_y:
+            return list(S), dU, dpsi, [Info.of(i) for i in infos], y
         return list(S), dU, dpsi, [Info.of(i) for i in infos]
 
     def current_estimate(self, xi: torch.Tensor, ks, divergence: bool = True, ward: bool = True):
@@ -284,6 +329,20 @@ class Context:
         _check(self.lib, self.lib.tslov_lanczos_matrix(self.handle, _ptr(psi), int(k),
                                                        T.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info)))
         return T, Info.of(info)
+
+    def tridiag_sign(self, diag, sub, sup):
+        """sgn(T) e_1 for the tridiagonal T (host sequences: k complex diagonal, k-1 real
+        sub-diagonal T_{j+1,j}, k-1 complex super-diagonal T_{j,j+1}); returns (c, Info)."""
+        a, b, g = _tridiag_arrays(diag, sub, sup)
+        k = len(diag)
+        c = torch.empty(k, dtype=torch.complex128, device=self.device)
+        info = InfoStruct()
+        _check(self.lib, self.lib.tslov_tridiag_sign(self.handle, k, a, b, g, _ptr(c), ctypes.byref(info)))
+        return c, Info.of(info)
+
+    def set_diagnostics(self, flags: int = 0):
+        """DIAG_EPS_A: single-source calls also fill Info.eps_A (one more Lanczos process)."""
+        _check(self.lib, self.lib.tslov_set_diagnostics(self.handle, int(flags)))
 
     def dense_sign(self, T: torch.Tensor, E: torch.Tensor | None = None):
         k = T.shape[0]
@@ -334,6 +393,32 @@ class Context:
         return f.value, b.value
 
 
+def _tridiag_arrays(diag, sub, sup):
+    import numpy as np
+    d = np.ascontiguousarray(np.asarray(diag, dtype=np.complex128))
+    k = d.shape[0]
+    lo = np.ascontiguousarray(np.asarray(sub, dtype=np.float64).reshape(max(k - 1, 0)))
+    hi = np.ascontiguousarray(np.asarray(sup, dtype=np.complex128).reshape(max(k - 1, 0)))
+    keep = (d, lo, hi)
+    ptr = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    arrays = (ptr(d), ptr(lo) if k > 1 else None, ptr(hi) if k > 1 else None)
+    _tridiag_arrays.keep = keep   # alive until the next call
+    return arrays
+
+
+def ritz_values(diag, sub, sup):
+    """Eigenvalues of the tridiagonal T (host, no device needed) and the sweeps used."""
+    import numpy as np
+    lib = load_library()
+    k = len(diag)
+    a, b, g = _tridiag_arrays(diag, sub, sup)
+    out = np.zeros(2 * k)
+    sw = ctypes.c_int()
+    _check(lib, lib.tslov_ritz_values(k, a, b, g, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      ctypes.byref(sw)))
+    return out[0::2] + 1j * out[1::2], sw.value
+
+
 class Deflation:
     """Keeps the eigenvector tensors and the eigenvalue array alive for the C struct."""
 
@@ -353,24 +438,34 @@ class Deflation:
 
 
 class SignGrad(torch.autograd.Function):
-    """S = Re <eta | TSL_k(H(U), psi)> with a hand-written backward (HIP).
+    """S = Re <eta | TSL_k(H(U), psi)> (or, with overlap=True, S = Re <eta | D_ov | psi>)
+    with a hand-written backward (HIP).
 
-    ``forward(U, psi, eta, ctx, k, recompute=0)`` loads U into the context, runs the
-    forward pass and the reverse-mode recursion once (regenerating the Krylov
-    vectors in segments of ``recompute`` steps if it is positive), and keeps
-    dS/dU and dS/dpsi;
-    ``backward`` scales them by the incoming gradient (torch's convention for
-    real outputs of complex inputs: grad = dS/dRe + i dS/dIm).
+    ``forward(U, psi, eta, ctx, k, recompute=0, defl=None, overlap=False)`` loads U
+    into the context, runs the forward pass and the reverse-mode recursion once
+    (regenerating the Krylov vectors in segments of ``recompute`` steps if it is
+    positive; deflating by ``defl``, a ``Deflation`` of eigenpairs of H(U), whose
+    motion with U is part of the derivative), and keeps dS/dU, dS/dpsi and
+    dS/deta (= the output TSL_k(psi), resp. D_ov psi).  ``backward`` scales them
+    by the incoming gradient (torch's convention for real outputs of complex
+    inputs: grad = dS/dRe + i dS/dIm).  The eigenpair tensors get no gradient:
+    they are functions of U, and their dependence is inside dS/dU.
     """
 
     @staticmethod
-    def forward(ctx, U, psi, eta, context: Context, k: int, recompute: int = 0):
+    def forward(ctx, U, psi, eta, context: Context, k: int, recompute: int = 0, defl: "Deflation | None" = None,
+                overlap: bool = False):
         context.set_links(U.detach())
-        S, dU, dpsi, _ = context.sign_grad(eta.detach(), psi.detach(), k, want_dpsi=True, recompute=recompute)
-        ctx.save_for_backward(dU, dpsi)
+        if overlap:
+            S, dU, dpsi, deta, _ = context.overlap_grad(eta.detach(), psi.detach(), k, defl=defl,
+                                                        recompute=recompute)
+        else:
+            S, dU, dpsi, _, deta = context.sign_grad(eta.detach(), psi.detach(), k, want_dpsi=True, defl=defl,
+                                                     recompute=recompute, want_y=True)
+        ctx.save_for_backward(dU, dpsi, deta)
         return torch.tensor(S, dtype=torch.float64, device=U.device)
 
     @staticmethod
     def backward(ctx, grad):
-        dU, dpsi = ctx.saved_tensors
-        return grad * dU, grad * dpsi, None, None, None, None
+        dU, dpsi, deta = ctx.saved_tensors
+        return grad * dU, grad * dpsi, grad * deta, None, None, None, None, None

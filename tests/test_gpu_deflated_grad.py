@@ -37,5 +37,5 @@ def test_deflated_gradient(dims, l, k, m):
     Sg, dU, dpsi, info = ctx.sign_grad(dev(eta), dev(psi), k, want_dpsi=True, defl=defl, recompute=m)
     ctx.close()
     eS, eG, eP = abs(Sg - S) / abs(S), rel(host(dU), G), rel(host(dpsi), pb)
-    say(f"deflated grad {dims} l={l} k={k} recompute={m}: S {eS:.2e} G {eG:.2e} dpsi {eP:.2e} cg iterations {info.reserved}")
+    say(f"deflated grad {dims} l={l} k={k} recompute={m}: S {eS:.2e} G {eG:.2e} dpsi {eP:.2e} cg iterations {info.cg_iters}")
     assert eS < 1e-10 and eG < 1e-8 and eP < 1e-8
