@@ -129,6 +129,20 @@ tslov_status tslov_apply_dw(tslov_ctx* ctx, const void* in, void* out, int dagge
  * Sec. 1 (definition after eq. overlap). */
 tslov_status tslov_apply_h(tslov_ctx* ctx, const void* in, void* out, int dagger);
 
+/* tslov_apply_h without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same operator, same arguments and same result bits as
+ * tslov_apply_h, with its two staging fields in a static device array of 32 MiB
+ * that each device holds for the life of the process, instead of the context's
+ * workspace.  The lattice must fit it: 2 * 12 * V complex values of the context
+ * precision (float64 / float32-link contexts: V <= 87381, e.g. up to 16^4; float32:
+ * twice that), else ERR_ARG.  It never times launches and never picks the
+ * marching chunk length by timing (it uses the context's pick if one was made,
+ * else the built-in choice).  Every call on a device shares that device's array:
+ * calls that overlap on one device (other streams, other contexts, other threads)
+ * race on it and must be serialised by the caller. */
+tslov_status tslov_apply_h_noalloc(tslov_ctx* ctx, const void* in, void* out, int dagger);
+
 /* Optional deflation by known eigenpairs of H (Sec. 3: the standard projection
  * for a diagonalisable matrix, eq. final_res without the mixing term):
  *   c_i = L_i^H psi,  psi_p = psi - sum_i c_i R_i,

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -114,6 +115,38 @@ std::vector<int> site_block_order(const Geom& g, int& nwg) {
 
 }  // namespace
 
+// Device memory of the allocation-free operator entry point: the two structure-
+// of-arrays staging fields (input and output of the stencil) for lattices of up
+// to kScratchBytes / (2 * 12 * sizeof(complex)) sites.  Each device holds its own
+// copy while the process lives; host code reaches it only through the address
+// hipGetSymbolAddress returns for that device (the array's name is a host-side
+// stand-in, not a device address).
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on the current device `dev`, looked up once per device.
+tslov_status scratch_address(int dev, char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(TSLOV_ERR_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(TSLOV_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return TSLOV_OK;
+}
+}  // namespace
+
 // A captured launch sequence and the key (list, sizes, buffers, launch shapes) it
 // was captured for.
 struct LoopGraph {
@@ -132,6 +165,7 @@ struct tslov_ctx {
     int antiperiodic = 1, precision = TSLOV_FP64;
     hipStream_t st = nullptr;
     int device = 0;
+    char* scratch = nullptr;   // this device's scratch array (allocation-free operator)
     size_t lds_max = 65536;
     int links_set = 0;
     int diag = 0;    // tslov_set_diagnostics flags
@@ -563,13 +597,15 @@ struct RitzJobs {
         next = 0;
         const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
         const int nt = (int)std::min<size_t>(kk.size(), std::min(hw, 16u));
+        // one entry: its divide-and-conquer halves run on threads of their own
+        const int inner = kk.size() == 1 ? 4 : 1;
         for (int t = 0; t < nt; ++t)
-            th.emplace_back([this] {
+            th.emplace_back([this, inner] {
                 for (int e; (e = next++) < (int)kk.size();) {
                     if (kk[e] < 1) continue;
                     const size_t o = (size_t)slot[e] * n + 1;   // step 1 of the slot
                     out[e] = tslov::ritz_summary(kk[e], reinterpret_cast<const double*>(&alpha[o]), &beta[o],
-                                                 reinterpret_cast<const double*>(&gamma[o]));
+                                                 reinterpret_cast<const double*>(&gamma[o]), inner);
                 }
             });
     }
@@ -1429,14 +1465,20 @@ tslov_status pick_apply_chunk(tslov_ctx* c, const Z<RL>* U, const Z<R>* a, Z<R>*
 
 // The operator on canonical spinors: to the context's field layout, the stencil,
 // and back.
+// staging: the two SoA fields (the context's workspace, or the scratch array of
+// the allocation-free entry point, which neither times launches nor picks the
+// marching chunk length by timing: it takes the context's pick if one was made,
+// else the built-in choice; every chunk length gives the same bits).
 template <typename R, typename RL>
-tslov_status apply_fields(tslov_ctx* c, const void* in, void* out, double mu, int g5in, int g5out) {
-    Z<R>* a = c->opf.as<Z<R>>();
+tslov_status apply_fields(tslov_ctx* c, const void* in, void* out, double mu, int g5in, int g5out, void* staging,
+                          int no_alloc) {
+    Z<R>* a = static_cast<Z<R>*>(staging);
     Z<R>* b = a + c->field_elems();
     const Z<RL>* U = links<RL>(c);
     tslov::launch_spinor_to_soa<R>((const ZD*)in, a, c->g, nullptr, c->st);
-    if (!c->tm_T_forced) CHK((pick_apply_chunk<R, RL>(c, U, a, b, mu, g5in, g5out)));
-    tslov::launch_apply<R, RL>(U, a, b, c->g, c->kappa, mu, g5in, g5out, c->st, TimedLaunch(c, 2).t,
+    if (!c->tm_T_forced && !no_alloc) CHK((pick_apply_chunk<R, RL>(c, U, a, b, mu, g5in, g5out)));
+    tslov::launch_apply<R, RL>(U, a, b, c->g, c->kappa, mu, g5in, g5out, c->st,
+                               no_alloc ? tslov::Timing{} : TimedLaunch(c, 2).t,
                                c->tm_T_forced ? c->tm_T_forced : std::max(c->tm_T, 0));
     tslov::launch_spinor_from_soa<R>(b, (ZD*)out, c->g, c->st);
     return TSLOV_OK;
@@ -1462,8 +1504,11 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
     HIPCHK(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, dev));
+    char* scr = nullptr;
+    CHK(scratch_address(dev, &scr));
     tslov_ctx* c = new tslov_ctx();
     c->device = dev;
+    c->scratch = scr;
     c->lds_max = prop.sharedMemPerBlock ? prop.sharedMemPerBlock : 65536;
     c->g.nx = d->dims[0];
     c->g.ny = d->dims[1];
@@ -1531,15 +1576,28 @@ tslov_status tslov_set_links(tslov_ctx* c, const void* U) {
     return TSLOV_OK;
 }
 
-static tslov_status apply_op(tslov_ctx* c, const void* in, void* out, double mu, int g5in, int g5out) {
+static tslov_status apply_op(tslov_ctx* c, const void* in, void* out, double mu, int g5in, int g5out,
+                             int no_alloc = 0) {
     if (!c || !in || !out) return fail(TSLOV_ERR_ARG, "null argument");
     if (!c->links_set) return fail(TSLOV_ERR_ARG, "links not set (call tslov_set_links first)");
     if (in == out) return fail(TSLOV_ERR_ARG, "in and out must not overlap");
-    CHK(ensure(c->opf, 2 * c->field_bytes()));
+    void* staging = nullptr;
+    if (no_alloc) {
+        if (2 * c->field_bytes() > kScratchBytes)
+            return fail(TSLOV_ERR_ARG, "lattice too large for the allocation-free operator (" +
+                                           std::to_string(2 * c->field_bytes()) + " bytes of staging, at most " +
+                                           std::to_string(kScratchBytes) + ")");
+        staging = c->scratch;
+    } else {
+        CHK(ensure(c->opf, 2 * c->field_bytes()));
+        staging = c->opf.p;
+    }
     switch (c->precision) {
-        case TSLOV_MIXED: CHK((apply_fields<float, float>(c, in, out, mu, g5in, g5out))); break;
-        case TSLOV_FP32_LINKS: CHK((apply_fields<double, float>(c, in, out, mu, g5in, g5out))); break;
-        default: CHK((apply_fields<double, double>(c, in, out, mu, g5in, g5out)));
+        case TSLOV_MIXED: CHK((apply_fields<float, float>(c, in, out, mu, g5in, g5out, staging, no_alloc))); break;
+        case TSLOV_FP32_LINKS:
+            CHK((apply_fields<double, float>(c, in, out, mu, g5in, g5out, staging, no_alloc)));
+            break;
+        default: CHK((apply_fields<double, double>(c, in, out, mu, g5in, g5out, staging, no_alloc)));
     }
     HIPCHK(hipGetLastError());
     return TSLOV_OK;
@@ -1553,6 +1611,11 @@ tslov_status tslov_apply_dw(tslov_ctx* c, const void* in, void* out, int dagger)
 tslov_status tslov_apply_h(tslov_ctx* c, const void* in, void* out, int dagger) {
     if (!c) return fail(TSLOV_ERR_ARG, "null context");
     return apply_op(c, in, out, dagger ? -c->mu : c->mu, 0, 1);
+}
+
+tslov_status tslov_apply_h_noalloc(tslov_ctx* c, const void* in, void* out, int dagger) {
+    if (!c) return fail(TSLOV_ERR_ARG, "null context");
+    return apply_op(c, in, out, dagger ? -c->mu : c->mu, 0, 1, 1);
 }
 
 tslov_status tslov_sign(tslov_ctx* c, const void* psi, void* out, int k, const tslov_deflation* defl,

@@ -37,7 +37,7 @@ EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links
            "tslov_current_estimate", "tslov_error_estimate", "tslov_lanczos_matrix", "tslov_dense_sign", "tslov_timing_enable",
            "tslov_timing_read", "tslov_kernel_bytes", "tslov_set_pair_ns", "tslov_get_pair_ns", "tslov_set_graphs", "tslov_set_apply_chunk",
            "tslov_get_apply_chunk", "tslov_overlap_grad", "tslov_tridiag_sign", "tslov_ritz_values",
-           "tslov_set_diagnostics"]
+           "tslov_set_diagnostics", "tslov_apply_h_noalloc"]
 
 
 class TslovLibraryMissing(ImportError):
@@ -107,6 +107,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_set_links": ([vp, vp], ci),
         "tslov_apply_dw": ([vp, vp, vp, ci], ci),
         "tslov_apply_h": ([vp, vp, vp, ci], ci),
+        "tslov_apply_h_noalloc": ([vp, vp, vp, ci], ci),
         "tslov_sign": ([vp, vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(InfoStruct)], ci),
         "tslov_overlap": ([vp, vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(InfoStruct)], ci),
         "tslov_sign_grad": ([vp, vp, vp, ci, ctypes.POINTER(DeflationStruct), ci, ctypes.POINTER(cd), vp, vp, vp,
@@ -209,6 +210,14 @@ class Context:
         x = self._spinor(x, "x")
         out = self._new_spinor()
         _check(self.lib, self.lib.tslov_apply_h(self.handle, _ptr(x), _ptr(out), int(dagger)))
+        return out
+
+    def apply_h_noalloc(self, x: torch.Tensor, out: torch.Tensor, dagger: bool = False) -> torch.Tensor:
+        """apply_h with no device allocation in the library (staging in its static
+        per-device array); the caller provides out."""
+        x = self._spinor(x, "x")
+        out = self._spinor(out, "out")
+        _check(self.lib, self.lib.tslov_apply_h_noalloc(self.handle, _ptr(x), _ptr(out), int(dagger)))
         return out
 
     def deflation(self, R: torch.Tensor, L: torch.Tensor, lam) -> "Deflation":
