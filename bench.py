@@ -262,6 +262,21 @@ def precision_14():
             out["biorth_err"] = info.biorth_err
             out["newton_iters"] = info.newton_iters
         ctx.close()
+    # the nested projected-matrix step (inner size 100) against the plain one: the
+    # sign alone, its dense-step time and the change of the result
+    ctx = Context(wl.dims, wl.mass, wl.mu)
+    ctx.set_links(U)
+    nest = {}
+    for m in (0, 100):
+        ctx.set_nested(m)
+        for _ in range(2):
+            y, info = ctx.sign(psi, wl.k)
+        torch.cuda.synchronize()
+        nest[m] = (y, info.ms[1], info.ms[5])
+    ctx.close()
+    out["nested_m100"] = {"dense_ms_plain": nest[0][1], "dense_ms_nested": nest[100][1],
+                          "sign_ms_plain": nest[0][2], "sign_ms_nested": nest[100][2],
+                          "rel_diff_y": rel_t(nest[100][0], nest[0][0])}
     S64, dU64, y64 = res["fp64"]
     for prec in ("fp32links", "mixed"):
         S, dU, y = res[prec]

@@ -283,6 +283,23 @@ tslov_status tslov_tridiag_sign(tslov_ctx* ctx, int k, const double* diag, const
 tslov_status tslov_ritz_values(int k, const double* diag, const double* sub, const double* sup, double* out,
                                int* sweeps);
 
+/* Nested projected-matrix step (one level of nesting, the paper's production
+ * setting, Sec. 4.1; the nested method itself is cited there, not described).
+ * With k_inner = m > 0, tslov_sign, tslov_overlap and tslov_error_estimate replace
+ * the dense sgn(T_k) e_1 of the outer process (k = k_used > m) by
+ *   T_k W^{1/2} e_1 ~ T_k V' (T')^{1/2} e_1,   W = (T_k^2)^{-1},
+ * an inner two-sided Lanczos process of size m on W with both spaces started from
+ * e_1 (its basis V', its projected matrix T', the principal square root).  The
+ * identity z (z^2)^{-1/2} = sgn(Re z) makes it exact for m = k; the inner space
+ * resolves the eigenvalues of T_k nearest zero first, so m well below k suffices
+ * (m = 100 is the paper's inner size).  The dense work then is O(k^2 m) for W and
+ * the inner products plus O(m^3) for the square root, in place of O(k^3) Newton
+ * steps.  k_inner = 0 (the default) or k_inner >= k_used: the plain dense step.
+ * The derivative calls always use the plain step (their Frechet derivative is that
+ * of sgn(T_k)).  ERR_ARG for k_inner outside [0, 1024]; ERR_BREAKDOWN for a serious
+ * breakdown of the inner process. */
+tslov_status tslov_set_nested(tslov_ctx* ctx, int k_inner);
+
 /* Optional per-call diagnostics of the context: TSLOV_DIAG_EPS_A makes tslov_sign,
  * tslov_overlap and tslov_sign_grad compute info->eps_A (Sec. 4.1 eq. error_est: one
  * more two-sided Lanczos process of size k on the output; only when info is given).

@@ -169,6 +169,8 @@ struct tslov_ctx {
     size_t lds_max = 65536;
     int links_set = 0;
     int diag = 0;    // tslov_set_diagnostics flags
+    int nest_m = 0;  // inner Krylov size of the nested projected-matrix step (0: plain)
+    Buf nestbuf;     // its inner basis, vectors and coefficients
     Buf U64, U32;
     Buf badflag;     // device int: a non-finite link element was seen
     Buf sbmap;       // Geom::sbmap
@@ -873,6 +875,48 @@ tslov_status dense_step(tslov_ctx* c, const SrcList& L, int grad, std::vector<in
     return TSLOV_OK;
 }
 
+// Nested projected-matrix step of a single entry (slot 0, k = k_used > m): sgn(T) e_1
+// = T W^{1/2} e_1 with W = (T^2)^{-1} formed densely (banded inverse, one product),
+// W^{1/2} e_1 from an inner two-sided Lanczos process of size m on W, and the
+// inner principal square root from the Newton sign of [[0, T'], [I, 0]].  Leaves
+// coef.c like dense_step.  iters: the inner Newton steps.
+tslov_status nested_dense_step(tslov_ctx* c, const SrcList& L, int m, std::vector<int>& iters,
+                               std::vector<int>* stagnated) {
+    const int k = L.k[0];
+    DenseWork w;
+    CHK(ensure_dense(c, c->slots, c->kcap, w));
+    tslov::launch_dense_build(c->coef, L, 0, w, c->st);            // X = T
+    tslov::launch_tridiag_inverse(L, w, c->st);                    // Xinv = T^{-1}
+    tslov::launch_dense_gemm(L, w, 3, 3, 4, c->st);                // Zt = T^{-2} = W
+    tslov::nest_prepare(w, k, c->st);                              // Y2 = W^T
+    const size_t nv = (size_t)k * m + 6 * (size_t)k + 2 * ((size_t)m + 2);
+    CHK(ensure(c->nestbuf, nv * sizeof(ZD) + ((size_t)m + 2) * sizeof(double) + 8 * sizeof(int)));
+    tslov::NestWork nw;
+    nw.Vb = c->nestbuf.as<ZD>();
+    nw.vec = nw.Vb + (size_t)k * m;
+    nw.alpha = nw.vec + 6 * (size_t)k;
+    nw.gamma = nw.alpha + m + 2;
+    nw.beta = (double*)(nw.gamma + m + 2);
+    nw.status = (int*)(nw.beta + m + 2);
+    tslov::nest_init(nw, k, c->st);
+    for (int j = 0; j < m; ++j) tslov::nest_step(w, nw, k, j, m, c->st);
+    HIPCHK(hipGetLastError());
+    int st[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(st, nw.status, sizeof(st), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (st[2]) return fail(TSLOV_ERR_BREAKDOWN, "serious breakdown of the inner Lanczos process at its step " +
+                                                    std::to_string(st[1]));
+    const int mu = st[1];
+    DenseWork w2;
+    CHK(ensure_dense(c, 1, 2 * mu, w2));
+    tslov::nest_block(nw, w2, mu, c->st);
+    const SrcList L2 = make_list({0}, {2 * mu});
+    CHK(newton(c, L2, 0, w2, iters, 0, stagnated));
+    tslov::nest_finish(nw, w2, c->coef, k, mu, c->st);
+    HIPCHK(hipGetLastError());
+    return TSLOV_OK;
+}
+
 // ---------------------------------------------------------------- backward
 struct GradOut {
     ZD* dU = nullptr;        // [src][4][V][3][3] or null
@@ -1123,7 +1167,8 @@ tslov_status sign_impl(tslov_ctx* c, const void* psi_in, void* out, int k, const
     std::vector<int> stag(1, 0);
     if (k_used > 0) {
         std::vector<int> iters;
-        CHK(dense_step(c, Ld, 0, iters, &stag));
+        if (c->nest_m > 0 && c->nest_m < k_used) CHK(nested_dense_step(c, Ld, c->nest_m, iters, &stag));
+        else CHK(dense_step(c, Ld, 0, iters, &stag));
         es[0].iters = iters[0];
     }
     const double t2 = now_ms();
@@ -1544,7 +1589,7 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
 void tslov_destroy(tslov_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
-    for (Buf* b : {&c->U64, &c->U32, &c->badflag, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
+    for (Buf* b : {&c->U64, &c->U32, &c->badflag, &c->nestbuf, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
                    &c->fields, &c->part, &c->coefmem, &c->dense, &c->denseInt, &c->densePart, &c->denseDelta,
                    &c->gpart, &c->gsrc, &c->bout, &c->wardp, &c->canon, &c->deflw, &c->deflx, &c->cgf, &c->cgp,
                    &c->cgs, &c->ckpt})
@@ -1860,6 +1905,13 @@ tslov_status tslov_ritz_values(int k, const double* diag, const double* sub, con
     }
     const int sw = tslov::tridiag_eigvals(k, diag, be.data(), ga.data(), out);
     if (sweeps) *sweeps = sw;
+    return TSLOV_OK;
+}
+
+tslov_status tslov_set_nested(tslov_ctx* c, int k_inner) {
+    if (!c) return fail(TSLOV_ERR_ARG, "null context");
+    if (k_inner < 0 || k_inner > kMaxK) return fail(TSLOV_ERR_ARG, "k_inner must be in [0, 1024]");
+    c->nest_m = k_inner;
     return TSLOV_OK;
 }
 

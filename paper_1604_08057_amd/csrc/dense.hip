@@ -876,6 +876,18 @@ void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, con
     hipLaunchKernelGGL(k_dense_delta, dim3(1, 1, L.n), dim3(kDB), 0, st, w, L, nblk);
 }
 
+void launch_tridiag_inverse(const SrcList& L, const DenseWork& w, hipStream_t st) {
+    const int kmax = L.k[0];
+    const size_t tl = (size_t)7 * kmax * sizeof(ZD) + (size_t)kmax * sizeof(int);
+    hipLaunchKernelGGL(k_tridiag_inv, dim3(1, 1, L.n), dim3(kDB), tl, st, w, L);
+}
+
+void launch_dense_gemm(const SrcList& L, const DenseWork& w, int ia, int ib, int ic, hipStream_t st) {
+    const int kmax = L.k[0];
+    dim3 g2(grid_for(kmax, 16), grid_for(kmax, 16), L.n);
+    hipLaunchKernelGGL(k_zgemm, g2, dim3(kDB), 0, st, w, L, ia, ib, ic, ic, 1.0, 0.0, 0);
+}
+
 // X <- Wk (the new iterate), Y <- Y2 if grad, partials of |X_new - X|^2 and |X_new|^2.
 __global__ __launch_bounds__(kDB) void k_ns_commit(DenseWork w0, SrcList L, int grad) {
     const int e = blockIdx.z, k = L.k[e];

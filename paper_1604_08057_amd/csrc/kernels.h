@@ -247,6 +247,33 @@ void dense_newton_step(const SrcList& L, int grad, int nb, size_t lds_bytes, con
 void dense_ns_step(const SrcList& L, int grad, const DenseWork& w, hipStream_t st);
 // |I - X^2|_F^2 of every entry into delta[2] (one GEMM into Zt and a reduction).
 void dense_residual(const SrcList& L, const DenseWork& w, hipStream_t st);
+// X^{-1} of the tridiagonal X (Gaussian elimination on the band) into Xinv, and
+// C = A B for workspace matrices A, B, C (indices: 0 X, 1 Y, 2 Wk, 3 Xinv, 4 Zt,
+// 5 Y2, 6 P2, 7 Y3), for every list entry.
+void launch_tridiag_inverse(const SrcList& L, const DenseWork& w, hipStream_t st);
+void launch_dense_gemm(const SrcList& L, const DenseWork& w, int ia, int ib, int ic, hipStream_t st);
+
+// ---------------------------------------------------------------- nested step
+// Inner two-sided Lanczos process of the nested projected-matrix step (nested.hip)
+// on W = (T^2)^{-1} (in Zt of the outer dense workspace, slot 0), from e_1.
+struct NestWork {
+    ZD* Vb;       // inner right basis V', column j at Vb + j k
+    ZD* vec;      // six vectors of length k: v, w, a = W v, b = W^H w, v_prev, w_prev
+    ZD* alpha;    // inner coefficients, 0-based step j: alpha[j], beta[j], gamma[j] (j >= 1)
+    double* beta;
+    ZD* gamma;
+    int* status;  // [0] stopped, [1] steps taken (m_used), [2] serious breakdown
+};
+// Y2 = W^T (so that both products of a step read the matrix with unit stride).
+void nest_prepare(const DenseWork& w, int k, hipStream_t st);
+void nest_init(const NestWork& nw, int k, hipStream_t st);
+// Inner step j of m (0-based).
+void nest_step(const DenseWork& w, const NestWork& nw, int k, int j, int m, hipStream_t st);
+// X = Wk = [[0, T'], [I, 0]] (2m x 2m) in w2 (slot 0), for the principal square root.
+void nest_block(const NestWork& nw, const DenseWork& w2, int m, hipStream_t st);
+// coef.c[1..k] = T V' (T')^{1/2} e_1 from X = sgn([[0, T'], [I, 0]]).
+void nest_finish(const NestWork& nw, const DenseWork& w2, Coef coef, int k, int m, hipStream_t st);
+
 // c = X e_1, adjoint seeds from Y, S = |x| Re sum_j c_j h_j.
 void launch_dense_extract(Coef coef, const SrcList& L, int grad, const DenseWork& w, hipStream_t st);
 

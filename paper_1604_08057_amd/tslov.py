@@ -37,7 +37,7 @@ EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links
            "tslov_current_estimate", "tslov_error_estimate", "tslov_lanczos_matrix", "tslov_dense_sign", "tslov_timing_enable",
            "tslov_timing_read", "tslov_kernel_bytes", "tslov_set_pair_ns", "tslov_get_pair_ns", "tslov_set_graphs", "tslov_set_apply_chunk",
            "tslov_get_apply_chunk", "tslov_overlap_grad", "tslov_tridiag_sign", "tslov_ritz_values",
-           "tslov_set_diagnostics", "tslov_apply_h_noalloc"]
+           "tslov_set_diagnostics", "tslov_apply_h_noalloc", "tslov_set_nested"]
 
 
 class TslovLibraryMissing(ImportError):
@@ -121,6 +121,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_ritz_values": ([ci, ctypes.POINTER(cd), ctypes.POINTER(cd), ctypes.POINTER(cd), ctypes.POINTER(cd),
                                ctypes.POINTER(ci)], ci),
         "tslov_set_diagnostics": ([vp, ci], ci),
+        "tslov_set_nested": ([vp, ci], ci),
         "tslov_current_estimate": ([vp, ci, vp, ctypes.POINTER(ci), vp, vp, vp, ctypes.POINTER(cd),
                                     ctypes.POINTER(InfoStruct)], ci),
         "tslov_error_estimate": ([vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(cd)], ci),
@@ -348,6 +349,10 @@ class Context:
         info = InfoStruct()
         _check(self.lib, self.lib.tslov_tridiag_sign(self.handle, k, a, b, g, _ptr(c), ctypes.byref(info)))
         return c, Info.of(info)
+
+    def set_nested(self, k_inner: int = 0):
+        """Nested projected-matrix step of the sign calls with inner Krylov size k_inner (0: plain)."""
+        _check(self.lib, self.lib.tslov_set_nested(self.handle, int(k_inner)))
 
     def set_diagnostics(self, flags: int = 0):
         """DIAG_EPS_A: single-source calls also fill Info.eps_A (one more Lanczos process)."""
