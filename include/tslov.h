@@ -283,6 +283,29 @@ tslov_status tslov_tridiag_sign(tslov_ctx* ctx, int k, const double* diag, const
 tslov_status tslov_ritz_values(int k, const double* diag, const double* sub, const double* sup, double* out,
                                int* sweeps);
 
+/* The paper's derivative method (Sec. 2, Theorem 1 and eq. func_derivative_1) for one
+ * link parameter t, U_nu(site) -> exp(i t X) U_nu(site) (X: host 3 x 3 complex
+ * matrix, 18 doubles row-major re/im; the derivative is linear in X, and a
+ * Hermitian traceless X is an su(3) direction, X = 1 the U(1) phase): the
+ * two-sided Lanczos process of size k on the block matrix
+ *   B = [[H, dH], [0, H]],   dH = d H / dt,
+ * from the source (x1, x2) (canonical spinors, device; x1 = NULL means zero), both
+ * Krylov spaces of B started there, y = |x| V_B sgn(T_B) e_1 with the halves into
+ * y1_out and y2_out.  With x1 = NULL, y1_out approximates d sgn(H) x2 / dt and y2_out
+ * sgn(H) x2 (eq. func_derivative_1); this differs at finite k from the derivative of
+ * the k-step approximation that tslov_sign_grad returns (it equals the derivative of
+ * the Ritz interpolation polynomial with its coefficients held fixed).  Float64
+ * whatever the context precision; the context's links and mu.  ERR_ARG for a link
+ * out of range or a non-finite X; ERR_BREAKDOWN as tslov_sign. */
+tslov_status tslov_block_sign(tslov_ctx* ctx, int nu, int site, const double* X, const void* x1, const void* x2,
+                              int k, void* y1_out, void* y2_out, tslov_info* info);
+
+/* Its error estimate (Sec. 4.1 eq. bA_error_est): with (y1, y2) = TSL_k(B, (0, psi))
+ * and (z1, z2) = TSL_k(B, (y1, y2)) (a fresh process from the first result),
+ * eps_B = |(z1, z2 - psi)| / (2 |psi|).  eps_out: host double. */
+tslov_status tslov_block_error_estimate(tslov_ctx* ctx, int nu, int site, const double* X, const void* psi, int k,
+                                        double* eps_out);
+
 /* Nested projected-matrix step (one level of nesting, the paper's production
  * setting, Sec. 4.1; the nested method itself is cited there, not described).
  * With k_inner = m > 0, tslov_sign, tslov_overlap and tslov_error_estimate replace

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtslov.so")
-SOURCES = ["fields.hip", "dense.hip", "deflate.hip", "solve.hip", "nested.hip", "api.hip", "ritz.cpp"]
+SOURCES = ["fields.hip", "dense.hip", "deflate.hip", "solve.hip", "nested.hip", "blocktsl.hip", "api.hip", "ritz.cpp"]
 ARCH = os.environ.get("TSLOV_OFFLOAD_ARCH", "gfx950")
 
 

@@ -170,6 +170,7 @@ struct tslov_ctx {
     int links_set = 0;
     int diag = 0;    // tslov_set_diagnostics flags
     int nest_m = 0;  // inner Krylov size of the nested projected-matrix step (0: plain)
+    Buf blk;         // block-matrix process: 14 working fields, 2k basis fields, partials
     Buf nestbuf;     // its inner basis, vectors and coefficients
     Buf U64, U32;
     Buf badflag;     // device int: a non-finite link element was seen
@@ -917,6 +918,99 @@ tslov_status nested_dense_step(tslov_ctx* c, const SrcList& L, int m, std::vecto
     return TSLOV_OK;
 }
 
+// Two-sided Lanczos process of size k on B = [[H, dH], [0, H]] (float64, this
+// context's links and mu) from the source (x1, x2) (canonical; x1 null: zero),
+// y = |x| V sgn(T) e_1 in both halves into y1, y2 (canonical).
+tslov_status block_tsl(tslov_ctx* c, const tslov::BlockTangent& t, const ZD* x1, const ZD* x2, int k, ZD* y1,
+                       ZD* y2, EntryStatus& es) {
+    const Geom& g = c->g;
+    const size_t fe = c->field_elems();
+    const int nb = tslov::blk_blocks(g);
+    CHK(ensure(c->blk, ((size_t)14 + 2 * (size_t)k) * fe * sizeof(ZD) + (size_t)8 * nb * sizeof(double)));
+    tslov::BlockFields f;
+    ZD* base = c->blk.as<ZD>();
+    for (int h = 0; h < 2; ++h) {
+        f.x[h] = base + (0 + h) * fe;
+        f.v[h] = base + (2 + h) * fe;
+        f.w[h] = base + (4 + h) * fe;
+        f.vp[h] = base + (6 + h) * fe;
+        f.wp[h] = base + (8 + h) * fe;
+        f.a[h] = base + (10 + h) * fe;
+        f.b[h] = base + (12 + h) * fe;
+        f.basis[h] = base + (14 + (size_t)h * k) * fe;
+    }
+    double* p0 = (double*)(base + (14 + 2 * (size_t)k) * fe);
+    double* p1 = p0 + 4 * nb;
+    CHK(ensure_work(c, 1, k, 0));
+    if (x1) tslov::launch_spinor_to_soa<double>(x1, f.x[0], g, nullptr, c->st);
+    else tslov::launch_zero((double*)f.x[0], 2 * fe, c->st);
+    tslov::launch_spinor_to_soa<double>(x2, f.x[1], g, nullptr, c->st);
+    std::vector<int> init(16, 0);
+    HIPCHK(hipMemcpyAsync(c->coef.status, init.data(), init.size() * sizeof(int), hipMemcpyHostToDevice, c->st));
+    tslov::launch_blk_start(f, g, c->coef, p0, c->st);
+    const ZD* U = c->U64.as<ZD>();
+    for (int j = 1; j <= k; ++j) {
+        tslov::launch_apply<double, double>(U, f.v[0], f.a[0], g, c->kappa, c->mu, 0, 1, c->st);
+        tslov::launch_apply<double, double>(U, f.v[1], f.a[1], g, c->kappa, c->mu, 0, 1, c->st);
+        tslov::launch_apply<double, double>(U, f.w[0], f.b[0], g, c->kappa, -c->mu, 0, 1, c->st);
+        tslov::launch_apply<double, double>(U, f.w[1], f.b[1], g, c->kappa, -c->mu, 0, 1, c->st);
+        tslov::launch_blk_tangent(U, t, g, c->kappa, c->mu, f.v[1], f.a[0], f.w[0], f.b[1], c->st);
+        tslov::launch_blk_step(f, g, c->coef, p0, p1, j, k, c->st);
+    }
+    HIPCHK(hipGetLastError());
+    int st[16];
+    double misc[16];
+    HIPCHK(hipMemcpyAsync(st, c->coef.status, sizeof(st), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(misc, c->coef.misc, sizeof(misc), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (st[2] == 3) return fail(TSLOV_ERR_ARG, "the block source is not finite");
+    es = EntryStatus();
+    es.k_used = st[1];
+    es.breakdown = st[2];
+    es.step = st[3];
+    es.norm_x = misc[0];
+    if (es.breakdown == 2)
+        return fail(TSLOV_ERR_BREAKDOWN, "serious breakdown of the block Lanczos process at step " +
+                                             std::to_string(es.step));
+    const size_t n12 = (size_t)12 * g.V;
+    if (es.k_used == 0) {
+        tslov::launch_zero((double*)y1, 2 * n12, c->st);
+        tslov::launch_zero((double*)y2, 2 * n12, c->st);
+        HIPCHK(hipStreamSynchronize(c->st));
+        return TSLOV_OK;
+    }
+    const SrcList Ld = make_list({0}, {es.k_used});
+    std::vector<int> iters, stag;
+    CHK(dense_step(c, Ld, 0, iters, &stag));
+    es.iters = iters[0];
+    es.flags = stag[0] ? TSLOV_FLAG_SIGN_STAGNATED : 0;
+    for (int h = 0; h < 2; ++h) {
+        Work<double> wk{};
+        wk.V = f.basis[h];
+        wk.fe = fe;
+        wk.kcap = k;
+        wk.ring = 0;
+        tslov::launch_assemble<double>(g, wk, Ld, c->coef, nullptr, 0, h ? y2 : y1, c->st);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    return TSLOV_OK;
+}
+
+tslov_status block_args(tslov_ctx* c, int nu, int site, const double* X, tslov::BlockTangent& t) {
+    if (!X) return fail(TSLOV_ERR_ARG, "null argument");
+    if (nu < 0 || nu > 3 || site < 0 || site >= c->g.V) return fail(TSLOV_ERR_ARG, "link out of range");
+    t.nu = nu;
+    t.site = site;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int r = 0; r < 2; ++r) {
+                t.X[a][b][r] = X[(a * 3 + b) * 2 + r];
+                if (!std::isfinite(t.X[a][b][r])) return fail(TSLOV_ERR_ARG, "X is not finite");
+            }
+    return TSLOV_OK;
+}
+
 // ---------------------------------------------------------------- backward
 struct GradOut {
     ZD* dU = nullptr;        // [src][4][V][3][3] or null
@@ -1081,8 +1175,9 @@ tslov_status prepare_defl(tslov_ctx* c, const tslov_deflation* defl, DeflSet& d)
 
 // Canonical spinor buffers of a context: 0 projected source, 1 source gradient,
 // 2 partial result (deflation); 3, 4 first and second result of the error
-// estimate; 5 g5 eta of the overlap derivative.
-constexpr int kCanonBufs = 6;
+// estimate; 5 g5 eta of the overlap derivative; 6, 7 the second block-matrix
+// result of the block error estimate.
+constexpr int kCanonBufs = 8;
 ZD* canon_buf(tslov_ctx* c, int i) { return c->canon.as<ZD>() + (size_t)i * 12 * c->g.V; }
 
 void fill_info(tslov_info* info, const EntryStatus& s, const double* ms) {
@@ -1589,7 +1684,7 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
 void tslov_destroy(tslov_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
-    for (Buf* b : {&c->U64, &c->U32, &c->badflag, &c->nestbuf, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
+    for (Buf* b : {&c->U64, &c->U32, &c->badflag, &c->nestbuf, &c->blk, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
                    &c->fields, &c->part, &c->coefmem, &c->dense, &c->denseInt, &c->densePart, &c->denseDelta,
                    &c->gpart, &c->gsrc, &c->bout, &c->wardp, &c->canon, &c->deflw, &c->deflx, &c->cgf, &c->cgp,
                    &c->cgs, &c->ckpt})
@@ -1905,6 +2000,56 @@ tslov_status tslov_ritz_values(int k, const double* diag, const double* sub, con
     }
     const int sw = tslov::tridiag_eigvals(k, diag, be.data(), ga.data(), out);
     if (sweeps) *sweeps = sw;
+    return TSLOV_OK;
+}
+
+tslov_status tslov_block_sign(tslov_ctx* c, int nu, int site, const double* X, const void* x1, const void* x2,
+                              int k, void* y1_out, void* y2_out, tslov_info* info) {
+    CHK(check_common(c, k, nullptr));
+    if (!x2 || !y1_out || !y2_out) return fail(TSLOV_ERR_ARG, "null argument");
+    if (y1_out == y2_out || y1_out == x1 || y1_out == x2 || y2_out == x1 || y2_out == x2)
+        return fail(TSLOV_ERR_ARG, "outputs must not overlap each other or the inputs");
+    tslov::BlockTangent t;
+    CHK(block_args(c, nu, site, X, t));
+    const double t0 = now_ms();
+    EntryStatus es;
+    CHK(block_tsl(c, t, (const ZD*)x1, (const ZD*)x2, k, (ZD*)y1_out, (ZD*)y2_out, es));
+    const double ms[6] = {0.0, 0.0, 0.0, 0.0, 0.0, now_ms() - t0};
+    fill_info(info, es, ms);
+    return TSLOV_OK;
+}
+
+tslov_status tslov_block_error_estimate(tslov_ctx* c, int nu, int site, const double* X, const void* psi, int k,
+                                        double* eps_out) {
+    CHK(check_common(c, k, nullptr));
+    if (!psi || !eps_out) return fail(TSLOV_ERR_ARG, "null argument");
+    tslov::BlockTangent t;
+    CHK(block_args(c, nu, site, X, t));
+    const size_t n12 = (size_t)12 * c->g.V;
+    CHK(ensure(c->canon, (size_t)kCanonBufs * n12 * sizeof(ZD)));
+    ZD* y1 = canon_buf(c, 3);
+    ZD* y2 = canon_buf(c, 4);
+    ZD* z1 = canon_buf(c, 6);
+    ZD* z2 = canon_buf(c, 7);
+    ZD* zero = canon_buf(c, 5);
+    EntryStatus es;
+    CHK(block_tsl(c, t, nullptr, (const ZD*)psi, k, y1, y2, es));
+    CHK(block_tsl(c, t, y1, y2, k, z1, z2, es));
+    tslov::launch_zero((double*)zero, 2 * n12, c->st);
+    CHK(ensure_host_part(c, 4096));
+    double* part = c->part.as<double>() + 2 * c->pstride();
+    double up = 0.0, lo = 0.0, nrm = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int nb = pass ? tslov::launch_diff_norm(z2, (const ZD*)psi, n12, part, c->st)
+                            : tslov::launch_diff_norm(zero, z1, n12, part, c->st);
+        HIPCHK(hipMemcpyAsync(c->host_part, part, (size_t)2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        for (int i = 0; i < nb; ++i) {
+            (pass ? lo : up) += c->host_part[2 * i];
+            if (pass) nrm += c->host_part[2 * i + 1];
+        }
+    }
+    *eps_out = nrm > 0.0 ? std::sqrt(up + lo) / (2.0 * std::sqrt(nrm)) : 0.0;
     return TSLOV_OK;
 }
 

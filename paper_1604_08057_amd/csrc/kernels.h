@@ -253,6 +253,35 @@ void dense_residual(const SrcList& L, const DenseWork& w, hipStream_t st);
 void launch_tridiag_inverse(const SrcList& L, const DenseWork& w, hipStream_t st);
 void launch_dense_gemm(const SrcList& L, const DenseWork& w, int ia, int ib, int ic, hipStream_t st);
 
+// ---------------------------------------------------------------- block-matrix process
+// One link parameter: U_nu(site) -> exp(i t X) U_nu(site), X as [a][b][re, im].
+struct BlockTangent {
+    int nu, site;
+    double X[3][3][2];
+};
+// Float64 SoA fields of the block process, [0] upper and [1] lower half: the source
+// x, the current and previous vectors, the products (then the residuals), and the
+// basis (step j at basis[h] + (j - 1) 12 ldv).
+struct BlockFields {
+    ZD* x[2];
+    ZD* v[2];
+    ZD* w[2];
+    ZD* vp[2];
+    ZD* wp[2];
+    ZD* a[2];
+    ZD* b[2];
+    ZD* basis[2];
+};
+int blk_blocks(const Geom& g);   // partial-sum blocks of the block-process kernels
+// out_a += dH in_a, out_b += dH^dag in_b (either pair null) for the tangent t.
+void launch_blk_tangent(const ZD* U, const BlockTangent& t, const Geom& g, double kappa, double mu, const ZD* in_a,
+                        ZD* out_a, const ZD* in_b, ZD* out_b, hipStream_t st);
+// v_1 = w_1 = x / |x| (|x| in coef.misc[0]; a zero source stops with k_used = 0).
+void launch_blk_start(const BlockFields& f, const Geom& g, Coef coef, double* part, hipStream_t st);
+// The recursion of step j after the products a = B v_j, b = B^H w_j (p0, p1: partials).
+void launch_blk_step(const BlockFields& f, const Geom& g, Coef coef, double* p0, double* p1, int j, int k,
+                     hipStream_t st);
+
 // ---------------------------------------------------------------- nested step
 // Inner two-sided Lanczos process of the nested projected-matrix step (nested.hip)
 // on W = (T^2)^{-1} (in Zt of the outer dense workspace, slot 0), from e_1.

@@ -37,7 +37,8 @@ EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links
            "tslov_current_estimate", "tslov_error_estimate", "tslov_lanczos_matrix", "tslov_dense_sign", "tslov_timing_enable",
            "tslov_timing_read", "tslov_kernel_bytes", "tslov_set_pair_ns", "tslov_get_pair_ns", "tslov_set_graphs", "tslov_set_apply_chunk",
            "tslov_get_apply_chunk", "tslov_overlap_grad", "tslov_tridiag_sign", "tslov_ritz_values",
-           "tslov_set_diagnostics", "tslov_apply_h_noalloc", "tslov_set_nested"]
+           "tslov_set_diagnostics", "tslov_apply_h_noalloc", "tslov_set_nested", "tslov_block_sign",
+           "tslov_block_error_estimate"]
 
 
 class TslovLibraryMissing(ImportError):
@@ -122,6 +123,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
                                ctypes.POINTER(ci)], ci),
         "tslov_set_diagnostics": ([vp, ci], ci),
         "tslov_set_nested": ([vp, ci], ci),
+        "tslov_block_sign": ([vp, ci, ci, ctypes.POINTER(cd), vp, vp, ci, vp, vp, ctypes.POINTER(InfoStruct)], ci),
+        "tslov_block_error_estimate": ([vp, ci, ci, ctypes.POINTER(cd), vp, ci, ctypes.POINTER(cd)], ci),
         "tslov_current_estimate": ([vp, ci, vp, ctypes.POINTER(ci), vp, vp, vp, ctypes.POINTER(cd),
                                     ctypes.POINTER(InfoStruct)], ci),
         "tslov_error_estimate": ([vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(cd)], ci),
@@ -349,6 +352,31 @@ class Context:
         info = InfoStruct()
         _check(self.lib, self.lib.tslov_tridiag_sign(self.handle, k, a, b, g, _ptr(c), ctypes.byref(info)))
         return c, Info.of(info)
+
+    def block_sign(self, nu: int, site: int, X, x2: torch.Tensor, k: int, x1: torch.Tensor | None = None):
+        """TSL_k on B = [[H, dH], [0, H]] for U_nu(site) -> exp(i t X) U_nu(site) from (x1, x2)
+        (x1 None: zero); returns (y1, y2, Info): with x1 None, y1 ~ d sgn(H) x2 / dt."""
+        import numpy as np
+        x2 = self._spinor(x2, "x2")
+        x1 = None if x1 is None else self._spinor(x1, "x1")
+        Xa = np.ascontiguousarray(np.asarray(X, dtype=np.complex128).reshape(3, 3))
+        y1, y2 = self._new_spinor(), self._new_spinor()
+        info = InfoStruct()
+        _check(self.lib, self.lib.tslov_block_sign(self.handle, int(nu), int(site),
+                                                   Xa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(x1),
+                                                   _ptr(x2), int(k), _ptr(y1), _ptr(y2), ctypes.byref(info)))
+        return y1, y2, Info.of(info)
+
+    def block_error_estimate(self, nu: int, site: int, X, psi: torch.Tensor, k: int) -> float:
+        """eps_B of the block process for the link parameter (eq. bA_error_est)."""
+        import numpy as np
+        psi = self._spinor(psi, "psi")
+        Xa = np.ascontiguousarray(np.asarray(X, dtype=np.complex128).reshape(3, 3))
+        eps = ctypes.c_double()
+        _check(self.lib, self.lib.tslov_block_error_estimate(self.handle, int(nu), int(site),
+                                                             Xa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                             _ptr(psi), int(k), ctypes.byref(eps)))
+        return eps.value
 
     def set_nested(self, k_inner: int = 0):
         """Nested projected-matrix step of the sign calls with inner Krylov size k_inner (0: plain)."""

@@ -1,0 +1,78 @@
+"""The paper's block-matrix derivative (Theorem 1, eq. func_derivative_1) and its error
+estimate (eq. bA_error_est) on the GPU against oracle.blockderiv.
+
+TSL of size k on B = [[H, dH], [0, H]] for one link parameter U_nu(x) -> exp(itX) U_nu(x):
+* from (0, psi): the upper half (the derivative) and the lower half (the sign)
+  against the oracle at the 4^4 workload (k = 40) for an su(3) and a U(1) direction,
+  on a spatial link in the bulk and on a temporal link across the antiperiodic
+  boundary (where the folded boundary sign must reach the tangent), to 1e-10 or
+  10 sigma; at the 8^4 workload (k = 100) for one direction;
+* from a general source (x1, x2) against the oracle's block process;
+* eps_B against the oracle's (two block processes, the second from the first result).
+"""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, rel, say
+from oracle import blockderiv as BD
+from oracle import grad as GR
+from oracle.wilson import WilsonOperator
+from synthetic import config_rng, workload, z2_complex_source
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(wl):
+    from paper_1604_08057_amd import Context
+    ctx = Context(wl.dims, wl.mass, wl.mu)
+    ctx.set_links(dev(wl.links()))
+    return ctx
+
+
+def _cases(wl):
+    r = config_rng(wl.config, 4)
+    V3 = wl.dims[0] * wl.dims[1] * wl.dims[2]
+    last_t = (wl.dims[3] - 1) * V3 + 5          # a site on the last time slice
+    return [(0, 17, GR.su3_direction(r)), (3, last_t, GR.su3_direction(r)), (3, last_t, np.eye(3, dtype=complex)),
+            (1, 40, np.eye(3, dtype=complex))]
+
+
+@pytest.mark.parametrize("config,k", [(1, 40), (2, 100)])
+def test_block_derivative_against_oracle(config, k):
+    wl = workload(config)
+    op = WilsonOperator(wl.dims, wl.mass, wl.mu)
+    U, psi = wl.links(), wl.psi()
+    ctx = _ctx(wl)
+    cases = _cases(wl) if config == 1 else _cases(wl)[1:2]
+    perm = np.random.default_rng(0).permutation(24 * op.volume)
+    for nu, site, X in cases:
+        ref = BD.d1_derivative(op, U, psi, k, nu, site, X)
+        alt = BD.d1_derivative(op, U, psi, k, nu, site, X, perm=perm)
+        sig = max(rel(alt["y1"], ref["y1"]), rel(alt["y2"], ref["y2"]))
+        y1, y2, info = ctx.block_sign(nu, site, X, dev(psi), k)
+        e1, e2 = rel(host(y1), ref["y1"]), rel(host(y2), ref["y2"])
+        say(f"block derivative {wl.dims} k={k} link ({nu}, {site}): d/dt err {e1:.2e} sign err {e2:.2e} "
+            f"(sigma {sig:.2e}) k_used {info.k_used} ms {info.ms[5]:.1f}")
+        assert info.k_used == ref["k_used"]
+        assert e1 < max(1e-10, 10 * sig) and e2 < max(1e-10, 10 * sig)
+    ctx.close()
+
+
+def test_block_process_general_source_and_error_estimate():
+    wl = workload(1)
+    op = WilsonOperator(wl.dims, wl.mass, wl.mu)
+    U, psi = wl.links(), wl.psi()
+    nu, site, X = _cases(wl)[1]
+    x1 = z2_complex_source(wl.volume, np.random.default_rng(8))
+    k = 30
+    bop = BD.BlockOperator(op, U, BD.link_direction_field(U, nu, site, X), psi.shape)
+    ref = BD.block_tsl(bop, x1, psi, k)
+    ctx = _ctx(wl)
+    y1, y2, info = ctx.block_sign(nu, site, X, dev(psi), k, x1=dev(x1))
+    e1, e2 = rel(host(y1), ref["y1"]), rel(host(y2), ref["y2"])
+    eps = ctx.block_error_estimate(nu, site, X, dev(psi), k)
+    ctx.close()
+    want = BD.eps_block(op, U, psi, k, nu, site, X)
+    say(f"block process from (x1, x2), k={k}: errs {e1:.2e} {e2:.2e}; eps_B {eps:.10e} (oracle {want:.10e})")
+    assert e1 < 1e-10 and e2 < 1e-10
+    assert abs(eps - want) < 1e-9 * want
