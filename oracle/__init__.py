@@ -19,7 +19,9 @@ Everything is float64 / complex128.  Modules:
 * ``grad``    -- derivative of S_k = Re<eta|TSL_k(H(U), psi)> with respect to all
   links by torch autograd, finite differences, the exact (Daleckii-Krein)
   gradient on tiny lattices and the U(1) Ward identity (Sec. 4.3);
-* ``deflation`` -- deflated sign function with known eigenpairs (Sec. 3, App. E).
+* ``deflation`` -- deflated sign function with known eigenpairs (Sec. 3, App. E);
+* ``constfield`` -- exact eigenpairs and sign of H on a gauge-rotated constant
+  field (one 12 x 12 matrix per momentum), the deflation inputs at 16^4.
 
 Parity status of each function is stated in its docstring; every function is
 pinned by ``tests/test_oracle_*.py`` against closed forms, identities or brute
