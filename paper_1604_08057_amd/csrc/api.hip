@@ -1016,6 +1016,7 @@ struct GradOut {
     ZD* dU = nullptr;        // [src][4][V][3][3] or null
     ZD* dpsi = nullptr;      // [src][V][4][3] or null
     double* jsum = nullptr;  // current estimator: [4][V] sum of U(1) projections
+    ZD* y = nullptr;         // recompute mode: sgn(H) psi per source, assembled segment by segment
     int accumulate = 0;
     int ward = 0;            // compute the Ward check (needs psi)
     const ZD* psi = nullptr;
@@ -1088,6 +1089,8 @@ tslov_status backward(tslov_ctx* c, const SrcList& L, GradOut& out) {
                 tslov::launch_fwd_replay<R, RL>(U, g, c->kappa, c->mu, wk, Lr, c->coef, j, c->st);
                 if (j <= j1) tslov::launch_recur_replay<R>(g, wk, Lr, c->coef, j, c->st);
             }
+            // the segment's share of y = |x| sum_j c_j v_j while its vectors are in the ring
+            if (out.y) tslov::launch_assemble<R>(g, wk, reaching(j0), c->coef, nullptr, 0, out.y, c->st, j0, j1);
             for (int j = j1; j >= j0; --j) reverse_step(j);
             tslov::launch_force<R>(g, c->kappa, c->mu, wk, reaching(j0), nchunk, c->gpart.as<ZD>(), c->st, j0, j1,
                                    1);
@@ -1373,8 +1376,11 @@ tslov_status grad_batched(tslov_ctx* c, BatchRequest& q) {
         if (Ld.n > 0) {
             CHK(dense_step(c, Ld, 1, iters, &stag));
             tg2 = now_ms();
-            if (q.y) tslov::launch_assemble<R>(c->g, work<R>(c), Ld, c->coef, nullptr, 0, q.y, c->st);
+            // with every vector stored y is assembled here; in recompute mode the reverse
+            // pass assembles it segment by segment from the regenerated vectors
+            if (q.y && !c->ring) tslov::launch_assemble<R>(c->g, work<R>(c), Ld, c->coef, nullptr, 0, q.y, c->st);
             GradOut go;
+            go.y = c->ring ? q.y : nullptr;
             go.dU = q.dU;
             go.dpsi = q.dpsi;
             go.jsum = q.jsum;

@@ -1120,22 +1120,26 @@ void launch_recur_replay(const Geom& g, const Work<R>& wk, const SrcList& L, Coe
     hipLaunchKernelGGL(k_recur<R>, grid, dim3(kPBlock), 0, st, g, wk, L, coef, j, np_sten(g.V), 1);
 }
 
-// out(s) = [psi(s) +] g5^{overlap} |x| sum_{j <= k_used} c_j v_j(s), canonical layout.
+// out(s) = [psi(s) +] g5^{overlap} |x| sum_{j <= k_used} c_j v_j(s), canonical layout;
+// with j1 > 0 the sum runs over j0..min(j1, k_used) and adds to out below the
+// entry's top segment (see launch_assemble).
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_assemble(Geom g, Work<R> wk, SrcList L, Coef coef0,
                                                      const ZD* __restrict__ psi_base, int overlap,
-                                                     ZD* __restrict__ out_base) {
+                                                     ZD* __restrict__ out_base, int j0, int j1) {
     const int e = blockIdx.y, slot = L.slot[e];
     const Coef coef = coef0.at(slot);
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= g.V) return;
     const size_t co = (size_t)L.src[e] * 12 * g.V;
     const int k = coef.status[1];
+    const int jlast = j1 > 0 ? min(j1, k) : k;
+    const bool add = j1 > 0 && k > j1;
     const double nx = coef.misc[0];
     ZD acc[12];
 #pragma unroll
     for (int p = 0; p < 12; ++p) acc[p] = mk<double>(0, 0);
-    for (int j = 1; j <= k; ++j) {
+    for (int j = j0; j <= jlast; ++j) {
         const ZD c = coef.c[j];
         const Z<R>* f = wk.v(slot, j);
 #pragma unroll
@@ -1145,16 +1149,18 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Geom g, Work<R> wk, SrcList
     for (int p = 0; p < 12; ++p) {
         const double sg = (overlap && p >= 6) ? -nx : nx;
         ZD o = sg * acc[p];
-        if (overlap) o = o + psi_base[co + (size_t)s * 12 + p];
-        out_base[co + (size_t)s * 12 + p] = o;
+        const size_t i = co + (size_t)s * 12 + p;
+        if (add) o = o + out_base[i];
+        else if (overlap) o = o + psi_base[i];
+        out_base[i] = o;
     }
 }
 
 template <typename R>
 void launch_assemble(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, const ZD* psi_canon,
-                     int overlap, ZD* out, hipStream_t st) {
+                     int overlap, ZD* out, hipStream_t st, int j0, int j1) {
     hipLaunchKernelGGL(k_assemble<R>, dim3(grid_for(g.V), L.n), dim3(kBlock), 0, st, g, wk, L, coef, psi_canon,
-                       overlap, out);
+                       overlap, out, j0, j1);
 }
 
 // =============================================================== backward (reverse mode)
@@ -1939,7 +1945,7 @@ int launch_biorth(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef,
     template void launch_recur<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);         \
     template void launch_recur_replay<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);  \
     template void launch_assemble<R>(const Geom&, const Work<R>&, const SrcList&, Coef, const ZD*, int, ZD*,    \
-                                     hipStream_t);                                                              \
+                                     hipStream_t, int, int);                                                    \
     template void launch_bwd_ra<R>(const Geom&, const Work<R>&, const SrcList&, Coef, int, hipStream_t);        \
     template void launch_force<R>(const Geom&, double, double, const Work<R>&, const SrcList&, int, ZD*,        \
                                   hipStream_t, int, int, int);                                                  \

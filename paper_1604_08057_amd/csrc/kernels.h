@@ -105,10 +105,13 @@ void launch_fwd_replay(const Z<RL>* U, const Geom& g, double kappa, double mu, c
                        Coef coef, int j, hipStream_t st);
 template <typename R>
 void launch_recur_replay(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, int j, hipStream_t st);
-// out[src] (canonical) = [psi[src] +] g5^{overlap} |x| sum_j c_j v_j
+// out[src] (canonical) = [psi[src] +] g5^{overlap} |x| sum_j c_j v_j over j = 1..k_used.
+// With j1 > 0 only the steps j0..min(j1, k_used) are summed (one recompute segment,
+// whose basis vectors sit in the ring): an entry whose k_used <= j1 (its top
+// segment) writes out, every lower segment adds to it.
 template <typename R>
 void launch_assemble(const Geom& g, const Work<R>& wk, const SrcList& L, Coef coef, const ZD* psi_canon,
-                     int overlap, ZD* out, hipStream_t st);
+                     int overlap, ZD* out, hipStream_t st, int j0 = 1, int j1 = 0);
 
 // Biorthogonality probe of every entry after its forward pass: block partials
 // (x^H v_k re, im, w_k^H x re, im), k = k_used (zeros below 2), in wk.p(slot, 3).

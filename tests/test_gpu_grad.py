@@ -158,15 +158,17 @@ def test_recompute_matches_stored(dims, k, m):
     ctx = Context(dims, -2.0, 0.2)
     ctx.set_links(dev(U))
     say(f"recompute dims={dims} k={k} m={m}")
-    S0, dU0, dp0, i0 = ctx.sign_grad(eta, psi, k, want_dpsi=True)
-    S1, dU1, dp1, i1 = ctx.sign_grad(eta, psi, k, want_dpsi=True, recompute=m)
+    S0, dU0, dp0, i0, y0 = ctx.sign_grad(eta, psi, k, want_dpsi=True, want_y=True)
+    S1, dU1, dp1, i1, y1 = ctx.sign_grad(eta, psi, k, want_dpsi=True, recompute=m, want_y=True)
     S2, dU2, _, _ = ctx.sign_grad(eta, psi, k, want_dpsi=True)   # back to storing every vector
     ctx.close()
-    e, ep = rel(host(dU1), host(dU0)), rel(host(dp1), host(dp0))
-    say(f"  k_used {i0.k_used}/{i1.k_used}: S equal {S1 == S0}, dpsi rel diff {ep:.2e}, dU rel diff {e:.2e}")
+    e, ep, ey = rel(host(dU1), host(dU0)), rel(host(dp1), host(dp0)), rel(host(y1), host(y0))
+    say(f"  k_used {i0.k_used}/{i1.k_used}: S equal {S1 == S0}, dpsi rel diff {ep:.2e}, dU rel diff {e:.2e}, "
+        f"y rel diff {ey:.2e}")
     assert i1.k_used == i0.k_used
     assert S1 == S0          # the forward pass is the same
     assert e < 1e-12 and ep < 1e-12
+    assert ey < 1e-13        # y from the regenerated segments: same vectors, summed by segment
     assert S2 == S0 and torch.equal(dU2, dU0)
 
 
