@@ -21,7 +21,9 @@ Everything is float64 / complex128.  Modules:
   gradient on tiny lattices and the U(1) Ward identity (Sec. 4.3);
 * ``deflation`` -- deflated sign function with known eigenpairs (Sec. 3, App. E);
 * ``constfield`` -- exact eigenpairs and sign of H on a gauge-rotated constant
-  field (one 12 x 12 matrix per momentum), the deflation inputs at 16^4.
+  field (one 12 x 12 matrix per momentum), the deflation inputs at 16^4;
+* ``tuning`` -- the tuning run that picks the Krylov sizes and its cross-check
+  (Sec. 4.1).
 
 Parity status of each function is stated in its docstring; every function is
 pinned by ``tests/test_oracle_*.py`` against closed forms, identities or brute
