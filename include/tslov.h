@@ -306,6 +306,38 @@ tslov_status tslov_block_sign(tslov_ctx* ctx, int nu, int site, const double* X,
 tslov_status tslov_block_error_estimate(tslov_ctx* ctx, int nu, int site, const double* X, const void* psi, int k,
                                         double* eps_out);
 
+/* One link parameter of the block-matrix derivative: U_nu(site) -> exp(i t X) U_nu(site),
+ * X a 3 x 3 complex matrix as 18 doubles, row-major (re, im). */
+typedef struct {
+    int nu;
+    int site;
+    double X[18];
+} tslov_link_direction;
+
+/* The tuning run that fixes the Krylov sizes before production runs (Sec. 4.1,
+ * numerical setup and tuning).  The trial vector is phi = (1, ..., 1) (built here).
+ * For every candidate i (outer size k_outer[i], nested inner size k_inner[i], 0 for
+ * the plain step; k_inner may be NULL for all-plain candidates):
+ *   eps_out[i] = eps_A of eq. error_est of the (deflated, if defl) sign of phi, or,
+ *                with dir, eps_B of eq. bA_error_est for that link direction and the
+ *                sparse source (0, phi) (k_inner must be 0 and defl NULL/empty then);
+ *   ms_out[i]  = wall time in ms of the first approximation (the sign of phi, or the
+ *                first block process), taken on its second run so that allocation and
+ *                first touch of a larger workspace do not count.
+ * A candidate whose process breaks down seriously or whose projected matrix has a
+ * Ritz value on the imaginary axis gets eps = +inf and ms = NaN.  *chosen receives the
+ * fastest candidate with eps <= trial_target (the first of equal times), -1 if none;
+ * the paper's rule of thumb is trial_target = 0.1 eps_0 for a wanted precision eps_0.
+ * With nrand > 0 and a choice, cross_out[r] receives the same error estimate for the
+ * caller's vector r of rand ([nrand][V][4][3] complex128, device) at the chosen
+ * parameters (the paper's cross-check, 20-30 random vectors, compared with eps_0 by
+ * the caller).  The context's nested setting is unchanged on return.  Times depend on
+ * the machine, so *chosen may differ between runs where candidates take similar time.
+ * ERR_ARG for sizes out of range, a bad direction, or nested/deflated block mode. */
+tslov_status tslov_tune_k(tslov_ctx* ctx, int ncand, const int* k_outer, const int* k_inner, double trial_target,
+                          const tslov_deflation* defl, const tslov_link_direction* dir, int nrand, const void* rand,
+                          double* eps_out, double* ms_out, int* chosen, double* cross_out);
+
 /* Nested projected-matrix step (one level of nesting, the paper's production
  * setting, Sec. 4.1; the nested method itself is cited there, not described).
  * With k_inner = m > 0, tslov_sign, tslov_overlap and tslov_error_estimate replace

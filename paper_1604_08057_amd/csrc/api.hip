@@ -185,6 +185,7 @@ struct tslov_ctx {
     Buf bout;        // per-entry canonical y and dpsi (Ward check)
     Buf wardp;       // Ward block maxima
     Buf canon;       // canonical spinors: projected source, partial result, error estimate
+    Buf trial;       // the tuning run's trial vector (1, ..., 1)
     Buf deflw;       // deflation coefficients, signs and partial sums
     Buf deflx;       // deflated derivative: R^H eta, R^H psibar, q, -q and dot partials
     Buf cgf, cgp, cgs;   // shifted solves: fields, partial sums, per-system scalars
@@ -1632,6 +1633,85 @@ tslov_status apply_fields(tslov_ctx* c, const void* in, void* out, double mu, in
 
 }  // namespace
 
+namespace {
+
+// eps_B of eq. bA_error_est for the tangent t and source (0, psi); ms_first (nullable)
+// receives the wall time of the first block process.  Uses canonical buffers 3..7.
+tslov_status block_eps(tslov_ctx* c, const tslov::BlockTangent& t, const ZD* psi, int k, double* eps_out,
+                       double* ms_first) {
+    const size_t n12 = (size_t)12 * c->g.V;
+    CHK(ensure(c->canon, (size_t)kCanonBufs * n12 * sizeof(ZD)));
+    ZD* y1 = canon_buf(c, 3);
+    ZD* y2 = canon_buf(c, 4);
+    ZD* z1 = canon_buf(c, 6);
+    ZD* z2 = canon_buf(c, 7);
+    ZD* zero = canon_buf(c, 5);
+    EntryStatus es;
+    HIPCHK(hipStreamSynchronize(c->st));
+    const double t0 = now_ms();
+    CHK(block_tsl(c, t, nullptr, psi, k, y1, y2, es));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (ms_first) *ms_first = now_ms() - t0;
+    CHK(block_tsl(c, t, y1, y2, k, z1, z2, es));
+    tslov::launch_zero((double*)zero, 2 * n12, c->st);
+    CHK(ensure_host_part(c, 4096));
+    double* part = c->part.as<double>() + 2 * c->pstride();
+    double up = 0.0, lo = 0.0, nrm = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int nb = pass ? tslov::launch_diff_norm(z2, psi, n12, part, c->st)
+                            : tslov::launch_diff_norm(zero, z1, n12, part, c->st);
+        HIPCHK(hipMemcpyAsync(c->host_part, part, (size_t)2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        for (int i = 0; i < nb; ++i) {
+            (pass ? lo : up) += c->host_part[2 * i];
+            if (pass) nrm += c->host_part[2 * i + 1];
+        }
+    }
+    *eps_out = nrm > 0.0 ? std::sqrt(up + lo) / (2.0 * std::sqrt(nrm)) : 0.0;
+    return TSLOV_OK;
+}
+
+// One candidate of the tuning run on source psi: the error estimate and the wall
+// time of the first approximation (its second run, so that allocation and first
+// touch of a larger workspace do not count).  A candidate whose process breaks
+// down or whose projected matrix has a Ritz value on the imaginary axis gets an
+// infinite error.
+tslov_status tune_candidate(tslov_ctx* c, const ZD* psi, int k, int k_inner, const tslov_deflation* defl,
+                            const tslov::BlockTangent* t, double* eps, double* ms) {
+    auto soft = [&](tslov_status s) {
+        if (s == TSLOV_ERR_BREAKDOWN || s == TSLOV_ERR_SIGN_UNDEFINED) {
+            *eps = INFINITY;
+            *ms = NAN;
+            return TSLOV_OK;
+        }
+        return s;
+    };
+    if (t) {
+        double m0 = 0.0;
+        tslov_status s = block_eps(c, *t, psi, k, eps, &m0);
+        if (s == TSLOV_OK) s = block_eps(c, *t, psi, k, eps, ms);
+        return soft(s);
+    }
+    const int keep = c->nest_m;
+    c->nest_m = k_inner;
+    ZD* y = canon_buf(c, 3);
+    tslov_status s = sign_dispatch(c, psi, y, k, defl, nullptr, 0, 0);
+    if (s == TSLOV_OK) {
+        HIPCHK(hipStreamSynchronize(c->st));
+        const double t0 = now_ms();
+        s = sign_dispatch(c, psi, y, k, defl, nullptr, 0, 0);
+        if (s == TSLOV_OK) {
+            HIPCHK(hipStreamSynchronize(c->st));
+            *ms = now_ms() - t0;
+            s = error_of(c, psi, y, k, defl, eps);
+        }
+    }
+    c->nest_m = keep;
+    return soft(s);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* tslov_last_error(void) { return g_err.c_str(); }
@@ -1690,7 +1770,7 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
 void tslov_destroy(tslov_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
-    for (Buf* b : {&c->U64, &c->U32, &c->badflag, &c->nestbuf, &c->blk, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
+    for (Buf* b : {&c->trial, &c->U64, &c->U32, &c->badflag, &c->nestbuf, &c->blk, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
                    &c->fields, &c->part, &c->coefmem, &c->dense, &c->denseInt, &c->densePart, &c->denseDelta,
                    &c->gpart, &c->gsrc, &c->bout, &c->wardp, &c->canon, &c->deflw, &c->deflx, &c->cgf, &c->cgp,
                    &c->cgs, &c->ckpt})
@@ -2031,31 +2111,48 @@ tslov_status tslov_block_error_estimate(tslov_ctx* c, int nu, int site, const do
     if (!psi || !eps_out) return fail(TSLOV_ERR_ARG, "null argument");
     tslov::BlockTangent t;
     CHK(block_args(c, nu, site, X, t));
+    return block_eps(c, t, (const ZD*)psi, k, eps_out, nullptr);
+}
+
+tslov_status tslov_tune_k(tslov_ctx* c, int ncand, const int* k_outer, const int* k_inner, double trial_target,
+                          const tslov_deflation* defl, const tslov_link_direction* dir, int nrand, const void* rand,
+                          double* eps_out, double* ms_out, int* chosen, double* cross_out) {
+    CHK(check_common(c, 1, defl));
+    if (ncand < 1 || !k_outer || !eps_out || !ms_out || !chosen) return fail(TSLOV_ERR_ARG, "null argument");
+    if (nrand < 0 || (nrand > 0 && (!rand || !cross_out))) return fail(TSLOV_ERR_ARG, "nrand needs rand and cross_out");
+    if (!(trial_target >= 0.0)) return fail(TSLOV_ERR_ARG, "trial_target must be >= 0");
+    for (int i = 0; i < ncand; ++i) {
+        if (k_outer[i] < 1 || k_outer[i] > kMaxK) return fail(TSLOV_ERR_ARG, "every k_outer must be in [1, 1024]");
+        const int ki = k_inner ? k_inner[i] : 0;
+        if (ki < 0 || ki > kMaxK) return fail(TSLOV_ERR_ARG, "every k_inner must be in [0, 1024]");
+        if (dir && ki != 0) return fail(TSLOV_ERR_ARG, "the block-matrix process has no nested step (k_inner = 0)");
+    }
+    if (dir && defl && defl->l != 0) return fail(TSLOV_ERR_ARG, "the block-matrix process takes no deflation");
+    tslov::BlockTangent t{};
+    if (dir) CHK(block_args(c, dir->nu, dir->site, dir->X, t));
     const size_t n12 = (size_t)12 * c->g.V;
     CHK(ensure(c->canon, (size_t)kCanonBufs * n12 * sizeof(ZD)));
-    ZD* y1 = canon_buf(c, 3);
-    ZD* y2 = canon_buf(c, 4);
-    ZD* z1 = canon_buf(c, 6);
-    ZD* z2 = canon_buf(c, 7);
-    ZD* zero = canon_buf(c, 5);
-    EntryStatus es;
-    CHK(block_tsl(c, t, nullptr, (const ZD*)psi, k, y1, y2, es));
-    CHK(block_tsl(c, t, y1, y2, k, z1, z2, es));
-    tslov::launch_zero((double*)zero, 2 * n12, c->st);
-    CHK(ensure_host_part(c, 4096));
-    double* part = c->part.as<double>() + 2 * c->pstride();
-    double up = 0.0, lo = 0.0, nrm = 0.0;
-    for (int pass = 0; pass < 2; ++pass) {
-        const int nb = pass ? tslov::launch_diff_norm(z2, (const ZD*)psi, n12, part, c->st)
-                            : tslov::launch_diff_norm(zero, z1, n12, part, c->st);
-        HIPCHK(hipMemcpyAsync(c->host_part, part, (size_t)2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    CHK(ensure(c->trial, n12 * sizeof(ZD)));
+    {
+        const std::vector<ZD> ones(n12, ZD{1.0, 0.0});
+        HIPCHK(hipMemcpyAsync(c->trial.p, ones.data(), n12 * sizeof(ZD), hipMemcpyHostToDevice, c->st));
         HIPCHK(hipStreamSynchronize(c->st));
-        for (int i = 0; i < nb; ++i) {
-            (pass ? lo : up) += c->host_part[2 * i];
-            if (pass) nrm += c->host_part[2 * i + 1];
-        }
     }
-    *eps_out = nrm > 0.0 ? std::sqrt(up + lo) / (2.0 * std::sqrt(nrm)) : 0.0;
+    const ZD* phi = c->trial.as<ZD>();
+    for (int i = 0; i < ncand; ++i)
+        CHK(tune_candidate(c, phi, k_outer[i], k_inner ? k_inner[i] : 0, defl, dir ? &t : nullptr, &eps_out[i],
+                           &ms_out[i]));
+    // the fastest candidate within the trial target (the first of equal times)
+    int best = -1;
+    for (int i = 0; i < ncand; ++i)
+        if (eps_out[i] <= trial_target && (best < 0 || ms_out[i] < ms_out[best])) best = i;
+    *chosen = best;
+    if (best >= 0)
+        for (int r = 0; r < nrand; ++r) {
+            double ms = 0.0;
+            CHK(tune_candidate(c, (const ZD*)rand + (size_t)r * n12, k_outer[best], k_inner ? k_inner[best] : 0, defl,
+                               dir ? &t : nullptr, &cross_out[r], &ms));
+        }
     return TSLOV_OK;
 }
 

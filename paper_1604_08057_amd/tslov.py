@@ -38,7 +38,7 @@ EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links
            "tslov_timing_read", "tslov_kernel_bytes", "tslov_set_pair_ns", "tslov_get_pair_ns", "tslov_set_graphs", "tslov_set_apply_chunk",
            "tslov_get_apply_chunk", "tslov_overlap_grad", "tslov_tridiag_sign", "tslov_ritz_values",
            "tslov_set_diagnostics", "tslov_apply_h_noalloc", "tslov_set_nested", "tslov_block_sign",
-           "tslov_block_error_estimate"]
+           "tslov_block_error_estimate", "tslov_tune_k"]
 
 
 class TslovLibraryMissing(ImportError):
@@ -61,6 +61,10 @@ class InfoStruct(ctypes.Structure):
                 ("cg_iters", ctypes.c_int), ("flags", ctypes.c_int), ("reserved", ctypes.c_int),
                 ("norm_x", ctypes.c_double), ("min_abs_re_ritz", ctypes.c_double), ("norm_T", ctypes.c_double),
                 ("biorth_err", ctypes.c_double), ("eps_A", ctypes.c_double), ("ms", ctypes.c_double * 6)]
+
+
+class LinkDirection(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_int), ("site", ctypes.c_int), ("X", ctypes.c_double * 18)]
 
 
 class DeflationStruct(ctypes.Structure):
@@ -125,6 +129,9 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_set_nested": ([vp, ci], ci),
         "tslov_block_sign": ([vp, ci, ci, ctypes.POINTER(cd), vp, vp, ci, vp, vp, ctypes.POINTER(InfoStruct)], ci),
         "tslov_block_error_estimate": ([vp, ci, ci, ctypes.POINTER(cd), vp, ci, ctypes.POINTER(cd)], ci),
+        "tslov_tune_k": ([vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci), cd, ctypes.POINTER(DeflationStruct),
+                          ctypes.POINTER(LinkDirection), ci, vp, ctypes.POINTER(cd), ctypes.POINTER(cd),
+                          ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
         "tslov_current_estimate": ([vp, ci, vp, ctypes.POINTER(ci), vp, vp, vp, ctypes.POINTER(cd),
                                     ctypes.POINTER(InfoStruct)], ci),
         "tslov_error_estimate": ([vp, vp, ci, ctypes.POINTER(DeflationStruct), ctypes.POINTER(cd)], ci),
@@ -377,6 +384,36 @@ class Context:
                                                              Xa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                                              _ptr(psi), int(k), ctypes.byref(eps)))
         return eps.value
+
+    def tune_k(self, k_outer, k_inner=None, trial_target: float = 1e-9, defl: "Deflation | None" = None,
+               direction=None, rand: torch.Tensor | None = None):
+        """The tuning run of the Krylov sizes on the trial vector (1, ..., 1): dict with
+        eps and ms per candidate, chosen (index or -1) and cross (the error of each
+        vector of rand, (nrand, V, 4, 3), at the chosen sizes).  direction = (nu, site, X)
+        switches to eps_B of the block-matrix derivative."""
+        import numpy as np
+        n = len(k_outer)
+        ko = (ctypes.c_int * n)(*[int(k) for k in k_outer])
+        ki = None if k_inner is None else (ctypes.c_int * n)(*[int(k) for k in k_inner])
+        eps = (ctypes.c_double * n)()
+        ms = (ctypes.c_double * n)()
+        chosen = ctypes.c_int()
+        d = None if defl is None else ctypes.byref(defl.struct)
+        dirp = None
+        if direction is not None:
+            nu, site, X = direction
+            Xa = np.ascontiguousarray(np.asarray(X, dtype=np.complex128)).view(np.float64).ravel()
+            dirp = ctypes.byref(LinkDirection(int(nu), int(site), (ctypes.c_double * 18)(*Xa.tolist())))
+        nrand, rp, cross = 0, None, None
+        if rand is not None:
+            rand = self._sources(rand, "rand")
+            nrand = rand.shape[0]
+            rp = _ptr(rand)
+            cross = (ctypes.c_double * nrand)()
+        _check(self.lib, self.lib.tslov_tune_k(self.handle, n, ko, ki, float(trial_target), d, dirp, nrand, rp, eps, ms,
+                                               ctypes.byref(chosen), cross))
+        return {"eps": list(eps), "ms": list(ms), "chosen": chosen.value,
+                "cross": list(cross) if (cross is not None and chosen.value >= 0) else []}
 
     def set_nested(self, k_inner: int = 0):
         """Nested projected-matrix step of the sign calls with inner Krylov size k_inner (0: plain)."""

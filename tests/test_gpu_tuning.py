@@ -1,0 +1,100 @@
+"""The tuning run of the Krylov sizes (Sec. 4.1) on the GPU against oracle.tuning.
+
+On the trial vector (1, ..., 1):
+* the error estimate of every candidate against the oracle's (eq. error_est): plain
+  and nested steps at the 4^4 workload, deflated candidates on 2^3x4 with 10
+  dense eigenpairs, and eps_B of the block-matrix derivative (eq. bA_error_est) for
+  a temporal link across the boundary, to 1e-9 relative or 10 sigma (sigma the
+  oracle's change under a permuted summation order: the nested step's inner
+  process on (T^2)^-1 amplifies rounding, 1e-6 relative at m = 16);
+* the choice equals the oracle's selection rule applied to the library's own times
+  and errors (the times are the machine's, so the rule is what can be compared);
+* the cross-check errors of three Z2 vectors at the chosen sizes against the oracle;
+* a target no candidate meets gives no choice and no cross-check.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import dev, say
+from oracle import deflation as DF
+from oracle import grad as GR
+from oracle import tuning as TU
+from oracle.wilson import WilsonOperator, dense_h
+from synthetic import config_rng, random_links, workload, z2_complex_source
+
+pytestmark = pytest.mark.gpu
+
+
+def _close(a, b, tol=1e-9):
+    return abs(a - b) <= tol * abs(b)
+
+
+def test_tuning_run_plain_and_nested():
+    from paper_1604_08057_amd import Context
+    wl = workload(1)
+    U = wl.links()
+    op = WilsonOperator(wl.dims, wl.mass, wl.mu)
+    phi = TU.trial_vector(wl.volume)
+    cands = [(16, 0), (32, 0), (48, 0), (64, 0), (64, 16), (64, 32)]
+    want = [TU.sign_error(op, U, phi, k, ki) for k, ki in cands]
+    perm = np.random.default_rng(0).permutation(12 * wl.volume)
+    sig = [abs(TU.sign_error(op, U, phi, k, ki, perm=perm) - w) for (k, ki), w in zip(cands, want)]
+    target = 1.01 * want[2]
+    r = config_rng(1, 4)
+    vecs = np.stack([z2_complex_source(wl.volume, r) for _ in range(3)])
+    ctx = Context(wl.dims, wl.mass, wl.mu)
+    ctx.set_links(dev(U))
+    res = ctx.tune_k([k for k, _ in cands], [ki for _, ki in cands], target, rand=dev(vecs))
+    for (k, ki), e, w, sg, ms in zip(cands, res["eps"], want, sig, res["ms"]):
+        say(f"  tune 4^4 k={k} inner={ki}: eps {e:.10e} (oracle {w:.10e}, sigma {sg:.1e}) {ms:.2f} ms")
+        assert abs(e - w) <= max(1e-9 * w, 10 * sg)
+    assert res["chosen"] == TU.select(res["eps"], res["ms"], target) >= 0
+    k, ki = cands[res["chosen"]]
+    for v, e in zip(vecs, res["cross"]):
+        w = TU.sign_error(op, U, v, k, ki)
+        assert _close(e, w)
+    say(f"  chosen {cands[res['chosen']]}, cross-check errors {['%.3e' % e for e in res['cross']]}")
+    none = ctx.tune_k([16, 32], None, 0.0, rand=dev(vecs))
+    assert none["chosen"] == -1 and none["cross"] == []
+    ctx.close()
+
+
+def test_tuning_run_deflated():
+    from paper_1604_08057_amd import Context
+    dims, l = (2, 2, 2, 4), 10
+    U = random_links(dims, 0.5, np.random.default_rng(21))
+    op = WilsonOperator(dims, -2.0, 0.3)
+    lam, R, L = DF.eigenpairs(dense_h(U, dims, -2.0, 0.3), l)
+    V = op.volume
+    phi = TU.trial_vector(V)
+    ks = [8, 16, 24]
+    want = [TU.sign_error(op, U, phi, k, defl=(lam, R, L)) for k in ks]
+    ctx = Context(dims, -2.0, 0.3)
+    ctx.set_links(dev(U))
+    defl = ctx.deflation(dev(R.T.reshape(l, V, 4, 3)), dev(L.T.reshape(l, V, 4, 3)), lam)
+    res = ctx.tune_k(ks, None, 1.0, defl=defl)
+    ctx.close()
+    for k, e, w in zip(ks, res["eps"], want):
+        say(f"  tune deflated 2^3x4 k={k}: eps {e:.10e} (oracle {w:.10e})")
+        assert _close(e, w)
+    assert res["chosen"] == TU.select(res["eps"], res["ms"], 1.0)
+
+
+def test_tuning_run_block_derivative():
+    from paper_1604_08057_amd import Context
+    wl = workload(1)
+    U = wl.links()
+    op = WilsonOperator(wl.dims, wl.mass, wl.mu)
+    phi = TU.trial_vector(wl.volume)
+    X = GR.su3_direction(config_rng(1, 4))
+    site = (wl.dims[3] - 1) * wl.dims[0] * wl.dims[1] * wl.dims[2] + 5
+    ks = [16, 32]
+    want = [TU.block_error(op, U, phi, k, 3, site, X) for k in ks]
+    ctx = Context(wl.dims, wl.mass, wl.mu)
+    ctx.set_links(dev(U))
+    res = ctx.tune_k(ks, None, 10.0, direction=(3, site, X))
+    ctx.close()
+    for k, e, w in zip(ks, res["eps"], want):
+        say(f"  tune block 4^4 k={k}: eps_B {e:.10e} (oracle {w:.10e})")
+        assert _close(e, w)
+    assert res["chosen"] == TU.select(res["eps"], res["ms"], 10.0)
