@@ -1,6 +1,10 @@
 """Per-kernel summary of a rocprofv3 kernel-trace results database (``-o run`` writes
-``run_results.db``): calls, total and mean duration, share of kernel time.  Usage:
-    python -m paper_1604_08057_amd.kernel_summary RUN_results.db [TOP]
+``run_results.db``): calls, total and mean duration, share of kernel time.  Given the
+bench.py JSON line of the same run, it also gives the mean duration of exactly the
+timed launches of the line's roofline kernels (the last launches of their kernel,
+as many as the line counts), the figure to set beside the line's HIP-event mean.
+Usage:
+    python -m paper_1604_08057_amd.kernel_summary RUN_results.db [TOP] [BENCH_JSON]
 """
 from __future__ import annotations
 
@@ -21,5 +25,25 @@ def summarise(db_path: str, top: int = 25) -> str:
     return "\n".join(out)
 
 
+def timed_launches(db_path: str, bench_json: str) -> str:
+    import json
+    line = next(x for x in open(bench_json) if x.strip().startswith("{") and '"metric"' in x)
+    rf = json.loads(line)["roofline"]
+    db = sqlite3.connect(db_path)
+    out = ["# timed launches of the bench line's roofline kernels (last launches of each kernel):",
+           f"# {'kernel':56s} {'launches':>8s} {'trace_mean_us':>14s} {'bench_mean_us':>14s}"]
+    for k in (rf, rf["other_pair"]):
+        name = re.sub(r" \(.*", "", k["kernel"]).replace("NS", "1")
+        n = int(k["launches"])
+        rows = list(db.execute("select end - start from kernels where name like ? order by start",
+                               (f"%tslov::{name}(%",)))
+        sel = [r[0] for r in rows[-n:]]
+        mean = sum(sel) / len(sel) / 1e3 if sel else float("nan")
+        out.append(f"{name[:58]:58s} {len(sel):8d} {mean:14.2f} {k['mean_us']:14.2f}")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     print(summarise(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 25))
+    if len(sys.argv) > 3:
+        print(timed_launches(sys.argv[1], sys.argv[3]))

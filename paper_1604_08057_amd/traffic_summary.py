@@ -5,8 +5,9 @@ traffic summary that bench.py reads.
 Each counter is scaled by what it reads for the probe's three 1 GiB device copies
 (the first three dispatches of each run): FETCH_SIZE and WRITE_SIZE count in KiB,
 and the copy's known bytes fix their scale.  The batched stencil pair kernels of
-the timed call (float32-link variant, the last dispatches of their class in the
-run: as many as the bench line's ``roofline`` reports for its timed steps) are
+the timed call (the class the bench line's ``roofline`` names, e.g. float64
+links and vectors; the last dispatches of that class in the run: as many as the
+line reports for its timed steps) are
 averaged per dispatch, the quantity bench.py sets beside its algorithmic bytes per
 launch.  Usage:
     python -m paper_1604_08057_amd.traffic_summary FETCH.csv WRITE.csv BENCH.json OUT.txt
@@ -54,8 +55,9 @@ def main(fetch_csv: str, write_csv: str, bench_json: str, out: str):
 
     rf = b["roofline"]
     dom_fwd = rf["kernel"].startswith("k_fwd_pair")
+    links = ", float>" if ", float>" in rf["kernel"] else ", double>"
     lines = ["# HBM traffic per dispatch from rocprofv3 counters: batched stencil pair kernels of the",
-             "# 6x18^3 batching workload (32 sources, k in [100, 400], float32 links, float64 vectors)",
+             f"# 6x18^3 batching workload (32 sources, k in [100, 400]; kernel class <double, NS{links})",
              "#",
              "# commands (repository root on the GPU box as $REPO), one counter per pass:",
              "#   cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \\",
@@ -73,7 +75,7 @@ def main(fetch_csv: str, write_csv: str, bench_json: str, out: str):
              "algorithmic(bench)"]
     res = {}
     for tag, prefix, is_fwd in (("fwd", "k_fwd_pair_ms<double, ", True), ("bwd", "k_bwd_rb_ms<double, ", False)):
-        rows = [(x, y) for x, y in sel(prefix) if ", float>" in x["Kernel_Name"]]
+        rows = [(x, y) for x, y in sel(prefix) if links in x["Kernel_Name"]]
         src = rf if is_fwd == dom_fwd else rf["other_pair"]
         n_last, alg = int(src["launches"]), float(src["bytes_per_launch"])
         rows = rows[-n_last:]
