@@ -28,14 +28,23 @@ Functions:
                          lattices: Daleckii-Krein with the matrix A in place of
                          psi eta^H (A = g5 for the full trace, A = (1/N) sum xi (g5 xi)^H
                          for the estimator with the exact sign);
-* ``divergence``      -- divergence and total current of eq. divergence_def.
+* ``divergence``      -- divergence and total current of eq. divergence_def;
+* ``physical_current`` -- the current of eq. lat_vec_cur itself,
+                         j = Tr(D_ov^{-1} dD_ov/dTheta) (complex), exactly (dense D_ov
+                         with the Schur sign, tiny lattices) or as the Z2-noise
+                         estimator (1/N) sum_s xi_s^H D_ov^{-1} dD_ov/dTheta xi_s with the
+                         same exact operators.  With A fixed, Tr(A g5 d sgn(H)) is the
+                         derivative of tr(A g5 sgn(H)) at fixed A, so both forms are
+                         ``exact_current`` with A = D_ov^{-1} g5 (resp. the noise
+                         average of xi xi^H D_ov^{-1} g5) for the real part and -i A for
+                         the imaginary part.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from .grad import grad_autograd, link_gradient_from_matrix, u1_projection
-from .sign import daleckii_krein
+from .sign import daleckii_krein, sign_schur
 from .wilson import WilsonOperator, dense_h, gamma5
 
 
@@ -77,3 +86,23 @@ def divergence(j: np.ndarray, op: WilsonOperator):
     div = sum(j[nu] - j[nu][bwd[nu]] for nu in range(4))
     tot = sum(j[nu] + j[nu][bwd[nu]] for nu in range(4))
     return div, tot
+
+
+def overlap_dense(U: np.ndarray, dims, mass: float, mu: float) -> np.ndarray:
+    """D_ov = 1 + g5 sgn(H) (eq. overlap, a = 1) with the Schur sign (tiny lattices)."""
+    H = dense_h(U, dims, mass, mu)
+    g5 = np.tile(np.repeat(np.diag(gamma5()).real, 3), H.shape[0] // 12)
+    return np.eye(H.shape[0], dtype=np.complex128) + g5[:, None] * sign_schur(H)
+
+
+def physical_current(U: np.ndarray, dims, mass: float, mu: float, xis: np.ndarray | None = None) -> np.ndarray:
+    """j(x, nu) = Tr(D_ov^{-1} dD_ov/dTheta_{x,nu}) as complex (4, V); with noise vectors
+    xis (N, V, 4, 3) the estimator (1/N) sum_s xi_s^H D_ov^{-1} dD_ov/dTheta xi_s."""
+    n = 12 * int(np.prod(dims))
+    Dinv = np.linalg.inv(overlap_dense(U, dims, mass, mu))
+    g5 = np.tile(np.repeat(np.diag(gamma5()).real, 3), n // 12)
+    W = Dinv * g5[None, :]                           # D_ov^{-1} g5
+    if xis is not None:
+        X = xis.reshape(len(xis), n).T               # columns xi_s
+        W = (X @ (X.conj().T @ W)) / len(xis)        # (1/N) sum xi xi^H D^{-1} g5
+    return exact_current(U, dims, mass, mu, W) + 1j * exact_current(U, dims, mass, mu, -1j * W)

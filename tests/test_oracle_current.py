@@ -8,7 +8,12 @@
   equals the exact-sign estimator for the same noise;
 * the divergence of the TSL estimator equals the mean of the per-sample Ward
   source terms (catches a sign or neighbour error in the projection or the
-  divergence), and a planted sign error in one link direction breaks it.
+  divergence), and a planted sign error in one link direction breaks it;
+* the physical current Tr(D_ov^{-1} dD_ov/dTheta) (eq. lat_vec_cur) equals
+  Richardson-extrapolated central differences of log det D_ov (Jacobi's formula),
+  its divergence vanishes at every site while the total current does not, and one
+  noise sample's divergence equals i [chi(x)^H (D_ov xi)(x) - |xi(x)|^2] with
+  chi = D_ov^{-H} xi.
 """
 import numpy as np
 import pytest
@@ -69,3 +74,56 @@ def test_divergence_equals_mean_ward_source_terms(setup):
     jb[2] = -jb[2]   # planted error: wrong sign of one direction's projection
     divb, _ = CU.divergence(jb, op)
     assert np.abs(divb - rhs).max() > 1e-3 * np.abs(j).max()
+
+
+# ------------------------------------------------------------------- the physical current (eq. lat_vec_cur)
+
+@pytest.fixture(scope="module")
+def gapped():
+    dims, m, mu = (2, 2, 2, 4), -1.0, 0.3
+    U = random_links(dims, 0.3, np.random.default_rng(2))
+    return dims, m, mu, U, WilsonOperator(dims, m, mu)
+
+
+def test_physical_current_is_the_derivative_of_log_det(gapped):
+    """j(x, nu) = d/dTheta log det D_ov (Jacobi's formula), central differences of the
+    dense determinant with the Schur sign."""
+    dims, m, mu, U, op = gapped
+    j = CU.physical_current(U, dims, m, mu)
+
+    def logdet(Uh):
+        s, l = np.linalg.slogdet(CU.overlap_dense(Uh, dims, m, mu))
+        return np.log(s) + l
+    def central(nu, site, h):
+        Up, Um = U.copy(), U.copy()
+        Up[nu, site] *= np.exp(1j * h)
+        Um[nu, site] *= np.exp(-1j * h)
+        return (logdet(Up) - logdet(Um)) / (2 * h)
+    for nu, site in ((0, 3), (3, 29), (2, 17)):
+        fd = (4 * central(nu, site, 1e-3) - central(nu, site, 2e-3)) / 3   # Richardson
+        assert abs(fd - j[nu, site]) < 1e-8 * abs(j[nu, site])
+
+
+def test_physical_current_divergence_vanishes(gapped):
+    """Gauge invariance of det D_ov: zero divergence at every site, nonzero total current."""
+    dims, m, mu, U, op = gapped
+    j = CU.physical_current(U, dims, m, mu)
+    dr, tr = CU.divergence(j.real, op)
+    di, ti = CU.divergence(j.imag, op)
+    assert np.abs(dr).max() < 1e-12 and np.abs(di).max() < 1e-12
+    assert np.abs(tr).max() > 0.1 and np.abs(ti).max() > 0.1
+
+
+def test_physical_current_sample_ward_identity(gapped):
+    """One noise sample xi, chi = D_ov^{-H} xi: the divergence of chi^H dD_ov/dTheta xi at x
+    is i [chi(x)^H (D_ov xi)(x) - |xi(x)|^2] (local U(1) rotation of chi^H D_ov xi)."""
+    dims, m, mu, U, op = gapped
+    xi = z2_complex_source(op.volume, np.random.default_rng(4))
+    js = CU.physical_current(U, dims, m, mu, xi[None])
+    D = CU.overlap_dense(U, dims, m, mu)
+    chi = np.linalg.solve(D.conj().T, xi.ravel()).reshape(xi.shape)
+    Dxi = (D @ xi.ravel()).reshape(xi.shape)
+    want = 1j * (np.einsum("vsa,vsa->v", chi.conj(), Dxi) - np.einsum("vsa,vsa->v", xi.conj(), xi))
+    dr, _ = CU.divergence(js.real, op)
+    di, _ = CU.divergence(js.imag, op)
+    assert np.abs(dr + 1j * di - want).max() < 1e-11 * np.abs(want).max()
