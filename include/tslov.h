@@ -253,6 +253,34 @@ tslov_status tslov_sign_grad_batched(tslov_ctx* ctx, int nsrc, const void* eta, 
 tslov_status tslov_current_estimate(tslov_ctx* ctx, int nsrc, const void* xi, const int* k, double* j_out,
                                     double* div_out, double* tot_out, double* ward_out, tslov_info* infos);
 
+/* Solve with the overlap operator (Sec. 1 eq. overlap, a = 1): x = D_ov^{-1} b
+ * (adjoint = 0) or x = D_ov^{-dag} b (adjoint = 1), with D_ov = 1 + g5 sgn(H) and sgn(H)
+ * the context's two-sided Lanczos approximation of size k (no deflation), and
+ * D_ov^dag = g5 D_ov(-mu) g5 (sgn(H)^dag = sgn(H(-mu))).  Conjugate gradients on the
+ * normal equations, each iteration two approximate applications, stopped at
+ * |b - A x| <= tol |b|.  The approximation is linear in its source only as far as it
+ * has converged (eps_A), so tol below eps_A is not reachable.  b, x: canonical
+ * spinors (device, distinct).  iters_out, relres_out (host, nullable): iterations and
+ * the final relative residual.  ERR_NOT_CONVERGED when maxit iterations do not reach
+ * tol (x holds the last iterate). */
+tslov_status tslov_overlap_solve(tslov_ctx* ctx, const void* b, void* x, int k, int adjoint, double tol, int maxit,
+                                 int* iters_out, double* relres_out);
+
+/* The physical U(1) vector current of Sec. 4.3 eq. lat_vec_cur,
+ *   j(x, nu) = Tr(D_ov^{-1} dD_ov/dTheta_{x,nu}),   U_nu(x) -> e^{i Theta} U_nu(x),
+ * by the Z2-noise estimator over the nsrc sources xi ([nsrc][V][4][3], device):
+ *   j_N = (1/N) sum_s chi_s^dag dD_ov/dTheta xi_s,   chi_s = D_ov^{-dag} xi_s
+ * (tslov_overlap_solve with tol, maxit per source; the derivative through the TSL
+ * approximation of size k, as tslov_sign_grad).  j_out (device): 8V doubles, the real
+ * parts [4][V] then the imaginary parts [4][V] (direction x, y, z, t, site);
+ * div_out, tot_out (device, nullable): 2V doubles each (real [V], imaginary [V]),
+ * the divergence and total current of eq. divergence_def at every site.
+ * iters_out, relres_out (host, nullable, nsrc): the solves' iterations and residuals.
+ * Meaningful where the TSL approximation has converged (eps_A well below tol). */
+tslov_status tslov_physical_current(tslov_ctx* ctx, int nsrc, const void* xi, int k, double tol, int maxit,
+                                    double* j_out, double* div_out, double* tot_out, int* iters_out,
+                                    double* relres_out);
+
 /* A-posteriori error estimate (Sec. 4.1, eq. error_est): with y = TSL(psi) and
  * z = TSL(y) (a fresh Krylov space with source y, same k and deflation),
  * eps_A = |z - psi| / (2 |psi|).  eps_out: host double. */

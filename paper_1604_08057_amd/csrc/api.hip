@@ -186,6 +186,8 @@ struct tslov_ctx {
     Buf wardp;       // Ward block maxima
     Buf canon;       // canonical spinors: projected source, partial result, error estimate
     Buf trial;       // the tuning run's trial vector (1, ..., 1)
+    Buf solvebuf;    // overlap solve: r, z, p, w and a g5 copy (canonical)
+    Buf physbuf;     // physical current: chi_s and the probes g5 chi_s, i g5 chi_s
     Buf deflw;       // deflation coefficients, signs and partial sums
     Buf deflx;       // deflated derivative: R^H eta, R^H psibar, q, -q and dot partials
     Buf cgf, cgp, cgs;   // shifted solves: fields, partial sums, per-system scalars
@@ -353,7 +355,7 @@ struct LoopKey {
     LoopKey& buffers(const tslov_ctx* c, const Work<R>& wk, const Z<RL>* U, int cls) {
         add(wk.V).add(wk.W).add(wk.A).add(wk.B).add(wk.AB).add(wk.SB).add(wk.F).add(wk.part);
         add(wk.fe).add(wk.kcap).add(wk.ring).add(wk.pstride);
-        add(c->coefmem.p).add(c->slots).add(c->kcap).add(U);
+        add(c->coefmem.p).add(c->slots).add(c->kcap).add(U).add(c->mu);
         return add(c->pair_ns[cls]).add(c->pair_ns_forced);
     }
 };
@@ -1635,6 +1637,87 @@ tslov_status apply_fields(tslov_ctx* c, const void* in, void* out, double mu, in
 
 namespace {
 
+// |v|^2 over n complex values (fixed-order block partials, host sum in block order).
+tslov_status norm2_dev(tslov_ctx* c, const ZD* v, size_t n, double* out) {
+    CHK(ensure_host_part(c, 8192));
+    double* part = c->part.as<double>() + 2 * c->pstride();
+    const int nb = tslov::launch_diff_norm(v, v, n, part, c->st);
+    HIPCHK(hipMemcpyAsync(c->host_part, part, (size_t)2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += c->host_part[2 * i + 1];
+    *out = s;
+    return TSLOV_OK;
+}
+
+// out = D_ov in (adjoint = 0) or D_ov^dag in (adjoint = 1) with the context's TSL sign of
+// size k: D_ov = 1 + g5 sgn(H) (eq. overlap), and since sgn(H)^dag = sgn(H^dag) with
+// H^dag = H(-mu), D_ov^dag = g5 D_ov(-mu) g5, the same process at -mu between two g5.
+// tmp: a canonical scratch field.
+tslov_status overlap_apply(tslov_ctx* c, const ZD* in, ZD* out, ZD* tmp, int k, int adjoint) {
+    if (!adjoint) return sign_dispatch(c, in, out, k, nullptr, nullptr, 1, 0);
+    const int V = c->g.V;
+    tslov::launch_combine(nullptr, in, 1, V, tmp, c->st);
+    const double mu = c->mu;
+    c->mu = -mu;
+    const tslov_status s = sign_dispatch(c, tmp, out, k, nullptr, nullptr, 1, 0);
+    c->mu = mu;
+    CHK(s);
+    tslov::launch_combine(nullptr, out, 1, V, out, c->st);
+    return TSLOV_OK;
+}
+
+// x with A x = b, A = D_ov (adjoint 0) or D_ov^dag (adjoint 1), by conjugate gradients on
+// the normal equations A^dag A x = A^dag b, stopped at |b - A x| <= tol |b| (the TSL
+// sign makes A an approximation, linear to its own accuracy).  Uses c->solvebuf.
+tslov_status overlap_cgnr(tslov_ctx* c, const ZD* b, ZD* x, int k, int adjoint, double tol, int maxit, int* iters,
+                          double* relres) {
+    const size_t n = (size_t)12 * c->g.V;
+    CHK(ensure(c->solvebuf, 5 * n * sizeof(ZD)));
+    CHK(ensure_work(c, 1, k, 0));      // the sign's workspace, whose partial-sum array norm2_dev uses
+    ZD* r = c->solvebuf.as<ZD>();
+    ZD* z = r + n;
+    ZD* p = z + n;
+    ZD* w = p + n;
+    ZD* tmp = w + n;
+    double bb = 0.0, zz = 0.0, ww = 0.0, rr = 0.0;
+    CHK(norm2_dev(c, b, n, &bb));
+    tslov::launch_zero((double*)x, 2 * n, c->st);
+    *iters = 0;
+    *relres = 0.0;
+    if (bb == 0.0) return TSLOV_OK;
+    HIPCHK(hipMemcpyAsync(r, b, n * sizeof(ZD), hipMemcpyDeviceToDevice, c->st));
+    CHK(overlap_apply(c, r, z, tmp, k, !adjoint));                  // z = A^dag r
+    HIPCHK(hipMemcpyAsync(p, z, n * sizeof(ZD), hipMemcpyDeviceToDevice, c->st));
+    CHK(norm2_dev(c, z, n, &zz));
+    rr = bb;
+    int it = 0;
+    while (it < maxit && rr > tol * tol * bb && zz > 0.0) {
+        CHK(overlap_apply(c, p, w, tmp, k, adjoint));               // w = A p
+        CHK(norm2_dev(c, w, n, &ww));
+        if (!(ww > 0.0)) break;
+        const double alpha = zz / ww;
+        tslov::launch_caxpy(p, alpha, x, n, c->st);
+        tslov::launch_caxpy(w, -alpha, r, n, c->st);
+        CHK(norm2_dev(c, r, n, &rr));
+        ++it;
+        if (rr <= tol * tol * bb) break;
+        CHK(overlap_apply(c, r, z, tmp, k, !adjoint));              // z = A^dag r
+        double zn = 0.0;
+        CHK(norm2_dev(c, z, n, &zn));
+        tslov::launch_cxpby(z, zn / zz, p, n, c->st);                // p = z + beta p
+        zz = zn;
+    }
+    *iters = it;
+    *relres = std::sqrt(rr / bb);
+    if (*relres > tol) return fail(TSLOV_ERR_NOT_CONVERGED, "overlap solve did not reach its tolerance");
+    return TSLOV_OK;
+}
+
+}  // namespace
+
+namespace {
+
 // eps_B of eq. bA_error_est for the tangent t and source (0, psi); ms_first (nullable)
 // receives the wall time of the first block process.  Uses canonical buffers 3..7.
 tslov_status block_eps(tslov_ctx* c, const tslov::BlockTangent& t, const ZD* psi, int k, double* eps_out,
@@ -1770,7 +1853,7 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
 void tslov_destroy(tslov_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
-    for (Buf* b : {&c->trial, &c->U64, &c->U32, &c->badflag, &c->nestbuf, &c->blk, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
+    for (Buf* b : {&c->trial, &c->solvebuf, &c->physbuf, &c->U64, &c->U32, &c->badflag, &c->nestbuf, &c->blk, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
                    &c->fields, &c->part, &c->coefmem, &c->dense, &c->denseInt, &c->densePart, &c->denseDelta,
                    &c->gpart, &c->gsrc, &c->bout, &c->wardp, &c->canon, &c->deflw, &c->deflx, &c->cgf, &c->cgp,
                    &c->cgs, &c->ckpt})
@@ -1969,6 +2052,61 @@ tslov_status tslov_current_estimate(tslov_ctx* c, int nsrc, const void* xi, cons
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
     if (ward_out) *ward_out = q.g_max > 0.0 ? q.ward_max / q.g_max : q.ward_max;
+    return TSLOV_OK;
+}
+
+tslov_status tslov_overlap_solve(tslov_ctx* c, const void* b, void* x, int k, int adjoint, double tol, int maxit,
+                                int* iters_out, double* relres_out) {
+    CHK(check_common(c, k, nullptr));
+    if (!b || !x) return fail(TSLOV_ERR_ARG, "null argument");
+    if (b == x) return fail(TSLOV_ERR_ARG, "b and x must not overlap");
+    if (!(tol > 0.0) || maxit < 1) return fail(TSLOV_ERR_ARG, "tol must be > 0 and maxit >= 1");
+    int it = 0;
+    double rel = 0.0;
+    const tslov_status s = overlap_cgnr(c, (const ZD*)b, (ZD*)x, k, adjoint ? 1 : 0, tol, maxit, &it, &rel);
+    if (iters_out) *iters_out = it;
+    if (relres_out) *relres_out = rel;
+    return s;
+}
+
+tslov_status tslov_physical_current(tslov_ctx* c, int nsrc, const void* xi, int k, double tol, int maxit, double* j_out,
+                                    double* div_out, double* tot_out, int* iters_out, double* relres_out) {
+    CHK(check_common(c, k, nullptr));
+    if (nsrc < 1 || nsrc > kMaxSources) return fail(TSLOV_ERR_ARG, "nsrc must be in [1, 2^20]");
+    if (!xi || !j_out) return fail(TSLOV_ERR_ARG, "null argument");
+    if (!(tol > 0.0) || maxit < 1) return fail(TSLOV_ERR_ARG, "tol must be > 0 and maxit >= 1");
+    const int V = c->g.V;
+    const size_t n = (size_t)12 * V;
+    CHK(ensure(c->physbuf, 2 * (size_t)nsrc * n * sizeof(ZD)));
+    ZD* chi = c->physbuf.as<ZD>();
+    ZD* probe = chi + (size_t)nsrc * n;
+    // chi_s = D_ov^{-dag} xi_s, so that xi_s^dag D_ov^{-1} = chi_s^dag
+    for (int s = 0; s < nsrc; ++s) {
+        int it = 0;
+        double rel = 0.0;
+        CHK(overlap_cgnr(c, (const ZD*)xi + (size_t)s * n, chi + (size_t)s * n, k, 1, tol, maxit, &it, &rel));
+        if (iters_out) iters_out[s] = it;
+        if (relres_out) relres_out[s] = rel;
+    }
+    // d/dTheta Re <eta|sgn(H)|xi> with eta = g5 chi gives Re chi^dag dD_ov/dTheta xi, and
+    // with eta = i g5 chi its imaginary part; each summed over the sources by the batch
+    std::vector<int> ks(nsrc, k);
+    for (int part = 0; part < 2; ++part) {
+        const ZD f = part ? ZD{0.0, 1.0} : ZD{1.0, 0.0};
+        for (int s = 0; s < nsrc; ++s)
+            tslov::launch_g5_scale(chi + (size_t)s * n, f, V, probe + (size_t)s * n, c->st);
+        BatchRequest q;
+        q.nsrc = nsrc;
+        q.eta = probe;
+        q.psi = (const ZD*)xi;
+        q.k = ks.data();
+        q.jsum = j_out + (size_t)part * 4 * V;
+        CHK(run_batched(c, q));
+        tslov::launch_current_finish(c->g, q.jsum, 1.0 / nsrc, div_out ? div_out + (size_t)part * V : nullptr,
+                                     tot_out ? tot_out + (size_t)part * V : nullptr, c->st);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
     return TSLOV_OK;
 }
 

@@ -7,6 +7,8 @@
 //   out   = TSL(psi_p) + sum_i s_i c_i R_i,   s_i = sgn(Re lambda_i)
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace tslov {
 
 // Per-block partial sums of L_i^H psi for i < l: part[b][2 i + {0, 1}].
@@ -124,6 +126,43 @@ __global__ __launch_bounds__(kBlock) void k_combine(const ZD* a, const ZD* b, in
 
 void launch_combine(const ZD* a, const ZD* b, int g5, int V, ZD* out, hipStream_t st) {
     hipLaunchKernelGGL(k_combine, dim3(grid_for(V)), dim3(kBlock), 0, st, a, b, g5, V, out);
+}
+
+// Pointwise vector operations of the overlap solve on canonical arrays of n complex values:
+// y += a x (a real); y = x + b y (b real); out = f g5 in (f complex, per site and spin).
+__global__ __launch_bounds__(kBlock) void k_caxpy(const ZD* __restrict__ x, double a, ZD* __restrict__ y, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        y[i] = y[i] + a * x[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cxpby(const ZD* __restrict__ x, double b, ZD* __restrict__ y, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        y[i] = x[i] + b * y[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_g5_scale(const ZD* __restrict__ in, ZD f, int V, ZD* __restrict__ out) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= V) return;
+#pragma unroll
+    for (int p = 0; p < 12; ++p) {
+        const size_t i = (size_t)s * 12 + p;
+        const ZD o = f * in[i];
+        out[i] = p >= 6 ? -1.0 * o : o;
+    }
+}
+
+void launch_caxpy(const ZD* x, double a, ZD* y, size_t n, hipStream_t st) {
+    const int nb = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(k_caxpy, dim3(nb), dim3(kBlock), 0, st, x, a, y, n);
+}
+
+void launch_cxpby(const ZD* x, double b, ZD* y, size_t n, hipStream_t st) {
+    const int nb = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(k_cxpby, dim3(nb), dim3(kBlock), 0, st, x, b, y, n);
+}
+
+void launch_g5_scale(const ZD* in, ZD f, int V, ZD* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_g5_scale, dim3(grid_for(V)), dim3(kBlock), 0, st, in, f, V, out);
 }
 
 // Partials of |a - b|^2 and |b|^2 over n complex values (error estimate).

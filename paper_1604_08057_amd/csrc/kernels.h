@@ -167,6 +167,10 @@ void launch_defl_finish(const ZD* R, const ZD* c, const double* sgn, const ZD* y
                         int overlap, ZD* out, hipStream_t st);
 int launch_diff_norm(const ZD* a, const ZD* b, size_t n, double* part, hipStream_t st);
 // out = [a +] g5^{g5} b on canonical spinors of V sites (a nullable; out may alias a or b).
+// overlap solve: y += a x, y = x + b y (n complex values, a and b real), out = f g5 in
+void launch_caxpy(const ZD* x, double a, ZD* y, size_t n, hipStream_t st);
+void launch_cxpby(const ZD* x, double b, ZD* y, size_t n, hipStream_t st);
+void launch_g5_scale(const ZD* in, ZD f, int V, ZD* out, hipStream_t st);
 void launch_combine(const ZD* a, const ZD* b, int g5, int V, ZD* out, hipStream_t st);
 
 // ---------------------------------------------------------------- deflated derivative

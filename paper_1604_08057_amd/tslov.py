@@ -38,7 +38,7 @@ EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links
            "tslov_timing_read", "tslov_kernel_bytes", "tslov_set_pair_ns", "tslov_get_pair_ns", "tslov_set_graphs", "tslov_set_apply_chunk",
            "tslov_get_apply_chunk", "tslov_overlap_grad", "tslov_tridiag_sign", "tslov_ritz_values",
            "tslov_set_diagnostics", "tslov_apply_h_noalloc", "tslov_set_nested", "tslov_block_sign",
-           "tslov_block_error_estimate", "tslov_tune_k"]
+           "tslov_block_error_estimate", "tslov_tune_k", "tslov_overlap_solve", "tslov_physical_current"]
 
 
 class TslovLibraryMissing(ImportError):
@@ -129,6 +129,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_set_nested": ([vp, ci], ci),
         "tslov_block_sign": ([vp, ci, ci, ctypes.POINTER(cd), vp, vp, ci, vp, vp, ctypes.POINTER(InfoStruct)], ci),
         "tslov_block_error_estimate": ([vp, ci, ci, ctypes.POINTER(cd), vp, ci, ctypes.POINTER(cd)], ci),
+        "tslov_overlap_solve": ([vp, vp, vp, ci, ci, cd, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
+        "tslov_physical_current": ([vp, ci, vp, ci, cd, ci, vp, vp, vp, ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
         "tslov_tune_k": ([vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci), cd, ctypes.POINTER(DeflationStruct),
                           ctypes.POINTER(LinkDirection), ci, vp, ctypes.POINTER(cd), ctypes.POINTER(cd),
                           ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
@@ -414,6 +416,29 @@ class Context:
                                                ctypes.byref(chosen), cross))
         return {"eps": list(eps), "ms": list(ms), "chosen": chosen.value,
                 "cross": list(cross) if (cross is not None and chosen.value >= 0) else []}
+
+    def overlap_solve(self, b: torch.Tensor, k: int, adjoint: bool = False, tol: float = 1e-10, maxit: int = 500):
+        """x = D_ov^{-1} b (or D_ov^{-dag} b) with the size-k sign; returns (x, iterations, relative residual)."""
+        b = self._spinor(b, "b")
+        x = self._new_spinor()
+        it, rel = ctypes.c_int(), ctypes.c_double()
+        _check(self.lib, self.lib.tslov_overlap_solve(self.handle, _ptr(b), _ptr(x), int(k), int(bool(adjoint)),
+                                                      float(tol), int(maxit), ctypes.byref(it), ctypes.byref(rel)))
+        return x, it.value, rel.value
+
+    def physical_current(self, xi: torch.Tensor, k: int, tol: float = 1e-10, maxit: int = 500):
+        """The Z2-noise estimate of Tr(D_ov^{-1} dD_ov/dTheta) over the sources xi (nsrc, V, 4, 3):
+        dict with j (complex (4, V)), div and tot (complex (V,)), iters and relres per source."""
+        xi = self._sources(xi, "xi")
+        n, V = xi.shape[0], self.volume
+        j = torch.empty((2, 4, V), dtype=torch.float64, device=self.device)
+        div = torch.empty((2, V), dtype=torch.float64, device=self.device)
+        tot = torch.empty((2, V), dtype=torch.float64, device=self.device)
+        it, rel = (ctypes.c_int * n)(), (ctypes.c_double * n)()
+        _check(self.lib, self.lib.tslov_physical_current(self.handle, n, _ptr(xi), int(k), float(tol), int(maxit),
+                                                         _ptr(j), _ptr(div), _ptr(tot), it, rel))
+        return {"j": torch.complex(j[0], j[1]), "div": torch.complex(div[0], div[1]),
+                "tot": torch.complex(tot[0], tot[1]), "iters": list(it), "relres": list(rel)}
 
     def set_nested(self, k_inner: int = 0):
         """Nested projected-matrix step of the sign calls with inner Krylov size k_inner (0: plain)."""

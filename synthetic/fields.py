@@ -171,6 +171,10 @@ CONFIGS = {
     # eigenvalue and |Re lambda| >= 0.025.
     5: Workload(5, "16^4 deflated", (16, 16, 16, 16), 0.35, -2.0, 0.3, 400, n_deflate=20,
                 extra={"field": "rotated-constant", "draw": 10}),
+    # 3x4^3 (the size of the paper's check of the current's divergence, mu = 0.3) with
+    # smooth links and a mass inside the overlap window: min |Re lambda(H)| = 0.29, so the
+    # TSL approximation converges (eps_A 1.4e-13 at k = 240) and D_ov can be inverted
+    6: Workload(6, "3x4^3 physical current", (4, 4, 4, 3), 0.1, -1.0, 0.3, 240, sources=4),
 }
 
 

@@ -61,6 +61,8 @@ def test_host_side_argument_errors(lib):
     assert lib.tslov_set_diagnostics(None, 1) == ERR_ARG
     assert lib.tslov_tridiag_sign(None, 4, None, None, None, None, None) == ERR_ARG
     assert lib.tslov_tune_k(None, 1, None, None, 0.0, None, None, 0, None, None, None, None, None) == ERR_ARG
+    assert lib.tslov_overlap_solve(None, None, None, 8, 0, 1e-10, 10, None, None) == ERR_ARG
+    assert lib.tslov_physical_current(None, 1, None, 8, 1e-10, 10, None, None, None, None, None) == ERR_ARG
     assert lib.tslov_kernel_bytes(None, 0) == 0.0
 
 
