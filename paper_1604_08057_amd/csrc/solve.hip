@@ -30,65 +30,122 @@ __device__ __forceinline__ int block_flag_cg(const int* p) {
     return r;
 }
 
-// (1 + S g) hop of one colour for a single field at chemical-potential factors (ep, em)
-template <int NU>
-__device__ __forceinline__ void cg_hop(ZD (&acc)[4], const ZD* __restrict__ U, const ZD* __restrict__ f, const Geom& g,
-                                       int s, int a, const Nbr& n, double ep, double em) {
-    const double up = (NU == 3) ? ep : 1.0, dn = (NU == 3) ? em : 1.0;
+// (1 + S g) hops of one colour for NS systems e0 .. e0 + NS - 1: each link row is loaded
+// once and applied to every live system's field, with the system's own
+// chemical-potential factors (ep, em) on the temporal hops.
+template <int NU, int NS>
+__device__ __forceinline__ void cg_hop(ZD (&acc)[NS][4], const ZD* __restrict__ U, const CgWork& cw, int e0,
+                                       int field, const int (&live)[NS], const Geom& g, int s, int a, const Nbr& n,
+                                       const double (&ep)[NS], const double (&em)[NS]) {
     ZD u[3];
     Spinor<double> p;
     load_row(u, U, g.ldv, NU, a, s);
-    load_spinor(p, f, g.ldv, n.fwd[NU]);
-    hop1<NU, +1>(acc, u, p, up);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        if (!live[i]) continue;
+        load_spinor(p, cw.field(e0 + i, field), g.ldv, n.fwd[NU]);
+        hop1<NU, +1>(acc[i], u, p, (NU == 3) ? ep[i] : 1.0);
+    }
     load_col_conj(u, U, g.ldv, NU, a, n.bwd[NU]);
-    load_spinor(p, f, g.ldv, n.bwd[NU]);
-    hop1<NU, -1>(acc, u, p, dn);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        if (!live[i]) continue;
+        load_spinor(p, cw.field(e0 + i, field), g.ldv, n.bwd[NU]);
+        hop1<NU, -1>(acc[i], u, p, (NU == 3) ? em[i] : 1.0);
+    }
 }
 
 }  // namespace
 
-// out_e = A_e in_e with A_e = sigma_e - H(m_e mu) (adj = 0) or its adjoint
-// conj(sigma_e) - H(-m_e mu) (adj = 1); H = g5 (1 - kappa hop).  Partials of |out|^2.
+// out_e = A_e in_e for the NS systems e = e0 .. e0 + NS - 1 of this block (e0 = NS y),
+// with A_e = sigma_e - H(m_e mu) (adj = 0) or its adjoint conj(sigma_e) - H(-m_e mu)
+// (adj = 1); H = g5 (1 - kappa hop).  Partials of |out_e|^2.  The systems share each
+// link load (the links are the same for all of them); frozen systems keep their fields
+// and partials.  Each system's arithmetic is that of a block of its own.
+template <int NS>
 __global__ __launch_bounds__(kCBlock) void k_cg_apply(const ZD* __restrict__ U, Geom g, double kappa, double emu,
                                                       CgWork cw, int adj, int in_field, int out_field, int preg) {
-    const int e = blockIdx.y;
-    CgRhs* st = cw.st + e;
-    if (block_flag_cg(&st->done)) return;
-    const ZD sig = adj ? cj(st->sigma) : st->sigma;
-    const double m = adj ? -st->msign : st->msign;
-    const double ep = m > 0 ? emu : 1.0 / emu, em = 1.0 / ep;
-    const ZD* __restrict__ in = cw.field(e, in_field);
-    ZD* __restrict__ out = cw.field(e, out_field);
+    const int e0 = blockIdx.y * NS;
+    __shared__ int live_s[NS];
+    if (threadIdx.x < NS) live_s[threadIdx.x] = !*(volatile const int*)&cw.st[e0 + threadIdx.x].done;
+    __syncthreads();
+    int live[NS], any = 0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        live[i] = live_s[i];
+        any |= live[i];
+    }
+    if (!any) return;
+    ZD sig[NS];
+    double ep[NS], em[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const CgRhs* st = cw.st + e0 + i;
+        sig[i] = adj ? cj(st->sigma) : st->sigma;
+        const double m = adj ? -st->msign : st->msign;
+        ep[i] = m > 0 ? emu : 1.0 / emu;
+        em[i] = 1.0 / ep[i];
+    }
     const int a = wave_colour();
     const int s = blockIdx.x * kSites + threadIdx.x % kSites;
-    double pv[1] = {0.0};
+    double pv[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) pv[i] = 0.0;
     if (s < g.V) {
         const Nbr n = neighbours(g, s);
-        ZD acc[4];
+        ZD acc[NS][4];
 #pragma unroll
-        for (int sp = 0; sp < 4; ++sp) acc[sp] = mk<double>(0, 0);
+        for (int i = 0; i < NS; ++i)
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) acc[i][sp] = mk<double>(0, 0);
 #pragma unroll 1
         for (int nu = 0; nu < 4; ++nu) {
             switch (nu) {
-                case 0: cg_hop<0>(acc, U, in, g, s, a, n, ep, em); break;
-                case 1: cg_hop<1>(acc, U, in, g, s, a, n, ep, em); break;
-                case 2: cg_hop<2>(acc, U, in, g, s, a, n, ep, em); break;
-                default: cg_hop<3>(acc, U, in, g, s, a, n, ep, em); break;
+                case 0: cg_hop<0, NS>(acc, U, cw, e0, in_field, live, g, s, a, n, ep, em); break;
+                case 1: cg_hop<1, NS>(acc, U, cw, e0, in_field, live, g, s, a, n, ep, em); break;
+                case 2: cg_hop<2, NS>(acc, U, cw, e0, in_field, live, g, s, a, n, ep, em); break;
+                default: cg_hop<3, NS>(acc, U, cw, e0, in_field, live, g, s, a, n, ep, em); break;
             }
         }
-        const FieldBase fi = field_base(in), fo = field_base(out);
 #pragma unroll
-        for (int sp = 0; sp < 4; ++sp) {
-            const int pl = sp * 3 + a;
-            const ZD x = fload<double>(fi, g.ldv, pl, (unsigned)s);
-            const double g5 = sp < 2 ? 1.0 : -1.0;
-            const ZD o = sig * x - g5 * (x - kappa * acc[sp]);
-            fstore<double>(fo, g.ldv, pl, (unsigned)s, o);
-            pv[0] += norm2(o);
+        for (int i = 0; i < NS; ++i) {
+            if (!live[i]) continue;
+            const FieldBase fi = field_base(cw.field(e0 + i, in_field)), fo = field_base(cw.field(e0 + i, out_field));
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+                const int pl = sp * 3 + a;
+                const ZD x = fload<double>(fi, g.ldv, pl, (unsigned)s);
+                const double g5 = sp < 2 ? 1.0 : -1.0;
+                const ZD o = sig[i] * x - g5 * (x - kappa * acc[i][sp]);
+                fstore<double>(fo, g.ldv, pl, (unsigned)s, o);
+                pv[i] += norm2(o);
+            }
         }
     }
-    write_partials<1, kCBlock>(cw.p(e, preg), pv);
+    block_sum<NS, kCBlock>(pv);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+            if (live[i]) cw.p(e0 + i, preg)[blockIdx.x] = pv[i];
 }
+
+namespace {
+
+// the operator launch over the nr systems, two per block when nr is even (measured at
+// 16^4 with 40 systems: 1, 2 and 4 per block took 8.00, 7.97 and 8.92 s per derivative:
+// the kernel waits on latency, not on link bytes, and more systems per block lengthen
+// each block's chain)
+void cg_apply(const ZD* U, const Geom& g, double kappa, double emu, int nr, const CgWork& cw, int adj, int in_field,
+              int out_field, int preg, hipStream_t st) {
+    if (nr % 2 == 0)
+        hipLaunchKernelGGL(k_cg_apply<2>, dim3(np_stencil(g.V), nr / 2), dim3(kCBlock), 0, st, U, g, kappa, emu, cw,
+                           adj, in_field, out_field, preg);
+    else
+        hipLaunchKernelGGL(k_cg_apply<1>, dim3(np_stencil(g.V), nr), dim3(kCBlock), 0, st, U, g, kappa, emu, cw, adj,
+                           in_field, out_field, preg);
+}
+
+}  // namespace
 
 // Right-hand sides: e < l: b = psi - c_e R_e;  e >= l (i = e - l):
 // b = s_i eta - pbar - q_i L_i with q_i = R_i^H (s_i eta - pbar).  r = b, x = 0,
@@ -309,8 +366,7 @@ void launch_cg_rhs(const Geom& g, const ZD* psi, const ZD* eta, const ZD* pbar, 
 
 void launch_cg_start(const ZD* U, const Geom& g, double kappa, double mu, int nr, const CgWork& cw, hipStream_t st) {
     const double emu = std::exp(mu);
-    hipLaunchKernelGGL(k_cg_apply, dim3(np_stencil(g.V), nr), dim3(kCBlock), 0, st, U, g, kappa, emu, cw, 1, kCgR,
-                       kCgZ, 2);
+    cg_apply(U, g, kappa, emu, nr, cw, 1, kCgR, kCgZ, 2, st);
     dim3 gp((g.V + kPBlock - 1) / kPBlock, 12, nr);
     hipLaunchKernelGGL(k_cg_init_p, gp, dim3(kPBlock), 0, st, g, cw, np_stencil(g.V));
 }
@@ -319,12 +375,11 @@ void launch_cg_iteration(const ZD* U, const Geom& g, double kappa, double mu, in
                          const CgWork& cw, hipStream_t st) {
     const double emu = std::exp(mu);
     const int par = it & 1;
-    const dim3 gs(np_stencil(g.V), nr);
     const dim3 gp((g.V + kPBlock - 1) / kPBlock, 12, nr);
-    hipLaunchKernelGGL(k_cg_apply, gs, dim3(kCBlock), 0, st, U, g, kappa, emu, cw, 0, kCgP, kCgW, 0);
+    cg_apply(U, g, kappa, emu, nr, cw, 0, kCgP, kCgW, 0, st);
     hipLaunchKernelGGL(k_cg_update_xr, gp, dim3(kPBlock), 0, st, g, cw, np_stencil(g.V), par);
     if (check) hipLaunchKernelGGL(k_cg_check, dim3(1, nr), dim3(kPBlock), 0, st, cw, np_point(g.V), tol * tol);
-    hipLaunchKernelGGL(k_cg_apply, gs, dim3(kCBlock), 0, st, U, g, kappa, emu, cw, 1, kCgR, kCgZ, 2);
+    cg_apply(U, g, kappa, emu, nr, cw, 1, kCgR, kCgZ, 2, st);
     hipLaunchKernelGGL(k_cg_update_p, gp, dim3(kPBlock), 0, st, g, cw, np_stencil(g.V), par);
 }
 
