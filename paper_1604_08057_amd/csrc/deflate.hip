@@ -11,21 +11,29 @@
 
 namespace tslov {
 
+// The deflation kernels treat a canonical spinor as a flat array of n = 12 V complex
+// values: block b covers elements [12 kBlock b, 12 kBlock (b + 1)) (the spinors of kBlock
+// sites) and lane t takes the 12 elements t, t + kBlock, ..., so that every load of a
+// wavefront reads 64 consecutive values.  Element j has spin (j mod 12) / 3.
+__device__ __forceinline__ size_t flat_elem(int m) {
+    return (size_t)blockIdx.x * 12 * kBlock + (size_t)m * kBlock + threadIdx.x;
+}
+
 // Per-block partial sums of L_i^H psi for i < l: part[b][2 i + {0, 1}].
 __global__ __launch_bounds__(kBlock) void k_defl_dots(const ZD* __restrict__ L, const ZD* __restrict__ psi, int V,
                                                       int l, double* __restrict__ part) {
-    const int s = blockIdx.x * kBlock + threadIdx.x;
     const size_t n = (size_t)V * 12;
     ZD x[12];
 #pragma unroll
-    for (int p = 0; p < 12; ++p) x[p] = (s < V) ? psi[(size_t)s * 12 + p] : mk<double>(0, 0);
+    for (int m = 0; m < 12; ++m) x[m] = flat_elem(m) < n ? psi[flat_elem(m)] : mk<double>(0, 0);
     for (int i = 0; i < l; ++i) {
         double v[2] = {0.0, 0.0};
-        if (s < V) {
-            const ZD* Li = L + (size_t)i * n + (size_t)s * 12;
+        const ZD* Li = L + (size_t)i * n;
 #pragma unroll
-            for (int p = 0; p < 12; ++p) {
-                const ZD t = cjmul(Li[p], x[p]);
+        for (int m = 0; m < 12; ++m) {
+            const size_t j = flat_elem(m);
+            if (j < n) {
+                const ZD t = cjmul(Li[j], x[m]);
                 v[0] += t.re;
                 v[1] += t.im;
             }
@@ -55,20 +63,20 @@ __global__ __launch_bounds__(kBlock) void k_defl_reduce(const double* __restrict
 // out = psi - sum_i c_i R_i
 __global__ __launch_bounds__(kBlock) void k_defl_project(const ZD* __restrict__ R, const ZD* __restrict__ psi,
                                                          const ZD* __restrict__ c, int V, int l, ZD* __restrict__ out) {
-    const int s = blockIdx.x * kBlock + threadIdx.x;
-    if (s >= V) return;
     const size_t n = (size_t)V * 12;
     ZD x[12];
 #pragma unroll
-    for (int p = 0; p < 12; ++p) x[p] = psi[(size_t)s * 12 + p];
+    for (int m = 0; m < 12; ++m) x[m] = flat_elem(m) < n ? psi[flat_elem(m)] : mk<double>(0, 0);
     for (int i = 0; i < l; ++i) {
         const ZD ci = c[i];
-        const ZD* Ri = R + (size_t)i * n + (size_t)s * 12;
+        const ZD* Ri = R + (size_t)i * n;
 #pragma unroll
-        for (int p = 0; p < 12; ++p) x[p] = x[p] - ci * Ri[p];
+        for (int m = 0; m < 12; ++m)
+            if (flat_elem(m) < n) x[m] = x[m] - ci * Ri[flat_elem(m)];
     }
 #pragma unroll
-    for (int p = 0; p < 12; ++p) out[(size_t)s * 12 + p] = x[p];
+    for (int m = 0; m < 12; ++m)
+        if (flat_elem(m) < n) out[flat_elem(m)] = x[m];
 }
 
 // out = [psi +] g5^{overlap} (y_p + sum_i sgn_i c_i R_i)
@@ -76,23 +84,24 @@ __global__ __launch_bounds__(kBlock) void k_defl_finish(const ZD* __restrict__ R
                                                         const double* __restrict__ sgn, const ZD* __restrict__ yp,
                                                         const ZD* __restrict__ psi, int V, int l, int overlap,
                                                         ZD* __restrict__ out) {
-    const int s = blockIdx.x * kBlock + threadIdx.x;
-    if (s >= V) return;
     const size_t n = (size_t)V * 12;
     ZD y[12];
 #pragma unroll
-    for (int p = 0; p < 12; ++p) y[p] = yp ? yp[(size_t)s * 12 + p] : mk<double>(0, 0);
+    for (int m = 0; m < 12; ++m) y[m] = (yp && flat_elem(m) < n) ? yp[flat_elem(m)] : mk<double>(0, 0);
     for (int i = 0; i < l; ++i) {
         const ZD ci = sgn[i] * c[i];
-        const ZD* Ri = R + (size_t)i * n + (size_t)s * 12;
+        const ZD* Ri = R + (size_t)i * n;
 #pragma unroll
-        for (int p = 0; p < 12; ++p) y[p] = y[p] + ci * Ri[p];
+        for (int m = 0; m < 12; ++m)
+            if (flat_elem(m) < n) y[m] = y[m] + ci * Ri[flat_elem(m)];
     }
 #pragma unroll
-    for (int p = 0; p < 12; ++p) {
-        ZD o = y[p];
-        if (overlap) o = ((p >= 6) ? -1.0 : 1.0) * o + psi[(size_t)s * 12 + p];
-        out[(size_t)s * 12 + p] = o;
+    for (int m = 0; m < 12; ++m) {
+        const size_t j = flat_elem(m);
+        if (j >= n) continue;
+        ZD o = y[m];
+        if (overlap) o = ((j % 12 >= 6) ? -1.0 : 1.0) * o + psi[j];
+        out[j] = o;
     }
 }
 
