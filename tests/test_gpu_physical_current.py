@@ -75,3 +75,21 @@ def test_physical_current_estimator(setup):
         f"max |tot| {np.abs(tot).max():.3e}; exact trace max |div| {np.abs(dr + 1j * di).max():.1e}")
     assert ew < 1e-9
     assert np.abs(tot).max() > 0.1
+
+
+def test_error_paths(setup):
+    """A solve stopped before its tolerance returns ERR_NOT_CONVERGED (forced from the host
+    with maxit = 1); bad tolerances and iteration limits are argument errors."""
+    from paper_1604_08057_amd.tslov import ERR_ARG, ERR_NOT_CONVERGED, TslovError
+    wl, ctx, _ = setup
+    b = dev(wl.psi()[0])
+    with pytest.raises(TslovError) as e:
+        ctx.overlap_solve(b, wl.k, tol=1e-14, maxit=1)
+    assert e.value.status == ERR_NOT_CONVERGED
+    for kw in ({"tol": 0.0}, {"maxit": 0}):
+        with pytest.raises(TslovError) as e:
+            ctx.overlap_solve(b, wl.k, **kw)
+        assert e.value.status == ERR_ARG
+    with pytest.raises(TslovError) as e:
+        ctx.physical_current(dev(wl.psi()), wl.k, tol=-1.0)
+    assert e.value.status == ERR_ARG

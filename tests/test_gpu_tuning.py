@@ -98,3 +98,25 @@ def test_tuning_run_block_derivative():
         say(f"  tune block 4^4 k={k}: eps_B {e:.10e} (oracle {w:.10e})")
         assert _close(e, w)
     assert res["chosen"] == TU.select(res["eps"], res["ms"], 10.0)
+
+
+def test_tuning_argument_errors():
+    """The block-matrix process has no nested step and takes no deflation; sizes out of range."""
+    from paper_1604_08057_amd import Context
+    from paper_1604_08057_amd.tslov import ERR_ARG, TslovError
+    wl = workload(1)
+    ctx = Context(wl.dims, wl.mass, wl.mu)
+    ctx.set_links(dev(wl.links()))
+    X = np.eye(3, dtype=complex)
+    for kw in ({"k_outer": [16], "k_inner": [8], "direction": (0, 3, X)},
+               {"k_outer": [0]}, {"k_outer": [16], "k_inner": [-1]}, {"k_outer": [16], "trial_target": -1.0}):
+        with pytest.raises(TslovError) as e:
+            ctx.tune_k(**kw)
+        assert e.value.status == ERR_ARG
+    r = np.random.default_rng(1)
+    R = r.standard_normal((1, wl.volume, 4, 3)) + 0j
+    defl = ctx.deflation(dev(R), dev(R / np.vdot(R, R).real), np.array([0.5 + 0.1j]))
+    with pytest.raises(TslovError) as e:
+        ctx.tune_k([16], defl=defl, direction=(0, 3, X))
+    assert e.value.status == ERR_ARG
+    ctx.close()
