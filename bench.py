@@ -403,8 +403,8 @@ def main():
         out["stencil_large"] = stencil_large()
         log(f"bench: 32^4 stencil {out['stencil_large']['achieved_GBs']:.0f} GB/s")
     if not args.no_cpu_baseline:
-        log("bench: timing the CPU oracle on a bounded sample (~20-40 s)")
-        out["cpu_baseline"] = cpu_baseline(20, sum(h["ks"]) / n)
+        log("bench: timing the CPU oracle on a bounded sample (~10-20 s)")
+        out["cpu_baseline"] = cpu_baseline(120, sum(h["ks"]) / n)
     print(json.dumps(out), flush=True)
 
 
