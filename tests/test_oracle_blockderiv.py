@@ -149,3 +149,101 @@ def test_block_error_estimate_tracks_the_derivative_error():
     assert all(b < a for a, b in zip(errs, errs[1:])), errs
     for e, p in zip(errs, eps):
         assert 0.01 < p / e < 100.0, (errs, eps)
+
+
+# ------------------------------------------------------------------ App. E deflation
+
+def _defl_problem(l=12, seed=21):
+    dims, mass, mu, U, psi, nu, site, X = _problem(seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    op = W.WilsonOperator(dims, mass, mu)
+    dU = BD.link_direction_field(U, nu, site, X)
+    x1 = psi * 0.3 + 0.2 * (rng.standard_normal(psi.shape) + 1j * rng.standard_normal(psi.shape))
+    return dims, mass, mu, U, dU, op, x1, psi
+
+
+def test_eigenvector_derivatives_match_finite_differences():
+    """dR_i and <dL_i|x> (normalised <L_i|dR_i> = <dL_i|R_i> = 0) against central
+    differences of the dense eigenvectors of H + t dH, each moved eigenvector scaled so
+    that its overlap with the unmoved partner is 1."""
+    dims, mass, mu, U, dU, op, x1, psi = _defl_problem()
+    H = W.dense_h(U, dims, mass, mu)
+    dH = W.dense_h(U + dU, dims, mass, mu) - H
+    l = 6
+    lam, R, L, dR, dLx = BD.eigenvector_derivatives(H, dH, l)
+    x = x1.ravel()
+    h = 1e-6
+    moved = {}
+    for s in (1.0, -1.0):
+        w, vl, vr = sla.eig(H + s * h * dH, left=True, right=True)
+        moved[s] = (w, vl, vr)
+    dLx_want = np.zeros(l, dtype=np.complex128)
+    for i in range(l):
+        cols = {}
+        for s, (w, vl, vr) in moved.items():
+            j = int(np.argmin(np.abs(w - lam[i])))
+            r = vr[:, j] / np.vdot(L[:, i], vr[:, j])           # L_i^H R_i(t) = 1
+            q = vl[:, j] / np.conj(np.vdot(vl[:, j], R[:, i]))  # L_i(t)^H R_i = 1
+            cols[s] = (r, q)
+        fd_r = (cols[1.0][0] - cols[-1.0][0]) / (2 * h)
+        fd_l = (np.vdot(cols[1.0][1], x) - np.vdot(cols[-1.0][1], x)) / (2 * h)
+        assert np.linalg.norm(fd_r - dR[:, i]) < 1e-5 * np.linalg.norm(dR[:, i]), i
+        dLx_want[i] = fd_l
+    assert np.abs(dLx(x) - dLx_want).max() < 1e-5 * np.abs(dLx_want).max()
+
+
+def test_full_deflation_is_the_exact_block_sign():
+    """l = n: the exact part alone is sgn(B)(x1, x2) = (sgn(H) x1 + L_sgn(H, dH) x2, sgn(H) x2)
+    (Theorem 1, the Frechet derivative by the block-matrix sign)."""
+    dims, mass, mu, U, dU, op, x1, psi = _defl_problem()
+    n = psi.size
+    res = BD.deflated_block_sign(op, U, dU, x1, psi, 4, n, dims, mass, mu)
+    H, dH = res["H"], res["dH"]
+    S = SG.sign_schur(H)
+    want1 = S @ x1.ravel() + SG.frechet_sign(H, dH) @ psi.ravel()
+    want2 = S @ psi.ravel()
+    assert np.linalg.norm(res["y1"].ravel() - want1) < 1e-10 * np.linalg.norm(want1)
+    assert np.linalg.norm(res["y2"].ravel() - want2) < 1e-10 * np.linalg.norm(want2)
+
+
+def test_projected_source_has_no_deflated_component():
+    """Pbar x carries no component along the deflated invariant subspace of B: both
+    coefficients c1, c2 of the projected source vanish (they would not if each pair's
+    part were subtracted from x1 before the next c1 is formed)."""
+    dims, mass, mu, U, dU, op, x1, psi = _defl_problem()
+    l = 10
+    res = BD.deflated_block_sign(op, U, dU, x1, psi, 8, l, dims, mass, mu)
+    lam, R, L, dR, dLx = BD.eigenvector_derivatives(res["H"], res["dH"], l)
+    p1, p2 = res["p1"], res["p2"]
+    c2p = L.conj().T @ p2
+    c1p = L.conj().T @ p1 + dLx(p2)
+    scale = np.abs(res["c1"]).max() + np.abs(res["c2"]).max()
+    assert np.abs(c2p).max() < 1e-12 * scale and np.abs(c1p).max() < 1e-10 * scale
+    # the listing's sequential subtraction leaves the cross terms in c1
+    x1s = x1.ravel().astype(np.complex128)
+    c1_seq = np.zeros(l, dtype=np.complex128)
+    c2 = res["c2"]
+    dlx2 = dLx(psi.ravel())
+    for i in range(l):
+        c1_seq[i] = np.vdot(L[:, i], x1s) + dlx2[i]
+        x1s = x1s - c1_seq[i] * R[:, i] - c2[i] * dR[:, i]
+    assert np.abs(c1_seq - res["c1"]).max() > 1e-6 * scale
+
+
+def test_deflation_improves_the_block_sign_at_fixed_k():
+    dims, mass, mu, U, dU, op, x1, psi = _defl_problem()
+    H = W.dense_h(U, dims, mass, mu)
+    dH = W.dense_h(U + dU, dims, mass, mu) - H
+    S = SG.sign_schur(H)
+    want = np.concatenate([S @ x1.ravel() + SG.frechet_sign(H, dH) @ psi.ravel(), S @ psi.ravel()])
+    errs = []
+    for l in (0, 10, 40):
+        res = BD.deflated_block_sign(op, U, dU, x1, psi, 24, l, dims, mass, mu)
+        got = np.concatenate([res["y1"].ravel(), res["y2"].ravel()])
+        errs.append(np.linalg.norm(got - want) / np.linalg.norm(want))
+    assert errs[2] < errs[1] < errs[0], errs
+    # eps_B of the deflated process (App. E's reason for general sources): falls with l
+    e0 = BD.eps_block_deflated(op, U, dU, psi, 24, 0, dims, mass, mu)
+    e40 = BD.eps_block_deflated(op, U, dU, psi, 24, 40, dims, mass, mu)
+    assert e40 < e0
+    assert BD.eps_block_deflated(op, U, dU, psi, 4, psi.size, dims, mass, mu) < 1e-12
