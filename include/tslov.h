@@ -328,11 +328,36 @@ tslov_status tslov_ritz_values(int k, const double* diag, const double* sub, con
 tslov_status tslov_block_sign(tslov_ctx* ctx, int nu, int site, const double* X, const void* x1, const void* x2,
                               int k, void* y1_out, void* y2_out, tslov_info* info);
 
+/* The block-matrix process deflated by eigenpairs of H (App. E, eq. array_app_defl_1):
+ * the eigenpairs (lambda_i, R_i, L_i) of defl (as for tslov_sign; L^H R = 1, distinct
+ * eigenvalues, accurate for the links set) span with their derivatives the
+ * 2l-dimensional invariant subspace of B with right basis (R_i, 0), (dR_i, R_i), which
+ * is treated exactly:
+ *   y = sum_i s_i [(R_i, 0) c1_i + (dR_i, R_i) c2_i] + TSL_k(B, Pbar x),
+ *   c2_i = L_i^H x2,  c1_i = L_i^H x1 + <dL_i|x2>,  s_i = sgn Re lambda_i,
+ *   Pbar x = (x1 - sum_i (c1_i R_i + c2_i dR_i), x2 - sum_i c2_i R_i),
+ * every coefficient taken from the input.  The eigenvector derivatives (normalised
+ * <L_i|dR_i> = <dL_i|R_i> = 0, eq. c1i_3 and eq. dRi) need the 2l singular
+ * consistent systems (lambda_i - H) z = P dH R_i and (lambda_i - H) z = P x2
+ * (P = 1 - sum_j R_j L_j^H), solved on the device by conjugate gradients on the
+ * normal equations to relative residual 1e-13 (ERR_NOT_CONVERGED after 1e5
+ * iterations; info->cg_iters = iterations used), their R_i components removed.
+ * defl = NULL or l = 0 is tslov_block_sign.  Other arguments and errors as there. */
+tslov_status tslov_block_sign_deflated(tslov_ctx* ctx, int nu, int site, const double* X, const void* x1,
+                                       const void* x2, int k, const tslov_deflation* defl, void* y1_out,
+                                       void* y2_out, tslov_info* info);
+
 /* Its error estimate (Sec. 4.1 eq. bA_error_est): with (y1, y2) = TSL_k(B, (0, psi))
  * and (z1, z2) = TSL_k(B, (y1, y2)) (a fresh process from the first result),
  * eps_B = |(z1, z2 - psi)| / (2 |psi|).  eps_out: host double. */
 tslov_status tslov_block_error_estimate(tslov_ctx* ctx, int nu, int site, const double* X, const void* psi, int k,
                                         double* eps_out);
+
+/* eps_B with the deflated block process (tslov_block_sign_deflated) for both
+ * applications, the second from the first result (App. E: the reason for deflating
+ * general sources).  defl = NULL or l = 0 is tslov_block_error_estimate. */
+tslov_status tslov_block_error_estimate_deflated(tslov_ctx* ctx, int nu, int site, const double* X, const void* psi,
+                                                 int k, const tslov_deflation* defl, double* eps_out);
 
 /* One link parameter of the block-matrix derivative: U_nu(site) -> exp(i t X) U_nu(site),
  * X a 3 x 3 complex matrix as 18 doubles, row-major (re, im). */
@@ -442,6 +467,24 @@ tslov_status tslov_get_apply_chunk(const tslov_ctx* ctx, int* T);
  * forward (fwd_ns) and reverse (bwd_ns) kernels; either pointer may be NULL. */
 tslov_status tslov_set_pair_ns(tslov_ctx* ctx, int ns);
 tslov_status tslov_get_pair_ns(const tslov_ctx* ctx, int* fwd_ns, int* bwd_ns);
+
+/* Operator form of the shifted solves in the deflated derivative (the conjugate
+ * gradients on the normal equations of the 2l systems (lambda_i - H) z = ...,
+ * Sec. 3 with App. B), each application covering all unconverged systems:
+ *   form = 0: multi-right-hand-side, eight systems per wavefront at eight sites,
+ *            reading each link element in one load;
+ *   form = 1: colour split, two systems per workgroup;
+ *   form = 2: the multi-right-hand-side layout with the link times half-spinor
+ *            products on the float64 matrix cores (v_mfma_f64_16x16x4f64);
+ *   form = 3 (the default): each thread marches one (x, y, z) site of one system
+ *            along t, the systems of a tile running back to back on one XCD.
+ * The results agree to rounding (the forms differ in the summation order of the
+ * residual norms and, on the matrix cores, of the link products).  Form 3 needs an
+ * (x, y, z) volume in multiples of 1024 sites and runs form 0 otherwise; forms 0
+ * and 2 need 7 * 5 * 12 * ldv + ldv complex doubles to stay below 4 GiB (lattices
+ * up to about 639,000 sites) and run form 1 above that.  ERR_ARG for any other
+ * form. */
+tslov_status tslov_set_cg_operator(tslov_ctx* ctx, int form);
 
 /* Algorithmic bytes moved by one launch of kernel class `which` (see above) for
  * this context's lattice and precision (minimal traffic, each field once). */

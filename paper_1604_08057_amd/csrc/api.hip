@@ -171,6 +171,7 @@ struct tslov_ctx {
     int diag = 0;    // tslov_set_diagnostics flags
     int nest_m = 0;  // inner Krylov size of the nested projected-matrix step (0: plain)
     Buf blk;         // block-matrix process: 14 working fields, 2k basis fields, partials
+    Buf bdefl;       // deflated block process: dH R_i, dR_i, the shifted solutions, temporaries, coefficients
     Buf nestbuf;     // its inner basis, vectors and coefficients
     Buf U64, U32;
     Buf badflag;     // device int: a non-finite link element was seen
@@ -216,6 +217,8 @@ struct tslov_ctx {
     // t-slices per chunk of the t-march operator: the timed pick (0: none yet,
     // -1: the operator does not march on this lattice) and a forced value
     int tm_T = 0, tm_T_forced = 0;
+    // operator form of the shifted solves of the deflated derivative (tslov::kCgOp*)
+    int cg_op = tslov::kCgOpTmarch;
 
     int nblk() const { return tslov::grid_for(g.V); }
     size_t field_elems() const { return (size_t)12 * g.ldv; }
@@ -1450,6 +1453,52 @@ constexpr double kCgTol = 1e-13;     // relative residual of the shifted solves
 constexpr int kCgMaxIter = 100000;
 constexpr int kCgCheckEvery = 8;
 
+// Workspace and per-system scalars of nr shifted systems (sigma_e - H(m_e mu)) x = b.
+tslov_status cg_setup(tslov_ctx* c, int nr, const ZD* sigma, const double* msign, tslov::CgWork& cw) {
+    const int ps = c->pstride();
+    CHK(ensure(c->cgf, (size_t)nr * tslov::kCgFields * c->field_elems() * sizeof(ZD)));
+    CHK(ensure(c->cgp, (size_t)nr * 4 * ps * sizeof(double)));
+    CHK(ensure(c->cgs, (size_t)nr * sizeof(tslov::CgRhs)));
+    cw.f = c->cgf.as<ZD>();
+    cw.part = c->cgp.as<double>();
+    cw.st = c->cgs.as<tslov::CgRhs>();
+    cw.fe = c->field_elems();
+    cw.pstride = ps;
+    cw.op = c->cg_op;
+    std::vector<tslov::CgRhs> st0(nr);
+    for (int e = 0; e < nr; ++e) {
+        st0[e] = tslov::CgRhs{};
+        st0[e].sigma = sigma[e];
+        st0[e].msign = msign[e];
+    }
+    HIPCHK(hipMemcpyAsync(cw.st, st0.data(), nr * sizeof(tslov::CgRhs), hipMemcpyHostToDevice, c->st));
+    return TSLOV_OK;
+}
+
+// Conjugate gradients on the normal equations of the nr systems whose right-hand sides
+// are loaded (r = b, x = 0, |b|^2 set): all in lockstep, each frozen once its residual
+// is below kCgTol |b|; the convergence flags are read every kCgCheckEvery iterations.
+tslov_status cg_solve(tslov_ctx* c, int nr, const tslov::CgWork& cw, int* iters) {
+    const ZD* U = c->U64.as<ZD>();
+    tslov::launch_cg_start(U, c->g, c->kappa, c->mu, nr, cw, c->st);
+    int it = 0, all_done = 0;
+    std::vector<tslov::CgRhs> sh(nr);
+    for (; it < kCgMaxIter && !all_done; ++it) {
+        const int check = (it % kCgCheckEvery) == kCgCheckEvery - 1;
+        tslov::launch_cg_iteration(U, c->g, c->kappa, c->mu, nr, it, check, kCgTol, cw, c->st);
+        if (check) {
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(sh.data(), cw.st, nr * sizeof(tslov::CgRhs), hipMemcpyDeviceToHost, c->st));
+            HIPCHK(hipStreamSynchronize(c->st));
+            all_done = 1;
+            for (int e = 0; e < nr; ++e) all_done &= sh[e].done;
+        }
+    }
+    *iters = it;
+    if (!all_done) return fail(TSLOV_ERR_NOT_CONVERGED, "shifted solves of the eigenpair derivative did not converge");
+    return TSLOV_OK;
+}
+
 // Derivative of the deflated S = Re eta^H [sum_i s_i Pi_i psi + TSL(P psi)], P = 1 - sum_i Pi_i,
 // with the eigenpairs moving with U (reduced-resolvent solves; see solve.hip).
 tslov_status deflated_grad(tslov_ctx* c, const ZD* eta, const ZD* psi, int k, const tslov_deflation* defl,
@@ -1505,42 +1554,19 @@ tslov_status deflated_grad(tslov_ctx* c, const ZD* eta, const ZD* psi, int k, co
     HIPCHK(hipMemcpyAsync(qd, qh.data(), l * sizeof(ZD), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemcpyAsync(mqd, mq.data(), l * sizeof(ZD), hipMemcpyHostToDevice, c->st));
     // shifted solves: e < l: (lambda_i - H) z = (1 - Pi_i) psi;  e >= l: (conj lambda_i - H^dag) z' = (1 - Pi_i^H) a_i
-    const int ps = c->pstride();
-    CHK(ensure(c->cgf, (size_t)nr * tslov::kCgFields * c->field_elems() * sizeof(ZD)));
-    CHK(ensure(c->cgp, (size_t)nr * 4 * ps * sizeof(double)));
-    CHK(ensure(c->cgs, (size_t)nr * sizeof(tslov::CgRhs)));
-    tslov::CgWork cw;
-    cw.f = c->cgf.as<ZD>();
-    cw.part = c->cgp.as<double>();
-    cw.st = c->cgs.as<tslov::CgRhs>();
-    cw.fe = c->field_elems();
-    cw.pstride = ps;
-    std::vector<tslov::CgRhs> st0(nr);
+    std::vector<ZD> sig(nr);
+    std::vector<double> msg(nr);
     for (int e = 0; e < nr; ++e) {
         const int i = e < l ? e : e - l;
         const double lr = defl->lambda[2 * i], li = defl->lambda[2 * i + 1];
-        st0[e] = tslov::CgRhs{};
-        st0[e].sigma = e < l ? ZD{lr, li} : ZD{lr, -li};
-        st0[e].msign = e < l ? 1.0 : -1.0;
+        sig[e] = e < l ? ZD{lr, li} : ZD{lr, -li};
+        msg[e] = e < l ? 1.0 : -1.0;
     }
-    HIPCHK(hipMemcpyAsync(cw.st, st0.data(), nr * sizeof(tslov::CgRhs), hipMemcpyHostToDevice, c->st));
-    const ZD* U = c->U64.as<ZD>();
+    tslov::CgWork cw;
+    CHK(cg_setup(c, nr, sig.data(), msg.data(), cw));
     tslov::launch_cg_rhs(c->g, psi, eta, pbar, d.R, d.L, d.c, qd, d.sgn, l, cw, c->st);
-    tslov::launch_cg_start(U, c->g, c->kappa, c->mu, nr, cw, c->st);
-    int it = 0, all_done = 0;
-    std::vector<tslov::CgRhs> sh(nr);
-    for (; it < kCgMaxIter && !all_done; ++it) {
-        const int check = (it % kCgCheckEvery) == kCgCheckEvery - 1;
-        tslov::launch_cg_iteration(U, c->g, c->kappa, c->mu, nr, it, check, kCgTol, cw, c->st);
-        if (check) {
-            HIPCHK(hipGetLastError());
-            HIPCHK(hipMemcpyAsync(sh.data(), cw.st, nr * sizeof(tslov::CgRhs), hipMemcpyDeviceToHost, c->st));
-            HIPCHK(hipStreamSynchronize(c->st));
-            all_done = 1;
-            for (int e = 0; e < nr; ++e) all_done &= sh[e].done;
-        }
-    }
-    if (!all_done) return fail(TSLOV_ERR_NOT_CONVERGED, "shifted solves of the eigenpair derivative did not converge");
+    int it = 0;
+    CHK(cg_solve(c, nr, cw, &it));
     tslov::launch_cg_finish(c->g, d.R, d.L, d.c, l, cw, c->st);
     tslov::launch_defl_force(c->g, c->kappa, c->mu, d.R, d.L, qd, l, cw, c->antiperiodic, dU, c->st);
     // source gradient: psibar = psibar_p + sum_i q_i L_i
@@ -1720,8 +1746,144 @@ namespace {
 
 // eps_B of eq. bA_error_est for the tangent t and source (0, psi); ms_first (nullable)
 // receives the wall time of the first block process.  Uses canonical buffers 3..7.
+// out = dH in (canonical) for the link tangent t, through the float64 SoA fields f0, f1.
+void apply_tangent(tslov_ctx* c, const tslov::BlockTangent& t, const ZD* in, ZD* out, ZD* f0, ZD* f1) {
+    const Geom& g = c->g;
+    tslov::launch_spinor_to_soa<double>(in, f0, g, nullptr, c->st);
+    tslov::launch_zero((double*)f1, 2 * c->field_elems(), c->st);
+    tslov::launch_blk_tangent(c->U64.as<ZD>(), t, g, c->kappa, c->mu, f0, f1, nullptr, nullptr, c->st);
+    tslov::launch_spinor_from_soa<double>(f1, out, g, c->st);
+}
+
+// Deflated block-matrix process (App. E, eq. array_app_defl_1): with the l eigenpairs
+// (lambda_i, R_i, L_i) of H (L^H R = 1) the 2l-dimensional invariant subspace of
+// B = [[H, dH], [0, H]] spanned by (R_i, 0), (dR_i, R_i) is treated exactly:
+//   c2_i = L_i^H x2,   c1_i = L_i^H x1 + <dL_i|x2>,
+//   y = sum_i s_i [(R_i, 0) c1_i + (dR_i, R_i) c2_i] + TSL_k(B, Pbar x),
+//   Pbar x = (x1 - sum_i (c1_i R_i + c2_i dR_i), x2 - sum_i c2_i R_i),
+// s_i = sgn Re lambda_i; every coefficient from the input x (Pbar x then has no
+// component along the deflated subspace).  The eigenvector derivatives (normalised
+// <L_i|dR_i> = <dL_i|R_i> = 0, eq. c1i_3 and eq. dRi):
+//   dR_i = sum_{j != i, j <= l} R_j (L_j^H dH R_i) / (lambda_i - lambda_j) + Q_i (lambda_i - H)^{-1} P_l dH R_i,
+//   <dL_i|x2> = L_i^H dH [ sum_{j != i} R_j c2_j / (lambda_i - lambda_j) + Q_i (lambda_i - H)^{-1} P_l x2 ],
+// P_l = 1 - sum_j R_j L_j^H, Q_i = 1 - R_i L_i^H.  The 2l singular consistent systems
+// (lambda_i - H) z = P_l dH R_i and (lambda_i - H) z = P_l x2 go to one batched CGNR
+// (the minimum-norm solution; Q_i removes its R_i component).
+tslov_status block_tsl_deflated(tslov_ctx* c, const tslov::BlockTangent& t, const DeflSet& d, const double* lambda,
+                                const ZD* x1, const ZD* x2, int k, ZD* y1, ZD* y2, EntryStatus& es) {
+    const Geom& g = c->g;
+    const int l = d.l, V = g.V, nb = c->nblk();
+    const size_t n12 = (size_t)12 * V, fe = c->field_elems();
+    // vectors: dHR[l], dR[l], Z[2l] (solutions), xk, p1, tmp, t1, t2 (canonical); f0, f1 (SoA);
+    // scalars: M[l][l] (column i = L^H dH R_i), c1, c2, coefficient scratch (l each), one dot;
+    // dot partials (nb x 2 l doubles)
+    const size_t nvec = (size_t)4 * l + 5;
+    CHK(ensure(c->bdefl, nvec * n12 * sizeof(ZD) + 2 * fe * sizeof(ZD) + ((size_t)l * l + 3 * (size_t)l + 1) * sizeof(ZD) +
+                             (size_t)nb * 2 * l * sizeof(double)));
+    ZD* base = c->bdefl.as<ZD>();
+    ZD* dHR = base;
+    ZD* dR = dHR + (size_t)l * n12;
+    ZD* Z = dR + (size_t)l * n12;
+    ZD* xk = Z + (size_t)2 * l * n12;
+    ZD* p1 = xk + n12;
+    ZD* tmp = p1 + n12;
+    ZD* t1 = tmp + n12;
+    ZD* t2 = t1 + n12;
+    ZD* f0 = t2 + n12;
+    ZD* f1 = f0 + fe;
+    ZD* M = f1 + fe;
+    ZD* c1 = M + (size_t)l * l;
+    ZD* c2 = c1 + l;
+    ZD* coef = c2 + l;
+    ZD* dot = coef + l;
+    double* part = (double*)(dot + 1);
+    auto vec = [&](ZD* b, int i) { return b + (size_t)i * n12; };
+    // dH R_i and M[., i] = L^H dH R_i
+    for (int i = 0; i < l; ++i) {
+        apply_tangent(c, t, d.R + (size_t)i * n12, vec(dHR, i), f0, f1);
+        tslov::launch_defl_coeffs(d.L, vec(dHR, i), V, l, part, M + (size_t)i * l, c->st);
+    }
+    // c2 = L^H x2, xk = P_l x2; the right-hand sides P_l dH R_i in place
+    tslov::launch_defl_coeffs(d.L, x2, V, l, part, c2, c->st);
+    tslov::launch_defl_project(d.R, x2, c2, V, l, xk, c->st);
+    for (int i = 0; i < l; ++i) tslov::launch_defl_project(d.R, vec(dHR, i), M + (size_t)i * l, V, l, vec(Z, i), c->st);
+    std::vector<ZD> Mh((size_t)l * l), c2h(l);
+    HIPCHK(hipMemcpyAsync(Mh.data(), M, Mh.size() * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(c2h.data(), c2, l * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+    // the 2l shifted systems: e < l with rhs P_l dH R_e (in Z[e]), e >= l with rhs xk
+    const int nr = 2 * l;
+    std::vector<ZD> sig(nr);
+    std::vector<double> msg(nr, 1.0);
+    for (int e = 0; e < nr; ++e) sig[e] = ZD{lambda[2 * (e % l)], lambda[2 * (e % l) + 1]};
+    tslov::CgWork cw;
+    CHK(cg_setup(c, nr, sig.data(), msg.data(), cw));
+    tslov::launch_cg_load(g, Z, l, xk, nr, cw, c->st);
+    int it = 0;
+    CHK(cg_solve(c, nr, cw, &it));
+    tslov::launch_cg_store(g, nr, cw, Z, c->st);
+    // Q_i on each solution
+    for (int e = 0; e < nr; ++e) {
+        const int i = e % l;
+        tslov::launch_defl_coeffs(d.L + (size_t)i * n12, vec(Z, e), V, 1, part, dot, c->st);
+        tslov::launch_defl_project(d.R + (size_t)i * n12, vec(Z, e), dot, V, 1, vec(Z, e), c->st);
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    std::vector<ZD> ch(l);
+    for (int i = 0; i < l; ++i) {
+        const ZD li{lambda[2 * i], lambda[2 * i + 1]};
+        // dR_i = Q_i z_i + sum_{j != i} R_j M[j][i] / (lambda_i - lambda_j)   (project with -coefficients)
+        std::vector<ZD> a(l), b(l);
+        for (int j = 0; j < l; ++j) {
+            if (j == i) {
+                a[j] = ZD{0.0, 0.0};
+                b[j] = ZD{0.0, 0.0};
+                continue;
+            }
+            const ZD dl{li.re - lambda[2 * j], li.im - lambda[2 * j + 1]};
+            const double den = dl.re * dl.re + dl.im * dl.im;
+            const ZD inv{dl.re / den, -dl.im / den};
+            const ZD m = Mh[(size_t)i * l + j];
+            a[j] = ZD{-(m.re * inv.re - m.im * inv.im), -(m.re * inv.im + m.im * inv.re)};
+            b[j] = ZD{-(c2h[j].re * inv.re - c2h[j].im * inv.im), -(c2h[j].re * inv.im + c2h[j].im * inv.re)};
+        }
+        HIPCHK(hipMemcpyAsync(coef, a.data(), l * sizeof(ZD), hipMemcpyHostToDevice, c->st));
+        tslov::launch_defl_project(d.R, vec(Z, i), coef, V, l, vec(dR, i), c->st);
+        // v_i = Q_i w_i + sum_{j != i} R_j c2_j / (lambda_i - lambda_j);  c1_i = L_i^H (x1 + dH v_i)
+        HIPCHK(hipMemcpyAsync(coef, b.data(), l * sizeof(ZD), hipMemcpyHostToDevice, c->st));
+        tslov::launch_defl_project(d.R, vec(Z, l + i), coef, V, l, t1, c->st);
+        apply_tangent(c, t, t1, t2, f0, f1);
+        if (x1) tslov::launch_combine(x1, t2, 0, V, t2, c->st);   // t2 = x1 + dH v_i
+        tslov::launch_defl_coeffs(d.L + (size_t)i * n12, t2, V, 1, part, c1 + i, c->st);
+        HIPCHK(hipStreamSynchronize(c->st));   // a and b are reused by the next i
+    }
+    // Pbar x: p1 = x1 - R c1 - dR c2, p2 = xk
+    if (x1) tslov::launch_defl_project(d.R, x1, c1, V, l, tmp, c->st);
+    else {
+        tslov::launch_zero((double*)p1, 2 * n12, c->st);
+        tslov::launch_defl_project(d.R, p1, c1, V, l, tmp, c->st);
+    }
+    tslov::launch_defl_project(dR, tmp, c2, V, l, p1, c->st);
+    CHK(block_tsl(c, t, p1, xk, k, y1, y2, es));
+    // exact part: y1 += sum_i s_i (c1_i R_i + c2_i dR_i), y2 += sum_i s_i c2_i R_i
+    tslov::launch_defl_finish(d.R, c1, d.sgn, y1, nullptr, V, l, 0, tmp, c->st);
+    tslov::launch_defl_finish(dR, c2, d.sgn, tmp, nullptr, V, l, 0, y1, c->st);
+    tslov::launch_defl_finish(d.R, c2, d.sgn, y2, nullptr, V, l, 0, tmp, c->st);
+    HIPCHK(hipMemcpyAsync(y2, tmp, n12 * sizeof(ZD), hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    es.cg_iters = it;
+    return TSLOV_OK;
+}
+
+// The block process with or without deflation.
+tslov_status block_any(tslov_ctx* c, const tslov::BlockTangent& t, const DeflSet& d, const double* lambda,
+                       const ZD* x1, const ZD* x2, int k, ZD* y1, ZD* y2, EntryStatus& es) {
+    if (d.l > 0) return block_tsl_deflated(c, t, d, lambda, x1, x2, k, y1, y2, es);
+    return block_tsl(c, t, x1, x2, k, y1, y2, es);
+}
+
 tslov_status block_eps(tslov_ctx* c, const tslov::BlockTangent& t, const ZD* psi, int k, double* eps_out,
-                       double* ms_first) {
+                       double* ms_first, const DeflSet& d = DeflSet(), const double* lambda = nullptr) {
     const size_t n12 = (size_t)12 * c->g.V;
     CHK(ensure(c->canon, (size_t)kCanonBufs * n12 * sizeof(ZD)));
     ZD* y1 = canon_buf(c, 3);
@@ -1732,10 +1894,10 @@ tslov_status block_eps(tslov_ctx* c, const tslov::BlockTangent& t, const ZD* psi
     EntryStatus es;
     HIPCHK(hipStreamSynchronize(c->st));
     const double t0 = now_ms();
-    CHK(block_tsl(c, t, nullptr, psi, k, y1, y2, es));
+    CHK(block_any(c, t, d, lambda, nullptr, psi, k, y1, y2, es));
     HIPCHK(hipStreamSynchronize(c->st));
     if (ms_first) *ms_first = now_ms() - t0;
-    CHK(block_tsl(c, t, y1, y2, k, z1, z2, es));
+    CHK(block_any(c, t, d, lambda, y1, y2, k, z1, z2, es));
     tslov::launch_zero((double*)zero, 2 * n12, c->st);
     CHK(ensure_host_part(c, 4096));
     double* part = c->part.as<double>() + 2 * c->pstride();
@@ -1853,7 +2015,7 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
 void tslov_destroy(tslov_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
-    for (Buf* b : {&c->trial, &c->solvebuf, &c->physbuf, &c->U64, &c->U32, &c->badflag, &c->nestbuf, &c->blk, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
+    for (Buf* b : {&c->trial, &c->solvebuf, &c->physbuf, &c->U64, &c->U32, &c->badflag, &c->nestbuf, &c->blk, &c->bdefl, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
                    &c->fields, &c->part, &c->coefmem, &c->dense, &c->denseInt, &c->densePart, &c->denseDelta,
                    &c->gpart, &c->gsrc, &c->bout, &c->wardp, &c->canon, &c->deflw, &c->deflx, &c->cgf, &c->cgp,
                    &c->cgs, &c->ckpt})
@@ -2227,29 +2389,45 @@ tslov_status tslov_ritz_values(int k, const double* diag, const double* sub, con
     return TSLOV_OK;
 }
 
-tslov_status tslov_block_sign(tslov_ctx* c, int nu, int site, const double* X, const void* x1, const void* x2,
-                              int k, void* y1_out, void* y2_out, tslov_info* info) {
-    CHK(check_common(c, k, nullptr));
+tslov_status tslov_block_sign_deflated(tslov_ctx* c, int nu, int site, const double* X, const void* x1,
+                                       const void* x2, int k, const tslov_deflation* defl, void* y1_out,
+                                       void* y2_out, tslov_info* info) {
+    CHK(check_common(c, k, defl));
     if (!x2 || !y1_out || !y2_out) return fail(TSLOV_ERR_ARG, "null argument");
     if (y1_out == y2_out || y1_out == x1 || y1_out == x2 || y2_out == x1 || y2_out == x2)
         return fail(TSLOV_ERR_ARG, "outputs must not overlap each other or the inputs");
     tslov::BlockTangent t;
     CHK(block_args(c, nu, site, X, t));
+    DeflSet d;
+    CHK(prepare_defl(c, defl, d));
     const double t0 = now_ms();
     EntryStatus es;
-    CHK(block_tsl(c, t, (const ZD*)x1, (const ZD*)x2, k, (ZD*)y1_out, (ZD*)y2_out, es));
+    CHK(block_any(c, t, d, d.l ? defl->lambda : nullptr, (const ZD*)x1, (const ZD*)x2, k, (ZD*)y1_out,
+                  (ZD*)y2_out, es));
     const double ms[6] = {0.0, 0.0, 0.0, 0.0, 0.0, now_ms() - t0};
     fill_info(info, es, ms);
     return TSLOV_OK;
 }
 
-tslov_status tslov_block_error_estimate(tslov_ctx* c, int nu, int site, const double* X, const void* psi, int k,
-                                        double* eps_out) {
-    CHK(check_common(c, k, nullptr));
+tslov_status tslov_block_sign(tslov_ctx* c, int nu, int site, const double* X, const void* x1, const void* x2,
+                              int k, void* y1_out, void* y2_out, tslov_info* info) {
+    return tslov_block_sign_deflated(c, nu, site, X, x1, x2, k, nullptr, y1_out, y2_out, info);
+}
+
+tslov_status tslov_block_error_estimate_deflated(tslov_ctx* c, int nu, int site, const double* X, const void* psi,
+                                                 int k, const tslov_deflation* defl, double* eps_out) {
+    CHK(check_common(c, k, defl));
     if (!psi || !eps_out) return fail(TSLOV_ERR_ARG, "null argument");
     tslov::BlockTangent t;
     CHK(block_args(c, nu, site, X, t));
-    return block_eps(c, t, (const ZD*)psi, k, eps_out, nullptr);
+    DeflSet d;
+    CHK(prepare_defl(c, defl, d));
+    return block_eps(c, t, (const ZD*)psi, k, eps_out, nullptr, d, d.l ? defl->lambda : nullptr);
+}
+
+tslov_status tslov_block_error_estimate(tslov_ctx* c, int nu, int site, const double* X, const void* psi, int k,
+                                        double* eps_out) {
+    return tslov_block_error_estimate_deflated(c, nu, site, X, psi, k, nullptr, eps_out);
 }
 
 tslov_status tslov_tune_k(tslov_ctx* c, int ncand, const int* k_outer, const int* k_inner, double trial_target,
@@ -2384,6 +2562,13 @@ tslov_status tslov_set_pair_ns(tslov_ctx* c, int ns) {
     if (!c) return fail(TSLOV_ERR_ARG, "null context");
     if (ns != 0 && ns != 1 && ns != 2 && ns != 4) return fail(TSLOV_ERR_ARG, "ns must be 0, 1, 2 or 4");
     c->pair_ns_forced = ns;
+    return TSLOV_OK;
+}
+
+tslov_status tslov_set_cg_operator(tslov_ctx* c, int form) {
+    if (!c) return fail(TSLOV_ERR_ARG, "null context");
+    if (form < tslov::kCgOpMulti || form > tslov::kCgOpTmarch) return fail(TSLOV_ERR_ARG, "form must be 0, 1, 2 or 3");
+    c->cg_op = form;
     return TSLOV_OK;
 }
 

@@ -185,18 +185,28 @@ struct CgRhs {
     int pad;
 };
 constexpr int kCgX = 0, kCgR = 1, kCgP = 2, kCgW = 3, kCgZ = 4, kCgFields = 5;
+// Operator forms of the shifted solves (all give the same hop sums; the partial sums
+// of |A p|^2 differ in their summation order): multi-right-hand-side site per thread
+// (default), colour split with two systems per block.
+constexpr int kCgOpMulti = 0, kCgOpColour = 1, kCgOpMfma = 2, kCgOpTmarch = 3;
 struct CgWork {
     ZD* f;        // [e][kCgFields] float64 SoA fields
     double* part; // [e][4][pstride]
     CgRhs* st;    // [e]
     size_t fe;
     int pstride;
+    int op;       // kCgOp*
     __host__ __device__ ZD* field(int e, int i) const { return f + ((size_t)e * kCgFields + i) * fe; }
     __host__ __device__ double* p(int e, int i) const { return part + ((size_t)e * 4 + i) * pstride; }
 };
 // right-hand sides of the 2l systems (Z_i psi, Z_i^H a_i), r = b, x = 0, |b|^2
 void launch_cg_rhs(const Geom& g, const ZD* psi, const ZD* eta, const ZD* pbar, const ZD* R, const ZD* L, const ZD* c,
                    const ZD* q, const double* sgn, int l, const CgWork& cw, hipStream_t st);
+// right-hand sides from canonical vectors (e < la: rhs_a + e 12 V; e >= la: rhs_b), r = b, x = 0, |b|^2
+void launch_cg_load(const Geom& g, const ZD* rhs_a, int la, const ZD* rhs_b, int nr, const CgWork& cw,
+                    hipStream_t st);
+// solutions x_e into out + e 12 V (canonical)
+void launch_cg_store(const Geom& g, int nr, const CgWork& cw, ZD* out, hipStream_t st);
 void launch_cg_start(const ZD* U, const Geom& g, double kappa, double mu, int nr, const CgWork& cw, hipStream_t st);
 // one CGNR iteration (check = 1: evaluate convergence afterwards)
 void launch_cg_iteration(const ZD* U, const Geom& g, double kappa, double mu, int nr, int it, int check, double tol,

@@ -38,7 +38,8 @@ EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links
            "tslov_timing_read", "tslov_kernel_bytes", "tslov_set_pair_ns", "tslov_get_pair_ns", "tslov_set_graphs", "tslov_set_apply_chunk",
            "tslov_get_apply_chunk", "tslov_overlap_grad", "tslov_tridiag_sign", "tslov_ritz_values",
            "tslov_set_diagnostics", "tslov_apply_h_noalloc", "tslov_set_nested", "tslov_block_sign",
-           "tslov_block_error_estimate", "tslov_tune_k", "tslov_overlap_solve", "tslov_physical_current"]
+           "tslov_block_error_estimate", "tslov_tune_k", "tslov_overlap_solve", "tslov_physical_current",
+           "tslov_set_cg_operator", "tslov_block_sign_deflated", "tslov_block_error_estimate_deflated"]
 
 
 class TslovLibraryMissing(ImportError):
@@ -129,6 +130,10 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_set_nested": ([vp, ci], ci),
         "tslov_block_sign": ([vp, ci, ci, ctypes.POINTER(cd), vp, vp, ci, vp, vp, ctypes.POINTER(InfoStruct)], ci),
         "tslov_block_error_estimate": ([vp, ci, ci, ctypes.POINTER(cd), vp, ci, ctypes.POINTER(cd)], ci),
+        "tslov_block_sign_deflated": ([vp, ci, ci, ctypes.POINTER(cd), vp, vp, ci, ctypes.POINTER(DeflationStruct), vp,
+                                       vp, ctypes.POINTER(InfoStruct)], ci),
+        "tslov_block_error_estimate_deflated": ([vp, ci, ci, ctypes.POINTER(cd), vp, ci,
+                                                 ctypes.POINTER(DeflationStruct), ctypes.POINTER(cd)], ci),
         "tslov_overlap_solve": ([vp, vp, vp, ci, ci, cd, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
         "tslov_physical_current": ([vp, ci, vp, ci, cd, ci, vp, vp, vp, ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
         "tslov_tune_k": ([vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci), cd, ctypes.POINTER(DeflationStruct),
@@ -143,6 +148,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_timing_read": ([vp, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
         "tslov_kernel_bytes": ([vp, ci], cd),
         "tslov_set_pair_ns": ([vp, ci], ci),
+        "tslov_set_cg_operator": ([vp, ci], ci),
         "tslov_set_graphs": ([vp, ci], ci),
         "tslov_set_apply_chunk": ([vp, ci], ci),
         "tslov_get_apply_chunk": ([vp, ctypes.POINTER(ci)], ci),
@@ -362,29 +368,43 @@ class Context:
         _check(self.lib, self.lib.tslov_tridiag_sign(self.handle, k, a, b, g, _ptr(c), ctypes.byref(info)))
         return c, Info.of(info)
 
-    def block_sign(self, nu: int, site: int, X, x2: torch.Tensor, k: int, x1: torch.Tensor | None = None):
+    def block_sign(self, nu: int, site: int, X, x2: torch.Tensor, k: int, x1: torch.Tensor | None = None,
+                   defl: "Deflation | None" = None):
         """TSL_k on B = [[H, dH], [0, H]] for U_nu(site) -> exp(i t X) U_nu(site) from (x1, x2)
-        (x1 None: zero); returns (y1, y2, Info): with x1 None, y1 ~ d sgn(H) x2 / dt."""
+        (x1 None: zero), optionally deflated by eigenpairs of H (App. E); returns
+        (y1, y2, Info): with x1 None, y1 ~ d sgn(H) x2 / dt."""
         import numpy as np
         x2 = self._spinor(x2, "x2")
         x1 = None if x1 is None else self._spinor(x1, "x1")
         Xa = np.ascontiguousarray(np.asarray(X, dtype=np.complex128).reshape(3, 3))
         y1, y2 = self._new_spinor(), self._new_spinor()
         info = InfoStruct()
-        _check(self.lib, self.lib.tslov_block_sign(self.handle, int(nu), int(site),
-                                                   Xa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(x1),
-                                                   _ptr(x2), int(k), _ptr(y1), _ptr(y2), ctypes.byref(info)))
+        Xp = Xa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if defl is None:
+            st = self.lib.tslov_block_sign(self.handle, int(nu), int(site), Xp, _ptr(x1), _ptr(x2), int(k), _ptr(y1),
+                                           _ptr(y2), ctypes.byref(info))
+        else:
+            st = self.lib.tslov_block_sign_deflated(self.handle, int(nu), int(site), Xp, _ptr(x1), _ptr(x2), int(k),
+                                                    ctypes.byref(defl.struct), _ptr(y1), _ptr(y2), ctypes.byref(info))
+        _check(self.lib, st)
         return y1, y2, Info.of(info)
 
-    def block_error_estimate(self, nu: int, site: int, X, psi: torch.Tensor, k: int) -> float:
-        """eps_B of the block process for the link parameter (eq. bA_error_est)."""
+    def block_error_estimate(self, nu: int, site: int, X, psi: torch.Tensor, k: int,
+                             defl: "Deflation | None" = None) -> float:
+        """eps_B of the block process for the link parameter (eq. bA_error_est), optionally
+        with the deflated block process applied twice (App. E)."""
         import numpy as np
         psi = self._spinor(psi, "psi")
         Xa = np.ascontiguousarray(np.asarray(X, dtype=np.complex128).reshape(3, 3))
         eps = ctypes.c_double()
-        _check(self.lib, self.lib.tslov_block_error_estimate(self.handle, int(nu), int(site),
-                                                             Xa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                                             _ptr(psi), int(k), ctypes.byref(eps)))
+        Xp = Xa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if defl is None:
+            st = self.lib.tslov_block_error_estimate(self.handle, int(nu), int(site), Xp, _ptr(psi), int(k),
+                                                     ctypes.byref(eps))
+        else:
+            st = self.lib.tslov_block_error_estimate_deflated(self.handle, int(nu), int(site), Xp, _ptr(psi), int(k),
+                                                              ctypes.byref(defl.struct), ctypes.byref(eps))
+        _check(self.lib, st)
         return eps.value
 
     def tune_k(self, k_outer, k_inner=None, trial_target: float = 1e-9, defl: "Deflation | None" = None,
@@ -489,6 +509,11 @@ class Context:
     def set_pair_ns(self, ns: int = 0):
         """Entries per workgroup of the batched colour-split pair kernels (0: timed pick)."""
         _check(self.lib, self.lib.tslov_set_pair_ns(self.handle, int(ns)))
+
+    def set_cg_operator(self, form: int = 3):
+        """Operator form of the deflated derivative's shifted solves: 0 multi-right-hand-side,
+        1 colour split, 2 matrix-core products, 3 t-march (default)."""
+        _check(self.lib, self.lib.tslov_set_cg_operator(self.handle, int(form)))
 
     def pair_ns(self):
         """The timed picks (forward, reverse); 0 while none is made."""

@@ -8,7 +8,11 @@ TSL of size k on B = [[H, dH], [0, H]] for one link parameter U_nu(x) -> exp(itX
   boundary (where the folded boundary sign must reach the tangent), to 1e-10 or
   10 sigma; at the 8^4 workload (k = 100) for one direction;
 * from a general source (x1, x2) against the oracle's block process;
-* eps_B against the oracle's (two block processes, the second from the first result).
+* eps_B against the oracle's (two block processes, the second from the first result);
+* the deflated block process (App. E) on 2^3x4 and 3^3x4 lattices with l = 10 and 20
+  eigenpairs of the dense H: both halves from a general source (x1, x2) and from
+  (0, psi), and the deflated eps_B, against oracle.blockderiv.deflated_block_sign
+  (eigenvector derivatives from the full dense spectrum), to 1e-10.
 """
 import numpy as np
 import pytest
@@ -75,4 +79,37 @@ def test_block_process_general_source_and_error_estimate():
     want = BD.eps_block(op, U, psi, k, nu, site, X)
     say(f"block process from (x1, x2), k={k}: errs {e1:.2e} {e2:.2e}; eps_B {eps:.10e} (oracle {want:.10e})")
     assert e1 < 1e-10 and e2 < 1e-10
+    assert abs(eps - want) < 1e-9 * want
+
+
+@pytest.mark.parametrize("dims,l,k", [((2, 2, 2, 4), 10, 24), ((3, 3, 3, 4), 20, 40)])
+def test_deflated_block_process_against_oracle(dims, l, k):
+    from paper_1604_08057_amd import Context
+    from oracle import deflation as DF
+    from oracle.wilson import dense_h
+    from synthetic import random_links
+    mass, mu = -2.0, 0.3
+    r = np.random.default_rng(41)
+    V = int(np.prod(dims))
+    U = random_links(dims, 0.5, r)
+    psi, x1 = z2_complex_source(V, r), z2_complex_source(V, r)
+    nu, site, X = 3, V - 2, GR.su3_direction(r)
+    op = WilsonOperator(dims, mass, mu)
+    dU = BD.link_direction_field(U, nu, site, X)
+    lam, R, L = DF.eigenpairs(dense_h(U, dims, mass, mu), l)
+    ctx = Context(dims, mass, mu)
+    ctx.set_links(dev(U))
+    defl = ctx.deflation(dev(R.T.reshape(l, V, 4, 3)), dev(L.T.reshape(l, V, 4, 3)), lam)
+    for src1 in (x1, None):
+        ref = BD.deflated_block_sign(op, U, dU, np.zeros_like(psi) if src1 is None else src1, psi, k, l, dims, mass, mu)
+        y1, y2, info = ctx.block_sign(nu, site, X, dev(psi), k, x1=None if src1 is None else dev(src1), defl=defl)
+        e1, e2 = rel(host(y1), ref["y1"]), rel(host(y2), ref["y2"])
+        say(f"deflated block process {dims} l={l} k={k} x1={'general' if src1 is not None else 'zero'}: "
+            f"errs {e1:.2e} {e2:.2e}, CG iterations {info.cg_iters}")
+        assert e1 < 1e-10 and e2 < 1e-10
+    eps = ctx.block_error_estimate(nu, site, X, dev(psi), k, defl=defl)
+    eps0 = ctx.block_error_estimate(nu, site, X, dev(psi), k)
+    ctx.close()
+    want = BD.eps_block_deflated(op, U, dU, psi, k, l, dims, mass, mu)
+    say(f"  deflated eps_B {eps:.10e} (oracle {want:.10e}; undeflated {eps0:.3e})")
     assert abs(eps - want) < 1e-9 * want

@@ -21,7 +21,12 @@ k = 400, one Z2 source psi and probe eta.
     Richardson-extrapolated central differences of the library forward, each side
     deflated by the exact eigenpairs of its own field, to 1e-6;
   - recompute = 20 against storing every Krylov vector (same S, dS/dU to 1e-12);
-  - the FP32-link variant of the same derivative, error against FP64 stated.
+  - the FP32-link variant of the same derivative, error against FP64 stated;
+* the four operator forms of the 40 shifted solves (multi-right-hand-side,
+  colour split, matrix-core and t-march) give the same derivative to 1e-9 (each
+  solve stops at relative residual 1e-13; the forms differ in the order of the
+  residual-norm sums and, on the matrix cores, of the link products), with the
+  time of each.
 """
 import numpy as np
 import pytest
@@ -155,3 +160,24 @@ def test_deflated_derivative_ward_fd_recompute(c5):
     c32.close()
     say(f"  fp32 links vs fp64: S {abs(S32 - S0) / abs(S0):.2e}, dU {rel(host(dU32), host(dU0)):.2e}, "
         f"dpsi {rel(host(dp32), host(dp0)):.2e}, D_ov psi {rel(host(dov32), host(dov0)):.2e}")
+
+
+def test_shifted_solve_operator_forms(c5):
+    wl, eig, U = c5["wl"], c5["eig"], c5["U"]
+    psi, eta = c5["psi"], c5["eta"]
+    ctx = _ctx(wl, U)
+    defl = ctx.deflation(dev(eig["R"]), dev(eig["L"]), eig["lam"])
+    res = {}
+    for form in (0, 1, 2, 3):
+        ctx.set_cg_operator(form)
+        S, dU, dp, dov, info = ctx.overlap_grad(dev(eta), dev(psi), wl.k, defl=defl, recompute=20)
+        res[form] = (S, host(dU), host(dp), info)
+        say(f"16^4 deflated derivative, operator form {form}: CG iterations {info.cg_iters}, "
+            f"solves {info.ms[4]:.0f} ms, total {info.ms[5]:.0f} ms")
+    ctx.close()
+    S1, G1, P1, _ = res[1]
+    for form in (0, 2, 3):
+        S0, G0, P0, _ = res[form]
+        eS, eG, eP = abs(S0 - S1) / abs(S1), rel(G0, G1), rel(P0, P1)
+        say(f"  form {form} vs colour split: S {eS:.2e} dU {eG:.2e} dpsi {eP:.2e}")
+        assert eS < 1e-12 and eG < 1e-9 and eP < 1e-9

@@ -5,7 +5,10 @@ reduced resolvents built from the full dense spectrum; the GPU solves the
 reduced-resolvent systems by CGNR to relative residual 1e-13.  Bar: S, dS/dU and
 dS/dpsi to 1e-10 relative (the float64 bar).
 Cases: l = 10 (k = 24) on 2^3x4 and l = 20 (k = 60) on 3^3x4, the latter also
-with the Krylov vectors regenerated in segments of 11 steps.
+with the Krylov vectors regenerated in segments of 11 steps; each with both
+operator forms of the shifted solves (multi-right-hand-side, colour split,
+matrix-core; the t-march form needs (x, y, z) volumes in multiples of 1024 sites and
+runs the colour split here).
 """
 import numpy as np
 import pytest
@@ -18,9 +21,10 @@ from synthetic import random_links, z2_complex_source
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("form", [0, 1, 2, 3])
 @pytest.mark.parametrize("dims,l,k,m", [((2, 2, 2, 4), 10, 24, 0), ((3, 3, 3, 4), 20, 60, 0),
                                         ((3, 3, 3, 4), 20, 60, 11)])
-def test_deflated_gradient(dims, l, k, m):
+def test_deflated_gradient(dims, l, k, m, form):
     from paper_1604_08057_amd import Context
     mass, mu = -2.0, 0.3
     r = np.random.default_rng(31)
@@ -32,9 +36,10 @@ def test_deflated_gradient(dims, l, k, m):
     G, S, pb = DF.deflated_gradient(U, psi, eta, k, dims, mass, mu, l)
     ctx = Context(dims, mass, mu)
     ctx.set_links(dev(U))
+    ctx.set_cg_operator(form)
     defl = ctx.deflation(dev(R.T.reshape(l, V, 4, 3)), dev(L.T.reshape(l, V, 4, 3)), lam)
     Sg, dU, dpsi, info = ctx.sign_grad(dev(eta), dev(psi), k, want_dpsi=True, defl=defl, recompute=m)
     ctx.close()
     eS, eG, eP = abs(Sg - S) / abs(S), rel(host(dU), G), rel(host(dpsi), pb)
-    say(f"deflated grad {dims} l={l} k={k} recompute={m}: S {eS:.2e} G {eG:.2e} dpsi {eP:.2e} cg iterations {info.cg_iters}")
+    say(f"deflated grad {dims} l={l} k={k} recompute={m} form={form}: S {eS:.2e} G {eG:.2e} dpsi {eP:.2e} cg iterations {info.cg_iters}")
     assert eS < 1e-10 and eG < 1e-10 and eP < 1e-10
