@@ -373,7 +373,8 @@ typedef struct {
  * the plain step; k_inner may be NULL for all-plain candidates):
  *   eps_out[i] = eps_A of eq. error_est of the (deflated, if defl) sign of phi, or,
  *                with dir, eps_B of eq. bA_error_est for that link direction and the
- *                sparse source (0, phi) (k_inner must be 0 and defl NULL/empty then);
+ *                sparse source (0, phi), of the deflated block process if defl
+ *                (tslov_block_error_estimate_deflated; k_inner must be 0 then);
  *   ms_out[i]  = wall time in ms of the first approximation (the sign of phi, or the
  *                first block process), taken on its second run so that allocation and
  *                first touch of a larger workspace do not count.
@@ -386,7 +387,7 @@ typedef struct {
  * parameters (the paper's cross-check, 20-30 random vectors, compared with eps_0 by
  * the caller).  The context's nested setting is unchanged on return.  Times depend on
  * the machine, so *chosen may differ between runs where candidates take similar time.
- * ERR_ARG for sizes out of range, a bad direction, or nested/deflated block mode. */
+ * ERR_ARG for sizes out of range, a bad direction, or nested block mode. */
 tslov_status tslov_tune_k(tslov_ctx* ctx, int ncand, const int* k_outer, const int* k_inner, double trial_target,
                           const tslov_deflation* defl, const tslov_link_direction* dir, int nrand, const void* rand,
                           double* eps_out, double* ms_out, int* chosen, double* cross_out);

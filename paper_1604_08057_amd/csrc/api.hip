@@ -1932,9 +1932,12 @@ tslov_status tune_candidate(tslov_ctx* c, const ZD* psi, int k, int k_inner, con
         return s;
     };
     if (t) {
+        DeflSet d;
+        CHK(prepare_defl(c, defl, d));
+        const double* lam = d.l ? defl->lambda : nullptr;
         double m0 = 0.0;
-        tslov_status s = block_eps(c, *t, psi, k, eps, &m0);
-        if (s == TSLOV_OK) s = block_eps(c, *t, psi, k, eps, ms);
+        tslov_status s = block_eps(c, *t, psi, k, eps, &m0, d, lam);
+        if (s == TSLOV_OK) s = block_eps(c, *t, psi, k, eps, ms, d, lam);
         return soft(s);
     }
     const int keep = c->nest_m;
@@ -2443,7 +2446,6 @@ tslov_status tslov_tune_k(tslov_ctx* c, int ncand, const int* k_outer, const int
         if (ki < 0 || ki > kMaxK) return fail(TSLOV_ERR_ARG, "every k_inner must be in [0, 1024]");
         if (dir && ki != 0) return fail(TSLOV_ERR_ARG, "the block-matrix process has no nested step (k_inner = 0)");
     }
-    if (dir && defl && defl->l != 0) return fail(TSLOV_ERR_ARG, "the block-matrix process takes no deflation");
     tslov::BlockTangent t{};
     if (dir) CHK(block_args(c, dir->nu, dir->site, dir->X, t));
     const size_t n12 = (size_t)12 * c->g.V;

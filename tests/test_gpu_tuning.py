@@ -6,7 +6,8 @@ On the trial vector (1, ..., 1):
   dense eigenpairs, and eps_B of the block-matrix derivative (eq. bA_error_est) for
   a temporal link across the boundary, to 1e-9 relative or 10 sigma (sigma the
   oracle's change under a permuted summation order: the nested step's inner
-  process on (T^2)^-1 amplifies rounding, 1e-6 relative at m = 16);
+  process on (T^2)^-1 amplifies rounding, 1e-6 relative at m = 16), and eps_B of
+  the deflated block process (App. E) on 2^3x4 with 10 dense eigenpairs;
 * the choice equals the oracle's selection rule applied to the library's own times
   and errors (the times are the machine's, so the rule is what can be compared);
 * the cross-check errors of three Z2 vectors at the chosen sizes against the oracle;
@@ -101,7 +102,7 @@ def test_tuning_run_block_derivative():
 
 
 def test_tuning_argument_errors():
-    """The block-matrix process has no nested step and takes no deflation; sizes out of range."""
+    """The block-matrix process has no nested step; sizes out of range."""
     from paper_1604_08057_amd import Context
     from paper_1604_08057_amd.tslov import ERR_ARG, TslovError
     wl = workload(1)
@@ -113,10 +114,30 @@ def test_tuning_argument_errors():
         with pytest.raises(TslovError) as e:
             ctx.tune_k(**kw)
         assert e.value.status == ERR_ARG
-    r = np.random.default_rng(1)
-    R = r.standard_normal((1, wl.volume, 4, 3)) + 0j
-    defl = ctx.deflation(dev(R), dev(R / np.vdot(R, R).real), np.array([0.5 + 0.1j]))
-    with pytest.raises(TslovError) as e:
-        ctx.tune_k([16], defl=defl, direction=(0, 3, X))
-    assert e.value.status == ERR_ARG
     ctx.close()
+
+
+def test_tuning_run_deflated_block_derivative():
+    """The block-matrix candidates with deflation (App. E): eps_B of the deflated block
+    process on (0, phi) against the oracle's, for each candidate."""
+    from paper_1604_08057_amd import Context
+    from oracle import blockderiv as BD
+    dims, mass, mu, l = (2, 2, 2, 4), -2.0, 0.3, 10
+    r = np.random.default_rng(43)
+    V = int(np.prod(dims))
+    U = random_links(dims, 0.5, r)
+    nu, site, X = 1, 3, GR.su3_direction(r)
+    lam, R, L = DF.eigenpairs(dense_h(U, dims, mass, mu), l)
+    ctx = Context(dims, mass, mu)
+    ctx.set_links(dev(U))
+    defl = ctx.deflation(dev(R.T.reshape(l, V, 4, 3)), dev(L.T.reshape(l, V, 4, 3)), lam)
+    ks = [12, 24]
+    res = ctx.tune_k(ks, trial_target=1.0, defl=defl, direction=(nu, site, X))
+    ctx.close()
+    op = WilsonOperator(dims, mass, mu)
+    dU = BD.link_direction_field(U, nu, site, X)
+    phi = np.ones((V, 4, 3), dtype=np.complex128)
+    for k, e in zip(ks, res["eps"]):
+        w = BD.eps_block_deflated(op, U, dU, phi, k, l, dims, mass, mu)
+        say(f"  tune deflated block 2^3x4 l={l} k={k}: eps_B {e:.10e} (oracle {w:.10e})")
+        assert _close(e, w)
