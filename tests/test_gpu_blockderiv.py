@@ -113,3 +113,45 @@ def test_deflated_block_process_against_oracle(dims, l, k):
     want = BD.eps_block_deflated(op, U, dU, psi, k, l, dims, mass, mu)
     say(f"  deflated eps_B {eps:.10e} (oracle {want:.10e}; undeflated {eps0:.3e})")
     assert abs(eps - want) < 1e-9 * want
+
+
+def test_deflated_block_process_errors():
+    """A deflated eigenvalue on the imaginary axis gives ERR_SIGN_UNDEFINED; a non-finite
+    direction or a link out of range ERR_ARG; one eigenpair (l = 1) against the oracle;
+    the operator form of the shifted solves must be 0..3."""
+    from paper_1604_08057_amd import Context
+    from paper_1604_08057_amd.tslov import ERR_ARG, ERR_SIGN_UNDEFINED, TslovError
+    from oracle import deflation as DF
+    from oracle.wilson import dense_h
+    from synthetic import random_links
+    dims, mass, mu = (2, 2, 2, 4), -2.0, 0.3
+    r = np.random.default_rng(47)
+    V = int(np.prod(dims))
+    U = random_links(dims, 0.5, r)
+    psi = z2_complex_source(V, r)
+    lam, R, L = DF.eigenpairs(dense_h(U, dims, mass, mu), 1)
+    ctx = Context(dims, mass, mu)
+    ctx.set_links(dev(U))
+    Rd, Ld = dev(R.T.reshape(1, V, 4, 3)), dev(L.T.reshape(1, V, 4, 3))
+    X = GR.su3_direction(r)
+    for bad in (np.array([0.0 + 0.2j]),):
+        with pytest.raises(TslovError) as e:
+            ctx.block_sign(1, 3, X, dev(psi), 16, defl=ctx.deflation(Rd, Ld, bad))
+        assert e.value.status == ERR_SIGN_UNDEFINED
+    defl = ctx.deflation(Rd, Ld, lam)
+    for nu, site, Xb in ((4, 3, X), (1, V, X), (1, 3, np.full((3, 3), np.nan, dtype=complex))):
+        with pytest.raises(TslovError) as e:
+            ctx.block_sign(nu, site, Xb, dev(psi), 16, defl=defl)
+        assert e.value.status == ERR_ARG
+    for form in (-1, 4):
+        with pytest.raises(TslovError) as e:
+            ctx.set_cg_operator(form)
+        assert e.value.status == ERR_ARG
+    y1, y2, info = ctx.block_sign(1, 3, X, dev(psi), 16, defl=defl)
+    ctx.close()
+    op = WilsonOperator(dims, mass, mu)
+    ref = BD.deflated_block_sign(op, U, BD.link_direction_field(U, 1, 3, X), np.zeros_like(psi), psi, 16, 1, dims,
+                                 mass, mu)
+    e1, e2 = rel(host(y1), ref["y1"]), rel(host(y2), ref["y2"])
+    say(f"deflated block process, one eigenpair: errs {e1:.2e} {e2:.2e}, CG iterations {info.cg_iters}")
+    assert e1 < 1e-10 and e2 < 1e-10
