@@ -106,3 +106,16 @@ def physical_current(U: np.ndarray, dims, mass: float, mu: float, xis: np.ndarra
         X = xis.reshape(len(xis), n).T               # columns xi_s
         W = (X @ (X.conj().T @ W)) / len(xis)        # (1/N) sum xi xi^H D^{-1} g5
     return exact_current(U, dims, mass, mu, W) + 1j * exact_current(U, dims, mass, mu, -1j * W)
+
+
+def current_deflated(U: np.ndarray, xis: np.ndarray, ks, dims, mass: float, mu: float, l: int, **kw):
+    """Estimator j_N (4, V) with the deflated TSL sign per source (Sec. 4.3 with Sec. 3):
+    each term the U(1) projection of the deflated link gradient (the eigenpairs' motion
+    included) of Re <g5 xi_s | sgn(H) | xi_s>, the l smallest-|lambda| eigenpairs of the
+    dense H deflated.  With l = n the sign is exact and so is each term."""
+    from .deflation import deflated_gradient
+    j = np.zeros((4, int(np.prod(dims))))
+    for xi, k in zip(xis, ks):
+        G, _, _ = deflated_gradient(U, xi, g5_source(xi), int(k), dims, mass, mu, l, **kw)
+        j += u1_projection(G, U)
+    return j / len(xis)

@@ -9,6 +9,9 @@
 * the divergence of the TSL estimator equals the mean of the per-sample Ward
   source terms (catches a sign or neighbour error in the projection or the
   divergence), and a planted sign error in one link direction breaks it;
+* the deflated estimator with every eigenpair deflated (l = n) equals the exact-sign
+  estimator for the same noise (Daleckii-Krein, matrix form), and with l < n its
+  divergence equals the mean Ward source terms of the deflated samples;
 * the physical current Tr(D_ov^{-1} dD_ov/dTheta) (eq. lat_vec_cur) equals
   Richardson-extrapolated central differences of log det D_ov (Jacobi's formula),
   its divergence vanishes at every site while the total current does not, and one
@@ -127,3 +130,33 @@ def test_physical_current_sample_ward_identity(gapped):
     dr, _ = CU.divergence(js.real, op)
     di, _ = CU.divergence(js.imag, op)
     assert np.abs(dr + 1j * di - want).max() < 1e-11 * np.abs(want).max()
+
+
+def test_deflated_estimator_full_deflation_is_exact(setup):
+    U, xis, op = setup
+    n = 12 * op.volume
+    j = CU.current_deflated(U, xis[:2], [8, 8], DIMS, MASS, MU, n)
+    A = sum(np.outer(xi.ravel(), CU.g5_source(xi).ravel().conj()) for xi in xis[:2]) / 2
+    jx = CU.exact_current(U, DIMS, MASS, MU, A=A)
+    assert np.abs(j - jx).max() < 1e-9 * np.abs(jx).max()
+
+
+def test_deflated_estimator_divergence_is_the_ward_source(setup):
+    """sum_nu [j(x, nu) - j(x - nu, nu)] = mean over samples of -Im eta^H y + Im psibar^H psi
+    at every site, y the deflated sign of xi and psibar its source gradient."""
+    from oracle import deflation as DF
+    from oracle.wilson import dense_h
+    U, xis, op = setup
+    l, k = 10, 12
+    j = CU.current_deflated(U, xis[:2], [k, k], DIMS, MASS, MU, l)
+    div, _ = CU.divergence(j, op)
+    H = dense_h(U, DIMS, MASS, MU)
+    lam, R, L = DF.eigenpairs(H, l)
+    rhs = np.zeros(op.volume)
+    for xi in xis[:2]:
+        eta = CU.g5_source(xi)
+        y = DF.deflated_sign(op, U, xi, k, lam, R, L)
+        _, _, pb = DF.deflated_gradient(U, xi, eta, k, DIMS, MASS, MU, l)
+        rhs += (-np.einsum("vab,vab->v", eta.conj(), y).imag + np.einsum("vab,vab->v", pb.conj(), xi).imag)
+    rhs /= 2
+    assert np.abs(div - rhs).max() < 1e-9 * np.abs(j).max()
