@@ -234,6 +234,18 @@ tslov_status tslov_sign_grad_batched(tslov_ctx* ctx, int nsrc, const void* eta, 
                                      double* S_out, void* dU_out, void* dpsi_out, void* y_out,
                                      tslov_info* infos);
 
+/* The batched derivative with deflation: for s < nsrc exactly what tslov_sign_grad
+ * computes with defl for that source alone (the same bits), S_s = Re <eta_s | the
+ * deflated sign of psi_s>, the derivative including the eigenpairs' motion.  The TSL
+ * parts run as one batch (as tslov_sign_grad_batched); the 2l shifted systems of
+ * every source run as one batched conjugate-gradient solve of 2l nsrc systems
+ * (infos[s].cg_iters = its iterations).  Arguments as tslov_sign_grad_batched, defl as
+ * tslov_sign_grad; defl = NULL or l = 0 is tslov_sign_grad_batched.  Workspace: three
+ * canonical spinors and 10 l float64 SoA fields per source beyond the batch's. */
+tslov_status tslov_sign_grad_batched_deflated(tslov_ctx* ctx, int nsrc, const void* eta, const void* psi,
+                                              const int* k, const tslov_deflation* defl, double* S_out,
+                                              void* dU_out, void* dpsi_out, void* y_out, tslov_info* infos);
+
 /* Stochastic estimator of the link-current trace (Sec. 4, the U(1) vector current
  * test, eq. lat_vec_cur without the inverse Dirac operator): with Z2 noise xi_s,
  *   j(x, nu) = (1/nsrc) sum_s dS_s/dTheta_{x,nu},  S_s = Re <g5 xi_s | sgn(H) | xi_s>,
@@ -252,6 +264,16 @@ tslov_status tslov_sign_grad_batched(tslov_ctx* ctx, int nsrc, const void* eta, 
  * Requesting it costs one extra assembly and source gradient per source. */
 tslov_status tslov_current_estimate(tslov_ctx* ctx, int nsrc, const void* xi, const int* k, double* j_out,
                                     double* div_out, double* tot_out, double* ward_out, tslov_info* infos);
+
+/* The same estimator with the deflated sign (Sec. 4.3 with Sec. 3): every term the U(1)
+ * projection of the deflated link gradient of Re <g5 xi_s | sgn(H) | xi_s>, the
+ * eigenpairs' motion included (as tslov_sign_grad_batched_deflated computes it), and
+ * the Ward residual of the deflated samples.  defl = NULL or l = 0 is
+ * tslov_current_estimate.  Workspace: per source one link gradient and (for the Ward
+ * check) three canonical spinors beyond tslov_sign_grad_batched_deflated's. */
+tslov_status tslov_current_estimate_deflated(tslov_ctx* ctx, int nsrc, const void* xi, const int* k,
+                                             const tslov_deflation* defl, double* j_out, double* div_out,
+                                             double* tot_out, double* ward_out, tslov_info* infos);
 
 /* Solve with the overlap operator (Sec. 1 eq. overlap, a = 1): x = D_ov^{-1} b
  * (adjoint = 0) or x = D_ov^{-dag} b (adjoint = 1), with D_ov = 1 + g5 sgn(H) and sgn(H)

@@ -172,6 +172,8 @@ struct tslov_ctx {
     int nest_m = 0;  // inner Krylov size of the nested projected-matrix step (0: plain)
     Buf blk;         // block-matrix process: 14 working fields, 2k basis fields, partials
     Buf bdefl;       // deflated block process: dH R_i, dR_i, the shifted solutions, temporaries, coefficients
+    Buf deflb;       // batched deflated derivative: projected sources, TSL source gradients and outputs
+    Buf curdefl;     // deflated current estimator: g5 xi, per-source dU, y, dpsi and U(1) projections
     Buf nestbuf;     // its inner basis, vectors and coefficients
     Buf U64, U32;
     Buf badflag;     // device int: a non-finite link element was seen
@@ -1501,85 +1503,127 @@ tslov_status cg_solve(tslov_ctx* c, int nr, const tslov::CgWork& cw, int* iters)
 
 // Derivative of the deflated S = Re eta^H [sum_i s_i Pi_i psi + TSL(P psi)], P = 1 - sum_i Pi_i,
 // with the eigenpairs moving with U (reduced-resolvent solves; see solve.hip).
-tslov_status deflated_grad(tslov_ctx* c, const ZD* eta, const ZD* psi, int k, const tslov_deflation* defl,
-                           int recompute, double* S_out, ZD* dU, ZD* dpsi, ZD* y, tslov_info* info) {
+// Deflated derivative of nsrc sources at once (eta, psi, dU, dpsi, y: contiguous per
+// source; k, S_out, infos: per source).  The TSL parts of all sources run as one
+// batch; the 2l shifted systems of every source run as one batched CGNR of 2l nsrc
+// systems, each system's arithmetic that of a solve of its own, so that a source gives
+// the bits of its single-source call.
+tslov_status deflated_grad_batched(tslov_ctx* c, int nsrc, const ZD* eta, const ZD* psi, const int* k,
+                                   const tslov_deflation* defl, int recompute, double* S_out, ZD* dU, ZD* dpsi,
+                                   ZD* y, tslov_info* infos) {
     const double t0 = now_ms();
     DeflSet d;
     CHK(prepare_defl(c, defl, d));
     const int l = d.l, V = c->g.V, nr = 2 * l;
-    const size_t n12 = (size_t)12 * V;
-    CHK(ensure(c->canon, (size_t)kCanonBufs * n12 * sizeof(ZD)));
-    ZD* psip = canon_buf(c, 0);
-    ZD* pbar = canon_buf(c, 1);
+    const size_t n12 = (size_t)12 * V, nfd = (size_t)12 * V * nsrc;
     const int nb = c->nblk();
-    CHK(ensure(c->deflx, (size_t)4 * l * sizeof(ZD) + (size_t)nb * 2 * l * sizeof(double)));
-    ZD* dRe = c->deflx.as<ZD>();
-    ZD* dRp = dRe + l;
-    ZD* qd = dRp + l;
-    ZD* mqd = qd + l;
-    double* xpart = (double*)(mqd + l);
-    tslov::launch_defl_coeffs(d.L, psi, V, l, d.part, d.c, c->st);          // c_i = L_i^H psi
-    tslov::launch_defl_project(d.R, psi, d.c, V, l, psip, c->st);           // psi_p = psi - R c
-    // TSL part on the projected source (link gradient into dU, source gradient into pbar)
-    double S_tsl = 0.0;
+    // canonical: projected sources, source gradients of the TSL part, TSL outputs (if y)
+    CHK(ensure(c->deflb, (2 + (y ? 1 : 0)) * nfd * sizeof(ZD)));
+    ZD* psip = c->deflb.as<ZD>();
+    ZD* pbar = psip + nfd;
+    ZD* ytsl = y ? pbar + nfd : nullptr;
+    // per source: c (L^H psi), R^H eta, R^H psibar_p, q, -q (l each); dot partials
+    CHK(ensure(c->deflx, (size_t)5 * l * nsrc * sizeof(ZD) + (size_t)nb * 2 * l * sizeof(double)));
+    ZD* cd = c->deflx.as<ZD>();
+    ZD* dRe = cd + (size_t)l * nsrc;
+    ZD* dRp = dRe + (size_t)l * nsrc;
+    ZD* qd = dRp + (size_t)l * nsrc;
+    ZD* mqd = qd + (size_t)l * nsrc;
+    double* xpart = (double*)(mqd + (size_t)l * nsrc);
+    auto at = [&](const ZD* b, int s) { return b + (size_t)s * n12; };
+    auto atm = [&](ZD* b, int s) { return b + (size_t)s * n12; };
+    auto cof = [&](ZD* b, int s) { return b + (size_t)s * l; };
+    for (int s = 0; s < nsrc; ++s) {
+        tslov::launch_defl_coeffs(d.L, at(psi, s), V, l, xpart, cof(cd, s), c->st);            // c_i = L_i^H psi
+        tslov::launch_defl_project(d.R, at(psi, s), cof(cd, s), V, l, atm(psip, s), c->st);    // psi_p = psi - R c
+    }
+    // TSL parts on the projected sources (link gradients into dU, source gradients into pbar)
+    std::vector<double> S_tsl(nsrc, 0.0);
     BatchRequest q;
-    q.nsrc = 1;
+    q.nsrc = nsrc;
     q.eta = eta;
     q.psi = psip;
-    q.k = &k;
-    q.S_out = &S_tsl;
+    q.k = k;
+    q.S_out = S_tsl.data();
     q.dU = dU;
     q.dpsi = pbar;
-    q.y = y ? canon_buf(c, 2) : nullptr;
-    q.infos = info;
+    q.y = ytsl;
+    q.infos = infos;
     q.recompute = recompute;
     CHK(run_batched(c, q));
-    // y = TSL(psi_p) + sum_i s_i c_i R_i
-    if (y) tslov::launch_defl_finish(d.R, d.c, d.sgn, canon_buf(c, 2), psi, V, l, 0, y, c->st);
-    tslov::launch_defl_coeffs(d.R, eta, V, l, xpart, dRe, c->st);          // R_i^H eta
-    tslov::launch_defl_coeffs(d.R, pbar, V, l, xpart, dRp, c->st);         // R_i^H psibar_p
-    std::vector<ZD> ch(l), de(l), dp(l), qh(l), mq(l);
+    for (int s = 0; s < nsrc; ++s) {
+        // y = TSL(psi_p) + sum_i s_i c_i R_i
+        if (y) tslov::launch_defl_finish(d.R, cof(cd, s), d.sgn, at(ytsl, s), nullptr, V, l, 0, atm(y, s), c->st);
+        tslov::launch_defl_coeffs(d.R, at(eta, s), V, l, xpart, cof(dRe, s), c->st);      // R_i^H eta
+        tslov::launch_defl_coeffs(d.R, at(pbar, s), V, l, xpart, cof(dRp, s), c->st);     // R_i^H psibar_p
+    }
+    const size_t nl = (size_t)l * nsrc;
+    std::vector<ZD> ch(nl), de(nl), dp(nl), qh(nl), mq(nl);
     std::vector<double> sg(l);
-    HIPCHK(hipMemcpyAsync(ch.data(), d.c, l * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipMemcpyAsync(de.data(), dRe, l * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipMemcpyAsync(dp.data(), dRp, l * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(ch.data(), cd, nl * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(de.data(), dRe, nl * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(dp.data(), dRp, nl * sizeof(ZD), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipMemcpyAsync(sg.data(), d.sgn, l * sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
-    double S = S_tsl;
-    for (int i = 0; i < l; ++i) {
-        qh[i] = ZD{sg[i] * de[i].re - dp[i].re, sg[i] * de[i].im - dp[i].im};   // R_i^H a_i
-        mq[i] = ZD{-qh[i].re, -qh[i].im};
-        S += sg[i] * (de[i].re * ch[i].re + de[i].im * ch[i].im);             // Re conj(R_i^H eta) c_i
-    }
-    HIPCHK(hipMemcpyAsync(qd, qh.data(), l * sizeof(ZD), hipMemcpyHostToDevice, c->st));
-    HIPCHK(hipMemcpyAsync(mqd, mq.data(), l * sizeof(ZD), hipMemcpyHostToDevice, c->st));
-    // shifted solves: e < l: (lambda_i - H) z = (1 - Pi_i) psi;  e >= l: (conj lambda_i - H^dag) z' = (1 - Pi_i^H) a_i
-    std::vector<ZD> sig(nr);
-    std::vector<double> msg(nr);
-    for (int e = 0; e < nr; ++e) {
-        const int i = e < l ? e : e - l;
-        const double lr = defl->lambda[2 * i], li = defl->lambda[2 * i + 1];
-        sig[e] = e < l ? ZD{lr, li} : ZD{lr, -li};
-        msg[e] = e < l ? 1.0 : -1.0;
-    }
+    std::vector<double> S(S_tsl);
+    for (int s = 0; s < nsrc; ++s)
+        for (int i = 0; i < l; ++i) {
+            const size_t m = (size_t)s * l + i;
+            qh[m] = ZD{sg[i] * de[m].re - dp[m].re, sg[i] * de[m].im - dp[m].im};   // R_i^H a_i
+            mq[m] = ZD{-qh[m].re, -qh[m].im};
+            S[s] += sg[i] * (de[m].re * ch[m].re + de[m].im * ch[m].im);         // Re conj(R_i^H eta) c_i
+        }
+    HIPCHK(hipMemcpyAsync(qd, qh.data(), nl * sizeof(ZD), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(mqd, mq.data(), nl * sizeof(ZD), hipMemcpyHostToDevice, c->st));
+    // shifted solves of source s, systems 2 l s + e: e < l: (lambda_i - H) z = (1 - Pi_i) psi;
+    // e >= l: (conj lambda_i - H^dag) z' = (1 - Pi_i^H) a_i
+    const int nt = nr * nsrc;
+    std::vector<ZD> sig(nt);
+    std::vector<double> msg(nt);
+    for (int s = 0; s < nsrc; ++s)
+        for (int e = 0; e < nr; ++e) {
+            const int i = e < l ? e : e - l;
+            const double lr = defl->lambda[2 * i], li = defl->lambda[2 * i + 1];
+            sig[(size_t)s * nr + e] = e < l ? ZD{lr, li} : ZD{lr, -li};
+            msg[(size_t)s * nr + e] = e < l ? 1.0 : -1.0;
+        }
     tslov::CgWork cw;
-    CHK(cg_setup(c, nr, sig.data(), msg.data(), cw));
-    tslov::launch_cg_rhs(c->g, psi, eta, pbar, d.R, d.L, d.c, qd, d.sgn, l, cw, c->st);
+    CHK(cg_setup(c, nt, sig.data(), msg.data(), cw));
+    auto view = [&](int s) {   // the source's 2l systems
+        tslov::CgWork v = cw;
+        v.f += (size_t)s * nr * tslov::kCgFields * cw.fe;
+        v.part += (size_t)s * nr * 4 * cw.pstride;
+        v.st += (size_t)s * nr;
+        return v;
+    };
+    for (int s = 0; s < nsrc; ++s)
+        tslov::launch_cg_rhs(c->g, at(psi, s), at(eta, s), at(pbar, s), d.R, d.L, cof(cd, s), cof(qd, s), d.sgn, l,
+                             view(s), c->st);
     int it = 0;
-    CHK(cg_solve(c, nr, cw, &it));
-    tslov::launch_cg_finish(c->g, d.R, d.L, d.c, l, cw, c->st);
-    tslov::launch_defl_force(c->g, c->kappa, c->mu, d.R, d.L, qd, l, cw, c->antiperiodic, dU, c->st);
-    // source gradient: psibar = psibar_p + sum_i q_i L_i
-    if (dpsi) tslov::launch_defl_project(d.L, pbar, mqd, V, l, dpsi, c->st);
+    CHK(cg_solve(c, nt, cw, &it));
+    for (int s = 0; s < nsrc; ++s) {
+        tslov::launch_cg_finish(c->g, d.R, d.L, cof(cd, s), l, view(s), c->st);
+        tslov::launch_defl_force(c->g, c->kappa, c->mu, d.R, d.L, cof(qd, s), l, view(s), c->antiperiodic,
+                                 dU + (size_t)s * 36 * V, c->st);
+        // source gradient: psibar = psibar_p + sum_i q_i L_i
+        if (dpsi) tslov::launch_defl_project(d.L, at(pbar, s), cof(mqd, s), V, l, atm(dpsi, s), c->st);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
-    if (S_out) *S_out = S;
-    if (info) {
-        info->cg_iters = it;
-        info->ms[4] = now_ms() - t0 - info->ms[5];
-        info->ms[5] = now_ms() - t0;
+    for (int s = 0; s < nsrc; ++s) {
+        if (S_out) S_out[s] = S[s];
+        if (infos) {
+            infos[s].cg_iters = it;
+            infos[s].ms[4] = now_ms() - t0 - infos[s].ms[5];
+            infos[s].ms[5] = now_ms() - t0;
+        }
     }
     return TSLOV_OK;
+}
+
+tslov_status deflated_grad(tslov_ctx* c, const ZD* eta, const ZD* psi, int k, const tslov_deflation* defl,
+                           int recompute, double* S_out, ZD* dU, ZD* dpsi, ZD* y, tslov_info* info) {
+    return deflated_grad_batched(c, 1, eta, psi, &k, defl, recompute, S_out, dU, dpsi, y, info);
 }
 
 }  // namespace
@@ -2018,7 +2062,7 @@ tslov_status tslov_create(const tslov_lattice_desc* d, void* stream, tslov_ctx**
 void tslov_destroy(tslov_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
-    for (Buf* b : {&c->trial, &c->solvebuf, &c->physbuf, &c->U64, &c->U32, &c->badflag, &c->nestbuf, &c->blk, &c->bdefl, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
+    for (Buf* b : {&c->trial, &c->solvebuf, &c->physbuf, &c->U64, &c->U32, &c->badflag, &c->nestbuf, &c->blk, &c->bdefl, &c->deflb, &c->curdefl, &c->sbmap, &c->opf, &c->basisV, &c->basisW, &c->basisA, &c->basisB, &c->abarS, &c->sbarS,
                    &c->fields, &c->part, &c->coefmem, &c->dense, &c->denseInt, &c->densePart, &c->denseDelta,
                    &c->gpart, &c->gsrc, &c->bout, &c->wardp, &c->canon, &c->deflw, &c->deflx, &c->cgf, &c->cgp,
                    &c->cgs, &c->ckpt})
@@ -2196,6 +2240,21 @@ tslov_status tslov_sign_grad_batched(tslov_ctx* c, int nsrc, const void* eta, co
     return run_batched(c, q);
 }
 
+tslov_status tslov_sign_grad_batched_deflated(tslov_ctx* c, int nsrc, const void* eta, const void* psi, const int* k,
+                                              const tslov_deflation* defl, double* S_out, void* dU_out,
+                                              void* dpsi_out, void* y_out, tslov_info* infos) {
+    if (!defl || defl->l == 0)
+        return tslov_sign_grad_batched(c, nsrc, eta, psi, k, S_out, dU_out, dpsi_out, y_out, infos);
+    CHK(check_common(c, 1, defl));
+    if (nsrc < 1 || nsrc > kMaxSources) return fail(TSLOV_ERR_ARG, "nsrc must be in [1, 2^20]");
+    if (!eta || !psi || !k || !dU_out) return fail(TSLOV_ERR_ARG, "null argument");
+    for (int s = 0; s < nsrc; ++s)
+        if (k[s] < 1 || k[s] > kMaxK) return fail(TSLOV_ERR_ARG, "every k must be in [1, 1024]");
+    if (infos) std::memset(infos, 0, (size_t)nsrc * sizeof(tslov_info));
+    return deflated_grad_batched(c, nsrc, (const ZD*)eta, (const ZD*)psi, k, defl, 0, S_out, (ZD*)dU_out,
+                                 (ZD*)dpsi_out, (ZD*)y_out, infos);
+}
+
 tslov_status tslov_current_estimate(tslov_ctx* c, int nsrc, const void* xi, const int* k, double* j_out,
                                     double* div_out, double* tot_out, double* ward_out, tslov_info* infos) {
     if (!c) return fail(TSLOV_ERR_ARG, "null context");
@@ -2217,6 +2276,65 @@ tslov_status tslov_current_estimate(tslov_ctx* c, int nsrc, const void* xi, cons
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
     if (ward_out) *ward_out = q.g_max > 0.0 ? q.ward_max / q.g_max : q.ward_max;
+    return TSLOV_OK;
+}
+
+tslov_status tslov_current_estimate_deflated(tslov_ctx* c, int nsrc, const void* xi, const int* k,
+                                             const tslov_deflation* defl, double* j_out, double* div_out,
+                                             double* tot_out, double* ward_out, tslov_info* infos) {
+    if (!defl || defl->l == 0) return tslov_current_estimate(c, nsrc, xi, k, j_out, div_out, tot_out, ward_out, infos);
+    CHK(check_common(c, 1, defl));
+    if (nsrc < 1 || nsrc > kMaxSources) return fail(TSLOV_ERR_ARG, "nsrc must be in [1, 2^20]");
+    if (!xi || !k || !j_out) return fail(TSLOV_ERR_ARG, "null argument");
+    for (int s = 0; s < nsrc; ++s)
+        if (k[s] < 1 || k[s] > kMaxK) return fail(TSLOV_ERR_ARG, "every k must be in [1, 1024]");
+    const Geom& g = c->g;
+    const int V = g.V;
+    const size_t n12 = (size_t)12 * V, nfd = n12 * nsrc;
+    // eta_s = g5 xi_s, per-source dU, y and dpsi (the latter two for the Ward check)
+    const int want_w = ward_out ? 1 : 0;
+    CHK(ensure(c->curdefl, (nfd * (1 + 2 * want_w) + (size_t)nsrc * 36 * V) * sizeof(ZD) +
+                               (want_w ? (size_t)nsrc * 4 * g.ldv * sizeof(double) : 0)));
+    ZD* eta = c->curdefl.as<ZD>();
+    ZD* dU = eta + nfd;
+    ZD* y = want_w ? dU + (size_t)nsrc * 36 * V : nullptr;
+    ZD* dp = want_w ? y + nfd : nullptr;
+    double* gsrc = want_w ? (double*)(dp + nfd) : nullptr;
+    const ZD* xs = (const ZD*)xi;
+    for (int s = 0; s < nsrc; ++s) tslov::launch_g5_scale(xs + (size_t)s * n12, ZD{1.0, 0.0}, V, eta + (size_t)s * n12, c->st);
+    if (infos) std::memset(infos, 0, (size_t)nsrc * sizeof(tslov_info));
+    CHK(deflated_grad_batched(c, nsrc, eta, xs, k, defl, 0, nullptr, dU, dp, y, infos));
+    tslov::launch_u1_projection(g, c->U64.as<ZD>(), dU, nsrc, c->antiperiodic, gsrc, j_out, 0, c->st);
+    if (want_w) {
+        // per-sample Ward residuals, in chunks of kMaxBatch entries
+        double wmax = 0.0, gmax = 0.0;
+        const int nb = c->nblk();
+        for (int s0 = 0; s0 < nsrc; s0 += tslov::kMaxBatch) {
+            const int n = std::min(nsrc - s0, tslov::kMaxBatch);
+            SrcList L{};
+            L.n = n;
+            for (int e = 0; e < n; ++e) {
+                L.slot[e] = e;
+                L.src[e] = s0 + e;
+                L.k[e] = k[s0 + e];
+            }
+            CHK(ensure(c->wardp, (size_t)n * nb * 2 * sizeof(double)));
+            CHK(ensure_host_part(c, 2 * n * nb));
+            tslov::launch_ward(g, gsrc + (size_t)s0 * 4 * g.ldv, L, xs, y + (size_t)s0 * n12, dp + (size_t)s0 * n12,
+                               c->wardp.as<double>(), c->st);
+            HIPCHK(hipMemcpyAsync(c->host_part, c->wardp.p, (size_t)n * nb * 2 * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->st));
+            HIPCHK(hipStreamSynchronize(c->st));
+            for (int i = 0; i < n * nb; ++i) {
+                wmax = std::max(wmax, c->host_part[2 * i]);
+                gmax = std::max(gmax, c->host_part[2 * i + 1]);
+            }
+        }
+        *ward_out = gmax > 0.0 ? wmax / gmax : wmax;
+    }
+    tslov::launch_current_finish(g, j_out, 1.0 / nsrc, div_out, tot_out, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
     return TSLOV_OK;
 }
 

@@ -213,6 +213,10 @@ void launch_cg_iteration(const ZD* U, const Geom& g, double kappa, double mu, in
                          const CgWork& cw, hipStream_t st);
 // projections (1 - Pi_i) / (1 - Pi_i^H) of the solutions and the conj(c_i) scaling
 void launch_cg_finish(const Geom& g, const ZD* R, const ZD* L, const ZD* c, int l, const CgWork& cw, hipStream_t st);
+// U(1) projections -Im tr(G_e^H U) of nsrc canonical link gradients dU[e] into gsrc[e][4][ldv]
+// (nullable) and summed over e into jsum[4][V] (accumulate: added to its contents)
+void launch_u1_projection(const Geom& g, const ZD* U64, const ZD* dU, int nsrc, int antiperiodic, double* gsrc,
+                          double* jsum, int accumulate, hipStream_t st);
 // dU += eigenpair-motion terms (canonical dU, boundary sign undone)
 void launch_defl_force(const Geom& g, double kappa, double mu, const ZD* R, const ZD* L, const ZD* q, int l,
                        const CgWork& cw, int antiperiodic, ZD* dU, hipStream_t st);

@@ -814,7 +814,39 @@ __global__ __launch_bounds__(kBlock) void k_defl_force(Geom g, double kappa, dou
     }
 }
 
+// U(1) projections g_e(x, nu) = -Im tr(G_e^H U_nu(x)) of canonical link gradients
+// dU[e][nu][x][3][3] (the boundary sign undone, so U is the caller's field: U64 times
+// the folded sign), into gsrc[e][nu][ldv] (nullable) and, summed over the sources in
+// order, into jsum[nu][V] (added to its contents with accumulate).
+__global__ __launch_bounds__(kBlock) void k_u1_projection(Geom g, const ZD* __restrict__ U64, const ZD* __restrict__ dU,
+                                                          int nsrc, int antiperiodic, double* __restrict__ gsrc,
+                                                          double* __restrict__ jsum, int accumulate) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const int nu = blockIdx.y;
+    if (s >= g.V) return;
+    const double sign = (nu == 3 && antiperiodic && s / (g.nx * g.ny * g.nz) == g.nt - 1) ? -1.0 : 1.0;
+    ZD u[9];
+#pragma unroll
+    for (int ab = 0; ab < 9; ++ab) u[ab] = sign * U64[(size_t)(nu * 9 + ab) * g.ldv + s];
+    double tot = accumulate ? jsum[(size_t)nu * g.V + s] : 0.0;
+    for (int e = 0; e < nsrc; ++e) {
+        const ZD* G = dU + (((size_t)e * 4 + nu) * g.V + s) * 9;
+        double im = 0.0;
+#pragma unroll
+        for (int ab = 0; ab < 9; ++ab) im += cjmul(G[ab], u[ab]).im;
+        if (gsrc) gsrc[((size_t)e * 4 + nu) * g.ldv + s] = -im;
+        tot += -im;
+    }
+    jsum[(size_t)nu * g.V + s] = tot;
+}
+
 // ---------------------------------------------------------------- launchers
+void launch_u1_projection(const Geom& g, const ZD* U64, const ZD* dU, int nsrc, int antiperiodic, double* gsrc,
+                          double* jsum, int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_u1_projection, dim3(grid_for(g.V), 4), dim3(kBlock), 0, st, g, U64, dU, nsrc, antiperiodic,
+                       gsrc, jsum, accumulate);
+}
+
 void launch_cg_rhs(const Geom& g, const ZD* psi, const ZD* eta, const ZD* pbar, const ZD* R, const ZD* L, const ZD* c,
                    const ZD* q, const double* sgn, int l, const CgWork& cw, hipStream_t st) {
     const int nb = grid_for(g.V);

@@ -39,7 +39,8 @@ EXPORTS = ["tslov_create", "tslov_destroy", "tslov_last_error", "tslov_set_links
            "tslov_get_apply_chunk", "tslov_overlap_grad", "tslov_tridiag_sign", "tslov_ritz_values",
            "tslov_set_diagnostics", "tslov_apply_h_noalloc", "tslov_set_nested", "tslov_block_sign",
            "tslov_block_error_estimate", "tslov_tune_k", "tslov_overlap_solve", "tslov_physical_current",
-           "tslov_set_cg_operator", "tslov_block_sign_deflated", "tslov_block_error_estimate_deflated"]
+           "tslov_set_cg_operator", "tslov_block_sign_deflated", "tslov_block_error_estimate_deflated",
+           "tslov_sign_grad_batched_deflated", "tslov_current_estimate_deflated"]
 
 
 class TslovLibraryMissing(ImportError):
@@ -149,6 +150,10 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "tslov_kernel_bytes": ([vp, ci], cd),
         "tslov_set_pair_ns": ([vp, ci], ci),
         "tslov_set_cg_operator": ([vp, ci], ci),
+        "tslov_sign_grad_batched_deflated": ([vp, ci, vp, vp, ctypes.POINTER(ci), ctypes.POINTER(DeflationStruct),
+                                              ctypes.POINTER(cd), vp, vp, vp, ctypes.POINTER(InfoStruct)], ci),
+        "tslov_current_estimate_deflated": ([vp, ci, vp, ctypes.POINTER(ci), ctypes.POINTER(DeflationStruct), vp, vp,
+                                             vp, ctypes.POINTER(cd), ctypes.POINTER(InfoStruct)], ci),
         "tslov_set_graphs": ([vp, ci], ci),
         "tslov_set_apply_chunk": ([vp, ci], ci),
         "tslov_get_apply_chunk": ([vp, ctypes.POINTER(ci)], ci),
@@ -311,9 +316,10 @@ class Context:
         return x.contiguous()
 
     def sign_grad_batched(self, eta: torch.Tensor, psi: torch.Tensor, ks, want_dpsi: bool = False,
-                          want_y: bool = False):
+                          want_y: bool = False, defl: "Deflation | None" = None):
         """Per-source S_s, dS_s/dU and (optionally) dS_s/dpsi_s for a batch (nsrc, V, 4, 3);
-        with want_y also every y_s = TSL(psi_s) (a fifth value)."""
+        with want_y also every y_s = TSL(psi_s) (a fifth value); with defl each source as
+        the deflated single-source derivative."""
         psi = self._sources(psi, "psi")
         eta = self._sources(eta, "eta")
         n = psi.shape[0]
@@ -325,15 +331,23 @@ class Context:
         dU = torch.empty((n, 4, self.volume, 3, 3), dtype=torch.complex128, device=self.device)
         dpsi = torch.empty_like(psi) if want_dpsi else None
         y = torch.empty_like(psi) if want_y else None
-        _check(self.lib, self.lib.tslov_sign_grad_batched(self.handle, n, _ptr(eta), _ptr(psi), k, S, _ptr(dU),
-                                                          _ptr(dpsi), _ptr(y), infos))
+        if defl is None:
+            st = self.lib.tslov_sign_grad_batched(self.handle, n, _ptr(eta), _ptr(psi), k, S, _ptr(dU), _ptr(dpsi),
+                                                  _ptr(y), infos)
+        else:
+            st = self.lib.tslov_sign_grad_batched_deflated(self.handle, n, _ptr(eta), _ptr(psi), k,
+                                                           ctypes.byref(defl.struct), S, _ptr(dU), _ptr(dpsi),
+                                                           _ptr(y), infos)
+        _check(self.lib, st)
         if want_y:
             return list(S), dU, dpsi, [Info.of(i) for i in infos], y
         return list(S), dU, dpsi, [Info.of(i) for i in infos]
 
-    def current_estimate(self, xi: torch.Tensor, ks, divergence: bool = True, ward: bool = True):
+    def current_estimate(self, xi: torch.Tensor, ks, divergence: bool = True, ward: bool = True,
+                         defl: "Deflation | None" = None):
         """j (4, V) = mean over sources of the U(1) link derivatives of Re <g5 xi|sgn(H)|xi>,
-        with divergence and total current per site and the per-sample Ward residual."""
+        with divergence and total current per site and the per-sample Ward residual;
+        with defl the deflated sign (the eigenpairs' motion included)."""
         xi = self._sources(xi, "xi")
         n = xi.shape[0]
         if len(ks) != n:
@@ -344,8 +358,13 @@ class Context:
         tot = torch.empty(self.volume, dtype=torch.float64, device=self.device) if divergence else None
         w = ctypes.c_double()
         infos = (InfoStruct * n)()
-        _check(self.lib, self.lib.tslov_current_estimate(self.handle, n, _ptr(xi), k, _ptr(j), _ptr(div), _ptr(tot),
-                                                         ctypes.byref(w) if ward else None, infos))
+        wp = ctypes.byref(w) if ward else None
+        if defl is None:
+            st = self.lib.tslov_current_estimate(self.handle, n, _ptr(xi), k, _ptr(j), _ptr(div), _ptr(tot), wp, infos)
+        else:
+            st = self.lib.tslov_current_estimate_deflated(self.handle, n, _ptr(xi), k, ctypes.byref(defl.struct),
+                                                          _ptr(j), _ptr(div), _ptr(tot), wp, infos)
+        _check(self.lib, st)
         return j, div, tot, (w.value if ward else None), [Info.of(i) for i in infos]
 
     def lanczos_matrix(self, psi: torch.Tensor, k: int):

@@ -14,7 +14,9 @@
   divergence and total current to 1e-10 of max |j|, the per-sample Ward
   residual below 1e-10;
 * more sources than one launch serves (70 > 64): the estimator accumulates over
-  consecutive groups and still matches the oracle.
+  consecutive groups and still matches the oracle;
+* the deflated estimator (10 eigenpairs of the dense H, the eigenpairs' motion in
+  every term) against the oracle's, and its Ward residual over 70 sources.
 """
 import numpy as np
 import pytest
@@ -176,3 +178,36 @@ def test_current_estimate_many_groups():
     ks = list(r.integers(4, 13, size=n))
     say(f"current estimator 2x2x2x4, {n} sources")
     _current_case(dims, -2.0, 0.3, U, _sources(n, 32, 46), ks, "70 sources")
+
+
+@pytest.mark.parametrize("nsrc", [3, 70])
+def test_current_estimate_deflated(nsrc):
+    """The deflated estimator (l = 10 on 2^3x4) against oracle.current.current_deflated:
+    j, divergence and total current to 1e-10, the deflated samples' Ward residual below
+    1e-9; 70 sources run the Ward check in two chunks."""
+    from oracle import deflation as DF
+    from oracle.wilson import dense_h
+    dims, mass, mu, l = (2, 2, 2, 4), -2.0, 0.3, 10
+    r = np.random.default_rng(49)
+    U = random_links(dims, 0.5, r)
+    xis = _sources(nsrc, 32, 50)
+    ks = [int(v) for v in r.integers(8, 25, size=nsrc)]
+    lam, R, L = DF.eigenpairs(dense_h(U, dims, mass, mu), l)
+    op = WilsonOperator(dims, mass, mu)
+    sub = min(nsrc, 6)   # the oracle's deflated gradients take about a second per source
+    jr = CU.current_deflated(U, xis[:sub], ks[:sub], dims, mass, mu, l)
+    dr, tr = CU.divergence(jr, op)
+    ctx = _ctx(dims, mass, mu, U)
+    defl = ctx.deflation(dev(R.T.reshape(l, 32, 4, 3)), dev(L.T.reshape(l, 32, 4, 3)), lam)
+    j, div, tot, ward, infos = ctx.current_estimate(dev(xis[:sub]), ks[:sub], defl=defl)
+    scale = np.abs(jr).max()
+    ej = rel(host(j), jr)
+    ed, et = np.abs(host(div) - dr).max() / scale, np.abs(host(tot) - tr).max() / scale
+    say(f"  deflated current ({sub} sources): j {ej:.2e} div {ed:.2e} tot {et:.2e} ward {ward:.2e} "
+        f"cg iterations {infos[0].cg_iters}")
+    assert ej < 1e-10 and ed < 1e-10 and et < 1e-10 and ward < 1e-9
+    if nsrc > sub:
+        j2, _, _, ward2, _ = ctx.current_estimate(dev(xis), ks, defl=defl)
+        say(f"  deflated current ({nsrc} sources): Ward residual {ward2:.2e}")
+        assert ward2 < 1e-9
+    ctx.close()
