@@ -325,6 +325,30 @@ __device__ __forceinline__ void recon1_add(Z<R> (&acc)[4], const Z<R> (&o)[2], R
     else { acc[2] = acc[2] - l2; acc[3] = acc[3] - l3; }
 }
 
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// u . h for one link row and the colour vector of one half spin, as a fixed chain
+// of fused multiply-adds.  Written out so that the result does not depend on how
+// the compiler would contract a plain expression, which varies with the code that
+// produced h (in registers from the projection, or read back from LDS): every hop
+// form that uses it gives the same bits.
+template <typename R>
+__device__ __forceinline__ Z<R> row_dot(const Z<R> (&u)[3], Z<R> h0, Z<R> h1, Z<R> h2) {
+    R re = u[0].re * h0.re, im = u[0].re * h0.im;
+    re = fmadd(-u[0].im, h0.im, re);
+    im = fmadd(u[0].im, h0.re, im);
+    re = fmadd(u[1].re, h1.re, re);
+    im = fmadd(u[1].re, h1.im, im);
+    re = fmadd(-u[1].im, h1.im, re);
+    im = fmadd(u[1].im, h1.re, im);
+    re = fmadd(u[2].re, h2.re, re);
+    im = fmadd(u[2].re, h2.im, im);
+    re = fmadd(-u[2].im, h2.im, re);
+    im = fmadd(u[2].im, h2.re, im);
+    return mk<R>(re, im);
+}
+
 // acc += coef * [(1 + S g_NU) u psi]_a with u given by its row a (forward hop,
 // u = U_nu(x)) or by conj of its column a (backward hop, u = U_nu(x-nu)^dag).
 template <int NU, int S, typename R>
@@ -332,7 +356,7 @@ __device__ __forceinline__ void hop1(Z<R> (&acc)[4], const Z<R> (&urow)[3], cons
     Z<R> h[2][3], o[2];
     project<NU, S>(psi, h);
 #pragma unroll
-    for (int s = 0; s < 2; ++s) o[s] = urow[0] * h[s][0] + urow[1] * h[s][1] + urow[2] * h[s][2];
+    for (int s = 0; s < 2; ++s) o[s] = row_dot(urow, h[s][0], h[s][1], h[s][2]);
     recon1_add<NU, S>(acc, o, coef);
 }
 

@@ -322,6 +322,96 @@ __device__ __forceinline__ void hop_all_pairN(Z<R> (&acca)[NS][4], Z<R> (&accb)[
     }
 }
 
+// Colour-split hops of one entry with the neighbour spinors shared through LDS.
+// Thread (a, l) loads only colour a of the four neighbour spinors of a direction
+// (four spins each), projects it to its two half-spinor components and publishes
+// them; after a barrier it reads the three colours of each half spinor of its own
+// site and applies its link row.  A neighbour value thus passes the vector L1 once
+// per block, not once per colour wavefront.  Every half-spinor component, product
+// and sum is formed by the operations of hop_dir_pair1 and hop_dir_pairN in the same
+// order (the link-row products by row_dot's fixed chain), so the accumulators get
+// the same bits as with those.  All threads of the block must call it (`in`
+// false for sites past the volume: no loads, their slots are not read).
+template <typename R>
+struct HopX {
+    Z<R> h[4][2][3][kSites];   // hop (A forward, B forward, A backward, B backward), half spin, colour, site
+};
+
+template <int NU, int S, typename R>
+__device__ __forceinline__ void hop1_x(Z<R> (&acc)[4], const Z<R> (&urow)[3], const Z<R> (&hx)[2][3][kSites], int l,
+                                       R coef) {
+    Z<R> h[2][3], o[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) h[s][c] = hx[s][c][l];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) o[s] = row_dot(urow, h[s][0], h[s][1], h[s][2]);
+    recon1_add<NU, S>(acc, o, coef);
+}
+
+template <int NU, typename R, typename RL>
+__device__ __forceinline__ void hop_dir_pair_x(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<RL>* __restrict__ U,
+                                               const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
+                                               const Geom& g, int s, int a, int l, bool in, const Nbr& n, R ep,
+                                               R em, HopX<R>& x) {
+    const R up = (NU == 3) ? ep : R(1), dn = (NU == 3) ? em : R(1);
+    Z<R> uf[3], ub[3];
+    if (in) {
+        const FieldBase ra = field_base(fa), rb = field_base(fb);
+        const unsigned yf = (unsigned)n.fwd[NU], yb = (unsigned)n.bwd[NU];
+        Z<R> p[4][4];   // colour a of A(x+nu), B(x+nu), A(x-nu), B(x-nu)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            p[0][sp] = fload<R>(ra, g.ldv, sp * 3 + a, yf);
+            p[1][sp] = fload<R>(rb, g.ldv, sp * 3 + a, yf);
+            p[2][sp] = fload<R>(ra, g.ldv, sp * 3 + a, yb);
+            p[3][sp] = fload<R>(rb, g.ldv, sp * 3 + a, yb);
+        }
+        load_row(uf, U, g.ldv, NU, a, s);
+        load_col_conj(ub, U, g.ldv, NU, a, n.bwd[NU]);
+        Z<R> h0, h1;
+        project_col<NU, +1>(p[0][0], p[0][1], p[0][2], p[0][3], h0, h1);
+        x.h[0][0][a][l] = h0;
+        x.h[0][1][a][l] = h1;
+        project_col<NU, +1>(p[1][0], p[1][1], p[1][2], p[1][3], h0, h1);
+        x.h[1][0][a][l] = h0;
+        x.h[1][1][a][l] = h1;
+        project_col<NU, -1>(p[2][0], p[2][1], p[2][2], p[2][3], h0, h1);
+        x.h[2][0][a][l] = h0;
+        x.h[2][1][a][l] = h1;
+        project_col<NU, -1>(p[3][0], p[3][1], p[3][2], p[3][3], h0, h1);
+        x.h[3][0][a][l] = h0;
+        x.h[3][1][a][l] = h1;
+    }
+    __syncthreads();
+    if (in) {
+        hop1_x<NU, +1>(acca, uf, x.h[0], l, up);
+        hop1_x<NU, +1>(accb, uf, x.h[1], l, dn);
+        hop1_x<NU, -1>(acca, ub, x.h[2], l, dn);
+        hop1_x<NU, -1>(accb, ub, x.h[3], l, up);
+    }
+    __syncthreads();   // the next direction overwrites the slots
+}
+
+template <typename R, typename RL>
+__device__ __forceinline__ void hop_all_pair_x(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<RL>* __restrict__ U,
+                                               const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
+                                               const Geom& g, int s, int a, R ep, R em, HopX<R>& x) {
+    const int l = threadIdx.x % kSites;
+    const bool in = s < g.V;
+    const Nbr n = neighbours(g, in ? s : 0);
+#pragma unroll 1
+    for (int nu = 0; nu < 4; ++nu) {
+        switch (nu) {
+            case 0: hop_dir_pair_x<0>(acca, accb, U, fa, fb, g, s, a, l, in, n, ep, em, x); break;
+            case 1: hop_dir_pair_x<1>(acca, accb, U, fa, fb, g, s, a, l, in, n, ep, em, x); break;
+            case 2: hop_dir_pair_x<2>(acca, accb, U, fa, fb, g, s, a, l, in, n, ep, em, x); break;
+            default: hop_dir_pair_x<3>(acca, accb, U, fa, fb, g, s, a, l, in, n, ep, em, x); break;
+        }
+    }
+}
+
 // Block-uniform reads of the stop flags of NS entries (1 for an entry past the
 // end of the list), with one pair of barriers for all of them.
 template <int NS>
@@ -980,7 +1070,11 @@ __global__ __launch_bounds__(kCBlock) void k_fwd_pair_ms(const Z<RL>* __restrict
         zero1(acca[q]);
         zero1(accb[q]);
     }
-    if (s < g.V) {
+    if constexpr (NS == 1) {
+        __shared__ HopX<R> x;
+        hop_all_pair_x(acca[0], accb[0], U, rin[0], sin[0], g, s, a, (R)emu, (R)(1.0 / emu), x);
+        mem_fence_compiler();
+    } else if (s < g.V) {
         hop_all_pairN<NS>(acca, accb, U, rin, sin, live, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu));
         mem_fence_compiler();
     }
@@ -1574,7 +1668,11 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb_ms(const Z<RL>* __restrict__
         zero1(accs[q]);
         zero1(accr[q]);
     }
-    if (s < g.V) {
+    if constexpr (NS == 1) {
+        __shared__ HopX<R> x;
+        hop_all_pair_x(accs[0], accr[0], U, fs[0], fr[0], g, s, a, (R)emu, (R)(1.0 / emu), x);
+        mem_fence_compiler();
+    } else if (s < g.V) {
         hop_all_pairN<NS>(accs, accr, U, fs, fr, live, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu));
         mem_fence_compiler();
     }
