@@ -150,24 +150,42 @@ __device__ __forceinline__ FieldBase field_base(const Z<R>* base) {
 
 // The plane address passes through readfirstlane: it is uniform by
 // construction, and the intrinsic keeps the compiler from folding the site
-// offset into a per-load 64-bit vector address.
-__device__ __forceinline__ char* uniform_ptr(char* p) {
+// offset into a per-load 64-bit vector address.  The result is a pointer into the
+// global address space, so that loads and stores are global instructions (scalar
+// base, 32-bit vector offset) rather than flat ones: a flat access takes a 64-bit
+// vector address and is counted with the LDS accesses, so a wait for LDS data
+// would also wait for it.
+#define TSLOV_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ TSLOV_GLOBAL char* uniform_ptr(char* p) {
     const unsigned long long v = reinterpret_cast<unsigned long long>(p);
     const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
     const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
-    return reinterpret_cast<char*>(((unsigned long long)hi << 32) | lo);
+    return (TSLOV_GLOBAL char*)(((unsigned long long)hi << 32) | lo);
 }
 
 template <typename R>
 __device__ __forceinline__ Z<R> fload(FieldBase f, int ldv, int pl, unsigned s) {
-    const char* plane = uniform_ptr(f.p + (size_t)pl * (size_t)ldv * sizeof(Z<R>));
-    return *reinterpret_cast<const Z<R>*>(plane + (size_t)(unsigned)(s * (unsigned)sizeof(Z<R>)));
+    const TSLOV_GLOBAL char* plane = uniform_ptr(f.p + (size_t)pl * (size_t)ldv * sizeof(Z<R>));
+    const TSLOV_GLOBAL R* q = (const TSLOV_GLOBAL R*)(plane + (size_t)(unsigned)(s * (unsigned)sizeof(Z<R>)));
+    return mk<R>(q[0], q[1]);   // one 2-element load
+}
+
+// Streaming load: for operands this kernel reads once (an epilogue's own-site
+// fields), so that they do not displace from L2 the neighbour spinors and links
+// that other blocks of the launch still read.
+template <typename R>
+__device__ __forceinline__ Z<R> fload_nt(FieldBase f, int ldv, int pl, unsigned s) {
+    const TSLOV_GLOBAL char* plane = uniform_ptr(f.p + (size_t)pl * (size_t)ldv * sizeof(Z<R>));
+    const TSLOV_GLOBAL R* q = (const TSLOV_GLOBAL R*)(plane + (size_t)(unsigned)(s * (unsigned)sizeof(Z<R>)));
+    return mk<R>(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1));
 }
 
 template <typename R>
 __device__ __forceinline__ void fstore(FieldBase f, int ldv, int pl, unsigned s, Z<R> v) {
-    char* plane = uniform_ptr(f.p + (size_t)pl * (size_t)ldv * sizeof(Z<R>));
-    *reinterpret_cast<Z<R>*>(plane + (size_t)(unsigned)(s * (unsigned)sizeof(Z<R>))) = v;
+    TSLOV_GLOBAL char* plane = uniform_ptr(f.p + (size_t)pl * (size_t)ldv * sizeof(Z<R>));
+    TSLOV_GLOBAL R* q = (TSLOV_GLOBAL R*)(plane + (size_t)(unsigned)(s * (unsigned)sizeof(Z<R>)));
+    q[0] = v.re;   // one 2-element store
+    q[1] = v.im;
 }
 
 // Streaming store: for results that the next reader, a kernel whose blocks sit on
@@ -175,8 +193,8 @@ __device__ __forceinline__ void fstore(FieldBase f, int ldv, int pl, unsigned s,
 // this kernel's neighbouring blocks still read from L2.
 template <typename R>
 __device__ __forceinline__ void fstore_nt(FieldBase f, int ldv, int pl, unsigned s, Z<R> v) {
-    char* plane = uniform_ptr(f.p + (size_t)pl * (size_t)ldv * sizeof(Z<R>));
-    R* q = reinterpret_cast<R*>(plane + (size_t)(unsigned)(s * (unsigned)sizeof(Z<R>)));
+    TSLOV_GLOBAL char* plane = uniform_ptr(f.p + (size_t)pl * (size_t)ldv * sizeof(Z<R>));
+    TSLOV_GLOBAL R* q = (TSLOV_GLOBAL R*)(plane + (size_t)(unsigned)(s * (unsigned)sizeof(Z<R>)));
     __builtin_nontemporal_store(v.re, q);
     __builtin_nontemporal_store(v.im, q + 1);
 }

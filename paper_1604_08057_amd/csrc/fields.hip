@@ -1503,11 +1503,11 @@ __device__ __forceinline__ void bwd_rb_finish(const Geom& g, double kappa, const
             const int pl = sp * 3 + a;
             const unsigned i = (unsigned)s;
             const R sg = sp < 2 ? R(1) : R(-1);
-            const Z<R> w_s = fload<R>(rw, g.ldv, pl, i);
-            const Z<R> v_s = fload<R>(rv, g.ldv, pl, i);
-            const Z<R> a_s = fload<R>(ra, g.ldv, pl, i);
-            const Z<R> b_s = fload<R>(rb, g.ldv, pl, i);
-            Z<R> vb = etac * fload<R>(re, g.ldv, pl, i) + ca * b_s;
+            const Z<R> w_s = fload_nt<R>(rw, g.ldv, pl, i);
+            const Z<R> v_s = fload_nt<R>(rv, g.ldv, pl, i);
+            const Z<R> a_s = fload_nt<R>(ra, g.ldv, pl, i);
+            const Z<R> b_s = fload_nt<R>(rb, g.ldv, pl, i);
+            Z<R> vb = etac * fload_nt<R>(re, g.ldv, pl, i) + ca * b_s;
             Z<R> wb = abc * a_s;
             Z<R> ab_s = ca * w_s;
             if (!LAST) {
@@ -1517,8 +1517,8 @@ __device__ __forceinline__ void bwd_rb_finish(const Geom& g, double kappa, const
                 vb = vb + sg * (r_s - kap * accr[sp]) - alc * r_s;
                 wb = wb + sg * (sb_s - kap * accs[sp]) - alr * sb_s;
                 if (carry) {
-                    vb = vb - gnc * fload<R>(field_base(rbar_n), g.ldv, pl, i);
-                    wb = wb - bn * fload<R>(field_base(sbar_n), g.ldv, pl, i);
+                    vb = vb - gnc * fload_nt<R>(field_base(rbar_n), g.ldv, pl, i);
+                    wb = wb - bn * fload_nt<R>(field_base(sbar_n), g.ldv, pl, i);
                 }
             }
             vbo[sp] = vb;

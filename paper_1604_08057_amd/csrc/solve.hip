@@ -144,8 +144,9 @@ __device__ __forceinline__ void load_spinor_off(Spinor<double>& p, FieldBase f, 
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const char* plane = uniform_ptr(f.p + (size_t)(sp * 3 + c) * (size_t)ldv * sizeof(ZD));
-            p.c[sp][c] = *reinterpret_cast<const ZD*>(plane + (size_t)off);
+            const TSLOV_GLOBAL char* plane = uniform_ptr(f.p + (size_t)(sp * 3 + c) * (size_t)ldv * sizeof(ZD));
+            const TSLOV_GLOBAL double* q = (const TSLOV_GLOBAL double*)(plane + (size_t)off);
+            p.c[sp][c] = mk<double>(q[0], q[1]);
         }
 }
 
@@ -234,8 +235,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 2))) v
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const ZD o = sig * x.c[sp][c] - g5 * (x.c[sp][c] - kappa * acc.c[sp][c]);
-                    char* plane = uniform_ptr(out.p + (size_t)(sp * 3 + c) * (size_t)g.ldv * sizeof(ZD));
-                    *reinterpret_cast<ZD*>(plane + (size_t)off) = o;
+                    TSLOV_GLOBAL char* plane = uniform_ptr(out.p + (size_t)(sp * 3 + c) * (size_t)g.ldv * sizeof(ZD));
+                    TSLOV_GLOBAL double* q = (TSLOV_GLOBAL double*)(plane + (size_t)off);
+                    q[0] = o.re;
+                    q[1] = o.im;
                     pv += norm2(o);
                 }
             }
@@ -501,8 +504,10 @@ __global__ __launch_bounds__(kWave) void k_cg_apply_mfma(const ZD* __restrict__ 
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const ZD o = sig * x.c[sp][c] - g5 * (x.c[sp][c] - kappa * acc.c[sp][c]);
-                    char* plane = uniform_ptr(out.p + (size_t)(sp * 3 + c) * (size_t)g.ldv * sizeof(ZD));
-                    *reinterpret_cast<ZD*>(plane + (size_t)off) = o;
+                    TSLOV_GLOBAL char* plane = uniform_ptr(out.p + (size_t)(sp * 3 + c) * (size_t)g.ldv * sizeof(ZD));
+                    TSLOV_GLOBAL double* q = (TSLOV_GLOBAL double*)(plane + (size_t)off);
+                    q[0] = o.re;
+                    q[1] = o.im;
                     pv += norm2(o);
                 }
             }
