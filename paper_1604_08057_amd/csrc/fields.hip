@@ -142,6 +142,12 @@ __device__ __forceinline__ void load1(Z<R> (&p)[4], const Z<R>* __restrict__ f, 
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp) p[sp] = fload<R>(field_base(f), ldv, sp * 3 + a, (unsigned)s);
 }
+// load1 with the streaming hint, for a field this kernel reads once
+template <typename R>
+__device__ __forceinline__ void load1_nt(Z<R> (&p)[4], const Z<R>* __restrict__ f, int ldv, int a, int s) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) p[sp] = fload_nt<R>(field_base(f), ldv, sp * 3 + a, (unsigned)s);
+}
 
 template <typename R>
 __device__ __forceinline__ void store1(Z<R>* __restrict__ f, int ldv, int a, int s, const Z<R> (&p)[4]) {
@@ -863,7 +869,7 @@ __device__ __forceinline__ void fwd_pair_finish(const Geom& g, double kappa, con
         store1_nt(wk.b(slot, j), g.ldv, a, s, bv);
         if (!replay && has_eta) {
             Z<R> e[4];
-            load1(e, wk.f(slot, 1), g.ldv, a, s);
+            load1_nt(e, wk.f(slot, 1), g.ldv, a, s);
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp) {
                 const ZD ev = cjmul(zcast<double>(e[sp]), zcast<double>(v[sp]));
