@@ -280,64 +280,18 @@ __device__ __forceinline__ void hop_half_pair(Z<R> (&acca)[4], Z<R> (&accb)[4], 
         hop_two_dirs_pair_eager<2, 3>(acca, accb, U, fa, fb, g, s, a, n, ep, em);
 }
 
-// The colour-split pair hops for NS entries of a batch at once: every link row is
-// loaded once and applied to the 2*NS fields (A_q at +mu, B_q at -mu) of the
-// entries whose bit is set in the block-uniform mask `live`.  Each accumulator
-// receives the same operations in the same order as with one entry.
-template <int NU, int NS, typename R, typename RL>
-__device__ __forceinline__ void hop_dir_pairN(Z<R> (&acca)[NS][4], Z<R> (&accb)[NS][4], const Z<RL>* __restrict__ U,
-                                              const Z<R>* const (&fa)[NS], const Z<R>* const (&fb)[NS],
-                                              unsigned live, const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
-    const R up = (NU == 3) ? ep : R(1), dn = (NU == 3) ? em : R(1);
-    Z<R> u[3];
-    Spinor<R> p;
-    load_row(u, U, g.ldv, NU, a, s);
-#pragma unroll
-    for (int q = 0; q < NS; ++q) {
-        if (live & (1u << q)) {
-            load_spinor(p, fa[q], g.ldv, n.fwd[NU]);
-            hop1<NU, +1>(acca[q], u, p, up);
-            load_spinor(p, fb[q], g.ldv, n.fwd[NU]);
-            hop1<NU, +1>(accb[q], u, p, dn);
-        }
-    }
-    load_col_conj(u, U, g.ldv, NU, a, n.bwd[NU]);
-#pragma unroll
-    for (int q = 0; q < NS; ++q) {
-        if (live & (1u << q)) {
-            load_spinor(p, fa[q], g.ldv, n.bwd[NU]);
-            hop1<NU, -1>(acca[q], u, p, dn);
-            load_spinor(p, fb[q], g.ldv, n.bwd[NU]);
-            hop1<NU, -1>(accb[q], u, p, up);
-        }
-    }
-}
-
-template <int NS, typename R, typename RL>
-__device__ __forceinline__ void hop_all_pairN(Z<R> (&acca)[NS][4], Z<R> (&accb)[NS][4], const Z<RL>* __restrict__ U,
-                                              const Z<R>* const (&fa)[NS], const Z<R>* const (&fb)[NS],
-                                              unsigned live, const Geom& g, int s, int a, const Nbr& n, R ep, R em) {
-#pragma unroll 1
-    for (int nu = 0; nu < 4; ++nu) {
-        switch (nu) {
-            case 0: hop_dir_pairN<0, NS>(acca, accb, U, fa, fb, live, g, s, a, n, ep, em); break;
-            case 1: hop_dir_pairN<1, NS>(acca, accb, U, fa, fb, live, g, s, a, n, ep, em); break;
-            case 2: hop_dir_pairN<2, NS>(acca, accb, U, fa, fb, live, g, s, a, n, ep, em); break;
-            default: hop_dir_pairN<3, NS>(acca, accb, U, fa, fb, live, g, s, a, n, ep, em); break;
-        }
-    }
-}
-
-// Colour-split hops of one entry with the neighbour spinors shared through LDS.
-// Thread (a, l) loads only colour a of the four neighbour spinors of a direction
-// (four spins each), projects it to its two half-spinor components and publishes
-// them; after a barrier it reads the three colours of each half spinor of its own
-// site and applies its link row.  A neighbour value thus passes the vector L1 once
-// per block, not once per colour wavefront.  Every half-spinor component, product
-// and sum is formed by the operations of hop_dir_pair1 and hop_dir_pairN in the same
-// order (the link-row products by row_dot's fixed chain), so the accumulators get
-// the same bits as with those.  All threads of the block must call it (`in`
-// false for sites past the volume: no loads, their slots are not read).
+// Colour-split hops of NS entries of a batch (A_q at +mu, B_q at -mu) with the neighbour
+// spinors shared through LDS.  Thread (a, l) loads only colour a of the four neighbour
+// spinors of a direction (four spins each), projects it to its two half-spinor
+// components and publishes them; after a barrier it reads the three colours of each
+// half spinor of its own site and applies its link row.  A neighbour value thus passes
+// the vector L1 once per block, not once per colour wavefront, and the link rows are
+// loaded once for all NS entries (the entries whose bit is set in the block-uniform
+// mask `live`).  Every half-spinor component, product and sum of an entry is formed by
+// the same operations in the same order whatever NS (the link-row products by
+// row_dot's fixed chain), so an entry gets the same bits in every shape.  All threads
+// of the block must call it (`in` false for sites past the volume: no loads, their
+// slots are not read).
 template <typename R>
 struct HopX {
     Z<R> h[4][2][3][kSites];   // hop (A forward, B forward, A backward, B backward), half spin, colour, site
@@ -356,64 +310,80 @@ __device__ __forceinline__ void hop1_x(Z<R> (&acc)[4], const Z<R> (&urow)[3], co
     recon1_add<NU, S>(acc, o, coef);
 }
 
-template <int NU, typename R, typename RL>
-__device__ __forceinline__ void hop_dir_pair_x(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<RL>* __restrict__ U,
-                                               const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
-                                               const Geom& g, int s, int a, int l, bool in, const Nbr& n, R ep,
-                                               R em, HopX<R>& x) {
+template <int NU, int NS, typename R, typename RL>
+__device__ __forceinline__ void hop_dir_pair_x(Z<R> (&acca)[NS][4], Z<R> (&accb)[NS][4], const Z<RL>* __restrict__ U,
+                                               const Z<R>* const (&fa)[NS], const Z<R>* const (&fb)[NS],
+                                               unsigned live, const Geom& g, int s, int a, int l, bool in,
+                                               const Nbr& n, R ep, R em, HopX<R> (&x)[NS]) {
     const R up = (NU == 3) ? ep : R(1), dn = (NU == 3) ? em : R(1);
     Z<R> uf[3], ub[3];
     if (in) {
-        const FieldBase ra = field_base(fa), rb = field_base(fb);
         const unsigned yf = (unsigned)n.fwd[NU], yb = (unsigned)n.bwd[NU];
-        Z<R> p[4][4];   // colour a of A(x+nu), B(x+nu), A(x-nu), B(x-nu)
 #pragma unroll
-        for (int sp = 0; sp < 4; ++sp) {
-            p[0][sp] = fload<R>(ra, g.ldv, sp * 3 + a, yf);
-            p[1][sp] = fload<R>(rb, g.ldv, sp * 3 + a, yf);
-            p[2][sp] = fload<R>(ra, g.ldv, sp * 3 + a, yb);
-            p[3][sp] = fload<R>(rb, g.ldv, sp * 3 + a, yb);
+        for (int q = 0; q < NS; ++q) {
+            if (!(live & (1u << q))) continue;
+            if (q > 0) mem_fence_compiler();   // one entry's neighbour operands in flight at a time
+            const FieldBase ra = field_base(fa[q]), rb = field_base(fb[q]);
+            Z<R> p[4][4];   // colour a of A(x+nu), B(x+nu), A(x-nu), B(x-nu)
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+                p[0][sp] = fload<R>(ra, g.ldv, sp * 3 + a, yf);
+                p[1][sp] = fload<R>(rb, g.ldv, sp * 3 + a, yf);
+                p[2][sp] = fload<R>(ra, g.ldv, sp * 3 + a, yb);
+                p[3][sp] = fload<R>(rb, g.ldv, sp * 3 + a, yb);
+            }
+            if (q == NS - 1) {
+                load_row(uf, U, g.ldv, NU, a, s);
+                load_col_conj(ub, U, g.ldv, NU, a, n.bwd[NU]);
+            }
+            Z<R> h0, h1;
+            project_col<NU, +1>(p[0][0], p[0][1], p[0][2], p[0][3], h0, h1);
+            x[q].h[0][0][a][l] = h0;
+            x[q].h[0][1][a][l] = h1;
+            project_col<NU, +1>(p[1][0], p[1][1], p[1][2], p[1][3], h0, h1);
+            x[q].h[1][0][a][l] = h0;
+            x[q].h[1][1][a][l] = h1;
+            project_col<NU, -1>(p[2][0], p[2][1], p[2][2], p[2][3], h0, h1);
+            x[q].h[2][0][a][l] = h0;
+            x[q].h[2][1][a][l] = h1;
+            project_col<NU, -1>(p[3][0], p[3][1], p[3][2], p[3][3], h0, h1);
+            x[q].h[3][0][a][l] = h0;
+            x[q].h[3][1][a][l] = h1;
         }
-        load_row(uf, U, g.ldv, NU, a, s);
-        load_col_conj(ub, U, g.ldv, NU, a, n.bwd[NU]);
-        Z<R> h0, h1;
-        project_col<NU, +1>(p[0][0], p[0][1], p[0][2], p[0][3], h0, h1);
-        x.h[0][0][a][l] = h0;
-        x.h[0][1][a][l] = h1;
-        project_col<NU, +1>(p[1][0], p[1][1], p[1][2], p[1][3], h0, h1);
-        x.h[1][0][a][l] = h0;
-        x.h[1][1][a][l] = h1;
-        project_col<NU, -1>(p[2][0], p[2][1], p[2][2], p[2][3], h0, h1);
-        x.h[2][0][a][l] = h0;
-        x.h[2][1][a][l] = h1;
-        project_col<NU, -1>(p[3][0], p[3][1], p[3][2], p[3][3], h0, h1);
-        x.h[3][0][a][l] = h0;
-        x.h[3][1][a][l] = h1;
+        if (!(live & (1u << (NS - 1)))) {   // the last entry is past the list's end
+            load_row(uf, U, g.ldv, NU, a, s);
+            load_col_conj(ub, U, g.ldv, NU, a, n.bwd[NU]);
+        }
     }
     __syncthreads();
     if (in) {
-        hop1_x<NU, +1>(acca, uf, x.h[0], l, up);
-        hop1_x<NU, +1>(accb, uf, x.h[1], l, dn);
-        hop1_x<NU, -1>(acca, ub, x.h[2], l, dn);
-        hop1_x<NU, -1>(accb, ub, x.h[3], l, up);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            if (!(live & (1u << q))) continue;
+            hop1_x<NU, +1>(acca[q], uf, x[q].h[0], l, up);
+            hop1_x<NU, +1>(accb[q], uf, x[q].h[1], l, dn);
+            hop1_x<NU, -1>(acca[q], ub, x[q].h[2], l, dn);
+            hop1_x<NU, -1>(accb[q], ub, x[q].h[3], l, up);
+        }
     }
     __syncthreads();   // the next direction overwrites the slots
 }
 
-template <typename R, typename RL>
-__device__ __forceinline__ void hop_all_pair_x(Z<R> (&acca)[4], Z<R> (&accb)[4], const Z<RL>* __restrict__ U,
-                                               const Z<R>* __restrict__ fa, const Z<R>* __restrict__ fb,
-                                               const Geom& g, int s, int a, R ep, R em, HopX<R>& x) {
+template <int NS, typename R, typename RL>
+__device__ __forceinline__ void hop_all_pair_x(Z<R> (&acca)[NS][4], Z<R> (&accb)[NS][4], const Z<RL>* __restrict__ U,
+                                               const Z<R>* const (&fa)[NS], const Z<R>* const (&fb)[NS],
+                                               unsigned live, const Geom& g, int s, int a, R ep, R em,
+                                               HopX<R> (&x)[NS]) {
     const int l = threadIdx.x % kSites;
     const bool in = s < g.V;
     const Nbr n = neighbours(g, in ? s : 0);
 #pragma unroll 1
     for (int nu = 0; nu < 4; ++nu) {
         switch (nu) {
-            case 0: hop_dir_pair_x<0>(acca, accb, U, fa, fb, g, s, a, l, in, n, ep, em, x); break;
-            case 1: hop_dir_pair_x<1>(acca, accb, U, fa, fb, g, s, a, l, in, n, ep, em, x); break;
-            case 2: hop_dir_pair_x<2>(acca, accb, U, fa, fb, g, s, a, l, in, n, ep, em, x); break;
-            default: hop_dir_pair_x<3>(acca, accb, U, fa, fb, g, s, a, l, in, n, ep, em, x); break;
+            case 0: hop_dir_pair_x<0, NS>(acca, accb, U, fa, fb, live, g, s, a, l, in, n, ep, em, x); break;
+            case 1: hop_dir_pair_x<1, NS>(acca, accb, U, fa, fb, live, g, s, a, l, in, n, ep, em, x); break;
+            case 2: hop_dir_pair_x<2, NS>(acca, accb, U, fa, fb, live, g, s, a, l, in, n, ep, em, x); break;
+            default: hop_dir_pair_x<3, NS>(acca, accb, U, fa, fb, live, g, s, a, l, in, n, ep, em, x); break;
         }
     }
 }
@@ -1076,14 +1046,9 @@ __global__ __launch_bounds__(kCBlock) void k_fwd_pair_ms(const Z<RL>* __restrict
         zero1(acca[q]);
         zero1(accb[q]);
     }
-    if constexpr (NS == 1) {
-        __shared__ HopX<R> x;
-        hop_all_pair_x(acca[0], accb[0], U, rin[0], sin[0], g, s, a, (R)emu, (R)(1.0 / emu), x);
-        mem_fence_compiler();
-    } else if (s < g.V) {
-        hop_all_pairN<NS>(acca, accb, U, rin, sin, live, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu));
-        mem_fence_compiler();
-    }
+    __shared__ HopX<R> x[NS];
+    hop_all_pair_x<NS>(acca, accb, U, rin, sin, live, g, s, a, (R)emu, (R)(1.0 / emu), x);
+    mem_fence_compiler();
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         if (live & (1u << q)) {
@@ -1674,14 +1639,9 @@ __global__ __launch_bounds__(kCBlock) void k_bwd_rb_ms(const Z<RL>* __restrict__
         zero1(accs[q]);
         zero1(accr[q]);
     }
-    if constexpr (NS == 1) {
-        __shared__ HopX<R> x;
-        hop_all_pair_x(accs[0], accr[0], U, fs[0], fr[0], g, s, a, (R)emu, (R)(1.0 / emu), x);
-        mem_fence_compiler();
-    } else if (s < g.V) {
-        hop_all_pairN<NS>(accs, accr, U, fs, fr, live, g, s, a, neighbours(g, s), (R)emu, (R)(1.0 / emu));
-        mem_fence_compiler();
-    }
+    __shared__ HopX<R> x[NS];
+    hop_all_pair_x<NS>(accs, accr, U, fs, fr, live, g, s, a, (R)emu, (R)(1.0 / emu), x);
+    mem_fence_compiler();
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         if (live & (1u << q)) {
