@@ -350,7 +350,7 @@ __device__ __forceinline__ void hop_dir_pair_x(Z<R> (&acca)[NS][4], Z<R> (&accb)
             x[q].h[3][0][a][l] = h0;
             x[q].h[3][1][a][l] = h1;
         }
-        if (!(live & (1u << (NS - 1)))) {   // the last entry is past the list's end
+        if (!(live & (1u << (NS - 1)))) {   // the last entry is stopped or past the list's end
             load_row(uf, U, g.ldv, NU, a, s);
             load_col_conj(ub, U, g.ldv, NU, a, n.bwd[NU]);
         }
