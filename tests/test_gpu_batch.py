@@ -8,7 +8,9 @@
 * on that layout, 1, 2 or 4 entries per workgroup and the timed pick give the
   same bits (five entries: a ragged last workgroup);
 * against the oracle per source: S, dS/dU, dS/dpsi to 1e-10 relative;
-* a zero source inside a batch: S = 0 and zero derivatives, the others unchanged;
+* a zero source inside a batch: S = 0 and zero derivatives, the others unchanged; on
+  the colour-split lattice with one, two and four entries per workgroup, all giving the
+  same bits;
 * the current estimator against the oracle estimator (mean of per-source U(1)
   projections of autograd gradients, eta = g5 xi): j to 1e-10 relative,
   divergence and total current to 1e-10 of max |j|, the per-sample Ward
@@ -211,3 +213,35 @@ def test_current_estimate_deflated(nsrc):
         say(f"  deflated current ({nsrc} sources): Ward residual {ward2:.2e}")
         assert ward2 < 1e-9
     ctx.close()
+
+
+def test_zero_source_colour_split_every_shape():
+    """A zero source inside a batch on the colour-split lattice (10^4): it stops at the
+    first step, and with two or four entries per workgroup its workgroups keep running
+    for the others (its slots masked out of the LDS exchange).  Every shape gives the
+    bits of one entry per workgroup, the zero source S = 0 and zero derivatives, and
+    each other source the bits of its single-source call."""
+    dims, mass, mu = (10, 10, 10, 10), -2.0, 0.3
+    U = random_links(dims, 0.4, np.random.default_rng(29))
+    ks = [20, 14, 18, 20, 9]
+    psis, etas = _sources(5, 10000, 51), _sources(5, 10000, 52)
+    psis[2] = 0.0
+    ctx = _ctx(dims, mass, mu, U)
+    runs = {}
+    for ns in (1, 2, 4):
+        ctx.set_pair_ns(ns)
+        S, dU, dpsi, infos = ctx.sign_grad_batched(dev(etas), dev(psis), ks, want_dpsi=True)
+        say(f"batched 10^4 with a zero source, entries per workgroup {ns}: k_used {[i.k_used for i in infos]}")
+        assert S[2] == 0.0 and infos[2].k_used == 0
+        assert torch.count_nonzero(dU[2]).item() == 0 and torch.count_nonzero(dpsi[2]).item() == 0
+        runs[ns] = (S, dU, dpsi)
+    ctx.set_pair_ns(1)
+    for s in (0, 3, 4):
+        S1, dU1, _, _ = ctx.sign_grad(dev(etas[s]), dev(psis[s]), ks[s])
+        assert runs[1][0][s] == S1 and torch.equal(runs[1][1][s], dU1), s
+    ctx.close()
+    S0, dU0, dpsi0 = runs[1]
+    for ns in (2, 4):
+        S, dU, dpsi = runs[ns]
+        assert S == S0, ns
+        assert torch.equal(dU, dU0) and torch.equal(dpsi, dpsi0), ns
